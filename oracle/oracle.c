@@ -1,0 +1,1315 @@
+/*
+ * OS-MPM FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded double-precision implementation of the
+ * overlapping-Schwarz material point method (arXiv 2605.09097): APIC
+ * particle-to-grid transfer, the backward-Euler incremental potential
+ * minimised by Newton's method with Jacobi-preconditioned CG and a halving
+ * line search, APIC grid-to-particle transfer with the deformation-gradient
+ * update and advection, boundary-grid selection, overlap arbitration, the
+ * mass-weighted projection, the coarse-to-fine interpolation, the temporal
+ * interpolation and the multiplicative Schwarz frame.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no code, header, table or
+ * helper with the GPU library and must never be used as a fallback for it.
+ *
+ * Every function names the section / equation of the paper it follows.
+ * Readings of passages the paper leaves open are stated where they are used
+ * and listed together in the design notes of the repository.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no OpenMP, no intrinsics).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_ARG 1
+#define OR_E_NOMEM 2
+#define OR_E_OUT_OF_GRID 4
+#define OR_E_INVERTED 5
+
+#define BC_FIX 0
+#define BC_TRANSLATE 1
+#define BC_ROTATE 2
+
+/* ------------------------------------------------------------------ */
+/* Data                                                                */
+/* ------------------------------------------------------------------ */
+
+/* One subdomain: its structured grid (an integer lattice of pitch h0),
+ * its particles and its grid state.  All arrays are owned by the caller.
+ * Particle arrays are row-major per particle: x[p*d+a], F[p*d*d+a*d+b]. */
+typedef struct {
+  int dim;
+  int n[3];               /* nodes per axis (n[2] == 1 in 2D) */
+  double h0;              /* lattice pitch */
+  long long origin_q[3];  /* grid origin in lattice units */
+  long long dx_q;         /* grid spacing in lattice units */
+
+  int np;
+  double *x, *v, *B, *F;  /* particle state, updated in place */
+  double *mass, *vol;     /* m_p and V_p^0 */
+  int *mat;               /* material index */
+  unsigned char *flags;   /* bit0: Schwarz boundary particle; bit 1+g: scene group g */
+
+  int n_mat;
+  double *mu, *lam;       /* Lame parameters per material */
+
+  int n_groups;
+  int *bc_kind;           /* BC_FIX / BC_TRANSLATE / BC_ROTATE */
+  int *bc_mask;           /* component mask */
+  double *bc_param;       /* [n_groups][8] */
+
+  double m_ref;           /* unit of the fixed-point node masses: m_ref / 2^32 */
+  double tau;             /* selection threshold (a mass) */
+
+  /* grid state, caller-allocated */
+  double *m;              /* [nn]     lumped node mass */
+  double *vn;             /* [nn][d]  node velocity from P2G */
+  double *u;              /* [nn][d]  displacement unknown x_hat - x */
+  signed char *bcg;       /* [nn][d]  scene-BC group constraining the DOF, or -1 */
+  long long *q_all;       /* [nn]     fixed-point node mass, all particles */
+  long long *q_bnd;       /* [nn]     fixed-point node mass, boundary particles */
+  unsigned char *gamma;   /* [nn]     boundary grid set */
+  unsigned char *recv;    /* [nn]     receiver set after arbitration */
+  double *vbc;            /* [nn][d]  Schwarz Dirichlet velocity on receivers */
+  int use_schwarz_bc;
+} or_domain;
+
+typedef struct {
+  double newton_rtol, newton_atol, cg_rtol;
+  int max_newton, max_cg, max_ls;
+  int project_psd;        /* 1: per-particle PSD projection of dP/dF */
+  double gravity[3];
+} or_solve_opts;
+
+typedef struct {
+  int newton_iters, cg_iters, ls_halvings, converged, ls_failed;
+  double gnorm0, gnorm, energy;
+} or_solve_stats;
+
+typedef struct {
+  int M, k_max;
+  double eps_conv, eps_tol;
+  or_solve_opts coarse, fine;
+} or_schwarz_opts;
+
+typedef struct {
+  int iters, converged;
+  double r_B, r_S;
+  int n_recv_B, n_recv_S, n_amb;
+  int newton_B, newton_S, cg_B, cg_S, ls_B, ls_S;
+} or_schwarz_stats;
+
+/* ------------------------------------------------------------------ */
+/* Grid and quadratic B-spline weights                                 */
+/* ------------------------------------------------------------------ */
+
+static int nnodes(const or_domain *D) { return D->n[0] * D->n[1] * D->n[2]; }
+static double grid_dx(const or_domain *D) { return (double)D->dx_q * D->h0; }
+static int node_flat(const or_domain *D, const int *i) {
+  return i[0] + D->n[0] * (i[1] + D->n[1] * i[2]);
+}
+static void node_index(const or_domain *D, int flat, int *i) {
+  i[0] = flat % D->n[0];
+  i[1] = (flat / D->n[0]) % D->n[1];
+  i[2] = flat / (D->n[0] * D->n[1]);
+}
+/* Node position x_i = (origin_q + i * dx_q) * h0 on the integer lattice. */
+static void node_pos(const or_domain *D, const int *i, double *x) {
+  for (int a = 0; a < D->dim; ++a)
+    x[a] = (double)(D->origin_q[a] + (long long)i[a] * D->dx_q) * D->h0;
+}
+
+/* Quadratic B-spline support of a point (the nodal shape functions N_i of
+ * the structured grid, Sec. 2.2.2).  The paper does not state the order; the
+ * quadratic B-spline with a 3^d stencil is used.  base = floor(xi - 1/2),
+ * f = xi - base in [1/2, 3/2). */
+typedef struct {
+  int base[3];
+  double f[3];
+  double w[3][3], dw[3][3];
+} stencil;
+
+static int stencil_at(const or_domain *D, const double *xp, stencil *s) {
+  const double dx = grid_dx(D);
+  const double inv_dx = 1.0 / dx;
+  for (int a = 0; a < 3; ++a) {
+    s->base[a] = 0;
+    s->f[a] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      s->w[a][k] = 0.0;
+      s->dw[a][k] = 0.0;
+    }
+  }
+  for (int a = 0; a < D->dim; ++a) {
+    const double o = (double)D->origin_q[a] * D->h0;
+    const double xi = (xp[a] - o) * inv_dx;
+    const double bf = floor(xi - 0.5);
+    if (!(bf >= 0.0 && bf <= (double)(D->n[a] - 3))) return OR_E_OUT_OF_GRID;
+    const double f = xi - bf;
+    const double t0 = 1.5 - f, t1 = f - 1.0, t2 = f - 0.5;
+    s->base[a] = (int)bf;
+    s->f[a] = f;
+    s->w[a][0] = 0.5 * (t0 * t0);
+    s->w[a][1] = 0.75 - t1 * t1;
+    s->w[a][2] = 0.5 * (t2 * t2);
+    s->dw[a][0] = -t0 * inv_dx;
+    s->dw[a][1] = -2.0 * t1 * inv_dx;
+    s->dw[a][2] = t2 * inv_dx;
+  }
+  return OR_OK;
+}
+
+static int stencil_size(const or_domain *D) { return D->dim == 3 ? 27 : 9; }
+
+/* Stencil node number s (x fastest): its flat node index, N_ip, grad N_ip and
+ * x_i - x_p.  N = w_x*w_y (2D), (w_x*w_y)*w_z (3D). */
+static void stencil_node(const or_domain *D, const stencil *st, int s, int *flat, double *N,
+                         double *gN, double *dxv) {
+  int k[3] = {s % 3, (s / 3) % 3, s / 9};
+  int idx[3] = {0, 0, 0};
+  const double dx = grid_dx(D);
+  for (int a = 0; a < D->dim; ++a) {
+    idx[a] = st->base[a] + k[a];
+    dxv[a] = ((double)k[a] - st->f[a]) * dx;
+  }
+  *flat = node_flat(D, idx);
+  const double wx = st->w[0][k[0]], wy = st->w[1][k[1]];
+  const double dwx = st->dw[0][k[0]], dwy = st->dw[1][k[1]];
+  if (D->dim == 2) {
+    *N = wx * wy;
+    gN[0] = dwx * wy;
+    gN[1] = wx * dwy;
+  } else {
+    const double wz = st->w[2][k[2]], dwz = st->dw[2][k[2]];
+    *N = (wx * wy) * wz;
+    gN[0] = (dwx * wy) * wz;
+    gN[1] = (wx * dwy) * wz;
+    gN[2] = (wx * wy) * dwz;
+  }
+}
+
+/* Exported for the B-spline identity pins. */
+int or_weights(const or_domain *D, const double *xp, int *flat, double *N, double *gN) {
+  stencil st;
+  int rc = stencil_at(D, xp, &st);
+  if (rc) return rc;
+  double dxv[3];
+  for (int s = 0; s < stencil_size(D); ++s)
+    stencil_node(D, &st, s, &flat[s], &N[s], &gN[3 * s], dxv);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Binning: stable counting sort of particles by the cell of their     */
+/* base node, in tile-major key order.                                  */
+/* ------------------------------------------------------------------ */
+
+/* Number of keys for a tile shape: base positions per axis are n-2, padded to
+ * whole tiles; key = tile_flat * tile_volume + local_flat (x fastest). */
+long long or_num_keys(const or_domain *D, const int *tile) {
+  long long nk = 1;
+  for (int a = 0; a < D->dim; ++a) {
+    long long nb = D->n[a] - 2;
+    long long nt = (nb + tile[a] - 1) / tile[a];
+    nk *= nt * tile[a];
+  }
+  return nk;
+}
+
+static long long bin_key(const or_domain *D, const int *tile, const int *base) {
+  long long ntile[3] = {1, 1, 1}, T[3] = {1, 1, 1}, t[3] = {0, 0, 0}, l[3] = {0, 0, 0};
+  for (int a = 0; a < D->dim; ++a) {
+    T[a] = tile[a];
+    ntile[a] = (D->n[a] - 2 + tile[a] - 1) / tile[a];
+    t[a] = base[a] / tile[a];
+    l[a] = base[a] % tile[a];
+  }
+  long long tf = t[0] + ntile[0] * (t[1] + ntile[1] * t[2]);
+  long long lf = l[0] + T[0] * (l[1] + T[1] * l[2]);
+  return tf * (T[0] * T[1] * T[2]) + lf;
+}
+
+/* perm[i] = original index of the i-th particle in sorted order (stable);
+ * cell_start has num_keys + 1 entries. */
+int or_sort(const or_domain *D, const int *tile, int *perm, int *cell_start) {
+  const long long nk = or_num_keys(D, tile);
+  long long *key = (long long *)malloc(sizeof(long long) * (size_t)(D->np > 0 ? D->np : 1));
+  int *next = (int *)malloc(sizeof(int) * (size_t)(nk + 1));
+  if (!key || !next) {
+    free(key);
+    free(next);
+    return OR_E_NOMEM;
+  }
+  for (long long k = 0; k <= nk; ++k) cell_start[k] = 0;
+  for (int p = 0; p < D->np; ++p) {
+    stencil st;
+    if (stencil_at(D, &D->x[p * D->dim], &st)) {
+      free(key);
+      free(next);
+      return OR_E_OUT_OF_GRID;
+    }
+    key[p] = bin_key(D, tile, st.base);
+    cell_start[key[p] + 1] += 1;
+  }
+  for (long long k = 0; k < nk; ++k) cell_start[k + 1] += cell_start[k];
+  for (long long k = 0; k <= nk; ++k) next[k] = cell_start[k];
+  for (int p = 0; p < D->np; ++p) perm[next[key[p]]++] = p;
+  free(key);
+  free(next);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* APIC particle-to-grid (Eq. p2g_transfer, Sec. 2.2.4; Eq. p2g_substep) */
+/* ------------------------------------------------------------------ */
+
+static double fixed_scale(const or_domain *D) { return 4294967296.0 / D->m_ref; }
+
+/* Fixed-point node mass contribution: rint(N_ip * (m_p * 2^32 / m_ref)).  Node
+ * selection sums these as integers so the selected sets do not depend on the
+ * order of summation (reading of the "small mass threshold" of Sec. 3.2.1). */
+static long long fixed_mass(double N, double mq) { return llrint(N * mq); }
+
+/* m_i = sum m_p N_ip; (mv)_i = sum m_p N_ip (v_p + B_p D_p^-1 (x_i - x_p)) with
+ * the quadratic-B-spline inertia tensor D_p = (dx^2/4) I (APIC); v_i = (mv)_i/m_i
+ * on nodes with m_i > 0 (the active set).  Also builds the fixed-point node
+ * mass of all particles (arbitration, Eq. overlap_donor) and selects the
+ * scene-BC nodes of each particle group. */
+int or_p2g(or_domain *D) {
+  const int d = D->dim, nn = nnodes(D), ss = stencil_size(D);
+  const double dx = grid_dx(D), inv_dx = 1.0 / dx;
+  const double Dinv = 4.0 * inv_dx * inv_dx;
+  const double scale = fixed_scale(D);
+  const long long tau_q = llrint(D->tau * scale);
+  long long *qg = NULL;
+  if (D->n_groups > 0) {
+    qg = (long long *)calloc((size_t)D->n_groups * (size_t)nn, sizeof(long long));
+    if (!qg) return OR_E_NOMEM;
+  }
+  for (int i = 0; i < nn; ++i) {
+    D->m[i] = 0.0;
+    D->q_all[i] = 0;
+    for (int a = 0; a < d; ++a) {
+      D->vn[i * d + a] = 0.0;
+      D->bcg[i * d + a] = -1;
+    }
+  }
+  for (int p = 0; p < D->np; ++p) {
+    stencil st;
+    if (stencil_at(D, &D->x[p * d], &st)) {
+      free(qg);
+      return OR_E_OUT_OF_GRID;
+    }
+    const double mp = D->mass[p];
+    const double mq = mp * scale;
+    const double *vp = &D->v[p * d];
+    const double *Bp = &D->B[p * d * d];
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      const double mN = mp * N;
+      D->m[i] += mN;
+      for (int a = 0; a < d; ++a) {
+        double aff = 0.0;
+        for (int b = 0; b < d; ++b) aff += Bp[a * d + b] * dxv[b];
+        D->vn[i * d + a] += mN * (vp[a] + Dinv * aff);
+      }
+      const long long q = fixed_mass(N, mq);
+      D->q_all[i] += q;
+      for (int g = 0; g < D->n_groups; ++g)
+        if (D->flags[p] & (2u << g)) qg[(size_t)g * nn + i] += q;
+    }
+  }
+  for (int i = 0; i < nn; ++i) {
+    if (D->m[i] > 0.0)
+      for (int a = 0; a < d; ++a) D->vn[i * d + a] /= D->m[i];
+    for (int a = 0; a < d; ++a) {
+      for (int g = 0; g < D->n_groups; ++g) {
+        if ((D->bc_mask[g] >> a) & 1) {
+          if (qg[(size_t)g * nn + i] > tau_q && D->m[i] > 0.0) {
+            D->bcg[i * d + a] = (signed char)g;
+            break;
+          }
+        }
+      }
+    }
+  }
+  free(qg);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Compressible Neo-Hookean energy (Sec. 4: "Neo-Hookean"; the paper    */
+/* gives no formula).  Psi = mu/2 (|F|^2 - d) - mu ln J + lam/2 (ln J)^2, */
+/* which in 2D is the plane-strain energy of diag(F, 1) (Sec. 4.3).      */
+/* ------------------------------------------------------------------ */
+
+static double det_d(const double *F, int d) {
+  if (d == 2) return F[0] * F[3] - F[1] * F[2];
+  return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+         F[2] * (F[3] * F[7] - F[4] * F[6]);
+}
+
+/* Cofactor matrix: cof(F)_ij = dJ/dF_ij. */
+static void cofactor(const double *F, int d, double *C) {
+  if (d == 2) {
+    C[0] = F[3];
+    C[1] = -F[2];
+    C[2] = -F[1];
+    C[3] = F[0];
+    return;
+  }
+  C[0] = F[4] * F[8] - F[5] * F[7];
+  C[1] = F[5] * F[6] - F[3] * F[8];
+  C[2] = F[3] * F[7] - F[4] * F[6];
+  C[3] = F[2] * F[7] - F[1] * F[8];
+  C[4] = F[0] * F[8] - F[2] * F[6];
+  C[5] = F[1] * F[6] - F[0] * F[7];
+  C[6] = F[1] * F[5] - F[2] * F[4];
+  C[7] = F[2] * F[3] - F[0] * F[5];
+  C[8] = F[0] * F[4] - F[1] * F[3];
+}
+
+/* Psi(F); +inf when J <= 0. */
+static double nh_psi(const double *F, int d, double mu, double lam) {
+  const double J = det_d(F, d);
+  if (!(J > 0.0)) return INFINITY;
+  const double lnJ = log(J);
+  double tr = 0.0;
+  for (int k = 0; k < d * d; ++k) tr += F[k] * F[k];
+  return 0.5 * mu * (tr - (double)d) - mu * lnJ + 0.5 * lam * lnJ * lnJ;
+}
+
+/* First Piola stress P = mu (F - F^-T) + lam ln J F^-T and its derivative
+ * A[(ab),(ce)] = dP_ab/dF_ce
+ *   = mu d_ac d_be + (mu - lam ln J) Finv_ea Finv_bc + lam Finv_ba Finv_ec. */
+static int nh_stress(const double *F, int d, double mu, double lam, double *P, double *A) {
+  const double J = det_d(F, d);
+  if (!(J > 0.0)) return OR_E_INVERTED;
+  const double lnJ = log(J);
+  double C[9], Finv[9];
+  cofactor(F, d, C);
+  /* F^-1 = cof(F)^T / J */
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) Finv[a * d + b] = C[b * d + a] / J;
+  if (P)
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        const double FinvT = Finv[b * d + a];
+        P[a * d + b] = mu * (F[a * d + b] - FinvT) + lam * lnJ * FinvT;
+      }
+  if (A) {
+    const int n = d * d;
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b)
+        for (int c = 0; c < d; ++c)
+          for (int e = 0; e < d; ++e) {
+            double v = 0.0;
+            if (a == c && b == e) v += mu;
+            v += (mu - lam * lnJ) * Finv[e * d + a] * Finv[b * d + c];
+            v += lam * Finv[b * d + a] * Finv[e * d + c];
+            A[(a * d + b) * n + (c * d + e)] = v;
+          }
+  }
+  return OR_OK;
+}
+
+/* Projection of a symmetric n x n matrix onto the PSD cone: cyclic Jacobi
+ * eigendecomposition (Golub & Van Loan, Sec. 8.5), negative eigenvalues set
+ * to zero.  A matrix whose eigenvalues are all >= 0 is returned unchanged.
+ * The paper does not discuss definiteness of the tangent K (Sec. 2.2.5);
+ * projected Newton is the reading used here. */
+static void psd_project(double *A, int n) {
+  double W[81], V[81];
+  memcpy(W, A, sizeof(double) * (size_t)(n * n));
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+  double diag2 = 0.0;
+  for (int i = 0; i < n; ++i) diag2 += W[i * n + i] * W[i * n + i];
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += W[p * n + q] * W[p * n + q];
+    if (off <= 1e-32 * diag2 || off == 0.0) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = W[p * n + q];
+        if (apq == 0.0) continue;
+        const double theta = (W[q * n + q] - W[p * n + p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0);
+        const double s = t * c;
+        /* W <- W J, V <- V J (columns p, q) */
+        for (int k = 0; k < n; ++k) {
+          const double wkp = W[k * n + p], wkq = W[k * n + q];
+          W[k * n + p] = c * wkp - s * wkq;
+          W[k * n + q] = s * wkp + c * wkq;
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+        /* W <- J^T W (rows p, q) */
+        for (int k = 0; k < n; ++k) {
+          const double wpk = W[p * n + k], wqk = W[q * n + k];
+          W[p * n + k] = c * wpk - s * wqk;
+          W[q * n + k] = s * wpk + c * wqk;
+        }
+      }
+  }
+  int neg = 0;
+  for (int i = 0; i < n; ++i)
+    if (W[i * n + i] < 0.0) neg = 1;
+  if (!neg) return;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < n; ++k) {
+        const double lk = W[k * n + k] > 0.0 ? W[k * n + k] : 0.0;
+        v += V[i * n + k] * lk * V[j * n + k];
+      }
+      A[i * n + j] = v;
+    }
+}
+
+/* Exported for the constitutive pins. */
+int or_nh_eval(int d, const double *F, double mu, double lam, double *psi, double *P, double *A,
+               int project) {
+  *psi = nh_psi(F, d, mu, lam);
+  int rc = nh_stress(F, d, mu, lam, P, A);
+  if (rc) return rc;
+  if (A && project) psd_project(A, d * d);
+  return OR_OK;
+}
+
+int or_psd_project(double *A, int n) {
+  if (n < 1 || n > 9) return OR_E_ARG;
+  psd_project(A, n);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Incremental potential, gradient and Hessian-vector product           */
+/* (Eq. discrete_energy, Eq. F_update, Sec. 2.2.5)                      */
+/* ------------------------------------------------------------------ */
+
+/* Per-particle kinematics fixed for one implicit solve: the stencil nodes,
+ * N_ip and c_ip = F_p^nT grad N_ip(x_p^n), so that
+ * F_p(u) = (I + sum_i u_i grad N_ip^T) F_p^n = F_p^n + sum_i u_i c_ip^T. */
+typedef struct {
+  int ss, d;
+  int *node;   /* [np][ss] */
+  double *N;   /* [np][ss] */
+  double *c;   /* [np][ss][d] */
+} kin;
+
+static void kin_free(kin *K) {
+  free(K->node);
+  free(K->N);
+  free(K->c);
+}
+
+static int kin_build(const or_domain *D, kin *K) {
+  const int d = D->dim, ss = stencil_size(D);
+  K->ss = ss;
+  K->d = d;
+  size_t np = (size_t)(D->np > 0 ? D->np : 1);
+  K->node = (int *)malloc(sizeof(int) * np * ss);
+  K->N = (double *)malloc(sizeof(double) * np * ss);
+  K->c = (double *)malloc(sizeof(double) * np * ss * d);
+  if (!K->node || !K->N || !K->c) {
+    kin_free(K);
+    return OR_E_NOMEM;
+  }
+  for (int p = 0; p < D->np; ++p) {
+    stencil st;
+    if (stencil_at(D, &D->x[p * d], &st)) {
+      kin_free(K);
+      return OR_E_OUT_OF_GRID;
+    }
+    const double *Fn = &D->F[p * d * d];
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      K->node[p * ss + s] = i;
+      K->N[p * ss + s] = N;
+      for (int b = 0; b < d; ++b) {
+        double cb = 0.0;
+        for (int e = 0; e < d; ++e) cb += Fn[e * d + b] * gN[e];
+        K->c[(p * ss + s) * d + b] = cb;
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* F_p(u) = F_p^n + sum_i u_i c_ip^T */
+static void particle_F(const or_domain *D, const kin *K, int p, const double *u, double *F) {
+  const int d = D->dim, ss = K->ss;
+  for (int k = 0; k < d * d; ++k) F[k] = D->F[p * d * d + k];
+  for (int s = 0; s < ss; ++s) {
+    const int i = K->node[p * ss + s];
+    const double *c = &K->c[(p * ss + s) * d];
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) F[a * d + b] += u[i * d + a] * c[b];
+  }
+}
+
+static int is_active(const or_domain *D, int i) { return D->m[i] > 0.0; }
+
+/* E(u) = sum_i m_i/(2 dt^2) |u_i - dt v_i^n|^2 + sum_p V_p Psi(F_p(u)) - sum_i m_i g.u_i
+ * (Eq. discrete_energy with x_hat = x^n + u, x_tilde = x^n + dt v^n and
+ * f_ext = m_i g; the constant -sum x_i^n . f_ext is dropped). */
+static double energy_k(const or_domain *D, const kin *K, double dt, const double *grav,
+                       const double *u) {
+  const int d = D->dim, nn = nnodes(D);
+  double E = 0.0;
+  for (int i = 0; i < nn; ++i) {
+    if (!is_active(D, i)) continue;
+    double s2 = 0.0, gu = 0.0;
+    for (int a = 0; a < d; ++a) {
+      const double r = u[i * d + a] - dt * D->vn[i * d + a];
+      s2 += r * r;
+      gu += grav[a] * u[i * d + a];
+    }
+    E += D->m[i] / (2.0 * dt * dt) * s2 - D->m[i] * gu;
+  }
+  for (int p = 0; p < D->np; ++p) {
+    double F[9];
+    particle_F(D, K, p, u, F);
+    const int mt = D->mat[p];
+    E += D->vol[p] * nh_psi(F, d, D->mu[mt], D->lam[mt]);
+  }
+  return E;
+}
+
+/* grad E: m_i/dt^2 (u_i - dt v_i) - m_i g + sum_p V_p P(F_p) c_ip  on every
+ * active node (the negative of the residual of Eq. grid_residual). */
+static int gradient_k(const or_domain *D, const kin *K, double dt, const double *grav,
+                      const double *u, double *g) {
+  const int d = D->dim, nn = nnodes(D), ss = K->ss;
+  for (int i = 0; i < nn * d; ++i) g[i] = 0.0;
+  for (int p = 0; p < D->np; ++p) {
+    double F[9], P[9];
+    particle_F(D, K, p, u, F);
+    const int mt = D->mat[p];
+    if (nh_stress(F, d, D->mu[mt], D->lam[mt], P, NULL)) return OR_E_INVERTED;
+    for (int s = 0; s < ss; ++s) {
+      const int i = K->node[p * ss + s];
+      const double *c = &K->c[(p * ss + s) * d];
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < d; ++b) t += P[a * d + b] * c[b];
+        g[i * d + a] += D->vol[p] * t;
+      }
+    }
+  }
+  for (int i = 0; i < nn; ++i) {
+    if (!is_active(D, i)) continue;
+    for (int a = 0; a < d; ++a)
+      g[i * d + a] += D->m[i] / (dt * dt) * (u[i * d + a] - dt * D->vn[i * d + a]) - D->m[i] * grav[a];
+  }
+  return OR_OK;
+}
+
+/* dP/dF of every particle at u, optionally PSD-projected: A_p, [np][d^4]. */
+static int hessian_blocks(const or_domain *D, const kin *K, const double *u, int project,
+                          double *A) {
+  const int d = D->dim, n = d * d;
+  for (int p = 0; p < D->np; ++p) {
+    double F[9];
+    particle_F(D, K, p, u, F);
+    const int mt = D->mat[p];
+    double *Ap = &A[(size_t)p * n * n];
+    if (nh_stress(F, d, D->mu[mt], D->lam[mt], NULL, Ap)) return OR_E_INVERTED;
+    if (project) psd_project(Ap, n);
+  }
+  return OR_OK;
+}
+
+/* (H w)_i = m_i/dt^2 w_i + sum_p V_p (A_p : dF_p) c_ip, dF_p = sum_j w_j c_jp^T
+ * (the Hessian of E, Sec. 2.2.5, applied through the particles). */
+static void hvp_k(const or_domain *D, const kin *K, const double *A, double dt, const double *w,
+                  double *y) {
+  const int d = D->dim, nn = nnodes(D), ss = K->ss, n = d * d;
+  for (int i = 0; i < nn * d; ++i) y[i] = 0.0;
+  for (int p = 0; p < D->np; ++p) {
+    double dF[9] = {0};
+    for (int s = 0; s < ss; ++s) {
+      const int j = K->node[p * ss + s];
+      const double *c = &K->c[(p * ss + s) * d];
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) dF[a * d + b] += w[j * d + a] * c[b];
+    }
+    const double *Ap = &A[(size_t)p * n * n];
+    double dP[9];
+    for (int r = 0; r < n; ++r) {
+      double t = 0.0;
+      for (int q = 0; q < n; ++q) t += Ap[r * n + q] * dF[q];
+      dP[r] = t;
+    }
+    for (int s = 0; s < ss; ++s) {
+      const int i = K->node[p * ss + s];
+      const double *c = &K->c[(p * ss + s) * d];
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < d; ++b) t += dP[a * d + b] * c[b];
+        y[i * d + a] += D->vol[p] * t;
+      }
+    }
+  }
+  for (int i = 0; i < nn; ++i) {
+    if (!is_active(D, i)) continue;
+    for (int a = 0; a < d; ++a) y[i * d + a] += D->m[i] / (dt * dt) * w[i * d + a];
+  }
+}
+
+/* Jacobi diagonal of H: m_i/dt^2 + sum_p V_p sum_{b,e} A_(ab),(ae) c_b c_e. */
+static void diag_k(const or_domain *D, const kin *K, const double *A, double dt, double *dg) {
+  const int d = D->dim, nn = nnodes(D), ss = K->ss, n = d * d;
+  for (int i = 0; i < nn * d; ++i) dg[i] = 0.0;
+  for (int p = 0; p < D->np; ++p) {
+    const double *Ap = &A[(size_t)p * n * n];
+    for (int s = 0; s < ss; ++s) {
+      const int i = K->node[p * ss + s];
+      const double *c = &K->c[(p * ss + s) * d];
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < d; ++b)
+          for (int e = 0; e < d; ++e) t += Ap[(a * d + b) * n + (a * d + e)] * c[b] * c[e];
+        dg[i * d + a] += D->vol[p] * t;
+      }
+    }
+  }
+  for (int i = 0; i < nn; ++i) {
+    if (!is_active(D, i)) continue;
+    for (int a = 0; a < d; ++a) dg[i * d + a] += D->m[i] / (dt * dt);
+  }
+}
+
+/* E(u + alpha du) - E(u), evaluated term by term in a form free of the
+ * cancellation of two large totals (exact arithmetic gives the difference of
+ * two energies; this is the comparison of the halving line search, Sec. 2.2.5):
+ *   inertia:  m/(2dt^2) (2 alpha r.du + alpha^2 |du|^2), r = u - dt v^n
+ *   gravity: -alpha m g.du
+ *   elastic:  V [mu/2 (2 F:D + D:D) - mu L + lam/2 L (2 ln J + L)],
+ *             D = alpha sum du_i c_i^T, L = log1p(dJ/J),
+ *             dJ = det(F+D) - det F expanded in powers of D.
+ * Returns +inf when any particle reaches J <= 0. */
+static double delta_energy_k(const or_domain *D, const kin *K, double dt, const double *grav,
+                             const double *u, const double *du, double alpha) {
+  const int d = D->dim, nn = nnodes(D), ss = K->ss;
+  double dE = 0.0;
+  for (int i = 0; i < nn; ++i) {
+    if (!is_active(D, i)) continue;
+    double rd = 0.0, dd = 0.0, gd = 0.0;
+    for (int a = 0; a < d; ++a) {
+      const double r = u[i * d + a] - dt * D->vn[i * d + a];
+      rd += r * du[i * d + a];
+      dd += du[i * d + a] * du[i * d + a];
+      gd += grav[a] * du[i * d + a];
+    }
+    dE += D->m[i] / (2.0 * dt * dt) * (2.0 * alpha * rd + alpha * alpha * dd) - alpha * D->m[i] * gd;
+  }
+  for (int p = 0; p < D->np; ++p) {
+    double F[9], Dm[9] = {0};
+    particle_F(D, K, p, u, F);
+    for (int s = 0; s < ss; ++s) {
+      const int j = K->node[p * ss + s];
+      const double *c = &K->c[(p * ss + s) * d];
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) Dm[a * d + b] += du[j * d + a] * c[b];
+    }
+    for (int k = 0; k < d * d; ++k) Dm[k] *= alpha;
+    const double J = det_d(F, d);
+    double CF[9], CD[9];
+    cofactor(F, d, CF);
+    double dJ = 0.0;
+    if (d == 2) {
+      for (int k = 0; k < 4; ++k) dJ += CF[k] * Dm[k];
+      dJ += det_d(Dm, 2);
+    } else {
+      cofactor(Dm, 3, CD);
+      for (int k = 0; k < 9; ++k) dJ += CF[k] * Dm[k];
+      for (int k = 0; k < 9; ++k) dJ += F[k] * CD[k];
+      dJ += det_d(Dm, 3);
+    }
+    if (!(J > 0.0) || !(J + dJ > 0.0)) return INFINITY;
+    const double lnJ = log(J);
+    const double L = log1p(dJ / J);
+    double FD = 0.0, DD = 0.0;
+    for (int k = 0; k < d * d; ++k) {
+      FD += F[k] * Dm[k];
+      DD += Dm[k] * Dm[k];
+    }
+    const int mt = D->mat[p];
+    const double mu = D->mu[mt], lam = D->lam[mt];
+    dE += D->vol[p] * (0.5 * mu * (2.0 * FD + DD) - mu * L + 0.5 * lam * L * (2.0 * lnJ + L));
+  }
+  return dE;
+}
+
+/* ------------------------------------------------------------------ */
+/* Dirichlet data                                                       */
+/* ------------------------------------------------------------------ */
+
+/* Prescribed displacement of DOF (i, a) for scene group g over a step dt.
+ * FIX: 0.  TRANSLATE: dt * velocity.  ROTATE: incremental rigid rotation of
+ * the node position about an axis (Rodrigues). */
+static double scene_value(const or_domain *D, int g, int i, int a, double dt) {
+  const double *pr = &D->bc_param[8 * g];
+  if (D->bc_kind[g] == BC_FIX) return 0.0;
+  if (D->bc_kind[g] == BC_TRANSLATE) return dt * pr[a];
+  /* ROTATE: pr = {cx, cy, cz, kx, ky, kz, omega}; 3D only */
+  int idx[3];
+  double xi[3] = {0, 0, 0};
+  node_index(D, i, idx);
+  node_pos(D, idx, xi);
+  const double th = pr[6] * dt;
+  const double r[3] = {xi[0] - pr[0], xi[1] - pr[1], xi[2] - pr[2]};
+  const double k[3] = {pr[3], pr[4], pr[5]};
+  const double kr = k[0] * r[0] + k[1] * r[1] + k[2] * r[2];
+  const double kxr[3] = {k[1] * r[2] - k[2] * r[1], k[2] * r[0] - k[0] * r[2], k[0] * r[1] - k[1] * r[0]};
+  const double ct = cos(th), st = sin(th);
+  const double rr = r[a] * ct + kxr[a] * st + k[a] * kr * (1.0 - ct);
+  return rr - r[a];
+}
+
+/* Dirichlet flags and values of every DOF for a step dt: scene groups first,
+ * then the Schwarz receivers (velocity data times dt); only active nodes. */
+int or_dirichlet(const or_domain *D, double dt, unsigned char *dir, double *ud) {
+  const int d = D->dim, nn = nnodes(D);
+  for (int i = 0; i < nn; ++i)
+    for (int a = 0; a < d; ++a) {
+      dir[i * d + a] = 0;
+      ud[i * d + a] = 0.0;
+      if (!is_active(D, i)) continue;
+      const int g = D->bcg[i * d + a];
+      if (g >= 0) {
+        dir[i * d + a] = 1;
+        ud[i * d + a] = scene_value(D, g, i, a, dt);
+      } else if (D->use_schwarz_bc && D->recv[i]) {
+        dir[i * d + a] = 1;
+        ud[i * d + a] = dt * D->vbc[i * d + a];
+      }
+    }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Newton's method with Jacobi-PCG and halving line search (Sec. 2.2.5) */
+/* ------------------------------------------------------------------ */
+
+static double dot_masked(const double *a, const double *b, const unsigned char *fr, int n) {
+  double s = 0.0;
+  for (int k = 0; k < n; ++k)
+    if (fr[k]) s += a[k] * b[k];
+  return s;
+}
+
+/* Minimises E over the free DOFs (active and not Dirichlet).  u^0 = dt v^n on
+ * free DOFs and the prescribed values on Dirichlet DOFs.  Stop when
+ * |g_free| <= max(rtol |g_free(u^0)|, atol * sum_i m_i * dx / dt^2), tested
+ * before the line search (the paper gives no stopping rule; the absolute
+ * floor keeps a nearly equilibrated solve from iterating on rounding noise).
+ * Direction: PCG from 0 on H d = -g with the Jacobi preconditioner, stop at
+ * |r| <= cg_rtol |r_0|.  Line search: alpha = 1, halved while E does not
+ * decrease, at most max_ls halvings; failure keeps u and ends the solve. */
+int or_solve(or_domain *D, double dt, const or_solve_opts *opt, or_solve_stats *st) {
+  const int d = D->dim, nn = nnodes(D), n = d * d, ndof = nn * d;
+  memset(st, 0, sizeof(*st));
+  kin K;
+  int rc = kin_build(D, &K);
+  if (rc) return rc;
+  unsigned char *dir = (unsigned char *)malloc((size_t)ndof);
+  unsigned char *fr = (unsigned char *)malloc((size_t)ndof);
+  double *ud = (double *)malloc(sizeof(double) * ndof);
+  double *g = (double *)malloc(sizeof(double) * ndof);
+  double *dg = (double *)malloc(sizeof(double) * ndof);
+  double *del = (double *)malloc(sizeof(double) * ndof);
+  double *r = (double *)malloc(sizeof(double) * ndof);
+  double *z = (double *)malloc(sizeof(double) * ndof);
+  double *pv = (double *)malloc(sizeof(double) * ndof);
+  double *q = (double *)malloc(sizeof(double) * ndof);
+  double *A = (double *)malloc(sizeof(double) * (size_t)(D->np > 0 ? D->np : 1) * n * n);
+  if (!dir || !fr || !ud || !g || !dg || !del || !r || !z || !pv || !q || !A) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
+  or_dirichlet(D, dt, dir, ud);
+  for (int i = 0; i < nn; ++i)
+    for (int a = 0; a < d; ++a) {
+      const int k = i * d + a;
+      fr[k] = (unsigned char)(is_active(D, i) && !dir[k]);
+      if (!is_active(D, i))
+        D->u[k] = 0.0;
+      else if (dir[k])
+        D->u[k] = ud[k];
+      else
+        D->u[k] = dt * D->vn[k];
+    }
+  /* gradient scale of the absolute floor: total node mass * dx / dt^2, the
+   * force that displaces the whole domain by one cell in one step */
+  double mtot = 0.0;
+  for (int i = 0; i < nn; ++i)
+    if (is_active(D, i)) mtot += D->m[i];
+  const double gscale = mtot * grid_dx(D) / (dt * dt);
+  for (int it = 0;; ++it) {
+    rc = gradient_k(D, &K, dt, opt->gravity, D->u, g);
+    if (rc) goto done;
+    const double gn = sqrt(dot_masked(g, g, fr, ndof));
+    if (it == 0) st->gnorm0 = gn;
+    st->gnorm = gn;
+    const double tol = fmax(opt->newton_rtol * st->gnorm0, opt->newton_atol * gscale);
+    if (gn <= tol) {
+      st->converged = 1;
+      break;
+    }
+    if (it == opt->max_newton) break;
+    rc = hessian_blocks(D, &K, D->u, opt->project_psd, A);
+    if (rc) goto done;
+    diag_k(D, &K, A, dt, dg);
+    /* PCG on H del = -g */
+    for (int k = 0; k < ndof; ++k) {
+      del[k] = 0.0;
+      r[k] = fr[k] ? -g[k] : 0.0;
+      z[k] = fr[k] ? r[k] / dg[k] : 0.0;
+      pv[k] = z[k];
+    }
+    double rz = dot_masked(r, z, fr, ndof);
+    const double r0 = sqrt(dot_masked(r, r, fr, ndof));
+    for (int k = 0; k < opt->max_cg && r0 > 0.0; ++k) {
+      hvp_k(D, &K, A, dt, pv, q);
+      for (int j = 0; j < ndof; ++j)
+        if (!fr[j]) q[j] = 0.0;
+      const double pq = dot_masked(pv, q, fr, ndof);
+      if (!(pq > 0.0)) break;
+      const double alpha = rz / pq;
+      for (int j = 0; j < ndof; ++j) {
+        del[j] += alpha * pv[j];
+        r[j] -= alpha * q[j];
+      }
+      st->cg_iters += 1;
+      if (sqrt(dot_masked(r, r, fr, ndof)) <= opt->cg_rtol * r0) break;
+      for (int j = 0; j < ndof; ++j) z[j] = fr[j] ? r[j] / dg[j] : 0.0;
+      const double rz_new = dot_masked(r, z, fr, ndof);
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      for (int j = 0; j < ndof; ++j) pv[j] = z[j] + beta * pv[j];
+    }
+    /* halving line search */
+    double alpha = 1.0;
+    int accepted = 0;
+    for (int ls = 0; ls <= opt->max_ls; ++ls) {
+      const double dE = delta_energy_k(D, &K, dt, opt->gravity, D->u, del, alpha);
+      if (dE < 0.0) {
+        accepted = 1;
+        break;
+      }
+      if (ls == opt->max_ls) break;
+      alpha *= 0.5;
+      st->ls_halvings += 1;
+    }
+    if (!accepted) {
+      st->ls_failed = 1;
+      break;
+    }
+    for (int j = 0; j < ndof; ++j) D->u[j] += alpha * del[j];
+    st->newton_iters += 1;
+  }
+  st->energy = energy_k(D, &K, dt, opt->gravity, D->u);
+  rc = OR_OK;
+done:
+  kin_free(&K);
+  free(dir);
+  free(fr);
+  free(ud);
+  free(g);
+  free(dg);
+  free(del);
+  free(r);
+  free(z);
+  free(pv);
+  free(q);
+  free(A);
+  return rc;
+}
+
+/* Exported single pieces, for the finite-difference pins. */
+int or_energy(const or_domain *D, double dt, const double *grav, const double *u, double *E) {
+  kin K;
+  int rc = kin_build(D, &K);
+  if (rc) return rc;
+  *E = energy_k(D, &K, dt, grav, u);
+  kin_free(&K);
+  return OR_OK;
+}
+
+int or_delta_energy(const or_domain *D, double dt, const double *grav, const double *u,
+                    const double *du, double alpha, double *dE) {
+  kin K;
+  int rc = kin_build(D, &K);
+  if (rc) return rc;
+  *dE = delta_energy_k(D, &K, dt, grav, u, du, alpha);
+  kin_free(&K);
+  return OR_OK;
+}
+
+int or_gradient(const or_domain *D, double dt, const double *grav, const double *u, double *g) {
+  kin K;
+  int rc = kin_build(D, &K);
+  if (rc) return rc;
+  rc = gradient_k(D, &K, dt, grav, u, g);
+  kin_free(&K);
+  return rc;
+}
+
+int or_hvp(const or_domain *D, double dt, const double *u, const double *w, int project, double *y,
+           double *diag) {
+  const int n = D->dim * D->dim;
+  kin K;
+  int rc = kin_build(D, &K);
+  if (rc) return rc;
+  double *A = (double *)malloc(sizeof(double) * (size_t)(D->np > 0 ? D->np : 1) * n * n);
+  if (!A) {
+    kin_free(&K);
+    return OR_E_NOMEM;
+  }
+  rc = hessian_blocks(D, &K, u, project, A);
+  if (!rc) {
+    if (y) hvp_k(D, &K, A, dt, w, y);
+    if (diag) diag_k(D, &K, A, dt, diag);
+  }
+  free(A);
+  kin_free(&K);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* APIC grid-to-particle, F update, advection (Eqs. g2p_v, g2p_B,       */
+/* F_update, advection; Eqs. g2p_v_substep .. advect_substep)           */
+/* ------------------------------------------------------------------ */
+
+/* With v_i = u_i / dt on the active nodes:
+ *   v_p = sum N_ip v_i,  B_p = sum N_ip v_i (x_i - x_p)^T,
+ *   F_p <- (I + sum u_i grad N_ip^T) F_p,  x_p <- x_p + dt v_p. */
+int or_g2p(or_domain *D, double dt) {
+  const int d = D->dim, ss = stencil_size(D);
+  for (int p = 0; p < D->np; ++p) {
+    stencil st;
+    if (stencil_at(D, &D->x[p * d], &st)) return OR_E_OUT_OF_GRID;
+    double vp[3] = {0, 0, 0}, Bp[9] = {0}, G[9] = {0};
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      if (!is_active(D, i)) continue;
+      for (int a = 0; a < d; ++a) {
+        const double vi = D->u[i * d + a] / dt;
+        vp[a] += N * vi;
+        for (int b = 0; b < d; ++b) {
+          Bp[a * d + b] += N * vi * dxv[b];
+          G[a * d + b] += D->u[i * d + a] * gN[b];
+        }
+      }
+    }
+    double *Fp = &D->F[p * d * d];
+    double Fnew[9];
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double t = Fp[a * d + b];
+        for (int e = 0; e < d; ++e) t += G[a * d + e] * Fp[e * d + b];
+        Fnew[a * d + b] = t;
+      }
+    for (int k = 0; k < d * d; ++k) {
+      Fp[k] = Fnew[k];
+      D->B[p * d * d + k] = Bp[k];
+    }
+    for (int a = 0; a < d; ++a) {
+      D->v[p * d + a] = vp[a];
+      D->x[p * d + a] += dt * vp[a];
+    }
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Interface operators (Sec. 3.2)                                       */
+/* ------------------------------------------------------------------ */
+
+/* Gamma_alpha = {i : sum_{p in boundary layer} m_p N_ip > tau} with the sum
+ * in fixed point (Eq. boundary_grid_set). */
+static int boundary_set(or_domain *D) {
+  const int d = D->dim, nn = nnodes(D), ss = stencil_size(D);
+  const double scale = fixed_scale(D);
+  const long long tau_q = llrint(D->tau * scale);
+  for (int i = 0; i < nn; ++i) D->q_bnd[i] = 0;
+  for (int p = 0; p < D->np; ++p) {
+    if (!(D->flags[p] & 1u)) continue;
+    stencil st;
+    if (stencil_at(D, &D->x[p * d], &st)) return OR_E_OUT_OF_GRID;
+    const double mq = D->mass[p] * scale;
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      D->q_bnd[i] += fixed_mass(N, mq);
+    }
+  }
+  for (int i = 0; i < nn; ++i) {
+    D->gamma[i] = (unsigned char)(D->q_bnd[i] > tau_q && is_active(D, i));
+    D->recv[i] = D->gamma[i];
+  }
+  return OR_OK;
+}
+
+/* Boundary sets of both domains and the overlap arbitration (Eq.
+ * overlap_donor): a coarse node and a fine node at the same lattice point,
+ * both in their boundary sets, are ambiguous; the side with the larger
+ * fixed-point node mass is the donor (ties: the coarse side) and is removed
+ * from its own receiver set. */
+int or_interface(or_domain *B, or_domain *S, int *n_amb) {
+  if (B->dim != S->dim || B->m_ref != S->m_ref || B->h0 != S->h0) return OR_E_ARG;
+  int rc = boundary_set(B);
+  if (rc) return rc;
+  rc = boundary_set(S);
+  if (rc) return rc;
+  const int d = B->dim, nnB = nnodes(B);
+  int amb = 0;
+  for (int I = 0; I < nnB; ++I) {
+    if (!B->gamma[I]) continue;
+    int iB[3], jS[3] = {0, 0, 0};
+    node_index(B, I, iB);
+    int hit = 1;
+    for (int a = 0; a < d; ++a) {
+      const long long L = B->origin_q[a] + (long long)iB[a] * B->dx_q;
+      const long long t = L - S->origin_q[a];
+      if (t < 0 || t % S->dx_q != 0 || t / S->dx_q >= S->n[a]) {
+        hit = 0;
+        break;
+      }
+      jS[a] = (int)(t / S->dx_q);
+    }
+    if (!hit) continue;
+    const int j = node_flat(S, jS);
+    if (!S->gamma[j]) continue;
+    amb += 1;
+    if (B->q_all[I] >= S->q_all[j])
+      B->recv[I] = 0; /* coarse side donates */
+    else
+      S->recv[j] = 0; /* fine side donates */
+  }
+  *n_amb = amb;
+  return OR_OK;
+}
+
+/* Pi_{S->B} (Eq. spatial_projection) on the coarse receivers: every active
+ * fine node j is a point mass m_S,j at x_S,j; v_B,I = sum m_j v_j N_I(x_j) /
+ * (sum m_j N_I(x_j) + eps_tol).  Non-receivers get 0. */
+int or_project(const or_domain *S, const or_domain *B, double eps_tol, const double *vS,
+               double *out) {
+  const int d = B->dim, nnB = nnodes(B), nnS = nnodes(S), ss = stencil_size(B);
+  double *num = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *den = (double *)calloc((size_t)nnB, sizeof(double));
+  if (!num || !den) {
+    free(num);
+    free(den);
+    return OR_E_NOMEM;
+  }
+  for (int j = 0; j < nnS; ++j) {
+    if (!(S->m[j] > 0.0)) continue;
+    int jS[3];
+    double xj[3] = {0, 0, 0};
+    node_index(S, j, jS);
+    node_pos(S, jS, xj);
+    stencil st;
+    if (stencil_at(B, xj, &st)) {
+      free(num);
+      free(den);
+      return OR_E_OUT_OF_GRID;
+    }
+    for (int s = 0; s < ss; ++s) {
+      int I;
+      double N, gN[3], dxv[3];
+      stencil_node(B, &st, s, &I, &N, gN, dxv);
+      const double w = S->m[j] * N;
+      den[I] += w;
+      for (int a = 0; a < d; ++a) num[I * d + a] += w * vS[j * d + a];
+    }
+  }
+  for (int I = 0; I < nnB; ++I)
+    for (int a = 0; a < d; ++a)
+      out[I * d + a] = B->recv[I] ? num[I * d + a] / (den[I] + eps_tol) : 0.0;
+  free(num);
+  free(den);
+  return OR_OK;
+}
+
+/* I_{B->S} (Eq. interp_BtoS) on the fine receivers: v_S,j = sum_I v_B,I
+ * N_I(x_S,j), inactive coarse nodes carrying zero velocity.  Non-receivers
+ * get 0. */
+int or_interp(const or_domain *B, const double *vB, const or_domain *S, double *out) {
+  const int d = B->dim, nnS = nnodes(S), ss = stencil_size(B);
+  for (int j = 0; j < nnS; ++j) {
+    for (int a = 0; a < d; ++a) out[j * d + a] = 0.0;
+    if (!S->recv[j]) continue;
+    int jS[3];
+    double xj[3] = {0, 0, 0};
+    node_index(S, j, jS);
+    node_pos(S, jS, xj);
+    stencil st;
+    if (stencil_at(B, xj, &st)) return OR_E_OUT_OF_GRID;
+    for (int s = 0; s < ss; ++s) {
+      int I;
+      double N, gN[3], dxv[3];
+      stencil_node(B, &st, s, &I, &N, gN, dxv);
+      if (!(B->m[I] > 0.0)) continue;
+      for (int a = 0; a < d; ++a) out[j * d + a] += N * vB[I * d + a];
+    }
+  }
+  return OR_OK;
+}
+
+/* T_m (Eq. temporal_interp): (1 - m/M) v^n + (m/M) v^{n+1}. */
+void or_temporal(int n, int m, int M, const double *vn, const double *vn1, double *out) {
+  const double a = (double)m / (double)M;
+  for (int k = 0; k < n; ++k) out[k] = (1.0 - a) * vn[k] + a * vn1[k];
+}
+
+/* ------------------------------------------------------------------ */
+/* Frames                                                               */
+/* ------------------------------------------------------------------ */
+
+static double norm_diff_masked(const double *a, const double *b, const unsigned char *mask, int nn,
+                               int d, double *norm_a) {
+  double s = 0.0, t = 0.0;
+  for (int i = 0; i < nn; ++i) {
+    if (!mask[i]) continue;
+    for (int c = 0; c < d; ++c) {
+      const double e = a[i * d + c] - b[i * d + c];
+      s += e * e;
+      t += a[i * d + c] * a[i * d + c];
+    }
+  }
+  *norm_a = sqrt(t);
+  return sqrt(s);
+}
+
+/* One backward-Euler step of a single domain (Sec. 2.2): P2G, implicit
+ * solve, G2P with F update and advection. */
+int or_single_frame(or_domain *D, double dt, const or_solve_opts *opt, or_solve_stats *st) {
+  int rc = or_p2g(D);
+  if (rc) return rc;
+  D->use_schwarz_bc = 0;
+  rc = or_solve(D, dt, opt, st);
+  if (rc) return rc;
+  return or_g2p(D, dt);
+}
+
+/* One global frame t_n -> t_{n+1} of the multiplicative Schwarz method
+ * (Alg. 1, Secs. 3.3-3.5).  Readings where the paper is open:
+ *  - Pi reads the latest fine P2G grid (Step 0 at k = 0, the grid after the
+ *    last sub-step otherwise); the projected data computed for the residual
+ *    of iteration k is the coarse boundary data of iteration k+1;
+ *  - v_GS^(0) = I(v_B^n) (Step 0, "previous time step" velocity);
+ *  - residual denominators are floored at 1e-30, an empty receiver set gives
+ *    r = 0, and the frame ends after k_max iterations if not converged. */
+int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opts *o,
+                     or_schwarz_stats *st) {
+  const int d = B->dim, nnB = nnodes(B), nnS = nnodes(S), npS = S->np;
+  const double dt = dT / (double)o->M;
+  int rc = OR_OK;
+  memset(st, 0, sizeof(*st));
+  double *sx = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d);
+  double *sv = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d);
+  double *sB = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d * d);
+  double *sF = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d * d);
+  double *vBn = (double *)malloc(sizeof(double) * nnB * d);
+  double *vBk = (double *)malloc(sizeof(double) * nnB * d);
+  double *vGB = (double *)malloc(sizeof(double) * nnB * d);
+  double *vGBnew = (double *)malloc(sizeof(double) * nnB * d);
+  double *vGSprev = (double *)malloc(sizeof(double) * nnS * d);
+  double *vGSn = (double *)malloc(sizeof(double) * nnS * d);
+  double *vGSn1 = (double *)malloc(sizeof(double) * nnS * d);
+  if (!sx || !sv || !sB || !sF || !vBn || !vBk || !vGB || !vGBnew || !vGSprev || !vGSn || !vGSn1) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
+  /* Step 0: store fine state (Eq. store_states), P2G on both, boundary sets. */
+  memcpy(sx, S->x, sizeof(double) * npS * d);
+  memcpy(sv, S->v, sizeof(double) * npS * d);
+  memcpy(sB, S->B, sizeof(double) * npS * d * d);
+  memcpy(sF, S->F, sizeof(double) * npS * d * d);
+  if ((rc = or_p2g(B)) || (rc = or_p2g(S))) goto done;
+  if ((rc = or_interface(B, S, &st->n_amb))) goto done;
+  for (int i = 0; i < nnB; ++i) st->n_recv_B += B->recv[i];
+  for (int i = 0; i < nnS; ++i) st->n_recv_S += S->recv[i];
+  memcpy(vBn, B->vn, sizeof(double) * nnB * d);
+  if ((rc = or_project(S, B, o->eps_tol, S->vn, vGB))) goto done;
+  if ((rc = or_interp(B, vBn, S, vGSprev))) goto done;
+  for (int k = 0; k < o->k_max; ++k) {
+    or_solve_stats ss;
+    /* 1. coarse solve over dT with Pi data on the coarse receivers */
+    memcpy(B->vbc, vGB, sizeof(double) * nnB * d);
+    B->use_schwarz_bc = 1;
+    if ((rc = or_solve(B, dT, &o->coarse, &ss))) goto done;
+    st->newton_B += ss.newton_iters;
+    st->cg_B += ss.cg_iters;
+    st->ls_B += ss.ls_halvings;
+    for (int i = 0; i < nnB; ++i)
+      for (int a = 0; a < d; ++a) vBk[i * d + a] = (B->m[i] > 0.0) ? B->u[i * d + a] / dT : 0.0;
+    /* 2. fine sub-cycling from the restored state */
+    memcpy(S->x, sx, sizeof(double) * npS * d);
+    memcpy(S->v, sv, sizeof(double) * npS * d);
+    memcpy(S->B, sB, sizeof(double) * npS * d * d);
+    memcpy(S->F, sF, sizeof(double) * npS * d * d);
+    if ((rc = or_p2g(S))) goto done;
+    if ((rc = or_interp(B, vBn, S, vGSn))) goto done;
+    if ((rc = or_interp(B, vBk, S, vGSn1))) goto done;
+    for (int m = 1; m <= o->M; ++m) {
+      or_temporal(nnS * d, m, o->M, vGSn, vGSn1, S->vbc);
+      S->use_schwarz_bc = 1;
+      if ((rc = or_solve(S, dt, &o->fine, &ss))) goto done;
+      st->newton_S += ss.newton_iters;
+      st->cg_S += ss.cg_iters;
+      st->ls_S += ss.ls_halvings;
+      if ((rc = or_g2p(S, dt))) goto done;
+      if ((rc = or_p2g(S))) goto done;
+    }
+    /* 3. convergence check (Eqs. convergence_residuals, convergence_criterion) */
+    if ((rc = or_project(S, B, o->eps_tol, S->vn, vGBnew))) goto done;
+    double nB, nS;
+    const double dB = norm_diff_masked(vGBnew, vGB, B->recv, nnB, d, &nB);
+    const double dS = norm_diff_masked(vGSn1, vGSprev, S->recv, nnS, d, &nS);
+    st->r_B = dB / fmax(nB, 1e-30);
+    st->r_S = dS / fmax(nS, 1e-30);
+    memcpy(vGB, vGBnew, sizeof(double) * nnB * d);
+    memcpy(vGSprev, vGSn1, sizeof(double) * nnS * d);
+    st->iters = k + 1;
+    if (st->r_B <= o->eps_conv && st->r_S <= o->eps_conv) {
+      st->converged = 1;
+      break;
+    }
+  }
+  /* 4. post-convergence coarse G2P and advection (Sec. 3.5) */
+  rc = or_g2p(B, dT);
+done:
+  free(sx);
+  free(sv);
+  free(sB);
+  free(sF);
+  free(vBn);
+  free(vBk);
+  free(vGB);
+  free(vGBnew);
+  free(vGSprev);
+  free(vGSn);
+  free(vGSn1);
+  return rc;
+}
