@@ -1,0 +1,256 @@
+/*
+ * osmpm.h -- C ABI of the MI355X (gfx950) OS-MPM library.
+ *
+ * The library implements the hot path of the overlapping Schwarz space-time
+ * refinement method for the material point method (arXiv 2605.09097):
+ * per-subdomain implicit MPM steps (APIC particle-to-grid transfer, the
+ * backward-Euler incremental potential minimised by Newton's method whose
+ * linear systems are solved by matrix-free conjugate gradients with
+ * Hessian-vector products evaluated through the particles, APIC
+ * grid-to-particle transfer with the deformation-gradient update and
+ * advection) and the coupling of a coarse background domain B with a fine
+ * refined domain S (boundary-grid selection, overlap arbitration,
+ * mass-weighted projection Pi, interpolation I, temporal interpolation T and
+ * the multiplicative Schwarz frame).
+ *
+ * Conventions (every entry point):
+ *  - Pointers named *_host point to host memory; every other array pointer
+ *    is a device pointer on the context's device.  Arrays are dense and
+ *    row-major: per-particle vectors are [n][d], per-particle matrices
+ *    [n][d][d], per-node vectors [n_nodes][d] with nodes numbered x fastest
+ *    (i = ix + nx * (iy + ny * iz)).
+ *  - The caller owns every buffer it passes; the library copies what it
+ *    keeps and never frees caller memory.  Handles own their device storage
+ *    until destroyed.
+ *  - Work is enqueued on the context's stream and is asynchronous unless the
+ *    call returns statistics (those synchronise).  Errors raised on the
+ *    device (a particle outside its grid, an inverted particle at an accepted
+ *    iterate) are reported by the next synchronising call and by
+ *    osmpm_sync().
+ *  - Every call returns an osmpm_status; nothing throws across the ABI.
+ *    osmpm_last_error() gives a message for the last failure on a context.
+ *  - Non-convergence of Newton, CG, the line search or the Schwarz loop is
+ *    not an error: it is reported in the statistics with converged = 0.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef OSMPM_H
+#define OSMPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OSMPM_OK = 0,
+  OSMPM_E_INVALID_ARG = 1, /* bad argument, detected before any work is queued */
+  OSMPM_E_NO_MEMORY = 2,   /* device or pinned-host allocation failed */
+  OSMPM_E_DEVICE = 3,      /* HIP runtime error */
+  OSMPM_E_OUT_OF_GRID = 4, /* a particle's 3^d stencil left its grid */
+  OSMPM_E_INVERTED = 5,    /* det F <= 0 at an iterate that had to be evaluated */
+  OSMPM_E_STATE = 7        /* call out of order (e.g. solve before P2G) */
+} osmpm_status;
+
+typedef enum {
+  OSMPM_FP64 = 0,  /* every quantity in double precision */
+  OSMPM_MIXED = 1  /* FP32 bulk (P2G, stress blocks, Hessian-vector products, CG
+                      iterates) with FP64 Newton residual, line-search energy,
+                      CG dot products, Schwarz residuals and positions */
+} osmpm_precision;
+
+typedef enum { OSMPM_BC_FIX = 0, OSMPM_BC_TRANSLATE = 1, OSMPM_BC_ROTATE = 2 } osmpm_bc_kind;
+
+typedef struct osmpm_ctx osmpm_ctx;
+typedef struct osmpm_domain osmpm_domain;
+
+/* Structured grid of one subdomain on an integer lattice of pitch h0:
+ * node i sits at x_i = (origin_q + i * dx_q) * h0 (per axis), so nodes of
+ * two domains coincide exactly when their lattice coordinates are equal
+ * (the coincidence test of the overlap arbitration, Eq. overlap_donor). */
+typedef struct {
+  int32_t dim;         /* 2 or 3 */
+  int32_t n_nodes[3];  /* nodes per axis; n_nodes[2] = 1 in 2D */
+  double h0;           /* lattice pitch */
+  int64_t origin_q[3]; /* origin in lattice units */
+  int64_t dx_q;        /* grid spacing in lattice units */
+} osmpm_grid;
+
+/* Compressible Neo-Hookean material (Sec. 4): Young's modulus and Poisson
+ * ratio; Psi = mu/2 (|F|^2 - d) - mu ln J + lam/2 (ln J)^2. */
+typedef struct {
+  double E, nu;
+} osmpm_material;
+
+/* Newton / CG / line-search controls of one implicit solve (Sec. 2.2.5).
+ * Newton stops when |g_free| <= max(newton_rtol |g_free(u0)|,
+ * newton_atol * sum_i m_i * dx / dt^2) or after max_newton steps; CG stops at
+ * |r| <= cg_rtol |r0| or after max_cg iterations; the line search halves at
+ * most max_ls times.  project_psd = 1 projects each particle's dP/dF onto the
+ * PSD cone.  gravity is the body-force acceleration (f_ext = m_i g). */
+typedef struct {
+  double newton_rtol, newton_atol, cg_rtol;
+  int32_t max_newton, max_cg, max_ls;
+  int32_t project_psd;
+  double gravity[3];
+} osmpm_solve_opts;
+
+typedef struct {
+  int32_t newton_iters, cg_iters, ls_halvings, converged, ls_failed;
+  double gnorm0, gnorm;
+} osmpm_solve_stats;
+
+/* Multiplicative Schwarz controls (Alg. 1): sub-cycling ratio M = dT/dt,
+ * iteration cap k_max, convergence tolerance eps_conv on the relative
+ * interface-velocity changes r_B and r_S (Eq. convergence_criterion) and the
+ * vacuum regulariser eps_tol of the projection (Eq. spatial_projection). */
+typedef struct {
+  int32_t M, k_max;
+  double eps_conv, eps_tol;
+  osmpm_solve_opts coarse, fine;
+} osmpm_schwarz_opts;
+
+typedef struct {
+  int32_t iters, converged;
+  double r_B, r_S;
+  int32_t n_recv_B, n_recv_S, n_amb;
+  int32_t newton_B, newton_S, cg_B, cg_S, ls_B, ls_S;
+} osmpm_schwarz_stats;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on HIP device `device`.  `stream` is a hipStream_t
+ * borrowed from the caller (e.g. torch.cuda.current_stream().cuda_stream) or
+ * NULL for the default stream; the context never destroys it. */
+osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out);
+osmpm_status osmpm_ctx_set_stream(osmpm_ctx *ctx, void *stream);
+/* Waits for all queued work and reports device-side errors. */
+osmpm_status osmpm_sync(osmpm_ctx *ctx);
+const char *osmpm_last_error(const osmpm_ctx *ctx);
+void osmpm_ctx_destroy(osmpm_ctx *ctx);
+
+/* ---------------------------------------------------------------- domain */
+
+/* Creates a subdomain (Sec. 3.1) with room for `capacity` particles.  tile
+ * gives the cells per axis of one workgroup tile of the particle/grid
+ * kernels (0 = library default); the particle sort orders bins tile-major. */
+osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t precision,
+                                 int64_t capacity, const int32_t *tile_host, osmpm_domain **out);
+void osmpm_domain_destroy(osmpm_domain *dom);
+
+/* Material table (host array of n_mat entries). */
+osmpm_status osmpm_domain_set_materials(osmpm_domain *dom, const osmpm_material *mats_host,
+                                        int32_t n_mat);
+
+/* Copies n particles in: positions x [n][d], velocities v [n][d], affine
+ * matrices B [n][d][d], deformation gradients F [n][d][d], masses m_p and
+ * initial volumes V_p^0 [n], material indices [n] and flags [n] (bit 0: the
+ * particle belongs to the boundary layer P^partial of Sec. 3.2.1; bit 1+g:
+ * member of scene boundary-condition group g).  The library may reorder
+ * particles (binning); osmpm_get_particles returns each one's input index. */
+osmpm_status osmpm_domain_set_particles(osmpm_domain *dom, int64_t n, const double *x,
+                                        const double *v, const double *B, const double *F,
+                                        const double *mass, const double *vol, const int32_t *mat,
+                                        const uint8_t *flags);
+
+/* Node selection by particle mass (Eq. boundary_grid_set): node masses are
+ * summed in fixed point with unit m_ref / 2^32 (per contribution
+ * rint(N_ip * m_p * 2^32 / m_ref)), and a node is selected when its sum
+ * exceeds rint(tau * 2^32 / m_ref).  Both domains of a pair must use the same
+ * m_ref. */
+osmpm_status osmpm_domain_set_selection(osmpm_domain *dom, double m_ref, double tau);
+
+/* Scene Dirichlet groups (host arrays of n_groups <= 4 entries): kind
+ * (osmpm_bc_kind), component mask and 8 parameters each.  FIX: u = 0.
+ * TRANSLATE: u = dt * params[0..d-1] (a velocity).  ROTATE (3D): incremental
+ * rigid rotation about the axis through params[0..2] with unit direction
+ * params[3..5] at angular velocity params[6].  A node is constrained by the
+ * lowest group whose selected mass (as above) exceeds tau; scene groups take
+ * precedence over Schwarz data on the same DOF. */
+osmpm_status osmpm_domain_set_scene_bc(osmpm_domain *dom, int32_t n_groups, const int32_t *kind_host,
+                                       const int32_t *mask_host, const double *params_host);
+
+/* Particle-to-grid transfer (Eq. p2g_transfer): bins particles by the cell of
+ * their base node with a stable counting sort, then accumulates
+ * m_i = sum m_p N_ip and (mv)_i = sum m_p N_ip (v_p + B_p D_p^-1 (x_i - x_p)),
+ * D_p = dx^2/4 I, sets v_i = (mv)_i / m_i on active nodes (m_i > 0) and
+ * selects the scene-BC nodes. */
+osmpm_status osmpm_p2g(osmpm_domain *dom);
+
+/* One implicit backward-Euler solve over dt (Eq. discrete_energy, Sec. 2.2.5)
+ * on the grid of the last P2G: the displacement u = x_hat - x^n minimising
+ * E_h over the free DOFs.  use_schwarz_bc = 1 also prescribes
+ * u = dt * v_bc on the receiver nodes (osmpm_set_schwarz_bc).  Synchronises;
+ * stats may be NULL. */
+osmpm_status osmpm_implicit_solve(osmpm_domain *dom, double dt, int32_t use_schwarz_bc,
+                                  const osmpm_solve_opts *opts, osmpm_solve_stats *stats_host);
+
+/* Grid-to-particle transfer with v_i = u_i / dt (Eqs. g2p_v, g2p_B), the
+ * deformation-gradient update (Eq. F_update) and advection (Eq. advection). */
+osmpm_status osmpm_g2p(osmpm_domain *dom, double dt);
+
+/* Boundary sets Gamma_B, Gamma_S from the boundary-layer particles (Eq.
+ * boundary_grid_set) and the receiver sets after the mass arbitration of
+ * coincident boundary nodes (Eq. overlap_donor, ties to B).  Uses the grids
+ * of the last P2G of each domain.  n_amb_host (may be NULL) receives the
+ * number of ambiguous node pairs; synchronises when it is not NULL. */
+osmpm_status osmpm_interface_build(osmpm_domain *B, osmpm_domain *S, int32_t *n_amb_host);
+
+/* Pi_{S->B} (Eq. spatial_projection) of the fine field vS ([nS][d]; NULL =
+ * S's P2G velocity) over S's active nodes onto B's receivers:
+ * out_I = sum m_j v_j N_I(x_j) / (sum m_j N_I(x_j) + eps_tol); 0 elsewhere. */
+osmpm_status osmpm_project_S_to_B(osmpm_domain *S, osmpm_domain *B, double eps_tol,
+                                  const double *vS, double *out);
+
+/* I_{B->S} (Eq. interp_BtoS) of the coarse field vB ([nB][d]; NULL = B's P2G
+ * velocity) at S's receivers: out_j = sum_I v_I N_I(x_j), inactive coarse
+ * nodes contributing zero; 0 on non-receivers. */
+osmpm_status osmpm_interp_B_to_S(osmpm_domain *B, const double *vB, osmpm_domain *S, double *out);
+
+/* T_m (Eq. temporal_interp): out = (1 - m/M) vn + (m/M) vn1 over n values. */
+osmpm_status osmpm_temporal_interp(osmpm_ctx *ctx, int64_t n, int32_t m, int32_t M, const double *vn,
+                                   const double *vn1, double *out);
+
+/* Receiver velocities ([n_nodes][d]) prescribed by the next solve with
+ * use_schwarz_bc = 1. */
+osmpm_status osmpm_set_schwarz_bc(osmpm_domain *dom, const double *vbc);
+
+/* One global frame t_n -> t_n + dT of Alg. 1 on the pair (B, S): store the
+ * fine state, P2G on both, boundary sets and arbitration, then Schwarz
+ * iterations (Pi -> coarse solve -> restore fine state, P2G, I at both
+ * endpoints -> M fine sub-steps of T_m, solve, G2P, P2G -> residuals) until
+ * r_B <= eps_conv and r_S <= eps_conv or k_max, then the coarse G2P and
+ * advection.  Synchronises; stats may be NULL. */
+osmpm_status osmpm_schwarz_frame(osmpm_domain *B, osmpm_domain *S, double dT,
+                                 const osmpm_schwarz_opts *opts, osmpm_schwarz_stats *stats_host);
+
+/* One single-domain step: P2G, implicit solve, G2P.  Synchronises. */
+osmpm_status osmpm_single_frame(osmpm_domain *dom, double dt, const osmpm_solve_opts *opts,
+                                osmpm_solve_stats *stats_host);
+
+/* ---------------------------------------------------------------- readback */
+
+/* Particle state in the library's current order; id receives each
+ * particle's index in the last osmpm_domain_set_particles input.  Any output
+ * may be NULL. */
+osmpm_status osmpm_get_particles(osmpm_domain *dom, double *x, double *v, double *B, double *F,
+                                 int32_t *id);
+/* Grid of the last P2G / solve: node mass m [n_nodes], P2G velocity vn and
+ * displacement u [n_nodes][d].  Any output may be NULL. */
+osmpm_status osmpm_get_grid(osmpm_domain *dom, double *m, double *vn, double *u);
+/* Interface sets: gamma and recv flags [n_nodes] (uint8) and the fixed-point
+ * node mass of all particles q_all [n_nodes] (int64).  Any may be NULL. */
+osmpm_status osmpm_get_sets(osmpm_domain *dom, uint8_t *gamma, uint8_t *recv, int64_t *q_all);
+/* The permutation applied by the last sort (perm[i] = position before the
+ * sort of the particle now at i) and the bin offsets cell_start
+ * [n_keys + 1]. */
+osmpm_status osmpm_get_sort(osmpm_domain *dom, int32_t *perm, int32_t *cell_start);
+/* Sizes: particles, nodes, sort keys (host outputs, any may be NULL). */
+osmpm_status osmpm_domain_info(osmpm_domain *dom, int64_t *n_particles, int64_t *n_nodes,
+                               int64_t *n_keys);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSMPM_H */

@@ -1,0 +1,345 @@
+// Device-side building blocks of the OS-MPM kernels (gfx950, wave64).
+//
+// Grid geometry, the quadratic B-spline stencil, the compressible
+// Neo-Hookean stress and its tangent, the per-particle PSD projection, and
+// wave/workgroup reductions.  Arithmetic that decides an integer (the base
+// node of a particle, the fixed-point node masses) is written with FMA
+// contraction disabled so that it rounds exactly like the definition.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace osmpm {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 waves)
+constexpr int kMaxGroups = 4;
+
+// Error bits raised by kernels (OR-ed into a device word).
+constexpr int kErrOutOfGrid = 1;
+constexpr int kErrInverted = 2;
+constexpr int kErrTile = 4;
+
+struct GridDev {
+  int n[3];          // nodes per axis
+  int nn;            // total nodes
+  double origin[3];  // (double)origin_q * h0
+  double dx, inv_dx; // (double)dx_q * h0 and 1 / dx
+  long long origin_q[3];
+  long long dx_q;
+  double h0;
+};
+
+// Tiles of T cells (base-node positions) per axis; a tile's LDS region holds
+// the (T + 2)^d nodes its particles touch.
+struct TileGeom {
+  int T[3], nt[3], R[3];
+  int nreg, tvol, ntiles, nblocks;
+};
+
+struct SceneBC {
+  int n_groups;
+  int kind[kMaxGroups];
+  int mask[kMaxGroups];
+  double param[kMaxGroups][8];
+};
+
+template <int D>
+struct Stencil {
+  int base[D];
+  double f[D];
+  double w[D][3];
+  double dw[D][3];
+};
+
+// Quadratic B-spline weights of a point: xi = (x - o) / dx, base =
+// floor(xi - 1/2), f = xi - base.  Returns false when the 3^d stencil leaves
+// the grid; the base is then clamped so every later access stays in bounds.
+template <int D>
+__device__ inline bool stencil_eval(const double *xp, const GridDev &g, Stencil<D> &s) {
+#pragma clang fp contract(off)
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double xi = (xp[a] - g.origin[a]) * g.inv_dx;
+    double bf = __builtin_floor(xi - 0.5);
+    const double hi = (double)(g.n[a] - 3);
+    if (!(bf >= 0.0 && bf <= hi)) {
+      ok = false;
+      bf = (bf > hi) ? hi : 0.0;
+    }
+    const double f = xi - bf;
+    const double t0 = 1.5 - f, t1 = f - 1.0, t2 = f - 0.5;
+    s.base[a] = (int)bf;
+    s.f[a] = f;
+    s.w[a][0] = 0.5 * (t0 * t0);
+    s.w[a][1] = 0.75 - t1 * t1;
+    s.w[a][2] = 0.5 * (t2 * t2);
+    s.dw[a][0] = -t0 * g.inv_dx;
+    s.dw[a][1] = -2.0 * t1 * g.inv_dx;
+    s.dw[a][2] = t2 * g.inv_dx;
+  }
+  return ok;
+}
+
+// N_ip of stencil offset k: w_x w_y in 2D, (w_x w_y) w_z in 3D (this product
+// order feeds the fixed-point masses).
+template <int D>
+__device__ inline double stencil_N(const Stencil<D> &s, const int *k) {
+#pragma clang fp contract(off)
+  if constexpr (D == 2) {
+    return s.w[0][k[0]] * s.w[1][k[1]];
+  } else {
+    return (s.w[0][k[0]] * s.w[1][k[1]]) * s.w[2][k[2]];
+  }
+}
+
+template <int D>
+__device__ inline void stencil_gradN(const Stencil<D> &s, const int *k, double *gN) {
+  if constexpr (D == 2) {
+    gN[0] = s.dw[0][k[0]] * s.w[1][k[1]];
+    gN[1] = s.w[0][k[0]] * s.dw[1][k[1]];
+  } else {
+    gN[0] = (s.dw[0][k[0]] * s.w[1][k[1]]) * s.w[2][k[2]];
+    gN[1] = (s.w[0][k[0]] * s.dw[1][k[1]]) * s.w[2][k[2]];
+    gN[2] = (s.w[0][k[0]] * s.w[1][k[1]]) * s.dw[2][k[2]];
+  }
+}
+
+template <int D>
+constexpr int stencil_count() {
+  return D == 3 ? 27 : 9;
+}
+
+template <int D>
+__device__ inline void stencil_offset(int s, int *k) {
+  k[0] = s % 3;
+  k[1] = (s / 3) % 3;
+  if constexpr (D == 3) k[2] = s / 9;
+}
+
+template <int D>
+__device__ inline int node_flat(const GridDev &g, const int *idx) {
+  if constexpr (D == 2) {
+    return idx[0] + g.n[0] * idx[1];
+  } else {
+    return idx[0] + g.n[0] * (idx[1] + g.n[1] * idx[2]);
+  }
+}
+
+template <int D>
+__device__ inline void node_unflat(const GridDev &g, int i, int *idx) {
+  idx[0] = i % g.n[0];
+  if constexpr (D == 2) {
+    idx[1] = i / g.n[0];
+  } else {
+    idx[1] = (i / g.n[0]) % g.n[1];
+    idx[2] = i / (g.n[0] * g.n[1]);
+  }
+}
+
+// x_i = (origin_q + i * dx_q) * h0
+template <int D>
+__device__ inline void node_position(const GridDev &g, const int *idx, double *x) {
+#pragma unroll
+  for (int a = 0; a < D; ++a) x[a] = (double)(g.origin_q[a] + (long long)idx[a] * g.dx_q) * g.h0;
+}
+
+// Fixed-point node-mass contribution rint(N * (m_p * 2^32 / m_ref)).
+__device__ inline long long fixed_mass(double N, double mq) {
+#pragma clang fp contract(off)
+  return (long long)__builtin_rint(N * mq);
+}
+
+// ---------------------------------------------------------------- tiles
+__device__ inline int tile_of_block(const TileGeom &tg, int b) {
+  // Consecutive workgroups are dealt round-robin to the 8 XCDs; give each XCD
+  // a contiguous band of tiles so halo nodes stay in one L2.
+  const int per = tg.nblocks >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__device__ inline void tile_origin(const TileGeom &tg, int t, int *org) {
+  org[0] = (t % tg.nt[0]) * tg.T[0];
+  org[1] = ((t / tg.nt[0]) % tg.nt[1]) * tg.T[1];
+  org[2] = (t / (tg.nt[0] * tg.nt[1])) * tg.T[2];
+}
+
+// ---------------------------------------------------------------- small dense algebra
+template <int D>
+__device__ inline double det(const double *F) {
+  if constexpr (D == 2) {
+    return F[0] * F[3] - F[1] * F[2];
+  } else {
+    return F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+           F[2] * (F[3] * F[7] - F[4] * F[6]);
+  }
+}
+
+template <int D>
+__device__ inline void cofactor(const double *F, double *C) {
+  if constexpr (D == 2) {
+    C[0] = F[3];
+    C[1] = -F[2];
+    C[2] = -F[1];
+    C[3] = F[0];
+  } else {
+    C[0] = F[4] * F[8] - F[5] * F[7];
+    C[1] = F[5] * F[6] - F[3] * F[8];
+    C[2] = F[3] * F[7] - F[4] * F[6];
+    C[3] = F[2] * F[7] - F[1] * F[8];
+    C[4] = F[0] * F[8] - F[2] * F[6];
+    C[5] = F[1] * F[6] - F[0] * F[7];
+    C[6] = F[1] * F[5] - F[2] * F[4];
+    C[7] = F[2] * F[3] - F[0] * F[5];
+    C[8] = F[0] * F[4] - F[1] * F[3];
+  }
+}
+
+// Neo-Hookean first Piola stress P = mu (F - F^-T) + lam ln J F^-T and,
+// optionally, A = dP/dF stored as an n x n matrix, n = D*D, index (a*D+b).
+template <int D>
+__device__ inline bool nh_stress(const double *F, double mu, double lam, double *P, double *A) {
+  constexpr int n = D * D;
+  const double J = det<D>(F);
+  if (!(J > 0.0)) return false;
+  const double lnJ = log(J);
+  double C[n], Fi[n];
+  cofactor<D>(F, C);
+  const double iJ = 1.0 / J;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) Fi[a * D + b] = C[b * D + a] * iJ;  // F^-1
+  if (P) {
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        const double FiT = Fi[b * D + a];
+        P[a * D + b] = mu * (F[a * D + b] - FiT) + lam * lnJ * FiT;
+      }
+  }
+  if (A) {
+    const double c1 = mu - lam * lnJ;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+#pragma unroll
+          for (int e = 0; e < D; ++e) {
+            double v = c1 * Fi[e * D + a] * Fi[b * D + c] + lam * Fi[b * D + a] * Fi[e * D + c];
+            if (a == c && b == e) v += mu;
+            A[(a * D + b) * n + (c * D + e)] = v;
+          }
+  }
+  return true;
+}
+
+// Projection of the symmetric n x n matrix A onto the PSD cone by a cyclic
+// Jacobi eigendecomposition with negative eigenvalues clamped to zero.  A is
+// left untouched when no eigenvalue is negative.  All indices are
+// compile-time constants so W and V stay in registers.
+template <int n>
+__device__ inline void psd_project(double *A) {
+  double W[n * n], V[n * n];
+#pragma unroll
+  for (int i = 0; i < n * n; ++i) W[i] = A[i];
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
+  double diag2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < n; ++i) diag2 += W[i * n + i] * W[i * n + i];
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0;
+#pragma unroll
+    for (int p = 0; p < n; ++p)
+#pragma unroll
+      for (int q = p + 1; q < n; ++q) off += W[p * n + q] * W[p * n + q];
+    if (off <= 1e-32 * diag2 || off == 0.0) break;
+#pragma unroll
+    for (int p = 0; p < n; ++p)
+#pragma unroll
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = W[p * n + q];
+        if (apq != 0.0) {
+          const double theta = (W[q * n + q] - W[p * n + p]) / (2.0 * apq);
+          const double t = (theta >= 0.0 ? 1.0 : -1.0) /
+                           (__builtin_fabs(theta) + __builtin_sqrt(theta * theta + 1.0));
+          const double c = 1.0 / __builtin_sqrt(t * t + 1.0);
+          const double s = t * c;
+#pragma unroll
+          for (int k = 0; k < n; ++k) {
+            const double wkp = W[k * n + p], wkq = W[k * n + q];
+            W[k * n + p] = c * wkp - s * wkq;
+            W[k * n + q] = s * wkp + c * wkq;
+            const double vkp = V[k * n + p], vkq = V[k * n + q];
+            V[k * n + p] = c * vkp - s * vkq;
+            V[k * n + q] = s * vkp + c * vkq;
+          }
+#pragma unroll
+          for (int k = 0; k < n; ++k) {
+            const double wpk = W[p * n + k], wqk = W[q * n + k];
+            W[p * n + k] = c * wpk - s * wqk;
+            W[q * n + k] = s * wpk + c * wqk;
+          }
+        }
+      }
+  }
+  bool neg = false;
+#pragma unroll
+  for (int i = 0; i < n; ++i) neg |= (W[i * n + i] < 0.0);
+  if (!neg) return;
+  double lam[n];
+#pragma unroll
+  for (int k = 0; k < n; ++k) lam[k] = W[k * n + k] > 0.0 ? W[k * n + k] : 0.0;
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) v += V[i * n + k] * lam[k] * V[j * n + k];
+      A[i * n + j] = v;
+    }
+}
+
+// Packed upper triangle of a symmetric n x n matrix: index of (r, c), r <= c.
+template <int n>
+__device__ __host__ constexpr int sym_index(int r, int c) {
+  return r * n - (r * (r - 1)) / 2 + (c - r);
+}
+
+// ---------------------------------------------------------------- reductions
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over a workgroup of kBlock threads; every thread gets the total.
+__device__ inline double block_sum(double v, double *lds4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) lds4[w] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) t += lds4[i];
+  return t;
+}
+
+// Sum of a partials array in a fixed order (deterministic), computed by one
+// workgroup; every thread gets the total.
+__device__ inline double reduce_partials(const double *part, int n, double *lds4) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) v += part[i];
+  return block_sum(v, lds4);
+}
+
+}  // namespace osmpm
