@@ -1,0 +1,140 @@
+"""OS-MPM benchmark: particle-steps/s of the Schwarz-coupled implicit step.
+
+One step = one global frame t_n -> t_n + dT of the multiplicative Schwarz
+method on the refined 2D inclusion (coarse dx = 1/160 on [0,1]^2, fine
+dx = 1/400 on [0.3,0.7]^2, 2x2 particles per cell, sub-cycling ratio M = 2,
+dT = 1e-3): P2G on both domains, boundary sets and arbitration, Schwarz
+iterations (projection, coarse Newton-PCG solve, fine state restore, P2G,
+interpolation, M fine sub-steps of temporal interpolation, solve, G2P, P2G,
+residuals) until both interface residuals are below 1e-5, then the coarse
+G2P.  particle-steps per frame = N_B + M N_S; Schwarz re-iterations count as
+cost.  Inputs are resident in HBM before timing starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "inclusion_refined"
+
+
+def _frame_particle_steps(sc):
+    return sc.B.n_particles + sc.M * sc.S.n_particles
+
+
+def cpu_baseline(sc, frames, budget_s=30.0):
+    """The CPU oracle (single-threaded FP64 C) on the first frames of the same
+    workload; returns (value, sample description, state)."""
+    import oracle
+
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    t0 = time.perf_counter()
+    done = 0
+    for f in range(frames):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        oracle.schwarz_frame(OB, OS, sc.dT, oo)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return done * _frame_particle_steps(sc) / dt, done, dt, (OB, OS)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the method's multiplicative Schwarz loop is "
+              "sequential and this build measures one GPU's share (see --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding, scenes
+
+    sc = scenes.workload(WORKLOAD)
+    ctx = binding.Context(0)
+    pair = binding.SchwarzPair(ctx, sc)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    stats = []
+
+    # parity sample: the first frames against the oracle (also the CPU baseline)
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        value_cpu, nfr, tcpu, (OB, OS) = cpu_baseline(sc, args.cpu_frames)
+        for _ in range(nfr):
+            pair.frame(opts)
+        errs = {}
+        for name, D, O, spec in (("B", pair.B, OB, sc.B), ("S", pair.S, OS, sc.S)):
+            _, _, u = D.grid_state()
+            x, _, _, _ = D.particles_input_order()
+            u = u.cpu().numpy()
+            errs["u_" + name] = float(np.linalg.norm(u - O.u) / max(np.linalg.norm(O.u), 1e-300))
+            errs["x_" + name] = float(np.linalg.norm((x - spec.x) - (O.x - spec.x)) /
+                                      max(np.linalg.norm(O.x - spec.x), 1e-300))
+        cpu = {"value": value_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+               "sample": "frames 0-%d of the same workload, FP64 C oracle, one thread, %.1f s"
+                         % (nfr - 1, tcpu)}
+        parity = {"frames": nfr, "max_rel_err_vs_oracle": max(errs.values()), **errs}
+        pair.close()
+        pair = binding.SchwarzPair(ctx, sc)
+
+    for _ in range(args.warmup):
+        pair.frame(opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(pair.frame(opts))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ps = _frame_particle_steps(sc)
+    value = args.steps * ps / elapsed
+    iters = [s.iters for s in stats]
+    out = {
+        "metric": "particle-steps/s, OS-MPM implicit step, mixed FP32 vs FP64 at <=1e-5 rel err",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "2D inclusion, coarse dx 1/160, fine dx 1/400, 2x2 ppc, M=2, dT=1e-3, "
+                               "frames %d-%d" % (args.warmup, args.warmup + args.steps - 1),
+                   "N_B": sc.B.n_particles, "N_S": sc.S.n_particles, "path": "fp64",
+                   "schwarz_iters_mean": float(np.mean(iters)),
+                   "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
+                   "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats]))},
+        "roofline": None,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out))
+    pair.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
