@@ -78,6 +78,7 @@ struct osmpm_domain {
   CgState *cg = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *part_q = nullptr, *part_rz = nullptr, *part_rr = nullptr;
   int nb_node = 1, nb_part = 1;
+  int cg_hint = 8;  // CG iterations of the previous solve (first batch size)
   // interface / Schwarz work buffers ([nn][D] unless noted)
   double *pnum = nullptr, *pden = nullptr /*[nn]*/, *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
   bool have_p2g = false;
@@ -300,34 +301,34 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
     // PCG on H del = -g
     k_cg_init<D><<<d->nb_node, kBlock, 0, c->stream>>>(nd, d->gg, d->gd, d->fr, d->r, d->z, d->p0, d->p1, d->del,
                                                        d->Hp, d->part_rz, d->part_rr, d->cg);
-    int k = 0;
-    while (k < o->max_cg) {
-      const int kend = std::min(k + kCgChunk, o->max_cg);
-      for (; k < kend; ++k) {
-        double *pcur = (k & 1) ? d->p1 : d->p0;
-        double *pprev = (k & 1) ? d->p0 : d->p1;
-        k_cg_hvp<D><<<d->tg.nblocks, kBlock, lh, c->stream>>>(k, d->tg, d->g, d->cell_start, a.x, d->Atil, d->cap,
-                                                              d->m, dt, nd, d->z, pprev, pcur, d->Hp, d->part_rz,
-                                                              d->part_rr, d->nb_node, o->cg_rtol, d->part_q, d->cg);
-        k_cg_update<D><<<d->nb_node, kBlock, 0, c->stream>>>(k, nd, d->m, dt, d->fr, d->gd, pcur, d->Hp, d->r, d->z,
-                                                             d->del, d->part_q, d->tg.nblocks, d->part_rz,
+    // Batches of iterations between host checks: the first batch is sized
+    // from the previous solve's count so the loop usually ends after one or
+    // two checks; iterations launched after convergence exit at once.
+    int launched = 0;
+    int batch = std::max(4, std::min(d->cg_hint, o->max_cg));
+    for (;;) {
+      const int nb = std::min(batch, o->max_cg + 1 - launched);
+      for (int j = 0; j < nb; ++j) {
+        k_cg_hvp<D><<<d->tg.nblocks, kBlock, lh, c->stream>>>(d->tg, d->g, d->cell_start, a.x, d->Atil, d->cap, d->m,
+                                                              dt, nd, d->z, d->p0, d->p1, d->Hp, d->part_rz,
+                                                              d->part_rr, d->nb_node, o->cg_rtol, o->max_cg,
+                                                              d->part_q, d->cg);
+        k_cg_update<D><<<d->nb_node, kBlock, 0, c->stream>>>(nd, d->m, dt, d->fr, d->gd, d->p0, d->p1, d->Hp, d->r,
+                                                             d->z, d->del, d->part_q, d->tg.nblocks, d->part_rz,
                                                              d->part_rr, d->cg);
       }
+      launched += nb;
       if ((s = check_launch(c))) return s;
-      s = ensure_pin(c, 8);
-      if (s) return s;
       HIP_TRY(c, hipMemcpyAsync(c->h_pin, d->cg, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
       CgState hs;
       std::memcpy(&hs, c->h_pin, sizeof(CgState));
-      if (hs.done) break;
-    }
-    {
-      HIP_TRY(c, hipMemcpyAsync(c->h_pin, d->cg, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      CgState hs;
-      std::memcpy(&hs, c->h_pin, sizeof(CgState));
-      S.cg_iters += hs.iter;
+      if (hs.done || launched > o->max_cg) {
+        S.cg_iters += hs.iter;
+        d->cg_hint = hs.iter + 1;
+        break;
+      }
+      batch = 4;
     }
     // halving line search on the exact energy difference
     double alpha = 1.0;

@@ -72,31 +72,55 @@ __global__ void k_keys(int n, const double *x, int64_t cap, GridDev g, TileGeom 
   atomicAdd(&count[k], 1);
 }
 
-// Exclusive scan of nk counts by one workgroup of 1024 threads (each thread
-// scans a contiguous chunk); cell_start[nk] is the total.  cursor receives a
-// copy of the offsets for the scatter.
+// Exclusive scan of nk counts by one workgroup of 1024 threads, 4096
+// elements per pass (each thread four consecutive counts, so loads and
+// stores are coalesced); cell_start[nk] is the total.  cursor receives a copy
+// of the offsets for the scatter.
 __global__ void __launch_bounds__(1024) k_scan(int nk, const int *count, int *cell_start, int *cursor) {
-  __shared__ int part[1024];
-  const int tid = threadIdx.x;
-  const int chunk = (nk + 1023) / 1024;
-  const int s = tid * chunk, e = min(nk, s + chunk);
-  int sum = 0;
-  for (int i = s; i < e; ++i) sum += count[i];
-  part[tid] = sum;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = (tid >= off) ? part[tid - off] : 0;
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int carry = 0;
+  for (int base = 0; base < nk; base += 4096) {
+    int v[4];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = base + 4 * tid + j;
+      v[j] = (idx < nk) ? count[idx] : 0;
+      s += v[j];
+    }
+    int xs = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(xs, off, 64);
+      if (lane >= off) xs += y;
+    }
+    if (lane == 63) wsum[w] = xs;
     __syncthreads();
-    part[tid] += v;
+    if (w == 0) {
+      int ws = (lane < 16) ? wsum[lane] : 0;
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const int y = __shfl_up(ws, off, 64);
+        if (lane >= off) ws += y;
+      }
+      if (lane < 16) wsum[lane] = ws;
+    }
+    __syncthreads();
+    int excl = carry + (w > 0 ? wsum[w - 1] : 0) + (xs - s);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = base + 4 * tid + j;
+      if (idx < nk) {
+        cell_start[idx] = excl;
+        cursor[idx] = excl;
+      }
+      excl += v[j];
+    }
+    carry += wsum[15];
     __syncthreads();
   }
-  int run = part[tid] - sum;
-  for (int i = s; i < e; ++i) {
-    cell_start[i] = run;
-    cursor[i] = run;
-    run += count[i];
-  }
-  if (tid == 1023) cell_start[nk] = part[1023];
+  if (tid == 0) cell_start[nk] = carry;
 }
 
 __global__ void k_scatter(int n, const int *key, int *cursor, int *perm) {
@@ -651,54 +675,124 @@ __global__ void k_cg_init(int ndof, const double *gg, const double *gdiag, const
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     S->iter = 0;
     S->done = 0;
+    S->knext = 0;
+    S->kcur = 0;
   }
 }
 
-// CG iteration k, first half.  Every workgroup sums the (r, z) and (r, r)
-// partials of the previous update in the same order, tests convergence
-// |r| <= rtol |r0|, and forms beta.  The search direction p = z + beta p_prev is
-// formed on the fly (tile regions in LDS, owned DOFs stored to p_cur).  The
-// particle part scatters Hp = sum_p Atil:G gradN and accumulates the
-// quadratic form p^T H p = sum_p G:Atil:G + sum_i m_i/dt^2 |p_i|^2, so the
-// product and its curvature complete in one pass.
+// Sum over a workgroup of two values at once (every thread gets both).
+__device__ inline void block_sum2(double &a, double &b, double *lds8) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    lds8[w] = a;
+    lds8[4 + w] = b;
+  }
+  __syncthreads();
+  a = lds8[0] + lds8[1] + lds8[2] + lds8[3];
+  b = lds8[4] + lds8[5] + lds8[6] + lds8[7];
+}
+
+// CG iteration, first half.  The iteration index k comes from the device
+// state (so a chunk of iterations can be replayed with fixed arguments).
+// Every workgroup sums the (r, z) and (r, r) partials of the previous update
+// in the same order, tests |r| <= rtol |r0| (and k < max_cg), and forms beta.
+// The search direction p = z + beta p_prev is formed on the fly (tile regions
+// in LDS, owned DOFs stored to p_cur).  The particle part scatters
+// Hp = sum_p Atil:G gradN and accumulates the curvature
+// p^T H p = sum_p G:Atil:G + sum_i m_i/dt^2 |p_i|^2, so the product and its
+// curvature complete in one pass.  All global loads that do not depend on
+// beta are issued before the reduction so their latencies overlap.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_cg_hvp(int it, TileGeom tg, GridDev g, const int *cell_start,
-                                                   const double *x, const double *Atil, int64_t cap,
-                                                   const double *gm, double dt, int ndof, const double *z,
-                                                   const double *pprev, double *pcur, double *Hp,
+__global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const int *cell_start, const double *x,
+                                                   const double *Atil, int64_t cap, const double *gm, double dt,
+                                                   int ndof, const double *z, double *pA, double *pB, double *Hp,
                                                    const double *part_rz, const double *part_rr, int n_part,
-                                                   double rtol, double *part_q, CgState *S) {
+                                                   double rtol, int max_cg, double *part_q, CgState *S) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   extern __shared__ double lds[];
-  __shared__ double red[kBlock / 64];
-  const double rz_new = reduce_partials(part_rz, n_part, red);
-  const double rr = reduce_partials(part_rr, n_part, red);
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  const int it = S->knext;
+  const double *pprev = (it & 1) ? pA : pB;
+  double *pcur = (it & 1) ? pB : pA;
+  // tile and its particle range
+  const int t = tile_of_block(tg, blockIdx.x);
+  int p0 = 0, p1 = 0, org[3] = {0, 0, 0};
+  const bool tile_ok = tile_range(tg, cell_start, t, p0, p1, org) && p0 < p1;
+  const int nreg = tg.nreg;
+  // --- independent loads
+  double prz = 0.0, prr = 0.0;
+  for (int i = tid; i < n_part; i += kBlock) {
+    prz += part_rz[i];
+    prr += part_rr[i];
+  }
+  const int k0 = blockIdx.x * kBlock + tid;
+  double nz = 0.0, npv = 0.0, nm = 0.0;
+  if (k0 < ndof) {
+    nz = z[k0];
+    npv = pprev[k0];
+    nm = gm[k0 / D];
+  }
+  int ri = -1;
+  double rzv[D], rpv[D];
+  if (tile_ok && tid < nreg) {
+    ri = region_node<D>(tg, g, org, tid);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      rzv[a] = (ri >= 0) ? z[ri * D + a] : 0.0;
+      rpv[a] = (ri >= 0) ? pprev[ri * D + a] : 0.0;
+    }
+  }
+  const int pp = p0 + tid;
+  const bool have_p = tile_ok && pp < p1;
+  double xp[D], At[ns];
+  if (have_p) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) xp[a] = x[a * cap + pp];
+#pragma unroll
+    for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + pp];
+  }
+  // --- reduction, convergence test, beta
+  block_sum2(prz, prr, red);
+  const double rz_new = prz, rr = prr;
   const double rr0 = (it == 0) ? rr : S->rr0;
-  const bool done = (it == 0) ? !(rr0 > 0.0) : (__builtin_sqrt(rr) <= rtol * __builtin_sqrt(rr0));
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  const bool done = (it >= max_cg) || ((it == 0) ? !(rr0 > 0.0) : (sqrt(rr) <= rtol * sqrt(rr0)));
+  if (blockIdx.x == 0 && tid == 0) {
     if (it == 0) S->rr0 = rr0;
     if (done) S->done = 1;
     S->rz[it & 1] = rz_new;
+    S->kcur = it;
   }
-  if (done) return;
+  if (done || S->done) return;
   const double beta = (it == 0) ? 0.0 : rz_new / S->rz[(it + 1) & 1];
   const double mdt = 1.0 / (dt * dt);
   double q = 0.0;
   // node part: owned DOFs of the new direction and its mass term
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ndof; k += gridDim.x * blockDim.x) {
+  if (k0 < ndof) {
+    const double pv = nz + beta * npv;
+    pcur[k0] = pv;
+    q += nm * mdt * pv * pv;
+  }
+  for (int k = k0 + gridDim.x * kBlock; k < ndof; k += gridDim.x * kBlock) {
     const double pv = z[k] + beta * pprev[k];
     pcur[k] = pv;
     q += gm[k / D] * mdt * pv * pv;
   }
-  // particle part
-  const int t = tile_of_block(tg, blockIdx.x);
-  int p0, p1, org[3];
-  if (tile_range(tg, cell_start, t, p0, p1, org) && p0 < p1) {
-    const int nreg = tg.nreg;
+  if (tile_ok) {
     double *lp = lds;
     double *lh = lds + D * nreg;
-    for (int r = threadIdx.x; r < nreg; r += kBlock) {
+    if (tid < nreg) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        lp[a * nreg + tid] = (ri >= 0) ? rzv[a] + beta * rpv[a] : 0.0;
+        lh[a * nreg + tid] = 0.0;
+      }
+    }
+    for (int r = tid + kBlock; r < nreg; r += kBlock) {
       const int i = region_node<D>(tg, g, org, r);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -707,10 +801,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(int it, TileGeom tg, GridDev 
       }
     }
     __syncthreads();
-    for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
-      double xp[D];
+    for (int p = pp; p < p1; p += kBlock) {
+      if (p != pp) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+        for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+#pragma unroll
+        for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + p];
+      }
       Stencil<D> st;
       stencil_eval<D>(xp, g, st);
       int l[3];
@@ -732,9 +829,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(int it, TileGeom tg, GridDev 
           for (int b = 0; b < D; ++b) G[a * D + b] += pa * gN[b];
         }
       }
-      double At[ns];
-#pragma unroll
-      for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + p];
       double T[n];
 #pragma unroll
       for (int rr2 = 0; rr2 < n; ++rr2) {
@@ -762,8 +856,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(int it, TileGeom tg, GridDev 
       }
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < nreg; r += kBlock) {
-      const int i = region_node<D>(tg, g, org, r);
+    for (int r = tid; r < nreg; r += kBlock) {
+      const int i = (r == tid) ? ri : region_node<D>(tg, g, org, r);
       if (i < 0) continue;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -773,47 +867,82 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(int it, TileGeom tg, GridDev 
     }
   }
   const double tq = block_sum(q, red);
-  if (threadIdx.x == 0) part_q[blockIdx.x] = tq;
+  if (tid == 0) part_q[blockIdx.x] = tq;
 }
 
-// CG iteration k, second half: alpha = (r, z) / p^T H p; del += alpha p,
+// CG iteration, second half: alpha = (r, z) / p^T H p; del += alpha p,
 // r -= alpha H p (H p = scatter + m/dt^2 p), z = r / D on free DOFs; the
 // scatter buffer is cleared for the next product; partial (r, z), (r, r).
+// Node data are loaded before the curvature partials are reduced.
 template <int D>
-__global__ void k_cg_update(int it, int ndof, const double *gm, double dt, const uint8_t *fr, const double *gdiag,
-                            const double *pcur, double *Hp, double *r, double *z, double *del, const double *part_q,
-                            int n_q, double *part_rz, double *part_rr, CgState *S) {
-  __shared__ double red[kBlock / 64];
+__global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm, double dt, const uint8_t *fr,
+                                                      const double *gdiag, const double *pA, const double *pB,
+                                                      double *Hp, double *r, double *z, double *del,
+                                                      const double *part_q, int n_q, double *part_rz,
+                                                      double *part_rr, CgState *S) {
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
   if (S->done) return;
-  const double pq = reduce_partials(part_q, n_q, red);
+  const int it = S->kcur;
+  const double *pcur = (it & 1) ? pB : pA;
+  double pq = 0.0;
+  for (int i = tid; i < n_q; i += kBlock) pq += part_q[i];
+  const int k0 = blockIdx.x * kBlock + tid;
+  double hs = 0.0, pv = 0.0, rv = 0.0, dv = 0.0, dg = 1.0, m = 0.0;
+  bool f = false;
+  if (k0 < ndof) {
+    f = fr[k0];
+    hs = Hp[k0];
+    pv = pcur[k0];
+    rv = r[k0];
+    dv = del[k0];
+    dg = gdiag[k0];
+    m = gm[k0 / D];
+  }
+  pq = block_sum(pq, red);
   if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) S->done = 1;
+    if (blockIdx.x == 0 && tid == 0) S->done = 1;
     return;
   }
   const double alpha = S->rz[it & 1] / pq;
   const double mdt = 1.0 / (dt * dt);
   double rz = 0.0, rr = 0.0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ndof; k += gridDim.x * blockDim.x) {
-    const double hs = Hp[k];
+  if (k0 < ndof) {
+    Hp[k0] = 0.0;
+    if (f) {
+      const double hv = hs + m * mdt * pv;
+      del[k0] = dv + alpha * pv;
+      const double rn = rv - alpha * hv;
+      r[k0] = rn;
+      const double zv = rn / dg;
+      z[k0] = zv;
+      rz += rn * zv;
+      rr += rn * rn;
+    }
+  }
+  for (int k = k0 + gridDim.x * kBlock; k < ndof; k += gridDim.x * kBlock) {
+    const double h2 = Hp[k];
     Hp[k] = 0.0;
     if (!fr[k]) continue;
-    const double pv = pcur[k];
-    const double hv = hs + gm[k / D] * mdt * pv;
-    del[k] += alpha * pv;
-    const double rv = r[k] - alpha * hv;
-    r[k] = rv;
-    const double zv = rv / gdiag[k];
+    const double p2 = pcur[k];
+    const double hv = h2 + gm[k / D] * mdt * p2;
+    del[k] += alpha * p2;
+    const double rn = r[k] - alpha * hv;
+    r[k] = rn;
+    const double zv = rn / gdiag[k];
     z[k] = zv;
-    rz += rv * zv;
-    rr += rv * rv;
+    rz += rn * zv;
+    rr += rn * rn;
   }
-  const double a = block_sum(rz, red);
-  const double b = block_sum(rr, red);
-  if (threadIdx.x == 0) {
-    part_rz[blockIdx.x] = a;
-    part_rr[blockIdx.x] = b;
+  block_sum2(rz, rr, red);
+  if (tid == 0) {
+    part_rz[blockIdx.x] = rz;
+    part_rr[blockIdx.x] = rr;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) S->iter = it + 1;
+  if (blockIdx.x == 0 && tid == 0) {
+    S->iter = it + 1;
+    S->knext = it + 1;
+  }
 }
 
 // ====================================================================== line search
@@ -1130,13 +1259,12 @@ __global__ void k_resid(int nn, const uint8_t *recv, const double *a, const doub
                                           int, double *);                                                          \
   template __global__ void k_cg_init<D>(int, const double *, const double *, const uint8_t *, double *, double *, \
                                         double *, double *, double *, double *, double *, double *, CgState *);   \
-  template __global__ void k_cg_hvp<D>(int, TileGeom, GridDev, const int *, const double *, const double *,        \
-                                       int64_t, const double *, double, int, const double *, const double *,       \
-                                       double *, double *, const double *, const double *, int, double, double *, \
-                                       CgState *);                                                                 \
-  template __global__ void k_cg_update<D>(int, int, const double *, double, const uint8_t *, const double *,       \
-                                          const double *, double *, double *, double *, double *, const double *, \
-                                          int, double *, double *, CgState *);                                    \
+  template __global__ void k_cg_hvp<D>(TileGeom, GridDev, const int *, const double *, const double *, int64_t,   \
+                                       const double *, double, int, const double *, double *, double *, double *, \
+                                       const double *, const double *, int, double, int, double *, CgState *);      \
+  template __global__ void k_cg_update<D>(int, const double *, double, const uint8_t *, const double *,            \
+                                          const double *, const double *, double *, double *, double *, double *, \
+                                          const double *, int, double *, double *, CgState *);                    \
   template __global__ void k_delta_energy_p<D>(int, GridDev, const double *, const double *, const double *,       \
                                                const int *, const double *, const double *, int64_t,              \
                                                const double *, const double *, double, double *);                 \

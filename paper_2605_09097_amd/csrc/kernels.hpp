@@ -12,9 +12,10 @@ struct CgState {
   double rz[2];
   double rr0;
   double pad;
-  int iter;
-  int done;
-  int pad2[2];
+  int iter;   // completed updates
+  int done;   // converged, broke down or hit max_cg
+  int knext;  // index of the next iteration (written by the update kernel)
+  int kcur;   // index of the running iteration (written by the product kernel)
 };
 
 __global__ void k_fill_d(int64_t n, double v, double *a);
@@ -63,14 +64,14 @@ __global__ void k_cg_init(int ndof, const double *gg, const double *gdiag, const
                           double *p0, double *p1, double *del, double *Hp, double *part_rz, double *part_rr,
                           CgState *S);
 template <int D>
-__global__ void k_cg_hvp(int it, TileGeom tg, GridDev g, const int *cell_start, const double *x, const double *Atil,
-                         int64_t cap, const double *gm, double dt, int ndof, const double *z, const double *pprev,
-                         double *pcur, double *Hp, const double *part_rz, const double *part_rr, int n_part,
-                         double rtol, double *part_q, CgState *S);
+__global__ void k_cg_hvp(TileGeom tg, GridDev g, const int *cell_start, const double *x, const double *Atil,
+                         int64_t cap, const double *gm, double dt, int ndof, const double *z, double *pA, double *pB,
+                         double *Hp, const double *part_rz, const double *part_rr, int n_part, double rtol,
+                         int max_cg, double *part_q, CgState *S);
 template <int D>
-__global__ void k_cg_update(int it, int ndof, const double *gm, double dt, const uint8_t *fr, const double *gdiag,
-                            const double *pcur, double *Hp, double *r, double *z, double *del, const double *part_q,
-                            int n_q, double *part_rz, double *part_rr, CgState *S);
+__global__ void k_cg_update(int ndof, const double *gm, double dt, const uint8_t *fr, const double *gdiag,
+                            const double *pA, const double *pB, double *Hp, double *r, double *z, double *del,
+                            const double *part_q, int n_q, double *part_rz, double *part_rr, CgState *S);
 template <int D>
 __global__ void k_delta_energy_p(int np, GridDev g, const double *x, const double *F, const double *vol,
                                  const int *mat, const double *mu_t, const double *lam_t, int64_t cap,

@@ -72,9 +72,13 @@ def test_sort_bit_exact_3d(ctx):
     D.close()
 
 
-def test_sort_scene_domains(ctx):
+@pytest.mark.parametrize("name", ["inclusion_tiny", "inclusion_refined"])
+def test_sort_scene_domains(ctx, name):
+    """Both domains of the small and the refined inclusion (the refined fine
+    grid has 25,600 bins, so the bin scan runs several passes with a ragged
+    tail)."""
     b = _binding()
-    sc = _scenes().workload("inclusion_tiny")
+    sc = _scenes().workload(name)
     for spec in (sc.B, sc.S):
         D = b.Domain(ctx, spec)
         D.p2g()
