@@ -50,6 +50,30 @@ def cpu_baseline(sc, frames, budget_s=30.0):
     return done * _frame_particle_steps(sc) / dt, done, dt, (OB, OS)
 
 
+def counter_traffic():
+    """HBM bytes per working CG-product launch from the committed rocprofv3
+    counter summary, or None when the kernel sources changed since the
+    counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "cg_product_inclusion_refined_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    csrc = os.path.join(ROOT, "paper_2605_09097_amd", "csrc")
+    src = open(os.path.join(csrc, "kernels.hip"), "rb").read() + open(os.path.join(csrc, "device.hpp"), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != vals.get("kernel_source_sha256_16"):
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -57,6 +81,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--profile-steps", type=int, default=0, help="frames of the instrumented pass (0: --steps)")
+    ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's multiplicative Schwarz loop is "
@@ -99,11 +125,39 @@ def main():
     for _ in range(args.warmup):
         pair.frame(opts)
     torch.cuda.synchronize()
+    # Timed region (no instrumentation).
     t0 = time.perf_counter()
     for _ in range(args.steps):
         stats.append(pair.frame(opts))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # Kernel durations: the same number of frames again with every launch of
+    # the instrumented kernels timestamped by its dispatch (HIP events on the
+    # library's stream).  Timestamped dispatches serialise the queue, so this
+    # pass is kept apart from the throughput measurement above.
+    kern = {}
+    ctx.profile(True)
+    t1 = time.perf_counter()
+    for _ in range(args.profile_steps if args.profile_steps > 0 else args.steps):
+        pair.frame(opts)
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t1
+    for kid, name in ((binding.OSMPM_K_CG_PRODUCT, "cg_product"), (binding.OSMPM_K_CG_UPDATE, "cg_update"),
+                      (binding.OSMPM_K_P2G, "p2g"), (binding.OSMPM_K_G2P, "g2p"),
+                      (binding.OSMPM_K_GRAD_HESS, "grad_hess")):
+        n, ms, by = ctx.profile_query(kid)
+        if n:
+            kern[name] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n,
+                          "bytes_per_launch": by / n, "achieved_GBps": by / (ms * 1e-3) / 1e9,
+                          "frac_hbm": by / (ms * 1e-3) / 8e12}
+    ctx.profile(False)
+    if args.calibrate_copy:
+        # a plain device copy of known size, for scaling HBM counters
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
 
     ps = _frame_particle_steps(sc)
     value = args.steps * ps / elapsed
@@ -127,7 +181,15 @@ def main():
                    "schwarz_iters_mean": float(np.mean(iters)),
                    "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
                    "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats]))},
-        "roofline": None,
+        "roofline": ({"bound": "hbm", "kernel": "k_cg_hvp (CG Hessian-vector product)",
+                      "achieved": kern["cg_product"]["achieved_GBps"], "peak": 8000.0, "unit": "GB/s",
+                      "frac": kern["cg_product"]["frac_hbm"], "traffic": counter_traffic(),
+                      "avg_us": kern["cg_product"]["avg_us"],
+                      "bytes_per_launch": kern["cg_product"]["bytes_per_launch"]}
+                     if "cg_product" in kern else None),
+        "kernels": kern,
+        "profiled_pass_ms_per_step": 1e3 * elapsed_prof / max(1, args.profile_steps if args.profile_steps > 0
+                                                               else args.steps),
         "cpu_baseline": cpu,
         "parity": parity,
     }

@@ -61,6 +61,16 @@ typedef enum {
 
 typedef enum { OSMPM_BC_FIX = 0, OSMPM_BC_TRANSLATE = 1, OSMPM_BC_ROTATE = 2 } osmpm_bc_kind;
 
+/* Instrumented kernels (osmpm_profile_query). */
+typedef enum {
+  OSMPM_K_CG_PRODUCT = 0, /* CG Hessian-vector product through the particles */
+  OSMPM_K_CG_UPDATE = 1,  /* CG vector update and dot products */
+  OSMPM_K_P2G = 2,        /* APIC particle-to-grid */
+  OSMPM_K_G2P = 3,        /* APIC grid-to-particle, F update, advection */
+  OSMPM_K_GRAD_HESS = 4,  /* gradient and per-particle tangent build */
+  OSMPM_K_COUNT = 5
+} osmpm_kernel;
+
 typedef struct osmpm_ctx osmpm_ctx;
 typedef struct osmpm_domain osmpm_domain;
 
@@ -127,6 +137,19 @@ osmpm_status osmpm_ctx_set_stream(osmpm_ctx *ctx, void *stream);
 /* Waits for all queued work and reports device-side errors. */
 osmpm_status osmpm_sync(osmpm_ctx *ctx);
 const char *osmpm_last_error(const osmpm_ctx *ctx);
+
+/* Kernel timing with HIP events on the context stream.  enable = 1 clears the
+ * counters and records an event pair around every launch of the
+ * instrumented kernels (osmpm_kernel); enable = 0 stops.  CG launches that
+ * only find the solve already finished are not counted.  Synchronises. */
+osmpm_status osmpm_profile_enable(osmpm_ctx *ctx, int32_t enable);
+/* Counted launches, their summed duration in milliseconds and their summed
+ * algorithmic bytes (the bytes the operation must move once: particle arrays
+ * read or written, node arrays gathered, atomic updates as read + write) for
+ * kernel `which` since profiling was enabled.  Outputs may be NULL.
+ * Synchronises. */
+osmpm_status osmpm_profile_query(osmpm_ctx *ctx, int32_t which, int64_t *launches, double *total_ms,
+                                 double *bytes);
 void osmpm_ctx_destroy(osmpm_ctx *ctx);
 
 /* ---------------------------------------------------------------- domain */

@@ -19,10 +19,12 @@ LIB_PATH = os.path.join(_PKG, "libosmpm.so")
 OSMPM_OK, OSMPM_E_INVALID_ARG, OSMPM_E_NO_MEMORY, OSMPM_E_DEVICE = 0, 1, 2, 3
 OSMPM_E_OUT_OF_GRID, OSMPM_E_INVERTED, OSMPM_E_STATE = 4, 5, 7
 OSMPM_FP64, OSMPM_MIXED = 0, 1
+OSMPM_K_CG_PRODUCT, OSMPM_K_CG_UPDATE, OSMPM_K_P2G, OSMPM_K_G2P, OSMPM_K_GRAD_HESS = 0, 1, 2, 3, 4
 
 # Every symbol the header declares (checked by the CPU test suite).
 ABI_SYMBOLS = [
     "osmpm_ctx_create", "osmpm_ctx_set_stream", "osmpm_sync", "osmpm_last_error", "osmpm_ctx_destroy",
+    "osmpm_profile_enable", "osmpm_profile_query",
     "osmpm_domain_create", "osmpm_domain_destroy", "osmpm_domain_set_materials",
     "osmpm_domain_set_particles", "osmpm_domain_set_selection", "osmpm_domain_set_scene_bc",
     "osmpm_p2g", "osmpm_implicit_solve", "osmpm_g2p", "osmpm_interface_build",
@@ -76,6 +78,8 @@ def _declare(L):
         "osmpm_ctx_create": [C.c_int32, _vp, P(_vp)],
         "osmpm_ctx_set_stream": [_vp, _vp],
         "osmpm_sync": [_vp],
+        "osmpm_profile_enable": [_vp, C.c_int32],
+        "osmpm_profile_query": [_vp, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)],
         "osmpm_domain_create": [_vp, P(osmpm_grid), C.c_int32, C.c_int64, P(C.c_int32), P(_vp)],
         "osmpm_domain_set_materials": [_vp, P(osmpm_material), C.c_int32],
         "osmpm_domain_set_particles": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -173,6 +177,15 @@ class Context:
 
     def sync(self):
         self.check(lib().osmpm_sync(self.handle), "sync")
+
+    def profile(self, enable):
+        self.check(lib().osmpm_profile_enable(self.handle, int(enable)), "profile_enable")
+
+    def profile_query(self, which):
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        self.check(lib().osmpm_profile_query(self.handle, which, C.byref(n), C.byref(ms), C.byref(by)),
+                   "profile_query")
+        return n.value, ms.value, by.value
 
     def temporal_interp(self, m, M, vn, vn1, out):
         self.check(lib().osmpm_temporal_interp(self.handle, vn.numel(), m, M, _ptr(vn), _ptr(vn1), _ptr(out)),

@@ -13,6 +13,8 @@
 #include <string>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "../../include/osmpm.h"
 #include "kernels.hpp"
 
@@ -37,6 +39,19 @@ int blocks_for(int64_t n, int cap_blocks = 1024) {
 
 }  // namespace
 
+// Kernel timing: HIP events recorded on the context stream around every
+// launch of the instrumented kernels while profiling is enabled.
+struct ProfPending {
+  hipEvent_t a, b;
+  int which;
+  double bytes;
+  int cg_iter;  // iteration index of a CG launch, -1 otherwise
+};
+struct ProfSlot {
+  int64_t launches = 0;
+  double ms = 0.0, bytes = 0.0;
+};
+
 struct osmpm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -45,6 +60,10 @@ struct osmpm_ctx {
   double *h_pin = nullptr;
   size_t h_pin_doubles = 0;
   std::string last_error;
+  bool prof = false;
+  ProfSlot slots[OSMPM_K_COUNT];
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<ProfPending> pending;
 };
 
 struct osmpm_domain {
@@ -123,6 +142,75 @@ osmpm_status ensure_pin(osmpm_ctx *c, size_t doubles) {
   return OSMPM_OK;
 }
 
+// ---------------------------------------------------------------- profiling
+hipEvent_t prof_event(osmpm_ctx *c) {
+  if (c->ev_pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDefault) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = c->ev_pool.back();
+  c->ev_pool.pop_back();
+  return e;
+}
+
+// Launch of an instrumented kernel.  With profiling on, the dispatch itself
+// carries the start and stop timestamps (hipExtLaunchKernelGGL), so no extra
+// packets are inserted between kernels.
+template <typename F, typename... Args>
+void launch(osmpm_ctx *c, int which, double bytes, int cg_iter, F kernel, dim3 grid, dim3 block, uint32_t shm,
+            Args... args) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c->prof) {
+    a = prof_event(c);
+    b = prof_event(c);
+    if (!a || !b) a = b = nullptr;
+  }
+  hipExtLaunchKernelGGL(kernel, grid, block, shm, c->stream, a, b, 0, args...);
+  if (a) c->pending.push_back({a, b, which, bytes, cg_iter});
+}
+
+// Folds completed timings into the counters; call only after the stream has
+// been synchronised.  CG launches at or beyond `cg_done` iterations (those
+// that found the solve finished and exited) are dropped.
+void prof_harvest(osmpm_ctx *c, int cg_done = 1 << 30) {
+  for (const ProfPending &p : c->pending) {
+    if (p.cg_iter < 0 || p.cg_iter < cg_done) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        ProfSlot &sl = c->slots[p.which];
+        sl.launches += 1;
+        sl.ms += ms;
+        sl.bytes += p.bytes;
+      }
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+// Algorithmic bytes of one launch: the data the operation must move once
+// (particle arrays read or written, node arrays gathered, atomics counted as
+// read + write), independent of caching.
+double alg_bytes(int which, int D, double np, double nn) {
+  const double ns = (D * D) * (D * D + 1) / 2.0;
+  switch (which) {
+    case OSMPM_K_CG_PRODUCT:  // x, Atil per particle; z, p_prev, p_cur, Hp (rmw) per DOF, mass per node
+      return np * 8.0 * (D + ns) + nn * 8.0 * (5.0 * D + 1.0);
+    case OSMPM_K_CG_UPDATE:  // Hp (read, clear), p, r (rmw), z, del (rmw), diag per DOF + mask; mass per node
+      return nn * (D * (8.0 * 8.0 + 1.0) + 8.0);
+    case OSMPM_K_P2G:  // x, v, B, mass, flags per particle; mass and momentum (rmw) per node
+      return np * (8.0 * (2.0 * D + D * D + 1.0) + 1.0) + nn * 16.0 * (1.0 + D);
+    case OSMPM_K_G2P:  // x, F read; x, v, B, F written; u and mass gathered per node
+      return np * 8.0 * (3.0 * D + 3.0 * D * D) + nn * 8.0 * (D + 1.0);
+    case OSMPM_K_GRAD_HESS:  // x, F, vol, mat read; Atil written; u read, gradient and diagonal rmw
+      return np * (8.0 * (D + D * D + 1.0 + ns) + 4.0) + nn * 8.0 * (5.0 * D);
+    default:
+      return 0.0;
+  }
+}
+
 // Copies the device error word and up to three partial arrays to pinned host
 // memory, waits, and returns their host sums (fixed order).
 struct Fetch {
@@ -144,6 +232,7 @@ osmpm_status fetch(osmpm_ctx *c, Fetch &f, int *err_out) {
     off += f.n[k];
   }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  prof_harvest(c);
   int err = 0;
   std::memcpy(&err, c->h_pin, sizeof(int));
   off = 1;
@@ -233,10 +322,10 @@ osmpm_status p2g_impl(osmpm_domain *d, bool want_qall) {
   const PartBuf &a = d->pb[d->cur];
   if (d->np > 0) {
     const double Dinv = 4.0 * d->g.inv_dx * d->g.inv_dx;
-    k_p2g<D><<<d->tg.nblocks, kBlock, lds_p2g(d), c->stream>>>(d->tg, d->g, d->cell_start, a.x, a.v, a.B, a.mass,
-                                                               a.flags, d->cap, d->bc.n_groups, fixed_scale(d),
-                                                               Dinv, want_q, d->m, d->vn, d->q_all, d->qg,
-                                                               c->d_err);
+    launch(c, OSMPM_K_P2G, alg_bytes(OSMPM_K_P2G, D, d->np, nn), -1, k_p2g<D>, dim3(d->tg.nblocks), dim3(kBlock),
+           (uint32_t)lds_p2g(d), d->tg, d->g, (const int *)d->cell_start, (const double *)a.x, (const double *)a.v,
+           (const double *)a.B, (const double *)a.mass, (const uint8_t *)a.flags, d->cap, d->bc.n_groups,
+           fixed_scale(d), Dinv, want_q, d->m, d->vn, d->q_all, d->qg, c->d_err);
   }
   k_p2g_final<D><<<blocks_for(nn, 1 << 20), kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->qg, d->bc, tau_fixed(d),
                                                                      d->bcg);
@@ -250,8 +339,9 @@ osmpm_status g2p_impl(osmpm_domain *d, double dt) {
   if (!d->have_p2g) return fail(c, OSMPM_E_STATE, "g2p before p2g");
   if (d->np == 0) return OSMPM_OK;
   PartBuf &a = d->pb[d->cur];
-  k_g2p<D><<<blocks_for(d->np, 1 << 20), kBlock, 0, c->stream>>>(d->np, d->g, d->m, d->u, dt, a.x, a.v, a.B, a.F,
-                                                                  d->cap, c->d_err);
+  launch(c, OSMPM_K_G2P, alg_bytes(OSMPM_K_G2P, D, d->np, d->g.nn), -1, k_g2p<D>, dim3(blocks_for(d->np, 1 << 20)),
+         dim3(kBlock), 0, d->np, d->g, (const double *)d->m, (const double *)d->u, dt, a.x, a.v, a.B, a.F, d->cap,
+         c->d_err);
   return check_launch(c);
 }
 
@@ -279,9 +369,11 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
     zero_d(c, d->gg, nd);
     zero_d(c, d->gd, nd);
     if (d->np > 0)
-      k_grad_hess<D><<<d->tg.nblocks, kBlock, lg, c->stream>>>(d->tg, d->g, d->cell_start, a.x, a.F, a.vol, a.mat,
-                                                               d->mu, d->lam, d->cap, d->u, 1, o->project_psd,
-                                                               d->gg, d->gd, d->Atil, c->d_err);
+      launch(c, OSMPM_K_GRAD_HESS, alg_bytes(OSMPM_K_GRAD_HESS, D, d->np, nn), -1, k_grad_hess<D>,
+             dim3(d->tg.nblocks), dim3(kBlock), (uint32_t)lg, d->tg, d->g, (const int *)d->cell_start,
+             (const double *)a.x, (const double *)a.F, (const double *)a.vol, (const int *)a.mat,
+             (const double *)d->mu, (const double *)d->lam, d->cap, (const double *)d->u, 1, o->project_psd, d->gg,
+             d->gd, d->Atil, c->d_err);
     k_grad_node<D><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->u, d->fr, dt, o->gravity[0],
                                                          o->gravity[1], o->gravity[2], d->gg, d->gd, 1, d->part_a);
     Fetch fg;
@@ -309,13 +401,15 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
     for (;;) {
       const int nb = std::min(batch, o->max_cg + 1 - launched);
       for (int j = 0; j < nb; ++j) {
-        k_cg_hvp<D><<<d->tg.nblocks, kBlock, lh, c->stream>>>(d->tg, d->g, d->cell_start, a.x, d->Atil, d->cap, d->m,
-                                                              dt, nd, d->z, d->p0, d->p1, d->Hp, d->part_rz,
-                                                              d->part_rr, d->nb_node, o->cg_rtol, o->max_cg,
-                                                              d->part_q, d->cg);
-        k_cg_update<D><<<d->nb_node, kBlock, 0, c->stream>>>(nd, d->m, dt, d->fr, d->gd, d->p0, d->p1, d->Hp, d->r,
-                                                             d->z, d->del, d->part_q, d->tg.nblocks, d->part_rz,
-                                                             d->part_rr, d->cg);
+        launch(c, OSMPM_K_CG_PRODUCT, alg_bytes(OSMPM_K_CG_PRODUCT, D, d->np, nn), launched + j, k_cg_hvp<D>,
+               dim3(d->tg.nblocks), dim3(kBlock), (uint32_t)lh, d->tg, d->g, (const int *)d->cell_start,
+               (const double *)a.x, (const double *)d->Atil, d->cap, (const double *)d->m, dt, nd,
+               (const double *)d->z, d->p0, d->p1, d->Hp, (const double *)d->part_rz, (const double *)d->part_rr,
+               d->nb_node, o->cg_rtol, o->max_cg, d->part_q, d->cg);
+        launch(c, OSMPM_K_CG_UPDATE, alg_bytes(OSMPM_K_CG_UPDATE, D, d->np, nn), launched + j, k_cg_update<D>,
+               dim3(d->nb_node), dim3(kBlock), 0, nd, (const double *)d->m, dt, (const uint8_t *)d->fr,
+               (const double *)d->gd, (const double *)d->p0, (const double *)d->p1, d->Hp, d->r, d->z, d->del,
+               (const double *)d->part_q, d->tg.nblocks, d->part_rz, d->part_rr, d->cg);
       }
       launched += nb;
       if ((s = check_launch(c))) return s;
@@ -323,6 +417,7 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
       HIP_TRY(c, hipStreamSynchronize(c->stream));
       CgState hs;
       std::memcpy(&hs, c->h_pin, sizeof(CgState));
+      prof_harvest(c, hs.iter);
       if (hs.done || launched > o->max_cg) {
         S.cg_iters += hs.iter;
         d->cg_hint = hs.iter + 1;
@@ -597,6 +692,26 @@ osmpm_status osmpm_sync(osmpm_ctx *ctx) {
   return device_error(ctx, err);
 }
 
+osmpm_status osmpm_profile_enable(osmpm_ctx *ctx, int32_t enable) {
+  if (!ctx) return OSMPM_E_INVALID_ARG;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  prof_harvest(ctx);
+  for (auto &sl : ctx->slots) sl = ProfSlot{};
+  ctx->prof = enable != 0;
+  return OSMPM_OK;
+}
+
+osmpm_status osmpm_profile_query(osmpm_ctx *ctx, int32_t which, int64_t *launches, double *total_ms,
+                                 double *bytes) {
+  if (!ctx || which < 0 || which >= OSMPM_K_COUNT) return OSMPM_E_INVALID_ARG;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  prof_harvest(ctx);
+  if (launches) *launches = ctx->slots[which].launches;
+  if (total_ms) *total_ms = ctx->slots[which].ms;
+  if (bytes) *bytes = ctx->slots[which].bytes;
+  return OSMPM_OK;
+}
+
 const char *osmpm_last_error(const osmpm_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
 
 void osmpm_ctx_destroy(osmpm_ctx *ctx) {
@@ -605,6 +720,8 @@ void osmpm_ctx_destroy(osmpm_ctx *ctx) {
   (void)hipFree(ctx->d_err);
   (void)hipFree(ctx->d_count);
   if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
+  prof_harvest(ctx);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
 
