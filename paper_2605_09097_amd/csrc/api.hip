@@ -24,8 +24,12 @@ namespace {
 
 constexpr int kCgChunk = 8;
 
+// Particle arrays, component-major [rows][capacity].  Positions, masses and
+// volumes are FP64; velocities, affine matrices and deformation gradients
+// are stored in the domain's bulk type (FP64, or FP32 in the mixed path).
 struct PartBuf {
-  double *x = nullptr, *v = nullptr, *B = nullptr, *F = nullptr, *mass = nullptr, *vol = nullptr;
+  double *x = nullptr, *mass = nullptr, *vol = nullptr;
+  void *v = nullptr, *B = nullptr, *F = nullptr;
   int *mat = nullptr, *id = nullptr;
   uint8_t *flags = nullptr;
 };
@@ -92,8 +96,11 @@ struct osmpm_domain {
   uint8_t *gamma = nullptr, *recv = nullptr, *fr = nullptr;
   long long *q_all = nullptr, *q_bnd = nullptr, *qg = nullptr;
   // solver
-  double *gg = nullptr, *gd = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *del = nullptr,
-         *Hp = nullptr, *Atil = nullptr;
+  double *gg = nullptr;  // Newton gradient (FP64)
+  // bulk-type arrays: Jacobi diagonal, CG vectors, per-particle tangents
+  void *gd = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *del = nullptr, *Hp = nullptr,
+       *Atil = nullptr;
+  size_t tb = sizeof(double);  // bytes of the bulk type
   CgState *cg = nullptr;
   double *part_a = nullptr, *part_b = nullptr, *part_q = nullptr, *part_rz = nullptr, *part_rr = nullptr;
   int nb_node = 1, nb_part = 1;
@@ -128,6 +135,16 @@ osmpm_status dalloc(osmpm_domain *d, T **p, size_t n) {
   }
   d->allocs.push_back(q);
   *p = static_cast<T *>(q);
+  return OSMPM_OK;
+}
+
+osmpm_status dalloc_bytes(osmpm_domain *d, void **p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return fail(d->ctx, OSMPM_E_NO_MEMORY, "hipMalloc failed");
+  }
+  d->allocs.push_back(*p);
   return OSMPM_OK;
 }
 
@@ -193,19 +210,19 @@ void prof_harvest(osmpm_ctx *c, int cg_done = 1 << 30) {
 // Algorithmic bytes of one launch: the data the operation must move once
 // (particle arrays read or written, node arrays gathered, atomics counted as
 // read + write), independent of caching.
-double alg_bytes(int which, int D, double np, double nn) {
+double alg_bytes(int which, int D, double np, double nn, double tb) {
   const double ns = (D * D) * (D * D + 1) / 2.0;
   switch (which) {
     case OSMPM_K_CG_PRODUCT:  // x, Atil per particle; z, p_prev, p_cur, Hp (rmw) per DOF, mass per node
-      return np * 8.0 * (D + ns) + nn * 8.0 * (5.0 * D + 1.0);
+      return np * (8.0 * D + tb * ns) + nn * (tb * 5.0 * D + 8.0);
     case OSMPM_K_CG_UPDATE:  // Hp (read, clear), p, r (rmw), z, del (rmw), diag per DOF + mask; mass per node
-      return nn * (D * (8.0 * 8.0 + 1.0) + 8.0);
-    case OSMPM_K_P2G:  // x, v, B, mass, flags per particle; mass and momentum (rmw) per node
-      return np * (8.0 * (2.0 * D + D * D + 1.0) + 1.0) + nn * 16.0 * (1.0 + D);
-    case OSMPM_K_G2P:  // x, F read; x, v, B, F written; u and mass gathered per node
-      return np * 8.0 * (3.0 * D + 3.0 * D * D) + nn * 8.0 * (D + 1.0);
-    case OSMPM_K_GRAD_HESS:  // x, F, vol, mat read; Atil written; u read, gradient and diagonal rmw
-      return np * (8.0 * (D + D * D + 1.0 + ns) + 4.0) + nn * 8.0 * (5.0 * D);
+      return nn * (D * (tb * 8.0 + 1.0) + 8.0);
+    case OSMPM_K_P2G:  // x, mass, flags; v, B per particle; mass and momentum (rmw) per node
+      return np * (8.0 * (D + 1.0) + tb * (D + D * D) + 1.0) + nn * 16.0 * (1.0 + D);
+    case OSMPM_K_G2P:  // x read and written, F read; v, B, F written; u and mass gathered per node
+      return np * (16.0 * D + tb * (D + 3.0 * D * D)) + nn * 8.0 * (D + 1.0);
+    case OSMPM_K_GRAD_HESS:  // x, vol, mat, F read; Atil written; u read, gradient rmw, diagonal rmw
+      return np * (8.0 * (D + 1.0) + 4.0 + tb * (D * D + ns)) + nn * (8.0 * 3.0 * D + tb * 2.0 * D);
     default:
       return 0.0;
   }
@@ -260,7 +277,11 @@ osmpm_status check_launch(osmpm_ctx *c) {
 }
 
 void zero_d(osmpm_ctx *c, double *a, int64_t n) {
-  if (n > 0) k_fill_d<<<blocks_for(n), kBlock, 0, c->stream>>>(n, 0.0, a);
+  if (n > 0) k_fill<double><<<blocks_for(n), kBlock, 0, c->stream>>>(n, 0.0, a);
+}
+template <typename TB>
+void zero_tb(osmpm_ctx *c, void *a, int64_t n) {
+  if (n > 0) k_fill<TB><<<blocks_for(n), kBlock, 0, c->stream>>>(n, TB(0), static_cast<TB *>(a));
 }
 void zero_i64(osmpm_ctx *c, long long *a, int64_t n) {
   if (n > 0) k_fill_i64<<<blocks_for(n), kBlock, 0, c->stream>>>(n, a);
@@ -271,15 +292,17 @@ void zero_i32(osmpm_ctx *c, int *a, int64_t n) {
 
 int ndof(const osmpm_domain *d) { return d->g.nn * d->D; }
 
-size_t lds_p2g(const osmpm_domain *d) { return sizeof(double) * d->tg.nreg * (size_t)(2 + d->D + kMaxGroups); }
-size_t lds_grad(const osmpm_domain *d) { return sizeof(double) * d->tg.nreg * (size_t)(3 * d->D); }
-size_t lds_hvp(const osmpm_domain *d) { return sizeof(double) * d->tg.nreg * (size_t)(2 * d->D); }
+size_t lds_p2g(const osmpm_domain *d) {
+  return d->tg.nreg * (sizeof(long long) * (1 + kMaxGroups) + d->tb * (1 + d->D));
+}
+size_t lds_grad(const osmpm_domain *d) { return d->tg.nreg * (sizeof(double) * 2 * d->D + d->tb * d->D); }
+size_t lds_hvp(const osmpm_domain *d) { return d->tb * d->tg.nreg * (size_t)(2 * d->D); }
 
 double fixed_scale(const osmpm_domain *d) { return 4294967296.0 / d->m_ref; }
 long long tau_fixed(const osmpm_domain *d) { return llrint(d->tau * fixed_scale(d)); }
 
 // ---------------------------------------------------------------- sort + P2G
-template <int D>
+template <int D, typename TB>
 osmpm_status sort_particles(osmpm_domain *d) {
   osmpm_ctx *c = d->ctx;
   const int n = d->np;
@@ -294,9 +317,9 @@ osmpm_status sort_particles(osmpm_domain *d) {
   k_cellsort<<<blocks_for(d->nk, 1 << 20), kBlock, 0, c->stream>>>(d->nk, d->cell_start, d->perm);
   const int gb = blocks_for((int64_t)n * D * D, 2048);
   k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, D, d->perm, a.x, b.x, d->cap);
-  k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, D, d->perm, a.v, b.v, d->cap);
-  k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, d->perm, a.B, b.B, d->cap);
-  k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, d->perm, a.F, b.F, d->cap);
+  k_gather<TB><<<gb, kBlock, 0, c->stream>>>(n, D, d->perm, (const TB *)a.v, (TB *)b.v, d->cap);
+  k_gather<TB><<<gb, kBlock, 0, c->stream>>>(n, D * D, d->perm, (const TB *)a.B, (TB *)b.B, d->cap);
+  k_gather<TB><<<gb, kBlock, 0, c->stream>>>(n, D * D, d->perm, (const TB *)a.F, (TB *)b.F, d->cap);
   k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.mass, b.mass, d->cap);
   k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.vol, b.vol, d->cap);
   k_gather<int><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.mat, b.mat, d->cap);
@@ -306,10 +329,10 @@ osmpm_status sort_particles(osmpm_domain *d) {
   return check_launch(c);
 }
 
-template <int D>
+template <int D, typename TB>
 osmpm_status p2g_impl(osmpm_domain *d, bool want_qall) {
   osmpm_ctx *c = d->ctx;
-  osmpm_status s = sort_particles<D>(d);
+  osmpm_status s = sort_particles<D, TB>(d);
   if (s) return s;
   const int nn = d->g.nn;
   zero_d(c, d->m, nn);
@@ -322,9 +345,9 @@ osmpm_status p2g_impl(osmpm_domain *d, bool want_qall) {
   const PartBuf &a = d->pb[d->cur];
   if (d->np > 0) {
     const double Dinv = 4.0 * d->g.inv_dx * d->g.inv_dx;
-    launch(c, OSMPM_K_P2G, alg_bytes(OSMPM_K_P2G, D, d->np, nn), -1, k_p2g<D>, dim3(d->tg.nblocks), dim3(kBlock),
-           (uint32_t)lds_p2g(d), d->tg, d->g, (const int *)d->cell_start, (const double *)a.x, (const double *)a.v,
-           (const double *)a.B, (const double *)a.mass, (const uint8_t *)a.flags, d->cap, d->bc.n_groups,
+    launch(c, OSMPM_K_P2G, alg_bytes(OSMPM_K_P2G, D, d->np, nn, d->tb), -1, k_p2g<D, TB>, dim3(d->tg.nblocks),
+           dim3(kBlock), (uint32_t)lds_p2g(d), d->tg, d->g, (const int *)d->cell_start, (const double *)a.x,
+           (const TB *)a.v, (const TB *)a.B, (const double *)a.mass, (const uint8_t *)a.flags, d->cap, d->bc.n_groups,
            fixed_scale(d), Dinv, want_q, d->m, d->vn, d->q_all, d->qg, c->d_err);
   }
   k_p2g_final<D><<<blocks_for(nn, 1 << 20), kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->qg, d->bc, tau_fixed(d),
@@ -333,20 +356,20 @@ osmpm_status p2g_impl(osmpm_domain *d, bool want_qall) {
   return check_launch(c);
 }
 
-template <int D>
+template <int D, typename TB>
 osmpm_status g2p_impl(osmpm_domain *d, double dt) {
   osmpm_ctx *c = d->ctx;
   if (!d->have_p2g) return fail(c, OSMPM_E_STATE, "g2p before p2g");
   if (d->np == 0) return OSMPM_OK;
   PartBuf &a = d->pb[d->cur];
-  launch(c, OSMPM_K_G2P, alg_bytes(OSMPM_K_G2P, D, d->np, d->g.nn), -1, k_g2p<D>, dim3(blocks_for(d->np, 1 << 20)),
-         dim3(kBlock), 0, d->np, d->g, (const double *)d->m, (const double *)d->u, dt, a.x, a.v, a.B, a.F, d->cap,
-         c->d_err);
+  launch(c, OSMPM_K_G2P, alg_bytes(OSMPM_K_G2P, D, d->np, d->g.nn, d->tb), -1, k_g2p<D, TB>,
+         dim3(blocks_for(d->np, 1 << 20)), dim3(kBlock), 0, d->np, d->g, (const double *)d->m, (const double *)d->u, dt,
+         a.x, (TB *)a.v, (TB *)a.B, (TB *)a.F, d->cap, c->d_err);
   return check_launch(c);
 }
 
 // ---------------------------------------------------------------- implicit solve
-template <int D>
+template <int D, typename TB>
 osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm_solve_opts *o,
                         osmpm_solve_stats *st) {
   osmpm_ctx *c = d->ctx;
@@ -367,15 +390,16 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
   const size_t lg = lds_grad(d), lh = lds_hvp(d);
   for (int it = 0;; ++it) {
     zero_d(c, d->gg, nd);
-    zero_d(c, d->gd, nd);
+    zero_tb<TB>(c, d->gd, nd);
     if (d->np > 0)
-      launch(c, OSMPM_K_GRAD_HESS, alg_bytes(OSMPM_K_GRAD_HESS, D, d->np, nn), -1, k_grad_hess<D>,
+      launch(c, OSMPM_K_GRAD_HESS, alg_bytes(OSMPM_K_GRAD_HESS, D, d->np, nn, d->tb), -1, k_grad_hess<D, TB>,
              dim3(d->tg.nblocks), dim3(kBlock), (uint32_t)lg, d->tg, d->g, (const int *)d->cell_start,
-             (const double *)a.x, (const double *)a.F, (const double *)a.vol, (const int *)a.mat,
+             (const double *)a.x, (const TB *)a.F, (const double *)a.vol, (const int *)a.mat,
              (const double *)d->mu, (const double *)d->lam, d->cap, (const double *)d->u, 1, o->project_psd, d->gg,
-             d->gd, d->Atil, c->d_err);
-    k_grad_node<D><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->u, d->fr, dt, o->gravity[0],
-                                                         o->gravity[1], o->gravity[2], d->gg, d->gd, 1, d->part_a);
+             (TB *)d->gd, (TB *)d->Atil, c->d_err);
+    k_grad_node<D, TB><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->u, d->fr, dt, o->gravity[0],
+                                                             o->gravity[1], o->gravity[2], d->gg, (TB *)d->gd, 1,
+                                                             d->part_a);
     Fetch fg;
     fg.p[0] = d->part_a;
     fg.n[0] = d->nb_node;
@@ -391,8 +415,9 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
     }
     if (it == o->max_newton) break;
     // PCG on H del = -g
-    k_cg_init<D><<<d->nb_node, kBlock, 0, c->stream>>>(nd, d->gg, d->gd, d->fr, d->r, d->z, d->p0, d->p1, d->del,
-                                                       d->Hp, d->part_rz, d->part_rr, d->cg);
+    k_cg_init<D, TB><<<d->nb_node, kBlock, 0, c->stream>>>(nd, d->gg, (const TB *)d->gd, d->fr, (TB *)d->r,
+                                                           (TB *)d->z, (TB *)d->p0, (TB *)d->p1, (TB *)d->del,
+                                                           (TB *)d->Hp, d->part_rz, d->part_rr, d->cg);
     // Batches of iterations between host checks: the first batch is sized
     // from the previous solve's count so the loop usually ends after one or
     // two checks; iterations launched after convergence exit at once.
@@ -401,15 +426,16 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
     for (;;) {
       const int nb = std::min(batch, o->max_cg + 1 - launched);
       for (int j = 0; j < nb; ++j) {
-        launch(c, OSMPM_K_CG_PRODUCT, alg_bytes(OSMPM_K_CG_PRODUCT, D, d->np, nn), launched + j, k_cg_hvp<D>,
-               dim3(d->tg.nblocks), dim3(kBlock), (uint32_t)lh, d->tg, d->g, (const int *)d->cell_start,
-               (const double *)a.x, (const double *)d->Atil, d->cap, (const double *)d->m, dt, nd,
-               (const double *)d->z, d->p0, d->p1, d->Hp, (const double *)d->part_rz, (const double *)d->part_rr,
-               d->nb_node, o->cg_rtol, o->max_cg, d->part_q, d->cg);
-        launch(c, OSMPM_K_CG_UPDATE, alg_bytes(OSMPM_K_CG_UPDATE, D, d->np, nn), launched + j, k_cg_update<D>,
-               dim3(d->nb_node), dim3(kBlock), 0, nd, (const double *)d->m, dt, (const uint8_t *)d->fr,
-               (const double *)d->gd, (const double *)d->p0, (const double *)d->p1, d->Hp, d->r, d->z, d->del,
-               (const double *)d->part_q, d->tg.nblocks, d->part_rz, d->part_rr, d->cg);
+        launch(c, OSMPM_K_CG_PRODUCT, alg_bytes(OSMPM_K_CG_PRODUCT, D, d->np, nn, d->tb), launched + j,
+               k_cg_hvp<D, TB>, dim3(d->tg.nblocks), dim3(kBlock), (uint32_t)lh, d->tg, d->g,
+               (const int *)d->cell_start, (const double *)a.x, (const TB *)d->Atil, d->cap, (const double *)d->m, dt,
+               nd, (const TB *)d->z, (TB *)d->p0, (TB *)d->p1, (TB *)d->Hp, (const double *)d->part_rz,
+               (const double *)d->part_rr, d->nb_node, o->cg_rtol, o->max_cg, d->part_q, d->cg);
+        launch(c, OSMPM_K_CG_UPDATE, alg_bytes(OSMPM_K_CG_UPDATE, D, d->np, nn, d->tb), launched + j,
+               k_cg_update<D, TB>, dim3(d->nb_node), dim3(kBlock), 0, nd, (const double *)d->m, dt,
+               (const uint8_t *)d->fr, (const TB *)d->gd, (const TB *)d->p0, (const TB *)d->p1, (TB *)d->Hp,
+               (TB *)d->r, (TB *)d->z, (TB *)d->del, (const double *)d->part_q, d->tg.nblocks, d->part_rz,
+               d->part_rr, d->cg);
       }
       launched += nb;
       if ((s = check_launch(c))) return s;
@@ -430,9 +456,11 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
     bool accepted = false;
     for (int ls = 0; ls <= o->max_ls; ++ls) {
       if (d->np > 0)
-        k_delta_energy_p<D><<<d->nb_part, kBlock, 0, c->stream>>>(d->np, d->g, a.x, a.F, a.vol, a.mat, d->mu, d->lam,
-                                                                  d->cap, d->u, d->del, alpha, d->part_b);
-      k_delta_energy_n<D><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->u, d->del, dt, alpha,
+        k_delta_energy_p<D, TB><<<d->nb_part, kBlock, 0, c->stream>>>(d->np, d->g, a.x, (const TB *)a.F, a.vol,
+                                                                      a.mat, d->mu, d->lam, d->cap, d->u,
+                                                                      (const TB *)d->del, alpha, d->part_b);
+      k_delta_energy_n<D, TB><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->u, (const TB *)d->del, dt,
+                                                                    alpha,
                                                                 o->gravity[0], o->gravity[1], o->gravity[2],
                                                                 d->part_a);
       Fetch fe;
@@ -454,7 +482,7 @@ osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm
       S.ls_failed = 1;
       break;
     }
-    k_axpy<<<blocks_for(nd), kBlock, 0, c->stream>>>(nd, alpha, d->del, d->u);
+    k_axpy<TB><<<blocks_for(nd), kBlock, 0, c->stream>>>(nd, alpha, (const TB *)d->del, d->u);
     S.newton_iters += 1;
   }
   if ((s = check_launch(c))) return s;
@@ -512,9 +540,9 @@ osmpm_status copy_state(osmpm_domain *d, const PartBuf &from, PartBuf &to) {
   const int D = d->D;
   const size_t cap = (size_t)d->cap;
   HIP_TRY(c, hipMemcpyAsync(to.x, from.x, cap * D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.v, from.v, cap * D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.B, from.B, cap * D * D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.F, from.F, cap * D * D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(to.v, from.v, cap * D * d->tb, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(to.B, from.B, cap * D * D * d->tb, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(to.F, from.F, cap * D * D * d->tb, hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(to.mass, from.mass, cap * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(to.vol, from.vol, cap * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(to.mat, from.mat, cap * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
@@ -552,7 +580,7 @@ void add_stats(int &nt, int &cg, int &ls, const osmpm_solve_stats &s) {
 // One global frame of Alg. 1.  Buffers: B->w0 = Pi data of the current
 // iteration, B->w1 = Pi data of the next, B->w2 = v_B^(k+1); S->w0 = I(v_B^n),
 // S->w1 = I(v_B^(k+1)), S->w2 = previous I data for r_S.
-template <int D>
+template <int D, typename TB>
 osmpm_status schwarz_impl(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
                           osmpm_schwarz_stats *out) {
   osmpm_ctx *c = B->ctx;
@@ -563,7 +591,7 @@ osmpm_status schwarz_impl(osmpm_domain *B, osmpm_domain *S, double dT, const osm
   const int nB = B->g.nn * D, nS = S->g.nn * D;
   // Step 0
   if ((s = copy_state(S, S->pb[S->cur], S->st))) return s;
-  if ((s = p2g_impl<D>(B, true)) || (s = p2g_impl<D>(S, true))) return s;
+  if ((s = p2g_impl<D, TB>(B, true)) || (s = p2g_impl<D, TB>(S, true))) return s;
   if ((s = interface_impl<D>(B, S))) return s;
   if ((s = project_impl<D>(S, B, o->eps_tol, nullptr, B->w0))) return s;
   if ((s = interp_impl<D>(B, nullptr, S, S->w2))) return s;
@@ -571,20 +599,20 @@ osmpm_status schwarz_impl(osmpm_domain *B, osmpm_domain *S, double dT, const osm
     osmpm_solve_stats ss{};
     // 1. coarse solve with Pi data
     HIP_TRY(c, hipMemcpyAsync(B->vbc, B->w0, nB * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    if ((s = solve_impl<D>(B, dT, 1, &o->coarse, &ss))) return s;
+    if ((s = solve_impl<D, TB>(B, dT, 1, &o->coarse, &ss))) return s;
     add_stats(st.newton_B, st.cg_B, st.ls_B, ss);
     k_vel_from_u<D><<<blocks_for(B->g.nn, 1 << 20), kBlock, 0, c->stream>>>(B->g.nn, B->m, B->u, dT, B->w2);
     // 2. fine sub-cycling from the restored state
     if ((s = copy_state(S, S->st, S->pb[S->cur]))) return s;
-    if ((s = p2g_impl<D>(S, false))) return s;
+    if ((s = p2g_impl<D, TB>(S, false))) return s;
     if ((s = interp_impl<D>(B, nullptr, S, S->w0))) return s;
     if ((s = interp_impl<D>(B, B->w2, S, S->w1))) return s;
     for (int m = 1; m <= M; ++m) {
       k_temporal<<<blocks_for(nS), kBlock, 0, c->stream>>>(nS, (double)m / (double)M, S->w0, S->w1, S->vbc);
-      if ((s = solve_impl<D>(S, dt, 1, &o->fine, &ss))) return s;
+      if ((s = solve_impl<D, TB>(S, dt, 1, &o->fine, &ss))) return s;
       add_stats(st.newton_S, st.cg_S, st.ls_S, ss);
-      if ((s = g2p_impl<D>(S, dt))) return s;
-      if ((s = p2g_impl<D>(S, false))) return s;
+      if ((s = g2p_impl<D, TB>(S, dt))) return s;
+      if ((s = p2g_impl<D, TB>(S, false))) return s;
     }
     // 3. residuals
     if ((s = project_impl<D>(S, B, o->eps_tol, nullptr, B->w1))) return s;
@@ -599,7 +627,7 @@ osmpm_status schwarz_impl(osmpm_domain *B, osmpm_domain *S, double dT, const osm
     }
   }
   // 4. coarse G2P + advection with the last coarse solution
-  if ((s = g2p_impl<D>(B, dT))) return s;
+  if ((s = g2p_impl<D, TB>(B, dT))) return s;
   // receiver counts and ambiguous pairs
   {
     const int nbB = B->g.nn, nbS = S->g.nn;
@@ -649,6 +677,10 @@ TileGeom make_tiles(const osmpm_grid &gd, const int *T) {
 
 // ====================================================================== ABI
 #define DISPATCH(dim, call) ((dim) == 2 ? call<2> : call<3>)
+// Dispatch on dimension and bulk type of a domain.
+#define DISPATCH2(dom, call)                                                                              \
+  ((dom)->D == 2 ? ((dom)->precision == OSMPM_MIXED ? call<2, float> : call<2, double>)                 \
+                 : ((dom)->precision == OSMPM_MIXED ? call<3, float> : call<3, double>))
 
 extern "C" {
 
@@ -730,7 +762,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!ctx || !grid || !out) return OSMPM_E_INVALID_ARG;
   *out = nullptr;
   if (grid->dim != 2 && grid->dim != 3) return fail(ctx, OSMPM_E_INVALID_ARG, "dim must be 2 or 3");
-  if (precision != OSMPM_FP64) return fail(ctx, OSMPM_E_INVALID_ARG, "only OSMPM_FP64 is available");
+  if (precision != OSMPM_FP64 && precision != OSMPM_MIXED) return fail(ctx, OSMPM_E_INVALID_ARG, "bad precision");
   for (int a = 0; a < grid->dim; ++a)
     if (grid->n_nodes[a] < 3) return fail(ctx, OSMPM_E_INVALID_ARG, "grid needs >= 3 nodes per axis");
   if (grid->dim == 2 && grid->n_nodes[2] != 1) return fail(ctx, OSMPM_E_INVALID_ARG, "n_nodes[2] must be 1 in 2D");
@@ -745,6 +777,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   d->D = grid->dim;
   d->desc = *grid;
   d->precision = precision;
+  d->tb = (precision == OSMPM_MIXED) ? sizeof(float) : sizeof(double);
   d->cap = std::max<int64_t>(capacity, 1);
   GridDev &g = d->g;
   for (int a = 0; a < 3; ++a) {
@@ -770,9 +803,9 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   osmpm_status s = OSMPM_OK;
   auto part_alloc = [&](PartBuf &p) {
     if (!s) s = dalloc(d, &p.x, cap * D);
-    if (!s) s = dalloc(d, &p.v, cap * D);
-    if (!s) s = dalloc(d, &p.B, cap * D * D);
-    if (!s) s = dalloc(d, &p.F, cap * D * D);
+    if (!s) s = dalloc_bytes(d, &p.v, cap * D * d->tb);
+    if (!s) s = dalloc_bytes(d, &p.B, cap * D * D * d->tb);
+    if (!s) s = dalloc_bytes(d, &p.F, cap * D * D * d->tb);
     if (!s) s = dalloc(d, &p.mass, cap);
     if (!s) s = dalloc(d, &p.vol, cap);
     if (!s) s = dalloc(d, &p.mat, cap);
@@ -801,14 +834,14 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->q_bnd, nn);
   if (!s) s = dalloc(d, &d->qg, (size_t)nn * kMaxGroups);
   if (!s) s = dalloc(d, &d->gg, nd);
-  if (!s) s = dalloc(d, &d->gd, nd);
-  if (!s) s = dalloc(d, &d->r, nd);
-  if (!s) s = dalloc(d, &d->z, nd);
-  if (!s) s = dalloc(d, &d->p0, nd);
-  if (!s) s = dalloc(d, &d->p1, nd);
-  if (!s) s = dalloc(d, &d->del, nd);
-  if (!s) s = dalloc(d, &d->Hp, nd);
-  if (!s) s = dalloc(d, &d->Atil, cap * ns);
+  if (!s) s = dalloc_bytes(d, &d->gd, nd * d->tb);
+  if (!s) s = dalloc_bytes(d, &d->r, nd * d->tb);
+  if (!s) s = dalloc_bytes(d, &d->z, nd * d->tb);
+  if (!s) s = dalloc_bytes(d, &d->p0, nd * d->tb);
+  if (!s) s = dalloc_bytes(d, &d->p1, nd * d->tb);
+  if (!s) s = dalloc_bytes(d, &d->del, nd * d->tb);
+  if (!s) s = dalloc_bytes(d, &d->Hp, nd * d->tb);
+  if (!s) s = dalloc_bytes(d, &d->Atil, cap * ns * d->tb);
   if (!s) s = dalloc(d, &d->cg, 1);
   if (!s) s = dalloc(d, &d->part_a, nbmax);
   if (!s) s = dalloc(d, &d->part_b, nbmax);
@@ -873,10 +906,16 @@ osmpm_status osmpm_domain_set_particles(osmpm_domain *d, int64_t n, const double
   d->np = (int)n;
   if (n > 0) {
     const int gb = blocks_for(n * D * D, 2048);
-    k_aos_to_soa<<<gb, kBlock, 0, c->stream>>>(n, D, x, p.x, d->cap);
-    k_aos_to_soa<<<gb, kBlock, 0, c->stream>>>(n, D, v, p.v, d->cap);
-    k_aos_to_soa<<<gb, kBlock, 0, c->stream>>>(n, D * D, B, p.B, d->cap);
-    k_aos_to_soa<<<gb, kBlock, 0, c->stream>>>(n, D * D, F, p.F, d->cap);
+    k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D, x, p.x, d->cap);
+    if (d->precision == OSMPM_MIXED) {
+      k_aos_to_soa<float><<<gb, kBlock, 0, c->stream>>>(n, D, v, (float *)p.v, d->cap);
+      k_aos_to_soa<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, B, (float *)p.B, d->cap);
+      k_aos_to_soa<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, F, (float *)p.F, d->cap);
+    } else {
+      k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D, v, (double *)p.v, d->cap);
+      k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, B, (double *)p.B, d->cap);
+      k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, F, (double *)p.F, d->cap);
+    }
     HIP_TRY(c, hipMemcpyAsync(p.mass, mass, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(p.vol, vol, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(p.mat, mat, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
@@ -913,23 +952,24 @@ osmpm_status osmpm_domain_set_scene_bc(osmpm_domain *d, int32_t n_groups, const 
 
 osmpm_status osmpm_p2g(osmpm_domain *d) {
   if (!d) return OSMPM_E_INVALID_ARG;
-  return DISPATCH(d->D, p2g_impl)(d, true);
+  return DISPATCH2(d, p2g_impl)(d, true);
 }
 
 osmpm_status osmpm_implicit_solve(osmpm_domain *d, double dt, int32_t use_schwarz_bc, const osmpm_solve_opts *o,
                                   osmpm_solve_stats *st) {
   if (!d || !o) return OSMPM_E_INVALID_ARG;
   if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
-  return DISPATCH(d->D, solve_impl)(d, dt, use_schwarz_bc, o, st);
+  return DISPATCH2(d, solve_impl)(d, dt, use_schwarz_bc, o, st);
 }
 
 osmpm_status osmpm_g2p(osmpm_domain *d, double dt) {
   if (!d || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
-  return DISPATCH(d->D, g2p_impl)(d, dt);
+  return DISPATCH2(d, g2p_impl)(d, dt);
 }
 
 static bool pair_ok(const osmpm_domain *B, const osmpm_domain *S) {
-  return B && S && B->ctx == S->ctx && B->D == S->D && B->desc.h0 == S->desc.h0 && B->m_ref == S->m_ref;
+  return B && S && B->ctx == S->ctx && B->D == S->D && B->desc.h0 == S->desc.h0 && B->m_ref == S->m_ref &&
+         B->precision == S->precision;
 }
 
 osmpm_status osmpm_interface_build(osmpm_domain *B, osmpm_domain *S, int32_t *n_amb) {
@@ -974,15 +1014,15 @@ osmpm_status osmpm_schwarz_frame(osmpm_domain *B, osmpm_domain *S, double dT, co
                                  osmpm_schwarz_stats *st) {
   if (!pair_ok(B, S) || !o || !(dT > 0.0) || o->M < 1 || o->k_max < 1 || !(o->eps_tol >= 0.0))
     return OSMPM_E_INVALID_ARG;
-  return DISPATCH(B->D, schwarz_impl)(B, S, dT, o, st);
+  return DISPATCH2(B, schwarz_impl)(B, S, dT, o, st);
 }
 
 osmpm_status osmpm_single_frame(osmpm_domain *d, double dt, const osmpm_solve_opts *o, osmpm_solve_stats *st) {
   if (!d || !o || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
-  osmpm_status s = DISPATCH(d->D, p2g_impl)(d, false);
+  osmpm_status s = DISPATCH2(d, p2g_impl)(d, false);
   if (s) return s;
-  if ((s = DISPATCH(d->D, solve_impl)(d, dt, 0, o, st))) return s;
-  if ((s = DISPATCH(d->D, g2p_impl)(d, dt))) return s;
+  if ((s = DISPATCH2(d, solve_impl)(d, dt, 0, o, st))) return s;
+  if ((s = DISPATCH2(d, g2p_impl)(d, dt))) return s;
   return osmpm_sync(d->ctx);
 }
 
@@ -994,10 +1034,16 @@ osmpm_status osmpm_get_particles(osmpm_domain *d, double *x, double *v, double *
   if (n == 0) return OSMPM_OK;
   const PartBuf &p = d->pb[d->cur];
   const int gb = blocks_for(n * D * D, 2048);
-  if (x) k_soa_to_aos<<<gb, kBlock, 0, c->stream>>>(n, D, p.x, d->cap, x);
-  if (v) k_soa_to_aos<<<gb, kBlock, 0, c->stream>>>(n, D, p.v, d->cap, v);
-  if (B) k_soa_to_aos<<<gb, kBlock, 0, c->stream>>>(n, D * D, p.B, d->cap, B);
-  if (F) k_soa_to_aos<<<gb, kBlock, 0, c->stream>>>(n, D * D, p.F, d->cap, F);
+  if (x) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D, p.x, d->cap, x);
+  if (d->precision == OSMPM_MIXED) {
+    if (v) k_soa_to_aos<float><<<gb, kBlock, 0, c->stream>>>(n, D, (const float *)p.v, d->cap, v);
+    if (B) k_soa_to_aos<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const float *)p.B, d->cap, B);
+    if (F) k_soa_to_aos<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const float *)p.F, d->cap, F);
+  } else {
+    if (v) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D, (const double *)p.v, d->cap, v);
+    if (B) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const double *)p.B, d->cap, B);
+    if (F) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const double *)p.F, d->cap, F);
+  }
   if (id) HIP_TRY(c, hipMemcpyAsync(id, p.id, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
   return check_launch(c);
 }

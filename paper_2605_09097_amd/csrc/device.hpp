@@ -166,8 +166,8 @@ __device__ inline void tile_origin(const TileGeom &tg, int t, int *org) {
 }
 
 // ---------------------------------------------------------------- small dense algebra
-template <int D>
-__device__ inline double det(const double *F) {
+template <int D, typename T>
+__device__ inline T det(const T *F) {
   if constexpr (D == 2) {
     return F[0] * F[3] - F[1] * F[2];
   } else {
@@ -176,8 +176,8 @@ __device__ inline double det(const double *F) {
   }
 }
 
-template <int D>
-__device__ inline void cofactor(const double *F, double *C) {
+template <int D, typename T>
+__device__ inline void cofactor(const T *F, T *C) {
   if constexpr (D == 2) {
     C[0] = F[3];
     C[1] = -F[2];
@@ -197,16 +197,17 @@ __device__ inline void cofactor(const double *F, double *C) {
 }
 
 // Neo-Hookean first Piola stress P = mu (F - F^-T) + lam ln J F^-T and,
-// optionally, A = dP/dF stored as an n x n matrix, n = D*D, index (a*D+b).
-template <int D>
-__device__ inline bool nh_stress(const double *F, double mu, double lam, double *P, double *A) {
+// optionally, A = dP/dF stored as an n x n matrix, n = D*D, index (a*D+b),
+// in the arithmetic of T.
+template <int D, typename T>
+__device__ inline bool nh_stress(const T *F, T mu, T lam, T *P, T *A) {
   constexpr int n = D * D;
-  const double J = det<D>(F);
-  if (!(J > 0.0)) return false;
-  const double lnJ = log(J);
-  double C[n], Fi[n];
-  cofactor<D>(F, C);
-  const double iJ = 1.0 / J;
+  const T J = det<D, T>(F);
+  if (!(J > T(0))) return false;
+  const T lnJ = log(J);
+  T C[n], Fi[n];
+  cofactor<D, T>(F, C);
+  const T iJ = T(1) / J;
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -216,12 +217,12 @@ __device__ inline bool nh_stress(const double *F, double mu, double lam, double 
     for (int a = 0; a < D; ++a)
 #pragma unroll
       for (int b = 0; b < D; ++b) {
-        const double FiT = Fi[b * D + a];
+        const T FiT = Fi[b * D + a];
         P[a * D + b] = mu * (F[a * D + b] - FiT) + lam * lnJ * FiT;
       }
   }
   if (A) {
-    const double c1 = mu - lam * lnJ;
+    const T c1 = mu - lam * lnJ;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -230,7 +231,7 @@ __device__ inline bool nh_stress(const double *F, double mu, double lam, double 
         for (int c = 0; c < D; ++c)
 #pragma unroll
           for (int e = 0; e < D; ++e) {
-            double v = c1 * Fi[e * D + a] * Fi[b * D + c] + lam * Fi[b * D + a] * Fi[e * D + c];
+            T v = c1 * Fi[e * D + a] * Fi[b * D + c] + lam * Fi[b * D + a] * Fi[e * D + c];
             if (a == c && b == e) v += mu;
             A[(a * D + b) * n + (c * D + e)] = v;
           }
@@ -241,49 +242,50 @@ __device__ inline bool nh_stress(const double *F, double mu, double lam, double 
 // Projection of the symmetric n x n matrix A onto the PSD cone by a cyclic
 // Jacobi eigendecomposition with negative eigenvalues clamped to zero.  A is
 // left untouched when no eigenvalue is negative.  All indices are
-// compile-time constants so W and V stay in registers.
-template <int n>
-__device__ inline void psd_project(double *A) {
-  double W[n * n], V[n * n];
+// compile-time constants so W and V stay in registers.  Sweeps stop when the
+// off-diagonal mass falls below the precision of T.
+template <int n, typename T>
+__device__ inline void psd_project(T *A) {
+  constexpr T tol2 = sizeof(T) == 8 ? T(1e-32) : T(1e-13);
+  T W[n * n], V[n * n];
 #pragma unroll
   for (int i = 0; i < n * n; ++i) W[i] = A[i];
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
-    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? 1.0 : 0.0;
-  double diag2 = 0.0;
+    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j) ? T(1) : T(0);
+  T diag2 = T(0);
 #pragma unroll
   for (int i = 0; i < n; ++i) diag2 += W[i * n + i] * W[i * n + i];
   for (int sweep = 0; sweep < 50; ++sweep) {
-    double off = 0.0;
+    T off = T(0);
 #pragma unroll
     for (int p = 0; p < n; ++p)
 #pragma unroll
       for (int q = p + 1; q < n; ++q) off += W[p * n + q] * W[p * n + q];
-    if (off <= 1e-32 * diag2 || off == 0.0) break;
+    if (off <= tol2 * diag2 || off == T(0)) break;
 #pragma unroll
     for (int p = 0; p < n; ++p)
 #pragma unroll
       for (int q = p + 1; q < n; ++q) {
-        const double apq = W[p * n + q];
-        if (apq != 0.0) {
-          const double theta = (W[q * n + q] - W[p * n + p]) / (2.0 * apq);
-          const double t = (theta >= 0.0 ? 1.0 : -1.0) /
-                           (__builtin_fabs(theta) + __builtin_sqrt(theta * theta + 1.0));
-          const double c = 1.0 / __builtin_sqrt(t * t + 1.0);
-          const double s = t * c;
+        const T apq = W[p * n + q];
+        if (apq != T(0)) {
+          const T theta = (W[q * n + q] - W[p * n + p]) / (T(2) * apq);
+          const T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+          const T c = T(1) / sqrt(t * t + T(1));
+          const T s = t * c;
 #pragma unroll
           for (int k = 0; k < n; ++k) {
-            const double wkp = W[k * n + p], wkq = W[k * n + q];
+            const T wkp = W[k * n + p], wkq = W[k * n + q];
             W[k * n + p] = c * wkp - s * wkq;
             W[k * n + q] = s * wkp + c * wkq;
-            const double vkp = V[k * n + p], vkq = V[k * n + q];
+            const T vkp = V[k * n + p], vkq = V[k * n + q];
             V[k * n + p] = c * vkp - s * vkq;
             V[k * n + q] = s * vkp + c * vkq;
           }
 #pragma unroll
           for (int k = 0; k < n; ++k) {
-            const double wpk = W[p * n + k], wqk = W[q * n + k];
+            const T wpk = W[p * n + k], wqk = W[q * n + k];
             W[p * n + k] = c * wpk - s * wqk;
             W[q * n + k] = s * wpk + c * wqk;
           }
@@ -292,16 +294,16 @@ __device__ inline void psd_project(double *A) {
   }
   bool neg = false;
 #pragma unroll
-  for (int i = 0; i < n; ++i) neg |= (W[i * n + i] < 0.0);
+  for (int i = 0; i < n; ++i) neg |= (W[i * n + i] < T(0));
   if (!neg) return;
-  double lam[n];
+  T lam[n];
 #pragma unroll
-  for (int k = 0; k < n; ++k) lam[k] = W[k * n + k] > 0.0 ? W[k * n + k] : 0.0;
+  for (int k = 0; k < n; ++k) lam[k] = W[k * n + k] > T(0) ? W[k * n + k] : T(0);
 #pragma unroll
   for (int i = 0; i < n; ++i)
 #pragma unroll
     for (int j = 0; j < n; ++j) {
-      double v = 0.0;
+      T v = T(0);
 #pragma unroll
       for (int k = 0; k < n; ++k) v += V[i * n + k] * lam[k] * V[j * n + k];
       A[i * n + j] = v;

@@ -13,10 +13,13 @@
 namespace osmpm {
 
 // ====================================================================== misc
-__global__ void k_fill_d(int64_t n, double v, double *a) {
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T *a) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
 }
+template __global__ void k_fill<double>(int64_t, double, double *);
+template __global__ void k_fill<float>(int64_t, float, float *);
 __global__ void k_fill_i64(int64_t n, long long *a) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = 0;
@@ -30,19 +33,25 @@ __global__ void k_fill_u8(int64_t n, uint8_t *a) {
     a[i] = 0;
 }
 
-// [n][c] (caller layout) -> [c][cap] (library layout)
-__global__ void k_aos_to_soa(int64_t n, int c, const double *src, double *dst, int64_t cap) {
+// [n][c] (caller layout, FP64) -> [c][cap] (library layout, storage type T)
+template <typename T>
+__global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * c; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = i / c, r = i % c;
-    dst[r * cap + p] = src[i];
+    dst[r * cap + p] = (T)src[i];
   }
 }
-__global__ void k_soa_to_aos(int64_t n, int c, const double *src, int64_t cap, double *dst) {
+template <typename T>
+__global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * c; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = i / c, r = i % c;
-    dst[i] = src[r * cap + p];
+    dst[i] = (double)src[r * cap + p];
   }
 }
+template __global__ void k_aos_to_soa<double>(int64_t, int, const double *, double *, int64_t);
+template __global__ void k_aos_to_soa<float>(int64_t, int, const double *, float *, int64_t);
+template __global__ void k_soa_to_aos<double>(int64_t, int, const double *, int64_t, double *);
+template __global__ void k_soa_to_aos<float>(int64_t, int, const float *, int64_t, double *);
 __global__ void k_iota(int n, int *a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = i;
 }
@@ -155,6 +164,7 @@ __global__ void k_gather(int n, int rows, const int *perm, const T *src, T *dst,
   }
 }
 template __global__ void k_gather<double>(int, int, const int *, const double *, double *, int64_t);
+template __global__ void k_gather<float>(int, int, const int *, const float *, float *, int64_t);
 template __global__ void k_gather<int>(int, int, const int *, const int *, int *, int64_t);
 template __global__ void k_gather<uint8_t>(int, int, const int *, const uint8_t *, uint8_t *, int64_t);
 
@@ -207,9 +217,11 @@ __device__ inline int region_slot(const TileGeom &tg, const int *l, const int *k
 // ====================================================================== P2G
 // APIC P2G (Eq. p2g_transfer) of one tile into LDS, then global atomics.
 // Also the fixed-point node masses (all particles, and per scene group).
-template <int D>
+// TB is the accumulation type of the tile (FP32 in the mixed path); the
+// tile sums are added to the FP64 grid.
+template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const int *cell_start, const double *x,
-                                                const double *v, const double *B, const double *mass,
+                                                const TB *v, const TB *B, const double *mass,
                                                 const uint8_t *flags, int64_t cap, int n_groups, double scale,
                                                 double Dinv, int want_q, double *gm, double *gmv,
                                                 long long *q_all, long long *qg, int *err) {
@@ -218,11 +230,11 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
   int p0, p1, org[3];
   if (!tile_range(tg, cell_start, t, p0, p1, org) || p0 == p1) return;
   const int nreg = tg.nreg;
-  double *lm = lds;
-  double *lmv = lds + nreg;
-  long long *lq = reinterpret_cast<long long *>(lds + (1 + D) * nreg);
+  long long *lq = reinterpret_cast<long long *>(lds);
+  TB *lm = reinterpret_cast<TB *>(lq + (size_t)(1 + kMaxGroups) * nreg);
+  TB *lmv = lm + nreg;
   const int nq = want_q ? 1 + n_groups : 0;
-  for (int r = threadIdx.x; r < nreg * (1 + D); r += kBlock) lds[r] = 0.0;
+  for (int r = threadIdx.x; r < nreg * (1 + D); r += kBlock) lm[r] = TB(0);
   for (int r = threadIdx.x; r < nreg * nq; r += kBlock) lq[r] = 0;
   __syncthreads();
   for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
@@ -230,10 +242,10 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       xp[a] = x[a * cap + p];
-      vp[a] = v[a * cap + p];
+      vp[a] = (double)v[a * cap + p];
     }
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Bp[k] = B[k * cap + p];
+    for (int k = 0; k < D * D; ++k) Bp[k] = (double)B[k * cap + p];
     Stencil<D> st;
     stencil_eval<D>(xp, g, st);
     int l[3];
@@ -254,13 +266,13 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
       for (int a = 0; a < D; ++a) dxv[a] = ((double)k[a] - st.f[a]) * g.dx;
       const int r = region_slot<D>(tg, l, k);
       const double mN = mp * N;
-      atomicAdd(&lm[r], mN);
+      atomicAdd(&lm[r], (TB)mN);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         double aff = 0.0;
 #pragma unroll
         for (int b = 0; b < D; ++b) aff += Bp[a * D + b] * dxv[b];
-        atomicAdd(&lmv[a * nreg + r], mN * (vp[a] + Dinv * aff));
+        atomicAdd(&lmv[a * nreg + r], (TB)(mN * (vp[a] + Dinv * aff)));
       }
       if (want_q) {
         const long long q = fixed_mass(N, mq);
@@ -275,11 +287,11 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
   for (int r = threadIdx.x; r < nreg; r += kBlock) {
     const int i = region_node<D>(tg, g, org, r);
     if (i < 0) continue;
-    const double m = lm[r];
+    const double m = (double)lm[r];
     if (m != 0.0) {
       atomicAdd(&gm[i], m);
 #pragma unroll
-      for (int a = 0; a < D; ++a) atomicAdd(&gmv[i * D + a], lmv[a * nreg + r]);
+      for (int a = 0; a < D; ++a) atomicAdd(&gmv[i * D + a], (double)lmv[a * nreg + r]);
     }
     if (want_q) {
       if (lq[r] != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&q_all[i]), (unsigned long long)lq[r]);
@@ -318,9 +330,9 @@ __global__ void k_p2g_final(GridDev g, const double *gm, double *gv, const long 
 // ====================================================================== G2P
 // APIC G2P with v_i = u_i / dt (Eqs. g2p_v, g2p_B), F <- (I + sum u_i gradN^T) F
 // (Eq. F_update) and x <- x + dt v_p (Eq. advection).
-template <int D>
-__global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, double dt, double *x, double *v,
-                      double *B, double *F, int64_t cap, int *err) {
+template <int D, typename TB>
+__global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, double dt, double *x, TB *v, TB *B,
+                      TB *F, int64_t cap, int *err) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   double xp[D];
@@ -366,7 +378,7 @@ __global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, doubl
   }
   double Fp[D * D];
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) Fp[k] = F[k * cap + p];
+  for (int k = 0; k < D * D; ++k) Fp[k] = (double)F[k * cap + p];
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -374,12 +386,12 @@ __global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, doubl
       double t = Fp[a * D + b];
 #pragma unroll
       for (int e = 0; e < D; ++e) t += G[a * D + e] * Fp[e * D + b];
-      F[(a * D + b) * cap + p] = t;
-      B[(a * D + b) * cap + p] = Bp[a * D + b];
+      F[(a * D + b) * cap + p] = (TB)t;
+      B[(a * D + b) * cap + p] = (TB)Bp[a * D + b];
     }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    v[a * cap + p] = vp[a];
+    v[a * cap + p] = (TB)vp[a];
     x[a * cap + p] = xp[a] + dt * vp[a];
   }
 }
@@ -445,17 +457,17 @@ __global__ void k_bc_init(GridDev g, const double *gm, const double *gv, const i
 }
 
 // ====================================================================== gradient + Hessian
-// Per particle at the iterate u: F = (I + sum u_i gradN_i^T) F^n, P(F); the
-// gradient V P F^nT gradN_i is scattered.  With want_hess the particle's
-// tangent A = dP/dF (PSD-projected when asked) is folded with F^n and V,
-// Atil = V C^T A C with C: G -> G F^n, stored packed, and its contribution to
-// the Jacobi diagonal is scattered.
-template <int D>
+// Per particle at the iterate u: F = (I + sum u_i gradN_i^T) F^n and P(F) in
+// FP64; the gradient V P F^nT gradN_i is scattered (FP64).  With want_hess
+// the particle's tangent A = dP/dF (PSD-projected when asked) is evaluated in
+// the bulk type TB, folded with F^n and V, Atil = V C^T A C with C: G -> G F^n,
+// stored packed, and its contribution to the Jacobi diagonal is scattered.
+template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, const int *cell_start,
-                                                      const double *x, const double *F, const double *vol,
+                                                      const double *x, const TB *F, const double *vol,
                                                       const int *mat, const double *mu_t, const double *lam_t,
                                                       int64_t cap, const double *u, int want_hess, int project,
-                                                      double *gg, double *gdiag, double *Atil, int *err) {
+                                                      double *gg, TB *gdiag, TB *Atil, int *err) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   extern __shared__ double lds[];
@@ -465,14 +477,14 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
   const int nreg = tg.nreg;
   double *lu = lds;
   double *lg = lds + D * nreg;
-  double *ld = lds + 2 * D * nreg;
+  TB *ld = reinterpret_cast<TB *>(lds + 2 * D * nreg);
   for (int r = threadIdx.x; r < nreg; r += kBlock) {
     const int i = region_node<D>(tg, g, org, r);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       lu[a * nreg + r] = (i >= 0) ? u[i * D + a] : 0.0;
       lg[a * nreg + r] = 0.0;
-      ld[a * nreg + r] = 0.0;
+      ld[a * nreg + r] = TB(0);
     }
   }
   __syncthreads();
@@ -490,7 +502,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
     double Fn[n], Gu[n];
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-      Fn[k] = F[k * cap + p];
+      Fn[k] = (double)F[k * cap + p];
       Gu[k] = 0.0;
     }
 #pragma unroll
@@ -519,8 +531,8 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
       }
     const int mt = mat[p];
     const double mu = mu_t[mt], lam = lam_t[mt], V = vol[p];
-    double P[n], A[n * n];
-    if (!nh_stress<D>(Fc, mu, lam, P, want_hess ? A : nullptr)) {
+    double P[n];
+    if (!nh_stress<D, double>(Fc, mu, lam, P, nullptr)) {
       atomicOr(err, kErrInverted);
       continue;
     }
@@ -535,22 +547,30 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
         for (int c = 0; c < D; ++c) tv += P[a * D + c] * Fn[b * D + c];
         T[a * D + b] = V * tv;
       }
-    double At[ns];
+    TB At[ns];
     if (want_hess) {
-      if (project) psd_project<n>(A);
+      TB Fb[n], Fnb[n], A[n * n];
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        Fb[k] = (TB)Fc[k];
+        Fnb[k] = (TB)Fn[k];
+      }
+      nh_stress<D, TB>(Fb, (TB)mu, (TB)lam, nullptr, A);
+      if (project) psd_project<n, TB>(A);
       // T1[(ab),(cz)] = sum_y F_by A[(ay),(cz)];  Atil[(ab),(ce)] = V sum_z T1[(ab),(cz)] F_ez
-      double T1[n * n];
+      TB T1[n * n];
 #pragma unroll
       for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = 0; b < D; ++b)
 #pragma unroll
           for (int q = 0; q < n; ++q) {
-            double tv = 0.0;
+            TB tv = TB(0);
 #pragma unroll
-            for (int y = 0; y < D; ++y) tv += Fn[b * D + y] * A[(a * D + y) * n + q];
+            for (int y = 0; y < D; ++y) tv += Fnb[b * D + y] * A[(a * D + y) * n + q];
             T1[(a * D + b) * n + q] = tv;
           }
+      const TB Vb = (TB)V;
 #pragma unroll
       for (int rr = 0; rr < n; ++rr)
 #pragma unroll
@@ -559,10 +579,10 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
           for (int e = 0; e < D; ++e) {
             const int cc = c * D + e;
             if (cc < rr) continue;
-            double tv = 0.0;
+            TB tv = TB(0);
 #pragma unroll
-            for (int z = 0; z < D; ++z) tv += T1[rr * n + c * D + z] * Fn[e * D + z];
-            At[sym_index<n>(rr, cc)] = V * tv;
+            for (int z = 0; z < D; ++z) tv += T1[rr * n + c * D + z] * Fnb[e * D + z];
+            At[sym_index<n>(rr, cc)] = Vb * tv;
           }
 #pragma unroll
       for (int k = 0; k < ns; ++k) Atil[k * cap + p] = At[k];
@@ -582,16 +602,19 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
         atomicAdd(&lg[a * nreg + r], tv);
       }
       if (want_hess) {
+        TB gb[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) gb[a] = (TB)gN[a];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          double dv = 0.0;
+          TB dv = TB(0);
 #pragma unroll
           for (int b = 0; b < D; ++b)
 #pragma unroll
             for (int e = 0; e < D; ++e) {
               const int r1 = a * D + b, c1 = a * D + e;
-              const double av = (r1 <= c1) ? At[sym_index<n>(r1, c1)] : At[sym_index<n>(c1, r1)];
-              dv += av * gN[b] * gN[e];
+              const TB av = (r1 <= c1) ? At[sym_index<n>(r1, c1)] : At[sym_index<n>(c1, r1)];
+              dv += av * gb[b] * gb[e];
             }
           atomicAdd(&ld[a * nreg + r], dv);
         }
@@ -607,8 +630,8 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
       const double gv = lg[a * nreg + r];
       if (gv != 0.0) atomicAdd(&gg[i * D + a], gv);
       if (want_hess) {
-        const double dv = ld[a * nreg + r];
-        if (dv != 0.0) atomicAdd(&gdiag[i * D + a], dv);
+        const TB dv = ld[a * nreg + r];
+        if (dv != TB(0)) atomicAdd(&gdiag[i * D + a], dv);
       }
     }
   }
@@ -617,9 +640,9 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
 // Node part of the gradient: + m/dt^2 (u - dt v^n) - m g on active nodes,
 // masked to free DOFs; partial |g|^2.  With want_hess the Jacobi diagonal
 // becomes scatter + m/dt^2 (1 on non-free DOFs).
-template <int D>
+template <int D, typename TB>
 __global__ void k_grad_node(GridDev g, const double *gm, const double *gv, const double *u, const uint8_t *fr,
-                            double dt, double gx, double gy, double gz, double *gg, double *gdiag, int want_hess,
+                            double dt, double gx, double gy, double gz, double *gg, TB *gdiag, int want_hess,
                             double *part) {
   __shared__ double red[kBlock / 64];
   const double grav[3] = {gx, gy, gz};
@@ -635,7 +658,7 @@ __global__ void k_grad_node(GridDev g, const double *gm, const double *gv, const
       if (!fr[k]) gval = 0.0;
       gg[k] = gval;
       s2 += gval * gval;
-      if (want_hess) gdiag[k] = fr[k] ? gdiag[k] + m * idt2 : 1.0;
+      if (want_hess) gdiag[k] = fr[k] ? (TB)((double)gdiag[k] + m * idt2) : TB(1);
     }
   }
   const double t = block_sum(s2, red);
@@ -643,27 +666,39 @@ __global__ void k_grad_node(GridDev g, const double *gm, const double *gv, const
 }
 
 // ====================================================================== CG
+// The CG vectors r, z, p, Hp, del and the Jacobi diagonal are stored in the
+// bulk type TB (FP32 in the mixed path); scalars, dot products and the
+// vector arithmetic are FP64.
+
+// New search direction z + beta p_prev, rounded to the storage type.  Written
+// without FMA contraction so the LDS copy and the stored copy agree bit for bit.
+template <typename TB>
+__device__ inline TB cg_direction(TB z, double beta, TB pp) {
+#pragma clang fp contract(off)
+  const double t = beta * (double)pp;
+  return (TB)((double)z + t);
+}
+
 // r = -g, z = r / D on free DOFs; search-direction buffers, direction and
 // product cleared; partial (r, z) and (r, r).
-template <int D>
-__global__ void k_cg_init(int ndof, const double *gg, const double *gdiag, const uint8_t *fr, double *r, double *z,
-                          double *p0, double *p1, double *del, double *Hp, double *part_rz, double *part_rr,
-                          CgState *S) {
+template <int D, typename TB>
+__global__ void k_cg_init(int ndof, const double *gg, const TB *gdiag, const uint8_t *fr, TB *r, TB *z, TB *p0,
+                          TB *p1, TB *del, TB *Hp, double *part_rz, double *part_rr, CgState *S) {
   __shared__ double red[kBlock / 64];
   double rz = 0.0, rr = 0.0;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ndof; k += gridDim.x * blockDim.x) {
     const bool f = fr[k];
-    const double rv = f ? -gg[k] : 0.0;
-    const double zv = f ? rv / gdiag[k] : 0.0;
+    const TB rv = f ? (TB)(-gg[k]) : TB(0);
+    const TB zv = f ? (TB)((double)rv / (double)gdiag[k]) : TB(0);
     r[k] = rv;
     z[k] = zv;
-    p0[k] = 0.0;
-    p1[k] = 0.0;
-    del[k] = 0.0;
-    Hp[k] = 0.0;
+    p0[k] = TB(0);
+    p1[k] = TB(0);
+    del[k] = TB(0);
+    Hp[k] = TB(0);
     if (f) {
-      rz += rv * zv;
-      rr += rv * rv;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
     }
   }
   const double a = block_sum(rz, red);
@@ -705,10 +740,10 @@ __device__ inline void block_sum2(double &a, double &b, double *lds8) {
 // p^T H p = sum_p G:Atil:G + sum_i m_i/dt^2 |p_i|^2, so the product and its
 // curvature complete in one pass.  All global loads that do not depend on
 // beta are issued before the reduction so their latencies overlap.
-template <int D>
+template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const int *cell_start, const double *x,
-                                                   const double *Atil, int64_t cap, const double *gm, double dt,
-                                                   int ndof, const double *z, double *pA, double *pB, double *Hp,
+                                                   const TB *Atil, int64_t cap, const double *gm, double dt,
+                                                   int ndof, const TB *z, TB *pA, TB *pB, TB *Hp,
                                                    const double *part_rz, const double *part_rr, int n_part,
                                                    double rtol, int max_cg, double *part_q, CgState *S) {
   constexpr int n = D * D;
@@ -717,8 +752,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
   __shared__ double red[8];
   const int tid = threadIdx.x;
   const int it = S->knext;
-  const double *pprev = (it & 1) ? pA : pB;
-  double *pcur = (it & 1) ? pB : pA;
+  const TB *pprev = (it & 1) ? pA : pB;
+  TB *pcur = (it & 1) ? pB : pA;
   // tile and its particle range
   const int t = tile_of_block(tg, blockIdx.x);
   int p0 = 0, p1 = 0, org[3] = {0, 0, 0};
@@ -731,25 +766,27 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
     prr += part_rr[i];
   }
   const int k0 = blockIdx.x * kBlock + tid;
-  double nz = 0.0, npv = 0.0, nm = 0.0;
+  TB nz = TB(0), npv = TB(0);
+  double nm = 0.0;
   if (k0 < ndof) {
     nz = z[k0];
     npv = pprev[k0];
     nm = gm[k0 / D];
   }
   int ri = -1;
-  double rzv[D], rpv[D];
+  TB rzv[D], rpv[D];
   if (tile_ok && tid < nreg) {
     ri = region_node<D>(tg, g, org, tid);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      rzv[a] = (ri >= 0) ? z[ri * D + a] : 0.0;
-      rpv[a] = (ri >= 0) ? pprev[ri * D + a] : 0.0;
+      rzv[a] = (ri >= 0) ? z[ri * D + a] : TB(0);
+      rpv[a] = (ri >= 0) ? pprev[ri * D + a] : TB(0);
     }
   }
   const int pp = p0 + tid;
   const bool have_p = tile_ok && pp < p1;
-  double xp[D], At[ns];
+  double xp[D];
+  TB At[ns];
   if (have_p) {
 #pragma unroll
     for (int a = 0; a < D; ++a) xp[a] = x[a * cap + pp];
@@ -773,31 +810,31 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
   double q = 0.0;
   // node part: owned DOFs of the new direction and its mass term
   if (k0 < ndof) {
-    const double pv = nz + beta * npv;
+    const TB pv = cg_direction<TB>(nz, beta, npv);
     pcur[k0] = pv;
-    q += nm * mdt * pv * pv;
+    q += nm * mdt * (double)pv * (double)pv;
   }
   for (int k = k0 + gridDim.x * kBlock; k < ndof; k += gridDim.x * kBlock) {
-    const double pv = z[k] + beta * pprev[k];
+    const TB pv = cg_direction<TB>(z[k], beta, pprev[k]);
     pcur[k] = pv;
-    q += gm[k / D] * mdt * pv * pv;
+    q += gm[k / D] * mdt * (double)pv * (double)pv;
   }
   if (tile_ok) {
-    double *lp = lds;
-    double *lh = lds + D * nreg;
+    TB *lp = reinterpret_cast<TB *>(lds);
+    TB *lh = lp + D * nreg;
     if (tid < nreg) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        lp[a * nreg + tid] = (ri >= 0) ? rzv[a] + beta * rpv[a] : 0.0;
-        lh[a * nreg + tid] = 0.0;
+        lp[a * nreg + tid] = (ri >= 0) ? cg_direction<TB>(rzv[a], beta, rpv[a]) : TB(0);
+        lh[a * nreg + tid] = TB(0);
       }
     }
     for (int r = tid + kBlock; r < nreg; r += kBlock) {
       const int i = region_node<D>(tg, g, org, r);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        lp[a * nreg + r] = (i >= 0) ? z[i * D + a] + beta * pprev[i * D + a] : 0.0;
-        lh[a * nreg + r] = 0.0;
+        lp[a * nreg + r] = (i >= 0) ? cg_direction<TB>(z[i * D + a], beta, pprev[i * D + a]) : TB(0);
+        lh[a * nreg + r] = TB(0);
       }
     }
     __syncthreads();
@@ -812,9 +849,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
       stencil_eval<D>(xp, g, st);
       int l[3];
       if (!local_base<D>(tg, st, org, l)) continue;
-      double G[n];
+      TB G[n];
 #pragma unroll
-      for (int k = 0; k < n; ++k) G[k] = 0.0;
+      for (int k = 0; k < n; ++k) G[k] = TB(0);
 #pragma unroll
       for (int s = 0; s < stencil_count<D>(); ++s) {
         int k[3];
@@ -824,21 +861,23 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
         const int r = region_slot<D>(tg, l, k);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const double pa = lp[a * nreg + r];
+          const TB pa = lp[a * nreg + r];
 #pragma unroll
-          for (int b = 0; b < D; ++b) G[a * D + b] += pa * gN[b];
+          for (int b = 0; b < D; ++b) G[a * D + b] += pa * (TB)gN[b];
         }
       }
-      double T[n];
+      TB T[n];
+      TB qp = TB(0);
 #pragma unroll
       for (int rr2 = 0; rr2 < n; ++rr2) {
-        double tv = 0.0;
+        TB tv = TB(0);
 #pragma unroll
         for (int cc = 0; cc < n; ++cc)
           tv += ((rr2 <= cc) ? At[sym_index<n>(rr2, cc)] : At[sym_index<n>(cc, rr2)]) * G[cc];
         T[rr2] = tv;
-        q += G[rr2] * tv;
+        qp += G[rr2] * tv;
       }
+      q += (double)qp;
 #pragma unroll
       for (int s = 0; s < stencil_count<D>(); ++s) {
         int k[3];
@@ -848,9 +887,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
         const int r = region_slot<D>(tg, l, k);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          double tv = 0.0;
+          TB tv = TB(0);
 #pragma unroll
-          for (int b = 0; b < D; ++b) tv += T[a * D + b] * gN[b];
+          for (int b = 0; b < D; ++b) tv += T[a * D + b] * (TB)gN[b];
           atomicAdd(&lh[a * nreg + r], tv);
         }
       }
@@ -861,8 +900,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
       if (i < 0) continue;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const double hv = lh[a * nreg + r];
-        if (hv != 0.0) atomicAdd(&Hp[i * D + a], hv);
+        const TB hv = lh[a * nreg + r];
+        if (hv != TB(0)) atomicAdd(&Hp[i * D + a], hv);
       }
     }
   }
@@ -874,17 +913,16 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
 // r -= alpha H p (H p = scatter + m/dt^2 p), z = r / D on free DOFs; the
 // scatter buffer is cleared for the next product; partial (r, z), (r, r).
 // Node data are loaded before the curvature partials are reduced.
-template <int D>
+template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm, double dt, const uint8_t *fr,
-                                                      const double *gdiag, const double *pA, const double *pB,
-                                                      double *Hp, double *r, double *z, double *del,
-                                                      const double *part_q, int n_q, double *part_rz,
-                                                      double *part_rr, CgState *S) {
+                                                      const TB *gdiag, const TB *pA, const TB *pB, TB *Hp, TB *r,
+                                                      TB *z, TB *del, const double *part_q, int n_q,
+                                                      double *part_rz, double *part_rr, CgState *S) {
   __shared__ double red[8];
   const int tid = threadIdx.x;
   if (S->done) return;
   const int it = S->kcur;
-  const double *pcur = (it & 1) ? pB : pA;
+  const TB *pcur = (it & 1) ? pB : pA;
   double pq = 0.0;
   for (int i = tid; i < n_q; i += kBlock) pq += part_q[i];
   const int k0 = blockIdx.x * kBlock + tid;
@@ -892,11 +930,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm
   bool f = false;
   if (k0 < ndof) {
     f = fr[k0];
-    hs = Hp[k0];
-    pv = pcur[k0];
-    rv = r[k0];
-    dv = del[k0];
-    dg = gdiag[k0];
+    hs = (double)Hp[k0];
+    pv = (double)pcur[k0];
+    rv = (double)r[k0];
+    dv = (double)del[k0];
+    dg = (double)gdiag[k0];
     m = gm[k0 / D];
   }
   pq = block_sum(pq, red);
@@ -908,31 +946,31 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm
   const double mdt = 1.0 / (dt * dt);
   double rz = 0.0, rr = 0.0;
   if (k0 < ndof) {
-    Hp[k0] = 0.0;
+    Hp[k0] = TB(0);
     if (f) {
       const double hv = hs + m * mdt * pv;
-      del[k0] = dv + alpha * pv;
-      const double rn = rv - alpha * hv;
+      del[k0] = (TB)(dv + alpha * pv);
+      const TB rn = (TB)(rv - alpha * hv);
       r[k0] = rn;
-      const double zv = rn / dg;
+      const TB zv = (TB)((double)rn / dg);
       z[k0] = zv;
-      rz += rn * zv;
-      rr += rn * rn;
+      rz += (double)rn * (double)zv;
+      rr += (double)rn * (double)rn;
     }
   }
   for (int k = k0 + gridDim.x * kBlock; k < ndof; k += gridDim.x * kBlock) {
-    const double h2 = Hp[k];
-    Hp[k] = 0.0;
+    const double h2 = (double)Hp[k];
+    Hp[k] = TB(0);
     if (!fr[k]) continue;
-    const double p2 = pcur[k];
+    const double p2 = (double)pcur[k];
     const double hv = h2 + gm[k / D] * mdt * p2;
-    del[k] += alpha * p2;
-    const double rn = r[k] - alpha * hv;
+    del[k] = (TB)((double)del[k] + alpha * p2);
+    const TB rn = (TB)((double)r[k] - alpha * hv);
     r[k] = rn;
-    const double zv = rn / gdiag[k];
+    const TB zv = (TB)((double)rn / (double)gdiag[k]);
     z[k] = zv;
-    rz += rn * zv;
-    rr += rn * rn;
+    rz += (double)rn * (double)zv;
+    rr += (double)rn * (double)rn;
   }
   block_sum2(rz, rr, red);
   if (tid == 0) {
@@ -949,10 +987,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm
 // Per-particle part of E(u + alpha del) - E(u) in cancellation-free form:
 // V [mu/2 (2 F:Dm + Dm:Dm) - mu L + lam/2 L (2 ln J + L)], L = log1p(dJ / J),
 // dJ = det(F + Dm) - det F expanded in powers of Dm; +inf on inversion.
-template <int D>
-__global__ void k_delta_energy_p(int np, GridDev g, const double *x, const double *F, const double *vol,
+template <int D, typename TB>
+__global__ void k_delta_energy_p(int np, GridDev g, const double *x, const TB *F, const double *vol,
                                  const int *mat, const double *mu_t, const double *lam_t, int64_t cap,
-                                 const double *u, const double *del, double alpha, double *part) {
+                                 const double *u, const TB *del, double alpha, double *part) {
   constexpr int n = D * D;
   __shared__ double red[kBlock / 64];
   double e = 0.0;
@@ -967,7 +1005,7 @@ __global__ void k_delta_energy_p(int np, GridDev g, const double *x, const doubl
     for (int k = 0; k < n; ++k) {
       Gu[k] = 0.0;
       Gd[k] = 0.0;
-      Fn[k] = F[k * cap + p];
+      Fn[k] = (double)F[k * cap + p];
     }
 #pragma unroll
     for (int s = 0; s < stencil_count<D>(); ++s) {
@@ -980,7 +1018,7 @@ __global__ void k_delta_energy_p(int np, GridDev g, const double *x, const doubl
       stencil_gradN<D>(st, k, gN);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const double ua = u[i * D + a], da = del[i * D + a];
+        const double ua = u[i * D + a], da = (double)del[i * D + a];
 #pragma unroll
         for (int b = 0; b < D; ++b) {
           Gu[a * D + b] += ua * gN[b];
@@ -1002,19 +1040,19 @@ __global__ void k_delta_energy_p(int np, GridDev g, const double *x, const doubl
         Fc[a * D + b] = tf;
         Dm[a * D + b] = alpha * td;
       }
-    const double J = det<D>(Fc);
+    const double J = det<D, double>(Fc);
     double CF[n];
-    cofactor<D>(Fc, CF);
+    cofactor<D, double>(Fc, CF);
     double dJ = 0.0;
 #pragma unroll
     for (int k = 0; k < n; ++k) dJ += CF[k] * Dm[k];
     if constexpr (D == 3) {
       double CD[n];
-      cofactor<D>(Dm, CD);
+      cofactor<D, double>(Dm, CD);
 #pragma unroll
       for (int k = 0; k < n; ++k) dJ += Fc[k] * CD[k];
     }
-    dJ += det<D>(Dm);
+    dJ += det<D, double>(Dm);
     if (!(J > 0.0) || !(J + dJ > 0.0)) {
       e = HUGE_VAL;
       continue;
@@ -1036,8 +1074,8 @@ __global__ void k_delta_energy_p(int np, GridDev g, const double *x, const doubl
 }
 
 // Node part: m/(2 dt^2) (2 alpha (u - dt v^n).del + alpha^2 |del|^2) - alpha m g.del.
-template <int D>
-__global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, const double *u, const double *del,
+template <int D, typename TB>
+__global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, const double *u, const TB *del,
                                  double dt, double alpha, double gx, double gy, double gz, double *part) {
   __shared__ double red[kBlock / 64];
   const double grav[3] = {gx, gy, gz};
@@ -1048,7 +1086,7 @@ __global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, 
     double rd = 0.0, dd = 0.0, gd = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const double dv = del[i * D + a];
+      const double dv = (double)del[i * D + a];
       rd += (u[i * D + a] - dt * gv[i * D + a]) * dv;
       dd += dv * dv;
       gd += grav[a] * dv;
@@ -1059,9 +1097,13 @@ __global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, 
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void k_axpy(int n, double alpha, const double *xv, double *y) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) y[k] += alpha * xv[k];
+template <typename TB>
+__global__ void k_axpy(int n, double alpha, const TB *xv, double *y) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    y[k] += alpha * (double)xv[k];
 }
+template __global__ void k_axpy<double>(int, double, const double *, double *);
+template __global__ void k_axpy<float>(int, double, const float *, double *);
 
 // ====================================================================== interface
 // Fixed-point node mass of the boundary-layer particles (Eq. boundary_grid_set).
@@ -1240,36 +1282,12 @@ __global__ void k_resid(int nn, const uint8_t *recv, const double *a, const doub
 }
 
 // ====================================================================== instantiations
-#define OSMPM_INST(D)                                                                                              \
+#define OSMPM_INST_D(D)                                                                                            \
   template __global__ void k_keys<D>(int, const double *, int64_t, GridDev, TileGeom, int *, int *, int *);        \
-  template __global__ void k_p2g<D>(TileGeom, GridDev, const int *, const double *, const double *,                \
-                                    const double *, const double *, const uint8_t *, int64_t, int, double,        \
-                                    double, int, double *, double *, long long *, long long *, int *);            \
   template __global__ void k_p2g_final<D>(GridDev, const double *, double *, const long long *, SceneBC,          \
                                           long long, int8_t *);                                                    \
-  template __global__ void k_g2p<D>(int, GridDev, const double *, const double *, double, double *, double *,     \
-                                    double *, double *, int64_t, int *);                                          \
   template __global__ void k_bc_init<D>(GridDev, const double *, const double *, const int8_t *, const uint8_t *, \
                                         const double *, int, SceneBC, double, uint8_t *, double *, double *);     \
-  template __global__ void k_grad_hess<D>(TileGeom, GridDev, const int *, const double *, const double *,          \
-                                          const double *, const int *, const double *, const double *, int64_t,   \
-                                          const double *, int, int, double *, double *, double *, int *);         \
-  template __global__ void k_grad_node<D>(GridDev, const double *, const double *, const double *,                \
-                                          const uint8_t *, double, double, double, double, double *, double *,    \
-                                          int, double *);                                                          \
-  template __global__ void k_cg_init<D>(int, const double *, const double *, const uint8_t *, double *, double *, \
-                                        double *, double *, double *, double *, double *, double *, CgState *);   \
-  template __global__ void k_cg_hvp<D>(TileGeom, GridDev, const int *, const double *, const double *, int64_t,   \
-                                       const double *, double, int, const double *, double *, double *, double *, \
-                                       const double *, const double *, int, double, int, double *, CgState *);      \
-  template __global__ void k_cg_update<D>(int, const double *, double, const uint8_t *, const double *,            \
-                                          const double *, const double *, double *, double *, double *, double *, \
-                                          const double *, int, double *, double *, CgState *);                    \
-  template __global__ void k_delta_energy_p<D>(int, GridDev, const double *, const double *, const double *,       \
-                                               const int *, const double *, const double *, int64_t,              \
-                                               const double *, const double *, double, double *);                 \
-  template __global__ void k_delta_energy_n<D>(GridDev, const double *, const double *, const double *,           \
-                                               const double *, double, double, double, double, double, double *); \
   template __global__ void k_qbnd<D>(int, GridDev, const double *, const double *, const uint8_t *, int64_t,       \
                                      double, long long *);                                                         \
   template __global__ void k_arbitrate<D>(GridDev, GridDev, const uint8_t *, const uint8_t *, const long long *,   \
@@ -1283,7 +1301,37 @@ __global__ void k_resid(int nn, const uint8_t *recv, const double *a, const doub
   template __global__ void k_vel_from_u<D>(int, const double *, const double *, double, double *);                 \
   template __global__ void k_resid<D>(int, const uint8_t *, const double *, const double *, double *);
 
-OSMPM_INST(2)
-OSMPM_INST(3)
+#define OSMPM_INST_DT(D, TB)                                                                                       \
+  template __global__ void k_p2g<D, TB>(TileGeom, GridDev, const int *, const double *, const TB *, const TB *,    \
+                                        const double *, const uint8_t *, int64_t, int, double, double, int,       \
+                                        double *, double *, long long *, long long *, int *);                     \
+  template __global__ void k_g2p<D, TB>(int, GridDev, const double *, const double *, double, double *, TB *,      \
+                                        TB *, TB *, int64_t, int *);                                               \
+  template __global__ void k_grad_hess<D, TB>(TileGeom, GridDev, const int *, const double *, const TB *,          \
+                                              const double *, const int *, const double *, const double *,        \
+                                              int64_t, const double *, int, int, double *, TB *, TB *, int *);    \
+  template __global__ void k_grad_node<D, TB>(GridDev, const double *, const double *, const double *,            \
+                                              const uint8_t *, double, double, double, double, double *, TB *,    \
+                                              int, double *);                                                      \
+  template __global__ void k_cg_init<D, TB>(int, const double *, const TB *, const uint8_t *, TB *, TB *, TB *,    \
+                                            TB *, TB *, TB *, double *, double *, CgState *);                     \
+  template __global__ void k_cg_hvp<D, TB>(TileGeom, GridDev, const int *, const double *, const TB *, int64_t,    \
+                                           const double *, double, int, const TB *, TB *, TB *, TB *,             \
+                                           const double *, const double *, int, double, int, double *, CgState *); \
+  template __global__ void k_cg_update<D, TB>(int, const double *, double, const uint8_t *, const TB *,           \
+                                              const TB *, const TB *, TB *, TB *, TB *, TB *, const double *,     \
+                                              int, double *, double *, CgState *);                                \
+  template __global__ void k_delta_energy_p<D, TB>(int, GridDev, const double *, const TB *, const double *,       \
+                                                   const int *, const double *, const double *, int64_t,          \
+                                                   const double *, const TB *, double, double *);                 \
+  template __global__ void k_delta_energy_n<D, TB>(GridDev, const double *, const double *, const double *,       \
+                                                   const TB *, double, double, double, double, double, double *);
+
+OSMPM_INST_D(2)
+OSMPM_INST_D(3)
+OSMPM_INST_DT(2, double)
+OSMPM_INST_DT(2, float)
+OSMPM_INST_DT(3, double)
+OSMPM_INST_DT(3, float)
 
 }  // namespace osmpm

@@ -18,12 +18,15 @@ struct CgState {
   int kcur;   // index of the running iteration (written by the product kernel)
 };
 
-__global__ void k_fill_d(int64_t n, double v, double *a);
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T *a);
 __global__ void k_fill_i64(int64_t n, long long *a);
 __global__ void k_fill_i32(int64_t n, int v, int *a);
 __global__ void k_fill_u8(int64_t n, uint8_t *a);
-__global__ void k_aos_to_soa(int64_t n, int c, const double *src, double *dst, int64_t cap);
-__global__ void k_soa_to_aos(int64_t n, int c, const double *src, int64_t cap, double *dst);
+template <typename T>
+__global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap);
+template <typename T>
+__global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst);
 __global__ void k_iota(int n, int *a);
 
 template <int D>
@@ -34,52 +37,50 @@ __global__ void k_cellsort(int nk, const int *cell_start, int *perm);
 template <typename T>
 __global__ void k_gather(int n, int rows, const int *perm, const T *src, T *dst, int64_t cap);
 
-template <int D>
-__global__ void k_p2g(TileGeom tg, GridDev g, const int *cell_start, const double *x, const double *v,
-                      const double *B, const double *mass, const uint8_t *flags, int64_t cap, int n_groups,
-                      double scale, double Dinv, int want_q, double *gm, double *gmv, long long *q_all,
-                      long long *qg, int *err);
+template <int D, typename TB>
+__global__ void k_p2g(TileGeom tg, GridDev g, const int *cell_start, const double *x, const TB *v, const TB *B,
+                      const double *mass, const uint8_t *flags, int64_t cap, int n_groups, double scale, double Dinv,
+                      int want_q, double *gm, double *gmv, long long *q_all, long long *qg, int *err);
 template <int D>
 __global__ void k_p2g_final(GridDev g, const double *gm, double *gv, const long long *qg, SceneBC bc,
                             long long tau_q, int8_t *bcg);
-template <int D>
-__global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, double dt, double *x, double *v,
-                      double *B, double *F, int64_t cap, int *err);
+template <int D, typename TB>
+__global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, double dt, double *x, TB *v, TB *B, TB *F,
+                      int64_t cap, int *err);
 
 template <int D>
 __global__ void k_bc_init(GridDev g, const double *gm, const double *gv, const int8_t *bcg, const uint8_t *recv,
                           const double *vbc, int use_schwarz, SceneBC bc, double dt, uint8_t *fr, double *u,
                           double *part_m);
-template <int D>
-__global__ void k_grad_hess(TileGeom tg, GridDev g, const int *cell_start, const double *x, const double *F,
+template <int D, typename TB>
+__global__ void k_grad_hess(TileGeom tg, GridDev g, const int *cell_start, const double *x, const TB *F,
                             const double *vol, const int *mat, const double *mu_t, const double *lam_t, int64_t cap,
-                            const double *u, int want_hess, int project, double *gg, double *gdiag, double *Atil,
-                            int *err);
-template <int D>
+                            const double *u, int want_hess, int project, double *gg, TB *gdiag, TB *Atil, int *err);
+template <int D, typename TB>
 __global__ void k_grad_node(GridDev g, const double *gm, const double *gv, const double *u, const uint8_t *fr,
-                            double dt, double gx, double gy, double gz, double *gg, double *gdiag, int want_hess,
+                            double dt, double gx, double gy, double gz, double *gg, TB *gdiag, int want_hess,
                             double *part);
-template <int D>
-__global__ void k_cg_init(int ndof, const double *gg, const double *gdiag, const uint8_t *fr, double *r, double *z,
-                          double *p0, double *p1, double *del, double *Hp, double *part_rz, double *part_rr,
-                          CgState *S);
-template <int D>
-__global__ void k_cg_hvp(TileGeom tg, GridDev g, const int *cell_start, const double *x, const double *Atil,
-                         int64_t cap, const double *gm, double dt, int ndof, const double *z, double *pA, double *pB,
-                         double *Hp, const double *part_rz, const double *part_rr, int n_part, double rtol,
-                         int max_cg, double *part_q, CgState *S);
-template <int D>
-__global__ void k_cg_update(int ndof, const double *gm, double dt, const uint8_t *fr, const double *gdiag,
-                            const double *pA, const double *pB, double *Hp, double *r, double *z, double *del,
-                            const double *part_q, int n_q, double *part_rz, double *part_rr, CgState *S);
-template <int D>
-__global__ void k_delta_energy_p(int np, GridDev g, const double *x, const double *F, const double *vol,
-                                 const int *mat, const double *mu_t, const double *lam_t, int64_t cap,
-                                 const double *u, const double *del, double alpha, double *part);
-template <int D>
-__global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, const double *u, const double *del,
+template <int D, typename TB>
+__global__ void k_cg_init(int ndof, const double *gg, const TB *gdiag, const uint8_t *fr, TB *r, TB *z, TB *p0,
+                          TB *p1, TB *del, TB *Hp, double *part_rz, double *part_rr, CgState *S);
+template <int D, typename TB>
+__global__ void k_cg_hvp(TileGeom tg, GridDev g, const int *cell_start, const double *x, const TB *Atil, int64_t cap,
+                         const double *gm, double dt, int ndof, const TB *z, TB *pA, TB *pB, TB *Hp,
+                         const double *part_rz, const double *part_rr, int n_part, double rtol, int max_cg,
+                         double *part_q, CgState *S);
+template <int D, typename TB>
+__global__ void k_cg_update(int ndof, const double *gm, double dt, const uint8_t *fr, const TB *gdiag, const TB *pA,
+                            const TB *pB, TB *Hp, TB *r, TB *z, TB *del, const double *part_q, int n_q,
+                            double *part_rz, double *part_rr, CgState *S);
+template <int D, typename TB>
+__global__ void k_delta_energy_p(int np, GridDev g, const double *x, const TB *F, const double *vol, const int *mat,
+                                 const double *mu_t, const double *lam_t, int64_t cap, const double *u, const TB *del,
+                                 double alpha, double *part);
+template <int D, typename TB>
+__global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, const double *u, const TB *del,
                                  double dt, double alpha, double gx, double gy, double gz, double *part);
-__global__ void k_axpy(int n, double alpha, const double *xv, double *y);
+template <typename TB>
+__global__ void k_axpy(int n, double alpha, const TB *xv, double *y);
 
 template <int D>
 __global__ void k_qbnd(int np, GridDev g, const double *x, const double *mass, const uint8_t *flags, int64_t cap,

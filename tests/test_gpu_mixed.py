@@ -1,0 +1,98 @@
+"""GPU parity of the mixed-precision path (FP32 particle state, tangents,
+P2G accumulation and CG; FP64 Newton residual, line-search energy, dot
+products, grid, Schwarz residuals and positions) against the FP64 oracle.
+
+Bar: 1e-5 relative (2-norm) on grid displacements and particle
+displacements; bit-exact binning (it depends only on FP64 positions)."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err, tiny_domain
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-5
+MIXED_CG_RTOL = 1e-5  # FP32 CG iterates cannot resolve a tighter relative residual
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09097_amd import binding
+
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _b():
+    from paper_2605_09097_amd import binding
+
+    return binding
+
+
+def test_mixed_sort_bit_exact(ctx):
+    b = _b()
+    spec = tiny_domain(dim=2, n_cells=24, n_particles=3000, seed=41, margin=1)
+    D = b.Domain(ctx, spec, precision=b.OSMPM_MIXED)
+    D.p2g()
+    perm, cs = D.sort_result()
+    ctx.sync()
+    operm, ocs = oracle.Domain(spec).sort((8, 8))
+    assert np.array_equal(perm.cpu().numpy(), operm)
+    assert np.array_equal(cs.cpu().numpy(), ocs)
+    D.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mixed_solve_and_g2p(ctx, dim):
+    b = _b()
+    spec = tiny_domain(dim=dim, n_cells=16 if dim == 2 else 8, n_particles=1500 if dim == 2 else 800,
+                       seed=42, F_spread=0.08, v_scale=0.3, bc_kind=[0], bc_mask=[3 if dim == 2 else 7])
+    spec.flags[:] = np.where(spec.x[:, 1] < spec.x[:, 1].min() + 1.5 * spec.dx, 2, 0)
+    dt = 2e-3
+    grav = (0.0, -9.8, 0.0)[:dim]
+    D = b.Domain(ctx, spec, precision=b.OSMPM_MIXED)
+    D.p2g()
+    st = D.implicit_solve(dt, b.solve_opts(gravity=grav, cg_rtol=MIXED_CG_RTOL))
+    m, vn, u = D.grid_state()
+    ctx.sync()
+    O = oracle.Domain(spec)
+    O.p2g()
+    O.solve(dt, oracle.solve_opts(gravity=grav))
+    assert st.converged
+    assert rel_err(u.cpu().numpy(), O.u) < MIXED_TOL
+    D.g2p(dt)
+    O.g2p(dt)
+    x, v, B, F = D.particles_input_order()
+    assert rel_err(x - spec.x, O.x - spec.x) < MIXED_TOL
+    assert rel_err(F - np.eye(dim), O.F - np.eye(dim)) < MIXED_TOL
+    D.close()
+
+
+def test_mixed_schwarz_frames_inclusion_tiny(ctx):
+    b = _b()
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("inclusion_tiny")
+    pair = b.SchwarzPair(ctx, sc, precision=b.OSMPM_MIXED)
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    fine = b.solve_opts(cg_rtol=MIXED_CG_RTOL)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=fine, fine=fine)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    for f in range(3):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        ost = oracle.schwarz_frame(OB, OS, sc.dT, oo)
+        gst = pair.frame(go)
+        assert abs(gst.iters - ost.iters) <= 1
+    for Dg, Do, spec in ((pair.B, OB, sc.B), (pair.S, OS, sc.S)):
+        m, vn, u = Dg.grid_state()
+        x, v, Bm, F = Dg.particles_input_order()
+        assert rel_err(u.cpu().numpy(), Do.u) < MIXED_TOL
+        assert rel_err(x - spec.x, Do.x - spec.x) < MIXED_TOL
+    pair.close()
