@@ -77,9 +77,11 @@ def counter_traffic():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--no-fp64-compare", action="store_true", help="skip the FP64 GPU path comparison")
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--profile-steps", type=int, default=0, help="frames of the instrumented pass (0: --steps)")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
@@ -96,15 +98,17 @@ def main():
 
     sc = scenes.workload(WORKLOAD)
     ctx = binding.Context(0)
-    pair = binding.SchwarzPair(ctx, sc)
-    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
-    stats = []
+    prec = binding.OSMPM_MIXED if args.precision == "mixed" else binding.OSMPM_FP64
+    solve = binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
+    opts64 = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
 
-    # parity sample: the first frames against the oracle (also the CPU baseline)
+    # parity sample: the first frames against the FP64 oracle (also the CPU baseline)
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
         value_cpu, nfr, tcpu, (OB, OS) = cpu_baseline(sc, args.cpu_frames)
+        pair = binding.SchwarzPair(ctx, sc, precision=prec)
         for _ in range(nfr):
             pair.frame(opts)
         errs = {}
@@ -118,19 +122,24 @@ def main():
         cpu = {"value": value_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                "sample": "frames 0-%d of the same workload, FP64 C oracle, one thread, %.1f s"
                          % (nfr - 1, tcpu)}
-        parity = {"frames": nfr, "max_rel_err_vs_oracle": max(errs.values()), **errs}
+        parity = {"frames": nfr, "vs": "FP64 CPU oracle", "path": args.precision,
+                  "max_rel_err": max(errs.values()), **errs}
         pair.close()
-        pair = binding.SchwarzPair(ctx, sc)
 
-    for _ in range(args.warmup):
-        pair.frame(opts)
-    torch.cuda.synchronize()
+    def timed(precision, o, steps, warmup):
+        pr = binding.SchwarzPair(ctx, sc, precision=precision)
+        for _ in range(warmup):
+            pr.frame(o)
+        torch.cuda.synchronize()
+        st = []
+        t = time.perf_counter()
+        for _ in range(steps):
+            st.append(pr.frame(o))
+        torch.cuda.synchronize()
+        return pr, st, time.perf_counter() - t
+
     # Timed region (no instrumentation).
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(pair.frame(opts))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    pair, stats, elapsed = timed(prec, opts, args.steps, args.warmup)
     # Kernel durations: the same number of frames again with every launch of
     # the instrumented kernels timestamped by its dispatch (HIP events on the
     # library's stream).  Timestamped dispatches serialise the queue, so this
@@ -151,6 +160,13 @@ def main():
                           "bytes_per_launch": by / n, "achieved_GBps": by / (ms * 1e-3) / 1e9,
                           "frac_hbm": by / (ms * 1e-3) / 8e12}
     ctx.profile(False)
+    pair.close()
+    fp64 = None
+    if prec == binding.OSMPM_MIXED and not args.no_fp64_compare:
+        p64, st64, el64 = timed(binding.OSMPM_FP64, opts64, args.steps, args.warmup)
+        p64.close()
+        fp64 = {"value": args.steps * _frame_particle_steps(sc) / el64, "ms_per_step": 1e3 * el64 / args.steps,
+                "schwarz_iters_mean": float(np.mean([s.iters for s in st64]))}
     if args.calibrate_copy:
         # a plain device copy of known size, for scaling HBM counters
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -173,11 +189,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if prec == binding.OSMPM_MIXED else "f64",
         "data": "synthetic",
         "config": {"workload": "2D inclusion, coarse dx 1/160, fine dx 1/400, 2x2 ppc, M=2, dT=1e-3, "
                                "frames %d-%d" % (args.warmup, args.warmup + args.steps - 1),
-                   "N_B": sc.B.n_particles, "N_S": sc.S.n_particles, "path": "fp64",
+                   "N_B": sc.B.n_particles, "N_S": sc.S.n_particles, "path": args.precision,
                    "schwarz_iters_mean": float(np.mean(iters)),
                    "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
                    "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats]))},
@@ -190,11 +206,12 @@ def main():
         "kernels": kern,
         "profiled_pass_ms_per_step": 1e3 * elapsed_prof / max(1, args.profile_steps if args.profile_steps > 0
                                                                else args.steps),
+        "fp64_gpu_path": fp64,
+        "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
         "cpu_baseline": cpu,
         "parity": parity,
     }
     print(json.dumps(out))
-    pair.close()
     ctx.close()
 
 

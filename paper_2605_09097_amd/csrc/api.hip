@@ -293,10 +293,10 @@ void zero_i32(osmpm_ctx *c, int *a, int64_t n) {
 int ndof(const osmpm_domain *d) { return d->g.nn * d->D; }
 
 size_t lds_p2g(const osmpm_domain *d) {
-  return d->tg.nreg * (sizeof(long long) * (1 + kMaxGroups) + d->tb * (1 + d->D));
+  return d->tg.nreg * (sizeof(long long) * (1 + kMaxGroups) + sizeof(double) * (1 + d->D));
 }
-size_t lds_grad(const osmpm_domain *d) { return d->tg.nreg * (sizeof(double) * 2 * d->D + d->tb * d->D); }
-size_t lds_hvp(const osmpm_domain *d) { return d->tb * d->tg.nreg * (size_t)(2 * d->D); }
+size_t lds_grad(const osmpm_domain *d) { return d->tg.nreg * sizeof(double) * 3 * d->D; }
+size_t lds_hvp(const osmpm_domain *d) { return d->tg.nreg * (sizeof(double) + d->tb) * d->D; }
 
 double fixed_scale(const osmpm_domain *d) { return 4294967296.0 / d->m_ref; }
 long long tau_fixed(const osmpm_domain *d) { return llrint(d->tau * fixed_scale(d)); }

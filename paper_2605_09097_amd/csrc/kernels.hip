@@ -217,8 +217,10 @@ __device__ inline int region_slot(const TileGeom &tg, const int *l, const int *k
 // ====================================================================== P2G
 // APIC P2G (Eq. p2g_transfer) of one tile into LDS, then global atomics.
 // Also the fixed-point node masses (all particles, and per scene group).
-// TB is the accumulation type of the tile (FP32 in the mixed path); the
-// tile sums are added to the FP64 grid.
+// TB is the storage type of the particle velocity and affine matrix (FP32 in
+// the mixed path).  Tile sums are accumulated in FP64 LDS (ds_add_f64, which
+// measures about twice as fast as ds_add_f32 on gfx950) and added to the FP64
+// grid.
 template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const int *cell_start, const double *x,
                                                 const TB *v, const TB *B, const double *mass,
@@ -231,10 +233,10 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
   if (!tile_range(tg, cell_start, t, p0, p1, org) || p0 == p1) return;
   const int nreg = tg.nreg;
   long long *lq = reinterpret_cast<long long *>(lds);
-  TB *lm = reinterpret_cast<TB *>(lq + (size_t)(1 + kMaxGroups) * nreg);
-  TB *lmv = lm + nreg;
+  double *lm = reinterpret_cast<double *>(lq + (size_t)(1 + kMaxGroups) * nreg);
+  double *lmv = lm + nreg;
   const int nq = want_q ? 1 + n_groups : 0;
-  for (int r = threadIdx.x; r < nreg * (1 + D); r += kBlock) lm[r] = TB(0);
+  for (int r = threadIdx.x; r < nreg * (1 + D); r += kBlock) lm[r] = 0.0;
   for (int r = threadIdx.x; r < nreg * nq; r += kBlock) lq[r] = 0;
   __syncthreads();
   for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
@@ -266,13 +268,13 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
       for (int a = 0; a < D; ++a) dxv[a] = ((double)k[a] - st.f[a]) * g.dx;
       const int r = region_slot<D>(tg, l, k);
       const double mN = mp * N;
-      atomicAdd(&lm[r], (TB)mN);
+      atomicAdd(&lm[r], (double)(TB)mN);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         double aff = 0.0;
 #pragma unroll
         for (int b = 0; b < D; ++b) aff += Bp[a * D + b] * dxv[b];
-        atomicAdd(&lmv[a * nreg + r], (TB)(mN * (vp[a] + Dinv * aff)));
+        atomicAdd(&lmv[a * nreg + r], (double)(TB)(mN * (vp[a] + Dinv * aff)));
       }
       if (want_q) {
         const long long q = fixed_mass(N, mq);
@@ -287,11 +289,11 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
   for (int r = threadIdx.x; r < nreg; r += kBlock) {
     const int i = region_node<D>(tg, g, org, r);
     if (i < 0) continue;
-    const double m = (double)lm[r];
+    const double m = lm[r];
     if (m != 0.0) {
       atomicAdd(&gm[i], m);
 #pragma unroll
-      for (int a = 0; a < D; ++a) atomicAdd(&gmv[i * D + a], (double)lmv[a * nreg + r]);
+      for (int a = 0; a < D; ++a) atomicAdd(&gmv[i * D + a], lmv[a * nreg + r]);
     }
     if (want_q) {
       if (lq[r] != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&q_all[i]), (unsigned long long)lq[r]);
@@ -477,14 +479,14 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
   const int nreg = tg.nreg;
   double *lu = lds;
   double *lg = lds + D * nreg;
-  TB *ld = reinterpret_cast<TB *>(lds + 2 * D * nreg);
+  double *ld = lds + 2 * D * nreg;
   for (int r = threadIdx.x; r < nreg; r += kBlock) {
     const int i = region_node<D>(tg, g, org, r);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       lu[a * nreg + r] = (i >= 0) ? u[i * D + a] : 0.0;
       lg[a * nreg + r] = 0.0;
-      ld[a * nreg + r] = TB(0);
+      ld[a * nreg + r] = 0.0;
     }
   }
   __syncthreads();
@@ -616,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
               const TB av = (r1 <= c1) ? At[sym_index<n>(r1, c1)] : At[sym_index<n>(c1, r1)];
               dv += av * gb[b] * gb[e];
             }
-          atomicAdd(&ld[a * nreg + r], dv);
+          atomicAdd(&ld[a * nreg + r], (double)dv);
         }
       }
     }
@@ -630,8 +632,8 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
       const double gv = lg[a * nreg + r];
       if (gv != 0.0) atomicAdd(&gg[i * D + a], gv);
       if (want_hess) {
-        const TB dv = ld[a * nreg + r];
-        if (dv != TB(0)) atomicAdd(&gdiag[i * D + a], dv);
+        const double dv = ld[a * nreg + r];
+        if (dv != 0.0) atomicAdd(&gdiag[i * D + a], (TB)dv);
       }
     }
   }
@@ -820,13 +822,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
     q += gm[k / D] * mdt * (double)pv * (double)pv;
   }
   if (tile_ok) {
-    TB *lp = reinterpret_cast<TB *>(lds);
-    TB *lh = lp + D * nreg;
+    double *lh = lds;
+    TB *lp = reinterpret_cast<TB *>(lds + D * nreg);
     if (tid < nreg) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         lp[a * nreg + tid] = (ri >= 0) ? cg_direction<TB>(rzv[a], beta, rpv[a]) : TB(0);
-        lh[a * nreg + tid] = TB(0);
+        lh[a * nreg + tid] = 0.0;
       }
     }
     for (int r = tid + kBlock; r < nreg; r += kBlock) {
@@ -834,7 +836,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         lp[a * nreg + r] = (i >= 0) ? cg_direction<TB>(z[i * D + a], beta, pprev[i * D + a]) : TB(0);
-        lh[a * nreg + r] = TB(0);
+        lh[a * nreg + r] = 0.0;
       }
     }
     __syncthreads();
@@ -890,7 +892,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
           TB tv = TB(0);
 #pragma unroll
           for (int b = 0; b < D; ++b) tv += T[a * D + b] * (TB)gN[b];
-          atomicAdd(&lh[a * nreg + r], tv);
+          atomicAdd(&lh[a * nreg + r], (double)tv);
         }
       }
     }
@@ -900,8 +902,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
       if (i < 0) continue;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const TB hv = lh[a * nreg + r];
-        if (hv != TB(0)) atomicAdd(&Hp[i * D + a], hv);
+        const double hv = lh[a * nreg + r];
+        if (hv != 0.0) atomicAdd(&Hp[i * D + a], (TB)hv);
       }
     }
   }
