@@ -73,6 +73,7 @@ typedef enum {
 
 typedef struct osmpm_ctx osmpm_ctx;
 typedef struct osmpm_domain osmpm_domain;
+typedef struct osmpm_batch osmpm_batch;
 
 /* Structured grid of one subdomain on an integer lattice of pitch h0:
  * node i sits at x_i = (origin_q + i * dx_q) * h0 (per axis), so nodes of
@@ -250,6 +251,37 @@ osmpm_status osmpm_schwarz_frame(osmpm_domain *B, osmpm_domain *S, double dT,
 /* One single-domain step: P2G, implicit solve, G2P.  Synchronises. */
 osmpm_status osmpm_single_frame(osmpm_domain *dom, double dt, const osmpm_solve_opts *opts,
                                 osmpm_solve_stats *stats_host);
+
+/* ---------------------------------------------------------------- batches */
+
+/* A batch runs many independent scenes in shared launches: every stage of
+ * the frame is one launch over all scenes (one launch dimension indexes the
+ * scene), domains of uneven size included.  Each scene keeps its own Newton,
+ * CG, line-search and Schwarz decisions, taken on the device, so its results
+ * are those of running it alone; a scene whose Schwarz loop has converged
+ * leaves the remaining iterations' launches.  All members share the batch's
+ * dT, M and solver options (Alg. 1 per scene).
+ *
+ * osmpm_batch_create: n scenes (1 <= n <= 1024); coarse[i] (host array of
+ * handles) and, for Schwarz batches, fine[i] form pair i; fine = NULL makes a
+ * batch of single domains.  Members must share the context, dimension and
+ * precision, and no domain may appear twice.  The batch references the
+ * domains (it does not own them): destroy it before them; a batch whose
+ * member was destroyed returns OSMPM_E_STATE.  Per-scene settings
+ * (materials, particles, selection, scene BC parameters) are changed on the
+ * domains between frames as usual. */
+osmpm_status osmpm_batch_create(osmpm_ctx *ctx, int32_t n, osmpm_domain *const *coarse_host,
+                                osmpm_domain *const *fine_host, osmpm_batch **out);
+/* One global frame of Alg. 1 for every pair of a Schwarz batch (the steps of
+ * osmpm_schwarz_frame); stats_host[n] receives each pair's statistics (may be
+ * NULL).  Synchronises. */
+osmpm_status osmpm_batch_schwarz_frame(osmpm_batch *batch, double dT, const osmpm_schwarz_opts *opts,
+                                       osmpm_schwarz_stats *stats_host);
+/* One single-domain step (P2G, implicit solve, G2P) for every member of a
+ * batch created with fine = NULL; stats_host[n] may be NULL.  Synchronises. */
+osmpm_status osmpm_batch_single_frame(osmpm_batch *batch, double dt, const osmpm_solve_opts *opts,
+                                      osmpm_solve_stats *stats_host);
+void osmpm_batch_destroy(osmpm_batch *batch);
 
 /* ---------------------------------------------------------------- readback */
 

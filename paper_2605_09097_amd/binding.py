@@ -31,6 +31,7 @@ ABI_SYMBOLS = [
     "osmpm_project_S_to_B", "osmpm_interp_B_to_S", "osmpm_temporal_interp", "osmpm_set_schwarz_bc",
     "osmpm_schwarz_frame", "osmpm_single_frame", "osmpm_get_particles", "osmpm_get_grid",
     "osmpm_get_sets", "osmpm_get_sort", "osmpm_domain_info",
+    "osmpm_batch_create", "osmpm_batch_schwarz_frame", "osmpm_batch_single_frame", "osmpm_batch_destroy",
 ]
 
 
@@ -100,6 +101,9 @@ def _declare(L):
         "osmpm_get_sets": [_vp, _vp, _vp, _vp],
         "osmpm_get_sort": [_vp, _vp, _vp],
         "osmpm_domain_info": [_vp, P(C.c_int64), P(C.c_int64), P(C.c_int64)],
+        "osmpm_batch_create": [_vp, C.c_int32, P(_vp), P(_vp), P(_vp)],
+        "osmpm_batch_schwarz_frame": [_vp, C.c_double, P(osmpm_schwarz_opts), P(osmpm_schwarz_stats)],
+        "osmpm_batch_single_frame": [_vp, C.c_double, P(osmpm_solve_opts), P(osmpm_solve_stats)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -111,6 +115,8 @@ def _declare(L):
     L.osmpm_ctx_destroy.restype = None
     L.osmpm_domain_destroy.argtypes = [_vp]
     L.osmpm_domain_destroy.restype = None
+    L.osmpm_batch_destroy.argtypes = [_vp]
+    L.osmpm_batch_destroy.restype = None
 
 
 def lib():
@@ -380,3 +386,62 @@ class SchwarzPair:
     def close(self):
         self.B.close()
         self.S.close()
+
+
+class Batch:
+    """osmpm_batch over coarse/fine pairs (or single domains when fine is None)."""
+
+    def __init__(self, ctx: Context, coarse, fine=None):
+        self.ctx = ctx
+        self.n = n = len(coarse)
+        if fine is not None and len(fine) != n:
+            raise ValueError("coarse and fine lists differ in length")
+        cb = (C.c_void_p * n)(*[d.handle.value for d in coarse])
+        fb = (C.c_void_p * n)(*[d.handle.value for d in fine]) if fine is not None else None
+        h = C.c_void_p()
+        ctx.check(lib().osmpm_batch_create(ctx.handle, n, cb, fb, C.byref(h)), "batch_create")
+        self.handle = h
+        self.coarse, self.fine = list(coarse), (list(fine) if fine is not None else None)
+
+    def schwarz_frame(self, dT, opts):
+        st = (osmpm_schwarz_stats * self.n)()
+        self.ctx.check(lib().osmpm_batch_schwarz_frame(self.handle, dT, C.byref(opts), st), "batch_schwarz_frame")
+        return list(st)
+
+    def single_frame(self, dt, opts):
+        st = (osmpm_solve_stats * self.n)()
+        self.ctx.check(lib().osmpm_batch_single_frame(self.handle, dt, C.byref(opts), st), "batch_single_frame")
+        return list(st)
+
+    def close(self):
+        if self.handle:
+            lib().osmpm_batch_destroy(self.handle)
+            self.handle = None
+
+
+class SchwarzBatch:
+    """Many scenes (scenes.Scene with equal dT and M) as one Schwarz batch."""
+
+    def __init__(self, ctx: Context, scenes_, precision=OSMPM_FP64):
+        self.scenes = list(scenes_)
+        if len({(s.dT, s.M) for s in self.scenes}) != 1:
+            raise ValueError("scenes of a batch share dT and M")
+        self.dT, self.M = self.scenes[0].dT, self.scenes[0].M
+        self.pairs = [SchwarzPair(ctx, s, precision) for s in self.scenes]
+        self.batch = Batch(ctx, [p.B for p in self.pairs], [p.S for p in self.pairs])
+        self.frame_index = 0
+
+    def frame(self, opts):
+        for p in self.pairs:
+            pB, pS = p.scene.bc_params(self.frame_index)
+            p.B.set_bc_params(pB)
+            p.S.set_bc_params(pS)
+            p.frame_index = self.frame_index + 1
+        st = self.batch.schwarz_frame(self.dT, opts)
+        self.frame_index += 1
+        return st
+
+    def close(self):
+        self.batch.close()
+        for p in self.pairs:
+            p.close()

@@ -1,11 +1,15 @@
-// Host side of the C ABI declared in include/osmpm.h: handle management,
-// the binning/P2G/G2P pipelines, the Newton-PCG-line-search driver of one
-// implicit solve and the multiplicative Schwarz frame of Alg. 1.
+// Host side of the C ABI declared in include/osmpm.h: handle management and
+// the sequencing of the binning / P2G / G2P pipelines, the implicit solve
+// and the multiplicative Schwarz frame of Alg. 1.
 //
-// The host only sequences kernels and reads back a handful of scalars:
-// the Newton gradient norm, the CG state once per chunk of iterations, the
-// line-search energy change and the Schwarz residuals.  All arithmetic on
-// particles and nodes runs in the kernels of kernels.hip.
+// All work runs on groups of domains: a group holds n domains on one side
+// (single-domain work) or n coarse/fine pairs on two sides (Schwarz work), and
+// every stage is one launch over the whole group (blockIdx.y = domain).  A
+// single domain is a group of one.  Newton, CG and line-search decisions are
+// taken on the device per domain, so the host queues a fixed cycle of
+// launches and reads one small status block per cycle: the solve states, the
+// CG states, the Schwarz residual sums and the device error word.  All
+// arithmetic on particles and nodes runs in the kernels of kernels.hip.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -22,96 +26,126 @@ using namespace osmpm;
 
 namespace {
 
-constexpr int kCgChunk = 8;
-
-// Particle arrays, component-major [rows][capacity].  Positions, masses and
-// volumes are FP64; velocities, affine matrices and deformation gradients
-// are stored in the domain's bulk type (FP64, or FP32 in the mixed path).
-struct PartBuf {
-  double *x = nullptr, *mass = nullptr, *vol = nullptr;
-  void *v = nullptr, *B = nullptr, *F = nullptr;
-  int *mat = nullptr, *id = nullptr;
-  uint8_t *flags = nullptr;
-};
-
-int blocks_for(int64_t n, int cap_blocks = 1024) {
+int blocks_for(int64_t n, int cap_blocks = 1 << 20) {
   int64_t b = (n + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
   if (b > cap_blocks) b = cap_blocks;
   return (int)b;
 }
 
-}  // namespace
+int particle_blocks_host(int64_t np) { return blocks_for(np, 1024); }
 
-// Kernel timing: HIP events recorded on the context stream around every
-// launch of the instrumented kernels while profiling is enabled.
+// Kernel timing: start/stop timestamps of the dispatch of every instrumented
+// launch while profiling is enabled.
 struct ProfPending {
   hipEvent_t a, b;
   int which;
   double bytes;
-  int cg_iter;  // iteration index of a CG launch, -1 otherwise
+  int cg_iter;  // index of a CG launch within its cycle, -1 otherwise
 };
 struct ProfSlot {
   int64_t launches = 0;
   double ms = 0.0, bytes = 0.0;
 };
 
+// Work buffer indices understood by the kernels (see wbuf).
+constexpr int kBufVn = 4, kBufVbc = 5;
+
+}  // namespace
+
 struct osmpm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  int *d_err = nullptr;
-  int *d_count = nullptr;  // small device counters (ambiguous nodes)
-  double *h_pin = nullptr;
-  size_t h_pin_doubles = 0;
+  char *h_pin = nullptr;  // pinned staging of status reads
+  size_t h_pin_bytes = 0;
   std::string last_error;
   bool prof = false;
   ProfSlot slots[OSMPM_K_COUNT];
   std::vector<hipEvent_t> ev_pool;
   std::vector<ProfPending> pending;
+  std::vector<osmpm_batch *> groups;  // every live group (error words)
+  uint64_t next_uid = 1;
 };
 
+// Particle arrays, component-major [rows][capacity].  Positions, masses and
+// volumes are FP64; velocities, affine matrices and deformation gradients
+// are stored in the domain's bulk type (FP64, or FP32 in the mixed path).
 struct osmpm_domain {
   osmpm_ctx *ctx = nullptr;
+  uint64_t uid = 0;
+  uint64_t version = 1;  // bumped when the device descriptor changes
   int D = 2;
   osmpm_grid desc{};
   GridDev g{};
   TileGeom tg{};
   int precision = 0;
+  size_t tb = sizeof(double);  // bytes of the bulk type
   int64_t cap = 0;
   int np = 0;
-  PartBuf pb[2], st;
-  int cur = 0;
-  // binning
+  PartPtrs pb[2]{}, st{};
+  int cur = 0;             // host mirror of *d_cur
+  int *d_cur = nullptr;    // current particle buffer (device)
   int nk = 0;
   int *key = nullptr, *count = nullptr, *cell_start = nullptr, *cursor = nullptr, *perm = nullptr;
-  // materials
   int n_mat = 0;
   double *mu = nullptr, *lam = nullptr;
-  // node selection
   double m_ref = 1.0, tau = 0.0;
   SceneBC bc{};
-  // grid
-  double *m = nullptr, *vn = nullptr, *u = nullptr, *vbc = nullptr;
+  double *m = nullptr, *vn = nullptr, *u = nullptr, *vbc = nullptr, *gg = nullptr;
   int8_t *bcg = nullptr;
   uint8_t *gamma = nullptr, *recv = nullptr, *fr = nullptr;
   long long *q_all = nullptr, *q_bnd = nullptr, *qg = nullptr;
-  // solver
-  double *gg = nullptr;  // Newton gradient (FP64)
-  // bulk-type arrays: Jacobi diagonal, CG vectors, per-particle tangents
   void *gd = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *del = nullptr, *Hp = nullptr,
        *Atil = nullptr;
-  size_t tb = sizeof(double);  // bytes of the bulk type
-  CgState *cg = nullptr;
-  double *part_a = nullptr, *part_b = nullptr, *part_q = nullptr, *part_rz = nullptr, *part_rr = nullptr;
-  int nb_node = 1, nb_part = 1;
-  int cg_hint = 8;  // CG iterations of the previous solve (first batch size)
-  // interface / Schwarz work buffers ([nn][D] unless noted)
-  double *pnum = nullptr, *pden = nullptr /*[nn]*/, *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
+  double *pnum = nullptr, *pden = nullptr, *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
+  int cg_hint = 8;  // iterations of the last CG solve (sizes the next batch of launches)
   bool have_p2g = false;
+  osmpm_batch *solo = nullptr;  // this domain as a group of one
+  osmpm_batch *pair = nullptr;  // this coarse domain paired with a fine one
+  uint64_t pair_uid = 0;
   std::vector<void *> allocs;
 };
 
-// ---------------------------------------------------------------- helpers
+// Launch extents of one side of a group: maxima over its domains.
+struct Ext {
+  int max_np = 0, max_nn = 0, max_ndof = 0, max_nk = 0;
+  int tile_blocks = 8, node_blocks = 1, part_blocks = 1, nn_blocks = 1;
+  size_t lds_p2g = 0, lds_grad = 0, lds_hvp = 0;
+};
+
+// Status block read back once per cycle (one copy).
+struct StatusHdr {
+  int err;
+  int pad[15];
+};
+
+struct osmpm_batch {
+  osmpm_ctx *c = nullptr;
+  int D = 2, precision = 0;
+  size_t tb = sizeof(double);
+  int n = 0, sides = 1;
+  bool dead = false;
+  std::vector<osmpm_domain *> dom[2];
+  std::vector<uint64_t> stamp_uid[2], stamp_ver[2];
+  std::vector<DomDesc> hdd[2];
+  DomDesc *dd[2] = {nullptr, nullptr};
+  int *active[2] = {nullptr, nullptr};
+  std::vector<int> act[2];  // host mirror of active (-1: unknown)
+  // status block: header, n_amb[n], n_recv[2][n], resid[2][n][2], SolveState[2][n], CgState[2][n]
+  char *status = nullptr;
+  size_t status_bytes = 0;
+  size_t off_amb = 0, off_recv = 0, off_res = 0, off_ss = 0, off_cg = 0;
+  int *err = nullptr, *n_amb = nullptr, *n_recv = nullptr;
+  double *res = nullptr;
+  SolveState *ss[2] = {nullptr, nullptr};
+  CgState *cg[2] = {nullptr, nullptr};
+  double *parts = nullptr;
+  int stride = 0;
+  Ext ext[2];
+  std::vector<double> bytes[2][OSMPM_K_COUNT];  // algorithmic bytes per domain and kernel
+  std::vector<void *> allocs;
+};
+
 namespace {
 
 osmpm_status fail(osmpm_ctx *c, osmpm_status s, const std::string &msg) {
@@ -125,41 +159,37 @@ osmpm_status fail(osmpm_ctx *c, osmpm_status s, const std::string &msg) {
     if (e_ != hipSuccess) return fail((ctx), OSMPM_E_DEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
-template <typename T>
-osmpm_status dalloc(osmpm_domain *d, T **p, size_t n) {
-  if (n == 0) n = 1;
-  void *q = nullptr;
-  if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) {
-    *p = nullptr;
-    return fail(d->ctx, OSMPM_E_NO_MEMORY, "hipMalloc failed");
-  }
-  d->allocs.push_back(q);
-  *p = static_cast<T *>(q);
-  return OSMPM_OK;
-}
-
-osmpm_status dalloc_bytes(osmpm_domain *d, void **p, size_t bytes) {
+osmpm_status dalloc_bytes(osmpm_ctx *c, std::vector<void *> &list, void **p, size_t bytes) {
   if (bytes == 0) bytes = 8;
   if (hipMalloc(p, bytes) != hipSuccess) {
     *p = nullptr;
-    return fail(d->ctx, OSMPM_E_NO_MEMORY, "hipMalloc failed");
+    return fail(c, OSMPM_E_NO_MEMORY, "hipMalloc failed");
   }
-  d->allocs.push_back(*p);
+  list.push_back(*p);
   return OSMPM_OK;
 }
 
-osmpm_status ensure_pin(osmpm_ctx *c, size_t doubles) {
-  if (c->h_pin_doubles >= doubles) return OSMPM_OK;
+template <typename T>
+osmpm_status dalloc(osmpm_domain *d, T **p, size_t n) {
+  void *q = nullptr;
+  osmpm_status s = dalloc_bytes(d->ctx, d->allocs, &q, n * sizeof(T));
+  *p = static_cast<T *>(q);
+  return s;
+}
+
+osmpm_status ensure_pin(osmpm_ctx *c, size_t bytes) {
+  if (c->h_pin_bytes >= bytes) return OSMPM_OK;
   if (c->h_pin) (void)hipHostFree(c->h_pin);
   c->h_pin = nullptr;
-  size_t n = std::max<size_t>(doubles, 4096);
-  if (hipHostMalloc((void **)&c->h_pin, n * sizeof(double), hipHostMallocDefault) != hipSuccess)
+  c->h_pin_bytes = 0;
+  const size_t nb = std::max<size_t>(bytes, 1 << 16);
+  if (hipHostMalloc((void **)&c->h_pin, nb, hipHostMallocDefault) != hipSuccess)
     return fail(c, OSMPM_E_NO_MEMORY, "hipHostMalloc failed");
-  c->h_pin_doubles = n;
+  c->h_pin_bytes = nb;
   return OSMPM_OK;
 }
 
-// ---------------------------------------------------------------- profiling
+// ---------------------------------------------------------------- launches and profiling
 hipEvent_t prof_event(osmpm_ctx *c) {
   if (c->ev_pool.empty()) {
     hipEvent_t e;
@@ -171,28 +201,28 @@ hipEvent_t prof_event(osmpm_ctx *c) {
   return e;
 }
 
-// Launch of an instrumented kernel.  With profiling on, the dispatch itself
-// carries the start and stop timestamps (hipExtLaunchKernelGGL), so no extra
-// packets are inserted between kernels.
+// Every launch goes through here.  With profiling on, an instrumented launch
+// (which >= 0) carries start and stop timestamps on its own dispatch, so no
+// extra packets sit between kernels.
 template <typename F, typename... Args>
-void launch(osmpm_ctx *c, int which, double bytes, int cg_iter, F kernel, dim3 grid, dim3 block, uint32_t shm,
+void launch(osmpm_ctx *c, int which, double bytes, int cg_iter, F kernel, dim3 grid, dim3 block, size_t shm,
             Args... args) {
   hipEvent_t a = nullptr, b = nullptr;
-  if (c->prof) {
+  if (c->prof && which >= 0) {
     a = prof_event(c);
     b = prof_event(c);
     if (!a || !b) a = b = nullptr;
   }
-  hipExtLaunchKernelGGL(kernel, grid, block, shm, c->stream, a, b, 0, args...);
+  hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)shm, c->stream, a, b, 0, args...);
   if (a) c->pending.push_back({a, b, which, bytes, cg_iter});
 }
 
-// Folds completed timings into the counters; call only after the stream has
-// been synchronised.  CG launches at or beyond `cg_done` iterations (those
-// that found the solve finished and exited) are dropped.
-void prof_harvest(osmpm_ctx *c, int cg_done = 1 << 30) {
+// Folds completed timings into the counters (only after a stream
+// synchronisation).  CG launches with a cycle index at or beyond `cg_useful`
+// found every domain finished and exited at once; they are dropped.
+void prof_harvest(osmpm_ctx *c, int cg_useful = 1 << 30) {
   for (const ProfPending &p : c->pending) {
-    if (p.cg_iter < 0 || p.cg_iter < cg_done) {
+    if (p.cg_iter < 0 || p.cg_iter < cg_useful) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         ProfSlot &sl = c->slots[p.which];
@@ -207,9 +237,9 @@ void prof_harvest(osmpm_ctx *c, int cg_done = 1 << 30) {
   c->pending.clear();
 }
 
-// Algorithmic bytes of one launch: the data the operation must move once
-// (particle arrays read or written, node arrays gathered, atomics counted as
-// read + write), independent of caching.
+// Algorithmic bytes of one domain in one launch: the data the operation must
+// move once (particle arrays read or written, node arrays gathered, atomics
+// counted as read + write), independent of caching.
 double alg_bytes(int which, int D, double np, double nn, double tb) {
   const double ns = (D * D) * (D * D + 1) / 2.0;
   switch (which) {
@@ -228,41 +258,6 @@ double alg_bytes(int which, int D, double np, double nn, double tb) {
   }
 }
 
-// Copies the device error word and up to three partial arrays to pinned host
-// memory, waits, and returns their host sums (fixed order).
-struct Fetch {
-  const double *p[3] = {nullptr, nullptr, nullptr};
-  int n[3] = {0, 0, 0};
-  double sum[3] = {0, 0, 0};
-};
-
-osmpm_status fetch(osmpm_ctx *c, Fetch &f, int *err_out) {
-  size_t total = 1;
-  for (int k = 0; k < 3; ++k) total += f.n[k];
-  osmpm_status s = ensure_pin(c, total);
-  if (s) return s;
-  size_t off = 1;
-  HIP_TRY(c, hipMemcpyAsync(c->h_pin, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  for (int k = 0; k < 3; ++k) {
-    if (f.n[k] > 0)
-      HIP_TRY(c, hipMemcpyAsync(c->h_pin + off, f.p[k], f.n[k] * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    off += f.n[k];
-  }
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  prof_harvest(c);
-  int err = 0;
-  std::memcpy(&err, c->h_pin, sizeof(int));
-  off = 1;
-  for (int k = 0; k < 3; ++k) {
-    double acc = 0.0;
-    for (int i = 0; i < f.n[k]; ++i) acc += c->h_pin[off + i];
-    f.sum[k] = acc;
-    off += f.n[k];
-  }
-  *err_out = err;
-  return OSMPM_OK;
-}
-
 osmpm_status device_error(osmpm_ctx *c, int err) {
   if (err & kErrOutOfGrid) return fail(c, OSMPM_E_OUT_OF_GRID, "a particle or node left its grid");
   if (err & kErrInverted) return fail(c, OSMPM_E_INVERTED, "det F <= 0 at an evaluated iterate");
@@ -276,376 +271,621 @@ osmpm_status check_launch(osmpm_ctx *c) {
   return OSMPM_OK;
 }
 
-void zero_d(osmpm_ctx *c, double *a, int64_t n) {
-  if (n > 0) k_fill<double><<<blocks_for(n), kBlock, 0, c->stream>>>(n, 0.0, a);
-}
-template <typename TB>
-void zero_tb(osmpm_ctx *c, void *a, int64_t n) {
-  if (n > 0) k_fill<TB><<<blocks_for(n), kBlock, 0, c->stream>>>(n, TB(0), static_cast<TB *>(a));
-}
-void zero_i64(osmpm_ctx *c, long long *a, int64_t n) {
-  if (n > 0) k_fill_i64<<<blocks_for(n), kBlock, 0, c->stream>>>(n, a);
-}
-void zero_i32(osmpm_ctx *c, int *a, int64_t n) {
-  if (n > 0) k_fill_i32<<<blocks_for(n), kBlock, 0, c->stream>>>(n, 0, a);
-}
-
-int ndof(const osmpm_domain *d) { return d->g.nn * d->D; }
-
-size_t lds_p2g(const osmpm_domain *d) {
-  return d->tg.nreg * (sizeof(long long) * (1 + kMaxGroups) + sizeof(double) * (1 + d->D));
-}
-size_t lds_grad(const osmpm_domain *d) { return d->tg.nreg * sizeof(double) * 3 * d->D; }
-size_t lds_hvp(const osmpm_domain *d) { return d->tg.nreg * (sizeof(double) + d->tb) * d->D; }
+size_t lds_p2g(int D, int nreg) { return (size_t)nreg * (sizeof(long long) * (1 + kMaxGroups) + sizeof(double) * (1 + D)); }
+size_t lds_grad(int D, int nreg) { return (size_t)nreg * sizeof(double) * 3 * D; }
+size_t lds_hvp(int D, int nreg, size_t tb) { return (size_t)nreg * (sizeof(double) + tb) * D; }
 
 double fixed_scale(const osmpm_domain *d) { return 4294967296.0 / d->m_ref; }
 long long tau_fixed(const osmpm_domain *d) { return llrint(d->tau * fixed_scale(d)); }
 
-// ---------------------------------------------------------------- sort + P2G
-template <int D, typename TB>
-osmpm_status sort_particles(osmpm_domain *d) {
-  osmpm_ctx *c = d->ctx;
-  const int n = d->np;
-  PartBuf &a = d->pb[d->cur], &b = d->pb[d->cur ^ 1];
-  zero_i32(c, d->count, d->nk);
-  if (n > 0) {
-    k_keys<D><<<blocks_for(n, 1 << 20), kBlock, 0, c->stream>>>(n, a.x, d->cap, d->g, d->tg, d->key, d->count, c->d_err);
+// ---------------------------------------------------------------- groups
+void group_free(osmpm_batch *G) {
+  if (!G) return;
+  osmpm_ctx *c = G->c;
+  if (c) {
+    (void)hipStreamSynchronize(c->stream);
+    auto it = std::find(c->groups.begin(), c->groups.end(), G);
+    if (it != c->groups.end()) c->groups.erase(it);
   }
-  k_scan<<<1, 1024, 0, c->stream>>>(d->nk, d->count, d->cell_start, d->cursor);
-  if (n == 0) return check_launch(c);
-  k_scatter<<<blocks_for(n, 1 << 20), kBlock, 0, c->stream>>>(n, d->key, d->cursor, d->perm);
-  k_cellsort<<<blocks_for(d->nk, 1 << 20), kBlock, 0, c->stream>>>(d->nk, d->cell_start, d->perm);
-  const int gb = blocks_for((int64_t)n * D * D, 2048);
-  k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, D, d->perm, a.x, b.x, d->cap);
-  k_gather<TB><<<gb, kBlock, 0, c->stream>>>(n, D, d->perm, (const TB *)a.v, (TB *)b.v, d->cap);
-  k_gather<TB><<<gb, kBlock, 0, c->stream>>>(n, D * D, d->perm, (const TB *)a.B, (TB *)b.B, d->cap);
-  k_gather<TB><<<gb, kBlock, 0, c->stream>>>(n, D * D, d->perm, (const TB *)a.F, (TB *)b.F, d->cap);
-  k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.mass, b.mass, d->cap);
-  k_gather<double><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.vol, b.vol, d->cap);
-  k_gather<int><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.mat, b.mat, d->cap);
-  k_gather<int><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.id, b.id, d->cap);
-  k_gather<uint8_t><<<gb, kBlock, 0, c->stream>>>(n, 1, d->perm, a.flags, b.flags, d->cap);
-  d->cur ^= 1;
-  return check_launch(c);
+  for (void *p : G->allocs) (void)hipFree(p);
+  delete G;
 }
 
-template <int D, typename TB>
-osmpm_status p2g_impl(osmpm_domain *d, bool want_qall) {
-  osmpm_ctx *c = d->ctx;
-  osmpm_status s = sort_particles<D, TB>(d);
+// Per-domain partial-sum stride: the most workgroups any reduction of the
+// domain uses.
+int partial_stride(const osmpm_domain *d) {
+  const int nd = d->g.nn * d->D;
+  return std::max({node_blocks(nd), particle_blocks_host(d->cap), d->tg.nblocks, 2 * node_blocks(d->g.nn)}) + 8;
+}
+
+osmpm_status group_create(osmpm_ctx *c, int n, osmpm_domain *const *side0, osmpm_domain *const *side1,
+                          osmpm_batch **out) {
+  *out = nullptr;
+  if (n < 1 || n > 1024 || !side0) return fail(c, OSMPM_E_INVALID_ARG, "group size must be 1..1024");
+  auto *G = new osmpm_batch();
+  G->c = c;
+  G->n = n;
+  G->sides = side1 ? 2 : 1;
+  G->D = side0[0] ? side0[0]->D : 2;
+  G->precision = side0[0] ? side0[0]->precision : 0;
+  for (int s = 0; s < G->sides; ++s) {
+    osmpm_domain *const *src = s ? side1 : side0;
+    for (int i = 0; i < n; ++i) {
+      osmpm_domain *d = src[i];
+      if (!d || d->ctx != c || d->D != G->D || d->precision != G->precision) {
+        delete G;
+        return fail(c, OSMPM_E_INVALID_ARG, "group members must share context, dimension and precision");
+      }
+      G->dom[s].push_back(d);
+      G->stride = std::max(G->stride, partial_stride(d));
+    }
+    G->stamp_uid[s].assign(n, 0);
+    G->stamp_ver[s].assign(n, 0);
+    G->hdd[s].resize(n);
+    G->act[s].assign(n, -1);
+  }
+  G->tb = G->dom[0][0]->tb;
+  // status block layout
+  size_t off = sizeof(StatusHdr);
+  auto align = [](size_t v) { return (v + 63) & ~size_t(63); };
+  G->off_amb = off;
+  off = align(off + sizeof(int) * n);
+  G->off_recv = off;
+  off = align(off + sizeof(int) * 2 * n);
+  G->off_res = off;
+  off = align(off + sizeof(double) * 4 * n);
+  G->off_ss = off;
+  off = align(off + sizeof(SolveState) * 2 * n);
+  G->off_cg = off;
+  off = align(off + sizeof(CgState) * 2 * n);
+  G->status_bytes = off;
+  osmpm_status s = OSMPM_OK;
+  void *p = nullptr;
+  if (!s) s = dalloc_bytes(c, G->allocs, &p, G->status_bytes);
+  if (!s) {
+    G->status = static_cast<char *>(p);
+    G->err = reinterpret_cast<int *>(G->status);
+    G->n_amb = reinterpret_cast<int *>(G->status + G->off_amb);
+    G->n_recv = reinterpret_cast<int *>(G->status + G->off_recv);
+    G->res = reinterpret_cast<double *>(G->status + G->off_res);
+    for (int sd = 0; sd < 2; ++sd) {
+      G->ss[sd] = reinterpret_cast<SolveState *>(G->status + G->off_ss) + sd * n;
+      G->cg[sd] = reinterpret_cast<CgState *>(G->status + G->off_cg) + sd * n;
+    }
+  }
+  for (int sd = 0; sd < G->sides && !s; ++sd) {
+    if (!s) s = dalloc_bytes(c, G->allocs, &p, sizeof(DomDesc) * n);
+    G->dd[sd] = static_cast<DomDesc *>(p);
+    if (!s) s = dalloc_bytes(c, G->allocs, &p, sizeof(int) * n);
+    G->active[sd] = static_cast<int *>(p);
+  }
+  if (!s) s = dalloc_bytes(c, G->allocs, &p, sizeof(double) * (size_t)G->stride * 5 * 2 * n);
+  G->parts = static_cast<double *>(p);
+  if (!s && hipMemsetAsync(G->status, 0, G->status_bytes, c->stream) != hipSuccess)
+    s = fail(c, OSMPM_E_DEVICE, "hipMemsetAsync failed");
+  if (!s && ensure_pin(c, G->status_bytes)) s = OSMPM_E_NO_MEMORY;
+  if (s) {
+    group_free(G);
+    return s;
+  }
+  c->groups.push_back(G);
+  *out = G;
+  return OSMPM_OK;
+}
+
+DomDesc make_desc(const osmpm_domain *d) {
+  DomDesc x{};
+  x.g = d->g;
+  x.tg = d->tg;
+  x.bc = d->bc;
+  x.np = d->np;
+  x.ndof = d->g.nn * d->D;
+  x.nk = d->nk;
+  x.cap = d->cap;
+  x.scale = fixed_scale(d);
+  x.tau_q = tau_fixed(d);
+  x.Dinv = 4.0 * d->g.inv_dx * d->g.inv_dx;
+  x.cur = d->d_cur;
+  x.pb[0] = d->pb[0];
+  x.pb[1] = d->pb[1];
+  x.st = d->st;
+  x.key = d->key;
+  x.count = d->count;
+  x.cell_start = d->cell_start;
+  x.cursor = d->cursor;
+  x.perm = d->perm;
+  x.mu = d->mu;
+  x.lam = d->lam;
+  x.m = d->m;
+  x.vn = d->vn;
+  x.u = d->u;
+  x.vbc = d->vbc;
+  x.gg = d->gg;
+  x.bcg = d->bcg;
+  x.gamma = d->gamma;
+  x.recv = d->recv;
+  x.fr = d->fr;
+  x.q_all = d->q_all;
+  x.q_bnd = d->q_bnd;
+  x.qg = d->qg;
+  x.gd = d->gd;
+  x.r = d->r;
+  x.z = d->z;
+  x.p0 = d->p0;
+  x.p1 = d->p1;
+  x.del = d->del;
+  x.Hp = d->Hp;
+  x.Atil = d->Atil;
+  x.pnum = d->pnum;
+  x.pden = d->pden;
+  x.w0 = d->w0;
+  x.w1 = d->w1;
+  x.w2 = d->w2;
+  x.w3 = d->w3;
+  return x;
+}
+
+// Uploads the descriptors of members whose configuration changed since the
+// last upload and recomputes the launch extents.
+osmpm_status group_sync(osmpm_batch *G) {
+  osmpm_ctx *c = G->c;
+  if (G->dead) return fail(c, OSMPM_E_STATE, "a domain of this batch was destroyed");
+  for (int s = 0; s < G->sides; ++s) {
+    bool changed = false;
+    for (int i = 0; i < G->n; ++i) {
+      osmpm_domain *d = G->dom[s][i];
+      if (G->stamp_uid[s][i] == d->uid && G->stamp_ver[s][i] == d->version) continue;
+      DomDesc x = make_desc(d);
+      x.active = G->active[s] + i;
+      x.ss = G->ss[s] + i;
+      x.cg = G->cg[s] + i;
+      double *base = G->parts + (size_t)((s * G->n + i) * 5) * G->stride;
+      x.part_a = base;
+      x.part_b = base + G->stride;
+      x.part_q = base + 2 * (size_t)G->stride;
+      x.part_rz = base + 3 * (size_t)G->stride;
+      x.part_rr = base + 4 * (size_t)G->stride;
+      G->hdd[s][i] = x;
+      G->stamp_uid[s][i] = d->uid;
+      G->stamp_ver[s][i] = d->version;
+      changed = true;
+    }
+    if (!changed) continue;
+    HIP_TRY(c, hipMemcpyAsync(G->dd[s], G->hdd[s].data(), sizeof(DomDesc) * G->n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    Ext E;
+    for (int w = 0; w < OSMPM_K_COUNT; ++w) G->bytes[s][w].assign(G->n, 0.0);
+    for (int i = 0; i < G->n; ++i) {
+      const osmpm_domain *d = G->dom[s][i];
+      const int nd = d->g.nn * d->D;
+      E.max_np = std::max(E.max_np, d->np);
+      E.max_nn = std::max(E.max_nn, d->g.nn);
+      E.max_ndof = std::max(E.max_ndof, nd);
+      E.max_nk = std::max(E.max_nk, d->nk);
+      E.tile_blocks = std::max(E.tile_blocks, d->tg.nblocks);
+      E.node_blocks = std::max(E.node_blocks, node_blocks(nd));
+      E.part_blocks = std::max(E.part_blocks, particle_blocks_host(d->np));
+      E.nn_blocks = std::max(E.nn_blocks, node_blocks(d->g.nn));
+      E.lds_p2g = std::max(E.lds_p2g, lds_p2g(d->D, d->tg.nreg));
+      E.lds_grad = std::max(E.lds_grad, lds_grad(d->D, d->tg.nreg));
+      E.lds_hvp = std::max(E.lds_hvp, lds_hvp(d->D, d->tg.nreg, d->tb));
+      for (int w = 0; w < OSMPM_K_COUNT; ++w)
+        G->bytes[s][w][i] = alg_bytes(w, d->D, d->np, d->g.nn, (double)d->tb);
+    }
+    G->ext[s] = E;
+  }
+  return OSMPM_OK;
+}
+
+// Sets the active flags of one side (a launch only when they change).
+void set_active(osmpm_batch *G, int s, const std::vector<int> &want) {
+  if (want == G->act[s]) return;
+  FlagMask m{};
+  for (int i = 0; i < G->n; ++i)
+    if (want[i]) m.w[i >> 6] |= (uint64_t)1 << (i & 63);
+  launch(G->c, -1, 0, -1, k_set_flags, dim3(blocks_for(G->n)), dim3(kBlock), 0, G->active[s], G->n, m);
+  G->act[s] = want;
+}
+
+void set_all_active(osmpm_batch *G) {
+  std::vector<int> one(G->n, 1);
+  for (int s = 0; s < G->sides; ++s) set_active(G, s, one);
+}
+
+double active_bytes(const osmpm_batch *G, int s, int which) {
+  double b = 0.0;
+  for (int i = 0; i < G->n; ++i)
+    if (G->act[s][i] == 1) b += G->bytes[s][which][i];
+  return b;
+}
+
+// Copies the status block to pinned memory and waits.  Returns the device
+// error (sticky: the word is never cleared).
+osmpm_status read_status(osmpm_batch *G) {
+  osmpm_ctx *c = G->c;
+  osmpm_status s = check_launch(c);
   if (s) return s;
-  const int nn = d->g.nn;
-  zero_d(c, d->m, nn);
-  zero_d(c, d->vn, (int64_t)nn * D);
-  const int want_q = (want_qall || d->bc.n_groups > 0) ? 1 : 0;
-  if (want_q) {
-    zero_i64(c, d->q_all, nn);
-    zero_i64(c, d->qg, (int64_t)nn * std::max(d->bc.n_groups, 1));
-  }
-  const PartBuf &a = d->pb[d->cur];
-  if (d->np > 0) {
-    const double Dinv = 4.0 * d->g.inv_dx * d->g.inv_dx;
-    launch(c, OSMPM_K_P2G, alg_bytes(OSMPM_K_P2G, D, d->np, nn, d->tb), -1, k_p2g<D, TB>, dim3(d->tg.nblocks),
-           dim3(kBlock), (uint32_t)lds_p2g(d), d->tg, d->g, (const int *)d->cell_start, (const double *)a.x,
-           (const TB *)a.v, (const TB *)a.B, (const double *)a.mass, (const uint8_t *)a.flags, d->cap, d->bc.n_groups,
-           fixed_scale(d), Dinv, want_q, d->m, d->vn, d->q_all, d->qg, c->d_err);
-  }
-  k_p2g_final<D><<<blocks_for(nn, 1 << 20), kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->qg, d->bc, tau_fixed(d),
-                                                                     d->bcg);
-  d->have_p2g = true;
-  return check_launch(c);
+  if ((s = ensure_pin(c, G->status_bytes))) return s;
+  HIP_TRY(c, hipMemcpyAsync(c->h_pin, G->status, G->status_bytes, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int err = 0;
+  std::memcpy(&err, c->h_pin, sizeof(int));
+  return device_error(c, err);
+}
+const SolveState *h_ss(const osmpm_batch *G, int s) {
+  return reinterpret_cast<const SolveState *>(G->c->h_pin + G->off_ss) + s * G->n;
+}
+const CgState *h_cg(const osmpm_batch *G, int s) {
+  return reinterpret_cast<const CgState *>(G->c->h_pin + G->off_cg) + s * G->n;
+}
+const int *h_int(const osmpm_batch *G, size_t off) { return reinterpret_cast<const int *>(G->c->h_pin + off); }
+const double *h_res(const osmpm_batch *G) { return reinterpret_cast<const double *>(G->c->h_pin + G->off_res); }
+
+// ---------------------------------------------------------------- sort + P2G + G2P
+// Stable counting sort of every active domain's particles by tile-major bin
+// key, gathered into the other particle buffer; P2G targets are cleared.
+template <int D, typename TB>
+void sort_side(osmpm_batch *G, int s, int want_q) {
+  osmpm_ctx *c = G->c;
+  const Ext &E = G->ext[s];
+  const DomDesc *dd = G->dd[s];
+  const int n = G->n;
+  const int pb = blocks_for(E.max_np);
+  launch(c, -1, 0, -1, k_zero_grid, dim3(blocks_for(std::max(E.max_nk, E.max_ndof), 1024), n), dim3(kBlock), 0, dd,
+         want_q);
+  launch(c, -1, 0, -1, k_keys<D>, dim3(pb, n), dim3(kBlock), 0, dd, G->err);
+  launch(c, -1, 0, -1, k_scan, dim3(1, n), dim3(1024), 0, dd);
+  launch(c, -1, 0, -1, k_scatter, dim3(pb, n), dim3(kBlock), 0, dd);
+  launch(c, -1, 0, -1, k_cellsort, dim3(blocks_for(E.max_nk), n), dim3(kBlock), 0, dd);
+  launch(c, -1, 0, -1, k_gather_all<D, TB>, dim3(pb, n), dim3(kBlock), 0, dd);
+  launch(c, -1, 0, -1, k_flip, dim3(blocks_for(n)), dim3(kBlock), 0, dd, n);
+  for (int i = 0; i < n; ++i)
+    if (G->act[s][i] == 1) G->dom[s][i]->cur ^= 1;
 }
 
 template <int D, typename TB>
-osmpm_status g2p_impl(osmpm_domain *d, double dt) {
-  osmpm_ctx *c = d->ctx;
-  if (!d->have_p2g) return fail(c, OSMPM_E_STATE, "g2p before p2g");
-  if (d->np == 0) return OSMPM_OK;
-  PartBuf &a = d->pb[d->cur];
-  launch(c, OSMPM_K_G2P, alg_bytes(OSMPM_K_G2P, D, d->np, d->g.nn, d->tb), -1, k_g2p<D, TB>,
-         dim3(blocks_for(d->np, 1 << 20)), dim3(kBlock), 0, d->np, d->g, (const double *)d->m, (const double *)d->u, dt,
-         a.x, (TB *)a.v, (TB *)a.B, (TB *)a.F, d->cap, c->d_err);
-  return check_launch(c);
+void p2g_side(osmpm_batch *G, int s, bool want_qall) {
+  osmpm_ctx *c = G->c;
+  int want_q = want_qall ? 1 : 0;
+  for (int i = 0; i < G->n; ++i)
+    if (G->act[s][i] == 1 && G->dom[s][i]->bc.n_groups > 0) want_q = 1;
+  sort_side<D, TB>(G, s, want_q);
+  const Ext &E = G->ext[s];
+  launch(c, OSMPM_K_P2G, active_bytes(G, s, OSMPM_K_P2G), -1, k_p2g<D, TB>, dim3(E.tile_blocks, G->n), dim3(kBlock),
+         E.lds_p2g, (const DomDesc *)G->dd[s], want_q, G->err);
+  launch(c, -1, 0, -1, k_p2g_final<D>, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
+  for (int i = 0; i < G->n; ++i)
+    if (G->act[s][i] == 1) G->dom[s][i]->have_p2g = true;
+}
+
+template <int D, typename TB>
+void g2p_side(osmpm_batch *G, int s, double dt) {
+  const Ext &E = G->ext[s];
+  launch(G->c, OSMPM_K_G2P, active_bytes(G, s, OSMPM_K_G2P), -1, k_g2p<D, TB>, dim3(blocks_for(E.max_np), G->n),
+         dim3(kBlock), 0, (const DomDesc *)G->dd[s], dt, G->err);
+}
+
+template <int D, typename TB>
+void copy_state_side(osmpm_batch *G, int s, int to_store) {
+  const Ext &E = G->ext[s];
+  launch(G->c, -1, 0, -1, k_copy_state<D, TB>, dim3(blocks_for(E.max_np), G->n), dim3(kBlock), 0,
+         (const DomDesc *)G->dd[s], to_store);
 }
 
 // ---------------------------------------------------------------- implicit solve
+// Newton-PCG-line-search on every active domain of side s.  The host queues
+// cycles of [CG launches | line-search start | line-search round | step |
+// gradient, Newton test, CG start] and reads the states after each cycle;
+// each domain advances through its own phases on the device and skips the
+// launches of phases it is not in.  The number of CG launch pairs of a cycle
+// is sized from each domain's previous CG count.
 template <int D, typename TB>
-osmpm_status solve_impl(osmpm_domain *d, double dt, int use_schwarz, const osmpm_solve_opts *o,
-                        osmpm_solve_stats *st) {
-  osmpm_ctx *c = d->ctx;
-  if (!d->have_p2g) return fail(c, OSMPM_E_STATE, "solve before p2g");
-  if (!(dt > 0.0)) return fail(c, OSMPM_E_INVALID_ARG, "dt must be positive");
-  osmpm_solve_stats S{};
-  const int nn = d->g.nn, nd = ndof(d);
-  const PartBuf &a = d->pb[d->cur];
-  k_bc_init<D><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->bcg, d->recv, d->vbc, use_schwarz, d->bc,
-                                                     dt, d->fr, d->u, d->part_a);
-  int err = 0;
-  Fetch fm;
-  fm.p[0] = d->part_a;
-  fm.n[0] = d->nb_node;
-  osmpm_status s = fetch(c, fm, &err);
-  if (s) return s;
-  const double gscale = fm.sum[0] * d->g.dx / (dt * dt);
-  const size_t lg = lds_grad(d), lh = lds_hvp(d);
-  for (int it = 0;; ++it) {
-    zero_d(c, d->gg, nd);
-    zero_tb<TB>(c, d->gd, nd);
-    if (d->np > 0)
-      launch(c, OSMPM_K_GRAD_HESS, alg_bytes(OSMPM_K_GRAD_HESS, D, d->np, nn, d->tb), -1, k_grad_hess<D, TB>,
-             dim3(d->tg.nblocks), dim3(kBlock), (uint32_t)lg, d->tg, d->g, (const int *)d->cell_start,
-             (const double *)a.x, (const TB *)a.F, (const double *)a.vol, (const int *)a.mat,
-             (const double *)d->mu, (const double *)d->lam, d->cap, (const double *)d->u, 1, o->project_psd, d->gg,
-             (TB *)d->gd, (TB *)d->Atil, c->d_err);
-    k_grad_node<D, TB><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->u, d->fr, dt, o->gravity[0],
-                                                             o->gravity[1], o->gravity[2], d->gg, (TB *)d->gd, 1,
-                                                             d->part_a);
-    Fetch fg;
-    fg.p[0] = d->part_a;
-    fg.n[0] = d->nb_node;
-    if ((s = fetch(c, fg, &err))) return s;
-    if ((s = device_error(c, err))) return s;
-    const double gn = std::sqrt(fg.sum[0]);
-    if (it == 0) S.gnorm0 = gn;
-    S.gnorm = gn;
-    const double tol = std::max(o->newton_rtol * S.gnorm0, o->newton_atol * gscale);
-    if (gn <= tol) {
-      S.converged = 1;
-      break;
+osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int vbc_buf, const osmpm_solve_opts *o,
+                        std::vector<osmpm_solve_stats> *out) {
+  osmpm_ctx *c = G->c;
+  const Ext &E = G->ext[s];
+  const DomDesc *dd = G->dd[s];
+  const int n = G->n;
+  const dim3 blk(kBlock);
+  launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, vbc_buf);
+  launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt);
+  const double bg = active_bytes(G, s, OSMPM_K_GRAD_HESS);
+  auto grad_phase = [&]() {
+    launch(c, OSMPM_K_GRAD_HESS, bg, -1, k_grad_hess<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_grad, dd,
+           (int)o->project_psd, G->err);
+    launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
+           o->gravity[2]);
+    launch(c, -1, 0, -1, k_newton_check, dim3(1, n), blk, 0, dd, o->newton_rtol, o->newton_atol, (int)o->max_newton);
+    launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd);
+  };
+  grad_phase();
+  const double bp = active_bytes(G, s, OSMPM_K_CG_PRODUCT), bu = active_bytes(G, s, OSMPM_K_CG_UPDATE);
+  std::vector<int> hint(n), prev_phase(n, kPhaseCgInit), prev_iter(n, 0), prev_total(n, 0);
+  for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
+  const long max_cycles = (long)(o->max_newton + 1) * ((o->max_cg + 4) / 4 + o->max_ls + 3) + 8;
+  osmpm_status st;
+  for (long cyc = 0;; ++cyc) {
+    if (cyc > max_cycles) return fail(c, OSMPM_E_STATE, "implicit solve did not terminate");
+    int b = 4;
+    for (int i = 0; i < n; ++i) {
+      if (G->act[s][i] != 1) continue;
+      if (prev_phase[i] == kPhaseCgInit) b = std::max(b, hint[i] + 1);
+      if (prev_phase[i] == kPhaseCg) b = std::max(b, hint[i] - prev_iter[i] + 1);
     }
-    if (it == o->max_newton) break;
-    // PCG on H del = -g
-    k_cg_init<D, TB><<<d->nb_node, kBlock, 0, c->stream>>>(nd, d->gg, (const TB *)d->gd, d->fr, (TB *)d->r,
-                                                           (TB *)d->z, (TB *)d->p0, (TB *)d->p1, (TB *)d->del,
-                                                           (TB *)d->Hp, d->part_rz, d->part_rr, d->cg);
-    // Batches of iterations between host checks: the first batch is sized
-    // from the previous solve's count so the loop usually ends after one or
-    // two checks; iterations launched after convergence exit at once.
-    int launched = 0;
-    int batch = std::max(4, std::min(d->cg_hint, o->max_cg));
-    for (;;) {
-      const int nb = std::min(batch, o->max_cg + 1 - launched);
-      for (int j = 0; j < nb; ++j) {
-        launch(c, OSMPM_K_CG_PRODUCT, alg_bytes(OSMPM_K_CG_PRODUCT, D, d->np, nn, d->tb), launched + j,
-               k_cg_hvp<D, TB>, dim3(d->tg.nblocks), dim3(kBlock), (uint32_t)lh, d->tg, d->g,
-               (const int *)d->cell_start, (const double *)a.x, (const TB *)d->Atil, d->cap, (const double *)d->m, dt,
-               nd, (const TB *)d->z, (TB *)d->p0, (TB *)d->p1, (TB *)d->Hp, (const double *)d->part_rz,
-               (const double *)d->part_rr, d->nb_node, o->cg_rtol, o->max_cg, d->part_q, d->cg);
-        launch(c, OSMPM_K_CG_UPDATE, alg_bytes(OSMPM_K_CG_UPDATE, D, d->np, nn, d->tb), launched + j,
-               k_cg_update<D, TB>, dim3(d->nb_node), dim3(kBlock), 0, nd, (const double *)d->m, dt,
-               (const uint8_t *)d->fr, (const TB *)d->gd, (const TB *)d->p0, (const TB *)d->p1, (TB *)d->Hp,
-               (TB *)d->r, (TB *)d->z, (TB *)d->del, (const double *)d->part_q, d->tg.nblocks, d->part_rz,
-               d->part_rr, d->cg);
+    b = std::min(b, o->max_cg + 1);
+    for (int j = 0; j < b; ++j) {
+      launch(c, OSMPM_K_CG_PRODUCT, bp, j, k_cg_hvp<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, dt,
+             o->cg_rtol, (int)o->max_cg);
+      launch(c, OSMPM_K_CG_UPDATE, bu, j, k_cg_update<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt);
+    }
+    launch(c, -1, 0, -1, k_ls_begin, dim3(blocks_for(n)), blk, 0, dd, n);
+    launch(c, -1, 0, -1, k_delta_energy_p<D, TB>, dim3(E.part_blocks, n), blk, 0, dd);
+    launch(c, -1, 0, -1, k_delta_energy_n<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0],
+           o->gravity[1], o->gravity[2]);
+    launch(c, -1, 0, -1, k_ls_check, dim3(1, n), blk, 0, dd, (int)o->max_ls);
+    launch(c, -1, 0, -1, k_newton_step<TB>, dim3(E.node_blocks, n), blk, 0, dd);
+    grad_phase();
+    if ((st = read_status(G))) return st;
+    const SolveState *hs = h_ss(G, s);
+    const CgState *hc = h_cg(G, s);
+    int useful = 0;
+    bool all_done = true;
+    for (int i = 0; i < n; ++i) {
+      if (G->act[s][i] != 1) continue;
+      const bool was_cg = prev_phase[i] == kPhaseCgInit || prev_phase[i] == kPhaseCg;
+      const int start = prev_phase[i] == kPhaseCg ? prev_iter[i] : 0;
+      int did = 0;
+      if (was_cg && hs[i].phase != kPhaseCg) {  // a CG finished in this cycle
+        const int cnt = hs[i].cg_iters - prev_total[i];
+        hint[i] = cnt;
+        did = cnt - start + 1;
+      } else if (was_cg) {
+        did = hc[i].iter - start;
       }
-      launched += nb;
-      if ((s = check_launch(c))) return s;
-      HIP_TRY(c, hipMemcpyAsync(c->h_pin, d->cg, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      CgState hs;
-      std::memcpy(&hs, c->h_pin, sizeof(CgState));
-      prof_harvest(c, hs.iter);
-      if (hs.done || launched > o->max_cg) {
-        S.cg_iters += hs.iter;
-        d->cg_hint = hs.iter + 1;
-        break;
-      }
-      batch = 4;
+      useful = std::max(useful, did);
+      prev_phase[i] = hs[i].phase;
+      prev_iter[i] = hc[i].iter;
+      prev_total[i] = hs[i].cg_iters;
+      if (hs[i].phase != kPhaseDone) all_done = false;
     }
-    // halving line search on the exact energy difference
-    double alpha = 1.0;
-    bool accepted = false;
-    for (int ls = 0; ls <= o->max_ls; ++ls) {
-      if (d->np > 0)
-        k_delta_energy_p<D, TB><<<d->nb_part, kBlock, 0, c->stream>>>(d->np, d->g, a.x, (const TB *)a.F, a.vol,
-                                                                      a.mat, d->mu, d->lam, d->cap, d->u,
-                                                                      (const TB *)d->del, alpha, d->part_b);
-      k_delta_energy_n<D, TB><<<d->nb_node, kBlock, 0, c->stream>>>(d->g, d->m, d->vn, d->u, (const TB *)d->del, dt,
-                                                                    alpha,
-                                                                o->gravity[0], o->gravity[1], o->gravity[2],
-                                                                d->part_a);
-      Fetch fe;
-      fe.p[0] = d->part_a;
-      fe.n[0] = d->nb_node;
-      fe.p[1] = d->part_b;
-      fe.n[1] = d->np > 0 ? d->nb_part : 0;
-      if ((s = fetch(c, fe, &err))) return s;
-      const double dE = fe.sum[0] + fe.sum[1];
-      if (dE < 0.0) {
-        accepted = true;
-        break;
-      }
-      if (ls == o->max_ls) break;
-      alpha *= 0.5;
-      S.ls_halvings += 1;
-    }
-    if (!accepted) {
-      S.ls_failed = 1;
-      break;
-    }
-    k_axpy<TB><<<blocks_for(nd), kBlock, 0, c->stream>>>(nd, alpha, (const TB *)d->del, d->u);
-    S.newton_iters += 1;
+    prof_harvest(c, useful);
+    if (all_done) break;
   }
-  if ((s = check_launch(c))) return s;
-  if (st) *st = S;
-  return OSMPM_OK;
-}
-
-// ---------------------------------------------------------------- interface
-template <int D>
-osmpm_status boundary_set(osmpm_domain *d) {
-  osmpm_ctx *c = d->ctx;
-  zero_i64(c, d->q_bnd, d->g.nn);
-  const PartBuf &a = d->pb[d->cur];
-  if (d->np > 0)
-    k_qbnd<D><<<blocks_for(d->np, 1 << 20), kBlock, 0, c->stream>>>(d->np, d->g, a.x, a.mass, a.flags, d->cap,
-                                                                     fixed_scale(d), d->q_bnd);
-  k_gamma<<<blocks_for(d->g.nn, 1 << 20), kBlock, 0, c->stream>>>(d->g.nn, d->q_bnd, d->m, tau_fixed(d), d->gamma,
-                                                                   d->recv);
-  return check_launch(c);
-}
-
-template <int D>
-osmpm_status interface_impl(osmpm_domain *B, osmpm_domain *S) {
-  osmpm_ctx *c = B->ctx;
-  osmpm_status s;
-  if ((s = boundary_set<D>(B)) || (s = boundary_set<D>(S))) return s;
-  zero_i32(c, c->d_count, 1);
-  k_arbitrate<D><<<blocks_for(B->g.nn, 1 << 20), kBlock, 0, c->stream>>>(B->g, S->g, B->gamma, S->gamma, B->q_all,
-                                                                          S->q_all, B->recv, S->recv, c->d_count);
-  return check_launch(c);
-}
-
-template <int D>
-osmpm_status project_impl(osmpm_domain *S, osmpm_domain *B, double eps_tol, const double *vS, double *out) {
-  osmpm_ctx *c = B->ctx;
-  zero_d(c, B->pnum, (int64_t)B->g.nn * D);
-  zero_d(c, B->pden, B->g.nn);
-  k_project_scatter<D><<<blocks_for(S->g.nn, 1 << 20), kBlock, 0, c->stream>>>(S->g, B->g, S->m, vS ? vS : S->vn,
-                                                                                 B->pnum, B->pden, c->d_err);
-  k_project_final<D><<<blocks_for(B->g.nn, 1 << 20), kBlock, 0, c->stream>>>(B->g.nn, B->recv, B->pnum, B->pden,
-                                                                              eps_tol, out);
-  return check_launch(c);
-}
-
-template <int D>
-osmpm_status interp_impl(osmpm_domain *B, const double *vB, osmpm_domain *S, double *out) {
-  osmpm_ctx *c = B->ctx;
-  k_interp<D><<<blocks_for(S->g.nn, 1 << 20), kBlock, 0, c->stream>>>(B->g, S->g, B->m, vB ? vB : B->vn, S->recv,
-                                                                       out, c->d_err);
-  return check_launch(c);
-}
-
-osmpm_status copy_state(osmpm_domain *d, const PartBuf &from, PartBuf &to) {
-  osmpm_ctx *c = d->ctx;
-  const int D = d->D;
-  const size_t cap = (size_t)d->cap;
-  HIP_TRY(c, hipMemcpyAsync(to.x, from.x, cap * D * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.v, from.v, cap * D * d->tb, hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.B, from.B, cap * D * D * d->tb, hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.F, from.F, cap * D * D * d->tb, hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.mass, from.mass, cap * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.vol, from.vol, cap * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.mat, from.mat, cap * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.id, from.id, cap * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(to.flags, from.flags, cap * sizeof(uint8_t), hipMemcpyDeviceToDevice, c->stream));
-  return OSMPM_OK;
-}
-
-template <int D>
-osmpm_status residual(osmpm_domain *d, const double *a, const double *b, double *r_out) {
-  osmpm_ctx *c = d->ctx;
-  const int nb = blocks_for(d->g.nn);
-  k_resid<D><<<nb, kBlock, 0, c->stream>>>(d->g.nn, d->recv, a, b, d->part_b);
-  osmpm_status s = check_launch(c);
-  if (s) return s;
-  s = ensure_pin(c, 2 * nb + 1);
-  if (s) return s;
-  HIP_TRY(c, hipMemcpyAsync(c->h_pin, d->part_b, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  double s1 = 0.0, s2 = 0.0;
-  for (int i = 0; i < nb; ++i) {
-    s1 += c->h_pin[2 * i];
-    s2 += c->h_pin[2 * i + 1];
+  const SolveState *hs = h_ss(G, s);
+  if (out) out->assign(n, osmpm_solve_stats{});
+  for (int i = 0; i < n; ++i) {
+    if (G->act[s][i] != 1) continue;
+    G->dom[s][i]->cg_hint = std::max(hint[i], 1);
+    if (out) {
+      osmpm_solve_stats &r = (*out)[i];
+      r.newton_iters = hs[i].newton_iters;
+      r.cg_iters = hs[i].cg_iters;
+      r.ls_halvings = hs[i].ls_halvings;
+      r.converged = hs[i].converged;
+      r.ls_failed = hs[i].ls_failed;
+      r.gnorm0 = hs[i].gnorm0;
+      r.gnorm = hs[i].gnorm;
+    }
   }
-  *r_out = std::sqrt(s1) / std::max(std::sqrt(s2), 1e-30);
   return OSMPM_OK;
 }
 
-void add_stats(int &nt, int &cg, int &ls, const osmpm_solve_stats &s) {
+// ---------------------------------------------------------------- interface (two-sided groups)
+template <int D>
+void interface_group(osmpm_batch *G) {
+  osmpm_ctx *c = G->c;
+  const int n = G->n;
+  for (int s = 0; s < 2; ++s) {
+    launch(c, -1, 0, -1, k_qbnd<D>, dim3(blocks_for(G->ext[s].max_np), n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[s]);
+    launch(c, -1, 0, -1, k_gamma, dim3(blocks_for(G->ext[s].max_nn), n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
+  }
+  launch(c, -1, 0, -1, k_fill<int>, dim3(blocks_for(n)), dim3(kBlock), 0, (int64_t)n, 0, G->n_amb);
+  launch(c, -1, 0, -1, k_arbitrate<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
+         (const DomDesc *)G->dd[0], (const DomDesc *)G->dd[1], G->n_amb);
+}
+
+// Receiver counts of both sides into the status block (after arbitration).
+template <int D>
+void count_recv(osmpm_batch *G) {
+  for (int s = 0; s < 2; ++s)
+    launch(G->c, -1, 0, -1, k_count_recv, dim3(1, G->n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[s], G->n_recv + s * G->n);
+}
+
+// Pi_{S->B} into B's work buffer `which` (or out_ext when which < 0).
+template <int D>
+void project_group(osmpm_batch *G, double eps_tol, const double *vS_ext, int which, double *out_ext) {
+  osmpm_ctx *c = G->c;
+  const int n = G->n;
+  launch(c, -1, 0, -1, k_zero_proj, dim3(blocks_for(G->ext[0].max_ndof, 1024), n), dim3(kBlock), 0,
+         (const DomDesc *)G->dd[0]);
+  launch(c, -1, 0, -1, k_project_scatter<D>, dim3(blocks_for(G->ext[1].max_nn), n), dim3(kBlock), 0,
+         (const DomDesc *)G->dd[1], (const DomDesc *)G->dd[0], vS_ext, G->err);
+  launch(c, -1, 0, -1, k_project_final<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
+         (const DomDesc *)G->dd[0], eps_tol, which, out_ext);
+}
+
+// I_{B->S} from B's buffer src (or vB_ext) into S's buffer dst (or out_ext).
+template <int D>
+void interp_group(osmpm_batch *G, int src, const double *vB_ext, int dst, double *out_ext) {
+  launch(G->c, -1, 0, -1, k_interp<D>, dim3(blocks_for(G->ext[1].max_nn), G->n), dim3(kBlock), 0,
+         (const DomDesc *)G->dd[0], (const DomDesc *)G->dd[1], src, vB_ext, dst, out_ext, G->err);
+}
+
+// Relative interface changes r = |a - b| / |a| over each domain's receivers
+// (Eq. convergence_residuals), reduced on the device into the status block.
+template <int D>
+void resid_side(osmpm_batch *G, int s, int a_buf, int b_buf) {
+  osmpm_ctx *c = G->c;
+  launch(c, -1, 0, -1, k_resid<D>, dim3(G->ext[s].nn_blocks, G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s],
+         a_buf, b_buf);
+  launch(c, -1, 0, -1, k_resid_final, dim3(1, G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s],
+         G->res + 2 * s * G->n);
+}
+
+void add_stats(int32_t &nt, int32_t &cg, int32_t &ls, const osmpm_solve_stats &s) {
   nt += s.newton_iters;
   cg += s.cg_iters;
   ls += s.ls_halvings;
 }
 
-// One global frame of Alg. 1.  Buffers: B->w0 = Pi data of the current
-// iteration, B->w1 = Pi data of the next, B->w2 = v_B^(k+1); S->w0 = I(v_B^n),
-// S->w1 = I(v_B^(k+1)), S->w2 = previous I data for r_S.
+// One global frame of Alg. 1 for every pair of a two-sided group.  Work
+// buffer roles: on B, Pi data of the current and the next iteration alternate
+// between w0 and w1, and w2 holds v_B^(k+1); on S, w0 holds I(v_B^n), and the
+// new and previous I(v_B^(k+1)) alternate between w1 and w2.  A pair whose
+// residuals pass the test leaves the group's launches; the coarse G2P runs
+// for all pairs at the end.
 template <int D, typename TB>
-osmpm_status schwarz_impl(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
-                          osmpm_schwarz_stats *out) {
-  osmpm_ctx *c = B->ctx;
-  osmpm_schwarz_stats st{};
-  osmpm_status s;
+osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *o, osmpm_schwarz_stats *out) {
+  osmpm_ctx *c = G->c;
+  const int n = G->n;
   const int M = o->M;
   const double dt = dT / (double)M;
-  const int nB = B->g.nn * D, nS = S->g.nn * D;
-  // Step 0
-  if ((s = copy_state(S, S->pb[S->cur], S->st))) return s;
-  if ((s = p2g_impl<D, TB>(B, true)) || (s = p2g_impl<D, TB>(S, true))) return s;
-  if ((s = interface_impl<D>(B, S))) return s;
-  if ((s = project_impl<D>(S, B, o->eps_tol, nullptr, B->w0))) return s;
-  if ((s = interp_impl<D>(B, nullptr, S, S->w2))) return s;
+  osmpm_status s;
+  if ((s = group_sync(G))) return s;
+  std::vector<osmpm_schwarz_stats> st(n);
+  set_all_active(G);
+  // step 0
+  copy_state_side<D, TB>(G, 1, 1);
+  p2g_side<D, TB>(G, 0, true);
+  p2g_side<D, TB>(G, 1, true);
+  interface_group<D>(G);
+  int piB = 0, piB_next = 1, iS_new = 1, iS_prev = 2;
+  project_group<D>(G, o->eps_tol, nullptr, piB, nullptr);
+  interp_group<D>(G, kBufVn, nullptr, iS_prev, nullptr);
+  std::vector<int> live(n, 1);
+  std::vector<osmpm_solve_stats> ss;
   for (int k = 0; k < o->k_max; ++k) {
-    osmpm_solve_stats ss{};
-    // 1. coarse solve with Pi data
-    HIP_TRY(c, hipMemcpyAsync(B->vbc, B->w0, nB * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    if ((s = solve_impl<D, TB>(B, dT, 1, &o->coarse, &ss))) return s;
-    add_stats(st.newton_B, st.cg_B, st.ls_B, ss);
-    k_vel_from_u<D><<<blocks_for(B->g.nn, 1 << 20), kBlock, 0, c->stream>>>(B->g.nn, B->m, B->u, dT, B->w2);
-    // 2. fine sub-cycling from the restored state
-    if ((s = copy_state(S, S->st, S->pb[S->cur]))) return s;
-    if ((s = p2g_impl<D, TB>(S, false))) return s;
-    if ((s = interp_impl<D>(B, nullptr, S, S->w0))) return s;
-    if ((s = interp_impl<D>(B, B->w2, S, S->w1))) return s;
+    // 1. coarse solve with the projected data
+    if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss))) return s;
+    for (int i = 0; i < n; ++i)
+      if (live[i]) add_stats(st[i].newton_B, st[i].cg_B, st[i].ls_B, ss[i]);
+    launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[0], dT);
+    // 2. fine sub-cycling from the stored state
+    copy_state_side<D, TB>(G, 1, 0);
+    p2g_side<D, TB>(G, 1, false);
+    interp_group<D>(G, kBufVn, nullptr, 0, nullptr);
+    interp_group<D>(G, 2, nullptr, iS_new, nullptr);
     for (int m = 1; m <= M; ++m) {
-      k_temporal<<<blocks_for(nS), kBlock, 0, c->stream>>>(nS, (double)m / (double)M, S->w0, S->w1, S->vbc);
-      if ((s = solve_impl<D, TB>(S, dt, 1, &o->fine, &ss))) return s;
-      add_stats(st.newton_S, st.cg_S, st.ls_S, ss);
-      if ((s = g2p_impl<D, TB>(S, dt))) return s;
-      if ((s = p2g_impl<D, TB>(S, false))) return s;
+      launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(G->ext[1].max_ndof, 1024), n), dim3(kBlock), 0,
+             (const DomDesc *)G->dd[1], (double)m / (double)M, 0, iS_new);
+      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss))) return s;
+      for (int i = 0; i < n; ++i)
+        if (live[i]) add_stats(st[i].newton_S, st[i].cg_S, st[i].ls_S, ss[i]);
+      g2p_side<D, TB>(G, 1, dt);
+      p2g_side<D, TB>(G, 1, false);
     }
     // 3. residuals
-    if ((s = project_impl<D>(S, B, o->eps_tol, nullptr, B->w1))) return s;
-    if ((s = residual<D>(B, B->w1, B->w0, &st.r_B))) return s;
-    if ((s = residual<D>(S, S->w1, S->w2, &st.r_S))) return s;
-    std::swap(B->w0, B->w1);
-    std::swap(S->w2, S->w1);
-    st.iters = k + 1;
-    if (st.r_B <= o->eps_conv && st.r_S <= o->eps_conv) {
-      st.converged = 1;
-      break;
+    project_group<D>(G, o->eps_tol, nullptr, piB_next, nullptr);
+    resid_side<D>(G, 0, piB_next, piB);
+    resid_side<D>(G, 1, iS_new, iS_prev);
+    if ((s = read_status(G))) return s;
+    const double *res = h_res(G);
+    std::swap(piB, piB_next);
+    std::swap(iS_new, iS_prev);
+    bool any = false;
+    for (int i = 0; i < n; ++i) {
+      if (!live[i]) continue;
+      const double rB = std::sqrt(res[2 * i]) / std::max(std::sqrt(res[2 * i + 1]), 1e-30);
+      const double rS = std::sqrt(res[2 * n + 2 * i]) / std::max(std::sqrt(res[2 * n + 2 * i + 1]), 1e-30);
+      st[i].r_B = rB;
+      st[i].r_S = rS;
+      st[i].iters = k + 1;
+      if (rB <= o->eps_conv && rS <= o->eps_conv) {
+        st[i].converged = 1;
+        live[i] = 0;
+      } else {
+        any = true;
+      }
     }
+    if (!any) break;
+    set_active(G, 0, live);
+    set_active(G, 1, live);
   }
-  // 4. coarse G2P + advection with the last coarse solution
-  if ((s = g2p_impl<D, TB>(B, dT))) return s;
-  // receiver counts and ambiguous pairs
-  {
-    const int nbB = B->g.nn, nbS = S->g.nn;
-    std::vector<uint8_t> hb(nbB), hs(nbS);
-    HIP_TRY(c, hipMemcpyAsync(hb.data(), B->recv, nbB, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(hs.data(), S->recv, nbS, hipMemcpyDeviceToHost, c->stream));
-    int amb = 0;
-    HIP_TRY(c, hipMemcpyAsync(&amb, c->d_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (uint8_t v : hb) st.n_recv_B += v;
-    for (uint8_t v : hs) st.n_recv_S += v;
-    st.n_amb = amb;
+  // 4. coarse G2P + advection with the last coarse solution of every pair
+  set_all_active(G);
+  g2p_side<D, TB>(G, 0, dT);
+  count_recv<D>(G);
+  if ((s = read_status(G))) return s;
+  const int *amb = h_int(G, G->off_amb);
+  const int *nrecv = h_int(G, G->off_recv);
+  for (int i = 0; i < n; ++i) {
+    st[i].n_amb = amb[i];
+    st[i].n_recv_B = nrecv[i];
+    st[i].n_recv_S = nrecv[n + i];
+    if (out) out[i] = st[i];
   }
-  int err = 0;
-  Fetch f0;
-  if ((s = fetch(c, f0, &err))) return s;
-  if ((s = device_error(c, err))) return s;
-  if (out) *out = st;
+  return OSMPM_OK;
+}
+
+template <int D, typename TB>
+osmpm_status single_group(osmpm_batch *G, double dt, const osmpm_solve_opts *o, osmpm_solve_stats *out) {
+  osmpm_status s;
+  if ((s = group_sync(G))) return s;
+  std::vector<int> one(G->n, 1);
+  set_active(G, 0, one);
+  p2g_side<D, TB>(G, 0, false);
+  std::vector<osmpm_solve_stats> ss;
+  if ((s = solve_side<D, TB>(G, 0, dt, 0, kBufVbc, o, &ss))) return s;
+  g2p_side<D, TB>(G, 0, dt);
+  if ((s = read_status(G))) return s;
+  if (out)
+    for (int i = 0; i < G->n; ++i) out[i] = ss[i];
+  return OSMPM_OK;
+}
+
+// Single-domain entry points work on the domain's group of one.
+osmpm_status solo_ready(osmpm_domain *d) {
+  osmpm_status s = group_sync(d->solo);
+  if (s) return s;
+  set_active(d->solo, 0, std::vector<int>(1, 1));
+  return OSMPM_OK;
+}
+
+template <int D, typename TB>
+osmpm_status p2g_solo(osmpm_domain *d) {
+  osmpm_status s = solo_ready(d);
+  if (s) return s;
+  p2g_side<D, TB>(d->solo, 0, true);
+  return check_launch(d->ctx);
+}
+
+template <int D, typename TB>
+osmpm_status solve_solo(osmpm_domain *d, double dt, int use_schwarz, const osmpm_solve_opts *o,
+                        osmpm_solve_stats *st) {
+  osmpm_status s = solo_ready(d);
+  if (s) return s;
+  std::vector<osmpm_solve_stats> ss;
+  if ((s = solve_side<D, TB>(d->solo, 0, dt, use_schwarz, kBufVbc, o, &ss))) return s;
+  if (st) *st = ss[0];
+  return OSMPM_OK;
+}
+
+template <int D, typename TB>
+osmpm_status g2p_solo(osmpm_domain *d, double dt) {
+  osmpm_status s = solo_ready(d);
+  if (s) return s;
+  g2p_side<D, TB>(d->solo, 0, dt);
+  return check_launch(d->ctx);
+}
+
+// The group of one coarse/fine pair, created on first use and kept by B.
+osmpm_status pair_group(osmpm_domain *B, osmpm_domain *S, osmpm_batch **out) {
+  if (B->pair && B->pair_uid == S->uid && !B->pair->dead) {
+    *out = B->pair;
+  } else {
+    if (B->pair) group_free(B->pair);
+    B->pair = nullptr;
+    osmpm_status s = group_create(B->ctx, 1, &B, &S, &B->pair);
+    if (s) return s;
+    B->pair_uid = S->uid;
+    *out = B->pair;
+  }
+  osmpm_status s = group_sync(*out);
+  if (s) return s;
+  set_all_active(*out);
   return OSMPM_OK;
 }
 
@@ -673,14 +913,19 @@ TileGeom make_tiles(const osmpm_grid &gd, const int *T) {
   return tg;
 }
 
+bool pair_ok(const osmpm_domain *B, const osmpm_domain *S) {
+  return B && S && B != S && B->ctx == S->ctx && B->D == S->D && B->desc.h0 == S->desc.h0 && B->m_ref == S->m_ref &&
+         B->precision == S->precision;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
 #define DISPATCH(dim, call) ((dim) == 2 ? call<2> : call<3>)
-// Dispatch on dimension and bulk type of a domain.
-#define DISPATCH2(dom, call)                                                                              \
-  ((dom)->D == 2 ? ((dom)->precision == OSMPM_MIXED ? call<2, float> : call<2, double>)                 \
-                 : ((dom)->precision == OSMPM_MIXED ? call<3, float> : call<3, double>))
+// Dispatch on dimension and bulk type.
+#define DISPATCH2(D_, prec_, call) \
+  ((D_) == 2 ? ((prec_) == OSMPM_MIXED ? call<2, float> : call<2, double>) \
+             : ((prec_) == OSMPM_MIXED ? call<3, float> : call<3, double>))
 
 extern "C" {
 
@@ -694,17 +939,10 @@ osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out) {
     return OSMPM_E_DEVICE;
   }
   c->stream = (hipStream_t)stream;
-  if (hipMalloc(&c->d_err, sizeof(int)) != hipSuccess || hipMalloc(&c->d_count, sizeof(int)) != hipSuccess) {
-    delete c;
-    return OSMPM_E_NO_MEMORY;
-  }
-  (void)hipMemsetAsync(c->d_err, 0, sizeof(int), c->stream);
-  (void)hipMemsetAsync(c->d_count, 0, sizeof(int), c->stream);
   if (ensure_pin(c, 1 << 16)) {
     delete c;
     return OSMPM_E_NO_MEMORY;
   }
-  (void)hipStreamSynchronize(c->stream);
   *out = c;
   return OSMPM_OK;
 }
@@ -717,10 +955,18 @@ osmpm_status osmpm_ctx_set_stream(osmpm_ctx *ctx, void *stream) {
 
 osmpm_status osmpm_sync(osmpm_ctx *ctx) {
   if (!ctx) return OSMPM_E_INVALID_ARG;
-  int err = 0;
-  Fetch f;
-  osmpm_status s = fetch(ctx, f, &err);
+  osmpm_status s = check_launch(ctx);
   if (s) return s;
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  prof_harvest(ctx);
+  int err = 0;
+  for (osmpm_batch *G : ctx->groups) {
+    int e = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_pin, G->err, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    std::memcpy(&e, ctx->h_pin, sizeof(int));
+    err |= e;
+  }
   return device_error(ctx, err);
 }
 
@@ -749,10 +995,9 @@ const char *osmpm_last_error(const osmpm_ctx *ctx) { return ctx ? ctx->last_erro
 void osmpm_ctx_destroy(osmpm_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
-  (void)hipFree(ctx->d_err);
-  (void)hipFree(ctx->d_count);
-  if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
   prof_harvest(ctx);
+  while (!ctx->groups.empty()) group_free(ctx->groups.back());
+  if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   delete ctx;
 }
@@ -768,12 +1013,15 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (grid->dim == 2 && grid->n_nodes[2] != 1) return fail(ctx, OSMPM_E_INVALID_ARG, "n_nodes[2] must be 1 in 2D");
   if (!(grid->h0 > 0.0) || grid->dx_q <= 0 || capacity < 0 || capacity > (1LL << 30))
     return fail(ctx, OSMPM_E_INVALID_ARG, "bad grid spacing or capacity");
+  if ((int64_t)grid->n_nodes[0] * grid->n_nodes[1] * grid->n_nodes[2] * grid->dim >= (1LL << 31))
+    return fail(ctx, OSMPM_E_INVALID_ARG, "grid too large");
   int T[3] = {grid->dim == 2 ? 8 : 4, grid->dim == 2 ? 8 : 4, grid->dim == 2 ? 1 : 4};
   if (tile_host)
     for (int a = 0; a < grid->dim; ++a)
       if (tile_host[a] > 0) T[a] = tile_host[a];
   auto *d = new osmpm_domain();
   d->ctx = ctx;
+  d->uid = ctx->next_uid++;
   d->D = grid->dim;
   d->desc = *grid;
   d->precision = precision;
@@ -798,14 +1046,12 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   d->nk = d->tg.ntiles * d->tg.tvol;
   const int D = d->D, nn = g.nn, nd = nn * D;
   const size_t cap = (size_t)d->cap;
-  d->nb_node = blocks_for(nd);
-  d->nb_part = blocks_for(d->cap);
   osmpm_status s = OSMPM_OK;
-  auto part_alloc = [&](PartBuf &p) {
+  auto part_alloc = [&](PartPtrs &p) {
     if (!s) s = dalloc(d, &p.x, cap * D);
-    if (!s) s = dalloc_bytes(d, &p.v, cap * D * d->tb);
-    if (!s) s = dalloc_bytes(d, &p.B, cap * D * D * d->tb);
-    if (!s) s = dalloc_bytes(d, &p.F, cap * D * D * d->tb);
+    if (!s) s = dalloc_bytes(ctx, d->allocs, &p.v, cap * D * d->tb);
+    if (!s) s = dalloc_bytes(ctx, d->allocs, &p.B, cap * D * D * d->tb);
+    if (!s) s = dalloc_bytes(ctx, d->allocs, &p.F, cap * D * D * d->tb);
     if (!s) s = dalloc(d, &p.mass, cap);
     if (!s) s = dalloc(d, &p.vol, cap);
     if (!s) s = dalloc(d, &p.mat, cap);
@@ -816,7 +1062,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   part_alloc(d->pb[1]);
   part_alloc(d->st);
   const int ns = (D * D) * (D * D + 1) / 2;
-  const int nbmax = std::max({d->nb_node, d->nb_part, d->tg.nblocks, blocks_for(nn)}) * 2 + 8;
+  if (!s) s = dalloc(d, &d->d_cur, 1);
   if (!s) s = dalloc(d, &d->key, cap);
   if (!s) s = dalloc(d, &d->perm, cap);
   if (!s) s = dalloc(d, &d->count, (size_t)d->nk + 1);
@@ -834,20 +1080,14 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->q_bnd, nn);
   if (!s) s = dalloc(d, &d->qg, (size_t)nn * kMaxGroups);
   if (!s) s = dalloc(d, &d->gg, nd);
-  if (!s) s = dalloc_bytes(d, &d->gd, nd * d->tb);
-  if (!s) s = dalloc_bytes(d, &d->r, nd * d->tb);
-  if (!s) s = dalloc_bytes(d, &d->z, nd * d->tb);
-  if (!s) s = dalloc_bytes(d, &d->p0, nd * d->tb);
-  if (!s) s = dalloc_bytes(d, &d->p1, nd * d->tb);
-  if (!s) s = dalloc_bytes(d, &d->del, nd * d->tb);
-  if (!s) s = dalloc_bytes(d, &d->Hp, nd * d->tb);
-  if (!s) s = dalloc_bytes(d, &d->Atil, cap * ns * d->tb);
-  if (!s) s = dalloc(d, &d->cg, 1);
-  if (!s) s = dalloc(d, &d->part_a, nbmax);
-  if (!s) s = dalloc(d, &d->part_b, nbmax);
-  if (!s) s = dalloc(d, &d->part_q, nbmax);
-  if (!s) s = dalloc(d, &d->part_rz, nbmax);
-  if (!s) s = dalloc(d, &d->part_rr, nbmax);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->gd, nd * d->tb);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->r, nd * d->tb);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->z, nd * d->tb);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->p0, nd * d->tb);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->p1, nd * d->tb);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->del, nd * d->tb);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->Hp, nd * d->tb);
+  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->Atil, cap * ns * d->tb);
   if (!s) s = dalloc(d, &d->pnum, nd);
   if (!s) s = dalloc(d, &d->pden, nn);
   if (!s) s = dalloc(d, &d->w0, nd);
@@ -856,24 +1096,52 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->w3, nd);
   if (!s) s = dalloc(d, &d->mu, 64);
   if (!s) s = dalloc(d, &d->lam, 64);
+  if (!s) {
+    osmpm_domain *self = d;
+    s = group_create(ctx, 1, &self, nullptr, &d->solo);
+  }
   if (s) {
     osmpm_domain_destroy(d);
     return s;
   }
   // defined initial contents
-  zero_d(ctx, d->vbc, nd);
-  zero_d(ctx, d->u, nd);
-  zero_d(ctx, d->m, nn);
-  (void)hipMemsetAsync(d->recv, 0, nn, ctx->stream);
-  (void)hipMemsetAsync(d->gamma, 0, nn, ctx->stream);
-  (void)hipMemsetAsync(d->q_all, 0, nn * sizeof(long long), ctx->stream);
+  auto zero = [&](void *p, size_t bytes) {
+    if (!s && hipMemsetAsync(p, 0, bytes, ctx->stream) != hipSuccess) s = OSMPM_E_DEVICE;
+  };
+  zero(d->d_cur, sizeof(int));
+  zero(d->vbc, nd * sizeof(double));
+  zero(d->u, nd * sizeof(double));
+  zero(d->m, nn * sizeof(double));
+  zero(d->vn, nd * sizeof(double));
+  zero(d->recv, nn);
+  zero(d->gamma, nn);
+  zero(d->q_all, nn * sizeof(long long));
+  zero(d->q_bnd, nn * sizeof(long long));
+  for (double *w : {d->w0, d->w1, d->w2, d->w3}) zero(w, nd * sizeof(double));
+  if (!s && hipStreamSynchronize(ctx->stream) != hipSuccess) s = OSMPM_E_DEVICE;
+  if (s) {
+    osmpm_domain_destroy(d);
+    return fail(ctx, s, "device initialisation failed");
+  }
   *out = d;
-  return check_launch(ctx);
+  return OSMPM_OK;
 }
 
 void osmpm_domain_destroy(osmpm_domain *dom) {
   if (!dom) return;
-  if (dom->ctx) (void)hipStreamSynchronize(dom->ctx->stream);
+  osmpm_ctx *c = dom->ctx;
+  if (c) (void)hipStreamSynchronize(c->stream);
+  group_free(dom->solo);
+  group_free(dom->pair);
+  if (c) {
+    // groups that hold this domain can no longer run; pair groups of other
+    // coarse domains that use it as their fine side are released
+    std::vector<osmpm_batch *> gs = c->groups;
+    for (osmpm_batch *G : gs)
+      for (int s = 0; s < G->sides; ++s)
+        for (osmpm_domain *m : G->dom[s])
+          if (m == dom) G->dead = true;
+  }
   for (void *p : dom->allocs) (void)hipFree(p);
   delete dom;
 }
@@ -902,25 +1170,26 @@ osmpm_status osmpm_domain_set_particles(osmpm_domain *d, int64_t n, const double
   if (n > 0 && (!x || !v || !B || !F || !mass || !vol || !mat || !flags)) return OSMPM_E_INVALID_ARG;
   osmpm_ctx *c = d->ctx;
   const int D = d->D;
-  PartBuf &p = d->pb[d->cur];
+  PartPtrs &p = d->pb[d->cur];
   d->np = (int)n;
+  d->version += 1;
   if (n > 0) {
-    const int gb = blocks_for(n * D * D, 2048);
-    k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D, x, p.x, d->cap);
+    const dim3 gb(blocks_for(n * D * D, 2048)), blk(kBlock);
+    launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D, x, (double *)p.x, d->cap);
     if (d->precision == OSMPM_MIXED) {
-      k_aos_to_soa<float><<<gb, kBlock, 0, c->stream>>>(n, D, v, (float *)p.v, d->cap);
-      k_aos_to_soa<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, B, (float *)p.B, d->cap);
-      k_aos_to_soa<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, F, (float *)p.F, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D, v, (float *)p.v, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D * D, B, (float *)p.B, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D * D, F, (float *)p.F, d->cap);
     } else {
-      k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D, v, (double *)p.v, d->cap);
-      k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, B, (double *)p.B, d->cap);
-      k_aos_to_soa<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, F, (double *)p.F, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D, v, (double *)p.v, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D * D, B, (double *)p.B, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D * D, F, (double *)p.F, d->cap);
     }
     HIP_TRY(c, hipMemcpyAsync(p.mass, mass, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(p.vol, vol, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(p.mat, mat, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(p.flags, flags, n * sizeof(uint8_t), hipMemcpyDeviceToDevice, c->stream));
-    k_iota<<<blocks_for(n), kBlock, 0, c->stream>>>((int)n, p.id);
+    launch(c, -1, 0, -1, k_iota, dim3(blocks_for(n)), blk, 0, (int)n, p.id);
   }
   d->have_p2g = false;
   return check_launch(c);
@@ -928,6 +1197,7 @@ osmpm_status osmpm_domain_set_particles(osmpm_domain *d, int64_t n, const double
 
 osmpm_status osmpm_domain_set_selection(osmpm_domain *d, double m_ref, double tau) {
   if (!d || !(m_ref > 0.0) || !(tau >= 0.0)) return OSMPM_E_INVALID_ARG;
+  if (d->m_ref != m_ref || d->tau != tau) d->version += 1;
   d->m_ref = m_ref;
   d->tau = tau;
   return OSMPM_OK;
@@ -946,85 +1216,126 @@ osmpm_status osmpm_domain_set_scene_bc(osmpm_domain *d, int32_t n_groups, const 
     bc.mask[gi] = mask[gi];
     for (int k = 0; k < 8; ++k) bc.param[gi][k] = params[gi * 8 + k];
   }
+  if (std::memcmp(&bc, &d->bc, sizeof(SceneBC)) != 0) d->version += 1;
   d->bc = bc;
   return OSMPM_OK;
 }
 
 osmpm_status osmpm_p2g(osmpm_domain *d) {
   if (!d) return OSMPM_E_INVALID_ARG;
-  return DISPATCH2(d, p2g_impl)(d, true);
+  return DISPATCH2(d->D, d->precision, p2g_solo)(d);
 }
 
 osmpm_status osmpm_implicit_solve(osmpm_domain *d, double dt, int32_t use_schwarz_bc, const osmpm_solve_opts *o,
                                   osmpm_solve_stats *st) {
   if (!d || !o) return OSMPM_E_INVALID_ARG;
   if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
-  return DISPATCH2(d, solve_impl)(d, dt, use_schwarz_bc, o, st);
+  if (!(dt > 0.0)) return fail(d->ctx, OSMPM_E_INVALID_ARG, "dt must be positive");
+  if (!d->have_p2g) return fail(d->ctx, OSMPM_E_STATE, "solve before p2g");
+  return DISPATCH2(d->D, d->precision, solve_solo)(d, dt, use_schwarz_bc, o, st);
 }
 
 osmpm_status osmpm_g2p(osmpm_domain *d, double dt) {
   if (!d || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
-  return DISPATCH2(d, g2p_impl)(d, dt);
-}
-
-static bool pair_ok(const osmpm_domain *B, const osmpm_domain *S) {
-  return B && S && B->ctx == S->ctx && B->D == S->D && B->desc.h0 == S->desc.h0 && B->m_ref == S->m_ref &&
-         B->precision == S->precision;
+  if (!d->have_p2g) return fail(d->ctx, OSMPM_E_STATE, "g2p before p2g");
+  return DISPATCH2(d->D, d->precision, g2p_solo)(d, dt);
 }
 
 osmpm_status osmpm_interface_build(osmpm_domain *B, osmpm_domain *S, int32_t *n_amb) {
   if (!pair_ok(B, S)) return OSMPM_E_INVALID_ARG;
   if (!B->have_p2g || !S->have_p2g) return fail(B->ctx, OSMPM_E_STATE, "interface before p2g");
-  osmpm_status s = DISPATCH(B->D, interface_impl)(B, S);
-  if (s || !n_amb) return s;
-  osmpm_ctx *c = B->ctx;
-  int v = 0;
-  HIP_TRY(c, hipMemcpyAsync(&v, c->d_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  *n_amb = v;
+  osmpm_batch *G = nullptr;
+  osmpm_status s = pair_group(B, S, &G);
+  if (s) return s;
+  DISPATCH(B->D, interface_group)(G);
+  if ((s = read_status(G))) return s;
+  if (n_amb) *n_amb = h_int(G, G->off_amb)[0];
   return OSMPM_OK;
 }
 
 osmpm_status osmpm_project_S_to_B(osmpm_domain *S, osmpm_domain *B, double eps_tol, const double *vS, double *out) {
   if (!pair_ok(B, S) || !out || !(eps_tol >= 0.0)) return OSMPM_E_INVALID_ARG;
-  return DISPATCH(B->D, project_impl)(S, B, eps_tol, vS, out);
+  osmpm_batch *G = nullptr;
+  osmpm_status s = pair_group(B, S, &G);
+  if (s) return s;
+  DISPATCH(B->D, project_group)(G, eps_tol, vS, -1, out);
+  return check_launch(B->ctx);
 }
 
 osmpm_status osmpm_interp_B_to_S(osmpm_domain *B, const double *vB, osmpm_domain *S, double *out) {
   if (!pair_ok(B, S) || !out) return OSMPM_E_INVALID_ARG;
-  return DISPATCH(B->D, interp_impl)(B, vB, S, out);
+  osmpm_batch *G = nullptr;
+  osmpm_status s = pair_group(B, S, &G);
+  if (s) return s;
+  DISPATCH(B->D, interp_group)(G, vB ? -1 : kBufVn, vB, -1, out);
+  return check_launch(B->ctx);
 }
 
 osmpm_status osmpm_temporal_interp(osmpm_ctx *ctx, int64_t n, int32_t m, int32_t M, const double *vn,
                                    const double *vn1, double *out) {
   if (!ctx || n < 0 || M < 1 || m < 0 || m > M || (n > 0 && (!vn || !vn1 || !out))) return OSMPM_E_INVALID_ARG;
   if (n == 0) return OSMPM_OK;
-  k_temporal<<<blocks_for(n), kBlock, 0, ctx->stream>>>(n, (double)m / (double)M, vn, vn1, out);
+  launch(ctx, -1, 0, -1, k_temporal_1, dim3(blocks_for(n, 4096)), dim3(kBlock), 0, n, (double)m / (double)M, vn, vn1,
+         out);
   return check_launch(ctx);
 }
 
 osmpm_status osmpm_set_schwarz_bc(osmpm_domain *d, const double *vbc) {
   if (!d || !vbc) return OSMPM_E_INVALID_ARG;
   osmpm_ctx *c = d->ctx;
-  HIP_TRY(c, hipMemcpyAsync(d->vbc, vbc, (size_t)ndof(d) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(d->vbc, vbc, (size_t)d->g.nn * d->D * sizeof(double), hipMemcpyDeviceToDevice,
+                            c->stream));
   return OSMPM_OK;
+}
+
+static bool schwarz_opts_ok(const osmpm_schwarz_opts *o) {
+  return o && o->M >= 1 && o->k_max >= 1 && o->eps_tol >= 0.0 && o->coarse.max_newton >= 0 && o->coarse.max_cg >= 0 &&
+         o->coarse.max_ls >= 0 && o->fine.max_newton >= 0 && o->fine.max_cg >= 0 && o->fine.max_ls >= 0;
 }
 
 osmpm_status osmpm_schwarz_frame(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
                                  osmpm_schwarz_stats *st) {
-  if (!pair_ok(B, S) || !o || !(dT > 0.0) || o->M < 1 || o->k_max < 1 || !(o->eps_tol >= 0.0))
-    return OSMPM_E_INVALID_ARG;
-  return DISPATCH2(B, schwarz_impl)(B, S, dT, o, st);
+  if (!pair_ok(B, S) || !schwarz_opts_ok(o) || !(dT > 0.0)) return OSMPM_E_INVALID_ARG;
+  osmpm_batch *G = nullptr;
+  osmpm_status s = pair_group(B, S, &G);
+  if (s) return s;
+  return DISPATCH2(B->D, B->precision, schwarz_group)(G, dT, o, st);
 }
 
 osmpm_status osmpm_single_frame(osmpm_domain *d, double dt, const osmpm_solve_opts *o, osmpm_solve_stats *st) {
   if (!d || !o || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
-  osmpm_status s = DISPATCH2(d, p2g_impl)(d, false);
-  if (s) return s;
-  if ((s = DISPATCH2(d, solve_impl)(d, dt, 0, o, st))) return s;
-  if ((s = DISPATCH2(d, g2p_impl)(d, dt))) return s;
-  return osmpm_sync(d->ctx);
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  return DISPATCH2(d->D, d->precision, single_group)(d->solo, dt, o, st);
 }
+
+osmpm_status osmpm_batch_create(osmpm_ctx *ctx, int32_t n, osmpm_domain *const *coarse, osmpm_domain *const *fine,
+                                osmpm_batch **out) {
+  if (!ctx || !out || !coarse || n < 1) return OSMPM_E_INVALID_ARG;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!coarse[i]) return OSMPM_E_INVALID_ARG;
+    if (fine && !pair_ok(coarse[i], fine[i])) return fail(ctx, OSMPM_E_INVALID_ARG, "mismatched coarse/fine pair");
+    for (int j = 0; j < i; ++j)
+      if (coarse[j] == coarse[i] || (fine && (fine[j] == fine[i] || fine[j] == coarse[i] || coarse[j] == fine[i])))
+        return fail(ctx, OSMPM_E_INVALID_ARG, "a domain appears twice in the batch");
+  }
+  return group_create(ctx, n, coarse, fine, out);
+}
+
+osmpm_status osmpm_batch_schwarz_frame(osmpm_batch *b, double dT, const osmpm_schwarz_opts *o,
+                                       osmpm_schwarz_stats *stats) {
+  if (!b || b->sides != 2 || !schwarz_opts_ok(o) || !(dT > 0.0)) return OSMPM_E_INVALID_ARG;
+  return DISPATCH2(b->D, b->precision, schwarz_group)(b, dT, o, stats);
+}
+
+osmpm_status osmpm_batch_single_frame(osmpm_batch *b, double dt, const osmpm_solve_opts *o,
+                                      osmpm_solve_stats *stats) {
+  if (!b || b->sides != 1 || !o || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  return DISPATCH2(b->D, b->precision, single_group)(b, dt, o, stats);
+}
+
+void osmpm_batch_destroy(osmpm_batch *b) { group_free(b); }
 
 osmpm_status osmpm_get_particles(osmpm_domain *d, double *x, double *v, double *B, double *F, int32_t *id) {
   if (!d) return OSMPM_E_INVALID_ARG;
@@ -1032,17 +1343,17 @@ osmpm_status osmpm_get_particles(osmpm_domain *d, double *x, double *v, double *
   const int D = d->D;
   const int64_t n = d->np;
   if (n == 0) return OSMPM_OK;
-  const PartBuf &p = d->pb[d->cur];
-  const int gb = blocks_for(n * D * D, 2048);
-  if (x) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D, p.x, d->cap, x);
+  const PartPtrs &p = d->pb[d->cur];
+  const dim3 gb(blocks_for(n * D * D, 2048)), blk(kBlock);
+  if (x) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D, (const double *)p.x, d->cap, x);
   if (d->precision == OSMPM_MIXED) {
-    if (v) k_soa_to_aos<float><<<gb, kBlock, 0, c->stream>>>(n, D, (const float *)p.v, d->cap, v);
-    if (B) k_soa_to_aos<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const float *)p.B, d->cap, B);
-    if (F) k_soa_to_aos<float><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const float *)p.F, d->cap, F);
+    if (v) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D, (const float *)p.v, d->cap, v);
+    if (B) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D * D, (const float *)p.B, d->cap, B);
+    if (F) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D * D, (const float *)p.F, d->cap, F);
   } else {
-    if (v) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D, (const double *)p.v, d->cap, v);
-    if (B) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const double *)p.B, d->cap, B);
-    if (F) k_soa_to_aos<double><<<gb, kBlock, 0, c->stream>>>(n, D * D, (const double *)p.F, d->cap, F);
+    if (v) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D, (const double *)p.v, d->cap, v);
+    if (B) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D * D, (const double *)p.B, d->cap, B);
+    if (F) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D * D, (const double *)p.F, d->cap, F);
   }
   if (id) HIP_TRY(c, hipMemcpyAsync(id, p.id, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
   return check_launch(c);

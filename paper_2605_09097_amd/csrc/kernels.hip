@@ -1,13 +1,15 @@
-// OS-MPM kernels for gfx950 (wave64, 256-thread workgroups).
+// OS-MPM kernels for gfx950 (wave64, 256-thread workgroups), batched over
+// domains: blockIdx.y selects the domain, blockIdx.x the block inside it.
 //
-// Particle-to-grid style kernels (P2G, gradient/Hessian build, CG
+// Particle-to-grid style kernels (P2G, gradient/tangent build, CG
 // Hessian-vector product) run one workgroup per tile of cells: the particles
 // of a tile are contiguous after the binning sort, their 3^d stencils touch
 // the (T+2)^d nodes of the tile region, which is staged in LDS (gathers) and
-// accumulated in LDS with LDS atomics (scatters) before one pass of global
-// atomics per node.  Node kernels are grid-stride loops over DOFs.
+// accumulated in FP64 LDS with LDS atomics (scatters) before one pass of
+// global atomics per node.  Node kernels are grid-stride loops over DOFs.
 // Reductions go through per-workgroup partials that the consumer sums in a
-// fixed order, so every scalar is deterministic run to run.
+// fixed order, so every scalar is deterministic run to run.  Decision
+// kernels advance each domain's Newton / line-search state on the device.
 #include "kernels.hpp"
 
 namespace osmpm {
@@ -20,18 +22,9 @@ __global__ void k_fill(int64_t n, T v, T *a) {
 }
 template __global__ void k_fill<double>(int64_t, double, double *);
 template __global__ void k_fill<float>(int64_t, float, float *);
-__global__ void k_fill_i64(int64_t n, long long *a) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    a[i] = 0;
-}
-__global__ void k_fill_i32(int64_t n, int v, int *a) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    a[i] = v;
-}
-__global__ void k_fill_u8(int64_t n, uint8_t *a) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    a[i] = 0;
-}
+template __global__ void k_fill<int>(int64_t, int, int *);
+template __global__ void k_fill<long long>(int64_t, long long, long long *);
+template __global__ void k_fill<uint8_t>(int64_t, uint8_t, uint8_t *);
 
 // [n][c] (caller layout, FP64) -> [c][cap] (library layout, storage type T)
 template <typename T>
@@ -52,41 +45,102 @@ template __global__ void k_aos_to_soa<double>(int64_t, int, const double *, doub
 template __global__ void k_aos_to_soa<float>(int64_t, int, const double *, float *, int64_t);
 template __global__ void k_soa_to_aos<double>(int64_t, int, const double *, int64_t, double *);
 template __global__ void k_soa_to_aos<float>(int64_t, int, const float *, int64_t, double *);
+
 __global__ void k_iota(int n, int *a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = i;
 }
 
-// ====================================================================== sort
+// flags[i] = bit i of m.
+__global__ void k_set_flags(int *flags, int n, FlagMask m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = (int)((m.w[i >> 6] >> (i & 63)) & 1u);
+}
+
+// T_m (Eq. temporal_interp) on plain arrays.
+__global__ void k_temporal_1(int64_t n, double am, const double *vn, const double *vn1, double *out) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    out[k] = (1.0 - am) * vn[k] + am * vn1[k];
+}
+
+// Sum over a workgroup of two values at once (every thread gets both).
+__device__ inline void block_sum2(double &a, double &b, double *lds8) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    lds8[w] = a;
+    lds8[4 + w] = b;
+  }
+  __syncthreads();
+  a = lds8[0] + lds8[1] + lds8[2] + lds8[3];
+  b = lds8[4] + lds8[5] + lds8[6] + lds8[7];
+}
+
+// Blocks of a grid-stride particle reduction (also its number of partials).
+__device__ inline int particle_blocks(int np) {
+  int b = (np + kBlock - 1) / kBlock;
+  return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+// ====================================================================== binning
+// Zeroes the bin histogram and the P2G targets of every active domain (with
+// want_q also the fixed-point masses of the boundary-set selection).
+__global__ void k_zero_grid(const DomDesc *dd, int want_q) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int nn = dm.g.nn;
+  const int stride = gridDim.x * blockDim.x;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int i = i0; i < dm.nk; i += stride) dm.count[i] = 0;
+  for (int i = i0; i < nn; i += stride) {
+    dm.m[i] = 0.0;
+    if (want_q) {
+      dm.q_all[i] = 0;
+      dm.q_bnd[i] = 0;
+      for (int gi = 0; gi < dm.bc.n_groups; ++gi) dm.qg[(int64_t)gi * nn + i] = 0;
+    }
+  }
+  for (int k = i0; k < dm.ndof; k += stride) dm.vn[k] = 0.0;
+}
+
 // Tile-major bin key of the particle's base node, and the bin histogram.
 template <int D>
-__global__ void k_keys(int n, const double *x, int64_t cap, GridDev g, TileGeom tg, int *key, int *count,
-                       int *err) {
+__global__ void k_keys(const DomDesc *dd, int *err) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  if (p >= dm.np) return;
+  const double *x = dm.pb[*dm.cur].x;
   double xp[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+  for (int a = 0; a < D; ++a) xp[a] = x[a * dm.cap + p];
   Stencil<D> st;
-  if (!stencil_eval<D>(xp, g, st)) atomicOr(err, kErrOutOfGrid);
+  if (!stencil_eval<D>(xp, dm.g, st)) atomicOr(err, kErrOutOfGrid);
   int t[3] = {0, 0, 0}, l[3] = {0, 0, 0};
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    t[a] = st.base[a] / tg.T[a];
-    l[a] = st.base[a] % tg.T[a];
+    t[a] = st.base[a] / dm.tg.T[a];
+    l[a] = st.base[a] % dm.tg.T[a];
   }
-  const int tf = t[0] + tg.nt[0] * (t[1] + tg.nt[1] * t[2]);
-  const int lf = l[0] + tg.T[0] * (l[1] + tg.T[1] * l[2]);
-  const int k = tf * tg.tvol + lf;
-  key[p] = k;
-  atomicAdd(&count[k], 1);
+  const int tf = t[0] + dm.tg.nt[0] * (t[1] + dm.tg.nt[1] * t[2]);
+  const int lf = l[0] + dm.tg.T[0] * (l[1] + dm.tg.T[1] * l[2]);
+  const int k = tf * dm.tg.tvol + lf;
+  dm.key[p] = k;
+  atomicAdd(&dm.count[k], 1);
 }
 
-// Exclusive scan of nk counts by one workgroup of 1024 threads, 4096
-// elements per pass (each thread four consecutive counts, so loads and
+// Exclusive scan of a domain's nk counts by one workgroup of 1024 threads,
+// 4096 elements per pass (each thread four consecutive counts, so loads and
 // stores are coalesced); cell_start[nk] is the total.  cursor receives a copy
 // of the offsets for the scatter.
-__global__ void __launch_bounds__(1024) k_scan(int nk, const int *count, int *cell_start, int *cursor) {
+__global__ void __launch_bounds__(1024) k_scan(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   __shared__ int wsum[16];
+  const int nk = dm.nk;
+  const int *count = dm.count;
+  int *cell_start = dm.cell_start, *cursor = dm.cursor;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int carry = 0;
   for (int base = 0; base < nk; base += 4096) {
@@ -132,18 +186,23 @@ __global__ void __launch_bounds__(1024) k_scan(int nk, const int *count, int *ce
   if (tid == 0) cell_start[nk] = carry;
 }
 
-__global__ void k_scatter(int n, const int *key, int *cursor, int *perm) {
+__global__ void k_scatter(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  perm[atomicAdd(&cursor[key[p]], 1)] = p;
+  if (p >= dm.np) return;
+  dm.perm[atomicAdd(&dm.cursor[dm.key[p]], 1)] = p;
 }
 
 // The scatter fills each bin in arbitrary order; sorting every bin by the
 // original index makes the result the stable counting sort.
-__global__ void k_cellsort(int nk, const int *cell_start, int *perm) {
+__global__ void k_cellsort(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= nk) return;
-  const int s = cell_start[k], e = cell_start[k + 1];
+  if (k >= dm.nk) return;
+  int *perm = dm.perm;
+  const int s = dm.cell_start[k], e = dm.cell_start[k + 1];
   for (int i = s + 1; i < e; ++i) {
     const int v = perm[i];
     int j = i - 1;
@@ -155,18 +214,67 @@ __global__ void k_cellsort(int nk, const int *cell_start, int *perm) {
   }
 }
 
-template <typename T>
-__global__ void k_gather(int n, int rows, const int *perm, const T *src, T *dst, int64_t cap) {
-  const int64_t total = (int64_t)n * rows;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / n, p = i % n;
-    dst[r * cap + p] = src[r * cap + perm[p]];
+// Gathers every particle array into the other buffer in bin order.
+template <int D, typename TB>
+__global__ void k_gather_all(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= dm.np) return;
+  const int c = *dm.cur;
+  const PartPtrs &a = dm.pb[c], &b = dm.pb[c ^ 1];
+  const int64_t cap = dm.cap;
+  const int q = dm.perm[p];
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    b.x[r * cap + p] = a.x[r * cap + q];
+    static_cast<TB *>(b.v)[r * cap + p] = static_cast<const TB *>(a.v)[r * cap + q];
   }
+#pragma unroll
+  for (int r = 0; r < D * D; ++r) {
+    static_cast<TB *>(b.B)[r * cap + p] = static_cast<const TB *>(a.B)[r * cap + q];
+    static_cast<TB *>(b.F)[r * cap + p] = static_cast<const TB *>(a.F)[r * cap + q];
+  }
+  b.mass[p] = a.mass[q];
+  b.vol[p] = a.vol[q];
+  b.mat[p] = a.mat[q];
+  b.id[p] = a.id[q];
+  b.flags[p] = a.flags[q];
 }
-template __global__ void k_gather<double>(int, int, const int *, const double *, double *, int64_t);
-template __global__ void k_gather<float>(int, int, const int *, const float *, float *, int64_t);
-template __global__ void k_gather<int>(int, int, const int *, const int *, int *, int64_t);
-template __global__ void k_gather<uint8_t>(int, int, const int *, const uint8_t *, uint8_t *, int64_t);
+
+__global__ void k_flip(const DomDesc *dd, int ndom) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i < ndom && *dd[i].active) *dd[i].cur ^= 1;
+}
+
+// Fine-state store / restore (Eq. store_states): to_store = 1 copies the
+// current buffer to the store, 0 copies it back.
+template <int D, typename TB>
+__global__ void k_copy_state(const DomDesc *dd, int to_store) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= dm.np) return;
+  const PartPtrs &cb = dm.pb[*dm.cur];
+  const PartPtrs &a = to_store ? cb : dm.st;
+  const PartPtrs &b = to_store ? dm.st : cb;
+  const int64_t cap = dm.cap;
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+    b.x[r * cap + p] = a.x[r * cap + p];
+    static_cast<TB *>(b.v)[r * cap + p] = static_cast<const TB *>(a.v)[r * cap + p];
+  }
+#pragma unroll
+  for (int r = 0; r < D * D; ++r) {
+    static_cast<TB *>(b.B)[r * cap + p] = static_cast<const TB *>(a.B)[r * cap + p];
+    static_cast<TB *>(b.F)[r * cap + p] = static_cast<const TB *>(a.F)[r * cap + p];
+  }
+  b.mass[p] = a.mass[p];
+  b.vol[p] = a.vol[p];
+  b.mat[p] = a.mat[p];
+  b.id[p] = a.id[p];
+  b.flags[p] = a.flags[p];
+}
 
 // ====================================================================== tiles
 // Particle range of tile t and its node-region origin.  Returns false for
@@ -217,21 +325,26 @@ __device__ inline int region_slot(const TileGeom &tg, const int *l, const int *k
 // ====================================================================== P2G
 // APIC P2G (Eq. p2g_transfer) of one tile into LDS, then global atomics.
 // Also the fixed-point node masses (all particles, and per scene group).
-// TB is the storage type of the particle velocity and affine matrix (FP32 in
-// the mixed path).  Tile sums are accumulated in FP64 LDS (ds_add_f64, which
-// measures about twice as fast as ds_add_f32 on gfx950) and added to the FP64
-// grid.
+// Velocities and affine matrices are read in the bulk type TB and every
+// contribution is rounded to TB; tile sums are accumulated in FP64 LDS
+// (ds_add_f64, which measures about twice as fast as ds_add_f32 on gfx950)
+// and added to the FP64 grid.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const int *cell_start, const double *x,
-                                                const TB *v, const TB *B, const double *mass,
-                                                const uint8_t *flags, int64_t cap, int n_groups, double scale,
-                                                double Dinv, int want_q, double *gm, double *gmv,
-                                                long long *q_all, long long *qg, int *err) {
+__global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, int *err) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active || (int)blockIdx.x >= dm.tg.nblocks) return;
   extern __shared__ double lds[];
+  const TileGeom &tg = dm.tg;
+  const GridDev &g = dm.g;
   const int t = tile_of_block(tg, blockIdx.x);
   int p0, p1, org[3];
-  if (!tile_range(tg, cell_start, t, p0, p1, org) || p0 == p1) return;
+  if (!tile_range(tg, dm.cell_start, t, p0, p1, org) || p0 == p1) return;
+  const PartPtrs &P = dm.pb[*dm.cur];
+  const int64_t cap = dm.cap;
+  const TB *v = static_cast<const TB *>(P.v);
+  const TB *B = static_cast<const TB *>(P.B);
   const int nreg = tg.nreg;
+  const int n_groups = dm.bc.n_groups;
   long long *lq = reinterpret_cast<long long *>(lds);
   double *lm = reinterpret_cast<double *>(lq + (size_t)(1 + kMaxGroups) * nreg);
   double *lmv = lm + nreg;
@@ -243,7 +356,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
     double xp[D], vp[D], Bp[D * D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      xp[a] = x[a * cap + p];
+      xp[a] = P.x[a * cap + p];
       vp[a] = (double)v[a * cap + p];
     }
 #pragma unroll
@@ -255,9 +368,9 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
       atomicOr(err, kErrTile);
       continue;
     }
-    const double mp = mass[p];
-    const double mq = mp * scale;
-    const uint8_t fl = flags[p];
+    const double mp = P.mass[p];
+    const double mq = mp * dm.scale;
+    const uint8_t fl = P.flags[p];
 #pragma unroll
     for (int s = 0; s < stencil_count<D>(); ++s) {
       int k[3];
@@ -274,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
         double aff = 0.0;
 #pragma unroll
         for (int b = 0; b < D; ++b) aff += Bp[a * D + b] * dxv[b];
-        atomicAdd(&lmv[a * nreg + r], (double)(TB)(mN * (vp[a] + Dinv * aff)));
+        atomicAdd(&lmv[a * nreg + r], (double)(TB)(mN * (vp[a] + dm.Dinv * aff)));
       }
       if (want_q) {
         const long long q = fixed_mass(N, mq);
@@ -291,15 +404,16 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
     if (i < 0) continue;
     const double m = lm[r];
     if (m != 0.0) {
-      atomicAdd(&gm[i], m);
+      atomicAdd(&dm.m[i], m);
 #pragma unroll
-      for (int a = 0; a < D; ++a) atomicAdd(&gmv[i * D + a], lmv[a * nreg + r]);
+      for (int a = 0; a < D; ++a) atomicAdd(&dm.vn[i * D + a], lmv[a * nreg + r]);
     }
     if (want_q) {
-      if (lq[r] != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&q_all[i]), (unsigned long long)lq[r]);
+      if (lq[r] != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&dm.q_all[i]), (unsigned long long)lq[r]);
       for (int gi = 0; gi < n_groups; ++gi) {
         const long long q = lq[(1 + gi) * nreg + r];
-        if (q != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&qg[(int64_t)gi * g.nn + i]), (unsigned long long)q);
+        if (q != 0)
+          atomicAdd(reinterpret_cast<unsigned long long *>(&dm.qg[(int64_t)gi * g.nn + i]), (unsigned long long)q);
       }
     }
   }
@@ -308,38 +422,47 @@ __global__ void __launch_bounds__(kBlock) k_p2g(TileGeom tg, GridDev g, const in
 // v_i = (mv)_i / m_i on active nodes; scene-BC group of each DOF (lowest
 // group selecting the node whose mask holds the component).
 template <int D>
-__global__ void k_p2g_final(GridDev g, const double *gm, double *gv, const long long *qg, SceneBC bc,
-                            long long tau_q, int8_t *bcg) {
+__global__ void k_p2g_final(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nn) return;
-  const double m = gm[i];
+  if (i >= dm.g.nn) return;
+  const double m = dm.m[i];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    if (m > 0.0) gv[i * D + a] /= m;
+    if (m > 0.0) dm.vn[i * D + a] /= m;
     int8_t gsel = -1;
     if (m > 0.0) {
-      for (int gi = 0; gi < bc.n_groups; ++gi) {
-        if (((bc.mask[gi] >> a) & 1) && qg[(int64_t)gi * g.nn + i] > tau_q) {
+      for (int gi = 0; gi < dm.bc.n_groups; ++gi) {
+        if (((dm.bc.mask[gi] >> a) & 1) && dm.qg[(int64_t)gi * dm.g.nn + i] > dm.tau_q) {
           gsel = (int8_t)gi;
           break;
         }
       }
     }
-    bcg[i * D + a] = gsel;
+    dm.bcg[i * D + a] = gsel;
   }
 }
 
 // ====================================================================== G2P
 // APIC G2P with v_i = u_i / dt (Eqs. g2p_v, g2p_B), F <- (I + sum u_i gradN^T) F
-// (Eq. F_update) and x <- x + dt v_p (Eq. advection).
+// (Eq. F_update) and x <- x + dt v_p (Eq. advection); FP64 arithmetic, v, B,
+// F stored in TB, x in FP64.
 template <int D, typename TB>
-__global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, double dt, double *x, TB *v, TB *B,
-                      TB *F, int64_t cap, int *err) {
+__global__ void k_g2p(const DomDesc *dd, double dt, int *err) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  if (p >= dm.np) return;
+  const PartPtrs &P = dm.pb[*dm.cur];
+  const int64_t cap = dm.cap;
+  const GridDev &g = dm.g;
+  TB *v = static_cast<TB *>(P.v);
+  TB *B = static_cast<TB *>(P.B);
+  TB *F = static_cast<TB *>(P.F);
   double xp[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+  for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
   Stencil<D> st;
   if (!stencil_eval<D>(xp, g, st)) atomicOr(err, kErrOutOfGrid);
   double vp[D], Bp[D * D], G[D * D];
@@ -358,14 +481,14 @@ __global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, doubl
 #pragma unroll
     for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
     const int i = node_flat<D>(g, idx);
-    if (!(gm[i] > 0.0)) continue;
+    if (!(dm.m[i] > 0.0)) continue;
     const double N = stencil_N<D>(st, k);
     double gN[D], dxv[D], ui[D];
     stencil_gradN<D>(st, k, gN);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       dxv[a] = ((double)k[a] - st.f[a]) * g.dx;
-      ui[a] = u[i * D + a];
+      ui[a] = dm.u[i * D + a];
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -394,7 +517,7 @@ __global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, doubl
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     v[a * cap + p] = (TB)vp[a];
-    x[a * cap + p] = xp[a] + dt * vp[a];
+    P.x[a * cap + p] = xp[a] + dt * vp[a];
   }
 }
 
@@ -422,16 +545,22 @@ __device__ inline double scene_value(const SceneBC &bc, int gi, const GridDev &g
 }
 
 // Free-DOF mask and initial iterate: inactive -> 0; scene DOF -> scene value;
-// Schwarz receiver -> dt * v_bc; free -> dt * v^n.  Partial sums of the node
-// mass for the Newton tolerance floor.
-template <int D>
-__global__ void k_bc_init(GridDev g, const double *gm, const double *gv, const int8_t *bcg, const uint8_t *recv,
-                          const double *vbc, int use_schwarz, SceneBC bc, double dt, uint8_t *fr, double *u,
-                          double *part_m) {
+// Schwarz receiver -> dt * v_bc (work buffer vbc_buf); free -> dt * v^n.
+// Clears the gradient and
+// the Jacobi-diagonal scatter targets of the first Newton iteration; partial
+// sums of the node mass (part_a) for the Newton tolerance floor.
+template <int D, typename TB>
+__global__ void k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = node_blocks(dm.ndof);
+  if (!*dm.active || (int)blockIdx.x >= nb) return;
   __shared__ double red[kBlock / 64];
+  const GridDev &g = dm.g;
+  TB *gdiag = static_cast<TB *>(dm.gd);
+  const double *vbc = wbuf(dm, vbc_buf);
   double msum = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += gridDim.x * blockDim.x) {
-    const double m = gm[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += nb * kBlock) {
+    const double m = dm.m[i];
     const bool act = m > 0.0;
     if (act) msum += m;
 #pragma unroll
@@ -440,42 +569,76 @@ __global__ void k_bc_init(GridDev g, const double *gm, const double *gv, const i
       uint8_t f = 0;
       double val = 0.0;
       if (act) {
-        const int gi = bcg[k];
+        const int gi = dm.bcg[k];
         if (gi >= 0) {
-          val = scene_value<D>(bc, gi, g, i, a, dt);
-        } else if (use_schwarz && recv[i]) {
+          val = scene_value<D>(dm.bc, gi, g, i, a, dt);
+        } else if (use_schwarz && dm.recv[i]) {
           val = dt * vbc[k];
         } else {
           f = 1;
-          val = dt * gv[k];
+          val = dt * dm.vn[k];
         }
       }
-      fr[k] = f;
-      u[k] = val;
+      dm.fr[k] = f;
+      dm.u[k] = val;
+      dm.gg[k] = 0.0;
+      gdiag[k] = TB(0);
     }
   }
   const double t = block_sum(msum, red);
-  if (threadIdx.x == 0) part_m[blockIdx.x] = t;
+  if (threadIdx.x == 0) dm.part_a[blockIdx.x] = t;
+}
+
+// Solve state at the start of an implicit solve: the gradient scale of the
+// absolute Newton floor, sum_i m_i * dx / dt^2.  One workgroup per domain.
+__global__ void k_solve_begin(const DomDesc *dd, double dt) {
+  const DomDesc &dm = dd[blockIdx.y];
+  __shared__ double red[kBlock / 64];
+  const bool act = *dm.active != 0;
+  const double mtot = act ? reduce_partials(dm.part_a, node_blocks(dm.ndof), red) : 0.0;
+  if (threadIdx.x == 0) {
+    SolveState &s = *dm.ss;
+    s.gnorm0 = 0.0;
+    s.gnorm = 0.0;
+    s.gscale = mtot * dm.g.dx / (dt * dt);
+    s.alpha = 0.0;
+    s.dE = 0.0;
+    s.it = 0;
+    s.phase = act ? kPhaseGrad : kPhaseDone;
+    s.ls_count = 0;
+    s.converged = 0;
+    s.ls_failed = 0;
+    s.newton_iters = 0;
+    s.cg_iters = 0;
+    s.ls_halvings = 0;
+    dm.cg->done = 1;
+    dm.cg->iter = 0;
+  }
 }
 
 // ====================================================================== gradient + Hessian
 // Per particle at the iterate u: F = (I + sum u_i gradN_i^T) F^n and P(F) in
-// FP64; the gradient V P F^nT gradN_i is scattered (FP64).  With want_hess
-// the particle's tangent A = dP/dF (PSD-projected when asked) is evaluated in
-// the bulk type TB, folded with F^n and V, Atil = V C^T A C with C: G -> G F^n,
-// stored packed, and its contribution to the Jacobi diagonal is scattered.
+// FP64; the gradient V P F^nT gradN_i is scattered (FP64).  The particle's
+// tangent A = dP/dF (PSD-projected when asked) is evaluated in the bulk type
+// TB, folded with F^n and V, Atil = V C^T A C with C: G -> G F^n, stored
+// packed, and its contribution to the Jacobi diagonal is scattered.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, const int *cell_start,
-                                                      const double *x, const TB *F, const double *vol,
-                                                      const int *mat, const double *mu_t, const double *lam_t,
-                                                      int64_t cap, const double *u, int want_hess, int project,
-                                                      double *gg, TB *gdiag, TB *Atil, int *err) {
+__global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int project, int *err) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active || !phase_wants_grad(dm.ss->phase) || (int)blockIdx.x >= dm.tg.nblocks) return;
   extern __shared__ double lds[];
+  const TileGeom &tg = dm.tg;
+  const GridDev &g = dm.g;
   const int t = tile_of_block(tg, blockIdx.x);
   int p0, p1, org[3];
-  if (!tile_range(tg, cell_start, t, p0, p1, org) || p0 == p1) return;
+  if (!tile_range(tg, dm.cell_start, t, p0, p1, org) || p0 == p1) return;
+  const PartPtrs &P = dm.pb[*dm.cur];
+  const int64_t cap = dm.cap;
+  const TB *F = static_cast<const TB *>(P.F);
+  TB *Atil = static_cast<TB *>(dm.Atil);
+  TB *gdiag = static_cast<TB *>(dm.gd);
   const int nreg = tg.nreg;
   double *lu = lds;
   double *lg = lds + D * nreg;
@@ -484,7 +647,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
     const int i = region_node<D>(tg, g, org, r);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      lu[a * nreg + r] = (i >= 0) ? u[i * D + a] : 0.0;
+      lu[a * nreg + r] = (i >= 0) ? dm.u[i * D + a] : 0.0;
       lg[a * nreg + r] = 0.0;
       ld[a * nreg + r] = 0.0;
     }
@@ -493,7 +656,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
   for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
     double xp[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+    for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
     Stencil<D> st;
     stencil_eval<D>(xp, g, st);
     int l[3];
@@ -531,10 +694,10 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
         for (int e = 0; e < D; ++e) tv += Gu[a * D + e] * Fn[e * D + b];
         Fc[a * D + b] = tv;
       }
-    const int mt = mat[p];
-    const double mu = mu_t[mt], lam = lam_t[mt], V = vol[p];
-    double P[n];
-    if (!nh_stress<D, double>(Fc, mu, lam, P, nullptr)) {
+    const int mt = P.mat[p];
+    const double mu = dm.mu[mt], lam = dm.lam[mt], V = P.vol[p];
+    double Pk[n];
+    if (!nh_stress<D, double>(Fc, mu, lam, Pk, nullptr)) {
       atomicOr(err, kErrInverted);
       continue;
     }
@@ -546,11 +709,11 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
       for (int b = 0; b < D; ++b) {
         double tv = 0.0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) tv += P[a * D + c] * Fn[b * D + c];
+        for (int c = 0; c < D; ++c) tv += Pk[a * D + c] * Fn[b * D + c];
         T[a * D + b] = V * tv;
       }
     TB At[ns];
-    if (want_hess) {
+    {
       TB Fb[n], Fnb[n], A[n * n];
 #pragma unroll
       for (int k = 0; k < n; ++k) {
@@ -603,23 +766,21 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
         for (int b = 0; b < D; ++b) tv += T[a * D + b] * gN[b];
         atomicAdd(&lg[a * nreg + r], tv);
       }
-      if (want_hess) {
-        TB gb[D];
+      TB gb[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a) gb[a] = (TB)gN[a];
+      for (int a = 0; a < D; ++a) gb[a] = (TB)gN[a];
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          TB dv = TB(0);
+      for (int a = 0; a < D; ++a) {
+        TB dv = TB(0);
 #pragma unroll
-          for (int b = 0; b < D; ++b)
+        for (int b = 0; b < D; ++b)
 #pragma unroll
-            for (int e = 0; e < D; ++e) {
-              const int r1 = a * D + b, c1 = a * D + e;
-              const TB av = (r1 <= c1) ? At[sym_index<n>(r1, c1)] : At[sym_index<n>(c1, r1)];
-              dv += av * gb[b] * gb[e];
-            }
-          atomicAdd(&ld[a * nreg + r], (double)dv);
-        }
+          for (int e = 0; e < D; ++e) {
+            const int r1 = a * D + b, c1 = a * D + e;
+            const TB av = (r1 <= c1) ? At[sym_index<n>(r1, c1)] : At[sym_index<n>(c1, r1)];
+            dv += av * gb[b] * gb[e];
+          }
+        atomicAdd(&ld[a * nreg + r], (double)dv);
       }
     }
   }
@@ -630,41 +791,66 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(TileGeom tg, GridDev g, co
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const double gv = lg[a * nreg + r];
-      if (gv != 0.0) atomicAdd(&gg[i * D + a], gv);
-      if (want_hess) {
-        const double dv = ld[a * nreg + r];
-        if (dv != 0.0) atomicAdd(&gdiag[i * D + a], (TB)dv);
-      }
+      if (gv != 0.0) atomicAdd(&dm.gg[i * D + a], gv);
+      const double dv = ld[a * nreg + r];
+      if (dv != 0.0) atomicAdd(&gdiag[i * D + a], (TB)dv);
     }
   }
 }
 
 // Node part of the gradient: + m/dt^2 (u - dt v^n) - m g on active nodes,
-// masked to free DOFs; partial |g|^2.  With want_hess the Jacobi diagonal
-// becomes scatter + m/dt^2 (1 on non-free DOFs).
+// masked to free DOFs; partial |g|^2 (part_a).  The Jacobi diagonal becomes
+// scatter + m/dt^2 (1 on non-free DOFs).
 template <int D, typename TB>
-__global__ void k_grad_node(GridDev g, const double *gm, const double *gv, const double *u, const uint8_t *fr,
-                            double dt, double gx, double gy, double gz, double *gg, TB *gdiag, int want_hess,
-                            double *part) {
+__global__ void k_grad_node(const DomDesc *dd, double dt, double gx, double gy, double gz) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = node_blocks(dm.ndof);
+  if (!*dm.active || !phase_wants_grad(dm.ss->phase) || (int)blockIdx.x >= nb) return;
   __shared__ double red[kBlock / 64];
+  TB *gdiag = static_cast<TB *>(dm.gd);
   const double grav[3] = {gx, gy, gz};
   const double idt2 = 1.0 / (dt * dt);
   double s2 = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += gridDim.x * blockDim.x) {
-    const double m = gm[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < dm.g.nn; i += nb * kBlock) {
+    const double m = dm.m[i];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const int k = i * D + a;
-      double gval = gg[k];
-      if (m > 0.0) gval += m * idt2 * (u[k] - dt * gv[k]) - m * grav[a];
-      if (!fr[k]) gval = 0.0;
-      gg[k] = gval;
+      double gval = dm.gg[k];
+      if (m > 0.0) gval += m * idt2 * (dm.u[k] - dt * dm.vn[k]) - m * grav[a];
+      if (!dm.fr[k]) gval = 0.0;
+      dm.gg[k] = gval;
       s2 += gval * gval;
-      if (want_hess) gdiag[k] = fr[k] ? (TB)((double)gdiag[k] + m * idt2) : TB(1);
+      gdiag[k] = dm.fr[k] ? (TB)((double)gdiag[k] + m * idt2) : TB(1);
     }
   }
   const double t = block_sum(s2, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) dm.part_a[blockIdx.x] = t;
+}
+
+// Newton stop test of every domain with a fresh gradient: stop when
+// |g_free| <= max(rtol |g_free(u0)|, atol * sum m * dx / dt^2) or after
+// max_newton steps, else go on to CG.  One workgroup per domain.
+__global__ void k_newton_check(const DomDesc *dd, double rtol, double atol, int max_newton) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active || !phase_wants_grad(dm.ss->phase)) return;
+  __shared__ double red[kBlock / 64];
+  const double g2 = reduce_partials(dm.part_a, node_blocks(dm.ndof), red);
+  if (threadIdx.x == 0) {
+    SolveState &s = *dm.ss;
+    const double gn = sqrt(g2);
+    if (s.it == 0) s.gnorm0 = gn;
+    s.gnorm = gn;
+    const double tol = fmax(rtol * s.gnorm0, atol * s.gscale);
+    if (gn <= tol) {
+      s.converged = 1;
+      s.phase = kPhaseDone;
+    } else if (s.it == max_newton) {
+      s.phase = kPhaseDone;
+    } else {
+      s.phase = kPhaseCgInit;
+    }
+  }
 }
 
 // ====================================================================== CG
@@ -682,15 +868,28 @@ __device__ inline TB cg_direction(TB z, double beta, TB pp) {
 }
 
 // r = -g, z = r / D on free DOFs; search-direction buffers, direction and
-// product cleared; partial (r, z) and (r, r).
+// product cleared; partial (r, z) and (r, r); the CG state is reset.  Runs for
+// domains whose Newton iteration goes on to CG.
 template <int D, typename TB>
-__global__ void k_cg_init(int ndof, const double *gg, const TB *gdiag, const uint8_t *fr, TB *r, TB *z, TB *p0,
-                          TB *p1, TB *del, TB *Hp, double *part_rz, double *part_rr, CgState *S) {
-  __shared__ double red[kBlock / 64];
+__global__ void k_cg_init(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = node_blocks(dm.ndof);
+  if (!*dm.active || dm.ss->phase != kPhaseCgInit || (int)blockIdx.x >= nb) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    dm.cg->iter = 0;
+    dm.cg->done = 0;
+    dm.cg->knext = 0;
+    dm.cg->kcur = 0;
+  }
+  __shared__ double red[8];
+  const TB *gdiag = static_cast<const TB *>(dm.gd);
+  TB *r = static_cast<TB *>(dm.r), *z = static_cast<TB *>(dm.z), *p0 = static_cast<TB *>(dm.p0);
+  TB *p1 = static_cast<TB *>(dm.p1), *del = static_cast<TB *>(dm.del), *Hp = static_cast<TB *>(dm.Hp);
   double rz = 0.0, rr = 0.0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < ndof; k += gridDim.x * blockDim.x) {
-    const bool f = fr[k];
-    const TB rv = f ? (TB)(-gg[k]) : TB(0);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += nb * kBlock) {
+    const bool f = dm.fr[k];
+    const TB rv = f ? (TB)(-dm.gg[k]) : TB(0);
+    dm.gg[k] = 0.0;  // scatter target of the next Newton iteration
     const TB zv = f ? (TB)((double)rv / (double)gdiag[k]) : TB(0);
     r[k] = rv;
     z[k] = zv;
@@ -703,33 +902,11 @@ __global__ void k_cg_init(int ndof, const double *gg, const TB *gdiag, const uin
       rr += (double)rv * (double)rv;
     }
   }
-  const double a = block_sum(rz, red);
-  const double b = block_sum(rr, red);
+  block_sum2(rz, rr, red);
   if (threadIdx.x == 0) {
-    part_rz[blockIdx.x] = a;
-    part_rr[blockIdx.x] = b;
+    dm.part_rz[blockIdx.x] = rz;
+    dm.part_rr[blockIdx.x] = rr;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    S->iter = 0;
-    S->done = 0;
-    S->knext = 0;
-    S->kcur = 0;
-  }
-}
-
-// Sum over a workgroup of two values at once (every thread gets both).
-__device__ inline void block_sum2(double &a, double &b, double *lds8) {
-  a = wave_sum(a);
-  b = wave_sum(b);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) {
-    lds8[w] = a;
-    lds8[4 + w] = b;
-  }
-  __syncthreads();
-  a = lds8[0] + lds8[1] + lds8[2] + lds8[3];
-  b = lds8[4] + lds8[5] + lds8[6] + lds8[7];
 }
 
 // CG iteration, first half.  The iteration index k comes from the device
@@ -743,29 +920,38 @@ __device__ inline void block_sum2(double &a, double &b, double *lds8) {
 // curvature complete in one pass.  All global loads that do not depend on
 // beta are issued before the reduction so their latencies overlap.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const int *cell_start, const double *x,
-                                                   const TB *Atil, int64_t cap, const double *gm, double dt,
-                                                   int ndof, const TB *z, TB *pA, TB *pB, TB *Hp,
-                                                   const double *part_rz, const double *part_rr, int n_part,
-                                                   double rtol, int max_cg, double *part_q, CgState *S) {
+__global__ void __launch_bounds__(kBlock) k_cg_hvp(const DomDesc *dd, double dt, double rtol, int max_cg) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
+  const DomDesc &dm = dd[blockIdx.y];
+  const TileGeom &tg = dm.tg;
+  if (!*dm.active || (int)blockIdx.x >= tg.nblocks) return;
+  CgState *S = dm.cg;
+  if (S->done) return;
   extern __shared__ double lds[];
   __shared__ double red[8];
+  const GridDev &g = dm.g;
   const int tid = threadIdx.x;
   const int it = S->knext;
+  const int ndof = dm.ndof;
+  const int64_t cap = dm.cap;
+  const TB *Atil = static_cast<const TB *>(dm.Atil);
+  const TB *z = static_cast<const TB *>(dm.z);
+  TB *pA = static_cast<TB *>(dm.p0), *pB = static_cast<TB *>(dm.p1), *Hp = static_cast<TB *>(dm.Hp);
   const TB *pprev = (it & 1) ? pA : pB;
   TB *pcur = (it & 1) ? pB : pA;
+  const double *x = dm.pb[*dm.cur].x;
+  const int n_part = node_blocks(ndof);
   // tile and its particle range
   const int t = tile_of_block(tg, blockIdx.x);
   int p0 = 0, p1 = 0, org[3] = {0, 0, 0};
-  const bool tile_ok = tile_range(tg, cell_start, t, p0, p1, org) && p0 < p1;
+  const bool tile_ok = tile_range(tg, dm.cell_start, t, p0, p1, org) && p0 < p1;
   const int nreg = tg.nreg;
   // --- independent loads
   double prz = 0.0, prr = 0.0;
   for (int i = tid; i < n_part; i += kBlock) {
-    prz += part_rz[i];
-    prr += part_rr[i];
+    prz += dm.part_rz[i];
+    prr += dm.part_rr[i];
   }
   const int k0 = blockIdx.x * kBlock + tid;
   TB nz = TB(0), npv = TB(0);
@@ -773,7 +959,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
   if (k0 < ndof) {
     nz = z[k0];
     npv = pprev[k0];
-    nm = gm[k0 / D];
+    nm = dm.m[k0 / D];
   }
   int ri = -1;
   TB rzv[D], rpv[D];
@@ -806,7 +992,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
     S->rz[it & 1] = rz_new;
     S->kcur = it;
   }
-  if (done || S->done) return;
+  if (done) return;
   const double beta = (it == 0) ? 0.0 : rz_new / S->rz[(it + 1) & 1];
   const double mdt = 1.0 / (dt * dt);
   double q = 0.0;
@@ -816,10 +1002,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
     pcur[k0] = pv;
     q += nm * mdt * (double)pv * (double)pv;
   }
-  for (int k = k0 + gridDim.x * kBlock; k < ndof; k += gridDim.x * kBlock) {
+  for (int k = k0 + tg.nblocks * kBlock; k < ndof; k += tg.nblocks * kBlock) {
     const TB pv = cg_direction<TB>(z[k], beta, pprev[k]);
     pcur[k] = pv;
-    q += gm[k / D] * mdt * (double)pv * (double)pv;
+    q += dm.m[k / D] * mdt * (double)pv * (double)pv;
   }
   if (tile_ok) {
     double *lh = lds;
@@ -908,7 +1094,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
     }
   }
   const double tq = block_sum(q, red);
-  if (tid == 0) part_q[blockIdx.x] = tq;
+  if (tid == 0) dm.part_q[blockIdx.x] = tq;
 }
 
 // CG iteration, second half: alpha = (r, z) / p^T H p; del += alpha p,
@@ -916,28 +1102,34 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(TileGeom tg, GridDev g, const
 // scatter buffer is cleared for the next product; partial (r, z), (r, r).
 // Node data are loaded before the curvature partials are reduced.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm, double dt, const uint8_t *fr,
-                                                      const TB *gdiag, const TB *pA, const TB *pB, TB *Hp, TB *r,
-                                                      TB *z, TB *del, const double *part_q, int n_q,
-                                                      double *part_rz, double *part_rr, CgState *S) {
+__global__ void __launch_bounds__(kBlock) k_cg_update(const DomDesc *dd, double dt) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = node_blocks(dm.ndof);
+  if (!*dm.active || (int)blockIdx.x >= nb) return;
+  CgState *S = dm.cg;
+  if (S->done) return;
   __shared__ double red[8];
   const int tid = threadIdx.x;
-  if (S->done) return;
   const int it = S->kcur;
-  const TB *pcur = (it & 1) ? pB : pA;
+  const int ndof = dm.ndof;
+  const TB *gdiag = static_cast<const TB *>(dm.gd);
+  const TB *pcur = static_cast<const TB *>((it & 1) ? dm.p1 : dm.p0);
+  TB *Hp = static_cast<TB *>(dm.Hp), *r = static_cast<TB *>(dm.r), *z = static_cast<TB *>(dm.z);
+  TB *del = static_cast<TB *>(dm.del);
+  const int n_q = dm.tg.nblocks;
   double pq = 0.0;
-  for (int i = tid; i < n_q; i += kBlock) pq += part_q[i];
+  for (int i = tid; i < n_q; i += kBlock) pq += dm.part_q[i];
   const int k0 = blockIdx.x * kBlock + tid;
   double hs = 0.0, pv = 0.0, rv = 0.0, dv = 0.0, dg = 1.0, m = 0.0;
   bool f = false;
   if (k0 < ndof) {
-    f = fr[k0];
+    f = dm.fr[k0];
     hs = (double)Hp[k0];
     pv = (double)pcur[k0];
     rv = (double)r[k0];
     dv = (double)del[k0];
     dg = (double)gdiag[k0];
-    m = gm[k0 / D];
+    m = dm.m[k0 / D];
   }
   pq = block_sum(pq, red);
   if (!(pq > 0.0)) {
@@ -960,12 +1152,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm
       rr += (double)rn * (double)rn;
     }
   }
-  for (int k = k0 + gridDim.x * kBlock; k < ndof; k += gridDim.x * kBlock) {
+  for (int k = k0 + nb * kBlock; k < ndof; k += nb * kBlock) {
     const double h2 = (double)Hp[k];
     Hp[k] = TB(0);
-    if (!fr[k]) continue;
+    if (!dm.fr[k]) continue;
     const double p2 = (double)pcur[k];
-    const double hv = h2 + gm[k / D] * mdt * p2;
+    const double hv = h2 + dm.m[k / D] * mdt * p2;
     del[k] = (TB)((double)del[k] + alpha * p2);
     const TB rn = (TB)((double)r[k] - alpha * hv);
     r[k] = rn;
@@ -976,8 +1168,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm
   }
   block_sum2(rz, rr, red);
   if (tid == 0) {
-    part_rz[blockIdx.x] = rz;
-    part_rr[blockIdx.x] = rr;
+    dm.part_rz[blockIdx.x] = rz;
+    dm.part_rr[blockIdx.x] = rr;
   }
   if (blockIdx.x == 0 && tid == 0) {
     S->iter = it + 1;
@@ -986,20 +1178,46 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int ndof, const double *gm
 }
 
 // ====================================================================== line search
+// Phase moves after the CG launches of a cycle, one thread per domain: a
+// freshly initialised CG is now running; a finished CG starts the line search
+// at alpha = 1 and its iteration count is added to the statistics.
+__global__ void k_ls_begin(const DomDesc *dd, int ndom) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i >= ndom) return;
+  const DomDesc &dm = dd[i];
+  if (!*dm.active) return;
+  SolveState &s = *dm.ss;
+  if (s.phase == kPhaseCgInit) s.phase = kPhaseCg;
+  if (s.phase == kPhaseCg && dm.cg->done) {
+    s.cg_iters += dm.cg->iter;
+    s.alpha = 1.0;
+    s.ls_count = 0;
+    s.phase = kPhaseLs;
+  }
+}
+
 // Per-particle part of E(u + alpha del) - E(u) in cancellation-free form:
 // V [mu/2 (2 F:Dm + Dm:Dm) - mu L + lam/2 L (2 ln J + L)], L = log1p(dJ / J),
 // dJ = det(F + Dm) - det F expanded in powers of Dm; +inf on inversion.
+// Partials in part_b.
 template <int D, typename TB>
-__global__ void k_delta_energy_p(int np, GridDev g, const double *x, const TB *F, const double *vol,
-                                 const int *mat, const double *mu_t, const double *lam_t, int64_t cap,
-                                 const double *u, const TB *del, double alpha, double *part) {
+__global__ void k_delta_energy_p(const DomDesc *dd) {
   constexpr int n = D * D;
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = particle_blocks(dm.np);
+  if (!*dm.active || dm.ss->phase != kPhaseLs || (int)blockIdx.x >= nb) return;
   __shared__ double red[kBlock / 64];
+  const PartPtrs &P = dm.pb[*dm.cur];
+  const int64_t cap = dm.cap;
+  const GridDev &g = dm.g;
+  const TB *F = static_cast<const TB *>(P.F);
+  const TB *del = static_cast<const TB *>(dm.del);
+  const double alpha = dm.ss->alpha;
   double e = 0.0;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < np; p += gridDim.x * blockDim.x) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < dm.np; p += nb * kBlock) {
     double xp[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+    for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
     Stencil<D> st;
     stencil_eval<D>(xp, g, st);
     double Gu[n], Gd[n], Fn[n];
@@ -1020,7 +1238,7 @@ __global__ void k_delta_energy_p(int np, GridDev g, const double *x, const TB *F
       stencil_gradN<D>(st, k, gN);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        const double ua = u[i * D + a], da = (double)del[i * D + a];
+        const double ua = dm.u[i * D + a], da = (double)del[i * D + a];
 #pragma unroll
         for (int b = 0; b < D; ++b) {
           Gu[a * D + b] += ua * gN[b];
@@ -1067,59 +1285,108 @@ __global__ void k_delta_energy_p(int np, GridDev g, const double *x, const TB *F
       FD += Fc[k] * Dm[k];
       DD += Dm[k] * Dm[k];
     }
-    const int mt = mat[p];
-    const double mu = mu_t[mt], lam = lam_t[mt];
-    e += vol[p] * (0.5 * mu * (2.0 * FD + DD) - mu * L + 0.5 * lam * L * (2.0 * lnJ + L));
+    const int mt = P.mat[p];
+    const double mu = dm.mu[mt], lam = dm.lam[mt];
+    e += P.vol[p] * (0.5 * mu * (2.0 * FD + DD) - mu * L + 0.5 * lam * L * (2.0 * lnJ + L));
   }
   const double t = block_sum(e, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) dm.part_b[blockIdx.x] = t;
 }
 
-// Node part: m/(2 dt^2) (2 alpha (u - dt v^n).del + alpha^2 |del|^2) - alpha m g.del.
+// Node part: m/(2 dt^2) (2 alpha (u - dt v^n).del + alpha^2 |del|^2) - alpha m g.del
+// (partials in part_a).
 template <int D, typename TB>
-__global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, const double *u, const TB *del,
-                                 double dt, double alpha, double gx, double gy, double gz, double *part) {
+__global__ void k_delta_energy_n(const DomDesc *dd, double dt, double gx, double gy, double gz) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = node_blocks(dm.ndof);
+  if (!*dm.active || dm.ss->phase != kPhaseLs || (int)blockIdx.x >= nb) return;
   __shared__ double red[kBlock / 64];
+  const TB *del = static_cast<const TB *>(dm.del);
+  const double alpha = dm.ss->alpha;
   const double grav[3] = {gx, gy, gz};
   double e = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += gridDim.x * blockDim.x) {
-    const double m = gm[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < dm.g.nn; i += nb * kBlock) {
+    const double m = dm.m[i];
     if (!(m > 0.0)) continue;
-    double rd = 0.0, dd = 0.0, gd = 0.0;
+    double rd = 0.0, dd2 = 0.0, gd = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const double dv = (double)del[i * D + a];
-      rd += (u[i * D + a] - dt * gv[i * D + a]) * dv;
-      dd += dv * dv;
+      rd += (dm.u[i * D + a] - dt * dm.vn[i * D + a]) * dv;
+      dd2 += dv * dv;
       gd += grav[a] * dv;
     }
-    e += m / (2.0 * dt * dt) * (2.0 * alpha * rd + alpha * alpha * dd) - alpha * m * gd;
+    e += m / (2.0 * dt * dt) * (2.0 * alpha * rd + alpha * alpha * dd2) - alpha * m * gd;
   }
   const double t = block_sum(e, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
+  if (threadIdx.x == 0) dm.part_a[blockIdx.x] = t;
 }
 
-template <typename TB>
-__global__ void k_axpy(int n, double alpha, const TB *xv, double *y) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
-    y[k] += alpha * (double)xv[k];
+// Halving decision of every searching domain: accept when the energy change
+// is negative; otherwise halve alpha, or give up after max_ls halvings (the
+// iterate is kept and the solve ends).  One workgroup per domain.
+__global__ void k_ls_check(const DomDesc *dd, int max_ls) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active || dm.ss->phase != kPhaseLs) return;
+  __shared__ double red[kBlock / 64];
+  const double en = reduce_partials(dm.part_a, node_blocks(dm.ndof), red);
+  const double ep = reduce_partials(dm.part_b, particle_blocks(dm.np), red);
+  if (threadIdx.x == 0) {
+    SolveState &s = *dm.ss;
+    const double dE = en + ep;
+    s.dE = dE;
+    if (dE < 0.0) {
+      s.phase = kPhaseStep;
+    } else if (s.ls_count == max_ls) {
+      s.ls_failed = 1;
+      s.phase = kPhaseDone;
+    } else {
+      s.alpha *= 0.5;
+      s.ls_count += 1;
+      s.ls_halvings += 1;
+    }
+  }
 }
-template __global__ void k_axpy<double>(int, double, const double *, double *);
-template __global__ void k_axpy<float>(int, double, const float *, double *);
+
+// u += alpha del for every domain that accepted a step; clears the diagonal
+// scatter target of the next iteration.  The phase stays kPhaseStep until the
+// next Newton test.
+template <typename TB>
+__global__ void k_newton_step(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = node_blocks(dm.ndof);
+  if (!*dm.active || (int)blockIdx.x >= nb) return;
+  SolveState &s = *dm.ss;
+  if (s.phase != kPhaseStep) return;
+  const double alpha = s.alpha;
+  const TB *del = static_cast<const TB *>(dm.del);
+  TB *gdiag = static_cast<TB *>(dm.gd);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += nb * kBlock) {
+    dm.u[k] += alpha * (double)del[k];
+    gdiag[k] = TB(0);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.newton_iters += 1;
+    s.it += 1;
+  }
+}
 
 // ====================================================================== interface
 // Fixed-point node mass of the boundary-layer particles (Eq. boundary_grid_set).
 template <int D>
-__global__ void k_qbnd(int np, GridDev g, const double *x, const double *mass, const uint8_t *flags, int64_t cap,
-                       double scale, long long *q_bnd) {
+__global__ void k_qbnd(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np || !(flags[p] & 1u)) return;
+  if (p >= dm.np) return;
+  const PartPtrs &P = dm.pb[*dm.cur];
+  if (!(P.flags[p] & 1u)) return;
   double xp[D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+  for (int a = 0; a < D; ++a) xp[a] = P.x[a * dm.cap + p];
   Stencil<D> st;
-  stencil_eval<D>(xp, g, st);
-  const double mq = mass[p] * scale;
+  stencil_eval<D>(xp, dm.g, st);
+  const double mq = P.mass[p] * dm.scale;
 #pragma unroll
   for (int s = 0; s < stencil_count<D>(); ++s) {
     int k[3], idx[3];
@@ -1127,60 +1394,89 @@ __global__ void k_qbnd(int np, GridDev g, const double *x, const double *mass, c
 #pragma unroll
     for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
     const long long q = fixed_mass(stencil_N<D>(st, k), mq);
-    if (q != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&q_bnd[node_flat<D>(g, idx)]), (unsigned long long)q);
+    if (q != 0)
+      atomicAdd(reinterpret_cast<unsigned long long *>(&dm.q_bnd[node_flat<D>(dm.g, idx)]), (unsigned long long)q);
   }
 }
 
-__global__ void k_gamma(int nn, const long long *q_bnd, const double *gm, long long tau_q, uint8_t *gamma,
-                        uint8_t *recv) {
+// Boundary node set Gamma (nodes whose boundary-layer mass exceeds tau) and
+// the receiver set before arbitration; the fixed-point accumulator is reset
+// for the next build.
+__global__ void k_gamma(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nn) return;
-  const uint8_t gsel = (q_bnd[i] > tau_q && gm[i] > 0.0) ? 1 : 0;
-  gamma[i] = gsel;
-  recv[i] = gsel;
+  if (i >= dm.g.nn) return;
+  const uint8_t gsel = (dm.q_bnd[i] > dm.tau_q && dm.m[i] > 0.0) ? 1 : 0;
+  dm.q_bnd[i] = 0;
+  dm.gamma[i] = gsel;
+  dm.recv[i] = gsel;
+}
+
+// Number of receiver nodes of each domain; one workgroup per domain.
+__global__ void k_count_recv(const DomDesc *dd, int *out) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  __shared__ double red[kBlock / 64];
+  double c = 0.0;
+  for (int i = threadIdx.x; i < dm.g.nn; i += kBlock) c += dm.recv[i] ? 1.0 : 0.0;
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) out[blockIdx.y] = (int)c;
 }
 
 // Overlap arbitration (Eq. overlap_donor): a coarse boundary node whose
 // lattice point is a fine boundary node is ambiguous; the larger fixed-point
 // node mass donates (ties: the coarse side) and leaves its receiver set.
 template <int D>
-__global__ void k_arbitrate(GridDev gB, GridDev gS, const uint8_t *gammaB, const uint8_t *gammaS,
-                            const long long *qB, const long long *qS, uint8_t *recvB, uint8_t *recvS, int *n_amb) {
+__global__ void k_arbitrate(const DomDesc *ddB, const DomDesc *ddS, int *n_amb) {
+  const DomDesc &B = ddB[blockIdx.y], &S = ddS[blockIdx.y];
+  if (!*B.active) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= gB.nn || !gammaB[I]) return;
+  if (I >= B.g.nn || !B.gamma[I]) return;
   int iB[3], jS[3];
-  node_unflat<D>(gB, I, iB);
+  node_unflat<D>(B.g, I, iB);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const long long L = gB.origin_q[a] + (long long)iB[a] * gB.dx_q;
-    const long long t = L - gS.origin_q[a];
-    if (t < 0 || t % gS.dx_q != 0 || t / gS.dx_q >= gS.n[a]) return;
-    jS[a] = (int)(t / gS.dx_q);
+    const long long L = B.g.origin_q[a] + (long long)iB[a] * B.g.dx_q;
+    const long long t = L - S.g.origin_q[a];
+    if (t < 0 || t % S.g.dx_q != 0 || t / S.g.dx_q >= S.g.n[a]) return;
+    jS[a] = (int)(t / S.g.dx_q);
   }
-  const int j = node_flat<D>(gS, jS);
-  if (!gammaS[j]) return;
-  atomicAdd(n_amb, 1);
-  if (qB[I] >= qS[j])
-    recvB[I] = 0;
+  const int j = node_flat<D>(S.g, jS);
+  if (!S.gamma[j]) return;
+  atomicAdd(&n_amb[blockIdx.y], 1);
+  if (B.q_all[I] >= S.q_all[j])
+    B.recv[I] = 0;
   else
-    recvS[j] = 0;
+    S.recv[j] = 0;
+}
+
+__global__ void k_zero_proj(const DomDesc *ddB) {
+  const DomDesc &B = ddB[blockIdx.y];
+  if (!*B.active) return;
+  const int stride = gridDim.x * blockDim.x;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < B.ndof; k += stride) B.pnum[k] = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B.g.nn; i += stride) B.pden[i] = 0.0;
 }
 
 // Pi_{S->B} numerator and denominator: every active fine node j scatters
-// m_j N_I(x_j) and m_j v_j N_I(x_j) onto its coarse stencil.
+// m_j N_I(x_j) and m_j v_j N_I(x_j) onto its coarse stencil.  The fine field
+// is S's P2G velocity unless an external array is given (a batch of one).
 template <int D>
-__global__ void k_project_scatter(GridDev gS, GridDev gB, const double *mS, const double *vS, double *num,
-                                  double *den, int *err) {
+__global__ void k_project_scatter(const DomDesc *ddS, const DomDesc *ddB, const double *vS_ext, int *err) {
+  const DomDesc &S = ddS[blockIdx.y], &B = ddB[blockIdx.y];
+  if (!*S.active) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= gS.nn) return;
-  const double m = mS[j];
+  if (j >= S.g.nn) return;
+  const double m = S.m[j];
   if (!(m > 0.0)) return;
+  const double *vS = vS_ext ? vS_ext : S.vn;
   int jS[3];
   double xj[D];
-  node_unflat<D>(gS, j, jS);
-  node_position<D>(gS, jS, xj);
+  node_unflat<D>(S.g, j, jS);
+  node_position<D>(S.g, jS, xj);
   Stencil<D> st;
-  if (!stencil_eval<D>(xj, gB, st)) {
+  if (!stencil_eval<D>(xj, B.g, st)) {
     atomicOr(err, kErrOutOfGrid);
     return;
   }
@@ -1190,40 +1486,49 @@ __global__ void k_project_scatter(GridDev gS, GridDev gB, const double *mS, cons
     stencil_offset<D>(s, k);
 #pragma unroll
     for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
-    const int I = node_flat<D>(gB, idx);
+    const int I = node_flat<D>(B.g, idx);
     const double w = m * stencil_N<D>(st, k);
-    atomicAdd(&den[I], w);
+    atomicAdd(&B.pden[I], w);
 #pragma unroll
-    for (int a = 0; a < D; ++a) atomicAdd(&num[I * D + a], w * vS[j * D + a]);
+    for (int a = 0; a < D; ++a) atomicAdd(&B.pnum[I * D + a], w * vS[j * D + a]);
   }
 }
 
+// out_I = num_I / (den_I + eps_tol) on coarse receivers, 0 elsewhere; out is
+// work buffer `which` of B, or out_ext when which < 0.
 template <int D>
-__global__ void k_project_final(int nn, const uint8_t *recv, const double *num, const double *den, double eps_tol,
-                                double *out) {
+__global__ void k_project_final(const DomDesc *ddB, double eps_tol, int which, double *out_ext) {
+  const DomDesc &B = ddB[blockIdx.y];
+  if (!*B.active) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
-  if (I >= nn) return;
-  const bool rc = recv[I];
+  if (I >= B.g.nn) return;
+  double *out = which < 0 ? out_ext : wbuf(B, which);
+  const bool rc = B.recv[I];
 #pragma unroll
-  for (int a = 0; a < D; ++a) out[I * D + a] = rc ? num[I * D + a] / (den[I] + eps_tol) : 0.0;
+  for (int a = 0; a < D; ++a) out[I * D + a] = rc ? B.pnum[I * D + a] / (B.pden[I] + eps_tol) : 0.0;
 }
 
-// I_{B->S} at the fine receivers (Eq. interp_BtoS).
+// I_{B->S} at the fine receivers (Eq. interp_BtoS): source is B's buffer src
+// (or vB_ext when src < 0), target S's buffer dst (or out_ext when dst < 0).
 template <int D>
-__global__ void k_interp(GridDev gB, GridDev gS, const double *mB, const double *vB, const uint8_t *recvS,
-                         double *out, int *err) {
+__global__ void k_interp(const DomDesc *ddB, const DomDesc *ddS, int src, const double *vB_ext, int dst,
+                         double *out_ext, int *err) {
+  const DomDesc &B = ddB[blockIdx.y], &S = ddS[blockIdx.y];
+  if (!*S.active) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= gS.nn) return;
+  if (j >= S.g.nn) return;
+  const double *vB = src < 0 ? vB_ext : wbuf(B, src);
+  double *out = dst < 0 ? out_ext : wbuf(S, dst);
   double acc[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) acc[a] = 0.0;
-  if (recvS[j]) {
+  if (S.recv[j]) {
     int jS[3];
     double xj[D];
-    node_unflat<D>(gS, j, jS);
-    node_position<D>(gS, jS, xj);
+    node_unflat<D>(S.g, j, jS);
+    node_position<D>(S.g, jS, xj);
     Stencil<D> st;
-    if (!stencil_eval<D>(xj, gB, st)) {
+    if (!stencil_eval<D>(xj, B.g, st)) {
       atomicOr(err, kErrOutOfGrid);
     } else {
 #pragma unroll
@@ -1232,8 +1537,8 @@ __global__ void k_interp(GridDev gB, GridDev gS, const double *mB, const double 
         stencil_offset<D>(s, k);
 #pragma unroll
         for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
-        const int I = node_flat<D>(gB, idx);
-        if (!(mB[I] > 0.0)) continue;
+        const int I = node_flat<D>(B.g, idx);
+        if (!(B.m[I] > 0.0)) continue;
         const double N = stencil_N<D>(st, k);
 #pragma unroll
         for (int a = 0; a < D; ++a) acc[a] += N * vB[I * D + a];
@@ -1244,30 +1549,50 @@ __global__ void k_interp(GridDev gB, GridDev gS, const double *mB, const double 
   for (int a = 0; a < D; ++a) out[j * D + a] = acc[a];
 }
 
-// T_m (Eq. temporal_interp).
-__global__ void k_temporal(int64_t n, double am, const double *vn, const double *vn1, double *out) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-    out[k] = (1.0 - am) * vn[k] + am * vn1[k];
+// T_m (Eq. temporal_interp) into the Schwarz data: v_bc = (1 - am) a + am b
+// for work buffers a, b.
+template <int D>
+__global__ void k_temporal(const DomDesc *dd, double am, int a_buf, int b_buf) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const double *a = wbuf(dm, a_buf), *b = wbuf(dm, b_buf);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += gridDim.x * blockDim.x)
+    dm.vbc[k] = (1.0 - am) * a[k] + am * b[k];
 }
 
-// v = u / dt on active nodes, 0 elsewhere.
+// w2 = u / dt on active nodes, 0 elsewhere (v_B^(k+1) of Eq. implicit_solve_coarse).
 template <int D>
-__global__ void k_vel_from_u(int nn, const double *gm, const double *u, double dt, double *v) {
+__global__ void k_vel_from_u(const DomDesc *dd, double dt) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nn) return;
-  const bool act = gm[i] > 0.0;
+  if (i >= dm.g.nn) return;
+  const bool act = dm.m[i] > 0.0;
 #pragma unroll
-  for (int a = 0; a < D; ++a) v[i * D + a] = act ? u[i * D + a] / dt : 0.0;
+  for (int a = 0; a < D; ++a) dm.w2[i * D + a] = act ? dm.u[i * D + a] / dt : 0.0;
+}
+
+// v_bc = work buffer src.
+template <int D>
+__global__ void k_copy_vbc(const DomDesc *dd, int src) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const double *s = wbuf(dm, src);
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += gridDim.x * blockDim.x) dm.vbc[k] = s[k];
 }
 
 // Partial sums over receiver nodes of |a - b|^2 and |a|^2 (Eq.
-// convergence_residuals).
+// convergence_residuals) into part_b[2 block], part_b[2 block + 1].
 template <int D>
-__global__ void k_resid(int nn, const uint8_t *recv, const double *a, const double *b, double *part) {
-  __shared__ double red[kBlock / 64];
+__global__ void k_resid(const DomDesc *dd, int a_buf, int b_buf) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const int nb = node_blocks(dm.g.nn);
+  if (!*dm.active || (int)blockIdx.x >= nb) return;
+  __shared__ double red[8];
+  const double *a = wbuf(dm, a_buf), *b = wbuf(dm, b_buf);
   double s = 0.0, t = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += gridDim.x * blockDim.x) {
-    if (!recv[i]) continue;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < dm.g.nn; i += nb * kBlock) {
+    if (!dm.recv[i]) continue;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
       const double e = a[i * D + c] - b[i * D + c];
@@ -1275,59 +1600,60 @@ __global__ void k_resid(int nn, const uint8_t *recv, const double *a, const doub
       t += a[i * D + c] * a[i * D + c];
     }
   }
-  const double x1 = block_sum(s, red);
-  const double x2 = block_sum(t, red);
+  block_sum2(s, t, red);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = x1;
-    part[2 * blockIdx.x + 1] = x2;
+    dm.part_b[2 * blockIdx.x] = s;
+    dm.part_b[2 * blockIdx.x + 1] = t;
+  }
+}
+
+// Sums of the residual partials of each domain into out[2 y], out[2 y + 1];
+// one workgroup per domain.
+__global__ void k_resid_final(const DomDesc *dd, double *out) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  __shared__ double red[8];
+  const int nb = node_blocks(dm.g.nn);
+  double s = 0.0, t = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+    s += dm.part_b[2 * i];
+    t += dm.part_b[2 * i + 1];
+  }
+  block_sum2(s, t, red);
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.y] = s;
+    out[2 * blockIdx.y + 1] = t;
   }
 }
 
 // ====================================================================== instantiations
-#define OSMPM_INST_D(D)                                                                                            \
-  template __global__ void k_keys<D>(int, const double *, int64_t, GridDev, TileGeom, int *, int *, int *);        \
-  template __global__ void k_p2g_final<D>(GridDev, const double *, double *, const long long *, SceneBC,          \
-                                          long long, int8_t *);                                                    \
-  template __global__ void k_bc_init<D>(GridDev, const double *, const double *, const int8_t *, const uint8_t *, \
-                                        const double *, int, SceneBC, double, uint8_t *, double *, double *);     \
-  template __global__ void k_qbnd<D>(int, GridDev, const double *, const double *, const uint8_t *, int64_t,       \
-                                     double, long long *);                                                         \
-  template __global__ void k_arbitrate<D>(GridDev, GridDev, const uint8_t *, const uint8_t *, const long long *,   \
-                                          const long long *, uint8_t *, uint8_t *, int *);                        \
-  template __global__ void k_project_scatter<D>(GridDev, GridDev, const double *, const double *, double *,       \
-                                                double *, int *);                                                  \
-  template __global__ void k_project_final<D>(int, const uint8_t *, const double *, const double *, double,       \
-                                              double *);                                                           \
-  template __global__ void k_interp<D>(GridDev, GridDev, const double *, const double *, const uint8_t *,         \
-                                       double *, int *);                                                           \
-  template __global__ void k_vel_from_u<D>(int, const double *, const double *, double, double *);                 \
-  template __global__ void k_resid<D>(int, const uint8_t *, const double *, const double *, double *);
+#define OSMPM_INST_D(D)                                                                                  \
+  template __global__ void k_keys<D>(const DomDesc *, int *);                                            \
+  template __global__ void k_p2g_final<D>(const DomDesc *);                                              \
+  template __global__ void k_qbnd<D>(const DomDesc *);                                                   \
+  template __global__ void k_arbitrate<D>(const DomDesc *, const DomDesc *, int *);                      \
+  template __global__ void k_project_scatter<D>(const DomDesc *, const DomDesc *, const double *, int *); \
+  template __global__ void k_project_final<D>(const DomDesc *, double, int, double *);                   \
+  template __global__ void k_interp<D>(const DomDesc *, const DomDesc *, int, const double *, int, double *, \
+                                       int *);                                                           \
+  template __global__ void k_temporal<D>(const DomDesc *, double, int, int);                                       \
+  template __global__ void k_vel_from_u<D>(const DomDesc *, double);                                     \
+  template __global__ void k_resid<D>(const DomDesc *, int, int);                                        \
+  template __global__ void k_copy_vbc<D>(const DomDesc *, int);
 
-#define OSMPM_INST_DT(D, TB)                                                                                       \
-  template __global__ void k_p2g<D, TB>(TileGeom, GridDev, const int *, const double *, const TB *, const TB *,    \
-                                        const double *, const uint8_t *, int64_t, int, double, double, int,       \
-                                        double *, double *, long long *, long long *, int *);                     \
-  template __global__ void k_g2p<D, TB>(int, GridDev, const double *, const double *, double, double *, TB *,      \
-                                        TB *, TB *, int64_t, int *);                                               \
-  template __global__ void k_grad_hess<D, TB>(TileGeom, GridDev, const int *, const double *, const TB *,          \
-                                              const double *, const int *, const double *, const double *,        \
-                                              int64_t, const double *, int, int, double *, TB *, TB *, int *);    \
-  template __global__ void k_grad_node<D, TB>(GridDev, const double *, const double *, const double *,            \
-                                              const uint8_t *, double, double, double, double, double *, TB *,    \
-                                              int, double *);                                                      \
-  template __global__ void k_cg_init<D, TB>(int, const double *, const TB *, const uint8_t *, TB *, TB *, TB *,    \
-                                            TB *, TB *, TB *, double *, double *, CgState *);                     \
-  template __global__ void k_cg_hvp<D, TB>(TileGeom, GridDev, const int *, const double *, const TB *, int64_t,    \
-                                           const double *, double, int, const TB *, TB *, TB *, TB *,             \
-                                           const double *, const double *, int, double, int, double *, CgState *); \
-  template __global__ void k_cg_update<D, TB>(int, const double *, double, const uint8_t *, const TB *,           \
-                                              const TB *, const TB *, TB *, TB *, TB *, TB *, const double *,     \
-                                              int, double *, double *, CgState *);                                \
-  template __global__ void k_delta_energy_p<D, TB>(int, GridDev, const double *, const TB *, const double *,       \
-                                                   const int *, const double *, const double *, int64_t,          \
-                                                   const double *, const TB *, double, double *);                 \
-  template __global__ void k_delta_energy_n<D, TB>(GridDev, const double *, const double *, const double *,       \
-                                                   const TB *, double, double, double, double, double, double *);
+#define OSMPM_INST_DT(D, TB)                                                                    \
+  template __global__ void k_gather_all<D, TB>(const DomDesc *);                                \
+  template __global__ void k_bc_init<D, TB>(const DomDesc *, double, int, int);                      \
+  template __global__ void k_copy_state<D, TB>(const DomDesc *, int);                           \
+  template __global__ void k_p2g<D, TB>(const DomDesc *, int, int *);                           \
+  template __global__ void k_g2p<D, TB>(const DomDesc *, double, int *);                        \
+  template __global__ void k_grad_hess<D, TB>(const DomDesc *, int, int *);                     \
+  template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \
+  template __global__ void k_cg_init<D, TB>(const DomDesc *);                                   \
+  template __global__ void k_cg_hvp<D, TB>(const DomDesc *, double, double, int);               \
+  template __global__ void k_cg_update<D, TB>(const DomDesc *, double);                         \
+  template __global__ void k_delta_energy_p<D, TB>(const DomDesc *);                            \
+  template __global__ void k_delta_energy_n<D, TB>(const DomDesc *, double, double, double, double);
 
 OSMPM_INST_D(2)
 OSMPM_INST_D(3)
@@ -1335,5 +1661,7 @@ OSMPM_INST_DT(2, double)
 OSMPM_INST_DT(2, float)
 OSMPM_INST_DT(3, double)
 OSMPM_INST_DT(3, float)
+template __global__ void k_newton_step<double>(const DomDesc *);
+template __global__ void k_newton_step<float>(const DomDesc *);
 
 }  // namespace osmpm

@@ -1,4 +1,11 @@
-// Kernel declarations shared by kernels.hip and the host orchestration.
+// Kernel interface shared by kernels.hip and the host orchestration.
+//
+// Every kernel runs over a batch of domains in one launch: blockIdx.y is the
+// domain's index in the batch and a device array of DomDesc describes each
+// domain (grid, tiles, buffers).  Domains of uneven size share a launch;
+// blocks beyond a domain's own range exit at once, and a domain whose
+// `active` flag is clear (or whose solve phase is finished) skips the launch.
+// A single domain is a batch of one.
 #pragma once
 
 #include "device.hpp"
@@ -13,96 +20,172 @@ struct CgState {
   double rr0;
   double pad;
   int iter;   // completed updates
-  int done;   // converged, broke down or hit max_cg
+  int done;   // converged, broke down, hit max_cg, or not solving
   int knext;  // index of the next iteration (written by the update kernel)
   int kcur;   // index of the running iteration (written by the product kernel)
 };
 
+// Phases of one domain's implicit solve.  The decision kernels move a domain
+// through them on the device; every other solve kernel runs only for domains
+// in its phase, so the host can queue a fixed cycle of launches for a whole
+// batch and read the states once per cycle.
+enum : int {
+  kPhaseDone = 0,    // converged, stopped, or not solving
+  kPhaseGrad = 1,    // gradient and tangents wanted at the current iterate
+  kPhaseCgInit = 2,  // Newton continues: CG to be initialised
+  kPhaseCg = 3,      // CG iterating
+  kPhaseLs = 4,      // line search on the CG direction
+  kPhaseStep = 5,    // step accepted: apply it, then the gradient again
+};
+
+// Newton / line-search state of one domain's implicit solve.
+struct SolveState {
+  double gnorm0, gnorm, gscale, alpha, dE;
+  int it;  // Newton iteration index
+  int phase;
+  int ls_count;
+  int converged, ls_failed;
+  int newton_iters, cg_iters, ls_halvings;
+};
+
+__host__ __device__ inline bool phase_wants_grad(int ph) { return ph == kPhaseGrad || ph == kPhaseStep; }
+
+// Bit set of up to 1024 domains, passed by value to set batch flags.
+struct FlagMask {
+  uint64_t w[16];
+};
+
+// One particle buffer (component-major [rows][capacity]); v, B, F are in
+// the domain's bulk type.
+struct PartPtrs {
+  double *x, *mass, *vol;
+  void *v, *B, *F;
+  int *mat, *id;
+  uint8_t *flags;
+};
+
+struct DomDesc {
+  GridDev g;
+  TileGeom tg;
+  SceneBC bc;
+  int np, ndof, nk;
+  int64_t cap;
+  double scale;     // 2^32 / m_ref
+  long long tau_q;  // selection threshold in fixed point
+  double Dinv;      // 4 / dx^2
+  int *cur;         // index of the current particle buffer (domain-owned)
+  int *active;      // takes part in batched launches (batch-owned)
+  SolveState *ss;   // solve state (batch-owned)
+  PartPtrs pb[2], st;
+  int *key, *count, *cell_start, *cursor, *perm;
+  const double *mu, *lam;
+  double *m, *vn, *u, *vbc, *gg;
+  int8_t *bcg;
+  uint8_t *gamma, *recv, *fr;
+  long long *q_all, *q_bnd, *qg;
+  void *gd, *r, *z, *p0, *p1, *del, *Hp, *Atil;
+  CgState *cg;
+  double *part_a, *part_b, *part_q, *part_rz, *part_rr;  // per-block partial sums (batch-owned)
+  double *pnum, *pden, *w0, *w1, *w2, *w3;                // interface work buffers
+};
+
+// Blocks a grid-stride node kernel uses for a domain (also the number of
+// partial sums it writes).
+__host__ __device__ inline int node_blocks(int ndof) {
+  int b = (ndof + kBlock - 1) / kBlock;
+  return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
 template <typename T>
 __global__ void k_fill(int64_t n, T v, T *a);
-__global__ void k_fill_i64(int64_t n, long long *a);
-__global__ void k_fill_i32(int64_t n, int v, int *a);
-__global__ void k_fill_u8(int64_t n, uint8_t *a);
 template <typename T>
 __global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap);
 template <typename T>
 __global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst);
 __global__ void k_iota(int n, int *a);
+__global__ void k_set_flags(int *flags, int n, FlagMask m);
+__global__ void k_temporal_1(int64_t n, double am, const double *vn, const double *vn1, double *out);
 
+// binning
 template <int D>
-__global__ void k_keys(int n, const double *x, int64_t cap, GridDev g, TileGeom tg, int *key, int *count, int *err);
-__global__ void k_scan(int nk, const int *count, int *cell_start, int *cursor);
-__global__ void k_scatter(int n, const int *key, int *cursor, int *perm);
-__global__ void k_cellsort(int nk, const int *cell_start, int *perm);
-template <typename T>
-__global__ void k_gather(int n, int rows, const int *perm, const T *src, T *dst, int64_t cap);
+__global__ void k_keys(const DomDesc *dd, int *err);
+__global__ void k_scan(const DomDesc *dd);
+__global__ void k_scatter(const DomDesc *dd);
+__global__ void k_cellsort(const DomDesc *dd);
+template <int D, typename TB>
+__global__ void k_gather_all(const DomDesc *dd);
+__global__ void k_flip(const DomDesc *dd, int ndom);
+template <int D, typename TB>
+__global__ void k_copy_state(const DomDesc *dd, int to_store);
+__global__ void k_zero_grid(const DomDesc *dd, int want_q);
 
+// transfers
 template <int D, typename TB>
-__global__ void k_p2g(TileGeom tg, GridDev g, const int *cell_start, const double *x, const TB *v, const TB *B,
-                      const double *mass, const uint8_t *flags, int64_t cap, int n_groups, double scale, double Dinv,
-                      int want_q, double *gm, double *gmv, long long *q_all, long long *qg, int *err);
+__global__ void k_p2g(const DomDesc *dd, int want_q, int *err);
 template <int D>
-__global__ void k_p2g_final(GridDev g, const double *gm, double *gv, const long long *qg, SceneBC bc,
-                            long long tau_q, int8_t *bcg);
+__global__ void k_p2g_final(const DomDesc *dd);
 template <int D, typename TB>
-__global__ void k_g2p(int n, GridDev g, const double *gm, const double *u, double dt, double *x, TB *v, TB *B, TB *F,
-                      int64_t cap, int *err);
+__global__ void k_g2p(const DomDesc *dd, double dt, int *err);
 
-template <int D>
-__global__ void k_bc_init(GridDev g, const double *gm, const double *gv, const int8_t *bcg, const uint8_t *recv,
-                          const double *vbc, int use_schwarz, SceneBC bc, double dt, uint8_t *fr, double *u,
-                          double *part_m);
+// implicit solve
 template <int D, typename TB>
-__global__ void k_grad_hess(TileGeom tg, GridDev g, const int *cell_start, const double *x, const TB *F,
-                            const double *vol, const int *mat, const double *mu_t, const double *lam_t, int64_t cap,
-                            const double *u, int want_hess, int project, double *gg, TB *gdiag, TB *Atil, int *err);
+__global__ void k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf);
+__global__ void k_solve_begin(const DomDesc *dd, double dt);
 template <int D, typename TB>
-__global__ void k_grad_node(GridDev g, const double *gm, const double *gv, const double *u, const uint8_t *fr,
-                            double dt, double gx, double gy, double gz, double *gg, TB *gdiag, int want_hess,
-                            double *part);
+__global__ void k_grad_hess(const DomDesc *dd, int project, int *err);
 template <int D, typename TB>
-__global__ void k_cg_init(int ndof, const double *gg, const TB *gdiag, const uint8_t *fr, TB *r, TB *z, TB *p0,
-                          TB *p1, TB *del, TB *Hp, double *part_rz, double *part_rr, CgState *S);
+__global__ void k_grad_node(const DomDesc *dd, double dt, double gx, double gy, double gz);
+__global__ void k_newton_check(const DomDesc *dd, double rtol, double atol, int max_newton);
 template <int D, typename TB>
-__global__ void k_cg_hvp(TileGeom tg, GridDev g, const int *cell_start, const double *x, const TB *Atil, int64_t cap,
-                         const double *gm, double dt, int ndof, const TB *z, TB *pA, TB *pB, TB *Hp,
-                         const double *part_rz, const double *part_rr, int n_part, double rtol, int max_cg,
-                         double *part_q, CgState *S);
+__global__ void k_cg_init(const DomDesc *dd);
 template <int D, typename TB>
-__global__ void k_cg_update(int ndof, const double *gm, double dt, const uint8_t *fr, const TB *gdiag, const TB *pA,
-                            const TB *pB, TB *Hp, TB *r, TB *z, TB *del, const double *part_q, int n_q,
-                            double *part_rz, double *part_rr, CgState *S);
+__global__ void k_cg_hvp(const DomDesc *dd, double dt, double rtol, int max_cg);
 template <int D, typename TB>
-__global__ void k_delta_energy_p(int np, GridDev g, const double *x, const TB *F, const double *vol, const int *mat,
-                                 const double *mu_t, const double *lam_t, int64_t cap, const double *u, const TB *del,
-                                 double alpha, double *part);
+__global__ void k_cg_update(const DomDesc *dd, double dt);
+__global__ void k_ls_begin(const DomDesc *dd, int ndom);
 template <int D, typename TB>
-__global__ void k_delta_energy_n(GridDev g, const double *gm, const double *gv, const double *u, const TB *del,
-                                 double dt, double alpha, double gx, double gy, double gz, double *part);
+__global__ void k_delta_energy_p(const DomDesc *dd);
+template <int D, typename TB>
+__global__ void k_delta_energy_n(const DomDesc *dd, double dt, double gx, double gy, double gz);
+__global__ void k_ls_check(const DomDesc *dd, int max_ls);
 template <typename TB>
-__global__ void k_axpy(int n, double alpha, const TB *xv, double *y);
+__global__ void k_newton_step(const DomDesc *dd);
 
+// interface
 template <int D>
-__global__ void k_qbnd(int np, GridDev g, const double *x, const double *mass, const uint8_t *flags, int64_t cap,
-                       double scale, long long *q_bnd);
-__global__ void k_gamma(int nn, const long long *q_bnd, const double *gm, long long tau_q, uint8_t *gamma,
-                        uint8_t *recv);
+__global__ void k_qbnd(const DomDesc *dd);
+__global__ void k_gamma(const DomDesc *dd);
+__global__ void k_count_recv(const DomDesc *dd, int *out);
 template <int D>
-__global__ void k_arbitrate(GridDev gB, GridDev gS, const uint8_t *gammaB, const uint8_t *gammaS,
-                            const long long *qB, const long long *qS, uint8_t *recvB, uint8_t *recvS, int *n_amb);
+__global__ void k_arbitrate(const DomDesc *ddB, const DomDesc *ddS, int *n_amb);
+__global__ void k_zero_proj(const DomDesc *ddB);
 template <int D>
-__global__ void k_project_scatter(GridDev gS, GridDev gB, const double *mS, const double *vS, double *num,
-                                  double *den, int *err);
+__global__ void k_project_scatter(const DomDesc *ddS, const DomDesc *ddB, const double *vS_ext, int *err);
 template <int D>
-__global__ void k_project_final(int nn, const uint8_t *recv, const double *num, const double *den, double eps_tol,
-                                double *out);
+__global__ void k_project_final(const DomDesc *ddB, double eps_tol, int which, double *out_ext);
 template <int D>
-__global__ void k_interp(GridDev gB, GridDev gS, const double *mB, const double *vB, const uint8_t *recvS,
-                         double *out, int *err);
-__global__ void k_temporal(int64_t n, double am, const double *vn, const double *vn1, double *out);
+__global__ void k_interp(const DomDesc *ddB, const DomDesc *ddS, int src, const double *vB_ext, int dst,
+                         double *out_ext, int *err);
 template <int D>
-__global__ void k_vel_from_u(int nn, const double *gm, const double *u, double dt, double *v);
+__global__ void k_temporal(const DomDesc *dd, double am, int a_buf, int b_buf);
 template <int D>
-__global__ void k_resid(int nn, const uint8_t *recv, const double *a, const double *b, double *part);
+__global__ void k_vel_from_u(const DomDesc *dd, double dt);
+template <int D>
+__global__ void k_resid(const DomDesc *dd, int a_buf, int b_buf);
+template <int D>
+__global__ void k_copy_vbc(const DomDesc *dd, int src);
+__global__ void k_resid_final(const DomDesc *dd, double *out);
+
+// Work buffer selector of the interface kernels.
+__device__ inline double *wbuf(const DomDesc &D, int k) {
+  switch (k) {
+    case 0: return D.w0;
+    case 1: return D.w1;
+    case 2: return D.w2;
+    case 3: return D.w3;
+    case 4: return D.vn;
+    default: return D.vbc;
+  }
+}
 
 }  // namespace osmpm

@@ -38,4 +38,4 @@ def test_binding_declares_signatures():
         pytest.skip("library not built")
     L = binding.lib()
     for s in binding.ABI_SYMBOLS:
-        assert getattr(L, s).restype is not None or s in ("osmpm_ctx_destroy", "osmpm_domain_destroy")
+        assert getattr(L, s).restype is not None or s in ("osmpm_ctx_destroy", "osmpm_domain_destroy", "osmpm_batch_destroy")

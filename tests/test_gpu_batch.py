@@ -1,0 +1,170 @@
+"""GPU parity of batched execution: many scenes of uneven sizes in shared
+launches, each checked against the FP64 CPU oracle run on that scene alone.
+
+A batch gives every scene its own Newton / CG / line-search / Schwarz
+decisions, so per-scene iteration counts must equal the oracle's and the
+per-scene results must meet the same bars as single-scene runs (1e-10
+relative for the FP64 path, 1e-5 for the mixed path).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09097_amd import binding
+
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _batch_scenes():
+    """Three inclusion scenes with different grids, radii, moduli and jitter
+    seeds (particle counts from ~1.7k to ~4k per scene)."""
+    from paper_2605_09097_amd import scenes
+
+    d = scenes.INCLUSION_DELTA
+    return [scenes.inclusion_scene(20, 50, r_inc=0.04, E_inc=3e4, seed=11, delta=d, name="b0"),
+            scenes.inclusion_scene(30, 60, r_inc=0.07, E_inc=1.5e5, seed=12, delta=d, name="b1"),
+            scenes.inclusion_scene(20, 40, r_inc=0.05, E_inc=8e4, seed=13, delta=d, name="b2")]
+
+
+def _oracle_frames(sc, n_frames):
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    stats = []
+    for f in range(n_frames):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        stats.append(oracle.schwarz_frame(OB, OS, sc.dT, oo))
+    return OB, OS, stats
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_schwarz_matches_oracle(ctx, precision):
+    from paper_2605_09097_amd import binding as b
+
+    scs = _batch_scenes()
+    n_frames = 2
+    if precision == "fp64":
+        prec, tol, so = b.OSMPM_FP64, FP64_TOL, b.solve_opts()
+    else:
+        prec, tol, so = b.OSMPM_MIXED, MIXED_TOL, b.solve_opts(cg_rtol=1e-5)
+    opts = b.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol, coarse=so, fine=so)
+    # A batch shares one projection regulariser eps_tol; each scene's oracle
+    # run uses the same value.
+    print("batch of %d scenes, %s, %d frames" % (len(scs), precision, n_frames), flush=True)
+    batch = b.SchwarzBatch(ctx, scs, precision=prec)
+    gstats = [batch.frame(opts) for _ in range(n_frames)]
+    for i, sc in enumerate(scs):
+        OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+        oo = oracle.schwarz_opts(sc.M, eps_tol=scs[0].eps_tol)
+        for f in range(n_frames):
+            pB, pS = sc.bc_params(f)
+            OB.set_bc_params(pB)
+            OS.set_bc_params(pS)
+            ost = oracle.schwarz_frame(OB, OS, sc.dT, oo)
+            gst = gstats[f][i]
+            assert gst.iters == ost.iters
+            assert gst.converged == ost.converged
+            assert (gst.n_recv_B, gst.n_recv_S, gst.n_amb) == (ost.n_recv_B, ost.n_recv_S, ost.n_amb)
+            if precision == "fp64":
+                assert gst.newton_B == ost.newton_B and gst.newton_S == ost.newton_S
+        pair = batch.pairs[i]
+        for Dg, Do, spec in ((pair.B, OB, sc.B), (pair.S, OS, sc.S)):
+            _, _, u = Dg.grid_state()
+            x, _, _, F = Dg.particles_input_order()
+            assert rel_err(u.cpu().numpy(), Do.u) < tol, (i, spec.dim)
+            assert rel_err(x - spec.x, Do.x - spec.x) < tol
+            if precision == "fp64":
+                assert rel_err(F - np.eye(2), Do.F - np.eye(2)) < tol
+            else:
+                # F is stored in FP32 in the mixed path: entries of order one
+                # carry ~6e-8 storage rounding, so (F - I) has no 1e-5 relative
+                # meaning at small strain; bound the entries instead.
+                assert np.abs(F - Do.F).max() < 1e-6
+    batch.close()
+
+
+def test_batch_equals_single_pair_runs(ctx):
+    """Each scene of a batch reproduces its own single-pair GPU run: same
+    Schwarz, Newton and CG counts, displacements equal to rounding."""
+    from paper_2605_09097_amd import binding as b
+
+    scs = _batch_scenes()
+    opts = b.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol)
+    batch = b.SchwarzBatch(ctx, scs)
+    bst = [batch.frame(opts) for _ in range(2)]
+    for i, sc in enumerate(scs):
+        pair = b.SchwarzPair(ctx, sc)
+        for f in range(2):
+            st = pair.frame(opts)
+            g = bst[f][i]
+            assert (st.iters, st.newton_B, st.newton_S) == (g.iters, g.newton_B, g.newton_S)
+            assert abs(st.cg_B - g.cg_B) <= 2 and abs(st.cg_S - g.cg_S) <= 2
+        for Dp, Db in ((pair.B, batch.pairs[i].B), (pair.S, batch.pairs[i].S)):
+            ua = Dp.grid_state()[2].cpu().numpy()
+            ub = Db.grid_state()[2].cpu().numpy()
+            assert rel_err(ub, ua) < 1e-12
+        pair.close()
+    batch.close()
+
+
+def test_batch_single_frames(ctx):
+    """A batch of single domains of different sizes (single_frame) against
+    the oracle's single-domain step on each."""
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    scs = [scenes.inclusion_single(inv_dx=40, n_frames=3, delta=0.01),
+           scenes.inclusion_single(inv_dx=24, n_frames=3, delta=0.01, seed=5)]
+    doms = [b.Domain(ctx, sc.B) for sc in scs]
+    orc = [oracle.Domain(sc.B) for sc in scs]
+    batch = b.Batch(ctx, doms)
+    for f in range(2):
+        for sc, D, O in zip(scs, doms, orc):
+            p, _ = sc.bc_params(f)
+            D.set_bc_params(p)
+            O.set_bc_params(p)
+        st = batch.single_frame(scs[0].dT, b.solve_opts())
+        for i, O in enumerate(orc):
+            ost = O.single_frame(scs[i].dT, oracle.solve_opts())
+            assert st[i].newton_iters == ost.newton_iters
+            assert st[i].converged == ost.converged
+    for sc, D, O in zip(scs, doms, orc):
+        u = D.grid_state()[2].cpu().numpy()
+        x = D.particles_input_order()[0]
+        assert rel_err(u, O.u) < FP64_TOL
+        assert rel_err(x - sc.B.x, O.x - sc.B.x) < FP64_TOL
+    batch.close()
+    for D in doms:
+        D.close()
+
+
+def test_batch_rejects_bad_members(ctx):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("inclusion_tiny")
+    B = b.Domain(ctx, sc.B)
+    S = b.Domain(ctx, sc.S)
+    with pytest.raises(b.OsmpmError):
+        b.Batch(ctx, [B, B], [S, S])
+    Sm = b.Domain(ctx, sc.S, precision=b.OSMPM_MIXED)
+    with pytest.raises(b.OsmpmError):
+        b.Batch(ctx, [B], [Sm])
+    for D in (B, S, Sm):
+        D.close()
