@@ -151,7 +151,7 @@ def main():
         pair.frame(opts)
     torch.cuda.synchronize()
     elapsed_prof = time.perf_counter() - t1
-    for kid, name in ((binding.OSMPM_K_CG_PRODUCT, "cg_product"), (binding.OSMPM_K_CG_UPDATE, "cg_update"),
+    for kid, name in ((binding.OSMPM_K_CG_ITER, "cg_iter"),
                       (binding.OSMPM_K_P2G, "p2g"), (binding.OSMPM_K_G2P, "g2p"),
                       (binding.OSMPM_K_GRAD_HESS, "grad_hess")):
         n, ms, by = ctx.profile_query(kid)
@@ -197,12 +197,12 @@ def main():
                    "schwarz_iters_mean": float(np.mean(iters)),
                    "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
                    "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats]))},
-        "roofline": ({"bound": "hbm", "kernel": "k_cg_hvp (CG Hessian-vector product)",
-                      "achieved": kern["cg_product"]["achieved_GBps"], "peak": 8000.0, "unit": "GB/s",
-                      "frac": kern["cg_product"]["frac_hbm"], "traffic": counter_traffic(),
-                      "avg_us": kern["cg_product"]["avg_us"],
-                      "bytes_per_launch": kern["cg_product"]["bytes_per_launch"]}
-                     if "cg_product" in kern else None),
+        "roofline": ({"bound": "hbm", "kernel": "k_cg_iter (CG iteration with the Hessian-vector product)",
+                      "achieved": kern["cg_iter"]["achieved_GBps"], "peak": 8000.0, "unit": "GB/s",
+                      "frac": kern["cg_iter"]["frac_hbm"], "traffic": counter_traffic(),
+                      "avg_us": kern["cg_iter"]["avg_us"],
+                      "bytes_per_launch": kern["cg_iter"]["bytes_per_launch"]}
+                     if "cg_iter" in kern else None),
         "kernels": kern,
         "profiled_pass_ms_per_step": 1e3 * elapsed_prof / max(1, args.profile_steps if args.profile_steps > 0
                                                                else args.steps),

@@ -63,12 +63,12 @@ typedef enum { OSMPM_BC_FIX = 0, OSMPM_BC_TRANSLATE = 1, OSMPM_BC_ROTATE = 2 } o
 
 /* Instrumented kernels (osmpm_profile_query). */
 typedef enum {
-  OSMPM_K_CG_PRODUCT = 0, /* CG Hessian-vector product through the particles */
-  OSMPM_K_CG_UPDATE = 1,  /* CG vector update and dot products */
-  OSMPM_K_P2G = 2,        /* APIC particle-to-grid */
-  OSMPM_K_G2P = 3,        /* APIC grid-to-particle, F update, advection */
-  OSMPM_K_GRAD_HESS = 4,  /* gradient and per-particle tangent build */
-  OSMPM_K_COUNT = 5
+  OSMPM_K_CG_ITER = 0,   /* one CG iteration: vector updates, Hessian-vector product
+                             through the particles and the inner products */
+  OSMPM_K_P2G = 1,       /* APIC particle-to-grid */
+  OSMPM_K_G2P = 2,       /* APIC grid-to-particle, F update, advection */
+  OSMPM_K_GRAD_HESS = 3, /* gradient and per-particle tangent build */
+  OSMPM_K_COUNT = 4
 } osmpm_kernel;
 
 typedef struct osmpm_ctx osmpm_ctx;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libosmpm.so")
 OSMPM_OK, OSMPM_E_INVALID_ARG, OSMPM_E_NO_MEMORY, OSMPM_E_DEVICE = 0, 1, 2, 3
 OSMPM_E_OUT_OF_GRID, OSMPM_E_INVERTED, OSMPM_E_STATE = 4, 5, 7
 OSMPM_FP64, OSMPM_MIXED = 0, 1
-OSMPM_K_CG_PRODUCT, OSMPM_K_CG_UPDATE, OSMPM_K_P2G, OSMPM_K_G2P, OSMPM_K_GRAD_HESS = 0, 1, 2, 3, 4
+OSMPM_K_CG_ITER, OSMPM_K_P2G, OSMPM_K_G2P, OSMPM_K_GRAD_HESS = 0, 1, 2, 3
 
 # Every symbol the header declares (checked by the CPU test suite).
 ABI_SYMBOLS = [

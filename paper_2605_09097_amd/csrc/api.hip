@@ -50,6 +50,9 @@ struct ProfSlot {
 
 // Work buffer indices understood by the kernels (see wbuf).
 constexpr int kBufVn = 4, kBufVbc = 5;
+// Partial-sum arrays per domain: two scalar reductions and the CG's three
+// inner products at two parities.
+constexpr int kPartArrays = 8;
 
 }  // namespace
 
@@ -95,7 +98,7 @@ struct osmpm_domain {
   int8_t *bcg = nullptr;
   uint8_t *gamma = nullptr, *recv = nullptr, *fr = nullptr;
   long long *q_all = nullptr, *q_bnd = nullptr, *qg = nullptr;
-  void *gd = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *del = nullptr, *Hp = nullptr,
+  void *gd = nullptr, *cr[2] = {}, *cs[2] = {}, *cw[3] = {}, *cu = nullptr, *cp = nullptr, *del = nullptr,
        *Atil = nullptr;
   double *pnum = nullptr, *pden = nullptr, *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
   int cg_hint = 8;  // iterations of the last CG solve (sizes the next batch of launches)
@@ -243,10 +246,9 @@ void prof_harvest(osmpm_ctx *c, int cg_useful = 1 << 30) {
 double alg_bytes(int which, int D, double np, double nn, double tb) {
   const double ns = (D * D) * (D * D + 1) / 2.0;
   switch (which) {
-    case OSMPM_K_CG_PRODUCT:  // x, Atil per particle; z, p_prev, p_cur, Hp (rmw) per DOF, mass per node
-      return np * (8.0 * D + tb * ns) + nn * (tb * 5.0 * D + 8.0);
-    case OSMPM_K_CG_UPDATE:  // Hp (read, clear), p, r (rmw), z, del (rmw), diag per DOF + mask; mass per node
-      return nn * (D * (tb * 8.0 + 1.0) + 8.0);
+    case OSMPM_K_CG_ITER:  // x, Atil per particle; per DOF r, w, s, u, p, del, diag and the mask read,
+                           // p, s, r, u, del written, one w cleared, w accumulated (rmw); mass per node
+      return np * (8.0 * D + tb * ns) + nn * (D * (tb * 15.0 + 1.0) + 8.0);
     case OSMPM_K_P2G:  // x, mass, flags; v, B per particle; mass and momentum (rmw) per node
       return np * (8.0 * (D + 1.0) + tb * (D + D * D) + 1.0) + nn * 16.0 * (1.0 + D);
     case OSMPM_K_G2P:  // x read and written, F read; v, B, F written; u and mass gathered per node
@@ -359,7 +361,7 @@ osmpm_status group_create(osmpm_ctx *c, int n, osmpm_domain *const *side0, osmpm
     if (!s) s = dalloc_bytes(c, G->allocs, &p, sizeof(int) * n);
     G->active[sd] = static_cast<int *>(p);
   }
-  if (!s) s = dalloc_bytes(c, G->allocs, &p, sizeof(double) * (size_t)G->stride * 5 * 2 * n);
+  if (!s) s = dalloc_bytes(c, G->allocs, &p, sizeof(double) * (size_t)G->stride * kPartArrays * 2 * n);
   G->parts = static_cast<double *>(p);
   if (!s && hipMemsetAsync(G->status, 0, G->status_bytes, c->stream) != hipSuccess)
     s = fail(c, OSMPM_E_DEVICE, "hipMemsetAsync failed");
@@ -409,12 +411,14 @@ DomDesc make_desc(const osmpm_domain *d) {
   x.q_bnd = d->q_bnd;
   x.qg = d->qg;
   x.gd = d->gd;
-  x.r = d->r;
-  x.z = d->z;
-  x.p0 = d->p0;
-  x.p1 = d->p1;
+  for (int k = 0; k < 2; ++k) {
+    x.cr[k] = d->cr[k];
+    x.cs[k] = d->cs[k];
+  }
+  for (int k = 0; k < 3; ++k) x.cw[k] = d->cw[k];
+  x.cu = d->cu;
+  x.cp = d->cp;
   x.del = d->del;
-  x.Hp = d->Hp;
   x.Atil = d->Atil;
   x.pnum = d->pnum;
   x.pden = d->pden;
@@ -439,12 +443,11 @@ osmpm_status group_sync(osmpm_batch *G) {
       x.active = G->active[s] + i;
       x.ss = G->ss[s] + i;
       x.cg = G->cg[s] + i;
-      double *base = G->parts + (size_t)((s * G->n + i) * 5) * G->stride;
+      double *base = G->parts + (size_t)((s * G->n + i) * kPartArrays) * G->stride;
       x.part_a = base;
       x.part_b = base + G->stride;
-      x.part_q = base + 2 * (size_t)G->stride;
-      x.part_rz = base + 3 * (size_t)G->stride;
-      x.part_rr = base + 4 * (size_t)G->stride;
+      x.part_cg = base + 2 * (size_t)G->stride;
+      x.pstride = G->stride;
       G->hdd[s][i] = x;
       G->stamp_uid[s][i] = d->uid;
       G->stamp_ver[s][i] = d->version;
@@ -599,25 +602,26 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd);
   };
   grad_phase();
-  const double bp = active_bytes(G, s, OSMPM_K_CG_PRODUCT), bu = active_bytes(G, s, OSMPM_K_CG_UPDATE);
+  const double bq = active_bytes(G, s, OSMPM_K_CG_ITER);
   std::vector<int> hint(n), prev_phase(n, kPhaseCgInit), prev_iter(n, 0), prev_total(n, 0);
   for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
   const long max_cycles = (long)(o->max_newton + 1) * ((o->max_cg + 4) / 4 + o->max_ls + 3) + 8;
   osmpm_status st;
   for (long cyc = 0;; ++cyc) {
     if (cyc > max_cycles) return fail(c, OSMPM_E_STATE, "implicit solve did not terminate");
+    // launches wanted this cycle: a fresh CG of n iterations takes n + 2
+    // (the product of u_0, n steps, the stop test), a running one the rest
     int b = 4;
     for (int i = 0; i < n; ++i) {
       if (G->act[s][i] != 1) continue;
-      if (prev_phase[i] == kPhaseCgInit) b = std::max(b, hint[i] + 1);
+      if (prev_phase[i] == kPhaseCgInit) b = std::max(b, hint[i] + 2);
       if (prev_phase[i] == kPhaseCg) b = std::max(b, hint[i] - prev_iter[i] + 1);
     }
-    b = std::min(b, o->max_cg + 1);
-    for (int j = 0; j < b; ++j) {
-      launch(c, OSMPM_K_CG_PRODUCT, bp, j, k_cg_hvp<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, dt,
+    b = std::min(b, o->max_cg + 2);
+    b += b & 1;  // even, so every cycle starts at parity 0
+    for (int j = 0; j < b; ++j)
+      launch(c, OSMPM_K_CG_ITER, bq, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt,
              o->cg_rtol, (int)o->max_cg);
-      launch(c, OSMPM_K_CG_UPDATE, bu, j, k_cg_update<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt);
-    }
     launch(c, -1, 0, -1, k_ls_begin, dim3(blocks_for(n)), blk, 0, dd, n);
     launch(c, -1, 0, -1, k_delta_energy_p<D, TB>, dim3(E.part_blocks, n), blk, 0, dd);
     launch(c, -1, 0, -1, k_delta_energy_n<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0],
@@ -635,12 +639,13 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
       const bool was_cg = prev_phase[i] == kPhaseCgInit || prev_phase[i] == kPhaseCg;
       const int start = prev_phase[i] == kPhaseCg ? prev_iter[i] : 0;
       int did = 0;
+      const int extra = prev_phase[i] == kPhaseCgInit ? 1 : 0;  // the product of u_0
       if (was_cg && hs[i].phase != kPhaseCg) {  // a CG finished in this cycle
         const int cnt = hs[i].cg_iters - prev_total[i];
         hint[i] = cnt;
-        did = cnt - start + 1;
+        did = cnt - start + 1 + extra;
       } else if (was_cg) {
-        did = hc[i].iter - start;
+        did = hc[i].iter - start + extra;
       }
       useful = std::max(useful, did);
       prev_phase[i] = hs[i].phase;
@@ -1081,12 +1086,9 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->qg, (size_t)nn * kMaxGroups);
   if (!s) s = dalloc(d, &d->gg, nd);
   if (!s) s = dalloc_bytes(ctx, d->allocs, &d->gd, nd * d->tb);
-  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->r, nd * d->tb);
-  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->z, nd * d->tb);
-  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->p0, nd * d->tb);
-  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->p1, nd * d->tb);
-  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->del, nd * d->tb);
-  if (!s) s = dalloc_bytes(ctx, d->allocs, &d->Hp, nd * d->tb);
+  for (void **v : {&d->cr[0], &d->cr[1], &d->cs[0], &d->cs[1], &d->cw[0], &d->cw[1], &d->cw[2], &d->cu, &d->cp,
+                   &d->del})
+    if (!s) s = dalloc_bytes(ctx, d->allocs, v, nd * d->tb);
   if (!s) s = dalloc_bytes(ctx, d->allocs, &d->Atil, cap * ns * d->tb);
   if (!s) s = dalloc(d, &d->pnum, nd);
   if (!s) s = dalloc(d, &d->pden, nn);

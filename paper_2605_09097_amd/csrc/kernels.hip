@@ -854,73 +854,112 @@ __global__ void k_newton_check(const DomDesc *dd, double rtol, double atol, int 
 }
 
 // ====================================================================== CG
-// The CG vectors r, z, p, Hp, del and the Jacobi diagonal are stored in the
-// bulk type TB (FP32 in the mixed path); scalars, dot products and the
-// vector arithmetic are FP64.
+// Jacobi-preconditioned CG on H del = -g over the free DOFs, in the
+// single-reduction form of Chronopoulos and Gear (1989): with u = D^-1 r and
+// w = A u, the step length follows from gamma = (r, u) and delta = (w, u)
+// alone, alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_(i-1)),
+// beta_i = gamma_i / gamma_(i-1), and the direction and its product are
+// carried by p_i = u_i + beta_i p_(i-1), s_i = w_i + beta_i s_(i-1).  In exact
+// arithmetic the iterates are those of standard PCG.  Both inner products
+// are available inside the pass that forms A u (delta through the particles,
+// sum_p G:Atil:G + sum_i m_i/dt^2 |u_i|^2), so one launch per iteration
+// suffices: kernel boundaries are the only grid-wide barrier, and every
+// launch costs one dependent dispatch.
+//
+// Vectors are stored in the bulk type TB (FP32 in the mixed path); scalars,
+// inner products and the vector arithmetic are FP64.
 
-// New search direction z + beta p_prev, rounded to the storage type.  Written
-// without FMA contraction so the LDS copy and the stored copy agree bit for bit.
+// p = u + beta p_prev, rounded to the storage type.
 template <typename TB>
-__device__ inline TB cg_direction(TB z, double beta, TB pp) {
+__device__ inline TB cg_direction(TB u, double beta, TB pp) {
 #pragma clang fp contract(off)
   const double t = beta * (double)pp;
-  return (TB)((double)z + t);
+  return (TB)((double)u + t);
 }
 
-// r = -g, z = r / D on free DOFs; search-direction buffers, direction and
-// product cleared; partial (r, z) and (r, r); the CG state is reset.  Runs for
-// domains whose Newton iteration goes on to CG.
+// s = w + beta s_old, r = r_old - alpha s, u = r / diag, each rounded to the
+// storage type.  No contraction, so the owner of a node and every workgroup
+// that recomputes it as a halo node obtain the same bits.
+template <typename TB>
+__device__ inline void cg_advance(TB r_old, TB w_old, TB s_old, TB dg, double alpha, double beta, TB &s, TB &r,
+                                  TB &u) {
+#pragma clang fp contract(off)
+  const double t = beta * (double)s_old;
+  s = (TB)((double)w_old + t);
+  const double a = alpha * (double)s;
+  r = (TB)((double)r_old - a);
+  u = (TB)((double)r / (double)dg);
+}
+
+template <typename TB>
+__device__ inline TB cg_precond(TB r, TB dg) {
+  return (TB)((double)r / (double)dg);
+}
+
+__device__ inline void block_sum3(double &a, double &b, double &c, double *lds12) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+    lds12[w] = a;
+    lds12[4 + w] = b;
+    lds12[8 + w] = c;
+  }
+  __syncthreads();
+  a = lds12[0] + lds12[1] + lds12[2] + lds12[3];
+  b = lds12[4] + lds12[5] + lds12[6] + lds12[7];
+  c = lds12[8] + lds12[9] + lds12[10] + lds12[11];
+}
+
+// r_0 = -g, s = p = del = 0, w = 0 on every DOF (r_0 masked to the free
+// DOFs); the gradient is cleared for the next Newton iteration and the CG
+// state reset.  Runs for domains whose Newton iteration goes on to CG.
 template <int D, typename TB>
 __global__ void k_cg_init(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || dm.ss->phase != kPhaseCgInit || (int)blockIdx.x >= nb) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    dm.cg->iter = 0;
-    dm.cg->done = 0;
-    dm.cg->knext = 0;
-    dm.cg->kcur = 0;
+    CgState &c = *dm.cg;
+    c.iter = 0;
+    c.done = 0;
+    c.k_at[0] = 0;
+    c.k_at[1] = 0;
   }
-  __shared__ double red[8];
-  const TB *gdiag = static_cast<const TB *>(dm.gd);
-  TB *r = static_cast<TB *>(dm.r), *z = static_cast<TB *>(dm.z), *p0 = static_cast<TB *>(dm.p0);
-  TB *p1 = static_cast<TB *>(dm.p1), *del = static_cast<TB *>(dm.del), *Hp = static_cast<TB *>(dm.Hp);
-  double rz = 0.0, rr = 0.0;
+  TB *r0 = static_cast<TB *>(dm.cr[0]), *r1 = static_cast<TB *>(dm.cr[1]);
+  TB *s0 = static_cast<TB *>(dm.cs[0]), *s1 = static_cast<TB *>(dm.cs[1]);
+  TB *w0 = static_cast<TB *>(dm.cw[0]), *w1 = static_cast<TB *>(dm.cw[1]), *w2 = static_cast<TB *>(dm.cw[2]);
+  TB *p = static_cast<TB *>(dm.cp), *del = static_cast<TB *>(dm.del);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += nb * kBlock) {
-    const bool f = dm.fr[k];
-    const TB rv = f ? (TB)(-dm.gg[k]) : TB(0);
+    r0[k] = dm.fr[k] ? (TB)(-dm.gg[k]) : TB(0);
     dm.gg[k] = 0.0;  // scatter target of the next Newton iteration
-    const TB zv = f ? (TB)((double)rv / (double)gdiag[k]) : TB(0);
-    r[k] = rv;
-    z[k] = zv;
-    p0[k] = TB(0);
-    p1[k] = TB(0);
+    r1[k] = TB(0);
+    s0[k] = TB(0);
+    s1[k] = TB(0);
+    w0[k] = TB(0);
+    w1[k] = TB(0);
+    w2[k] = TB(0);
+    p[k] = TB(0);
     del[k] = TB(0);
-    Hp[k] = TB(0);
-    if (f) {
-      rz += (double)rv * (double)zv;
-      rr += (double)rv * (double)rv;
-    }
-  }
-  block_sum2(rz, rr, red);
-  if (threadIdx.x == 0) {
-    dm.part_rz[blockIdx.x] = rz;
-    dm.part_rr[blockIdx.x] = rr;
   }
 }
 
-// CG iteration, first half.  The iteration index k comes from the device
-// state (so a chunk of iterations can be replayed with fixed arguments).
-// Every workgroup sums the (r, z) and (r, r) partials of the previous update
-// in the same order, tests |r| <= rtol |r0| (and k < max_cg), and forms beta.
-// The search direction p = z + beta p_prev is formed on the fly (tile regions
-// in LDS, owned DOFs stored to p_cur).  The particle part scatters
-// Hp = sum_p Atil:G gradN and accumulates the curvature
-// p^T H p = sum_p G:Atil:G + sum_i m_i/dt^2 |p_i|^2, so the product and its
-// curvature complete in one pass.  All global loads that do not depend on
-// beta are issued before the reduction so their latencies overlap.
+// CG iteration i of a domain (i read from the device state at parity q, so
+// launches alternate q = 0, 1 and a chunk of them can be replayed with fixed
+// arguments).  For i >= 1 every workgroup sums the partials of launch i - 1
+// in the same order and derives the same scalars: the stop test on
+// |r_(i-1)| <= rtol |r_0| (or i - 1 = max_cg), beta_(i-1) and alpha_(i-1).
+// Owned DOFs then apply p_(i-1) to del and form s_(i-1), r_i, u_i; the tile
+// region recomputes u_i at its nodes from r_(i-1), w_(i-1), s_(i-2) in LDS,
+// the particles scatter the stiffness part of w_i = A u_i and accumulate
+// (w_i, u_i); owned DOFs add the lumped-mass part m_i/dt^2 u_i to w_i and to
+// (w_i, u_i), and (r_i, u_i), (r_i, r_i).  i = 0 forms
+// u_0 = D^-1 r_0 and w_0 only.  Loads that do not depend on the scalars are
+// issued before the reduction.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_cg_hvp(const DomDesc *dd, double dt, double rtol, int max_cg) {
+__global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
@@ -929,105 +968,174 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(const DomDesc *dd, double dt,
   CgState *S = dm.cg;
   if (S->done) return;
   extern __shared__ double lds[];
-  __shared__ double red[8];
+  __shared__ double red[12];
   const GridDev &g = dm.g;
   const int tid = threadIdx.x;
-  const int it = S->knext;
+  const int i = S->k_at[q];
   const int ndof = dm.ndof;
+  const int nbt = tg.nblocks;
   const int64_t cap = dm.cap;
   const TB *Atil = static_cast<const TB *>(dm.Atil);
-  const TB *z = static_cast<const TB *>(dm.z);
-  TB *pA = static_cast<TB *>(dm.p0), *pB = static_cast<TB *>(dm.p1), *Hp = static_cast<TB *>(dm.Hp);
-  const TB *pprev = (it & 1) ? pA : pB;
-  TB *pcur = (it & 1) ? pB : pA;
+  const TB *dg = static_cast<const TB *>(dm.gd);
+  const TB *r_old = static_cast<const TB *>(dm.cr[(i + 1) & 1]);
+  TB *r_new = static_cast<TB *>(dm.cr[i & 1]);
+  const TB *w_old = static_cast<const TB *>(dm.cw[(i + 2) % 3]);
+  TB *w_new = static_cast<TB *>(dm.cw[i % 3]);
+  TB *w_clr = static_cast<TB *>(dm.cw[(i + 1) % 3]);
+  const TB *s_old = static_cast<const TB *>(dm.cs[i & 1]);
+  TB *s_new = static_cast<TB *>(dm.cs[(i + 1) & 1]);
+  TB *uu = static_cast<TB *>(dm.cu), *pp = static_cast<TB *>(dm.cp), *del = static_cast<TB *>(dm.del);
+  const double *pin = dm.part_cg + (size_t)(q ^ 1) * 3 * dm.pstride;
+  double *pout = dm.part_cg + (size_t)q * 3 * dm.pstride;
   const double *x = dm.pb[*dm.cur].x;
-  const int n_part = node_blocks(ndof);
-  // tile and its particle range
   const int t = tile_of_block(tg, blockIdx.x);
   int p0 = 0, p1 = 0, org[3] = {0, 0, 0};
   const bool tile_ok = tile_range(tg, dm.cell_start, t, p0, p1, org) && p0 < p1;
   const int nreg = tg.nreg;
   // --- independent loads
-  double prz = 0.0, prr = 0.0;
-  for (int i = tid; i < n_part; i += kBlock) {
-    prz += dm.part_rz[i];
-    prr += dm.part_rr[i];
-  }
-  const int k0 = blockIdx.x * kBlock + tid;
-  TB nz = TB(0), npv = TB(0);
-  double nm = 0.0;
-  if (k0 < ndof) {
-    nz = z[k0];
-    npv = pprev[k0];
-    nm = dm.m[k0 / D];
-  }
+  double sg = 0.0, sd = 0.0, sr = 0.0;
+  if (i > 0)
+    for (int j = tid; j < nbt; j += kBlock) {
+      sg += pin[j];
+      sd += pin[dm.pstride + j];
+      sr += pin[2 * dm.pstride + j];
+    }
   int ri = -1;
-  TB rzv[D], rpv[D];
+  TB hr[D], hw[D], hs[D], hd[D];
+  uint8_t hf[D];
   if (tile_ok && tid < nreg) {
     ri = region_node<D>(tg, g, org, tid);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      rzv[a] = (ri >= 0) ? z[ri * D + a] : TB(0);
-      rpv[a] = (ri >= 0) ? pprev[ri * D + a] : TB(0);
+      const int k = ri * D + a;
+      hf[a] = (ri >= 0) ? dm.fr[k] : 0;
+      hr[a] = (ri >= 0) ? r_old[k] : TB(0);
+      hw[a] = (ri >= 0 && i > 0) ? w_old[k] : TB(0);
+      hs[a] = (ri >= 0 && i > 0) ? s_old[k] : TB(0);
+      hd[a] = (ri >= 0) ? dg[k] : TB(1);
     }
   }
-  const int pp = p0 + tid;
-  const bool have_p = tile_ok && pp < p1;
+  if (i == 0 && tile_ok && tid < nreg && ri >= 0) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) hr[a] = r_new[ri * D + a];  // r_0
+  }
+  const int pp0 = p0 + tid;
+  const bool have_p = tile_ok && pp0 < p1;
   double xp[D];
   TB At[ns];
   if (have_p) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) xp[a] = x[a * cap + pp];
+    for (int a = 0; a < D; ++a) xp[a] = x[a * cap + pp0];
 #pragma unroll
-    for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + pp];
+    for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + pp0];
   }
-  // --- reduction, convergence test, beta
-  block_sum2(prz, prr, red);
-  const double rz_new = prz, rr = prr;
-  const double rr0 = (it == 0) ? rr : S->rr0;
-  const bool done = (it >= max_cg) || ((it == 0) ? !(rr0 > 0.0) : (sqrt(rr) <= rtol * sqrt(rr0)));
+  // --- scalars of iteration i - 1
+  double alpha = 0.0, beta = 0.0;
+  bool done = false;
+  if (i > 0) {
+    block_sum3(sg, sd, sr, red);
+    const double rr0 = (i == 1) ? sr : S->rr0;
+    if (i - 1 >= max_cg) {
+      done = true;
+    } else if (i == 1) {
+      done = !(rr0 > 0.0);
+    } else {
+      done = sqrt(sr) <= rtol * sqrt(rr0);
+    }
+    if (!done) {
+      beta = (i == 1) ? 0.0 : sg / S->gam[i & 1];
+      const double den = (i == 1) ? sd : sd - beta * sg / S->alp[i & 1];
+      if (den > 0.0)
+        alpha = sg / den;
+      else
+        done = true;
+    }
+    if (blockIdx.x == 0 && tid == 0) {
+      if (i == 1) S->rr0 = rr0;
+      S->gam[(i + 1) & 1] = sg;
+      S->alp[(i + 1) & 1] = alpha;
+    }
+  }
   if (blockIdx.x == 0 && tid == 0) {
-    if (it == 0) S->rr0 = rr0;
-    if (done) S->done = 1;
-    S->rz[it & 1] = rz_new;
-    S->kcur = it;
+    if (done) {
+      S->done = 1;
+      S->iter = i - 1;
+    } else {
+      S->iter = i;
+      S->k_at[q ^ 1] = i + 1;
+    }
   }
   if (done) return;
-  const double beta = (it == 0) ? 0.0 : rz_new / S->rz[(it + 1) & 1];
   const double mdt = 1.0 / (dt * dt);
-  double q = 0.0;
-  // node part: owned DOFs of the new direction and its mass term
-  if (k0 < ndof) {
-    const TB pv = cg_direction<TB>(nz, beta, npv);
-    pcur[k0] = pv;
-    q += nm * mdt * (double)pv * (double)pv;
+  double gsum = 0.0, dsum = 0.0, rsum = 0.0;
+  // --- owned DOFs
+  for (int k = blockIdx.x * kBlock + tid; k < ndof; k += nbt * kBlock) {
+    w_clr[k] = TB(0);
+    if (!dm.fr[k]) continue;
+    TB r, u;
+    if (i == 0) {
+      r = r_new[k];
+      u = cg_precond<TB>(r, dg[k]);
+    } else {
+      const TB pv = cg_direction<TB>(uu[k], beta, pp[k]);
+      pp[k] = pv;
+      del[k] = (TB)((double)del[k] + alpha * (double)pv);
+      TB s;
+      cg_advance<TB>(r_old[k], w_old[k], s_old[k], dg[k], alpha, beta, s, r, u);
+      s_new[k] = s;
+      r_new[k] = r;
+    }
+    uu[k] = u;
+    // lumped-mass part of w_i = A u_i; the particle part arrives by atomics
+    // from the tiles below, so the owner adds its share atomically too
+    const double mu = dm.m[k / D] * mdt * (double)u;
+    atomicAdd(&w_new[k], (TB)mu);
+    gsum += (double)r * (double)u;
+    rsum += (double)r * (double)r;
+    dsum += mu * (double)u;
   }
-  for (int k = k0 + tg.nblocks * kBlock; k < ndof; k += tg.nblocks * kBlock) {
-    const TB pv = cg_direction<TB>(z[k], beta, pprev[k]);
-    pcur[k] = pv;
-    q += dm.m[k / D] * mdt * (double)pv * (double)pv;
-  }
+  // --- w_i = A u_i through the tile's particles
   if (tile_ok) {
     double *lh = lds;
-    TB *lp = reinterpret_cast<TB *>(lds + D * nreg);
-    if (tid < nreg) {
+    TB *lu = reinterpret_cast<TB *>(lds + D * nreg);
+    for (int r = tid; r < nreg; r += kBlock) {
+      const int nd = (r == tid) ? ri : region_node<D>(tg, g, org, r);
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        lp[a * nreg + tid] = (ri >= 0) ? cg_direction<TB>(rzv[a], beta, rpv[a]) : TB(0);
-        lh[a * nreg + tid] = 0.0;
-      }
-    }
-    for (int r = tid + kBlock; r < nreg; r += kBlock) {
-      const int i = region_node<D>(tg, g, org, r);
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        lp[a * nreg + r] = (i >= 0) ? cg_direction<TB>(z[i * D + a], beta, pprev[i * D + a]) : TB(0);
+        TB u = TB(0);
+        if (nd >= 0) {
+          const int k = nd * D + a;
+          TB fr_r, fw, fs, fd;
+          uint8_t ff;
+          if (r == tid) {
+            ff = hf[a];
+            fr_r = hr[a];
+            fw = hw[a];
+            fs = hs[a];
+            fd = hd[a];
+          } else {
+            ff = dm.fr[k];
+            fr_r = (i == 0) ? r_new[k] : r_old[k];
+            fw = (i > 0) ? w_old[k] : TB(0);
+            fs = (i > 0) ? s_old[k] : TB(0);
+            fd = dg[k];
+          }
+          if (ff) {
+            if (i == 0) {
+              u = cg_precond<TB>(fr_r, fd);
+            } else {
+              TB s2, r2;
+              cg_advance<TB>(fr_r, fw, fs, fd, alpha, beta, s2, r2, u);
+            }
+          }
+        }
+        lu[a * nreg + r] = u;
         lh[a * nreg + r] = 0.0;
       }
     }
     __syncthreads();
-    for (int p = pp; p < p1; p += kBlock) {
-      if (p != pp) {
+    for (int p = pp0; p < p1; p += kBlock) {
+      if (p != pp0) {
 #pragma unroll
         for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
 #pragma unroll
@@ -1049,9 +1157,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(const DomDesc *dd, double dt,
         const int r = region_slot<D>(tg, l, k);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          const TB pa = lp[a * nreg + r];
+          const TB ua = lu[a * nreg + r];
 #pragma unroll
-          for (int b = 0; b < D; ++b) G[a * D + b] += pa * (TB)gN[b];
+          for (int b = 0; b < D; ++b) G[a * D + b] += ua * (TB)gN[b];
         }
       }
       TB T[n];
@@ -1065,7 +1173,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(const DomDesc *dd, double dt,
         T[rr2] = tv;
         qp += G[rr2] * tv;
       }
-      q += (double)qp;
+      dsum += (double)qp;
 #pragma unroll
       for (int s = 0; s < stencil_count<D>(); ++s) {
         int k[3];
@@ -1084,96 +1192,20 @@ __global__ void __launch_bounds__(kBlock) k_cg_hvp(const DomDesc *dd, double dt,
     }
     __syncthreads();
     for (int r = tid; r < nreg; r += kBlock) {
-      const int i = (r == tid) ? ri : region_node<D>(tg, g, org, r);
-      if (i < 0) continue;
+      const int nd = (r == tid) ? ri : region_node<D>(tg, g, org, r);
+      if (nd < 0) continue;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         const double hv = lh[a * nreg + r];
-        if (hv != 0.0) atomicAdd(&Hp[i * D + a], (TB)hv);
+        if (hv != 0.0) atomicAdd(&w_new[nd * D + a], (TB)hv);
       }
     }
   }
-  const double tq = block_sum(q, red);
-  if (tid == 0) dm.part_q[blockIdx.x] = tq;
-}
-
-// CG iteration, second half: alpha = (r, z) / p^T H p; del += alpha p,
-// r -= alpha H p (H p = scatter + m/dt^2 p), z = r / D on free DOFs; the
-// scatter buffer is cleared for the next product; partial (r, z), (r, r).
-// Node data are loaded before the curvature partials are reduced.
-template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_cg_update(const DomDesc *dd, double dt) {
-  const DomDesc &dm = dd[blockIdx.y];
-  const int nb = node_blocks(dm.ndof);
-  if (!*dm.active || (int)blockIdx.x >= nb) return;
-  CgState *S = dm.cg;
-  if (S->done) return;
-  __shared__ double red[8];
-  const int tid = threadIdx.x;
-  const int it = S->kcur;
-  const int ndof = dm.ndof;
-  const TB *gdiag = static_cast<const TB *>(dm.gd);
-  const TB *pcur = static_cast<const TB *>((it & 1) ? dm.p1 : dm.p0);
-  TB *Hp = static_cast<TB *>(dm.Hp), *r = static_cast<TB *>(dm.r), *z = static_cast<TB *>(dm.z);
-  TB *del = static_cast<TB *>(dm.del);
-  const int n_q = dm.tg.nblocks;
-  double pq = 0.0;
-  for (int i = tid; i < n_q; i += kBlock) pq += dm.part_q[i];
-  const int k0 = blockIdx.x * kBlock + tid;
-  double hs = 0.0, pv = 0.0, rv = 0.0, dv = 0.0, dg = 1.0, m = 0.0;
-  bool f = false;
-  if (k0 < ndof) {
-    f = dm.fr[k0];
-    hs = (double)Hp[k0];
-    pv = (double)pcur[k0];
-    rv = (double)r[k0];
-    dv = (double)del[k0];
-    dg = (double)gdiag[k0];
-    m = dm.m[k0 / D];
-  }
-  pq = block_sum(pq, red);
-  if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && tid == 0) S->done = 1;
-    return;
-  }
-  const double alpha = S->rz[it & 1] / pq;
-  const double mdt = 1.0 / (dt * dt);
-  double rz = 0.0, rr = 0.0;
-  if (k0 < ndof) {
-    Hp[k0] = TB(0);
-    if (f) {
-      const double hv = hs + m * mdt * pv;
-      del[k0] = (TB)(dv + alpha * pv);
-      const TB rn = (TB)(rv - alpha * hv);
-      r[k0] = rn;
-      const TB zv = (TB)((double)rn / dg);
-      z[k0] = zv;
-      rz += (double)rn * (double)zv;
-      rr += (double)rn * (double)rn;
-    }
-  }
-  for (int k = k0 + nb * kBlock; k < ndof; k += nb * kBlock) {
-    const double h2 = (double)Hp[k];
-    Hp[k] = TB(0);
-    if (!dm.fr[k]) continue;
-    const double p2 = (double)pcur[k];
-    const double hv = h2 + dm.m[k / D] * mdt * p2;
-    del[k] = (TB)((double)del[k] + alpha * p2);
-    const TB rn = (TB)((double)r[k] - alpha * hv);
-    r[k] = rn;
-    const TB zv = (TB)((double)rn / (double)gdiag[k]);
-    z[k] = zv;
-    rz += (double)rn * (double)zv;
-    rr += (double)rn * (double)rn;
-  }
-  block_sum2(rz, rr, red);
+  block_sum3(gsum, dsum, rsum, red);
   if (tid == 0) {
-    dm.part_rz[blockIdx.x] = rz;
-    dm.part_rr[blockIdx.x] = rr;
-  }
-  if (blockIdx.x == 0 && tid == 0) {
-    S->iter = it + 1;
-    S->knext = it + 1;
+    pout[blockIdx.x] = gsum;
+    pout[dm.pstride + blockIdx.x] = dsum;
+    pout[2 * dm.pstride + blockIdx.x] = rsum;
   }
 }
 
@@ -1650,8 +1682,7 @@ __global__ void k_resid_final(const DomDesc *dd, double *out) {
   template __global__ void k_grad_hess<D, TB>(const DomDesc *, int, int *);                     \
   template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \
   template __global__ void k_cg_init<D, TB>(const DomDesc *);                                   \
-  template __global__ void k_cg_hvp<D, TB>(const DomDesc *, double, double, int);               \
-  template __global__ void k_cg_update<D, TB>(const DomDesc *, double);                         \
+  template __global__ void k_cg_iter<D, TB>(const DomDesc *, int, double, double, int);         \
   template __global__ void k_delta_energy_p<D, TB>(const DomDesc *);                            \
   template __global__ void k_delta_energy_n<D, TB>(const DomDesc *, double, double, double, double);
 

@@ -12,17 +12,19 @@
 
 namespace osmpm {
 
-// Scalars of one CG solve, kept on the device between the two kernels of an
-// iteration.  rz is double-buffered by iteration parity so a kernel never
-// overwrites the value other workgroups of the same launch still read.
+// Scalars of one preconditioned CG solve in the single-reduction form (each
+// iteration applies the previous direction and forms the next residual, its
+// preconditioned image u and the product A u together).  Values written by a
+// launch are double-buffered by iteration parity so no workgroup overwrites
+// what another workgroup of the same launch still reads.
 struct CgState {
-  double rz[2];
-  double rr0;
+  double gam[2];  // (r, u) of earlier iterations, by parity
+  double alp[2];  // step lengths of earlier iterations, by parity
+  double rr0;     // |r_0|^2
   double pad;
-  int iter;   // completed updates
-  int done;   // converged, broke down, hit max_cg, or not solving
-  int knext;  // index of the next iteration (written by the update kernel)
-  int kcur;   // index of the running iteration (written by the product kernel)
+  int iter;       // directions applied so far
+  int done;       // converged, broke down, hit max_cg, or not solving
+  int k_at[2];    // iteration index read by a launch of parity q (written for q ^ 1)
 };
 
 // Phases of one domain's implicit solve.  The decision kernels move a domain
@@ -83,9 +85,15 @@ struct DomDesc {
   int8_t *bcg;
   uint8_t *gamma, *recv, *fr;
   long long *q_all, *q_bnd, *qg;
-  void *gd, *r, *z, *p0, *p1, *del, *Hp, *Atil;
+  void *gd;                // Jacobi diagonal
+  void *cr[2], *cs[2];     // residuals r, products s = A p (by parity)
+  void *cw[3];             // products w = A u (three-way rotation)
+  void *cu, *cp, *del;     // preconditioned residual u, direction p, Newton step
+  void *Atil;              // per-particle folded tangents (packed)
   CgState *cg;
-  double *part_a, *part_b, *part_q, *part_rz, *part_rr;  // per-block partial sums (batch-owned)
+  double *part_a, *part_b;  // per-block partial sums (batch-owned)
+  double *part_cg;          // CG partials [parity][(r,u), (Au,u), (r,r)][pstride]
+  int pstride;
   double *pnum, *pden, *w0, *w1, *w2, *w3;                // interface work buffers
 };
 
@@ -139,9 +147,7 @@ __global__ void k_newton_check(const DomDesc *dd, double rtol, double atol, int 
 template <int D, typename TB>
 __global__ void k_cg_init(const DomDesc *dd);
 template <int D, typename TB>
-__global__ void k_cg_hvp(const DomDesc *dd, double dt, double rtol, int max_cg);
-template <int D, typename TB>
-__global__ void k_cg_update(const DomDesc *dd, double dt);
+__global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg);
 __global__ void k_ls_begin(const DomDesc *dd, int ndom);
 template <int D, typename TB>
 __global__ void k_delta_energy_p(const DomDesc *dd);
