@@ -622,10 +622,8 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     for (int j = 0; j < b; ++j)
       launch(c, OSMPM_K_CG_ITER, bq, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt,
              o->cg_rtol, (int)o->max_cg);
-    launch(c, -1, 0, -1, k_ls_begin, dim3(blocks_for(n)), blk, 0, dd, n);
-    launch(c, -1, 0, -1, k_delta_energy_p<D, TB>, dim3(E.part_blocks, n), blk, 0, dd);
-    launch(c, -1, 0, -1, k_delta_energy_n<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0],
-           o->gravity[1], o->gravity[2]);
+    launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
+           o->gravity[0], o->gravity[1], o->gravity[2]);
     launch(c, -1, 0, -1, k_ls_check, dim3(1, n), blk, 0, dd, (int)o->max_ls);
     launch(c, -1, 0, -1, k_newton_step<TB>, dim3(E.node_blocks, n), blk, 0, dd);
     grad_phase();

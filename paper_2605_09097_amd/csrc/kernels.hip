@@ -1029,6 +1029,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
 #pragma unroll
     for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + pp0];
   }
+  // first owned DOF of the thread (usually its only one)
+  const int k0 = blockIdx.x * kBlock + tid;
+  uint8_t of = 0;
+  TB orr = TB(0), ow = TB(0), os = TB(0), od = TB(1), ou = TB(0), op = TB(0), odl = TB(0);
+  double om = 0.0;
+  if (k0 < ndof) {
+    of = dm.fr[k0];
+    if (of) {
+      orr = (i == 0) ? r_new[k0] : r_old[k0];
+      od = dg[k0];
+      om = dm.m[k0 / D];
+      if (i > 0) {
+        ow = w_old[k0];
+        os = s_old[k0];
+        ou = uu[k0];
+        op = pp[k0];
+        odl = del[k0];
+      }
+    }
+  }
   // --- scalars of iteration i - 1
   double alpha = 0.0, beta = 0.0;
   bool done = false;
@@ -1069,26 +1089,30 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   const double mdt = 1.0 / (dt * dt);
   double gsum = 0.0, dsum = 0.0, rsum = 0.0;
   // --- owned DOFs
-  for (int k = blockIdx.x * kBlock + tid; k < ndof; k += nbt * kBlock) {
+  for (int k = k0; k < ndof; k += nbt * kBlock) {
+    const bool first = (k == k0);
     w_clr[k] = TB(0);
-    if (!dm.fr[k]) continue;
+    if (!(first ? of : dm.fr[k])) continue;
     TB r, u;
     if (i == 0) {
-      r = r_new[k];
-      u = cg_precond<TB>(r, dg[k]);
+      r = first ? orr : r_new[k];
+      u = cg_precond<TB>(r, first ? od : dg[k]);
     } else {
-      const TB pv = cg_direction<TB>(uu[k], beta, pp[k]);
+      const TB pv = cg_direction<TB>(first ? ou : uu[k], beta, first ? op : pp[k]);
       pp[k] = pv;
-      del[k] = (TB)((double)del[k] + alpha * (double)pv);
+      del[k] = (TB)((double)(first ? odl : del[k]) + alpha * (double)pv);
       TB s;
-      cg_advance<TB>(r_old[k], w_old[k], s_old[k], dg[k], alpha, beta, s, r, u);
+      if (first)
+        cg_advance<TB>(orr, ow, os, od, alpha, beta, s, r, u);
+      else
+        cg_advance<TB>(r_old[k], w_old[k], s_old[k], dg[k], alpha, beta, s, r, u);
       s_new[k] = s;
       r_new[k] = r;
     }
     uu[k] = u;
     // lumped-mass part of w_i = A u_i; the particle part arrives by atomics
     // from the tiles below, so the owner adds its share atomically too
-    const double mu = dm.m[k / D] * mdt * (double)u;
+    const double mu = (first ? om : dm.m[k / D]) * mdt * (double)u;
     atomicAdd(&w_new[k], (TB)mu);
     gsum += (double)r * (double)u;
     rsum += (double)r * (double)r;
@@ -1210,179 +1234,189 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
 }
 
 // ====================================================================== line search
-// Phase moves after the CG launches of a cycle, one thread per domain: a
-// freshly initialised CG is now running; a finished CG starts the line search
-// at alpha = 1 and its iteration count is added to the statistics.
-__global__ void k_ls_begin(const DomDesc *dd, int ndom) {
-  const int i = threadIdx.x + blockIdx.x * blockDim.x;
-  if (i >= ndom) return;
-  const DomDesc &dm = dd[i];
-  if (!*dm.active) return;
-  SolveState &s = *dm.ss;
-  if (s.phase == kPhaseCgInit) s.phase = kPhaseCg;
-  if (s.phase == kPhaseCg && dm.cg->done) {
-    s.cg_iters += dm.cg->iter;
-    s.alpha = 1.0;
-    s.ls_count = 0;
-    s.phase = kPhaseLs;
+// A domain evaluates the line search when its CG has finished in this cycle
+// (first evaluation, alpha = 1) or when it is already searching (alpha from
+// the state).
+__device__ inline bool ls_evaluates(const DomDesc &dm, double &alpha) {
+  const int ph = dm.ss->phase;
+  if (ph == kPhaseLs) {
+    alpha = dm.ss->alpha;
+    return true;
   }
+  if ((ph == kPhaseCgInit || ph == kPhaseCg) && dm.cg->done) {
+    alpha = 1.0;
+    return true;
+  }
+  return false;
 }
 
-// Per-particle part of E(u + alpha del) - E(u) in cancellation-free form:
-// V [mu/2 (2 F:Dm + Dm:Dm) - mu L + lam/2 L (2 ln J + L)], L = log1p(dJ / J),
-// dJ = det(F + Dm) - det F expanded in powers of Dm; +inf on inversion.
-// Partials in part_b.
+// E(u + alpha del) - E(u) in cancellation-free form, one launch: workgroups
+// [0, nbp) take the particles, [nbp, nbp + nbn) the nodes.
+// Particle part: V [mu/2 (2 F:Dm + Dm:Dm) - mu L + lam/2 L (2 ln J + L)] with
+// L = log1p(dJ / J) and dJ = det(F + Dm) - det F expanded in powers of Dm
+// (+inf on inversion); partials in part_b.  Node part:
+// m/(2 dt^2) (2 alpha (u - dt v^n).del + alpha^2 |del|^2) - alpha m g.del;
+// partials in part_a.  The node workgroups also clear the Jacobi-diagonal
+// scatter target for the next Newton iteration (CG no longer reads it).
 template <int D, typename TB>
-__global__ void k_delta_energy_p(const DomDesc *dd) {
+__global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz) {
   constexpr int n = D * D;
   const DomDesc &dm = dd[blockIdx.y];
-  const int nb = particle_blocks(dm.np);
-  if (!*dm.active || dm.ss->phase != kPhaseLs || (int)blockIdx.x >= nb) return;
+  const int nbp = particle_blocks(dm.np), nbn = node_blocks(dm.ndof);
+  double alpha = 0.0;
+  if (!*dm.active || (int)blockIdx.x >= nbp + nbn || !ls_evaluates(dm, alpha)) return;
   __shared__ double red[kBlock / 64];
-  const PartPtrs &P = dm.pb[*dm.cur];
-  const int64_t cap = dm.cap;
   const GridDev &g = dm.g;
-  const TB *F = static_cast<const TB *>(P.F);
   const TB *del = static_cast<const TB *>(dm.del);
-  const double alpha = dm.ss->alpha;
   double e = 0.0;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < dm.np; p += nb * kBlock) {
-    double xp[D];
+  if ((int)blockIdx.x < nbp) {
+    const PartPtrs &P = dm.pb[*dm.cur];
+    const int64_t cap = dm.cap;
+    const TB *F = static_cast<const TB *>(P.F);
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < dm.np; p += nbp * kBlock) {
+      double xp[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
-    Stencil<D> st;
-    stencil_eval<D>(xp, g, st);
-    double Gu[n], Gd[n], Fn[n];
+      for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
+      Stencil<D> st;
+      stencil_eval<D>(xp, g, st);
+      double Gu[n], Gd[n], Fn[n];
 #pragma unroll
-    for (int k = 0; k < n; ++k) {
-      Gu[k] = 0.0;
-      Gd[k] = 0.0;
-      Fn[k] = (double)F[k * cap + p];
-    }
+      for (int k = 0; k < n; ++k) {
+        Gu[k] = 0.0;
+        Gd[k] = 0.0;
+        Fn[k] = (double)F[k * cap + p];
+      }
 #pragma unroll
-    for (int s = 0; s < stencil_count<D>(); ++s) {
-      int k[3], idx[3];
-      stencil_offset<D>(s, k);
+      for (int s = 0; s < stencil_count<D>(); ++s) {
+        int k[3], idx[3];
+        stencil_offset<D>(s, k);
 #pragma unroll
-      for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
-      const int i = node_flat<D>(g, idx);
-      double gN[D];
-      stencil_gradN<D>(st, k, gN);
+        for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
+        const int i = node_flat<D>(g, idx);
+        double gN[D];
+        stencil_gradN<D>(st, k, gN);
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const double ua = dm.u[i * D + a], da = (double)del[i * D + a];
+        for (int a = 0; a < D; ++a) {
+          const double ua = dm.u[i * D + a], da = (double)del[i * D + a];
+#pragma unroll
+          for (int b = 0; b < D; ++b) {
+            Gu[a * D + b] += ua * gN[b];
+            Gd[a * D + b] += da * gN[b];
+          }
+        }
+      }
+      double Fc[n], Dm[n];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int b = 0; b < D; ++b) {
-          Gu[a * D + b] += ua * gN[b];
-          Gd[a * D + b] += da * gN[b];
+          double tf = Fn[a * D + b], td = 0.0;
+#pragma unroll
+          for (int c = 0; c < D; ++c) {
+            tf += Gu[a * D + c] * Fn[c * D + b];
+            td += Gd[a * D + c] * Fn[c * D + b];
+          }
+          Fc[a * D + b] = tf;
+          Dm[a * D + b] = alpha * td;
         }
+      const double J = det<D, double>(Fc);
+      double CF[n];
+      cofactor<D, double>(Fc, CF);
+      double dJ = 0.0;
+#pragma unroll
+      for (int k = 0; k < n; ++k) dJ += CF[k] * Dm[k];
+      if constexpr (D == 3) {
+        double CD[n];
+        cofactor<D, double>(Dm, CD);
+#pragma unroll
+        for (int k = 0; k < n; ++k) dJ += Fc[k] * CD[k];
       }
-    }
-    double Fc[n], Dm[n];
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-      for (int b = 0; b < D; ++b) {
-        double tf = Fn[a * D + b], td = 0.0;
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-          tf += Gu[a * D + c] * Fn[c * D + b];
-          td += Gd[a * D + c] * Fn[c * D + b];
-        }
-        Fc[a * D + b] = tf;
-        Dm[a * D + b] = alpha * td;
+      dJ += det<D, double>(Dm);
+      if (!(J > 0.0) || !(J + dJ > 0.0)) {
+        e = HUGE_VAL;
+        continue;
       }
-    const double J = det<D, double>(Fc);
-    double CF[n];
-    cofactor<D, double>(Fc, CF);
-    double dJ = 0.0;
+      const double lnJ = log(J);
+      const double L = log1p(dJ / J);
+      double FD = 0.0, DD = 0.0;
 #pragma unroll
-    for (int k = 0; k < n; ++k) dJ += CF[k] * Dm[k];
-    if constexpr (D == 3) {
-      double CD[n];
-      cofactor<D, double>(Dm, CD);
+      for (int k = 0; k < n; ++k) {
+        FD += Fc[k] * Dm[k];
+        DD += Dm[k] * Dm[k];
+      }
+      const int mt = P.mat[p];
+      const double mu = dm.mu[mt], lam = dm.lam[mt];
+      e += P.vol[p] * (0.5 * mu * (2.0 * FD + DD) - mu * L + 0.5 * lam * L * (2.0 * lnJ + L));
+    }
+    const double t = block_sum(e, red);
+    if (threadIdx.x == 0) dm.part_b[blockIdx.x] = t;
+  } else {
+    const int bn = blockIdx.x - nbp;
+    const double grav[3] = {gx, gy, gz};
+    TB *gdiag = static_cast<TB *>(dm.gd);
+    for (int i = bn * blockDim.x + threadIdx.x; i < g.nn; i += nbn * kBlock) {
 #pragma unroll
-      for (int k = 0; k < n; ++k) dJ += Fc[k] * CD[k];
-    }
-    dJ += det<D, double>(Dm);
-    if (!(J > 0.0) || !(J + dJ > 0.0)) {
-      e = HUGE_VAL;
-      continue;
-    }
-    const double lnJ = log(J);
-    const double L = log1p(dJ / J);
-    double FD = 0.0, DD = 0.0;
+      for (int a = 0; a < D; ++a) gdiag[i * D + a] = TB(0);
+      const double m = dm.m[i];
+      if (!(m > 0.0)) continue;
+      double rd = 0.0, dd2 = 0.0, gd = 0.0;
 #pragma unroll
-    for (int k = 0; k < n; ++k) {
-      FD += Fc[k] * Dm[k];
-      DD += Dm[k] * Dm[k];
+      for (int a = 0; a < D; ++a) {
+        const double dv = (double)del[i * D + a];
+        rd += (dm.u[i * D + a] - dt * dm.vn[i * D + a]) * dv;
+        dd2 += dv * dv;
+        gd += grav[a] * dv;
+      }
+      e += m / (2.0 * dt * dt) * (2.0 * alpha * rd + alpha * alpha * dd2) - alpha * m * gd;
     }
-    const int mt = P.mat[p];
-    const double mu = dm.mu[mt], lam = dm.lam[mt];
-    e += P.vol[p] * (0.5 * mu * (2.0 * FD + DD) - mu * L + 0.5 * lam * L * (2.0 * lnJ + L));
+    const double t = block_sum(e, red);
+    if (threadIdx.x == 0) dm.part_a[bn] = t;
   }
-  const double t = block_sum(e, red);
-  if (threadIdx.x == 0) dm.part_b[blockIdx.x] = t;
 }
 
-// Node part: m/(2 dt^2) (2 alpha (u - dt v^n).del + alpha^2 |del|^2) - alpha m g.del
-// (partials in part_a).
-template <int D, typename TB>
-__global__ void k_delta_energy_n(const DomDesc *dd, double dt, double gx, double gy, double gz) {
-  const DomDesc &dm = dd[blockIdx.y];
-  const int nb = node_blocks(dm.ndof);
-  if (!*dm.active || dm.ss->phase != kPhaseLs || (int)blockIdx.x >= nb) return;
-  __shared__ double red[kBlock / 64];
-  const TB *del = static_cast<const TB *>(dm.del);
-  const double alpha = dm.ss->alpha;
-  const double grav[3] = {gx, gy, gz};
-  double e = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < dm.g.nn; i += nb * kBlock) {
-    const double m = dm.m[i];
-    if (!(m > 0.0)) continue;
-    double rd = 0.0, dd2 = 0.0, gd = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-      const double dv = (double)del[i * D + a];
-      rd += (dm.u[i * D + a] - dt * dm.vn[i * D + a]) * dv;
-      dd2 += dv * dv;
-      gd += grav[a] * dv;
-    }
-    e += m / (2.0 * dt * dt) * (2.0 * alpha * rd + alpha * alpha * dd2) - alpha * m * gd;
-  }
-  const double t = block_sum(e, red);
-  if (threadIdx.x == 0) dm.part_a[blockIdx.x] = t;
-}
-
-// Halving decision of every searching domain: accept when the energy change
-// is negative; otherwise halve alpha, or give up after max_ls halvings (the
-// iterate is kept and the solve ends).  One workgroup per domain.
+// Per-domain decisions after the CG launches of a cycle (one workgroup per
+// domain): a freshly initialised CG is now running; a CG that finished starts
+// the line search (its iteration count goes to the statistics, and its first
+// evaluation at alpha = 1 is the one just computed); a searching domain
+// accepts when the energy change is negative, else halves alpha, or gives up
+// after max_ls halvings (the iterate is kept and the solve ends).
 __global__ void k_ls_check(const DomDesc *dd, int max_ls) {
   const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active || dm.ss->phase != kPhaseLs) return;
+  if (!*dm.active) return;
+  SolveState *s = dm.ss;
+  const int ph = s->phase;
+  const bool cg_over = (ph == kPhaseCgInit || ph == kPhaseCg) && dm.cg->done;
+  if (!cg_over && ph != kPhaseLs) {
+    if (ph == kPhaseCgInit && threadIdx.x == 0) s->phase = kPhaseCg;
+    return;
+  }
   __shared__ double red[kBlock / 64];
   const double en = reduce_partials(dm.part_a, node_blocks(dm.ndof), red);
   const double ep = reduce_partials(dm.part_b, particle_blocks(dm.np), red);
   if (threadIdx.x == 0) {
-    SolveState &s = *dm.ss;
+    if (cg_over) {
+      s->cg_iters += dm.cg->iter;
+      s->alpha = 1.0;
+      s->ls_count = 0;
+    }
     const double dE = en + ep;
-    s.dE = dE;
+    s->dE = dE;
     if (dE < 0.0) {
-      s.phase = kPhaseStep;
-    } else if (s.ls_count == max_ls) {
-      s.ls_failed = 1;
-      s.phase = kPhaseDone;
+      s->phase = kPhaseStep;
+    } else if (s->ls_count == max_ls) {
+      s->ls_failed = 1;
+      s->phase = kPhaseDone;
     } else {
-      s.alpha *= 0.5;
-      s.ls_count += 1;
-      s.ls_halvings += 1;
+      s->alpha *= 0.5;
+      s->ls_count += 1;
+      s->ls_halvings += 1;
+      s->phase = kPhaseLs;
     }
   }
 }
 
-// u += alpha del for every domain that accepted a step; clears the diagonal
-// scatter target of the next iteration.  The phase stays kPhaseStep until the
-// next Newton test.
+// u += alpha del for every domain that accepted a step.  The phase stays
+// kPhaseStep until the next Newton test.
 template <typename TB>
 __global__ void k_newton_step(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
@@ -1392,11 +1426,8 @@ __global__ void k_newton_step(const DomDesc *dd) {
   if (s.phase != kPhaseStep) return;
   const double alpha = s.alpha;
   const TB *del = static_cast<const TB *>(dm.del);
-  TB *gdiag = static_cast<TB *>(dm.gd);
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += nb * kBlock) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += nb * kBlock)
     dm.u[k] += alpha * (double)del[k];
-    gdiag[k] = TB(0);
-  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     s.newton_iters += 1;
     s.it += 1;
@@ -1683,8 +1714,7 @@ __global__ void k_resid_final(const DomDesc *dd, double *out) {
   template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \
   template __global__ void k_cg_init<D, TB>(const DomDesc *);                                   \
   template __global__ void k_cg_iter<D, TB>(const DomDesc *, int, double, double, int);         \
-  template __global__ void k_delta_energy_p<D, TB>(const DomDesc *);                            \
-  template __global__ void k_delta_energy_n<D, TB>(const DomDesc *, double, double, double, double);
+  template __global__ void k_delta_energy<D, TB>(const DomDesc *, double, double, double, double);
 
 OSMPM_INST_D(2)
 OSMPM_INST_D(3)

@@ -148,11 +148,8 @@ template <int D, typename TB>
 __global__ void k_cg_init(const DomDesc *dd);
 template <int D, typename TB>
 __global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg);
-__global__ void k_ls_begin(const DomDesc *dd, int ndom);
 template <int D, typename TB>
-__global__ void k_delta_energy_p(const DomDesc *dd);
-template <int D, typename TB>
-__global__ void k_delta_energy_n(const DomDesc *dd, double dt, double gx, double gy, double gz);
+__global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz);
 __global__ void k_ls_check(const DomDesc *dd, int max_ls);
 template <typename TB>
 __global__ void k_newton_step(const DomDesc *dd);
