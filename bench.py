@@ -56,7 +56,7 @@ def counter_traffic():
     counters were taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "cg_product_inclusion_refined_pmc.txt")
+    path = os.path.join(ROOT, "profiles", "cg_iter_inclusion_refined_pmc.txt")
     if not os.path.exists(path):
         return None
     vals = {}
