@@ -74,6 +74,45 @@ def counter_traffic():
         return None
 
 
+def batched_form(ctx, n_scenes, steps, prec, solve):
+    """The batched form: n_scenes independent inclusion scenes of uneven sizes
+    (scenes.batch_scene) as one Schwarz batch, every stage one launch over all
+    scenes.  One warm-up frame, `steps` timed frames, then one instrumented
+    frame for the CG iteration's launch durations."""
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding, scenes
+
+    scs = [scenes.batch_scene(s) for s in range(n_scenes)]
+    opts = binding.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol, coarse=solve, fine=solve)
+    sb = binding.SchwarzBatch(ctx, scs, precision=prec)
+    sb.frame(opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    stats = [sb.frame(opts) for _ in range(steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    ctx.profile(True)
+    sb.frame(opts)
+    n, ms, by = ctx.profile_query(binding.OSMPM_K_CG_ITER)
+    ctx.profile(False)
+    sb.close()
+    ps = sum(_frame_particle_steps(sc) for sc in scs)
+    iters = [st.iters for fr in stats for st in fr]
+    return {"workload": "%d 2D inclusion scenes, radius U(0.03,0.08), inclusion E log-uniform [2e4,2e5], "
+                        "coarse dx in {1/80,1/120,1/160}, fine dx in {1/200,1/300,1/400}, 2x2 ppc, M=2, dT=1e-3, "
+                        "frames 1-%d" % (n_scenes, steps),
+            "scenes": n_scenes, "particles": int(sum(sc.B.n_particles + sc.S.n_particles for sc in scs)),
+            "particle_steps_per_frame": int(ps), "value": steps * ps / el, "unit": "particle-steps/s",
+            "ms_per_step": 1e3 * el / steps, "steps": steps, "warmup": 1,
+            "schwarz_iters_mean": float(np.mean(iters)), "schwarz_iters_max": int(max(iters)),
+            "converged_all": bool(all(st.converged for fr in stats for st in fr)),
+            "roofline": ({"bound": "hbm", "kernel": "k_cg_iter", "achieved": by / (ms * 1e-3) / 1e9, "peak": 8000.0,
+                          "unit": "GB/s", "frac": by / (ms * 1e-3) / 8e12, "avg_us": 1e3 * ms / n,
+                          "bytes_per_launch": by / n, "launches": n} if n else None)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +124,9 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--profile-steps", type=int, default=0, help="frames of the instrumented pass (0: --steps)")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
+    ap.add_argument("--batch-scenes", type=int, default=64,
+                    help="scenes of the batched form (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=5, help="timed frames of the batched form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's multiplicative Schwarz loop is "
@@ -167,6 +209,9 @@ def main():
         p64.close()
         fp64 = {"value": args.steps * _frame_particle_steps(sc) / el64, "ms_per_step": 1e3 * el64 / args.steps,
                 "schwarz_iters_mean": float(np.mean([s.iters for s in st64]))}
+    batched = None
+    if args.batch_scenes > 0:
+        batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve)
     if args.calibrate_copy:
         # a plain device copy of known size, for scaling HBM counters
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -210,6 +255,7 @@ def main():
         "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
         "cpu_baseline": cpu,
         "parity": parity,
+        "batched": batched,
     }
     print(json.dumps(out))
     ctx.close()

@@ -221,17 +221,24 @@ void launch(osmpm_ctx *c, int which, double bytes, int cg_iter, F kernel, dim3 g
 }
 
 // Folds completed timings into the counters (only after a stream
-// synchronisation).  CG launches with a cycle index at or beyond `cg_useful`
-// found every domain finished and exited at once; they are dropped.
-void prof_harvest(osmpm_ctx *c, int cg_useful = 1 << 30) {
+// synchronisation).  A CG launch with cycle index j is charged cg_bytes[j],
+// the algorithmic bytes of the domains that iterated in it; launches in
+// which every domain had finished (no entry, or zero) are dropped.
+void prof_harvest(osmpm_ctx *c, const std::vector<double> *cg_bytes = nullptr) {
   for (const ProfPending &p : c->pending) {
-    if (p.cg_iter < 0 || p.cg_iter < cg_useful) {
+    double bytes = p.bytes;
+    bool keep = true;
+    if (p.cg_iter >= 0) {
+      bytes = (cg_bytes && p.cg_iter < (int)cg_bytes->size()) ? (*cg_bytes)[p.cg_iter] : 0.0;
+      keep = bytes > 0.0;
+    }
+    if (keep) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         ProfSlot &sl = c->slots[p.which];
         sl.launches += 1;
         sl.ms += ms;
-        sl.bytes += p.bytes;
+        sl.bytes += bytes;
       }
     }
     c->ev_pool.push_back(p.a);
@@ -602,7 +609,6 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd);
   };
   grad_phase();
-  const double bq = active_bytes(G, s, OSMPM_K_CG_ITER);
   std::vector<int> hint(n), prev_phase(n, kPhaseCgInit), prev_iter(n, 0), prev_total(n, 0);
   for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
   const long max_cycles = (long)(o->max_newton + 1) * ((o->max_cg + 4) / 4 + o->max_ls + 3) + 8;
@@ -620,7 +626,7 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     b = std::min(b, o->max_cg + 2);
     b += b & 1;  // even, so every cycle starts at parity 0
     for (int j = 0; j < b; ++j)
-      launch(c, OSMPM_K_CG_ITER, bq, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt,
+      launch(c, OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt,
              o->cg_rtol, (int)o->max_cg);
     launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
            o->gravity[0], o->gravity[1], o->gravity[2]);
@@ -630,7 +636,7 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     if ((st = read_status(G))) return st;
     const SolveState *hs = h_ss(G, s);
     const CgState *hc = h_cg(G, s);
-    int useful = 0;
+    std::vector<double> cg_bytes(b, 0.0);
     bool all_done = true;
     for (int i = 0; i < n; ++i) {
       if (G->act[s][i] != 1) continue;
@@ -645,13 +651,13 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
       } else if (was_cg) {
         did = hc[i].iter - start + extra;
       }
-      useful = std::max(useful, did);
+      for (int j = 0; j < std::min(did, b); ++j) cg_bytes[j] += G->bytes[s][OSMPM_K_CG_ITER][i];
       prev_phase[i] = hs[i].phase;
       prev_iter[i] = hc[i].iter;
       prev_total[i] = hs[i].cg_iters;
       if (hs[i].phase != kPhaseDone) all_done = false;
     }
-    prof_harvest(c, useful);
+    prof_harvest(c, &cg_bytes);
     if (all_done) break;
   }
   const SolveState *hs = h_ss(G, s);
