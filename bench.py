@@ -84,9 +84,12 @@ def batched_form(ctx, n_scenes, steps, prec, solve):
 
     from paper_2605_09097_amd import binding, scenes
 
+    from paper_2605_09097_amd import autotune
+
     scs = [scenes.batch_scene(s) for s in range(n_scenes)]
     opts = binding.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol, coarse=solve, fine=solve)
-    sb = binding.SchwarzBatch(ctx, scs, precision=prec)
+    tile, tune = autotune.tune_batch(ctx, scs, opts, prec)
+    sb = binding.SchwarzBatch(ctx, scs, precision=prec, tile=tile)
     sb.frame(opts)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -108,6 +111,7 @@ def batched_form(ctx, n_scenes, steps, prec, solve):
             "ms_per_step": 1e3 * el / steps, "steps": steps, "warmup": 1,
             "schwarz_iters_mean": float(np.mean(iters)), "schwarz_iters_max": int(max(iters)),
             "converged_all": bool(all(st.converged for fr in stats for st in fr)),
+            "tile": list(tile), "tile_tuning_ms_per_frame": {str(k): 1e3 * v for k, v in tune.items()},
             "roofline": ({"bound": "hbm", "kernel": "k_cg_iter", "achieved": by / (ms * 1e-3) / 1e9, "peak": 8000.0,
                           "unit": "GB/s", "frac": by / (ms * 1e-3) / 8e12, "avg_us": 1e3 * ms / n,
                           "bytes_per_launch": by / n, "launches": n} if n else None)}
@@ -168,8 +172,13 @@ def main():
                   "max_rel_err": max(errs.values()), **errs}
         pair.close()
 
+    # tile shapes picked by measurement (outside the timed region)
+    from paper_2605_09097_amd import autotune
+
+    tile_B, tile_S, tune = autotune.tune_pair(ctx, sc, opts, prec)
+
     def timed(precision, o, steps, warmup):
-        pr = binding.SchwarzPair(ctx, sc, precision=precision)
+        pr = binding.SchwarzPair(ctx, sc, precision=precision, tile_B=tile_B, tile_S=tile_S)
         for _ in range(warmup):
             pr.frame(o)
         torch.cuda.synchronize()
@@ -241,7 +250,9 @@ def main():
                    "N_B": sc.B.n_particles, "N_S": sc.S.n_particles, "path": args.precision,
                    "schwarz_iters_mean": float(np.mean(iters)),
                    "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
-                   "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats]))},
+                   "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats])),
+                   "tile_B": list(tile_B), "tile_S": list(tile_S)},
+        "tile_tuning_ms_per_frame": {k: 1e3 * v for k, v in tune.items()},
         "roofline": ({"bound": "hbm", "kernel": "k_cg_iter (CG iteration with the Hessian-vector product)",
                       "achieved": kern["cg_iter"]["achieved_GBps"], "peak": 8000.0, "unit": "GB/s",
                       "frac": kern["cg_iter"]["frac_hbm"], "traffic": counter_traffic(),

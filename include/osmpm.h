@@ -135,6 +135,16 @@ typedef struct {
  * NULL for the default stream; the context never destroys it. */
 osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out);
 osmpm_status osmpm_ctx_set_stream(osmpm_ctx *ctx, void *stream);
+/* Solve cycles (a fixed sequence of CG, line-search, Newton-step, gradient
+ * and Newton-test launches plus the copy of the small status block) are
+ * replayed as HIP graphs, built once per batch side and cycle shape and
+ * cached; enable = 0 enqueues the launches one by one instead.  Results are
+ * identical either way.  Default: disabled (on the MI355X with ROCm 7 the
+ * replay measured about 2 % slower per frame than direct launches for the
+ * refined inclusion: the cost is the GPU's dependent-dispatch latency, which
+ * a graph does not remove).  Kernel timing (osmpm_profile_enable) always uses
+ * individual launches. */
+osmpm_status osmpm_ctx_set_graphs(osmpm_ctx *ctx, int32_t enable);
 /* Waits for all queued work and reports device-side errors. */
 osmpm_status osmpm_sync(osmpm_ctx *ctx);
 const char *osmpm_last_error(const osmpm_ctx *ctx);

@@ -23,7 +23,7 @@ OSMPM_K_CG_ITER, OSMPM_K_P2G, OSMPM_K_G2P, OSMPM_K_GRAD_HESS = 0, 1, 2, 3
 
 # Every symbol the header declares (checked by the CPU test suite).
 ABI_SYMBOLS = [
-    "osmpm_ctx_create", "osmpm_ctx_set_stream", "osmpm_sync", "osmpm_last_error", "osmpm_ctx_destroy",
+    "osmpm_ctx_create", "osmpm_ctx_set_stream", "osmpm_ctx_set_graphs", "osmpm_sync", "osmpm_last_error", "osmpm_ctx_destroy",
     "osmpm_profile_enable", "osmpm_profile_query",
     "osmpm_domain_create", "osmpm_domain_destroy", "osmpm_domain_set_materials",
     "osmpm_domain_set_particles", "osmpm_domain_set_selection", "osmpm_domain_set_scene_bc",
@@ -78,6 +78,7 @@ def _declare(L):
     sig = {
         "osmpm_ctx_create": [C.c_int32, _vp, P(_vp)],
         "osmpm_ctx_set_stream": [_vp, _vp],
+        "osmpm_ctx_set_graphs": [_vp, C.c_int32],
         "osmpm_sync": [_vp],
         "osmpm_profile_enable": [_vp, C.c_int32],
         "osmpm_profile_query": [_vp, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)],
@@ -183,6 +184,9 @@ class Context:
 
     def sync(self):
         self.check(lib().osmpm_sync(self.handle), "sync")
+
+    def graphs(self, enable):
+        self.check(lib().osmpm_ctx_set_graphs(self.handle, int(enable)), "set_graphs")
 
     def profile(self, enable):
         self.check(lib().osmpm_profile_enable(self.handle, int(enable)), "profile_enable")
@@ -422,12 +426,12 @@ class Batch:
 class SchwarzBatch:
     """Many scenes (scenes.Scene with equal dT and M) as one Schwarz batch."""
 
-    def __init__(self, ctx: Context, scenes_, precision=OSMPM_FP64):
+    def __init__(self, ctx: Context, scenes_, precision=OSMPM_FP64, tile=None):
         self.scenes = list(scenes_)
         if len({(s.dT, s.M) for s in self.scenes}) != 1:
             raise ValueError("scenes of a batch share dT and M")
         self.dT, self.M = self.scenes[0].dT, self.scenes[0].M
-        self.pairs = [SchwarzPair(ctx, s, precision) for s in self.scenes]
+        self.pairs = [SchwarzPair(ctx, s, precision, tile_B=tile, tile_S=tile) for s in self.scenes]
         self.batch = Batch(ctx, [p.B for p in self.pairs], [p.S for p in self.pairs])
         self.frame_index = 0
 

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -48,6 +49,23 @@ struct ProfSlot {
   double ms = 0.0, bytes = 0.0;
 };
 
+// Explicit HIP graph under construction: launches append kernel nodes in a
+// chain instead of being enqueued.
+struct GraphBuild {
+  hipGraph_t graph = nullptr;
+  hipGraphNode_t last = nullptr;
+  hipError_t err = hipSuccess;
+};
+
+// A cached solve cycle: key (launch count, step, solver options) and the
+// instantiated graph.
+struct CycleGraph {
+  int b = 0;
+  double dt = 0.0;
+  osmpm_solve_opts o{};
+  hipGraphExec_t exec = nullptr;
+};
+
 // Work buffer indices understood by the kernels (see wbuf).
 constexpr int kBufVn = 4, kBufVbc = 5;
 // Partial-sum arrays per domain: two scalar reductions and the CG's three
@@ -68,6 +86,8 @@ struct osmpm_ctx {
   std::vector<ProfPending> pending;
   std::vector<osmpm_batch *> groups;  // every live group (error words)
   uint64_t next_uid = 1;
+  bool graphs = false;            // replay solve cycles as HIP graphs
+  GraphBuild *rec = nullptr;      // graph being built (launches become nodes)
 };
 
 // Particle arrays, component-major [rows][capacity].  Positions, masses and
@@ -136,6 +156,7 @@ struct osmpm_batch {
   std::vector<int> act[2];  // host mirror of active (-1: unknown)
   // status block: header, n_amb[n], n_recv[2][n], resid[2][n][2], SolveState[2][n], CgState[2][n]
   char *status = nullptr;
+  char *h_status = nullptr;  // pinned host copy of the status block
   size_t status_bytes = 0;
   size_t off_amb = 0, off_recv = 0, off_res = 0, off_ss = 0, off_cg = 0;
   int *err = nullptr, *n_amb = nullptr, *n_recv = nullptr;
@@ -146,6 +167,7 @@ struct osmpm_batch {
   int stride = 0;
   Ext ext[2];
   std::vector<double> bytes[2][OSMPM_K_COUNT];  // algorithmic bytes per domain and kernel
+  std::vector<CycleGraph> cycles[2];            // cached solve-cycle graphs per side
   std::vector<void *> allocs;
 };
 
@@ -204,12 +226,45 @@ hipEvent_t prof_event(osmpm_ctx *c) {
   return e;
 }
 
-// Every launch goes through here.  With profiling on, an instrumented launch
-// (which >= 0) carries start and stop timestamps on its own dispatch, so no
-// extra packets sit between kernels.
+// Appends a kernel node to the graph being built; the arguments are
+// converted to the kernel's parameter types and copied by the runtime.
+template <typename... P, typename... A>
+void add_node(GraphBuild &gb, void (*kernel)(P...), dim3 grid, dim3 block, size_t shm, A... args) {
+  std::tuple<P...> vals(static_cast<P>(args)...);
+  void *ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+  std::apply(
+      [&](auto &...v) {
+        int i = 0;
+        ((ptrs[i++] = static_cast<void *>(&v)), ...);
+      },
+      vals);
+  hipKernelNodeParams np{};
+  np.func = reinterpret_cast<void *>(kernel);
+  np.gridDim = grid;
+  np.blockDim = block;
+  np.sharedMemBytes = (unsigned)shm;
+  np.kernelParams = ptrs;
+  np.extra = nullptr;
+  hipGraphNode_t node = nullptr;
+  const hipError_t e = hipGraphAddKernelNode(&node, gb.graph, gb.last ? &gb.last : nullptr, gb.last ? 1 : 0, &np);
+  if (e != hipSuccess) {
+    if (gb.err == hipSuccess) gb.err = e;
+  } else {
+    gb.last = node;
+  }
+}
+
+// Every launch goes through here.  While a graph is being built the launch
+// becomes a node.  With profiling on, an instrumented launch (which >= 0)
+// carries start and stop timestamps on its own dispatch, so no extra packets
+// sit between kernels.
 template <typename F, typename... Args>
 void launch(osmpm_ctx *c, int which, double bytes, int cg_iter, F kernel, dim3 grid, dim3 block, size_t shm,
             Args... args) {
+  if (c->rec) {
+    add_node(*c->rec, kernel, grid, block, shm, args...);
+    return;
+  }
   hipEvent_t a = nullptr, b = nullptr;
   if (c->prof && which >= 0) {
     a = prof_event(c);
@@ -296,6 +351,10 @@ void group_free(osmpm_batch *G) {
     auto it = std::find(c->groups.begin(), c->groups.end(), G);
     if (it != c->groups.end()) c->groups.erase(it);
   }
+  for (int s = 0; s < 2; ++s)
+    for (CycleGraph &cgph : G->cycles[s])
+      if (cgph.exec) (void)hipGraphExecDestroy(cgph.exec);
+  if (G->h_status) (void)hipHostFree(G->h_status);
   for (void *p : G->allocs) (void)hipFree(p);
   delete G;
 }
@@ -372,7 +431,8 @@ osmpm_status group_create(osmpm_ctx *c, int n, osmpm_domain *const *side0, osmpm
   G->parts = static_cast<double *>(p);
   if (!s && hipMemsetAsync(G->status, 0, G->status_bytes, c->stream) != hipSuccess)
     s = fail(c, OSMPM_E_DEVICE, "hipMemsetAsync failed");
-  if (!s && ensure_pin(c, G->status_bytes)) s = OSMPM_E_NO_MEMORY;
+  if (!s && hipHostMalloc((void **)&G->h_status, G->status_bytes, hipHostMallocDefault) != hipSuccess)
+    s = fail(c, OSMPM_E_NO_MEMORY, "hipHostMalloc failed");
   if (s) {
     group_free(G);
     return s;
@@ -461,6 +521,9 @@ osmpm_status group_sync(osmpm_batch *G) {
       changed = true;
     }
     if (!changed) continue;
+    for (CycleGraph &cgph : G->cycles[s])  // launch extents may change
+      if (cgph.exec) (void)hipGraphExecDestroy(cgph.exec);
+    G->cycles[s].clear();
     HIP_TRY(c, hipMemcpyAsync(G->dd[s], G->hdd[s].data(), sizeof(DomDesc) * G->n, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     Ext E;
@@ -509,27 +572,31 @@ double active_bytes(const osmpm_batch *G, int s, int which) {
   return b;
 }
 
-// Copies the status block to pinned memory and waits.  Returns the device
-// error (sticky: the word is never cleared).
+// Device error of the status block last copied to the host (sticky: the
+// word is never cleared).
+osmpm_status status_error(osmpm_batch *G) {
+  int err = 0;
+  std::memcpy(&err, G->h_status, sizeof(int));
+  return device_error(G->c, err);
+}
+
+// Copies the status block to its pinned host copy and waits.
 osmpm_status read_status(osmpm_batch *G) {
   osmpm_ctx *c = G->c;
   osmpm_status s = check_launch(c);
   if (s) return s;
-  if ((s = ensure_pin(c, G->status_bytes))) return s;
-  HIP_TRY(c, hipMemcpyAsync(c->h_pin, G->status, G->status_bytes, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(G->h_status, G->status, G->status_bytes, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  int err = 0;
-  std::memcpy(&err, c->h_pin, sizeof(int));
-  return device_error(c, err);
+  return status_error(G);
 }
 const SolveState *h_ss(const osmpm_batch *G, int s) {
-  return reinterpret_cast<const SolveState *>(G->c->h_pin + G->off_ss) + s * G->n;
+  return reinterpret_cast<const SolveState *>(G->h_status + G->off_ss) + s * G->n;
 }
 const CgState *h_cg(const osmpm_batch *G, int s) {
-  return reinterpret_cast<const CgState *>(G->c->h_pin + G->off_cg) + s * G->n;
+  return reinterpret_cast<const CgState *>(G->h_status + G->off_cg) + s * G->n;
 }
-const int *h_int(const osmpm_batch *G, size_t off) { return reinterpret_cast<const int *>(G->c->h_pin + off); }
-const double *h_res(const osmpm_batch *G) { return reinterpret_cast<const double *>(G->c->h_pin + G->off_res); }
+const int *h_int(const osmpm_batch *G, size_t off) { return reinterpret_cast<const int *>(G->h_status + off); }
+const double *h_res(const osmpm_batch *G) { return reinterpret_cast<const double *>(G->h_status + G->off_res); }
 
 // ---------------------------------------------------------------- sort + P2G + G2P
 // Stable counting sort of every active domain's particles by tile-major bin
@@ -625,15 +692,53 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     }
     b = std::min(b, o->max_cg + 2);
     b += b & 1;  // even, so every cycle starts at parity 0
-    for (int j = 0; j < b; ++j)
-      launch(c, OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt,
-             o->cg_rtol, (int)o->max_cg);
-    launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
-           o->gravity[0], o->gravity[1], o->gravity[2]);
-    launch(c, -1, 0, -1, k_ls_check, dim3(1, n), blk, 0, dd, (int)o->max_ls);
-    launch(c, -1, 0, -1, k_newton_step<TB>, dim3(E.node_blocks, n), blk, 0, dd);
-    grad_phase();
-    if ((st = read_status(G))) return st;
+    if (c->graphs && !c->prof) b = (b + 3) & ~3;  // fewer distinct cycle graphs
+    auto cycle = [&]() {
+      for (int j = 0; j < b; ++j)
+        launch(c, OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt,
+               o->cg_rtol, (int)o->max_cg);
+      launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
+             o->gravity[0], o->gravity[1], o->gravity[2]);
+      launch(c, -1, 0, -1, k_ls_check, dim3(1, n), blk, 0, dd, (int)o->max_ls);
+      launch(c, -1, 0, -1, k_newton_step<TB>, dim3(E.node_blocks, n), blk, 0, dd);
+      grad_phase();
+    };
+    if (c->graphs && !c->prof) {
+      // replay the cycle (its launches and the status copy) as one graph
+      CycleGraph *cg = nullptr;
+      for (CycleGraph &x : G->cycles[s])
+        if (x.b == b && x.dt == dt && std::memcmp(&x.o, o, sizeof(osmpm_solve_opts)) == 0) cg = &x;
+      if (!cg) {
+        GraphBuild gb;
+        HIP_TRY(c, hipGraphCreate(&gb.graph, 0));
+        c->rec = &gb;
+        cycle();
+        c->rec = nullptr;
+        hipGraphNode_t cp = nullptr;
+        if (gb.err == hipSuccess)
+          gb.err = hipGraphAddMemcpyNode1D(&cp, gb.graph, gb.last ? &gb.last : nullptr, gb.last ? 1 : 0,
+                                           G->h_status, G->status, G->status_bytes, hipMemcpyDeviceToHost);
+        hipGraphExec_t ex = nullptr;
+        if (gb.err == hipSuccess) gb.err = hipGraphInstantiate(&ex, gb.graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gb.graph);
+        if (gb.err != hipSuccess)
+          return fail(c, OSMPM_E_DEVICE, std::string("solve cycle graph: ") + hipGetErrorString(gb.err));
+        CycleGraph x;
+        x.b = b;
+        x.dt = dt;
+        x.o = *o;
+        x.exec = ex;
+        G->cycles[s].push_back(x);
+        cg = &G->cycles[s].back();
+      }
+      if ((st = check_launch(c))) return st;
+      HIP_TRY(c, hipGraphLaunch(cg->exec, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      if ((st = status_error(G))) return st;
+    } else {
+      cycle();
+      if ((st = read_status(G))) return st;
+    }
     const SolveState *hs = h_ss(G, s);
     const CgState *hc = h_cg(G, s);
     std::vector<double> cg_bytes(b, 0.0);
@@ -953,6 +1058,12 @@ osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out) {
     return OSMPM_E_NO_MEMORY;
   }
   *out = c;
+  return OSMPM_OK;
+}
+
+osmpm_status osmpm_ctx_set_graphs(osmpm_ctx *ctx, int32_t enable) {
+  if (!ctx) return OSMPM_E_INVALID_ARG;
+  ctx->graphs = enable != 0;
   return OSMPM_OK;
 }
 

@@ -168,3 +168,56 @@ def test_batch_rejects_bad_members(ctx):
         b.Batch(ctx, [B], [Sm])
     for D in (B, S, Sm):
         D.close()
+
+
+def _binding_scene_x(sc):
+    return sc.S.x
+
+
+def test_graph_replay_matches_eager(ctx):
+    """Solve cycles replayed as HIP graphs (osmpm_ctx_set_graphs) give the results of
+    the same launches enqueued one by one, frame after frame (every frame
+    replays the cached graphs many times, with eager work and host
+    synchronisations in between): equal iteration counts, and state equal to
+    rounding (grid sums use floating-point atomics, whose order varies from
+    run to run either way)."""
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("inclusion_tiny")
+    opts = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    runs = {}
+    for graphs in (True, False):
+        ctx.graphs(graphs)
+        pair = b.SchwarzPair(ctx, sc)
+        out = []
+        for _ in range(3):
+            st = pair.frame(opts)
+            out.append(((st.iters, st.newton_B, st.newton_S, st.cg_B, st.cg_S),
+                        pair.B.grid_state()[2].cpu().numpy().copy(), pair.S.grid_state()[2].cpu().numpy().copy(),
+                        pair.S.particles_input_order()[0].copy()))
+        pair.close()
+        runs[graphs] = out
+    ctx.graphs(False)
+    for fg, fe in zip(runs[True], runs[False]):
+        assert fg[0] == fe[0]
+        for a, e in zip(fg[1:3], fe[1:3]):
+            assert rel_err(a, e) < 1e-12
+        x0 = _binding_scene_x(sc)
+        assert rel_err(fg[3] - x0, fe[3] - x0) < 1e-12
+
+
+def test_autotune_picks_a_measured_candidate(ctx):
+    from paper_2605_09097_amd import autotune
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("inclusion_tiny")
+    opts = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    cands = [(4, 4), (8, 8)]
+    tB, tS, tim = autotune.tune_pair(ctx, sc, opts, candidates=cands, frames=1)
+    assert tB in cands and tS in cands
+    assert all(v > 0 for v in tim.values())
+    t, tim2 = autotune.tune_batch(ctx, [sc, scenes.inclusion_scene(20, 40, seed=3, delta=0.01)], opts,
+                                  candidates=cands)
+    assert t in cands and set(tim2) == set(cands)
