@@ -90,7 +90,7 @@ class SolveStats(C.Structure):
 class SchwarzOpts(C.Structure):
     _fields_ = [
         ("M", C.c_int), ("k_max", C.c_int), ("eps_conv", C.c_double), ("eps_tol", C.c_double),
-        ("coarse", SolveOpts), ("fine", SolveOpts),
+        ("coarse", SolveOpts), ("fine", SolveOpts), ("force_iters", C.c_int),
     ]
 
 
@@ -127,6 +127,9 @@ def _declare(L):
     L.or_single_frame.argtypes = [dom, C.c_double, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
     L.or_schwarz_frame.argtypes = [dom, dom, C.c_double, C.POINTER(SchwarzOpts),
                                    C.POINTER(SchwarzStats)]
+    L.or_single_frame_adjoint.argtypes = [dom, C.c_double, C.POINTER(SolveOpts), C.c_double] + [_dp] * 10
+    L.or_schwarz_frame_adjoint.argtypes = ([dom, dom, C.c_double, C.POINTER(SchwarzOpts), C.c_int, C.c_double]
+                                           + [_dp] * 20)
 
 
 def _ptr(a, t):
@@ -225,6 +228,15 @@ class Domain:
 
     def state(self):
         return {"x": self.x.copy(), "v": self.v.copy(), "B": self.B.copy(), "F": self.F.copy()}
+
+    def set_state(self, st):
+        """Overwrite the particle state in place (arrays keep their addresses)."""
+        for k in ("x", "v", "B", "F"):
+            getattr(self, k)[...] = st[k]
+
+    def set_lame(self, mu, lam):
+        self.mu[...] = mu
+        self.lam[...] = lam
 
     def node_positions(self):
         d = self.dim
@@ -368,9 +380,10 @@ def solve_opts(newton_rtol=1e-8, newton_atol=1e-13, cg_rtol=1e-10, max_newton=50
     return o
 
 
-def schwarz_opts(M, k_max=100, eps_conv=1e-5, eps_tol=0.0, coarse=None, fine=None):
+def schwarz_opts(M, k_max=100, eps_conv=1e-5, eps_tol=0.0, coarse=None, fine=None, force_iters=0):
     o = SchwarzOpts()
     o.M, o.k_max, o.eps_conv, o.eps_tol = M, k_max, eps_conv, eps_tol
+    o.force_iters = int(force_iters)
     o.coarse = coarse if coarse is not None else solve_opts()
     o.fine = fine if fine is not None else solve_opts()
     return o
@@ -381,3 +394,48 @@ def schwarz_frame(Bd: Domain, Sd: Domain, dT, opts):
     _check(lib().or_schwarz_frame(Bd.ref, Sd.ref, dT, C.byref(opts), C.byref(st)),
            "or_schwarz_frame")
     return st
+
+
+# ---------------------------------------------------------------- reverse mode
+def _adj_arrays(D, adj):
+    """Contiguous float64 copies of an adjoint state dict (zeros where absent)."""
+    out = {}
+    for k, shape in (("x", D.x.shape), ("v", D.v.shape), ("B", D.B.shape), ("F", D.F.shape)):
+        a = adj.get(k) if adj is not None else None
+        out[k] = np.ascontiguousarray(np.zeros(shape) if a is None else np.asarray(a, dtype=np.float64).reshape(shape))
+    return out
+
+
+def single_frame_adjoint(D: Domain, dt, opts, adj_end, adj_cg_rtol=1e-13):
+    """Adjoint of one single-domain frame.  D holds the start-of-frame state
+    (on exit: the end state, the frame being recomputed).  adj_end: adjoint
+    of the end state ({x, v, B, F}).  Returns (adjoint of the start state,
+    dL/dmu, dL/dlam per material)."""
+    a = _adj_arrays(D, adj_end)
+    o = {k: np.zeros_like(v) for k, v in a.items()}
+    mub = np.zeros_like(D.mu)
+    lab = np.zeros_like(D.lam)
+    _check(lib().or_single_frame_adjoint(D.ref, dt, C.byref(opts), adj_cg_rtol,
+                                         *[_ptr(a[k], _dp) for k in "xvBF"], *[_ptr(o[k], _dp) for k in "xvBF"],
+                                         _ptr(mub, _dp), _ptr(lab, _dp)), "or_single_frame_adjoint")
+    return o, mub, lab
+
+
+def schwarz_frame_adjoint(Bd: Domain, Sd: Domain, dT, opts, iters, adjB_end, adjS_end, adj_cg_rtol=1e-13):
+    """Adjoint of one Schwarz frame with `iters` Schwarz iterations (the
+    forward's count).  Bd, Sd hold the start-of-frame states (on exit the end
+    states).  Returns (adjoint of B's start state, of S's start state,
+    dL/dmu_B, dL/dlam_B, dL/dmu_S, dL/dlam_S), the material adjoints per
+    material index of each domain."""
+    aB = _adj_arrays(Bd, adjB_end)
+    aS = _adj_arrays(Sd, adjS_end)
+    oB = {k: np.zeros_like(v) for k, v in aB.items()}
+    oS = {k: np.zeros_like(v) for k, v in aS.items()}
+    mubB, labB = np.zeros_like(Bd.mu), np.zeros_like(Bd.lam)
+    mubS, labS = np.zeros_like(Sd.mu), np.zeros_like(Sd.lam)
+    _check(lib().or_schwarz_frame_adjoint(
+        Bd.ref, Sd.ref, dT, C.byref(opts), int(iters), adj_cg_rtol,
+        *[_ptr(aB[k], _dp) for k in "xvBF"], *[_ptr(aS[k], _dp) for k in "xvBF"],
+        *[_ptr(oB[k], _dp) for k in "xvBF"], *[_ptr(oS[k], _dp) for k in "xvBF"],
+        _ptr(mubB, _dp), _ptr(labB, _dp), _ptr(mubS, _dp), _ptr(labS, _dp)), "or_schwarz_frame_adjoint")
+    return oB, oS, mubB, labB, mubS, labS

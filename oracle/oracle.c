@@ -95,6 +95,7 @@ typedef struct {
   int M, k_max;
   double eps_conv, eps_tol;
   or_solve_opts coarse, fine;
+  int force_iters;        /* > 0: run exactly this many Schwarz iterations */
 } or_schwarz_opts;
 
 typedef struct {
@@ -1253,7 +1254,7 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
   memcpy(vBn, B->vn, sizeof(double) * nnB * d);
   if ((rc = or_project(S, B, o->eps_tol, S->vn, vGB))) goto done;
   if ((rc = or_interp(B, vBn, S, vGSprev))) goto done;
-  for (int k = 0; k < o->k_max; ++k) {
+  for (int k = 0; k < (o->force_iters > 0 ? o->force_iters : o->k_max); ++k) {
     or_solve_stats ss;
     /* 1. coarse solve over dT with Pi data on the coarse receivers */
     memcpy(B->vbc, vGB, sizeof(double) * nnB * d);
@@ -1292,6 +1293,11 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
     memcpy(vGB, vGBnew, sizeof(double) * nnB * d);
     memcpy(vGSprev, vGSn1, sizeof(double) * nnS * d);
     st->iters = k + 1;
+    if (o->force_iters > 0) {
+      st->converged = st->r_B <= o->eps_conv && st->r_S <= o->eps_conv;
+      if (k + 1 == o->force_iters) break;
+      continue;
+    }
     if (st->r_B <= o->eps_conv && st->r_S <= o->eps_conv) {
       st->converged = 1;
       break;
@@ -1311,5 +1317,813 @@ done:
   free(vGSprev);
   free(vGSn);
   free(vGSn1);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Reverse mode: the adjoint of a frame with respect to the start-of-    */
+/* frame particle states and the Lame parameters of every material.      */
+/*                                                                      */
+/* Discrete decisions (bins, active nodes, boundary and receiver sets,   */
+/* the number of Schwarz iterations) are held at their forward values.   */
+/* Each implicit solve is differentiated at its minimiser by the         */
+/* implicit-function theorem: with g_f(u*; inputs) = 0 on the free DOFs  */
+/* and the Dirichlet DOFs fixed by data, the adjoint lambda solves       */
+/* H_ff lambda = ubar_f with the Hessian of E at u* (not PSD-projected), */
+/* every input receives -lambda^T dg_f/d(input), and the Dirichlet data  */
+/* receive ubar_D - (H lambda)_D.  The transfers are transposed exactly, */
+/* including the dependence of N_ip and grad N_ip on the particle        */
+/* position (second derivatives of the quadratic B-spline).              */
+/* ------------------------------------------------------------------ */
+
+/* Second derivatives of N_ip with respect to x_p (d x d, symmetric) at stencil
+ * node s: d2w/df2 = (1, -2, 1) per axis for the three stencil offsets. */
+static void stencil_hess(const or_domain *D, const stencil *st, int s, double *Hs) {
+  const int d = D->dim;
+  const double dx = grid_dx(D), i2 = 1.0 / (dx * dx);
+  const int k[3] = {s % 3, (s / 3) % 3, s / 9};
+  double w[3] = {1, 1, 1}, dw[3] = {0, 0, 0}, ddw[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) {
+    w[a] = st->w[a][k[a]];
+    dw[a] = st->dw[a][k[a]];
+    ddw[a] = (k[a] == 1 ? -2.0 : 1.0) * i2;
+  }
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double v = 1.0;
+      for (int c = 0; c < d; ++c) {
+        if (a == b)
+          v *= (c == a) ? ddw[c] : w[c];
+        else
+          v *= (c == a || c == b) ? dw[c] : w[c];
+      }
+      Hs[a * d + b] = v;
+    }
+}
+
+/* A view of a domain with its particle and grid arrays replaced (the
+ * forward states stored for the reverse sweep). */
+static or_domain view_of(const or_domain *D, double *x, double *v, double *B, double *F, double *m,
+                         double *vn, double *u) {
+  or_domain V = *D;
+  V.x = x;
+  V.v = v;
+  V.B = B;
+  V.F = F;
+  V.m = m;
+  V.vn = vn;
+  V.u = u;
+  return V;
+}
+
+/* P2G transposed.  Given mbar, vnbar on the nodes (the adjoint of the node
+ * mass and of v = (mv)/m), adds the adjoint of x, v, B of the particles. */
+static int p2g_adjoint(const or_domain *D, const double *mbar, const double *vnbar, double *xbar,
+                       double *vbar, double *Bbar) {
+  const int d = D->dim, ss = stencil_size(D);
+  const double dx = grid_dx(D), Dinv = 4.0 / (dx * dx);
+  for (int p = 0; p < D->np; ++p) {
+    stencil st;
+    if (stencil_at(D, &D->x[p * d], &st)) return OR_E_OUT_OF_GRID;
+    const double mp = D->mass[p];
+    const double *vp = &D->v[p * d], *Bp = &D->B[p * d * d];
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      const double mi = D->m[i];
+      double pb[3] = {0, 0, 0}, mt = mbar[i];
+      if (mi > 0.0) {
+        for (int a = 0; a < d; ++a) {
+          pb[a] = vnbar[i * d + a] / mi;
+          mt -= vnbar[i * d + a] * D->vn[i * d + a] / mi;
+        }
+      }
+      double w[3], pw = 0.0;
+      for (int a = 0; a < d; ++a) {
+        double aff = 0.0;
+        for (int b = 0; b < d; ++b) aff += Bp[a * d + b] * dxv[b];
+        w[a] = vp[a] + Dinv * aff;
+        pw += pb[a] * w[a];
+      }
+      for (int a = 0; a < d; ++a) {
+        vbar[p * d + a] += mp * N * pb[a];
+        for (int b = 0; b < d; ++b) Bbar[(p * d + a) * d + b] += mp * N * Dinv * pb[a] * dxv[b];
+        double bt = 0.0; /* (B^T pb)_a */
+        for (int b = 0; b < d; ++b) bt += Bp[b * d + a] * pb[b];
+        xbar[p * d + a] += mp * ((mt + pw) * gN[a] - N * Dinv * bt);
+      }
+    }
+  }
+  return OR_OK;
+}
+
+/* G2P transposed.  D holds the particle state before G2P and u the grid
+ * displacement; given the adjoint of the particle state after G2P (xo, vo,
+ * Bo, Fo), adds ubar on the nodes and the adjoint of x and F before G2P
+ * (v and B before G2P do not reach the output). */
+static int g2p_adjoint(const or_domain *D, double dt, const double *xo, const double *vo,
+                       const double *Bo, const double *Fo, double *ubar, double *xbar, double *Fbar) {
+  const int d = D->dim, ss = stencil_size(D);
+  for (int p = 0; p < D->np; ++p) {
+    stencil st;
+    if (stencil_at(D, &D->x[p * d], &st)) return OR_E_OUT_OF_GRID;
+    const double *Fp = &D->F[p * d * d];
+    const double *Fb = &Fo[p * d * d], *Bb = &Bo[p * d * d];
+    double vt[3], G[9] = {0};
+    for (int a = 0; a < d; ++a) {
+      vt[a] = vo[p * d + a] + dt * xo[p * d + a];
+      xbar[p * d + a] += xo[p * d + a];
+    }
+    /* M1 = Fo F^T (for ubar), M2 = F Fo^T (for the position term) */
+    double M1[9], M2[9];
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+          t1 += Fb[a * d + c] * Fp[b * d + c];
+          t2 += Fp[a * d + c] * Fb[b * d + c];
+        }
+        M1[a * d + b] = t1;
+        M2[a * d + b] = t2;
+      }
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3], Hs[9];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      if (!is_active(D, i)) continue;
+      stencil_hess(D, &st, s, Hs);
+      const double *ui = &D->u[i * d];
+      double Bx[3], uv = 0.0, uBx = 0.0, Btu[3], Mu[3];
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0, t2 = 0.0, t3 = 0.0;
+        for (int b = 0; b < d; ++b) {
+          t += Bb[a * d + b] * dxv[b];
+          t2 += Bb[b * d + a] * ui[b];
+          t3 += M2[a * d + b] * ui[b];
+        }
+        Bx[a] = t;
+        Btu[a] = t2;
+        Mu[a] = t3;
+      }
+      for (int a = 0; a < d; ++a) {
+        uv += ui[a] * vt[a];
+        uBx += ui[a] * Bx[a];
+      }
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < d; ++b) t += M1[a * d + b] * gN[b];
+        ubar[i * d + a] += N * vt[a] / dt + N * Bx[a] / dt + t;
+        double h = 0.0;
+        for (int b = 0; b < d; ++b) h += Hs[a * d + b] * Mu[b];
+        xbar[p * d + a] += (uv / dt + uBx / dt) * gN[a] - N * Btu[a] / dt + h;
+      }
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) G[a * d + b] += ui[a] * gN[b];
+    }
+    /* Fbar_old += (I + G)^T Fo */
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double t = Fb[a * d + b];
+        for (int c = 0; c < d; ++c) t += G[c * d + a] * Fb[c * d + b];
+        Fbar[p * d * d + a * d + b] += t;
+      }
+  }
+  return OR_OK;
+}
+
+/* Adjoint of one converged implicit solve on D (whose u holds the
+ * minimiser), see the section comment.  Adds mbar, vnbar (nodes), xbar, Fbar
+ * (particles), mubar, lambar (materials) and, where given, vbcbar on the
+ * Schwarz receiver DOFs. */
+static int solve_adjoint(const or_domain *D, double dt, const double *grav, const double *ubar,
+                         double cg_rtol, int max_cg, double *mbar, double *vnbar, double *xbar,
+                         double *Fbar, double *mubar, double *lambar, double *vbcbar) {
+  const int d = D->dim, nn = nnodes(D), n = d * d, ndof = nn * d, ss = stencil_size(D);
+  kin K;
+  int rc = kin_build(D, &K);
+  if (rc) return rc;
+  unsigned char *dir = (unsigned char *)malloc((size_t)ndof);
+  unsigned char *fr = (unsigned char *)malloc((size_t)ndof);
+  double *ud = (double *)malloc(sizeof(double) * ndof);
+  double *lam = (double *)calloc((size_t)ndof, sizeof(double));
+  double *r = (double *)malloc(sizeof(double) * ndof);
+  double *z = (double *)malloc(sizeof(double) * ndof);
+  double *pv = (double *)malloc(sizeof(double) * ndof);
+  double *q = (double *)malloc(sizeof(double) * ndof);
+  double *dg = (double *)malloc(sizeof(double) * ndof);
+  double *A = (double *)malloc(sizeof(double) * (size_t)(D->np > 0 ? D->np : 1) * n * n);
+  if (!dir || !fr || !ud || !lam || !r || !z || !pv || !q || !dg || !A) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
+  or_dirichlet(D, dt, dir, ud);
+  for (int i = 0; i < nn; ++i)
+    for (int a = 0; a < d; ++a) fr[i * d + a] = (unsigned char)(is_active(D, i) && !dir[i * d + a]);
+  if ((rc = hessian_blocks(D, &K, D->u, 0, A))) goto done;
+  diag_k(D, &K, A, dt, dg);
+  /* PCG on H_ff lambda = ubar_f */
+  for (int k = 0; k < ndof; ++k) {
+    r[k] = fr[k] ? ubar[k] : 0.0;
+    z[k] = fr[k] ? r[k] / dg[k] : 0.0;
+    pv[k] = z[k];
+  }
+  {
+    double rz = dot_masked(r, z, fr, ndof);
+    const double r0 = sqrt(dot_masked(r, r, fr, ndof));
+    for (int k = 0; k < max_cg && r0 > 0.0; ++k) {
+      hvp_k(D, &K, A, dt, pv, q);
+      for (int j = 0; j < ndof; ++j)
+        if (!fr[j]) q[j] = 0.0;
+      const double pq = dot_masked(pv, q, fr, ndof);
+      if (!(pq > 0.0)) break;
+      const double alpha = rz / pq;
+      for (int j = 0; j < ndof; ++j) {
+        lam[j] += alpha * pv[j];
+        r[j] -= alpha * q[j];
+      }
+      if (sqrt(dot_masked(r, r, fr, ndof)) <= cg_rtol * r0) break;
+      for (int j = 0; j < ndof; ++j) z[j] = fr[j] ? r[j] / dg[j] : 0.0;
+      const double rz_new = dot_masked(r, z, fr, ndof);
+      const double beta = rz_new / rz;
+      rz = rz_new;
+      for (int j = 0; j < ndof; ++j) pv[j] = z[j] + beta * pv[j];
+    }
+  }
+  /* Dirichlet data: ubar_D - (H lambda)_D, on the Schwarz receiver DOFs */
+  if (vbcbar) {
+    hvp_k(D, &K, A, dt, lam, q);
+    for (int i = 0; i < nn; ++i)
+      for (int a = 0; a < d; ++a) {
+        const int k = i * d + a;
+        if (!is_active(D, i) || !dir[k] || D->bcg[k] >= 0 || !D->use_schwarz_bc || !D->recv[i]) continue;
+        vbcbar[k] += dt * (ubar[k] - q[k]);
+      }
+  }
+  /* node inputs: g_i = m_i/dt^2 (u_i - dt v_i) - m_i g + f_int,i */
+  for (int i = 0; i < nn; ++i) {
+    if (!is_active(D, i)) continue;
+    for (int a = 0; a < d; ++a) {
+      const int k = i * d + a;
+      if (!fr[k]) continue;
+      vnbar[k] += lam[k] * D->m[i] / dt;
+      mbar[i] -= lam[k] * ((D->u[k] - dt * D->vn[k]) / (dt * dt) - grav[a]);
+    }
+  }
+  /* particle inputs: phi_p = V P(F(u)) : (G_lambda F^n) */
+  for (int p = 0; p < D->np; ++p) {
+    stencil st;
+    if (stencil_at(D, &D->x[p * d], &st)) {
+      rc = OR_E_OUT_OF_GRID;
+      goto done;
+    }
+    const double *Fn = &D->F[p * d * d];
+    double Gu[9] = {0}, Gl[9] = {0};
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+          Gu[a * d + b] += D->u[i * d + a] * gN[b];
+          Gl[a * d + b] += lam[i * d + a] * gN[b];
+        }
+    }
+    double H[9], F[9], L[9], P[9], Ap[81];
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) H[a * d + b] = (a == b ? 1.0 : 0.0) + Gu[a * d + b];
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double t = 0.0, t2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+          t += H[a * d + c] * Fn[c * d + b];
+          t2 += Gl[a * d + c] * Fn[c * d + b];
+        }
+        F[a * d + b] = t;
+        L[a * d + b] = t2;
+      }
+    const int mt = D->mat[p];
+    if (nh_stress(F, d, D->mu[mt], D->lam[mt], P, Ap)) {
+      rc = OR_E_INVERTED;
+      goto done;
+    }
+    const double V = D->vol[p];
+    /* material: dP/dmu = F - F^-T, dP/dlam = ln J F^-T */
+    {
+      const double J = det_d(F, d), lnJ = log(J);
+      double C[9];
+      cofactor(F, d, C); /* F^-T = C / J */
+      double smu = 0.0, slam = 0.0;
+      for (int k = 0; k < n; ++k) {
+        smu += (F[k] - C[k] / J) * L[k];
+        slam += lnJ * C[k] / J * L[k];
+      }
+      mubar[mt] -= V * smu;
+      lambar[mt] -= V * slam;
+    }
+    /* AL = A : L */
+    double AL[9];
+    for (int r2 = 0; r2 < n; ++r2) {
+      double t = 0.0;
+      for (int c2 = 0; c2 < n; ++c2) t += Ap[r2 * n + c2] * L[c2];
+      AL[r2] = t;
+    }
+    /* Fbar^n -= V (H^T AL + Gl^T P) */
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double t = 0.0;
+        for (int c = 0; c < d; ++c) t += H[c * d + a] * AL[c * d + b] + Gl[c * d + a] * P[c * d + b];
+        Fbar[p * d * d + a * d + b] -= V * t;
+      }
+    /* xbar -= V sum_i Hs_ip (Y1^T u_i + Y2^T lambda_i), Y1 = AL F^nT, Y2 = P F^nT */
+    double Y1[9], Y2[9];
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double t1 = 0.0, t2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+          t1 += AL[a * d + c] * Fn[b * d + c];
+          t2 += P[a * d + c] * Fn[b * d + c];
+        }
+        Y1[a * d + b] = t1;
+        Y2[a * d + b] = t2;
+      }
+    for (int s = 0; s < ss; ++s) {
+      int i;
+      double N, gN[3], dxv[3], Hs[9];
+      stencil_node(D, &st, s, &i, &N, gN, dxv);
+      stencil_hess(D, &st, s, Hs);
+      double y[3];
+      for (int b = 0; b < d; ++b) {
+        double t = 0.0;
+        for (int a = 0; a < d; ++a) t += Y1[a * d + b] * D->u[i * d + a] + Y2[a * d + b] * lam[i * d + a];
+        y[b] = t;
+      }
+      for (int a = 0; a < d; ++a) {
+        double t = 0.0;
+        for (int b = 0; b < d; ++b) t += Hs[a * d + b] * y[b];
+        xbar[p * d + a] -= V * t;
+      }
+    }
+  }
+  rc = OR_OK;
+done:
+  kin_free(&K);
+  free(dir);
+  free(fr);
+  free(ud);
+  free(lam);
+  free(r);
+  free(z);
+  free(pv);
+  free(q);
+  free(dg);
+  free(A);
+  return rc;
+}
+
+/* Pi_{S->B} transposed: given the adjoint of the projected data on the
+ * coarse receivers, adds the adjoint of the fine node masses and velocities
+ * (S holds the fine grid the projection read). */
+static int project_adjoint(const or_domain *S, const or_domain *B, double eps_tol, const double *pbar,
+                           double *mbarS, double *vnbarS) {
+  const int d = B->dim, nnB = nnodes(B), nnS = nnodes(S), ss = stencil_size(B);
+  double *num = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *den = (double *)calloc((size_t)nnB, sizeof(double));
+  if (!num || !den) {
+    free(num);
+    free(den);
+    return OR_E_NOMEM;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = 0; j < nnS; ++j) {
+      if (!(S->m[j] > 0.0)) continue;
+      int jS[3];
+      double xj[3] = {0, 0, 0};
+      node_index(S, j, jS);
+      node_pos(S, jS, xj);
+      stencil st;
+      if (stencil_at(B, xj, &st)) {
+        free(num);
+        free(den);
+        return OR_E_OUT_OF_GRID;
+      }
+      for (int s = 0; s < ss; ++s) {
+        int I;
+        double N, gN[3], dxv[3];
+        stencil_node(B, &st, s, &I, &N, gN, dxv);
+        if (pass == 0) {
+          den[I] += S->m[j] * N;
+          for (int a = 0; a < d; ++a) num[I * d + a] += S->m[j] * N * S->vn[j * d + a];
+        } else if (B->recv[I]) {
+          const double de = den[I] + eps_tol;
+          double pn = 0.0;
+          for (int a = 0; a < d; ++a) pn += pbar[I * d + a] * num[I * d + a];
+          const double denbar = -pn / (de * de);
+          double vnum = 0.0;
+          for (int a = 0; a < d; ++a) {
+            const double numbar = pbar[I * d + a] / de;
+            vnbarS[j * d + a] += S->m[j] * N * numbar;
+            vnum += S->vn[j * d + a] * numbar;
+          }
+          mbarS[j] += N * (vnum + denbar);
+        }
+      }
+    }
+  }
+  free(num);
+  free(den);
+  return OR_OK;
+}
+
+/* I_{B->S} transposed: adds to vBbar the adjoint of the coarse velocity. */
+static int interp_adjoint(const or_domain *B, const or_domain *S, const double *ibar, double *vBbar) {
+  const int d = B->dim, nnS = nnodes(S), ss = stencil_size(B);
+  for (int j = 0; j < nnS; ++j) {
+    if (!S->recv[j]) continue;
+    int jS[3];
+    double xj[3] = {0, 0, 0};
+    node_index(S, j, jS);
+    node_pos(S, jS, xj);
+    stencil st;
+    if (stencil_at(B, xj, &st)) return OR_E_OUT_OF_GRID;
+    for (int s = 0; s < ss; ++s) {
+      int I;
+      double N, gN[3], dxv[3];
+      stencil_node(B, &st, s, &I, &N, gN, dxv);
+      if (!(B->m[I] > 0.0)) continue;
+      for (int a = 0; a < d; ++a) vBbar[I * d + a] += N * ibar[j * d + a];
+    }
+  }
+  return OR_OK;
+}
+
+/* Adjoint of a particle state: [x d][v d][B d^2][F d^2] per particle block,
+ * i.e. four arrays laid out like the state. */
+typedef struct {
+  double *x, *v, *B, *F;
+} adj_state;
+
+static int adj_alloc(adj_state *a, int np, int d) {
+  const size_t n = (size_t)(np > 0 ? np : 1);
+  a->x = (double *)calloc(n * d, sizeof(double));
+  a->v = (double *)calloc(n * d, sizeof(double));
+  a->B = (double *)calloc(n * d * d, sizeof(double));
+  a->F = (double *)calloc(n * d * d, sizeof(double));
+  return (a->x && a->v && a->B && a->F) ? OR_OK : OR_E_NOMEM;
+}
+static void adj_free(adj_state *a) {
+  free(a->x);
+  free(a->v);
+  free(a->B);
+  free(a->F);
+}
+static void adj_zero(adj_state *a, int np, int d) {
+  memset(a->x, 0, sizeof(double) * np * d);
+  memset(a->v, 0, sizeof(double) * np * d);
+  memset(a->B, 0, sizeof(double) * np * d * d);
+  memset(a->F, 0, sizeof(double) * np * d * d);
+}
+
+/* Stored forward state of one domain at one point of the frame. */
+typedef struct {
+  double *x, *v, *B, *F; /* particles */
+  double *m, *vn;        /* grid from the P2G of these particles */
+  signed char *bcg;      /* scene-BC groups of the DOFs at that P2G */
+  double *u, *vbc;       /* solution and Schwarz data of the following solve */
+} fwd_point;
+
+static int fwd_alloc(fwd_point *f, const or_domain *D) {
+  const int d = D->dim, nn = nnodes(D);
+  const size_t np = (size_t)(D->np > 0 ? D->np : 1);
+  f->x = (double *)malloc(sizeof(double) * np * d);
+  f->v = (double *)malloc(sizeof(double) * np * d);
+  f->B = (double *)malloc(sizeof(double) * np * d * d);
+  f->F = (double *)malloc(sizeof(double) * np * d * d);
+  f->m = (double *)malloc(sizeof(double) * nn);
+  f->vn = (double *)malloc(sizeof(double) * nn * d);
+  f->bcg = (signed char *)malloc((size_t)nn * d);
+  f->u = (double *)calloc((size_t)nn * d, sizeof(double));
+  f->vbc = (double *)calloc((size_t)nn * d, sizeof(double));
+  return (f->x && f->v && f->B && f->F && f->m && f->vn && f->bcg && f->u && f->vbc) ? OR_OK : OR_E_NOMEM;
+}
+static void fwd_free(fwd_point *f) {
+  free(f->x);
+  free(f->v);
+  free(f->B);
+  free(f->F);
+  free(f->m);
+  free(f->vn);
+  free(f->bcg);
+  free(f->u);
+  free(f->vbc);
+}
+static void fwd_save_particles(fwd_point *f, const or_domain *D) {
+  const int d = D->dim;
+  memcpy(f->x, D->x, sizeof(double) * D->np * d);
+  memcpy(f->v, D->v, sizeof(double) * D->np * d);
+  memcpy(f->B, D->B, sizeof(double) * D->np * d * d);
+  memcpy(f->F, D->F, sizeof(double) * D->np * d * d);
+}
+static void fwd_save_grid(fwd_point *f, const or_domain *D) {
+  memcpy(f->m, D->m, sizeof(double) * nnodes(D));
+  memcpy(f->vn, D->vn, sizeof(double) * nnodes(D) * D->dim);
+  memcpy(f->bcg, D->bcg, (size_t)nnodes(D) * D->dim);
+}
+static or_domain fwd_view(const or_domain *D, fwd_point *f) {
+  or_domain V = view_of(D, f->x, f->v, f->B, f->F, f->m, f->vn, f->u);
+  V.bcg = f->bcg;
+  V.vbc = f->vbc;
+  return V;
+}
+
+/* Adjoint of one single-domain frame (P2G, solve, G2P) of D, which holds the
+ * start-of-frame state on entry and the end-of-frame state on exit (the
+ * frame is recomputed).  abar_in: adjoint of the end state; abar_out
+ * (overwritten): adjoint of the start state; mubar, lambar accumulate. */
+int or_single_frame_adjoint(or_domain *D, double dt, const or_solve_opts *opt, double adj_cg_rtol,
+                            const double *xb, const double *vb, const double *Bb, const double *Fb,
+                            double *oxb, double *ovb, double *oBb, double *oFb, double *mubar,
+                            double *lambar) {
+  const int d = D->dim, nn = nnodes(D), np = D->np;
+  fwd_point f0;
+  int rc = fwd_alloc(&f0, D);
+  double *ubar = (double *)calloc((size_t)nn * d, sizeof(double));
+  double *mbar = (double *)calloc((size_t)nn, sizeof(double));
+  double *vnbar = (double *)calloc((size_t)nn * d, sizeof(double));
+  if (rc || !ubar || !mbar || !vnbar) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
+  fwd_save_particles(&f0, D);
+  {
+    or_solve_stats st;
+    if ((rc = or_p2g(D))) goto done;
+    fwd_save_grid(&f0, D);
+    D->use_schwarz_bc = 0;
+    if ((rc = or_solve(D, dt, opt, &st))) goto done;
+    memcpy(f0.u, D->u, sizeof(double) * nn * d);
+    if ((rc = or_g2p(D, dt))) goto done;
+  }
+  memset(oxb, 0, sizeof(double) * np * d);
+  memset(ovb, 0, sizeof(double) * np * d);
+  memset(oBb, 0, sizeof(double) * np * d * d);
+  memset(oFb, 0, sizeof(double) * np * d * d);
+  {
+    or_domain V = fwd_view(D, &f0);
+    V.use_schwarz_bc = 0;
+    if ((rc = g2p_adjoint(&V, dt, xb, vb, Bb, Fb, ubar, oxb, oFb))) goto done;
+    if ((rc = solve_adjoint(&V, dt, opt->gravity, ubar, adj_cg_rtol, 100000, mbar, vnbar, oxb, oFb, mubar,
+                            lambar, NULL)))
+      goto done;
+    if ((rc = p2g_adjoint(&V, mbar, vnbar, oxb, ovb, oBb))) goto done;
+  }
+done:
+  fwd_free(&f0);
+  free(ubar);
+  free(mbar);
+  free(vnbar);
+  return rc;
+}
+
+/* Adjoint of one Schwarz frame (Alg. 1) of the pair (B, S), which hold the
+ * start-of-frame states on entry and the end-of-frame states on exit.  The
+ * frame is recomputed with exactly `iters` Schwarz iterations (the count of
+ * the forward run), every intermediate stored, then swept in reverse:
+ * coarse G2P; for k = iters-1 .. 0: the projection that fed coarse solve
+ * k+1 (through the fine grid after the last sub-step), the M fine sub-steps
+ * (P2G, G2P, solve with its Schwarz data, T_m) from last to first, the
+ * restore of the stored fine state, both interpolations, v_B = u_B / dT and
+ * coarse solve k with its projected data; finally the projection of Step 0
+ * and the two Step-0 P2Gs.  Inputs xb*, vb*, Bb*, Fb*: adjoint of the
+ * end-of-frame particle states; outputs o* (overwritten): adjoint of the
+ * start-of-frame states; mubar*, lambar* accumulate per material. */
+int or_schwarz_frame_adjoint(or_domain *B, or_domain *S, double dT, const or_schwarz_opts *o, int iters,
+                             double adj_cg_rtol, const double *xbB, const double *vbB, const double *BbB,
+                             const double *FbB, const double *xbS, const double *vbS, const double *BbS,
+                             const double *FbS, double *oxB, double *ovB, double *oBB, double *oFB,
+                             double *oxS, double *ovS, double *oBS, double *oFS, double *mubarB,
+                             double *lambarB, double *mubarS, double *lambarS) {
+  const int d = B->dim, nnB = nnodes(B), nnS = nnodes(S), npB = B->np, npS = S->np, M = o->M;
+  const double dt = dT / (double)M;
+  const int K = iters;
+  if (K < 1 || M < 1) return OR_E_ARG;
+  int rc = OR_OK;
+  fwd_point fB = {0};
+  fwd_point *fS = (fwd_point *)calloc((size_t)K * (M + 1), sizeof(fwd_point));
+  double *uB = (double *)calloc((size_t)K * nnB * d, sizeof(double));
+  double *piB = (double *)calloc((size_t)K * nnB * d, sizeof(double));
+  double *vBk = (double *)malloc(sizeof(double) * nnB * d);
+  double *vGSn = (double *)malloc(sizeof(double) * nnS * d);
+  double *vGSn1 = (double *)malloc(sizeof(double) * nnS * d);
+  double *sx = NULL, *sv = NULL, *sB = NULL, *sF = NULL;
+  adj_state aB = {0}, aS0 = {0}, aS = {0}, aP = {0};
+  double *ubarB = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *ubarBk = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *mbarB = (double *)calloc((size_t)nnB, sizeof(double));
+  double *vnbarB = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *vBkbar = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *pibar = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *pibar_next = (double *)calloc((size_t)nnB * d, sizeof(double));
+  double *ubarS = (double *)calloc((size_t)nnS * d, sizeof(double));
+  double *mbarS = (double *)calloc((size_t)nnS, sizeof(double));
+  double *vnbarS = (double *)calloc((size_t)nnS * d, sizeof(double));
+  double *vbcbar = (double *)calloc((size_t)nnS * d, sizeof(double));
+  double *gSn = (double *)calloc((size_t)nnS * d, sizeof(double));
+  double *gSn1 = (double *)calloc((size_t)nnS * d, sizeof(double));
+  if (!fS || !uB || !piB || !vBk || !vGSn || !vGSn1 || !ubarB || !ubarBk || !mbarB || !vnbarB || !vBkbar ||
+      !pibar || !pibar_next || !ubarS || !mbarS || !vnbarS || !vbcbar || !gSn || !gSn1) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
+  if ((rc = fwd_alloc(&fB, B))) goto done;
+  for (int k = 0; k < K * (M + 1); ++k)
+    if ((rc = fwd_alloc(&fS[k], S))) goto done;
+  if ((rc = adj_alloc(&aB, npB, d)) || (rc = adj_alloc(&aS0, npS, d)) || (rc = adj_alloc(&aS, npS, d)) ||
+      (rc = adj_alloc(&aP, npS, d)))
+    goto done;
+  sx = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d);
+  sv = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d);
+  sB = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d * d);
+  sF = (double *)malloc(sizeof(double) * (size_t)(npS > 0 ? npS : 1) * d * d);
+  if (!sx || !sv || !sB || !sF) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
+
+  /* ---- forward recompute with storage ---- */
+  {
+    int n_amb;
+    or_solve_stats ss;
+    fwd_save_particles(&fB, B);
+    memcpy(sx, S->x, sizeof(double) * npS * d);
+    memcpy(sv, S->v, sizeof(double) * npS * d);
+    memcpy(sB, S->B, sizeof(double) * npS * d * d);
+    memcpy(sF, S->F, sizeof(double) * npS * d * d);
+    if ((rc = or_p2g(B)) || (rc = or_p2g(S))) goto done;
+    fwd_save_grid(&fB, B);
+    if ((rc = or_interface(B, S, &n_amb))) goto done;
+    if ((rc = or_project(S, B, o->eps_tol, S->vn, &piB[0]))) goto done;
+    for (int k = 0; k < K; ++k) {
+      memcpy(B->vbc, &piB[(size_t)k * nnB * d], sizeof(double) * nnB * d);
+      B->use_schwarz_bc = 1;
+      if ((rc = or_solve(B, dT, &o->coarse, &ss))) goto done;
+      memcpy(&uB[(size_t)k * nnB * d], B->u, sizeof(double) * nnB * d);
+      for (int i = 0; i < nnB; ++i)
+        for (int a = 0; a < d; ++a) vBk[i * d + a] = (B->m[i] > 0.0) ? B->u[i * d + a] / dT : 0.0;
+      memcpy(S->x, sx, sizeof(double) * npS * d);
+      memcpy(S->v, sv, sizeof(double) * npS * d);
+      memcpy(S->B, sB, sizeof(double) * npS * d * d);
+      memcpy(S->F, sF, sizeof(double) * npS * d * d);
+      if ((rc = or_p2g(S))) goto done;
+      if ((rc = or_interp(B, fB.vn, S, vGSn))) goto done;
+      if ((rc = or_interp(B, vBk, S, vGSn1))) goto done;
+      for (int m = 1; m <= M; ++m) {
+        fwd_point *f = &fS[k * (M + 1) + (m - 1)];
+        fwd_save_particles(f, S);
+        fwd_save_grid(f, S);
+        or_temporal(nnS * d, m, M, vGSn, vGSn1, S->vbc);
+        memcpy(f->vbc, S->vbc, sizeof(double) * nnS * d);
+        S->use_schwarz_bc = 1;
+        if ((rc = or_solve(S, dt, &o->fine, &ss))) goto done;
+        memcpy(f->u, S->u, sizeof(double) * nnS * d);
+        if ((rc = or_g2p(S, dt))) goto done;
+        if ((rc = or_p2g(S))) goto done;
+      }
+      fwd_point *fl = &fS[k * (M + 1) + M];
+      fwd_save_particles(fl, S);
+      fwd_save_grid(fl, S);
+      if (k + 1 < K)
+        if ((rc = or_project(S, B, o->eps_tol, S->vn, &piB[(size_t)(k + 1) * nnB * d]))) goto done;
+    }
+    memcpy(B->u, &uB[(size_t)(K - 1) * nnB * d], sizeof(double) * nnB * d);
+    if ((rc = or_g2p(B, dT))) goto done;
+  }
+
+  /* ---- reverse sweep ---- */
+  {
+    const double *grB = o->coarse.gravity, *grS = o->fine.gravity;
+    or_domain VB = view_of(B, fB.x, fB.v, fB.B, fB.F, fB.m, fB.vn, &uB[(size_t)(K - 1) * nnB * d]);
+    VB.bcg = fB.bcg;
+    VB.use_schwarz_bc = 1;
+    /* coarse G2P */
+    if ((rc = g2p_adjoint(&VB, dT, xbB, vbB, BbB, FbB, ubarB, aB.x, aB.F))) goto done;
+    for (int k = K - 1; k >= 0; --k) {
+      memset(ubarBk, 0, sizeof(double) * nnB * d);
+      if (k == K - 1) memcpy(ubarBk, ubarB, sizeof(double) * nnB * d);
+      /* adjoint of the fine state after the last sub-step of iteration k */
+      if (k == K - 1) {
+        memcpy(aS.x, xbS, sizeof(double) * npS * d);
+        memcpy(aS.v, vbS, sizeof(double) * npS * d);
+        memcpy(aS.B, BbS, sizeof(double) * npS * d * d);
+        memcpy(aS.F, FbS, sizeof(double) * npS * d * d);
+      } else {
+        adj_zero(&aS, npS, d);
+        /* the projection of this grid fed coarse solve k+1 */
+        or_domain VL = fwd_view(S, &fS[k * (M + 1) + M]);
+        memset(mbarS, 0, sizeof(double) * nnS);
+        memset(vnbarS, 0, sizeof(double) * nnS * d);
+        if ((rc = project_adjoint(&VL, B, o->eps_tol, pibar_next, mbarS, vnbarS))) goto done;
+        if ((rc = p2g_adjoint(&VL, mbarS, vnbarS, aS.x, aS.v, aS.B))) goto done;
+      }
+      memset(gSn, 0, sizeof(double) * nnS * d);
+      memset(gSn1, 0, sizeof(double) * nnS * d);
+      for (int m = M; m >= 1; --m) {
+        fwd_point *f = &fS[k * (M + 1) + (m - 1)];
+        or_domain V = fwd_view(S, f);
+        V.use_schwarz_bc = 1;
+        adj_zero(&aP, npS, d);
+        memset(ubarS, 0, sizeof(double) * nnS * d);
+        if ((rc = g2p_adjoint(&V, dt, aS.x, aS.v, aS.B, aS.F, ubarS, aP.x, aP.F))) goto done;
+        memset(mbarS, 0, sizeof(double) * nnS);
+        memset(vnbarS, 0, sizeof(double) * nnS * d);
+        memset(vbcbar, 0, sizeof(double) * nnS * d);
+        if ((rc = solve_adjoint(&V, dt, grS, ubarS, adj_cg_rtol, 100000, mbarS, vnbarS, aP.x, aP.F, mubarS,
+                                lambarS, vbcbar)))
+          goto done;
+        const double am = (double)m / (double)M;
+        for (int q = 0; q < nnS * d; ++q) {
+          gSn[q] += (1.0 - am) * vbcbar[q];
+          gSn1[q] += am * vbcbar[q];
+        }
+        if ((rc = p2g_adjoint(&V, mbarS, vnbarS, aP.x, aP.v, aP.B))) goto done;
+        adj_state t = aS;
+        aS = aP;
+        aP = t;
+      }
+      /* restore: the stored fine state */
+      for (int q = 0; q < npS * d; ++q) {
+        aS0.x[q] += aS.x[q];
+        aS0.v[q] += aS.v[q];
+      }
+      for (int q = 0; q < npS * d * d; ++q) {
+        aS0.B[q] += aS.B[q];
+        aS0.F[q] += aS.F[q];
+      }
+      /* interpolations: I(v_B^(k+1)) and I(v_B^n) */
+      memset(vBkbar, 0, sizeof(double) * nnB * d);
+      if ((rc = interp_adjoint(&VB, S, gSn1, vBkbar))) goto done;
+      if ((rc = interp_adjoint(&VB, S, gSn, vnbarB))) goto done;
+      for (int i = 0; i < nnB; ++i)
+        if (fB.m[i] > 0.0)
+          for (int a = 0; a < d; ++a) ubarBk[i * d + a] += vBkbar[i * d + a] / dT;
+      /* coarse solve k */
+      VB.u = &uB[(size_t)k * nnB * d];
+      VB.vbc = &piB[(size_t)k * nnB * d];
+      memset(pibar, 0, sizeof(double) * nnB * d);
+      if ((rc = solve_adjoint(&VB, dT, grB, ubarBk, adj_cg_rtol, 100000, mbarB, vnbarB, aB.x, aB.F, mubarB,
+                              lambarB, pibar)))
+        goto done;
+      memcpy(pibar_next, pibar, sizeof(double) * nnB * d);
+    }
+    /* Step 0: projection of the fine start grid, then both P2Gs */
+    {
+      or_domain V0 = fwd_view(S, &fS[0]);
+      memset(mbarS, 0, sizeof(double) * nnS);
+      memset(vnbarS, 0, sizeof(double) * nnS * d);
+      if ((rc = project_adjoint(&V0, B, o->eps_tol, pibar_next, mbarS, vnbarS))) goto done;
+      if ((rc = p2g_adjoint(&V0, mbarS, vnbarS, aS0.x, aS0.v, aS0.B))) goto done;
+    }
+    if ((rc = p2g_adjoint(&VB, mbarB, vnbarB, aB.x, aB.v, aB.B))) goto done;
+    memcpy(oxB, aB.x, sizeof(double) * npB * d);
+    memcpy(ovB, aB.v, sizeof(double) * npB * d);
+    memcpy(oBB, aB.B, sizeof(double) * npB * d * d);
+    memcpy(oFB, aB.F, sizeof(double) * npB * d * d);
+    memcpy(oxS, aS0.x, sizeof(double) * npS * d);
+    memcpy(ovS, aS0.v, sizeof(double) * npS * d);
+    memcpy(oBS, aS0.B, sizeof(double) * npS * d * d);
+    memcpy(oFS, aS0.F, sizeof(double) * npS * d * d);
+  }
+done:
+  if (fS) {
+    for (int k = 0; k < K * (M + 1); ++k) fwd_free(&fS[k]);
+    free(fS);
+  }
+  fwd_free(&fB);
+  free(uB);
+  free(piB);
+  free(vBk);
+  free(vGSn);
+  free(vGSn1);
+  free(sx);
+  free(sv);
+  free(sB);
+  free(sF);
+  adj_free(&aB);
+  adj_free(&aS0);
+  adj_free(&aS);
+  adj_free(&aP);
+  free(ubarB);
+  free(ubarBk);
+  free(mbarB);
+  free(vnbarB);
+  free(vBkbar);
+  free(pibar);
+  free(pibar_next);
+  free(ubarS);
+  free(mbarS);
+  free(vnbarS);
+  free(vbcbar);
+  free(gSn);
+  free(gSn1);
   return rc;
 }
