@@ -293,6 +293,45 @@ osmpm_status osmpm_batch_single_frame(osmpm_batch *batch, double dt, const osmpm
                                       osmpm_solve_stats *stats_host);
 void osmpm_batch_destroy(osmpm_batch *batch);
 
+/* ---------------------------------------------------------------- reverse mode */
+
+/* Adjoints (reverse-mode derivatives) of a frame.  The frame is recomputed
+ * from the domains' current states with its intermediates stored, then swept
+ * in reverse.  Discrete decisions (bins, active nodes, boundary and receiver
+ * sets, the Schwarz iteration count) are held at their forward values; each
+ * implicit solve (Sec. 2.2.5) is differentiated at its minimiser by the
+ * implicit-function theorem (the adjoint system H_ff lambda = ubar_f with the
+ * Hessian of Eq. discrete_energy, not PSD-projected, solved on the forward CG
+ * kernels to adj_cg_rtol); P2G (Eq. p2g_transfer), G2P (Eqs. g2p_v .. advection),
+ * Pi_{S->B} (Eq. spatial_projection), I_{B->S} (Eq. interp_BtoS) and T_m
+ * (Eq. temporal_interp) are transposed exactly, including the dependence of
+ * the weights on particle positions.
+ *
+ * Adjoint arrays are device FP64 in the caller's layout and particle order of
+ * the last osmpm_domain_set_particles: x, v [n][d], B, F [n][d][d].  Inputs:
+ * the adjoint of the end-of-frame state; outputs (overwritten): the adjoint of
+ * the start-of-frame state.  mubar / lambar (host, [n_mat] of each domain) ACCUMULATE
+ * the derivative with respect to the Lame parameters of each material.  On
+ * return the domains hold the end-of-frame state (as after the forward call).
+ * Synchronises.  All arithmetic of the reverse sweep is FP64; in the mixed
+ * path the stored forward states and the adjoint CG vectors are FP32. */
+osmpm_status osmpm_single_frame_adjoint(osmpm_domain *dom, double dt, const osmpm_solve_opts *opts,
+                                        double adj_cg_rtol, const double *xbar, const double *vbar,
+                                        const double *Bbar, const double *Fbar, double *xbar_out,
+                                        double *vbar_out, double *Bbar_out, double *Fbar_out,
+                                        double *mubar_host, double *lambar_host);
+/* The frame of osmpm_schwarz_frame on the pair (B, S) with exactly `iters`
+ * Schwarz iterations (the forward call's stats.iters). */
+osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, double dT,
+                                         const osmpm_schwarz_opts *opts, int32_t iters, double adj_cg_rtol,
+                                         const double *xbar_B, const double *vbar_B, const double *Bbar_B,
+                                         const double *Fbar_B, const double *xbar_S, const double *vbar_S,
+                                         const double *Bbar_S, const double *Fbar_S, double *xbar_B_out,
+                                         double *vbar_B_out, double *Bbar_B_out, double *Fbar_B_out,
+                                         double *xbar_S_out, double *vbar_S_out, double *Bbar_S_out,
+                                         double *Fbar_S_out, double *mubar_B_host, double *lambar_B_host,
+                                         double *mubar_S_host, double *lambar_S_host);
+
 /* ---------------------------------------------------------------- readback */
 
 /* Particle state in the library's current order; id receives each

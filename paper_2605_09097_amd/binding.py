@@ -32,6 +32,7 @@ ABI_SYMBOLS = [
     "osmpm_schwarz_frame", "osmpm_single_frame", "osmpm_get_particles", "osmpm_get_grid",
     "osmpm_get_sets", "osmpm_get_sort", "osmpm_domain_info",
     "osmpm_batch_create", "osmpm_batch_schwarz_frame", "osmpm_batch_single_frame", "osmpm_batch_destroy",
+    "osmpm_single_frame_adjoint", "osmpm_schwarz_frame_adjoint",
 ]
 
 
@@ -105,6 +106,10 @@ def _declare(L):
         "osmpm_batch_create": [_vp, C.c_int32, P(_vp), P(_vp), P(_vp)],
         "osmpm_batch_schwarz_frame": [_vp, C.c_double, P(osmpm_schwarz_opts), P(osmpm_schwarz_stats)],
         "osmpm_batch_single_frame": [_vp, C.c_double, P(osmpm_solve_opts), P(osmpm_solve_stats)],
+        "osmpm_single_frame_adjoint": [_vp, C.c_double, P(osmpm_solve_opts), C.c_double] + [_vp] * 8
+                                      + [P(C.c_double)] * 2,
+        "osmpm_schwarz_frame_adjoint": [_vp, _vp, C.c_double, P(osmpm_schwarz_opts), C.c_int32, C.c_double]
+                                       + [_vp] * 16 + [P(C.c_double)] * 4,
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -230,6 +235,7 @@ class Domain:
         ctx.check(lib().osmpm_domain_create(ctx.handle, C.byref(g), precision, cap, t, C.byref(h)),
                   "domain_create")
         self.handle = h
+        self.n_mat = len(spec.E)
         mats = (osmpm_material * len(spec.E))(*[osmpm_material(float(E), float(nu))
                                                   for E, nu in zip(spec.E, spec.nu)])
         ctx.check(lib().osmpm_domain_set_materials(h, mats, len(spec.E)), "set_materials")
@@ -253,6 +259,13 @@ class Domain:
         self.n = n
         self.ctx.check(lib().osmpm_domain_set_particles(self.handle, n, _ptr(x), _ptr(v), _ptr(B), _ptr(F),
                                                         _ptr(m), _ptr(V), _ptr(mat), _ptr(fl)), "set_particles")
+
+    def set_materials(self, E, nu):
+        """Young's moduli and Poisson ratios per material (Lame parameters by
+        the textbook relations)."""
+        mats = (osmpm_material * len(E))(*[osmpm_material(float(a), float(b)) for a, b in zip(E, nu)])
+        self.ctx.check(lib().osmpm_domain_set_materials(self.handle, mats, len(E)), "set_materials")
+        self.n_mat = len(E)
 
     def set_bc_params(self, params):
         p = np.zeros((max(self.n_groups, 1), 8))
@@ -449,3 +462,56 @@ class SchwarzBatch:
         self.batch.close()
         for p in self.pairs:
             p.close()
+
+
+# ---------------------------------------------------------------- reverse mode
+def _adj_in(D, adj):
+    """Device FP64 copies of an adjoint state dict (zeros where absent), in
+    the caller's layout and input particle order."""
+    torch = D.ctx.torch
+    dev, d, n = D.ctx.device, D.dim, D.n
+    out = []
+    for k, shape in (("x", (n, d)), ("v", (n, d)), ("B", (n, d, d)), ("F", (n, d, d))):
+        a = None if adj is None else adj.get(k)
+        t = torch.zeros(shape, dtype=torch.float64, device=dev) if a is None else \
+            torch.as_tensor(np.asarray(a, dtype=np.float64) if not hasattr(a, "device") else a).to(
+                device=dev, dtype=torch.float64).reshape(shape).contiguous()
+        out.append(t)
+    return out
+
+
+def _adj_out(D):
+    torch = D.ctx.torch
+    dev, d, n = D.ctx.device, D.dim, D.n
+    return [torch.zeros(s, dtype=torch.float64, device=dev) for s in ((n, d), (n, d), (n, d, d), (n, d, d))]
+
+
+def single_frame_adjoint(D: Domain, dt, opts, adj_end, adj_cg_rtol=1e-12):
+    """Adjoint of one single-domain frame from D's current state (see
+    osmpm_single_frame_adjoint).  Returns ({x, v, B, F} adjoint of the start
+    state as device tensors, dL/dmu, dL/dlam per material as numpy arrays)."""
+    a = _adj_in(D, adj_end)
+    o = _adj_out(D)
+    nm = D.n_mat
+    mub = (C.c_double * nm)()
+    lab = (C.c_double * nm)()
+    D.ctx.check(lib().osmpm_single_frame_adjoint(D.handle, dt, C.byref(opts), adj_cg_rtol, *[_ptr(t) for t in a],
+                                                 *[_ptr(t) for t in o], mub, lab), "single_frame_adjoint")
+    return dict(zip("xvBF", o)), np.array(mub[:]), np.array(lab[:])
+
+
+def schwarz_frame_adjoint(B: Domain, S: Domain, dT, opts, iters, adjB_end, adjS_end, adj_cg_rtol=1e-12):
+    """Adjoint of one Schwarz frame with `iters` iterations from the pair's
+    current states (see osmpm_schwarz_frame_adjoint).  Returns (adjoint of
+    B's start state, of S's start state, dL/dmu_B, dL/dlam_B, dL/dmu_S,
+    dL/dlam_S)."""
+    aB, aS = _adj_in(B, adjB_end), _adj_in(S, adjS_end)
+    oB, oS = _adj_out(B), _adj_out(S)
+    mB, lB = (C.c_double * B.n_mat)(), (C.c_double * B.n_mat)()
+    mS, lS = (C.c_double * S.n_mat)(), (C.c_double * S.n_mat)()
+    B.ctx.check(lib().osmpm_schwarz_frame_adjoint(B.handle, S.handle, dT, C.byref(opts), int(iters), adj_cg_rtol,
+                                                  *[_ptr(t) for t in aB], *[_ptr(t) for t in aS],
+                                                  *[_ptr(t) for t in oB], *[_ptr(t) for t in oS], mB, lB, mS, lS),
+                "schwarz_frame_adjoint")
+    return (dict(zip("xvBF", oB)), dict(zip("xvBF", oS)), np.array(mB[:]), np.array(lB[:]), np.array(mS[:]),
+            np.array(lS[:]))

@@ -1032,6 +1032,466 @@ bool pair_ok(const osmpm_domain *B, const osmpm_domain *S) {
          B->precision == S->precision;
 }
 
+// ---------------------------------------------------------------- reverse mode
+// Stored forward state of one domain at one point of a frame: the particle
+// arrays in their sorted order (as the kernels of that point saw them), the
+// bins, the grid from their P2G, the scene-BC mask and, for a point that
+// starts a solve, its solution and Schwarz data.
+struct TapePoint {
+  std::vector<void *> allocs;
+  PartPtrs p{};
+  int *cell_start = nullptr;
+  double *m = nullptr, *vn = nullptr, *u = nullptr, *vbc = nullptr;
+  int8_t *bcg = nullptr;
+};
+
+void tape_free(TapePoint &t) {
+  for (void *q : t.allocs) (void)hipFree(q);
+  t.allocs.clear();
+}
+
+osmpm_status tape_alloc(osmpm_domain *d, TapePoint &t) {
+  osmpm_ctx *c = d->ctx;
+  const size_t cap = (size_t)d->cap, nn = (size_t)d->g.nn, nd = nn * d->D;
+  const int D = d->D;
+  osmpm_status s = OSMPM_OK;
+  void *q = nullptr;
+  auto al = [&](size_t bytes) -> void * {
+    if (s) return nullptr;
+    s = dalloc_bytes(c, t.allocs, &q, bytes);
+    return s ? nullptr : q;
+  };
+  t.p.x = (double *)al(cap * D * sizeof(double));
+  t.p.v = al(cap * D * d->tb);
+  t.p.B = al(cap * D * D * d->tb);
+  t.p.F = al(cap * D * D * d->tb);
+  t.p.mass = (double *)al(cap * sizeof(double));
+  t.p.vol = (double *)al(cap * sizeof(double));
+  t.p.mat = (int *)al(cap * sizeof(int));
+  t.p.id = (int *)al(cap * sizeof(int));
+  t.p.flags = (uint8_t *)al(cap);
+  t.cell_start = (int *)al(((size_t)d->nk + 1) * sizeof(int));
+  t.m = (double *)al(nn * sizeof(double));
+  t.vn = (double *)al(nd * sizeof(double));
+  t.u = (double *)al(nd * sizeof(double));
+  t.vbc = (double *)al(nd * sizeof(double));
+  t.bcg = (int8_t *)al(nd);
+  if (s) tape_free(t);
+  return s;
+}
+
+// Copies between the domain's current buffers and a tape point; `dir` > 0
+// saves, < 0 loads.  what: bit 0 particles and bins, bit 1 grid, bit 2 the
+// solution u, bit 3 the Schwarz data.
+osmpm_status tape_copy(osmpm_domain *d, TapePoint &t, int dir, int what) {
+  osmpm_ctx *c = d->ctx;
+  const size_t cap = (size_t)d->cap, nn = (size_t)d->g.nn, nd = nn * d->D;
+  const int D = d->D;
+  PartPtrs &cp = d->pb[d->cur];
+  auto cpy = [&](void *dev, void *tp, size_t bytes) -> hipError_t {
+    return dir > 0 ? hipMemcpyAsync(tp, dev, bytes, hipMemcpyDeviceToDevice, c->stream)
+                   : hipMemcpyAsync(dev, tp, bytes, hipMemcpyDeviceToDevice, c->stream);
+  };
+  if (what & 1) {
+    HIP_TRY(c, cpy(cp.x, t.p.x, cap * D * sizeof(double)));
+    HIP_TRY(c, cpy(cp.v, t.p.v, cap * D * d->tb));
+    HIP_TRY(c, cpy(cp.B, t.p.B, cap * D * D * d->tb));
+    HIP_TRY(c, cpy(cp.F, t.p.F, cap * D * D * d->tb));
+    HIP_TRY(c, cpy(cp.mass, t.p.mass, cap * sizeof(double)));
+    HIP_TRY(c, cpy(cp.vol, t.p.vol, cap * sizeof(double)));
+    HIP_TRY(c, cpy(cp.mat, t.p.mat, cap * sizeof(int)));
+    HIP_TRY(c, cpy(cp.id, t.p.id, cap * sizeof(int)));
+    HIP_TRY(c, cpy(cp.flags, t.p.flags, cap));
+    HIP_TRY(c, cpy(d->cell_start, t.cell_start, ((size_t)d->nk + 1) * sizeof(int)));
+  }
+  if (what & 2) {
+    HIP_TRY(c, cpy(d->m, t.m, nn * sizeof(double)));
+    HIP_TRY(c, cpy(d->vn, t.vn, nd * sizeof(double)));
+    HIP_TRY(c, cpy(d->bcg, t.bcg, nd));
+  }
+  if (what & 4) HIP_TRY(c, cpy(d->u, t.u, nd * sizeof(double)));
+  if (what & 8) HIP_TRY(c, cpy(d->vbc, t.vbc, nd * sizeof(double)));
+  return OSMPM_OK;
+}
+
+// Particle adjoint in particle-id order, component-major [component][np].
+struct AdjState {
+  double *x = nullptr, *v = nullptr, *B = nullptr, *F = nullptr;
+};
+
+osmpm_status adj_alloc(osmpm_ctx *c, std::vector<void *> &list, int np, int D, AdjState &a) {
+  void *q = nullptr;
+  const size_t n = (size_t)std::max(np, 1);
+  osmpm_status s;
+  if ((s = dalloc_bytes(c, list, &q, n * D * sizeof(double)))) return s;
+  a.x = (double *)q;
+  if ((s = dalloc_bytes(c, list, &q, n * D * sizeof(double)))) return s;
+  a.v = (double *)q;
+  if ((s = dalloc_bytes(c, list, &q, n * D * D * sizeof(double)))) return s;
+  a.B = (double *)q;
+  if ((s = dalloc_bytes(c, list, &q, n * D * D * sizeof(double)))) return s;
+  a.F = (double *)q;
+  return OSMPM_OK;
+}
+
+osmpm_status adj_zero(osmpm_ctx *c, const AdjState &a, int np, int D) {
+  const size_t n = (size_t)std::max(np, 1);
+  HIP_TRY(c, hipMemsetAsync(a.x, 0, n * D * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(a.v, 0, n * D * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(a.B, 0, n * D * D * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(a.F, 0, n * D * D * sizeof(double), c->stream));
+  return OSMPM_OK;
+}
+
+osmpm_status zero_bytes(osmpm_ctx *c, void *p, size_t bytes) {
+  HIP_TRY(c, hipMemsetAsync(p, 0, bytes, c->stream));
+  return OSMPM_OK;
+}
+
+// Caller layout ([n][d], [n][d][d] rows in input order) <-> component-major.
+void adj_from_rows(osmpm_ctx *c, int np, int D, const double *x, const double *v, const double *B, const double *F,
+                   const AdjState &a) {
+  const dim3 gb(blocks_for((int64_t)np * D * D, 2048)), blk(kBlock);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D, x, a.x, (int64_t)np);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D, v, a.v, (int64_t)np);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D * D, B, a.B, (int64_t)np);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D * D, F, a.F, (int64_t)np);
+}
+void adj_to_rows(osmpm_ctx *c, int np, int D, const AdjState &a, double *x, double *v, double *B, double *F) {
+  const dim3 gb(blocks_for((int64_t)np * D * D, 2048)), blk(kBlock);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D, (const double *)a.x, (int64_t)np, x);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D, (const double *)a.v, (int64_t)np, v);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D * D, (const double *)a.B, (int64_t)np, B);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D * D, (const double *)a.F, (int64_t)np, F);
+}
+
+// P2G transposed on a stored point of domain d.
+template <int D, typename TB>
+void adj_p2g(osmpm_domain *d, const TapePoint &t, const double *mbar, const double *vnbar, const AdjState &a) {
+  if (d->np == 0) return;
+  launch(d->ctx, -1, 0, -1, k_adj_p2g<D, TB>, dim3(blocks_for(d->np)), dim3(kBlock), 0, d->g, d->np, d->cap,
+         (const double *)t.p.x, (const TB *)t.p.v, (const TB *)t.p.B, (const double *)t.p.mass, (const int *)t.p.id,
+         (const double *)t.m, (const double *)t.vn, mbar, vnbar, a.x, a.v, a.B);
+}
+
+// G2P transposed on a stored point (state before G2P, its grid, u).
+template <int D, typename TB>
+void adj_g2p(osmpm_domain *d, const TapePoint &t, const double *u, double dt, const AdjState &in, double *ubar,
+             const AdjState &out) {
+  if (d->np == 0) return;
+  launch(d->ctx, -1, 0, -1, k_adj_g2p<D, TB>, dim3(blocks_for(d->np)), dim3(kBlock), 0, d->g, d->np, d->cap,
+         (const double *)t.p.x, (const TB *)t.p.F, (const int *)t.p.id, (const double *)t.m, u, dt,
+         (const double *)in.x, (const double *)in.v, (const double *)in.B, (const double *)in.F, ubar, out.x,
+         out.F);
+}
+
+// Adjoint of the implicit solve of side s of a group of one, whose current
+// buffers hold the stored point (particles, bins, grid, scene-BC mask) and
+// whose solution is u_tape.  The tangents are rebuilt at the solution
+// without PSD projection, H_ff lambda = ubar_f is solved on the forward CG
+// kernels, and the input terms are scattered.
+template <int D, typename TB>
+osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const osmpm_solve_opts *o,
+                       double adj_rtol, const double *u_tape, const double *ubar, double *mbar, double *vnbar,
+                       double *vbcbar, double *hl, const AdjState &a, double *mubar, double *lambar) {
+  osmpm_ctx *c = G->c;
+  osmpm_domain *d = G->dom[s][0];
+  const Ext &E = G->ext[s];
+  const DomDesc *dd = G->dd[s];
+  const int n = G->n, nd = d->g.nn * d->D;
+  const dim3 blk(kBlock);
+  set_active(G, s, std::vector<int>(n, 1));
+  launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, kBufVbc);
+  HIP_TRY(c, hipMemcpyAsync(d->u, u_tape, (size_t)nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt);
+  launch(c, -1, 0, -1, k_grad_hess<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_grad, dd, 0, G->err);
+  launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
+         o->gravity[2]);
+  launch(c, -1, 0, -1, k_adj_set_rhs, dim3(E.node_blocks, n), blk, 0, dd, ubar);
+  launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd);
+  const int max_cg = 20000, chunk = 16;
+  osmpm_status st;
+  for (int launched = 0;; launched += chunk) {
+    for (int j = 0; j < chunk; ++j)
+      launch(c, -1, 0, -1, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt, adj_rtol,
+             max_cg);
+    if ((st = read_status(G))) return st;
+    if (h_cg(G, s)[0].done) break;
+    if (launched > max_cg + chunk) return fail(c, OSMPM_E_STATE, "adjoint CG did not terminate");
+  }
+  if ((st = zero_bytes(c, hl, (size_t)nd * sizeof(double)))) return st;
+  if (d->np > 0)
+    launch(c, -1, 0, -1, k_adj_hvp<D, TB>, dim3(blocks_for(d->np), n), blk, 0, dd, (const TB *)d->del, hl);
+  launch(c, -1, 0, -1, k_adj_solve_nodes<D, TB>, dim3(blocks_for(d->g.nn), n), blk, 0, dd, dt, o->gravity[0],
+         o->gravity[1], o->gravity[2], ubar, (const double *)hl, use_schwarz, mbar, vnbar, vbcbar);
+  if (d->np > 0)
+    launch(c, -1, 0, -1, k_adj_solve_particles<D, TB>, dim3(blocks_for(d->np), n), blk, 0, dd, a.x, a.F, d->np,
+           mubar, lambar);
+  return check_launch(c);
+}
+
+// Adjoint of one single-domain frame (P2G, solve, G2P) of d; see the ABI.
+template <int D, typename TB>
+osmpm_status single_adjoint_impl(osmpm_domain *d, double dt, const osmpm_solve_opts *o, double adj_rtol,
+                                 const double *const *in, double *const *out, double *mubar_h, double *lambar_h) {
+  osmpm_ctx *c = d->ctx;
+  osmpm_batch *G = d->solo;
+  osmpm_status s;
+  if ((s = group_sync(G))) return s;
+  set_active(G, 0, std::vector<int>(1, 1));
+  const int np = d->np, nn = d->g.nn, nd = nn * D;
+  std::vector<void *> mem;
+  TapePoint t0, te;
+  AdjState ain, aout;
+  double *ubar = nullptr, *mbar = nullptr, *vnbar = nullptr, *hl = nullptr, *mat = nullptr;
+  auto cleanup = [&]() {
+    tape_free(t0);
+    tape_free(te);
+    for (void *q : mem) (void)hipFree(q);
+  };
+  void *q = nullptr;
+  if ((s = tape_alloc(d, t0)) || (s = tape_alloc(d, te)) || (s = adj_alloc(c, mem, np, D, ain)) ||
+      (s = adj_alloc(c, mem, np, D, aout))) {
+    cleanup();
+    return s;
+  }
+  for (double **pp : {&ubar, &vnbar, &hl}) {
+    if ((s = dalloc_bytes(c, mem, &q, (size_t)nd * sizeof(double)))) {
+      cleanup();
+      return s;
+    }
+    *pp = (double *)q;
+  }
+  if ((s = dalloc_bytes(c, mem, &q, (size_t)nn * sizeof(double))) ||
+      (mbar = (double *)q, s = dalloc_bytes(c, mem, &q, 128 * sizeof(double)))) {
+    cleanup();
+    return s;
+  }
+  mat = (double *)q;
+  // forward with storage
+  p2g_side<D, TB>(G, 0, false);
+  if ((s = tape_copy(d, t0, 1, 1 | 2))) return cleanup(), s;
+  std::vector<osmpm_solve_stats> ss;
+  if ((s = solve_side<D, TB>(G, 0, dt, 0, kBufVbc, o, &ss))) return cleanup(), s;
+  if ((s = tape_copy(d, t0, 1, 4))) return cleanup(), s;
+  g2p_side<D, TB>(G, 0, dt);
+  if ((s = tape_copy(d, te, 1, 1 | 2 | 4))) return cleanup(), s;
+  // reverse
+  adj_from_rows(c, np, D, in[0], in[1], in[2], in[3], ain);
+  if ((s = adj_zero(c, aout, np, D)) || (s = zero_bytes(c, ubar, (size_t)nd * 8)) ||
+      (s = zero_bytes(c, mbar, (size_t)nn * 8)) || (s = zero_bytes(c, vnbar, (size_t)nd * 8)) ||
+      (s = zero_bytes(c, mat, 128 * 8)))
+    return cleanup(), s;
+  adj_g2p<D, TB>(d, t0, t0.u, dt, ain, ubar, aout);
+  if ((s = tape_copy(d, t0, -1, 1 | 2))) return cleanup(), s;
+  if ((s = adj_solve<D, TB>(G, 0, dt, 0, o, adj_rtol, t0.u, ubar, mbar, vnbar, nullptr, hl, aout, mat, mat + 64)))
+    return cleanup(), s;
+  adj_p2g<D, TB>(d, t0, mbar, vnbar, aout);
+  if ((s = tape_copy(d, te, -1, 1 | 2 | 4))) return cleanup(), s;
+  adj_to_rows(c, np, D, aout, out[0], out[1], out[2], out[3]);
+  std::vector<double> hm(128);
+  HIP_TRY(c, hipMemcpyAsync(hm.data(), mat, 128 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if ((s = read_status(G))) return cleanup(), s;
+  for (int k = 0; k < d->n_mat; ++k) {
+    mubar_h[k] += hm[k];
+    lambar_h[k] += hm[64 + k];
+  }
+  cleanup();
+  return OSMPM_OK;
+}
+
+// Adjoint of one Schwarz frame of the pair (B, S) with exactly K Schwarz
+// iterations (the forward's count): the frame is recomputed with storage and
+// swept in reverse in the order of the oracle's reverse mode; see the ABI.
+template <int D, typename TB>
+osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz_opts *o, int K, double adj_rtol,
+                                  const double *const *inB, const double *const *inS, double *const *outB,
+                                  double *const *outS, double *mat_h) {
+  osmpm_ctx *c = G->c;
+  osmpm_domain *B = G->dom[0][0], *S = G->dom[1][0];
+  const int M = o->M;
+  const double dt = dT / (double)M;
+  const int npB = B->np, npS = S->np, nnB = B->g.nn, nnS = S->g.nn, ndB = nnB * D, ndS = nnS * D;
+  osmpm_status s;
+  if ((s = group_sync(G))) return s;
+  std::vector<void *> mem;
+  TapePoint tB0, tBe;
+  std::vector<TapePoint> tS((size_t)K * (M + 1));
+  auto cleanup = [&]() {
+    tape_free(tB0);
+    tape_free(tBe);
+    for (TapePoint &t : tS) tape_free(t);
+    for (void *q : mem) (void)hipFree(q);
+  };
+  void *q = nullptr;
+  auto dbl = [&](size_t n, double **pp) -> osmpm_status {
+    osmpm_status r = dalloc_bytes(c, mem, &q, std::max<size_t>(n, 1) * sizeof(double));
+    if (!r) *pp = (double *)q;
+    return r;
+  };
+  double *uB = nullptr, *piB = nullptr, *ubarB = nullptr, *ubarBk = nullptr, *mbarB = nullptr, *vnbarB = nullptr,
+         *vBkbar = nullptr, *pibar = nullptr, *pibar_next = nullptr, *hlB = nullptr, *ubarS = nullptr,
+         *mbarS = nullptr, *vnbarS = nullptr, *vbcbar = nullptr, *gSn = nullptr, *gSn1 = nullptr, *hlS = nullptr,
+         *mat = nullptr;
+  AdjState aBin, aBo, aSin, aS, aP, aS0;
+  if ((s = tape_alloc(B, tB0)) || (s = tape_alloc(B, tBe)) || (s = dbl((size_t)K * ndB, &uB)) ||
+      (s = dbl((size_t)K * ndB, &piB)) || (s = dbl(ndB, &ubarB)) || (s = dbl(ndB, &ubarBk)) ||
+      (s = dbl(nnB, &mbarB)) || (s = dbl(ndB, &vnbarB)) || (s = dbl(ndB, &vBkbar)) || (s = dbl(ndB, &pibar)) ||
+      (s = dbl(ndB, &pibar_next)) || (s = dbl(ndB, &hlB)) || (s = dbl(ndS, &ubarS)) || (s = dbl(nnS, &mbarS)) ||
+      (s = dbl(ndS, &vnbarS)) || (s = dbl(ndS, &vbcbar)) || (s = dbl(ndS, &gSn)) || (s = dbl(ndS, &gSn1)) ||
+      (s = dbl(ndS, &hlS)) || (s = dbl(256, &mat)) || (s = adj_alloc(c, mem, npB, D, aBin)) ||
+      (s = adj_alloc(c, mem, npB, D, aBo)) || (s = adj_alloc(c, mem, npS, D, aSin)) ||
+      (s = adj_alloc(c, mem, npS, D, aS)) || (s = adj_alloc(c, mem, npS, D, aP)) ||
+      (s = adj_alloc(c, mem, npS, D, aS0))) {
+    cleanup();
+    return s;
+  }
+  for (TapePoint &t : tS)
+    if ((s = tape_alloc(S, t))) return cleanup(), s;
+  const DomDesc *ddB = G->dd[0], *ddS = G->dd[1];
+  const dim3 blk(kBlock);
+
+  // ---- forward recompute with storage
+  set_all_active(G);
+  copy_state_side<D, TB>(G, 1, 1);
+  p2g_side<D, TB>(G, 0, true);
+  p2g_side<D, TB>(G, 1, true);
+  if ((s = tape_copy(B, tB0, 1, 1 | 2))) return cleanup(), s;
+  interface_group<D>(G);
+  project_group<D>(G, o->eps_tol, nullptr, 0, nullptr);
+  HIP_TRY(c, hipMemcpyAsync(piB, B->w0, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+  for (int k = 0; k < K; ++k) {
+    HIP_TRY(c, hipMemcpyAsync(B->w0, piB + (size_t)k * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+    if ((s = solve_side<D, TB>(G, 0, dT, 1, 0, &o->coarse, nullptr))) return cleanup(), s;
+    HIP_TRY(c, hipMemcpyAsync(uB + (size_t)k * ndB, B->u, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+    launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(nnB), 1), blk, 0, ddB, dT);
+    copy_state_side<D, TB>(G, 1, 0);
+    p2g_side<D, TB>(G, 1, false);
+    TapePoint &t0 = tS[(size_t)k * (M + 1)];
+    if ((s = tape_copy(S, t0, 1, 1 | 2))) return cleanup(), s;
+    interp_group<D>(G, kBufVn, nullptr, 0, nullptr);
+    interp_group<D>(G, 2, nullptr, 1, nullptr);
+    for (int m = 1; m <= M; ++m) {
+      TapePoint &tp = tS[(size_t)k * (M + 1) + (m - 1)];
+      launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(ndS, 1024), 1), blk, 0, ddS, (double)m / (double)M, 0, 1);
+      if ((s = tape_copy(S, tp, 1, 8))) return cleanup(), s;
+      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, nullptr))) return cleanup(), s;
+      if ((s = tape_copy(S, tp, 1, 4))) return cleanup(), s;
+      g2p_side<D, TB>(G, 1, dt);
+      p2g_side<D, TB>(G, 1, false);
+      if ((s = tape_copy(S, tS[(size_t)k * (M + 1) + m], 1, 1 | 2))) return cleanup(), s;
+    }
+    if (k + 1 < K) {
+      project_group<D>(G, o->eps_tol, nullptr, 0, nullptr);
+      HIP_TRY(c, hipMemcpyAsync(piB + (size_t)(k + 1) * ndB, B->w0, (size_t)ndB * 8, hipMemcpyDeviceToDevice,
+                                c->stream));
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(B->u, uB + (size_t)(K - 1) * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+  g2p_side<D, TB>(G, 0, dT);
+  if ((s = tape_copy(B, tBe, 1, 1 | 2 | 4))) return cleanup(), s;
+  if ((s = read_status(G))) return cleanup(), s;
+
+  // ---- reverse sweep (adjoints in particle-id order)
+  adj_from_rows(c, npB, D, inB[0], inB[1], inB[2], inB[3], aBin);
+  adj_from_rows(c, npS, D, inS[0], inS[1], inS[2], inS[3], aSin);
+  if ((s = adj_zero(c, aBo, npB, D)) || (s = adj_zero(c, aS0, npS, D)) || (s = zero_bytes(c, ubarB, ndB * 8)) ||
+      (s = zero_bytes(c, mbarB, nnB * 8)) || (s = zero_bytes(c, vnbarB, ndB * 8)) ||
+      (s = zero_bytes(c, pibar_next, ndB * 8)) || (s = zero_bytes(c, mat, 256 * 8)))
+    return cleanup(), s;
+  adj_g2p<D, TB>(B, tB0, uB + (size_t)(K - 1) * ndB, dT, aBin, ubarB, aBo);
+  const int64_t nsS = (int64_t)npS * (2 * D + 2 * D * D);
+  for (int k = K - 1; k >= 0; --k) {
+    if (k == K - 1) {
+      HIP_TRY(c, hipMemcpyAsync(ubarBk, ubarB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+      for (int f = 0; f < 4; ++f) {
+        const size_t bytes = (size_t)std::max(npS, 1) * (f < 2 ? D : D * D) * 8;
+        const double *src = f == 0 ? aSin.x : f == 1 ? aSin.v : f == 2 ? aSin.B : aSin.F;
+        double *dst = f == 0 ? aS.x : f == 1 ? aS.v : f == 2 ? aS.B : aS.F;
+        HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream));
+      }
+    } else {
+      if ((s = zero_bytes(c, ubarBk, ndB * 8)) || (s = adj_zero(c, aS, npS, D))) return cleanup(), s;
+      // the projection of the grid after the last sub-step fed coarse solve k+1
+      TapePoint &tl = tS[(size_t)k * (M + 1) + M];
+      if ((s = tape_copy(S, tl, -1, 2))) return cleanup(), s;
+      launch(c, -1, 0, -1, k_zero_proj, dim3(blocks_for(ndB, 1024), 1), blk, 0, ddB);
+      launch(c, -1, 0, -1, k_project_scatter<D>, dim3(blocks_for(nnS), 1), blk, 0, ddS, ddB, (const double *)nullptr,
+             G->err);
+      if ((s = zero_bytes(c, mbarS, nnS * 8)) || (s = zero_bytes(c, vnbarS, ndS * 8))) return cleanup(), s;
+      launch(c, -1, 0, -1, k_adj_project<D>, dim3(blocks_for(nnS)), blk, 0, B->g, S->g, (const double *)tl.m,
+             (const double *)tl.vn, (const uint8_t *)B->recv, (const double *)B->pnum, (const double *)B->pden,
+             o->eps_tol, (const double *)pibar_next, mbarS, vnbarS);
+      adj_p2g<D, TB>(S, tl, mbarS, vnbarS, aS);
+    }
+    if ((s = zero_bytes(c, gSn, ndS * 8)) || (s = zero_bytes(c, gSn1, ndS * 8))) return cleanup(), s;
+    for (int m = M; m >= 1; --m) {
+      TapePoint &tp = tS[(size_t)k * (M + 1) + (m - 1)];
+      if ((s = adj_zero(c, aP, npS, D)) || (s = zero_bytes(c, ubarS, ndS * 8))) return cleanup(), s;
+      adj_g2p<D, TB>(S, tp, tp.u, dt, aS, ubarS, aP);
+      if ((s = tape_copy(S, tp, -1, 1 | 2 | 8))) return cleanup(), s;
+      if ((s = zero_bytes(c, mbarS, nnS * 8)) || (s = zero_bytes(c, vnbarS, ndS * 8)) ||
+          (s = zero_bytes(c, vbcbar, ndS * 8)))
+        return cleanup(), s;
+      if ((s = adj_solve<D, TB>(G, 1, dt, 1, &o->fine, adj_rtol, tp.u, ubarS, mbarS, vnbarS, vbcbar, hlS, aP,
+                                mat + 128, mat + 192)))
+        return cleanup(), s;
+      launch(c, -1, 0, -1, k_adj_temporal, dim3(blocks_for(ndS, 1024)), blk, 0, (int64_t)ndS, (double)m / (double)M,
+             (const double *)vbcbar, gSn, gSn1);
+      adj_p2g<D, TB>(S, tp, mbarS, vnbarS, aP);
+      std::swap(aS, aP);
+    }
+    // restore of the stored fine state
+    launch(c, -1, 0, -1, k_axpy_d, dim3(blocks_for(nsS, 2048)), blk, 0, (int64_t)npS * D, 1.0, (const double *)aS.x,
+           aS0.x);
+    launch(c, -1, 0, -1, k_axpy_d, dim3(blocks_for(nsS, 2048)), blk, 0, (int64_t)npS * D, 1.0, (const double *)aS.v,
+           aS0.v);
+    launch(c, -1, 0, -1, k_axpy_d, dim3(blocks_for(nsS, 2048)), blk, 0, (int64_t)npS * D * D, 1.0,
+           (const double *)aS.B, aS0.B);
+    launch(c, -1, 0, -1, k_axpy_d, dim3(blocks_for(nsS, 2048)), blk, 0, (int64_t)npS * D * D, 1.0,
+           (const double *)aS.F, aS0.F);
+    // interpolations I(v_B^(k+1)) and I(v_B^n)
+    if ((s = zero_bytes(c, vBkbar, ndB * 8))) return cleanup(), s;
+    launch(c, -1, 0, -1, k_adj_interp<D>, dim3(blocks_for(nnS)), blk, 0, B->g, S->g, (const double *)tB0.m,
+           (const uint8_t *)S->recv, (const double *)gSn1, vBkbar);
+    launch(c, -1, 0, -1, k_adj_interp<D>, dim3(blocks_for(nnS)), blk, 0, B->g, S->g, (const double *)tB0.m,
+           (const uint8_t *)S->recv, (const double *)gSn, vnbarB);
+    launch(c, -1, 0, -1, k_adj_vel<D>, dim3(blocks_for(nnB)), blk, 0, nnB, (const double *)tB0.m,
+           (const double *)vBkbar, dT, ubarBk);
+    // coarse solve k
+    if ((s = tape_copy(B, tB0, -1, 1 | 2))) return cleanup(), s;
+    HIP_TRY(c, hipMemcpyAsync(B->vbc, piB + (size_t)k * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+    if ((s = zero_bytes(c, pibar, ndB * 8))) return cleanup(), s;
+    if ((s = adj_solve<D, TB>(G, 0, dT, 1, &o->coarse, adj_rtol, uB + (size_t)k * ndB, ubarBk, mbarB, vnbarB, pibar,
+                              hlB, aBo, mat, mat + 64)))
+      return cleanup(), s;
+    HIP_TRY(c, hipMemcpyAsync(pibar_next, pibar, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+  }
+  // Step 0: projection of the fine start grid, then both P2Gs
+  {
+    TapePoint &t00 = tS[0];
+    if ((s = tape_copy(S, t00, -1, 2))) return cleanup(), s;
+    launch(c, -1, 0, -1, k_zero_proj, dim3(blocks_for(ndB, 1024), 1), blk, 0, ddB);
+    launch(c, -1, 0, -1, k_project_scatter<D>, dim3(blocks_for(nnS), 1), blk, 0, ddS, ddB, (const double *)nullptr,
+           G->err);
+    if ((s = zero_bytes(c, mbarS, nnS * 8)) || (s = zero_bytes(c, vnbarS, ndS * 8))) return cleanup(), s;
+    launch(c, -1, 0, -1, k_adj_project<D>, dim3(blocks_for(nnS)), blk, 0, B->g, S->g, (const double *)t00.m,
+           (const double *)t00.vn, (const uint8_t *)B->recv, (const double *)B->pnum, (const double *)B->pden,
+           o->eps_tol, (const double *)pibar_next, mbarS, vnbarS);
+    adj_p2g<D, TB>(S, t00, mbarS, vnbarS, aS0);
+  }
+  adj_p2g<D, TB>(B, tB0, mbarB, vnbarB, aBo);
+  // the pair back at its end-of-frame state
+  if ((s = tape_copy(B, tBe, -1, 1 | 2 | 4))) return cleanup(), s;
+  if ((s = tape_copy(S, tS[(size_t)(K - 1) * (M + 1) + M], -1, 1 | 2))) return cleanup(), s;
+  adj_to_rows(c, npB, D, aBo, outB[0], outB[1], outB[2], outB[3]);
+  adj_to_rows(c, npS, D, aS0, outS[0], outS[1], outS[2], outS[3]);
+  HIP_TRY(c, hipMemcpyAsync(mat_h, mat, 256 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  s = read_status(G);
+  cleanup();
+  return s;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1453,6 +1913,51 @@ osmpm_status osmpm_batch_single_frame(osmpm_batch *b, double dt, const osmpm_sol
 }
 
 void osmpm_batch_destroy(osmpm_batch *b) { group_free(b); }
+
+osmpm_status osmpm_single_frame_adjoint(osmpm_domain *d, double dt, const osmpm_solve_opts *o, double adj_cg_rtol,
+                                        const double *xbar, const double *vbar, const double *Bbar,
+                                        const double *Fbar, double *oxbar, double *ovbar, double *oBbar,
+                                        double *oFbar, double *mubar, double *lambar) {
+  if (!d || !o || !(dt > 0.0) || !(adj_cg_rtol > 0.0) || !mubar || !lambar) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  if (d->np > 0 && (!xbar || !vbar || !Bbar || !Fbar || !oxbar || !ovbar || !oBbar || !oFbar))
+    return OSMPM_E_INVALID_ARG;
+  const double *in[4] = {xbar, vbar, Bbar, Fbar};
+  double *out[4] = {oxbar, ovbar, oBbar, oFbar};
+  return DISPATCH2(d->D, d->precision, single_adjoint_impl)(d, dt, o, adj_cg_rtol, in, out, mubar, lambar);
+}
+
+osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
+                                         int32_t iters, double adj_cg_rtol, const double *xbB, const double *vbB,
+                                         const double *BbB, const double *FbB, const double *xbS,
+                                         const double *vbS, const double *BbS, const double *FbS, double *oxB,
+                                         double *ovB, double *oBB, double *oFB, double *oxS, double *ovS,
+                                         double *oBS, double *oFS, double *mubarB, double *lambarB, double *mubarS,
+                                         double *lambarS) {
+  if (!pair_ok(B, S) || !schwarz_opts_ok(o) || !(dT > 0.0) || iters < 1 || iters > o->k_max ||
+      !(adj_cg_rtol > 0.0) || !mubarB || !lambarB || !mubarS || !lambarS)
+    return OSMPM_E_INVALID_ARG;
+  if (B->np > 0 && (!xbB || !vbB || !BbB || !FbB || !oxB || !ovB || !oBB || !oFB)) return OSMPM_E_INVALID_ARG;
+  if (S->np > 0 && (!xbS || !vbS || !BbS || !FbS || !oxS || !ovS || !oBS || !oFS)) return OSMPM_E_INVALID_ARG;
+  osmpm_batch *G = nullptr;
+  osmpm_status s = pair_group(B, S, &G);
+  if (s) return s;
+  const double *inB[4] = {xbB, vbB, BbB, FbB}, *inS[4] = {xbS, vbS, BbS, FbS};
+  double *outB[4] = {oxB, ovB, oBB, oFB}, *outS[4] = {oxS, ovS, oBS, oFS};
+  std::vector<double> mat(256, 0.0);
+  s = DISPATCH2(B->D, B->precision, schwarz_adjoint_impl)(G, dT, o, iters, adj_cg_rtol, inB, inS, outB, outS,
+                                                          mat.data());
+  if (s) return s;
+  for (int k = 0; k < B->n_mat; ++k) {
+    mubarB[k] += mat[k];
+    lambarB[k] += mat[64 + k];
+  }
+  for (int k = 0; k < S->n_mat; ++k) {
+    mubarS[k] += mat[128 + k];
+    lambarS[k] += mat[192 + k];
+  }
+  return OSMPM_OK;
+}
 
 osmpm_status osmpm_get_particles(osmpm_domain *d, double *x, double *v, double *B, double *F, int32_t *id) {
   if (!d) return OSMPM_E_INVALID_ARG;

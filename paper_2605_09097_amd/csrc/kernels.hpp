@@ -179,6 +179,36 @@ template <int D>
 __global__ void k_copy_vbc(const DomDesc *dd, int src);
 __global__ void k_resid_final(const DomDesc *dd, double *out);
 
+// reverse mode (adjoint.hip)
+template <int D, typename TB>
+__global__ void k_adj_p2g(GridDev g, int np, int64_t cap, const double *x, const TB *v, const TB *B,
+                          const double *mass, const int *id, const double *m, const double *vn, const double *mbar,
+                          const double *vnbar, double *ax, double *av, double *aB);
+template <int D, typename TB>
+__global__ void k_adj_g2p(GridDev g, int np, int64_t cap, const double *x, const TB *F, const int *id,
+                          const double *m, const double *u, double dt, const double *ix, const double *iv,
+                          const double *iB, const double *iF, double *ubar, double *ox, double *oF);
+__global__ void k_adj_set_rhs(const DomDesc *dd, const double *ubar);
+template <int D, typename TB>
+__global__ void k_adj_hvp(const DomDesc *dd, const TB *lam, double *y);
+template <int D, typename TB>
+__global__ void k_adj_solve_nodes(const DomDesc *dd, double dt, double gx, double gy, double gz, const double *ubar,
+                                  const double *hl, int use_schwarz, double *mbar, double *vnbar, double *vbcbar);
+template <int D, typename TB>
+__global__ void k_adj_solve_particles(const DomDesc *dd, double *ax, double *aF, int np_adj, double *mubar,
+                                      double *lambar);
+template <int D>
+__global__ void k_adj_project(GridDev gB, GridDev gS, const double *mS, const double *vnS, const uint8_t *recvB,
+                              const double *num, const double *den, double eps_tol, const double *pbar,
+                              double *mbarS, double *vnbarS);
+template <int D>
+__global__ void k_adj_interp(GridDev gB, GridDev gS, const double *mB, const uint8_t *recvS, const double *ibar,
+                             double *vBbar);
+__global__ void k_adj_temporal(int64_t n, double am, const double *vbcbar, double *a, double *b);
+__global__ void k_axpy_d(int64_t n, double a, const double *x, double *y);
+template <int D>
+__global__ void k_adj_vel(int nn, const double *m, const double *vbar, double dT, double *ubar);
+
 // Work buffer selector of the interface kernels.
 __device__ inline double *wbuf(const DomDesc &D, int k) {
   switch (k) {

@@ -1,0 +1,107 @@
+"""GPU parity of the reverse mode against the oracle's (which is pinned by
+finite differences on the CPU): the adjoint of a single-domain frame and of
+a Schwarz frame for a random linear functional of the end-of-frame states,
+both with respect to the start-of-frame particle states and the Lame
+parameters of every material.  FP64 path: 1e-7 relative (the forward states
+of the two implementations agree to ~1e-13 and both adjoint solves run to
+1e-12); mixed path (FP32 stored states and adjoint CG vectors): 1e-3."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+TIGHT_OR = dict(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-13, max_newton=60, max_cg=20000)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09097_amd import binding
+
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _weights(state_shapes, seed):
+    rng = np.random.default_rng(seed)
+    return {k: rng.standard_normal(s) for k, s in state_shapes.items()}
+
+
+def _cmp(gpu_adj, or_adj, tol, what):
+    for k in "xvBF":
+        g = gpu_adj[k].cpu().numpy()
+        assert rel_err(g, or_adj[k]) < tol, (what, k, rel_err(g, or_adj[k]))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_frame_adjoint_parity(ctx, precision):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.inclusion_single(inv_dx=16, n_frames=3, delta=0.01)
+    prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
+    tol = 1e-7 if precision == "fp64" else 1e-3
+    so = b.solve_opts(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-12 if precision == "fp64" else 1e-5)
+    D = b.Domain(ctx, sc.B, precision=prec)
+    O = oracle.Domain(sc.B)
+    p, _ = sc.bc_params(0)
+    D.set_bc_params(p)
+    O.set_bc_params(p)
+    W = _weights({k: v.shape for k, v in O.state().items()}, 3)
+    print("single-domain frame adjoint,", precision, flush=True)
+    ga, gmu, glam = b.single_frame_adjoint(D, sc.dT, so, W, adj_cg_rtol=1e-12 if precision == "fp64" else 1e-6)
+    oa, omu, olam = oracle.single_frame_adjoint(O, sc.dT, oracle.solve_opts(**TIGHT_OR), W)
+    _cmp(ga, oa, tol, "state")
+    assert rel_err(gmu, omu) < tol and rel_err(glam, olam) < tol
+    # the domain holds the end-of-frame state afterwards
+    x = D.particles_input_order()[0]
+    assert rel_err(x - sc.B.x, O.x - sc.B.x) < (1e-9 if precision == "fp64" else 1e-4)
+    D.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_schwarz_frame_adjoint_parity(ctx, precision):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("inclusion_tiny")
+    prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
+    tol = 1e-7 if precision == "fp64" else 1e-3
+    so = b.solve_opts(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-12 if precision == "fp64" else 1e-5)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
+    sor = oracle.solve_opts(**TIGHT_OR)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=sor, fine=sor)
+    pair = b.SchwarzPair(ctx, sc, precision=prec)
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    for f in range(2):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        oracle.schwarz_frame(OB, OS, sc.dT, oo)
+        pair.frame(go)
+    pB, pS = sc.bc_params(2)
+    OB.set_bc_params(pB)
+    OS.set_bc_params(pS)
+    pair.B.set_bc_params(pB)
+    pair.S.set_bc_params(pS)
+    sB0, sS0 = OB.state(), OS.state()
+    K = oracle.schwarz_frame(OB, OS, sc.dT, oo).iters
+    OB.set_state(sB0)
+    OS.set_state(sS0)
+    WB = _weights({k: v.shape for k, v in sB0.items()}, 5)
+    WS = _weights({k: v.shape for k, v in sS0.items()}, 6)
+    print("Schwarz frame adjoint,", precision, "K =", K, flush=True)
+    gB, gS, gmB, glB, gmS, glS = b.schwarz_frame_adjoint(pair.B, pair.S, sc.dT, go, K, WB, WS,
+                                                         adj_cg_rtol=1e-12 if precision == "fp64" else 1e-6)
+    oB, oS_, omB, olB, omS, olS = oracle.schwarz_frame_adjoint(OB, OS, sc.dT, oo, K, WB, WS)
+    _cmp(gB, oB, tol, "B")
+    _cmp(gS, oS_, tol, "S")
+    for g, o in ((gmB, omB), (glB, olB), (gmS, omS), (glS, olS)):
+        assert rel_err(g, o) < tol, (g, o)
+    pair.close()
