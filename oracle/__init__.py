@@ -439,3 +439,46 @@ def schwarz_frame_adjoint(Bd: Domain, Sd: Domain, dT, opts, iters, adjB_end, adj
         *[_ptr(oB[k], _dp) for k in "xvBF"], *[_ptr(oS[k], _dp) for k in "xvBF"],
         _ptr(mubB, _dp), _ptr(labB, _dp), _ptr(mubS, _dp), _ptr(labS, _dp)), "or_schwarz_frame_adjoint")
     return oB, oS, mubB, labB, mubS, labS
+
+
+def schwarz_run(scene, E, n_frames, opts):
+    """Runs frames 0 .. n_frames-1 of a scene pair with Young's moduli E (the
+    fine domain's material list; the coarse one's is its prefix).  Returns
+    (B, S, per-frame start states, per-frame Schwarz iteration counts)."""
+    Bd, Sd = Domain(scene.B), Domain(scene.S)
+    nB = len(scene.B.E)
+    E = np.asarray(E, dtype=np.float64)
+    nu = np.asarray(scene.S.nu, dtype=np.float64)
+    mu, lam = lame(E, nu)
+    Bd.set_lame(mu[:nB], lam[:nB])
+    Sd.set_lame(mu, lam)
+    starts, iters = [], []
+    for f in range(n_frames):
+        starts.append((Bd.state(), Sd.state()))
+        pB, pS = scene.bc_params(f)
+        Bd.set_bc_params(pB)
+        Sd.set_bc_params(pS)
+        iters.append(schwarz_frame(Bd, Sd, scene.dT, opts).iters)
+    return Bd, Sd, starts, iters
+
+
+def schwarz_run_gradient(scene, E, Bd, Sd, starts, iters, opts, adjB_end, adjS_end=None):
+    """Reverse sweep over the frames of schwarz_run (frame adjoints from the
+    stored start states, last frame first).  Returns (dL/dE per material,
+    adjoint of the initial coarse state, of the initial fine state)."""
+    nB = len(scene.B.E)
+    nu = np.asarray(scene.S.nu, dtype=np.float64)
+    dmu = 1.0 / (2.0 * (1.0 + nu))
+    dlam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    dE = np.zeros(len(nu))
+    aB, aS = adjB_end, adjS_end
+    for f in range(len(iters) - 1, -1, -1):
+        Bd.set_state(starts[f][0])
+        Sd.set_state(starts[f][1])
+        pB, pS = scene.bc_params(f)
+        Bd.set_bc_params(pB)
+        Sd.set_bc_params(pS)
+        aB, aS, mB, lB, mS, lS = schwarz_frame_adjoint(Bd, Sd, scene.dT, opts, iters[f], aB, aS)
+        dE[:nB] += mB * dmu[:nB] + lB * dlam[:nB]
+        dE += mS * dmu + lS * dlam
+    return dE, aB, aS

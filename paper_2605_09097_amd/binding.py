@@ -267,6 +267,16 @@ class Domain:
         self.ctx.check(lib().osmpm_domain_set_materials(self.handle, mats, len(E)), "set_materials")
         self.n_mat = len(E)
 
+    def set_state(self, x, v, B, F):
+        """Overwrite the particle state (device tensors in input order) keeping
+        masses, volumes, materials and flags of the last set_particles."""
+        torch = self.ctx.torch
+        xs = [t.to(device=self.ctx.device, dtype=torch.float64).contiguous() for t in (x, v, B, F)]
+        _, _, _, _, m, V, mat, fl = self._in
+        self._state = xs
+        self.ctx.check(lib().osmpm_domain_set_particles(self.handle, self.n, *[_ptr(t) for t in xs], _ptr(m),
+                                                        _ptr(V), _ptr(mat), _ptr(fl)), "set_particles")
+
     def set_bc_params(self, params):
         p = np.zeros((max(self.n_groups, 1), 8))
         params = np.asarray(params, dtype=np.float64)

@@ -204,7 +204,8 @@ def inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.05, E_matrix=1e4,
     return Scene(name=name, B=B, S=S, dT=dT, M=M, n_frames=n_frames, bc_params=bc_params,
                  eps_tol=eps_tol_rel * float(S.mass.mean()),
                  meta={"inv_dx_B": inv_dx_B, "inv_dx_S": inv_dx_S, "r_inc": r_inc, "E_inc": E_inc,
-                       "E_matrix": E_matrix, "nu": nu, "ppc1d": ppc1d})
+                       "E_matrix": E_matrix, "nu": nu, "ppc1d": ppc1d, "top_disp": top_disp if loaded else 0.0,
+                       "ramp_frames": ramp_frames})
 
 
 def inclusion_single(inv_dx=50, ppc1d=2, r_inc=0.05, E_matrix=1e4, E_inc=1e5, nu=0.3, rho=1000.0,
@@ -392,3 +393,19 @@ def batch_scene(s: int, E_override: Optional[float] = None) -> Scene:
                          name="batch%d" % s)
     sc.meta.update({"seed": s})
     return sc
+
+
+def top_edge_target(sc: Scene, n_frames: int, seed: int = 0):
+    """Seeded target of the top-edge displacement loss of an inclusion scene:
+    the coarse particles of the driven top layer (scene group 1) and target
+    positions after n_frames, x0 + (0, -drive displacement) plus a seeded
+    offset of up to 1e-3 coarse cells per component.  Returns (indices into
+    the coarse particle arrays, target positions [k][2])."""
+    idx = np.nonzero(sc.B.flags & 4)[0]
+    x0 = np.asarray(sc.B.x)[idx]
+    ramp = sc.meta.get("ramp_frames", 1)
+    disp = sc.meta.get("top_disp", 0.0) * min(n_frames, ramp) / ramp
+    dxB = 1.0 / sc.meta.get("inv_dx_B", 1)
+    jit = uniform01(stream_seed(seed, 77), np.arange(2 * len(idx), dtype=np.uint64)).reshape(-1, 2) - 0.5
+    target = x0 + np.array([0.0, -disp]) + 2e-3 * dxB * jit
+    return idx, target

@@ -105,3 +105,45 @@ def test_schwarz_frame_adjoint_parity(ctx, precision):
     for g, o in ((gmB, omB), (glB, olB), (gmS, omS), (glS, olS)):
         assert rel_err(g, o) < tol, (g, o)
     pair.close()
+
+
+def test_autograd_gradient_matches_oracle(ctx):
+    """dL/dE through four frames of the small inclusion on the GPU
+    (torch.autograd over OSMPMStep, checkpoints every two frames, so the
+    reverse sweep restores and reruns segments) against the oracle's reverse
+    sweep over the same frames (FP64, tight solves)."""
+    import torch
+
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import diff, scenes
+
+    sc = scenes.workload("inclusion_tiny")
+    n = 4
+    so = b.solve_opts(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-12)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
+    idx, target = scenes.top_edge_target(sc, n, seed=3)
+    tS = np.asarray(sc.S.x) + 1e-4 * np.random.default_rng(4).standard_normal(np.asarray(sc.S.x).shape)
+    run = diff.SchwarzRun(ctx, sc, b.OSMPM_FP64, opts=go, checkpoint_every=2)
+    E = torch.tensor(np.asarray(sc.S.E, dtype=np.float64), requires_grad=True)
+    xB, xS = diff.osmpm_step().apply(E, run, n)
+    tgt = torch.as_tensor(target, device=xB.device)
+    tSd = torch.as_tensor(tS, device=xS.device)
+    L = 0.5 * ((xB[torch.as_tensor(idx, device=xB.device)] - tgt) ** 2).sum() + 0.5 * ((xS - tSd) ** 2).sum()
+    print("autograd through", n, "frames, iters", run.iters, flush=True)
+    L.backward()
+    run.close()
+
+    sor = oracle.solve_opts(**TIGHT_OR)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=sor, fine=sor)
+    E0 = np.asarray(sc.S.E, dtype=np.float64)
+    Bd, Sd, starts, iters = oracle.schwarz_run(sc, E0, n, oo)
+    assert iters == run.iters
+    r = Bd.x[idx] - target
+    q = Sd.x - tS
+    Lo = 0.5 * float(np.sum(r * r)) + 0.5 * float(np.sum(q * q))
+    xbar = np.zeros_like(Bd.x)
+    xbar[idx] = r
+    # (the reverse sweep leaves the oracle domains at an earlier state)
+    dE, _, _ = oracle.schwarz_run_gradient(sc, E0, Bd, Sd, starts, iters, oo, {"x": xbar}, {"x": q})
+    assert abs(float(L) - Lo) <= 1e-9 * abs(Lo)
+    assert rel_err(E.grad.numpy(), dE) < 1e-6, (E.grad.numpy(), dE)

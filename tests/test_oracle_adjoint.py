@@ -154,3 +154,51 @@ def test_schwarz_frame_adjoint_states_match_fd(schwarz_case, dom):
             fd = (c["run"](c["sB0"], s1, *lame) - c["run"](c["sB0"], s2, *lame)) / (2 * step)
             ad = float(np.sum(aS[k] * dirn))
         assert _rel(ad, fd) < TOL, (dom, k, ad, fd)
+
+
+def test_multi_frame_gradient_matches_fd():
+    """dL/dE through four Schwarz frames of the small inclusion (oracle
+    reverse sweep) against central differences of the forward with every
+    frame's Schwarz iteration count held.  L = seeded top-edge mismatch of the
+    coarse domain + a seeded mismatch of the fine particle positions (the
+    inclusion modulus reaches the top edge only weakly within four frames)."""
+    scenes = _scenes()
+    sc = scenes.workload("inclusion_tiny")
+    n = 4
+    so = oracle.solve_opts(**TIGHT)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
+    E0 = np.asarray(sc.S.E, dtype=np.float64)
+    idx, target = scenes.top_edge_target(sc, n, seed=3)
+    tS = np.asarray(sc.S.x) + 1e-4 * np.random.default_rng(4).standard_normal(np.asarray(sc.S.x).shape)
+
+    def loss(Bd, Sd):
+        r = Bd.x[idx] - target
+        q = Sd.x - tS
+        return 0.5 * float(np.sum(r * r)) + 0.5 * float(np.sum(q * q)), r, q
+
+    Bd, Sd, starts, iters = oracle.schwarz_run(sc, E0, n, oo)
+    L0, r, q = loss(Bd, Sd)
+    xbar = np.zeros_like(Bd.x)
+    xbar[idx] = r
+    dE, _, _ = oracle.schwarz_run_gradient(sc, E0, Bd, Sd, starts, iters, oo, {"x": xbar}, {"x": q})
+
+    def loss_at(E):
+        Bf, Sf = oracle.Domain(sc.B), oracle.Domain(sc.S)
+        mu, lam = oracle.lame(E, np.asarray(sc.S.nu))
+        Bf.set_lame(mu[:1], lam[:1])
+        Sf.set_lame(mu, lam)
+        for f in range(n):
+            pB, pS = sc.bc_params(f)
+            Bf.set_bc_params(pB)
+            Sf.set_bc_params(pS)
+            of = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so, force_iters=iters[f])
+            oracle.schwarz_frame(Bf, Sf, sc.dT, of)
+        return loss(Bf, Sf)[0]
+
+    for m in range(len(E0)):
+        h = 1e-4 * E0[m]
+        Ep, Em = E0.copy(), E0.copy()
+        Ep[m] += h
+        Em[m] -= h
+        fd = (loss_at(Ep) - loss_at(Em)) / (2 * h)
+        assert _rel(dE[m], fd) < 1e-5, (m, dE[m], fd)
