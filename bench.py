@@ -117,6 +117,36 @@ def batched_form(ctx, n_scenes, steps, prec, solve):
                           "bytes_per_launch": by / n, "launches": n} if n else None)}
 
 
+def adjoint_form(ctx, sc, prec, frames):
+    """Reverse mode on the same workload: dL/dE (matrix and inclusion Young's
+    moduli) of the seeded top-edge mismatch after `frames` frames, through
+    torch.autograd over the library's frame adjoints with one checkpoint
+    every 10 frames.  Forward and backward timed separately."""
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding, diff, scenes
+
+    run = diff.SchwarzRun(ctx, sc, prec, checkpoint_every=10)
+    idx, target = scenes.top_edge_target(sc, frames, seed=0)
+    E = torch.tensor(np.asarray(sc.S.E, dtype=np.float64), requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xB, xS = diff.osmpm_step().apply(E, run, frames)
+    L = 0.5 * ((xB[torch.as_tensor(idx, device=xB.device)] - torch.as_tensor(target, device=xB.device)) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    run.close()
+    return {"frames": frames, "checkpoint_every": 10, "loss": float(L), "dL_dE": [float(g) for g in E.grad],
+            "forward_ms_per_frame": 1e3 * (t1 - t0) / frames, "backward_ms_per_frame": 1e3 * (t2 - t1) / frames,
+            "schwarz_iters": run.iters,
+            "note": "backward = per segment: restore checkpoint, rerun frames; per frame: recompute with storage, "
+                    "reverse sweep (adjoint CG per solve)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +161,7 @@ def main():
     ap.add_argument("--batch-scenes", type=int, default=64,
                     help="scenes of the batched form (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed frames of the batched form")
+    ap.add_argument("--adjoint-frames", type=int, default=100, help="frames of the reverse-mode run (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's multiplicative Schwarz loop is "
@@ -218,6 +249,7 @@ def main():
         p64.close()
         fp64 = {"value": args.steps * _frame_particle_steps(sc) / el64, "ms_per_step": 1e3 * el64 / args.steps,
                 "schwarz_iters_mean": float(np.mean([s.iters for s in st64]))}
+    adjoint = adjoint_form(ctx, sc, prec, args.adjoint_frames) if args.adjoint_frames > 0 else None
     batched = None
     if args.batch_scenes > 0:
         batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve)
@@ -267,6 +299,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(out))
     ctx.close()
