@@ -148,7 +148,7 @@ __global__ void k_adj_g2p(GridDev g, int np, int64_t cap, const double *x, const
   }
 #pragma unroll
   for (int k = 0; k < n; ++k) {
-    Fp[k] = (double)F[k * cap + p];
+    Fp[k] = load_F<D>(F, cap, p, k);
     Fb[k] = iF[k * (int64_t)np + q];
     Bb[k] = iB[k * (int64_t)np + q];
   }
@@ -373,7 +373,7 @@ __global__ void k_adj_solve_particles(const DomDesc *dd, double *ax, double *aF,
     for (int a = 0; a < D; ++a) xp[a] = P0.x[a * cap + p];
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-      Fn[k] = (double)Fv[k * cap + p];
+      Fn[k] = load_F<D>(Fv, cap, p, k);
       Gu[k] = 0.0;
       Gl[k] = 0.0;
     }

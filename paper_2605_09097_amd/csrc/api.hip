@@ -1152,17 +1152,17 @@ osmpm_status zero_bytes(osmpm_ctx *c, void *p, size_t bytes) {
 void adj_from_rows(osmpm_ctx *c, int np, int D, const double *x, const double *v, const double *B, const double *F,
                    const AdjState &a) {
   const dim3 gb(blocks_for((int64_t)np * D * D, 2048)), blk(kBlock);
-  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D, x, a.x, (int64_t)np);
-  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D, v, a.v, (int64_t)np);
-  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D * D, B, a.B, (int64_t)np);
-  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D * D, F, a.F, (int64_t)np);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D, x, a.x, (int64_t)np, 0);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D, v, a.v, (int64_t)np, 0);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D * D, B, a.B, (int64_t)np, 0);
+  launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)np, D * D, F, a.F, (int64_t)np, 0);
 }
 void adj_to_rows(osmpm_ctx *c, int np, int D, const AdjState &a, double *x, double *v, double *B, double *F) {
   const dim3 gb(blocks_for((int64_t)np * D * D, 2048)), blk(kBlock);
-  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D, (const double *)a.x, (int64_t)np, x);
-  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D, (const double *)a.v, (int64_t)np, v);
-  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D * D, (const double *)a.B, (int64_t)np, B);
-  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D * D, (const double *)a.F, (int64_t)np, F);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D, (const double *)a.x, (int64_t)np, x, 0);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D, (const double *)a.v, (int64_t)np, v, 0);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D * D, (const double *)a.B, (int64_t)np, B, 0);
+  launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, (int64_t)np, D * D, (const double *)a.F, (int64_t)np, F, 0);
 }
 
 // P2G transposed on a stored point of domain d.
@@ -1752,15 +1752,15 @@ osmpm_status osmpm_domain_set_particles(osmpm_domain *d, int64_t n, const double
   d->version += 1;
   if (n > 0) {
     const dim3 gb(blocks_for(n * D * D, 2048)), blk(kBlock);
-    launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D, x, (double *)p.x, d->cap);
+    launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D, x, (double *)p.x, d->cap, 0);
     if (d->precision == OSMPM_MIXED) {
-      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D, v, (float *)p.v, d->cap);
-      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D * D, B, (float *)p.B, d->cap);
-      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D * D, F, (float *)p.F, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D, v, (float *)p.v, d->cap, 0);
+      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D * D, B, (float *)p.B, d->cap, 0);
+      launch(c, -1, 0, -1, k_aos_to_soa<float>, gb, blk, 0, (int64_t)n, D * D, F, (float *)p.F, d->cap, D + 1);
     } else {
-      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D, v, (double *)p.v, d->cap);
-      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D * D, B, (double *)p.B, d->cap);
-      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D * D, F, (double *)p.F, d->cap);
+      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D, v, (double *)p.v, d->cap, 0);
+      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D * D, B, (double *)p.B, d->cap, 0);
+      launch(c, -1, 0, -1, k_aos_to_soa<double>, gb, blk, 0, (int64_t)n, D * D, F, (double *)p.F, d->cap, D + 1);
     }
     HIP_TRY(c, hipMemcpyAsync(p.mass, mass, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(p.vol, vol, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1967,15 +1967,15 @@ osmpm_status osmpm_get_particles(osmpm_domain *d, double *x, double *v, double *
   if (n == 0) return OSMPM_OK;
   const PartPtrs &p = d->pb[d->cur];
   const dim3 gb(blocks_for(n * D * D, 2048)), blk(kBlock);
-  if (x) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D, (const double *)p.x, d->cap, x);
+  if (x) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D, (const double *)p.x, d->cap, x, 0);
   if (d->precision == OSMPM_MIXED) {
-    if (v) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D, (const float *)p.v, d->cap, v);
-    if (B) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D * D, (const float *)p.B, d->cap, B);
-    if (F) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D * D, (const float *)p.F, d->cap, F);
+    if (v) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D, (const float *)p.v, d->cap, v, 0);
+    if (B) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D * D, (const float *)p.B, d->cap, B, 0);
+    if (F) launch(c, -1, 0, -1, k_soa_to_aos<float>, gb, blk, 0, n, D * D, (const float *)p.F, d->cap, F, D + 1);
   } else {
-    if (v) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D, (const double *)p.v, d->cap, v);
-    if (B) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D * D, (const double *)p.B, d->cap, B);
-    if (F) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D * D, (const double *)p.F, d->cap, F);
+    if (v) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D, (const double *)p.v, d->cap, v, 0);
+    if (B) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D * D, (const double *)p.B, d->cap, B, 0);
+    if (F) launch(c, -1, 0, -1, k_soa_to_aos<double>, gb, blk, 0, n, D * D, (const double *)p.F, d->cap, F, D + 1);
   }
   if (id) HIP_TRY(c, hipMemcpyAsync(id, p.id, n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
   return check_launch(c);

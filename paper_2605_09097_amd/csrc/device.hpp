@@ -165,6 +165,13 @@ __device__ inline void tile_origin(const TileGeom &tg, int t, int *org) {
   org[2] = (t / (tg.nt[0] * tg.nt[1])) * tg.T[2];
 }
 
+// Entry k (row-major a*D+b) of F = I + H for a particle whose stored
+// displacement gradient H is in rows [k][cap].
+template <int D, typename TB>
+__device__ inline double load_F(const TB *H, int64_t cap, int p, int k) {
+  return (double)H[k * cap + p] + ((k % (D + 1)) == 0 ? 1.0 : 0.0);
+}
+
 // ---------------------------------------------------------------- small dense algebra
 template <int D, typename T>
 __device__ inline T det(const T *F) {

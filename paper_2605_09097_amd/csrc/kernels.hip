@@ -26,25 +26,30 @@ template __global__ void k_fill<int>(int64_t, int, int *);
 template __global__ void k_fill<long long>(int64_t, long long, long long *);
 template __global__ void k_fill<uint8_t>(int64_t, uint8_t, uint8_t *);
 
-// [n][c] (caller layout, FP64) -> [c][cap] (library layout, storage type T)
+// [n][c] (caller layout, FP64) -> [c][cap] (library layout, storage type T).
+// With eye = D + 1 the rows are a D x D matrix and the identity is taken
+// off the diagonal rows (r % eye == 0) in FP64 before rounding: F in, H out.
 template <typename T>
-__global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap) {
+__global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap, int eye) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * c; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = i / c, r = i % c;
-    dst[r * cap + p] = (T)src[i];
+    const double s = (eye && r % eye == 0) ? src[i] - 1.0 : src[i];
+    dst[r * cap + p] = (T)s;
   }
 }
+// Inverse of k_aos_to_soa; eye = D + 1 adds the identity back (H in, F out).
 template <typename T>
-__global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst) {
+__global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst, int eye) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * c; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = i / c, r = i % c;
-    dst[i] = (double)src[r * cap + p];
+    const double s = (double)src[r * cap + p];
+    dst[i] = (eye && r % eye == 0) ? s + 1.0 : s;
   }
 }
-template __global__ void k_aos_to_soa<double>(int64_t, int, const double *, double *, int64_t);
-template __global__ void k_aos_to_soa<float>(int64_t, int, const double *, float *, int64_t);
-template __global__ void k_soa_to_aos<double>(int64_t, int, const double *, int64_t, double *);
-template __global__ void k_soa_to_aos<float>(int64_t, int, const float *, int64_t, double *);
+template __global__ void k_aos_to_soa<double>(int64_t, int, const double *, double *, int64_t, int);
+template __global__ void k_aos_to_soa<float>(int64_t, int, const double *, float *, int64_t, int);
+template __global__ void k_soa_to_aos<double>(int64_t, int, const double *, int64_t, double *, int);
+template __global__ void k_soa_to_aos<float>(int64_t, int, const float *, int64_t, double *, int);
 
 __global__ void k_iota(int n, int *a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = i;
@@ -447,7 +452,8 @@ __global__ void k_p2g_final(const DomDesc *dd) {
 // ====================================================================== G2P
 // APIC G2P with v_i = u_i / dt (Eqs. g2p_v, g2p_B), F <- (I + sum u_i gradN^T) F
 // (Eq. F_update) and x <- x + dt v_p (Eq. advection); FP64 arithmetic, v, B,
-// F stored in TB, x in FP64.
+// H = F - I stored in TB, x in FP64.  With G = sum u_i gradN^T the update is
+// carried on H as H <- H + G + G H, which equals (I + G)(I + H) - I.
 template <int D, typename TB>
 __global__ void k_g2p(const DomDesc *dd, double dt, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
@@ -459,7 +465,7 @@ __global__ void k_g2p(const DomDesc *dd, double dt, int *err) {
   const GridDev &g = dm.g;
   TB *v = static_cast<TB *>(P.v);
   TB *B = static_cast<TB *>(P.B);
-  TB *F = static_cast<TB *>(P.F);
+  TB *H = static_cast<TB *>(P.F);
   double xp[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
@@ -501,17 +507,17 @@ __global__ void k_g2p(const DomDesc *dd, double dt, int *err) {
       }
     }
   }
-  double Fp[D * D];
+  double Hp[D * D];
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) Fp[k] = (double)F[k * cap + p];
+  for (int k = 0; k < D * D; ++k) Hp[k] = (double)H[k * cap + p];
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int b = 0; b < D; ++b) {
-      double t = Fp[a * D + b];
+      double t = Hp[a * D + b] + G[a * D + b];
 #pragma unroll
-      for (int e = 0; e < D; ++e) t += G[a * D + e] * Fp[e * D + b];
-      F[(a * D + b) * cap + p] = (TB)t;
+      for (int e = 0; e < D; ++e) t += G[a * D + e] * Hp[e * D + b];
+      H[(a * D + b) * cap + p] = (TB)t;
       B[(a * D + b) * cap + p] = (TB)Bp[a * D + b];
     }
 #pragma unroll
@@ -667,7 +673,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
     double Fn[n], Gu[n];
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-      Fn[k] = (double)F[k * cap + p];
+      Fn[k] = load_F<D>(F, cap, p, k);
       Gu[k] = 0.0;
     }
 #pragma unroll
@@ -1284,7 +1290,7 @@ __global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double g
       for (int k = 0; k < n; ++k) {
         Gu[k] = 0.0;
         Gd[k] = 0.0;
-        Fn[k] = (double)F[k * cap + p];
+        Fn[k] = load_F<D>(F, cap, p, k);
       }
 #pragma unroll
       for (int s = 0; s < stencil_count<D>(); ++s) {

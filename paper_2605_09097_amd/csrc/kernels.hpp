@@ -58,7 +58,11 @@ struct FlagMask {
 };
 
 // One particle buffer (component-major [rows][capacity]); v, B, F are in
-// the domain's bulk type.
+// the domain's bulk type.  The F rows hold the displacement gradient
+// H = F - I, not F: at the small strains of stiff or finely resolved domains
+// F sits within 1e-4 of the identity, where a 32-bit F would keep only about
+// three digits of the strain, while a 32-bit H keeps its relative accuracy
+// at any strain.
 struct PartPtrs {
   double *x, *mass, *vol;
   void *v, *B, *F;
@@ -107,9 +111,9 @@ __host__ __device__ inline int node_blocks(int ndof) {
 template <typename T>
 __global__ void k_fill(int64_t n, T v, T *a);
 template <typename T>
-__global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap);
+__global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap, int eye);
 template <typename T>
-__global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst);
+__global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst, int eye);
 __global__ void k_iota(int n, int *a);
 __global__ void k_set_flags(int *flags, int n, FlagMask m);
 __global__ void k_temporal_1(int64_t n, double am, const double *vn, const double *vn1, double *out);

@@ -349,6 +349,77 @@ def hertz_scene(inv_dx_B=32, inv_dx_S=128, ppc1d=2, R=0.5, E_cyl=1e5, E_block=1e
                  eps_tol=eps_tol_rel * float(S.mass.mean()), meta={"R": R})
 
 
+def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick=0.02, E=5e5, nu=0.35,
+               rho=1000.0, seed=0, dT=2e-3, M=4, n_frames=500, angle=math.pi, hinge_x=0.5,
+               fine_box=((0.4, 0.6), (-0.02, 0.22), (-0.02, 0.04)), band=0.02, tau_rel=1e-3,
+               eps_tol_rel=1e-9, name="fold"):
+    """3D folding slab: [0,length] x [0,width] x [0,thick], the layer of
+    particles within one spacing of x = 0 clamped, the layer at x = length
+    turned rigidly by `angle` about the axis through (hinge_x, ., thick/2)
+    along -y (the free end lifts) at a constant rate over n_frames frames.
+    The fine domain carries the material inside fine_box; the coarse domain
+    the material outside fine_box shrunk by band.  The coarse grid covers the
+    half circle the free end sweeps."""
+    lat = math.lcm(inv_dx_B, inv_dx_S, 100)
+    h0 = 1.0 / lat
+    (fx0, fx1), (fy0, fy1), (fz0, fz1) = fine_box
+
+    def slab(p):
+        return ((p[:, 0] >= 0.0) & (p[:, 0] <= length) & (p[:, 1] >= 0.0) & (p[:, 1] <= width)
+                & (p[:, 2] >= 0.0) & (p[:, 2] <= thick))
+
+    def in_box(p, sh):
+        return ((p[:, 0] >= fx0 + sh) & (p[:, 0] <= fx1 - sh) & (p[:, 1] >= fy0 + sh) & (p[:, 1] <= fy1 - sh)
+                & (p[:, 2] >= fz0 + sh) & (p[:, 2] <= fz1 - sh))
+
+    regB = lambda p: slab(p) & ~in_box(p, band)
+    regS = lambda p: slab(p) & in_box(p, 0.0)
+    ncx, ncy, ncz = int(round(length * inv_dx_B)), int(round(width * inv_dx_B)), max(1, int(round(thick * inv_dx_B)))
+    xB, _ = _sample(3, inv_dx_B, [0, 0, 0], [ncx, ncy, ncz], ppc1d, regB, seed, 8)
+    sx = [int(round(fx0 * inv_dx_S)), int(round(fx1 * inv_dx_S))]
+    sy = [int(round(fy0 * inv_dx_S)), int(round(fy1 * inv_dx_S))]
+    sz = [int(round(fz0 * inv_dx_S)), int(round(fz1 * inv_dx_S))]
+    xS, _ = _sample(3, inv_dx_S, [max(sx[0], 0), max(sy[0], 0), max(sz[0], 0)],
+                    [sx[1], sy[1], sz[1]], ppc1d, regS, seed, 9)
+    spB, spS = 1.0 / (inv_dx_B * ppc1d), 1.0 / (inv_dx_S * ppc1d)
+
+    def dist_out(p, sh):
+        e = [np.maximum.reduce([(lo + sh) - p[:, a], p[:, a] - (hi - sh), np.zeros(len(p))])
+             for a, (lo, hi) in enumerate(fine_box)]
+        return np.sqrt(e[0] ** 2 + e[1] ** 2 + e[2] ** 2)
+
+    def dist_in(p):
+        return np.min([np.minimum(p[:, a] - lo, hi - p[:, a]) for a, (lo, hi) in enumerate(fine_box)], axis=0)
+
+    flB = np.where(dist_out(xB, band) < spB, FLAG_BOUNDARY, 0)
+    flB = flB | np.where(xB[:, 0] < spB, 2, 0) | np.where(xB[:, 0] > length - spB, 4, 0)
+    flS = np.where(dist_in(xS) < spS, FLAG_BOUNDARY, 0)
+    m_ref = rho / (inv_dx_B ** 3 * ppc1d ** 3)
+    pad = 3
+    reach = length - hinge_x
+    cB = lat // inv_dx_B
+    lo = [-pad, -pad, -pad]
+    hi = [ncx + pad, ncy + pad, int(math.ceil((thick / 2 + reach) * inv_dx_B)) + pad]
+    B = _domain(3, h0, [l * cB for l in lo], cB, [hi[a] - lo[a] + 1 for a in range(3)], xB,
+                np.zeros(len(xB), np.int32), [E], [nu], rho, ppc1d, flB, [BC_FIX, BC_ROTATE], [0b111, 0b111],
+                m_ref, tau_rel)
+    cS = lat // inv_dx_S
+    loS = [sx[0] - pad, sy[0] - pad, sz[0] - pad]
+    hiS = [sx[1] + pad, sy[1] + pad, sz[1] + pad]
+    S = _domain(3, h0, [l * cS for l in loS], cS, [hiS[a] - loS[a] + 1 for a in range(3)], xS,
+                np.zeros(len(xS), np.int32), [E], [nu], rho, ppc1d, flS, [], [], m_ref, tau_rel)
+    omega = angle / (n_frames * dT)
+
+    def bc_params(frame):
+        pB = np.zeros((2, 8))
+        pB[1, :7] = [hinge_x, 0.0, thick / 2, 0.0, -1.0, 0.0, omega if frame < n_frames else 0.0]
+        return pB, np.zeros((1, 8))
+
+    return Scene(name=name, B=B, S=S, dT=dT, M=M, n_frames=n_frames, bc_params=bc_params,
+                 eps_tol=eps_tol_rel * float(S.mass.mean()) if len(xS) else 0.0,
+                 meta={"inv_dx_B": inv_dx_B, "inv_dx_S": inv_dx_S})
+
+
 def translation_scene(inv_dx_B=20, inv_dx_S=50, velocity=(0.3, -0.2), ppc1d=2, seed=0, dT=1e-3, M=2,
                       E=1e4, nu=0.3):
     """The inclusion geometry with no scene BCs and a uniform initial velocity:
@@ -375,6 +446,13 @@ def workload(name: str, seed: int = 0) -> Scene:
         return inclusion_scene(20, 50, seed=seed, n_frames=50, delta=INCLUSION_DELTA, name=name)
     if name == "inclusion_refined":
         return inclusion_scene(160, 400, seed=seed, n_frames=200, delta=INCLUSION_DELTA, name=name)
+    if name == "hertz":
+        return hertz_scene(128, 512, ppc1d=3, seed=seed, M=4, n_frames=400)
+    if name == "fold":
+        return fold_scene(seed=seed)
+    if name == "fold_tiny":
+        return fold_scene(20, 40, thick=0.1, fine_box=((0.35, 0.65), (-0.05, 0.25), (-0.05, 0.15)), band=0.05,
+                          dT=2e-3, M=2, n_frames=50, seed=seed, name=name)
     raise KeyError(name)
 
 

@@ -255,3 +255,22 @@ def test_out_of_grid_reported(ctx):
     assert e.value.status == b.OSMPM_E_OUT_OF_GRID
     D.close()
     own.close()
+
+
+def test_schwarz_frames_fold_3d(ctx):
+    """Two frames of the small 3D folding slab (27-node stencils, rotation
+    drive, ambiguous overlap nodes in the arbitration), FP64."""
+    sc = _scenes().workload("fold_tiny")
+    print("3D fold, 2 frames", flush=True)
+    pair, OB, OS, stats = _schwarz_run(ctx, sc, 2)
+    for gst, ost in stats:
+        assert gst.iters == ost.iters
+        assert (gst.n_recv_B, gst.n_recv_S, gst.n_amb) == (ost.n_recv_B, ost.n_recv_S, ost.n_amb)
+        assert gst.newton_B == ost.newton_B and gst.newton_S == ost.newton_S
+    for Dg, Do, spec in ((pair.B, OB, sc.B), (pair.S, OS, sc.S)):
+        _, _, u = Dg.grid_state()
+        x, _, _, F = Dg.particles_input_order()
+        assert rel_err(u.cpu().numpy(), Do.u) < FP64_TOL
+        assert rel_err(x - spec.x, Do.x - spec.x) < FP64_TOL
+        assert rel_err(F - np.eye(3), Do.F - np.eye(3)) < FP64_TOL
+    pair.close()
