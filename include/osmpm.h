@@ -345,9 +345,13 @@ osmpm_status osmpm_get_grid(osmpm_domain *dom, double *m, double *vn, double *u)
 /* Interface sets: gamma and recv flags [n_nodes] (uint8) and the fixed-point
  * node mass of all particles q_all [n_nodes] (int64).  Any may be NULL. */
 osmpm_status osmpm_get_sets(osmpm_domain *dom, uint8_t *gamma, uint8_t *recv, int64_t *q_all);
-/* The permutation applied by the last sort (perm[i] = position before the
- * sort of the particle now at i) and the bin offsets cell_start
- * [n_keys + 1]. */
+/* The stable counting sort of the last binning: perm[i] = position before
+ * the sort of the i-th particle in stable bin order, and the bin offsets
+ * cell_start [n_keys + 1] of that order.  The particle arrays store each
+ * tile's particles slot-major (the first particle of every non-empty cell of
+ * the tile in cell order, then the second, ...), so a tile occupies the same
+ * range [cell_start[t * tile_volume], cell_start[(t + 1) * tile_volume]) in
+ * both orders; osmpm_get_particles returns the storage order with ids. */
 osmpm_status osmpm_get_sort(osmpm_domain *dom, int32_t *perm, int32_t *cell_start);
 /* Sizes: particles, nodes, sort keys (host outputs, any may be NULL). */
 osmpm_status osmpm_domain_info(osmpm_domain *dom, int64_t *n_particles, int64_t *n_nodes,

@@ -49,7 +49,7 @@ __device__ inline void stencil_hess(const Stencil<D> &st, const int *k, double i
 //   xbar += m_p [(mt + pb.w) grad N - N Dinv B^T pb],
 // pb = vnbar_i / m_i, mt = mbar_i - vnbar_i.v_i / m_i, w = v_p + Dinv B_p (x_i - x_p).
 template <int D, typename TB>
-__global__ void k_adj_p2g(GridDev g, int np, int64_t cap, const double *x, const TB *v, const TB *B,
+__global__ void __launch_bounds__(kBlock) k_adj_p2g(GridDev g, int np, int64_t cap, const double *x, const TB *v, const TB *B,
                           const double *mass, const int *id, const double *m, const double *vn, const double *mbar,
                           const double *vnbar, double *ax, double *av, double *aB) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,7 +132,7 @@ __global__ void k_adj_p2g(GridDev g, int np, int64_t cap, const double *x, const
 // G2P: xbar += ix + sum_i [(u_i.vt + u_i.(iB dx_i))/dt grad N - N iB^T u_i/dt
 // + Hs_i (F iF^T u_i)], Fbar += (I + G_u)^T iF, vt = iv + dt ix.
 template <int D, typename TB>
-__global__ void k_adj_g2p(GridDev g, int np, int64_t cap, const double *x, const TB *F, const int *id,
+__global__ void __launch_bounds__(kBlock) k_adj_g2p(GridDev g, int np, int64_t cap, const double *x, const TB *F, const int *id,
                           const double *m, const double *u, double dt, const double *ix, const double *iv,
                           const double *iB, const double *iF, double *ubar, double *ox, double *oF) {
   constexpr int n = D * D;
@@ -239,7 +239,7 @@ __global__ void k_adj_g2p(GridDev g, int np, int64_t cap, const double *x, const
 // kernel forms r_0 = -g, so g = -ubar on the free DOFs (the free mask comes
 // from the Dirichlet setup of the same solve).  Moves the domain to the CG
 // start phase.
-__global__ void k_adj_set_rhs(const DomDesc *dd, const double *ubar) {
+__global__ void __launch_bounds__(kBlock) k_adj_set_rhs(const DomDesc *dd, const double *ubar) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || (int)blockIdx.x >= nb) return;
@@ -252,7 +252,7 @@ __global__ void k_adj_set_rhs(const DomDesc *dd, const double *ubar) {
 // of H lambda; lambda vanishes on the Dirichlet DOFs, so the lumped-mass part
 // does not reach them).  Tangents Atil in the packed folded form.
 template <int D, typename TB>
-__global__ void k_adj_hvp(const DomDesc *dd, const TB *lam, double *y) {
+__global__ void __launch_bounds__(kBlock) k_adj_hvp(const DomDesc *dd, const TB *lam, double *y) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
@@ -318,7 +318,7 @@ __global__ void k_adj_hvp(const DomDesc *dd, const TB *lam, double *y) {
 // (Dirichlet, not scene-constrained) the data receive
 // vbcbar += dt (ubar - (H lambda)).
 template <int D, typename TB>
-__global__ void k_adj_solve_nodes(const DomDesc *dd, double dt, double gx, double gy, double gz, const double *ubar,
+__global__ void __launch_bounds__(kBlock) k_adj_solve_nodes(const DomDesc *dd, double dt, double gx, double gy, double gz, const double *ubar,
                                   const double *hl, int use_schwarz, double *mbar, double *vnbar, double *vbcbar) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
@@ -349,7 +349,7 @@ __global__ void k_adj_solve_nodes(const DomDesc *dd, double dt, double gx, doubl
 // material adjoints mubar -= V (F - F^-T) : L, lambar -= V ln J F^-T : L,
 // L = G_lambda F^n, with the exact (unprojected) tangent A.
 template <int D, typename TB>
-__global__ void k_adj_solve_particles(const DomDesc *dd, double *ax, double *aF, int np_adj, double *mubar,
+__global__ void __launch_bounds__(kBlock) k_adj_solve_particles(const DomDesc *dd, double *ax, double *aF, int np_adj, double *mubar,
                                       double *lambar) {
   constexpr int n = D * D;
   const DomDesc &dm = dd[blockIdx.y];
@@ -507,7 +507,7 @@ __global__ void k_adj_solve_particles(const DomDesc *dd, double *ax, double *aF,
 // numbar = pbar / (den + eps), denbar = -(pbar.num) / (den + eps)^2, on the
 // coarse receivers.
 template <int D>
-__global__ void k_adj_project(GridDev gB, GridDev gS, const double *mS, const double *vnS, const uint8_t *recvB,
+__global__ void __launch_bounds__(kBlock) k_adj_project(GridDev gB, GridDev gS, const double *mS, const double *vnS, const uint8_t *recvB,
                               const double *num, const double *den, double eps_tol, const double *pbar,
                               double *mbarS, double *vnbarS) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -554,7 +554,7 @@ __global__ void k_adj_project(GridDev gB, GridDev gS, const double *mS, const do
 // I_{B->S} transposed: every fine receiver scatters N_I(x_j) ibar_j to its
 // active coarse stencil nodes.
 template <int D>
-__global__ void k_adj_interp(GridDev gB, GridDev gS, const double *mB, const uint8_t *recvS, const double *ibar,
+__global__ void __launch_bounds__(kBlock) k_adj_interp(GridDev gB, GridDev gS, const double *mB, const uint8_t *recvS, const double *ibar,
                              double *vBbar) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= gS.nn || !recvS[j]) return;
@@ -579,7 +579,7 @@ __global__ void k_adj_interp(GridDev gB, GridDev gS, const double *mB, const uin
 }
 
 // T_m transposed: a += (1 - am) vbcbar, b += am vbcbar.
-__global__ void k_adj_temporal(int64_t n, double am, const double *vbcbar, double *a, double *b) {
+__global__ void __launch_bounds__(kBlock) k_adj_temporal(int64_t n, double am, const double *vbcbar, double *a, double *b) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     a[k] += (1.0 - am) * vbcbar[k];
     b[k] += am * vbcbar[k];
@@ -588,7 +588,7 @@ __global__ void k_adj_temporal(int64_t n, double am, const double *vbcbar, doubl
 
 // v_B = u_B / dT on the active nodes, transposed: ubar += vbar / dT.
 template <int D>
-__global__ void k_adj_vel(int nn, const double *m, const double *vbar, double dT, double *ubar) {
+__global__ void __launch_bounds__(kBlock) k_adj_vel(int nn, const double *m, const double *vbar, double dT, double *ubar) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nn || !(m[i] > 0.0)) return;
 #pragma unroll
@@ -629,7 +629,7 @@ OSMPM_ADJ_INST_DT(3, float)
 
 namespace osmpm {
 // y += a x (grid-stride).
-__global__ void k_axpy_d(int64_t n, double a, const double *x, double *y) {
+__global__ void __launch_bounds__(kBlock) k_axpy_d(int64_t n, double a, const double *x, double *y) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     y[k] += a * x[k];
 }

@@ -109,7 +109,7 @@ struct osmpm_domain {
   int cur = 0;             // host mirror of *d_cur
   int *d_cur = nullptr;    // current particle buffer (device)
   int nk = 0;
-  int *key = nullptr, *count = nullptr, *cell_start = nullptr, *cursor = nullptr, *perm = nullptr;
+  int *key = nullptr, *count = nullptr, *cell_start = nullptr, *cursor = nullptr, *perm = nullptr, *lperm = nullptr;
   int n_mat = 0;
   double *mu = nullptr, *lam = nullptr;
   double m_ref = 1.0, tau = 0.0;
@@ -463,6 +463,7 @@ DomDesc make_desc(const osmpm_domain *d) {
   x.cell_start = d->cell_start;
   x.cursor = d->cursor;
   x.perm = d->perm;
+  x.lperm = d->lperm;
   x.mu = d->mu;
   x.lam = d->lam;
   x.m = d->m;
@@ -614,6 +615,7 @@ void sort_side(osmpm_batch *G, int s, int want_q) {
   launch(c, -1, 0, -1, k_scan, dim3(1, n), dim3(1024), 0, dd);
   launch(c, -1, 0, -1, k_scatter, dim3(pb, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_cellsort, dim3(blocks_for(E.max_nk), n), dim3(kBlock), 0, dd);
+  launch(c, -1, 0, -1, k_slot_layout, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_gather_all<D, TB>, dim3(pb, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_flip, dim3(blocks_for(n)), dim3(kBlock), 0, dd, n);
   for (int i = 0; i < n; ++i)
@@ -1645,6 +1647,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->d_cur, 1);
   if (!s) s = dalloc(d, &d->key, cap);
   if (!s) s = dalloc(d, &d->perm, cap);
+  if (!s) s = dalloc(d, &d->lperm, cap);
   if (!s) s = dalloc(d, &d->count, (size_t)d->nk + 1);
   if (!s) s = dalloc(d, &d->cell_start, (size_t)d->nk + 1);
   if (!s) s = dalloc(d, &d->cursor, (size_t)d->nk + 1);

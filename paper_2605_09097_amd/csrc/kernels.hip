@@ -16,7 +16,7 @@ namespace osmpm {
 
 // ====================================================================== misc
 template <typename T>
-__global__ void k_fill(int64_t n, T v, T *a) {
+__global__ void __launch_bounds__(kBlock) k_fill(int64_t n, T v, T *a) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
 }
@@ -30,7 +30,7 @@ template __global__ void k_fill<uint8_t>(int64_t, uint8_t, uint8_t *);
 // With eye = D + 1 the rows are a D x D matrix and the identity is taken
 // off the diagonal rows (r % eye == 0) in FP64 before rounding: F in, H out.
 template <typename T>
-__global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap, int eye) {
+__global__ void __launch_bounds__(kBlock) k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_t cap, int eye) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * c; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = i / c, r = i % c;
     const double s = (eye && r % eye == 0) ? src[i] - 1.0 : src[i];
@@ -39,7 +39,7 @@ __global__ void k_aos_to_soa(int64_t n, int c, const double *src, T *dst, int64_
 }
 // Inverse of k_aos_to_soa; eye = D + 1 adds the identity back (H in, F out).
 template <typename T>
-__global__ void k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst, int eye) {
+__global__ void __launch_bounds__(kBlock) k_soa_to_aos(int64_t n, int c, const T *src, int64_t cap, double *dst, int eye) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * c; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = i / c, r = i % c;
     const double s = (double)src[r * cap + p];
@@ -51,18 +51,18 @@ template __global__ void k_aos_to_soa<float>(int64_t, int, const double *, float
 template __global__ void k_soa_to_aos<double>(int64_t, int, const double *, int64_t, double *, int);
 template __global__ void k_soa_to_aos<float>(int64_t, int, const float *, int64_t, double *, int);
 
-__global__ void k_iota(int n, int *a) {
+__global__ void __launch_bounds__(kBlock) k_iota(int n, int *a) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = i;
 }
 
 // flags[i] = bit i of m.
-__global__ void k_set_flags(int *flags, int n, FlagMask m) {
+__global__ void __launch_bounds__(kBlock) k_set_flags(int *flags, int n, FlagMask m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) flags[i] = (int)((m.w[i >> 6] >> (i & 63)) & 1u);
 }
 
 // T_m (Eq. temporal_interp) on plain arrays.
-__global__ void k_temporal_1(int64_t n, double am, const double *vn, const double *vn1, double *out) {
+__global__ void __launch_bounds__(kBlock) k_temporal_1(int64_t n, double am, const double *vn, const double *vn1, double *out) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     out[k] = (1.0 - am) * vn[k] + am * vn1[k];
 }
@@ -91,7 +91,7 @@ __device__ inline int particle_blocks(int np) {
 // ====================================================================== binning
 // Zeroes the bin histogram and the P2G targets of every active domain (with
 // want_q also the fixed-point masses of the boundary-set selection).
-__global__ void k_zero_grid(const DomDesc *dd, int want_q) {
+__global__ void __launch_bounds__(kBlock) k_zero_grid(const DomDesc *dd, int want_q) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int nn = dm.g.nn;
@@ -111,7 +111,7 @@ __global__ void k_zero_grid(const DomDesc *dd, int want_q) {
 
 // Tile-major bin key of the particle's base node, and the bin histogram.
 template <int D>
-__global__ void k_keys(const DomDesc *dd, int *err) {
+__global__ void __launch_bounds__(kBlock) k_keys(const DomDesc *dd, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(1024) k_scan(const DomDesc *dd) {
   if (tid == 0) cell_start[nk] = carry;
 }
 
-__global__ void k_scatter(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_scatter(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -201,7 +201,7 @@ __global__ void k_scatter(const DomDesc *dd) {
 
 // The scatter fills each bin in arbitrary order; sorting every bin by the
 // original index makes the result the stable counting sort.
-__global__ void k_cellsort(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_cellsort(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -219,9 +219,53 @@ __global__ void k_cellsort(const DomDesc *dd) {
   }
 }
 
-// Gathers every particle array into the other buffer in bin order.
+// Storage order inside a tile: slot-major.  The particles of a tile are laid
+// out slot by slot, the first particle (in stable bin order) of every
+// non-empty cell in cell order, then the second, and so on; lperm[q] is the
+// pre-sort index of the particle stored at q.  Consecutive particles, hence
+// the lanes of a wave, then lie in distinct cells, so the node updates of one
+// wave-wide LDS atomic never address the same word, while every particle
+// array is still read contiguously.  One workgroup per tile; the rank of a
+// cell among the cells that hold a slot-j particle comes from wave ballots.
+__global__ void __launch_bounds__(kBlock) k_slot_layout(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  const TileGeom &tg = dm.tg;
+  if (!*dm.active || (int)blockIdx.x >= tg.ntiles) return;
+  const int tvol = tg.tvol;
+  const int *cs = dm.cell_start + (size_t)blockIdx.x * tvol;
+  const int p0 = cs[0];
+  if (p0 == cs[tvol]) return;
+  __shared__ int wtot[kBlock / 64];
+  __shared__ int wmax[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int mx = 0;
+  for (int c = threadIdx.x; c < tvol; c += kBlock) mx = max(mx, cs[c + 1] - cs[c]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+  if (lane == 0) wmax[w] = mx;
+  __syncthreads();
+  mx = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+  int dst = p0;  // first position of slot j
+  for (int j = 0; j < mx; ++j) {
+    for (int c0 = 0; c0 < tvol; c0 += kBlock) {
+      const int c = c0 + threadIdx.x;
+      const bool has = c < tvol && cs[c + 1] - cs[c] > j;
+      const unsigned long long bal = __ballot(has);
+      if (lane == 0) wtot[w] = __popcll(bal);
+      __syncthreads();
+      int before = 0;
+      for (int k = 0; k < w; ++k) before += wtot[k];
+      const int tot = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+      if (has) dm.lperm[dst + before + __popcll(bal & ((1ull << lane) - 1ull))] = dm.perm[cs[c] + j];
+      dst += tot;
+      __syncthreads();
+    }
+  }
+}
+
+// Gathers every particle array into the other buffer in storage order.
 template <int D, typename TB>
-__global__ void k_gather_all(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_gather_all(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,7 +273,7 @@ __global__ void k_gather_all(const DomDesc *dd) {
   const int c = *dm.cur;
   const PartPtrs &a = dm.pb[c], &b = dm.pb[c ^ 1];
   const int64_t cap = dm.cap;
-  const int q = dm.perm[p];
+  const int q = dm.lperm[p];
 #pragma unroll
   for (int r = 0; r < D; ++r) {
     b.x[r * cap + p] = a.x[r * cap + q];
@@ -247,7 +291,7 @@ __global__ void k_gather_all(const DomDesc *dd) {
   b.flags[p] = a.flags[q];
 }
 
-__global__ void k_flip(const DomDesc *dd, int ndom) {
+__global__ void __launch_bounds__(kBlock) k_flip(const DomDesc *dd, int ndom) {
   const int i = threadIdx.x + blockIdx.x * blockDim.x;
   if (i < ndom && *dd[i].active) *dd[i].cur ^= 1;
 }
@@ -255,7 +299,7 @@ __global__ void k_flip(const DomDesc *dd, int ndom) {
 // Fine-state store / restore (Eq. store_states): to_store = 1 copies the
 // current buffer to the store, 0 copies it back.
 template <int D, typename TB>
-__global__ void k_copy_state(const DomDesc *dd, int to_store) {
+__global__ void __launch_bounds__(kBlock) k_copy_state(const DomDesc *dd, int to_store) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -427,7 +471,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, i
 // v_i = (mv)_i / m_i on active nodes; scene-BC group of each DOF (lowest
 // group selecting the node whose mask holds the component).
 template <int D>
-__global__ void k_p2g_final(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -455,7 +499,7 @@ __global__ void k_p2g_final(const DomDesc *dd) {
 // H = F - I stored in TB, x in FP64.  With G = sum u_i gradN^T the update is
 // carried on H as H <- H + G + G H, which equals (I + G)(I + H) - I.
 template <int D, typename TB>
-__global__ void k_g2p(const DomDesc *dd, double dt, int *err) {
+__global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -556,7 +600,7 @@ __device__ inline double scene_value(const SceneBC &bc, int gi, const GridDev &g
 // the Jacobi-diagonal scatter targets of the first Newton iteration; partial
 // sums of the node mass (part_a) for the Newton tolerance floor.
 template <int D, typename TB>
-__global__ void k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf) {
+__global__ void __launch_bounds__(kBlock) k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || (int)blockIdx.x >= nb) return;
@@ -597,7 +641,7 @@ __global__ void k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc
 
 // Solve state at the start of an implicit solve: the gradient scale of the
 // absolute Newton floor, sum_i m_i * dx / dt^2.  One workgroup per domain.
-__global__ void k_solve_begin(const DomDesc *dd, double dt) {
+__global__ void __launch_bounds__(kBlock) k_solve_begin(const DomDesc *dd, double dt) {
   const DomDesc &dm = dd[blockIdx.y];
   __shared__ double red[kBlock / 64];
   const bool act = *dm.active != 0;
@@ -808,7 +852,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
 // masked to free DOFs; partial |g|^2 (part_a).  The Jacobi diagonal becomes
 // scatter + m/dt^2 (1 on non-free DOFs).
 template <int D, typename TB>
-__global__ void k_grad_node(const DomDesc *dd, double dt, double gx, double gy, double gz) {
+__global__ void __launch_bounds__(kBlock) k_grad_node(const DomDesc *dd, double dt, double gx, double gy, double gz) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || !phase_wants_grad(dm.ss->phase) || (int)blockIdx.x >= nb) return;
@@ -837,7 +881,7 @@ __global__ void k_grad_node(const DomDesc *dd, double dt, double gx, double gy, 
 // Newton stop test of every domain with a fresh gradient: stop when
 // |g_free| <= max(rtol |g_free(u0)|, atol * sum m * dx / dt^2) or after
 // max_newton steps, else go on to CG.  One workgroup per domain.
-__global__ void k_newton_check(const DomDesc *dd, double rtol, double atol, int max_newton) {
+__global__ void __launch_bounds__(kBlock) k_newton_check(const DomDesc *dd, double rtol, double atol, int max_newton) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active || !phase_wants_grad(dm.ss->phase)) return;
   __shared__ double red[kBlock / 64];
@@ -923,7 +967,7 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *lds12
 // DOFs); the gradient is cleared for the next Newton iteration and the CG
 // state reset.  Runs for domains whose Newton iteration goes on to CG.
 template <int D, typename TB>
-__global__ void k_cg_init(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || dm.ss->phase != kPhaseCgInit || (int)blockIdx.x >= nb) return;
@@ -1265,7 +1309,7 @@ __device__ inline bool ls_evaluates(const DomDesc &dm, double &alpha) {
 // partials in part_a.  The node workgroups also clear the Jacobi-diagonal
 // scatter target for the next Newton iteration (CG no longer reads it).
 template <int D, typename TB>
-__global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz) {
+__global__ void __launch_bounds__(kBlock) k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz) {
   constexpr int n = D * D;
   const DomDesc &dm = dd[blockIdx.y];
   const int nbp = particle_blocks(dm.np), nbn = node_blocks(dm.ndof);
@@ -1386,7 +1430,7 @@ __global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double g
 // evaluation at alpha = 1 is the one just computed); a searching domain
 // accepts when the energy change is negative, else halves alpha, or gives up
 // after max_ls halvings (the iterate is kept and the solve ends).
-__global__ void k_ls_check(const DomDesc *dd, int max_ls) {
+__global__ void __launch_bounds__(kBlock) k_ls_check(const DomDesc *dd, int max_ls) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   SolveState *s = dm.ss;
@@ -1424,7 +1468,7 @@ __global__ void k_ls_check(const DomDesc *dd, int max_ls) {
 // u += alpha del for every domain that accepted a step.  The phase stays
 // kPhaseStep until the next Newton test.
 template <typename TB>
-__global__ void k_newton_step(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_newton_step(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || (int)blockIdx.x >= nb) return;
@@ -1443,7 +1487,7 @@ __global__ void k_newton_step(const DomDesc *dd) {
 // ====================================================================== interface
 // Fixed-point node mass of the boundary-layer particles (Eq. boundary_grid_set).
 template <int D>
-__global__ void k_qbnd(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_qbnd(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1471,7 +1515,7 @@ __global__ void k_qbnd(const DomDesc *dd) {
 // Boundary node set Gamma (nodes whose boundary-layer mass exceeds tau) and
 // the receiver set before arbitration; the fixed-point accumulator is reset
 // for the next build.
-__global__ void k_gamma(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_gamma(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1483,7 +1527,7 @@ __global__ void k_gamma(const DomDesc *dd) {
 }
 
 // Number of receiver nodes of each domain; one workgroup per domain.
-__global__ void k_count_recv(const DomDesc *dd, int *out) {
+__global__ void __launch_bounds__(kBlock) k_count_recv(const DomDesc *dd, int *out) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   __shared__ double red[kBlock / 64];
@@ -1497,7 +1541,7 @@ __global__ void k_count_recv(const DomDesc *dd, int *out) {
 // lattice point is a fine boundary node is ambiguous; the larger fixed-point
 // node mass donates (ties: the coarse side) and leaves its receiver set.
 template <int D>
-__global__ void k_arbitrate(const DomDesc *ddB, const DomDesc *ddS, int *n_amb) {
+__global__ void __launch_bounds__(kBlock) k_arbitrate(const DomDesc *ddB, const DomDesc *ddS, int *n_amb) {
   const DomDesc &B = ddB[blockIdx.y], &S = ddS[blockIdx.y];
   if (!*B.active) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1520,7 +1564,7 @@ __global__ void k_arbitrate(const DomDesc *ddB, const DomDesc *ddS, int *n_amb) 
     S.recv[j] = 0;
 }
 
-__global__ void k_zero_proj(const DomDesc *ddB) {
+__global__ void __launch_bounds__(kBlock) k_zero_proj(const DomDesc *ddB) {
   const DomDesc &B = ddB[blockIdx.y];
   if (!*B.active) return;
   const int stride = gridDim.x * blockDim.x;
@@ -1532,7 +1576,7 @@ __global__ void k_zero_proj(const DomDesc *ddB) {
 // m_j N_I(x_j) and m_j v_j N_I(x_j) onto its coarse stencil.  The fine field
 // is S's P2G velocity unless an external array is given (a batch of one).
 template <int D>
-__global__ void k_project_scatter(const DomDesc *ddS, const DomDesc *ddB, const double *vS_ext, int *err) {
+__global__ void __launch_bounds__(kBlock) k_project_scatter(const DomDesc *ddS, const DomDesc *ddB, const double *vS_ext, int *err) {
   const DomDesc &S = ddS[blockIdx.y], &B = ddB[blockIdx.y];
   if (!*S.active) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1566,7 +1610,7 @@ __global__ void k_project_scatter(const DomDesc *ddS, const DomDesc *ddB, const 
 // out_I = num_I / (den_I + eps_tol) on coarse receivers, 0 elsewhere; out is
 // work buffer `which` of B, or out_ext when which < 0.
 template <int D>
-__global__ void k_project_final(const DomDesc *ddB, double eps_tol, int which, double *out_ext) {
+__global__ void __launch_bounds__(kBlock) k_project_final(const DomDesc *ddB, double eps_tol, int which, double *out_ext) {
   const DomDesc &B = ddB[blockIdx.y];
   if (!*B.active) return;
   const int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1580,7 +1624,7 @@ __global__ void k_project_final(const DomDesc *ddB, double eps_tol, int which, d
 // I_{B->S} at the fine receivers (Eq. interp_BtoS): source is B's buffer src
 // (or vB_ext when src < 0), target S's buffer dst (or out_ext when dst < 0).
 template <int D>
-__global__ void k_interp(const DomDesc *ddB, const DomDesc *ddS, int src, const double *vB_ext, int dst,
+__global__ void __launch_bounds__(kBlock) k_interp(const DomDesc *ddB, const DomDesc *ddS, int src, const double *vB_ext, int dst,
                          double *out_ext, int *err) {
   const DomDesc &B = ddB[blockIdx.y], &S = ddS[blockIdx.y];
   if (!*S.active) return;
@@ -1621,7 +1665,7 @@ __global__ void k_interp(const DomDesc *ddB, const DomDesc *ddS, int src, const 
 // T_m (Eq. temporal_interp) into the Schwarz data: v_bc = (1 - am) a + am b
 // for work buffers a, b.
 template <int D>
-__global__ void k_temporal(const DomDesc *dd, double am, int a_buf, int b_buf) {
+__global__ void __launch_bounds__(kBlock) k_temporal(const DomDesc *dd, double am, int a_buf, int b_buf) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const double *a = wbuf(dm, a_buf), *b = wbuf(dm, b_buf);
@@ -1631,7 +1675,7 @@ __global__ void k_temporal(const DomDesc *dd, double am, int a_buf, int b_buf) {
 
 // w2 = u / dt on active nodes, 0 elsewhere (v_B^(k+1) of Eq. implicit_solve_coarse).
 template <int D>
-__global__ void k_vel_from_u(const DomDesc *dd, double dt) {
+__global__ void __launch_bounds__(kBlock) k_vel_from_u(const DomDesc *dd, double dt) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1643,7 +1687,7 @@ __global__ void k_vel_from_u(const DomDesc *dd, double dt) {
 
 // v_bc = work buffer src.
 template <int D>
-__global__ void k_copy_vbc(const DomDesc *dd, int src) {
+__global__ void __launch_bounds__(kBlock) k_copy_vbc(const DomDesc *dd, int src) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const double *s = wbuf(dm, src);
@@ -1653,7 +1697,7 @@ __global__ void k_copy_vbc(const DomDesc *dd, int src) {
 // Partial sums over receiver nodes of |a - b|^2 and |a|^2 (Eq.
 // convergence_residuals) into part_b[2 block], part_b[2 block + 1].
 template <int D>
-__global__ void k_resid(const DomDesc *dd, int a_buf, int b_buf) {
+__global__ void __launch_bounds__(kBlock) k_resid(const DomDesc *dd, int a_buf, int b_buf) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.g.nn);
   if (!*dm.active || (int)blockIdx.x >= nb) return;
@@ -1678,7 +1722,7 @@ __global__ void k_resid(const DomDesc *dd, int a_buf, int b_buf) {
 
 // Sums of the residual partials of each domain into out[2 y], out[2 y + 1];
 // one workgroup per domain.
-__global__ void k_resid_final(const DomDesc *dd, double *out) {
+__global__ void __launch_bounds__(kBlock) k_resid_final(const DomDesc *dd, double *out) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   __shared__ double red[8];

@@ -83,7 +83,7 @@ struct DomDesc {
   int *active;      // takes part in batched launches (batch-owned)
   SolveState *ss;   // solve state (batch-owned)
   PartPtrs pb[2], st;
-  int *key, *count, *cell_start, *cursor, *perm;
+  int *key, *count, *cell_start, *cursor, *perm, *lperm;
   const double *mu, *lam;
   double *m, *vn, *u, *vbc, *gg;
   int8_t *bcg;
@@ -124,6 +124,7 @@ __global__ void k_keys(const DomDesc *dd, int *err);
 __global__ void k_scan(const DomDesc *dd);
 __global__ void k_scatter(const DomDesc *dd);
 __global__ void k_cellsort(const DomDesc *dd);
+__global__ void k_slot_layout(const DomDesc *dd);
 template <int D, typename TB>
 __global__ void k_gather_all(const DomDesc *dd);
 __global__ void k_flip(const DomDesc *dd, int ndom);
