@@ -308,6 +308,7 @@ void prof_harvest(osmpm_ctx *c, const std::vector<double> *cg_bytes = nullptr) {
 double alg_bytes(int which, int D, double np, double nn, double tb) {
   const double ns = (D * D) * (D * D + 1) / 2.0;
   switch (which) {
+    // nn: active nodes (m > 0) of the last P2G
     case OSMPM_K_CG_ITER:  // x, Atil per particle; per DOF r, w, s, u, p, del, diag and the mask read,
                            // p, s, r, u, del written, one w cleared, w accumulated (rmw); mass per node
       return np * (8.0 * D + tb * ns) + nn * (D * (tb * 15.0 + 1.0) + 8.0);
@@ -497,6 +498,8 @@ DomDesc make_desc(const osmpm_domain *d) {
   return x;
 }
 
+osmpm_status read_status(osmpm_batch *G);
+
 // Uploads the descriptors of members whose configuration changed since the
 // last upload and recomputes the launch extents.
 osmpm_status group_sync(osmpm_batch *G) {
@@ -543,11 +546,10 @@ osmpm_status group_sync(osmpm_batch *G) {
       E.lds_p2g = std::max(E.lds_p2g, lds_p2g(d->D, d->tg.nreg));
       E.lds_grad = std::max(E.lds_grad, lds_grad(d->D, d->tg.nreg));
       E.lds_hvp = std::max(E.lds_hvp, lds_hvp(d->D, d->tg.nreg, d->tb));
-      for (int w = 0; w < OSMPM_K_COUNT; ++w)
-        G->bytes[s][w][i] = alg_bytes(w, d->D, d->np, d->g.nn, (double)d->tb);
     }
     G->ext[s] = E;
   }
+  if (c->prof) return read_status(G);  // byte counts from the last P2G's active nodes
   return OSMPM_OK;
 }
 
@@ -581,6 +583,25 @@ osmpm_status status_error(osmpm_batch *G) {
   return device_error(G->c, err);
 }
 
+const SolveState *h_ss(const osmpm_batch *G, int s) {
+  return reinterpret_cast<const SolveState *>(G->h_status + G->off_ss) + s * G->n;
+}
+
+// Algorithmic bytes of the instrumented kernels for every domain of the
+// group, from particle counts and the active-node counts of the last P2G as
+// held by the host copy of the status block.
+void refresh_bytes(osmpm_batch *G) {
+  for (int s = 0; s < G->sides; ++s) {
+    const SolveState *hs = h_ss(G, s);
+    for (int w = 0; w < OSMPM_K_COUNT; ++w) G->bytes[s][w].resize(G->n, 0.0);
+    for (int i = 0; i < G->n; ++i) {
+      const osmpm_domain *d = G->dom[s][i];
+      for (int w = 0; w < OSMPM_K_COUNT; ++w)
+        G->bytes[s][w][i] = alg_bytes(w, d->D, d->np, hs[i].n_active, (double)d->tb);
+    }
+  }
+}
+
 // Copies the status block to its pinned host copy and waits.
 osmpm_status read_status(osmpm_batch *G) {
   osmpm_ctx *c = G->c;
@@ -588,10 +609,8 @@ osmpm_status read_status(osmpm_batch *G) {
   if (s) return s;
   HIP_TRY(c, hipMemcpyAsync(G->h_status, G->status, G->status_bytes, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->prof) refresh_bytes(G);
   return status_error(G);
-}
-const SolveState *h_ss(const osmpm_batch *G, int s) {
-  return reinterpret_cast<const SolveState *>(G->h_status + G->off_ss) + s * G->n;
 }
 const CgState *h_cg(const osmpm_batch *G, int s) {
   return reinterpret_cast<const CgState *>(G->h_status + G->off_cg) + s * G->n;
@@ -635,6 +654,14 @@ void p2g_side(osmpm_batch *G, int s, bool want_qall) {
   launch(c, -1, 0, -1, k_p2g_final<D>, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
   for (int i = 0; i < G->n; ++i)
     if (G->act[s][i] == 1) G->dom[s][i]->have_p2g = true;
+  if (c->prof && read_status(G) == OSMPM_OK && !c->pending.empty()) {
+    // charge the P2G just timed with the active nodes it produced
+    for (auto it = c->pending.rbegin(); it != c->pending.rend(); ++it)
+      if (it->which == OSMPM_K_P2G) {
+        it->bytes = active_bytes(G, s, OSMPM_K_P2G);
+        break;
+      }
+  }
 }
 
 template <int D, typename TB>

@@ -97,6 +97,7 @@ __global__ void __launch_bounds__(kBlock) k_zero_grid(const DomDesc *dd, int wan
   const int nn = dm.g.nn;
   const int stride = gridDim.x * blockDim.x;
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 == 0) dm.ss->n_active = 0;
   for (int i = i0; i < dm.nk; i += stride) dm.count[i] = 0;
   for (int i = i0; i < nn; i += stride) {
     dm.m[i] = 0.0;
@@ -469,14 +470,17 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, i
 }
 
 // v_i = (mv)_i / m_i on active nodes; scene-BC group of each DOF (lowest
-// group selecting the node whose mask holds the component).
+// group selecting the node whose mask holds the component); the count of
+// active nodes.
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const double m = (i < dm.g.nn) ? dm.m[i] : 0.0;
+  const unsigned long long act = __ballot(m > 0.0);
+  if ((threadIdx.x & 63) == 0 && act) atomicAdd(&dm.ss->n_active, (int)__popcll(act));
   if (i >= dm.g.nn) return;
-  const double m = dm.m[i];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     if (m > 0.0) dm.vn[i * D + a] /= m;
@@ -531,14 +535,17 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
 #pragma unroll
     for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
     const int i = node_flat<D>(g, idx);
-    if (!(dm.m[i] > 0.0)) continue;
+    // inactive nodes (m = 0) contribute nothing; both loads are issued
+    // unconditionally so that no load waits on the mass test
+    const double mi = dm.m[i];
     const double N = stencil_N<D>(st, k);
     double gN[D], dxv[D], ui[D];
     stencil_gradN<D>(st, k, gN);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       dxv[a] = ((double)k[a] - st.f[a]) * g.dx;
-      ui[a] = dm.u[i * D + a];
+      const double ua = dm.u[i * D + a];
+      ui[a] = (mi > 0.0) ? ua : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {

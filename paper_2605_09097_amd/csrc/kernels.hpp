@@ -48,6 +48,7 @@ struct SolveState {
   int ls_count;
   int converged, ls_failed;
   int newton_iters, cg_iters, ls_halvings;
+  int n_active;  // nodes with m > 0 after the last P2G
 };
 
 __host__ __device__ inline bool phase_wants_grad(int ph) { return ph == kPhaseGrad || ph == kPhaseStep; }
