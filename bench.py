@@ -74,6 +74,55 @@ def counter_traffic():
         return None
 
 
+def _kernel_stats(ctx):
+    """Per-kernel launch durations (HIP events on the library's stream) and
+    algorithmic bytes of the frames run since profiling was switched on."""
+    from paper_2605_09097_amd import binding
+
+    out = {}
+    for kid, name in ((binding.OSMPM_K_CG_ITER, "cg_iter"), (binding.OSMPM_K_P2G, "p2g"),
+                      (binding.OSMPM_K_G2P, "g2p"), (binding.OSMPM_K_GRAD_HESS, "grad_hess")):
+        n, ms, by = ctx.profile_query(kid)
+        if n:
+            out[name] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n, "bytes_per_launch": by / n,
+                         "achieved_GBps": by / (ms * 1e-3) / 1e9, "frac_hbm": by / (ms * 1e-3) / 8e12}
+    return out
+
+
+def large_form(ctx, name, prec, solve, frames, warmup):
+    """A large single-pair workload (the Hertz contact or the 3D fold): warm-up
+    frames, timed frames, then one instrumented frame for the per-kernel
+    launch durations.  Default tile shapes (no tuning)."""
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding, scenes
+
+    sc = scenes.workload(name)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
+    pair = binding.SchwarzPair(ctx, sc, precision=prec)
+    for _ in range(warmup):
+        pair.frame(opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    stats = [pair.frame(opts) for _ in range(frames)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    ctx.profile(True)
+    pair.frame(opts)
+    torch.cuda.synchronize()
+    kern = _kernel_stats(ctx)
+    ctx.profile(False)
+    pair.close()
+    ps = _frame_particle_steps(sc)
+    return {"workload": sc.name, "N_B": sc.B.n_particles, "N_S": sc.S.n_particles, "M": sc.M, "dT": sc.dT,
+            "frames": "%d-%d" % (warmup, warmup + frames - 1), "value": frames * ps / el,
+            "unit": "particle-steps/s", "ms_per_step": 1e3 * el / frames,
+            "schwarz_iters_mean": float(np.mean([st.iters for st in stats])),
+            "cg_per_frame_mean": float(np.mean([st.cg_B + st.cg_S for st in stats])),
+            "kernels": kern}
+
+
 def batched_form(ctx, n_scenes, steps, prec, solve):
     """The batched form: n_scenes independent inclusion scenes of uneven sizes
     (scenes.batch_scene) as one Schwarz batch, every stage one launch over all
@@ -98,9 +147,11 @@ def batched_form(ctx, n_scenes, steps, prec, solve):
     el = time.perf_counter() - t
     ctx.profile(True)
     sb.frame(opts)
-    n, ms, by = ctx.profile_query(binding.OSMPM_K_CG_ITER)
+    torch.cuda.synchronize()
+    kern = _kernel_stats(ctx)
     ctx.profile(False)
     sb.close()
+    cg = kern.get("cg_iter")
     ps = sum(_frame_particle_steps(sc) for sc in scs)
     iters = [st.iters for fr in stats for st in fr]
     return {"workload": "%d 2D inclusion scenes, radius U(0.03,0.08), inclusion E log-uniform [2e4,2e5], "
@@ -112,9 +163,10 @@ def batched_form(ctx, n_scenes, steps, prec, solve):
             "schwarz_iters_mean": float(np.mean(iters)), "schwarz_iters_max": int(max(iters)),
             "converged_all": bool(all(st.converged for fr in stats for st in fr)),
             "tile": list(tile), "tile_tuning_ms_per_frame": {str(k): 1e3 * v for k, v in tune.items()},
-            "roofline": ({"bound": "hbm", "kernel": "k_cg_iter", "achieved": by / (ms * 1e-3) / 1e9, "peak": 8000.0,
-                          "unit": "GB/s", "frac": by / (ms * 1e-3) / 8e12, "avg_us": 1e3 * ms / n,
-                          "bytes_per_launch": by / n, "launches": n} if n else None)}
+            "roofline": ({"bound": "hbm", "kernel": "k_cg_iter", "achieved": cg["achieved_GBps"], "peak": 8000.0,
+                          "unit": "GB/s", "frac": cg["frac_hbm"], "avg_us": cg["avg_us"],
+                          "bytes_per_launch": cg["bytes_per_launch"], "launches": cg["launches"]} if cg else None),
+            "kernels": kern}
 
 
 def adjoint_form(ctx, sc, prec, frames):
@@ -162,6 +214,8 @@ def main():
                     help="scenes of the batched form (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed frames of the batched form")
     ap.add_argument("--adjoint-frames", type=int, default=100, help="frames of the reverse-mode run (0 skips it)")
+    ap.add_argument("--large", default="hertz:2,fold:1",
+                    help="large single-pair workloads as name:timed_frames, comma separated ('' skips them)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's multiplicative Schwarz loop is "
@@ -233,14 +287,7 @@ def main():
         pair.frame(opts)
     torch.cuda.synchronize()
     elapsed_prof = time.perf_counter() - t1
-    for kid, name in ((binding.OSMPM_K_CG_ITER, "cg_iter"),
-                      (binding.OSMPM_K_P2G, "p2g"), (binding.OSMPM_K_G2P, "g2p"),
-                      (binding.OSMPM_K_GRAD_HESS, "grad_hess")):
-        n, ms, by = ctx.profile_query(kid)
-        if n:
-            kern[name] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n,
-                          "bytes_per_launch": by / n, "achieved_GBps": by / (ms * 1e-3) / 1e9,
-                          "frac_hbm": by / (ms * 1e-3) / 8e12}
+    kern = _kernel_stats(ctx)
     ctx.profile(False)
     pair.close()
     fp64 = None
@@ -253,6 +300,10 @@ def main():
     batched = None
     if args.batch_scenes > 0:
         batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve)
+    large = []
+    for item in filter(None, args.large.split(",")):
+        wl, nf = item.split(":")
+        large.append(large_form(ctx, wl, prec, solve, int(nf), warmup=1))
     if args.calibrate_copy:
         # a plain device copy of known size, for scaling HBM counters
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -299,6 +350,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "batched": batched,
+        "large": large,
         "adjoint": adjoint,
     }
     print(json.dumps(out))

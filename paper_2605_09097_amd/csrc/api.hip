@@ -110,6 +110,7 @@ struct osmpm_domain {
   int *d_cur = nullptr;    // current particle buffer (device)
   int nk = 0;
   int *key = nullptr, *count = nullptr, *cell_start = nullptr, *cursor = nullptr, *perm = nullptr, *lperm = nullptr;
+  int *tcount = nullptr;
   int n_mat = 0;
   double *mu = nullptr, *lam = nullptr;
   double m_ref = 1.0, tau = 0.0;
@@ -465,6 +466,7 @@ DomDesc make_desc(const osmpm_domain *d) {
   x.cursor = d->cursor;
   x.perm = d->perm;
   x.lperm = d->lperm;
+  x.tcount = d->tcount;
   x.mu = d->mu;
   x.lam = d->lam;
   x.m = d->m;
@@ -631,7 +633,9 @@ void sort_side(osmpm_batch *G, int s, int want_q) {
   launch(c, -1, 0, -1, k_zero_grid, dim3(blocks_for(std::max(E.max_nk, E.max_ndof), 1024), n), dim3(kBlock), 0, dd,
          want_q);
   launch(c, -1, 0, -1, k_keys<D>, dim3(pb, n), dim3(kBlock), 0, dd, G->err);
-  launch(c, -1, 0, -1, k_scan, dim3(1, n), dim3(1024), 0, dd);
+  launch(c, -1, 0, -1, k_tile_sum, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
+  launch(c, -1, 0, -1, k_tile_scan, dim3(1, n), dim3(1024), 0, dd);
+  launch(c, -1, 0, -1, k_cell_scan, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_scatter, dim3(pb, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_cellsort, dim3(blocks_for(E.max_nk), n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_slot_layout, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
@@ -1678,6 +1682,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->count, (size_t)d->nk + 1);
   if (!s) s = dalloc(d, &d->cell_start, (size_t)d->nk + 1);
   if (!s) s = dalloc(d, &d->cursor, (size_t)d->nk + 1);
+  if (!s) s = dalloc(d, &d->tcount, (size_t)d->tg.ntiles + 1);
   if (!s) s = dalloc(d, &d->m, nn);
   if (!s) s = dalloc(d, &d->vn, nd);
   if (!s) s = dalloc(d, &d->u, nd);

@@ -246,6 +246,30 @@ __device__ inline bool nh_stress(const T *F, T mu, T lam, T *P, T *A) {
   return true;
 }
 
+// True when the symmetric n x n matrix A is positive definite in T: its
+// Cholesky factorisation completes with positive pivots.  Such a matrix has
+// no negative eigenvalue, so its PSD projection is A itself.
+template <int n, typename T>
+__device__ inline bool chol_pd(const T *A) {
+  T L[n * (n + 1) / 2];  // packed lower triangle, row by row
+  bool ok = true;
+#pragma unroll
+  for (int i = 0; i < n; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) {
+      T v = A[i * n + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+      if (i == j) {
+        ok = ok && (v > T(0));
+        L[i * (i + 1) / 2 + i] = sqrt(v > T(0) ? v : T(1));
+      } else {
+        L[i * (i + 1) / 2 + j] = v / L[j * (j + 1) / 2 + j];
+      }
+    }
+  return ok;
+}
+
 // Projection of the symmetric n x n matrix A onto the PSD cone by a cyclic
 // Jacobi eigendecomposition with negative eigenvalues clamped to zero.  A is
 // left untouched when no eigenvalue is negative.  All indices are

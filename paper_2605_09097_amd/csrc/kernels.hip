@@ -136,26 +136,51 @@ __global__ void __launch_bounds__(kBlock) k_keys(const DomDesc *dd, int *err) {
   atomicAdd(&dm.count[k], 1);
 }
 
-// Exclusive scan of a domain's nk counts by one workgroup of 1024 threads,
-// 4096 elements per pass (each thread four consecutive counts, so loads and
-// stores are coalesced); cell_start[nk] is the total.  cursor receives a copy
-// of the offsets for the scatter.
-__global__ void __launch_bounds__(1024) k_scan(const DomDesc *dd) {
+// Bin offsets in three steps, using that bins are tile-major (tvol bins per
+// tile): the total of every tile, an exclusive scan of the tile totals, and
+// the scan of each tile's bins on top of its tile offset.
+
+// Sum of v over the workgroup (kBlock threads); every thread gets it.
+__device__ inline int block_sum_int(int v, int *lds4) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return lds4[0] + lds4[1] + lds4[2] + lds4[3];
+}
+
+__global__ void __launch_bounds__(kBlock) k_tile_sum(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active || (int)blockIdx.x >= dm.tg.ntiles) return;
+  __shared__ int red[kBlock / 64];
+  const int tvol = dm.tg.tvol;
+  const int *cnt = dm.count + (size_t)blockIdx.x * tvol;
+  int v = 0;
+  for (int c = threadIdx.x; c < tvol; c += kBlock) v += cnt[c];
+  v = block_sum_int(v, red);
+  if (threadIdx.x == 0) dm.tcount[blockIdx.x] = v;
+}
+
+// In-place exclusive scan of the tile totals by one workgroup of 1024
+// threads, 4096 totals per pass (four consecutive ones per thread, so loads
+// and stores are coalesced); the grand total goes to tcount[ntiles] and to
+// cell_start[nk].
+__global__ void __launch_bounds__(1024) k_tile_scan(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   __shared__ int wsum[16];
-  const int nk = dm.nk;
-  const int *count = dm.count;
-  int *cell_start = dm.cell_start, *cursor = dm.cursor;
+  const int nt = dm.tg.ntiles;
+  int *tc = dm.tcount;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int carry = 0;
-  for (int base = 0; base < nk; base += 4096) {
+  for (int base = 0; base < nt; base += 4096) {
     int v[4];
     int s = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int idx = base + 4 * tid + j;
-      v[j] = (idx < nk) ? count[idx] : 0;
+      v[j] = (idx < nt) ? tc[idx] : 0;
       s += v[j];
     }
     int xs = s;
@@ -180,16 +205,51 @@ __global__ void __launch_bounds__(1024) k_scan(const DomDesc *dd) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int idx = base + 4 * tid + j;
-      if (idx < nk) {
-        cell_start[idx] = excl;
-        cursor[idx] = excl;
-      }
+      if (idx < nt) tc[idx] = excl;
       excl += v[j];
     }
     carry += wsum[15];
     __syncthreads();
   }
-  if (tid == 0) cell_start[nk] = carry;
+  if (tid == 0) {
+    tc[nt] = carry;
+    dm.cell_start[dm.nk] = carry;
+  }
+}
+
+// Exclusive scan of one tile's bins, offset by the tile's
+// start; cursor receives a copy of the offsets for the scatter.
+__global__ void __launch_bounds__(kBlock) k_cell_scan(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active || (int)blockIdx.x >= dm.tg.ntiles) return;
+  __shared__ int wsum[kBlock / 64];
+  const int tvol = dm.tg.tvol;
+  const size_t b0 = (size_t)blockIdx.x * tvol;
+  const int *cnt = dm.count + b0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int carry = dm.tcount[blockIdx.x];
+  for (int base = 0; base < tvol; base += kBlock) {
+    const int c = base + tid;
+    const int v = (c < tvol) ? cnt[c] : 0;
+    int xs = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(xs, off, 64);
+      if (lane >= off) xs += y;
+    }
+    if (lane == 63) wsum[w] = xs;
+    __syncthreads();
+    int before = 0;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (c < tvol) {
+      const int e = carry + before + xs - v;
+      dm.cell_start[b0 + c] = e;
+      dm.cursor[b0 + c] = e;
+    }
+    carry += tot;
+    __syncthreads();
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_scatter(const DomDesc *dd) {
@@ -769,46 +829,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
         for (int c = 0; c < D; ++c) tv += Pk[a * D + c] * Fn[b * D + c];
         T[a * D + b] = V * tv;
       }
-    TB At[ns];
-    {
-      TB Fb[n], Fnb[n], A[n * n];
-#pragma unroll
-      for (int k = 0; k < n; ++k) {
-        Fb[k] = (TB)Fc[k];
-        Fnb[k] = (TB)Fn[k];
-      }
-      nh_stress<D, TB>(Fb, (TB)mu, (TB)lam, nullptr, A);
-      if (project) psd_project<n, TB>(A);
-      // T1[(ab),(cz)] = sum_y F_by A[(ay),(cz)];  Atil[(ab),(ce)] = V sum_z T1[(ab),(cz)] F_ez
-      TB T1[n * n];
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int b = 0; b < D; ++b)
-#pragma unroll
-          for (int q = 0; q < n; ++q) {
-            TB tv = TB(0);
-#pragma unroll
-            for (int y = 0; y < D; ++y) tv += Fnb[b * D + y] * A[(a * D + y) * n + q];
-            T1[(a * D + b) * n + q] = tv;
-          }
-      const TB Vb = (TB)V;
-#pragma unroll
-      for (int rr = 0; rr < n; ++rr)
-#pragma unroll
-        for (int c = 0; c < D; ++c)
-#pragma unroll
-          for (int e = 0; e < D; ++e) {
-            const int cc = c * D + e;
-            if (cc < rr) continue;
-            TB tv = TB(0);
-#pragma unroll
-            for (int z = 0; z < D; ++z) tv += T1[rr * n + c * D + z] * Fnb[e * D + z];
-            At[sym_index<n>(rr, cc)] = Vb * tv;
-          }
-#pragma unroll
-      for (int k = 0; k < ns; ++k) Atil[k * cap + p] = At[k];
-    }
+    // gradient scatter first, so that T is dead during the tangent work
 #pragma unroll
     for (int s = 0; s < stencil_count<D>(); ++s) {
       int k[3];
@@ -823,6 +844,58 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
         for (int b = 0; b < D; ++b) tv += T[a * D + b] * gN[b];
         atomicAdd(&lg[a * nreg + r], tv);
       }
+    }
+    TB At[ns];
+    {
+      TB Fb[n], Fnb[n], A[n * n];
+#pragma unroll
+      for (int k = 0; k < n; ++k) {
+        Fb[k] = (TB)Fc[k];
+        Fnb[k] = (TB)Fn[k];
+      }
+      nh_stress<D, TB>(Fb, (TB)mu, (TB)lam, nullptr, A);
+      // positive definite tangents (the common case) skip the eigensolve
+      if (project && !chol_pd<n, TB>(A)) psd_project<n, TB>(A);
+      // Atil[(ab),(ce)] = V sum_z Q[(ab),(cz)] F_ez with Q[(ab),(cz)] =
+      // sum_y F_by A[(ay),(cz)], one (a, c) block of A at a time; blocks with
+      // c < a hold only the lower triangle, which the packed form omits.
+      const TB Vb = (TB)V;
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = a; c < D; ++c) {
+          TB Q[D * D];
+#pragma unroll
+          for (int b = 0; b < D; ++b)
+#pragma unroll
+            for (int z = 0; z < D; ++z) {
+              TB tv = TB(0);
+#pragma unroll
+              for (int y = 0; y < D; ++y) tv += Fnb[b * D + y] * A[(a * D + y) * n + c * D + z];
+              Q[b * D + z] = tv;
+            }
+#pragma unroll
+          for (int b = 0; b < D; ++b)
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+              const int rr = a * D + b, cc = c * D + e;
+              if (cc < rr) continue;
+              TB tv = TB(0);
+#pragma unroll
+              for (int z = 0; z < D; ++z) tv += Q[b * D + z] * Fnb[e * D + z];
+              At[sym_index<n>(rr, cc)] = Vb * tv;
+            }
+        }
+#pragma unroll
+      for (int k = 0; k < ns; ++k) Atil[k * cap + p] = At[k];
+    }
+#pragma unroll
+    for (int s = 0; s < stencil_count<D>(); ++s) {
+      int k[3];
+      stencil_offset<D>(s, k);
+      double gN[D];
+      stencil_gradN<D>(st, k, gN);
+      const int r = region_slot<D>(tg, l, k);
       TB gb[D];
 #pragma unroll
       for (int a = 0; a < D; ++a) gb[a] = (TB)gN[a];

@@ -85,6 +85,7 @@ struct DomDesc {
   SolveState *ss;   // solve state (batch-owned)
   PartPtrs pb[2], st;
   int *key, *count, *cell_start, *cursor, *perm, *lperm;
+  int *tcount;  // per-tile bin totals, then tile offsets [ntiles + 1]
   const double *mu, *lam;
   double *m, *vn, *u, *vbc, *gg;
   int8_t *bcg;
@@ -122,7 +123,9 @@ __global__ void k_temporal_1(int64_t n, double am, const double *vn, const doubl
 // binning
 template <int D>
 __global__ void k_keys(const DomDesc *dd, int *err);
-__global__ void k_scan(const DomDesc *dd);
+__global__ void k_tile_sum(const DomDesc *dd);
+__global__ void k_tile_scan(const DomDesc *dd);
+__global__ void k_cell_scan(const DomDesc *dd);
 __global__ void k_scatter(const DomDesc *dd);
 __global__ void k_cellsort(const DomDesc *dd);
 __global__ void k_slot_layout(const DomDesc *dd);
