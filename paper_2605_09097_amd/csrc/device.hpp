@@ -44,19 +44,21 @@ struct SceneBC {
   double param[kMaxGroups][8];
 };
 
-template <int D>
+template <int D, typename T = double>
 struct Stencil {
   int base[D];
-  double f[D];
-  double w[D][3];
-  double dw[D][3];
+  T f[D];
+  T w[D][3];
+  T dw[D][3];
 };
 
 // Quadratic B-spline weights of a point: xi = (x - o) / dx, base =
 // floor(xi - 1/2), f = xi - base.  Returns false when the 3^d stencil leaves
 // the grid; the base is then clamped so every later access stays in bounds.
-template <int D>
-__device__ inline bool stencil_eval(const double *xp, const GridDev &g, Stencil<D> &s) {
+// The base and f are always formed in FP64 (the base decides the bin); the
+// weights are evaluated in T from f rounded to T.
+template <int D, typename T>
+__device__ inline bool stencil_eval(const double *xp, const GridDev &g, Stencil<D, T> &s) {
 #pragma clang fp contract(off)
   bool ok = true;
 #pragma unroll
@@ -68,24 +70,25 @@ __device__ inline bool stencil_eval(const double *xp, const GridDev &g, Stencil<
       ok = false;
       bf = (bf > hi) ? hi : 0.0;
     }
-    const double f = xi - bf;
-    const double t0 = 1.5 - f, t1 = f - 1.0, t2 = f - 0.5;
+    const T f = (T)(xi - bf);
+    const T t0 = T(1.5) - f, t1 = f - T(1.0), t2 = f - T(0.5);
+    const T idx = (T)g.inv_dx;
     s.base[a] = (int)bf;
     s.f[a] = f;
-    s.w[a][0] = 0.5 * (t0 * t0);
-    s.w[a][1] = 0.75 - t1 * t1;
-    s.w[a][2] = 0.5 * (t2 * t2);
-    s.dw[a][0] = -t0 * g.inv_dx;
-    s.dw[a][1] = -2.0 * t1 * g.inv_dx;
-    s.dw[a][2] = t2 * g.inv_dx;
+    s.w[a][0] = T(0.5) * (t0 * t0);
+    s.w[a][1] = T(0.75) - t1 * t1;
+    s.w[a][2] = T(0.5) * (t2 * t2);
+    s.dw[a][0] = -t0 * idx;
+    s.dw[a][1] = T(-2.0) * t1 * idx;
+    s.dw[a][2] = t2 * idx;
   }
   return ok;
 }
 
 // N_ip of stencil offset k: w_x w_y in 2D, (w_x w_y) w_z in 3D (this product
 // order feeds the fixed-point masses).
-template <int D>
-__device__ inline double stencil_N(const Stencil<D> &s, const int *k) {
+template <int D, typename T>
+__device__ inline T stencil_N(const Stencil<D, T> &s, const int *k) {
 #pragma clang fp contract(off)
   if constexpr (D == 2) {
     return s.w[0][k[0]] * s.w[1][k[1]];
@@ -94,8 +97,8 @@ __device__ inline double stencil_N(const Stencil<D> &s, const int *k) {
   }
 }
 
-template <int D>
-__device__ inline void stencil_gradN(const Stencil<D> &s, const int *k, double *gN) {
+template <int D, typename T>
+__device__ inline void stencil_gradN(const Stencil<D, T> &s, const int *k, T *gN) {
   if constexpr (D == 2) {
     gN[0] = s.dw[0][k[0]] * s.w[1][k[1]];
     gN[1] = s.w[0][k[0]] * s.dw[1][k[1]];

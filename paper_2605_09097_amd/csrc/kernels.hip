@@ -412,8 +412,8 @@ __device__ inline int region_node(const TileGeom &tg, const GridDev &g, const in
 
 // Local offsets of a particle's base node in its tile; false if it does not
 // belong to the tile (a corrupted binning; the particle is then skipped).
-template <int D>
-__device__ inline bool local_base(const TileGeom &tg, const Stencil<D> &st, const int *org, int *l) {
+template <int D, typename T>
+__device__ inline bool local_base(const TileGeom &tg, const Stencil<D, T> &st, const int *org, int *l) {
   bool ok = true;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -435,10 +435,12 @@ __device__ inline int region_slot(const TileGeom &tg, const int *l, const int *k
 // ====================================================================== P2G
 // APIC P2G (Eq. p2g_transfer) of one tile into LDS, then global atomics.
 // Also the fixed-point node masses (all particles, and per scene group).
-// Velocities and affine matrices are read in the bulk type TB and every
-// contribution is rounded to TB; tile sums are accumulated in FP64 LDS
-// (ds_add_f64, which measures about twice as fast as ds_add_f32 on gfx950)
-// and added to the FP64 grid.
+// The weights N and the mass terms m_p N are evaluated in FP64 and rounded
+// to the bulk type TB (so the active set m_i > 0 and the fixed-point masses
+// follow their definitions exactly); the momentum terms are evaluated in TB
+// from the TB velocities and affine matrices.  Tile sums are accumulated in
+// FP64 LDS (ds_add_f64, which measures about twice as fast as ds_add_f32 on
+// gfx950) and added to the FP64 grid.
 template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
@@ -462,15 +464,17 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, i
   for (int r = threadIdx.x; r < nreg * (1 + D); r += kBlock) lm[r] = 0.0;
   for (int r = threadIdx.x; r < nreg * nq; r += kBlock) lq[r] = 0;
   __syncthreads();
+  const TB dx_t = (TB)g.dx, Dinv_t = (TB)dm.Dinv;
   for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    double xp[D], vp[D], Bp[D * D];
+    double xp[D];
+    TB vp[D], Bp[D * D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       xp[a] = P.x[a * cap + p];
-      vp[a] = (double)v[a * cap + p];
+      vp[a] = v[a * cap + p];
     }
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Bp[k] = (double)B[k * cap + p];
+    for (int k = 0; k < D * D; ++k) Bp[k] = B[k * cap + p];
     Stencil<D> st;
     stencil_eval<D>(xp, g, st);
     int l[3];
@@ -481,23 +485,29 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, i
     const double mp = P.mass[p];
     const double mq = mp * dm.scale;
     const uint8_t fl = P.flags[p];
+    TB f_t[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) f_t[a] = (TB)st.f[a];
 #pragma unroll
     for (int s = 0; s < stencil_count<D>(); ++s) {
       int k[3];
       stencil_offset<D>(s, k);
+      // N and the mass term in FP64, so that m_i > 0 (the active set) and
+      // the fixed-point masses match their definition exactly; the momentum
+      // term in the bulk type
       const double N = stencil_N<D>(st, k);
-      double dxv[D];
-#pragma unroll
-      for (int a = 0; a < D; ++a) dxv[a] = ((double)k[a] - st.f[a]) * g.dx;
       const int r = region_slot<D>(tg, l, k);
-      const double mN = mp * N;
-      atomicAdd(&lm[r], (double)(TB)mN);
+      const TB mN = (TB)(mp * N);
+      atomicAdd(&lm[r], (double)mN);
+      TB dxv[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) dxv[a] = ((TB)k[a] - f_t[a]) * dx_t;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        double aff = 0.0;
+        TB aff = TB(0);
 #pragma unroll
         for (int b = 0; b < D; ++b) aff += Bp[a * D + b] * dxv[b];
-        atomicAdd(&lmv[a * nreg + r], (double)(TB)(mN * (vp[a] + dm.Dinv * aff)));
+        atomicAdd(&lmv[a * nreg + r], (double)(mN * (vp[a] + Dinv_t * aff)));
       }
       if (want_q) {
         const long long q = fixed_mass(N, mq);
@@ -559,9 +569,11 @@ __global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
 
 // ====================================================================== G2P
 // APIC G2P with v_i = u_i / dt (Eqs. g2p_v, g2p_B), F <- (I + sum u_i gradN^T) F
-// (Eq. F_update) and x <- x + dt v_p (Eq. advection); FP64 arithmetic, v, B,
-// H = F - I stored in TB, x in FP64.  With G = sum u_i gradN^T the update is
-// carried on H as H <- H + G + G H, which equals (I + G)(I + H) - I.
+// (Eq. F_update) and x <- x + dt v_p (Eq. advection).  Weights and the sums
+// v_p, B_p, G = sum u_i gradN^T are formed in the bulk type TB (FP32 in the
+// mixed path); v, B and H = F - I are stored in TB, and the update of H and
+// the advection of x are carried out in FP64.  The update is applied to H as
+// H <- H + G + G H, which equals (I + G)(I + H) - I.
 template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
@@ -577,17 +589,18 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
   double xp[D];
 #pragma unroll
   for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
-  Stencil<D> st;
+  Stencil<D, TB> st;
   if (!stencil_eval<D>(xp, g, st)) atomicOr(err, kErrOutOfGrid);
-  double vp[D], Bp[D * D], G[D * D];
+  TB vp[D], Bp[D * D], G[D * D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) vp[a] = 0.0;
+  for (int a = 0; a < D; ++a) vp[a] = TB(0);
 #pragma unroll
   for (int k = 0; k < D * D; ++k) {
-    Bp[k] = 0.0;
-    G[k] = 0.0;
+    Bp[k] = TB(0);
+    G[k] = TB(0);
   }
   const double idt = 1.0 / dt;
+  const TB dx_t = (TB)g.dx;
 #pragma unroll
   for (int s = 0; s < stencil_count<D>(); ++s) {
     int k[3], idx[3];
@@ -598,23 +611,24 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
     // inactive nodes (m = 0) contribute nothing; both loads are issued
     // unconditionally so that no load waits on the mass test
     const double mi = dm.m[i];
-    const double N = stencil_N<D>(st, k);
-    double gN[D], dxv[D], ui[D];
+    const TB N = stencil_N<D>(st, k);
+    TB gN[D], dxv[D];
+    double ui[D];
     stencil_gradN<D>(st, k, gN);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      dxv[a] = ((double)k[a] - st.f[a]) * g.dx;
+      dxv[a] = ((TB)k[a] - st.f[a]) * dx_t;
       const double ua = dm.u[i * D + a];
       ui[a] = (mi > 0.0) ? ua : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      const double vi = ui[a] * idt;
+      const TB vi = (TB)(ui[a] * idt);
       vp[a] += N * vi;
 #pragma unroll
       for (int b = 0; b < D; ++b) {
         Bp[a * D + b] += N * vi * dxv[b];
-        G[a * D + b] += ui[a] * gN[b];
+        G[a * D + b] += (TB)ui[a] * gN[b];
       }
     }
   }
@@ -625,16 +639,16 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int b = 0; b < D; ++b) {
-      double t = Hp[a * D + b] + G[a * D + b];
+      double t = Hp[a * D + b] + (double)G[a * D + b];
 #pragma unroll
-      for (int e = 0; e < D; ++e) t += G[a * D + e] * Hp[e * D + b];
+      for (int e = 0; e < D; ++e) t += (double)G[a * D + e] * Hp[e * D + b];
       H[(a * D + b) * cap + p] = (TB)t;
-      B[(a * D + b) * cap + p] = (TB)Bp[a * D + b];
+      B[(a * D + b) * cap + p] = Bp[a * D + b];
     }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    v[a * cap + p] = (TB)vp[a];
-    P.x[a * cap + p] = xp[a] + dt * vp[a];
+    v[a * cap + p] = vp[a];
+    P.x[a * cap + p] = xp[a] + dt * (double)vp[a];
   }
 }
 
@@ -1295,7 +1309,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
 #pragma unroll
         for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + p];
       }
-      Stencil<D> st;
+      Stencil<D, TB> st;  // weights in the bulk type
       stencil_eval<D>(xp, g, st);
       int l[3];
       if (!local_base<D>(tg, st, org, l)) continue;
@@ -1306,14 +1320,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
       for (int s = 0; s < stencil_count<D>(); ++s) {
         int k[3];
         stencil_offset<D>(s, k);
-        double gN[D];
+        TB gN[D];
         stencil_gradN<D>(st, k, gN);
         const int r = region_slot<D>(tg, l, k);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           const TB ua = lu[a * nreg + r];
 #pragma unroll
-          for (int b = 0; b < D; ++b) G[a * D + b] += ua * (TB)gN[b];
+          for (int b = 0; b < D; ++b) G[a * D + b] += ua * gN[b];
         }
       }
       TB T[n];
@@ -1332,14 +1346,14 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
       for (int s = 0; s < stencil_count<D>(); ++s) {
         int k[3];
         stencil_offset<D>(s, k);
-        double gN[D];
+        TB gN[D];
         stencil_gradN<D>(st, k, gN);
         const int r = region_slot<D>(tg, l, k);
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           TB tv = TB(0);
 #pragma unroll
-          for (int b = 0; b < D; ++b) tv += T[a * D + b] * (TB)gN[b];
+          for (int b = 0; b < D; ++b) tv += T[a * D + b] * gN[b];
           atomicAdd(&lh[a * nreg + r], (double)tv);
         }
       }
