@@ -123,6 +123,44 @@ def large_form(ctx, name, prec, solve, frames, warmup):
             "kernels": kern}
 
 
+def domain_probe(ctx, spec_s, prec):
+    """Per-kernel launch durations on one domain of a workload
+    (name:side[:tile], side B or S, tile as AxB or AxBxC): five P2Gs, one
+    implicit solve of two Newton steps with exactly 100 CG iterations each
+    (random particle velocities from seed 7 so that the solve has work),
+    and three P2G + G2P pairs."""
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding, scenes
+
+    parts = spec_s.split(":")
+    sc = scenes.workload(parts[0])
+    spec = sc.B if parts[1] == "B" else sc.S
+    tile = tuple(int(t) for t in parts[2].split("x")) if len(parts) > 2 else None
+    dom = binding.Domain(ctx, spec, precision=prec, tile=tile)
+    rng = np.random.default_rng(7)
+    v = 0.05 * rng.standard_normal(spec.x.shape)
+    dom.set_state(*[torch.as_tensor(a) for a in (spec.x, v, spec.B, spec.F)])
+    dt = sc.dT / (sc.M if parts[1] == "S" else 1)
+    dom.p2g()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(5):
+        dom.p2g()
+    st = dom.implicit_solve(dt, binding.solve_opts(newton_rtol=0.0, newton_atol=0.0, cg_rtol=0.0, max_newton=2,
+                                                   max_cg=100))
+    for _ in range(3):
+        dom.g2p(dt)
+        dom.p2g()
+    torch.cuda.synchronize()
+    kern = _kernel_stats(ctx)
+    ctx.profile(False)
+    dom.close()
+    return {"probe": spec_s, "particles": spec.n_particles, "path": "mixed" if prec == binding.OSMPM_MIXED
+            else "fp64", "newton": st.newton_iters, "cg": st.cg_iters, "kernels": kern}
+
+
 def batched_form(ctx, n_scenes, steps, prec, solve):
     """The batched form: n_scenes independent inclusion scenes of uneven sizes
     (scenes.batch_scene) as one Schwarz batch, every stage one launch over all
@@ -214,6 +252,8 @@ def main():
                     help="scenes of the batched form (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed frames of the batched form")
     ap.add_argument("--adjoint-frames", type=int, default=100, help="frames of the reverse-mode run (0 skips it)")
+    ap.add_argument("--domain-probe", default="",
+                    help="only time the kernels on one domain, workload:side[:tile] (e.g. hertz:B:8x8), and exit")
     ap.add_argument("--large", default="hertz:2,fold:1",
                     help="large single-pair workloads as name:timed_frames, comma separated ('' skips them)")
     args = ap.parse_args()
@@ -227,9 +267,20 @@ def main():
 
     from paper_2605_09097_amd import binding, scenes
 
-    sc = scenes.workload(WORKLOAD)
     ctx = binding.Context(0)
     prec = binding.OSMPM_MIXED if args.precision == "mixed" else binding.OSMPM_FP64
+    if args.domain_probe:
+        out = domain_probe(ctx, args.domain_probe, prec)
+        if args.calibrate_copy:
+            a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+            b = torch.empty_like(a)
+            for _ in range(3):
+                b.copy_(a)
+            torch.cuda.synchronize()
+        print(json.dumps(out))
+        ctx.close()
+        return
+    sc = scenes.workload(WORKLOAD)
     solve = binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10)
     opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
     opts64 = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol)

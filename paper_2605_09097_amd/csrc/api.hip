@@ -42,8 +42,9 @@ struct ProfPending {
   hipEvent_t a, b;
   int which;
   double bytes;
-  int cg_iter;  // index of a CG launch within its cycle, -1 otherwise
+  int cg_iter;  // index of a CG launch within its cycle, kCgSpan for a whole cycle's CG launches, -1 otherwise
 };
+constexpr int kCgSpan = -2;
 struct ProfSlot {
   int64_t launches = 0;
   double ms = 0.0, bytes = 0.0;
@@ -279,20 +280,31 @@ void launch(osmpm_ctx *c, int which, double bytes, int cg_iter, F kernel, dim3 g
 // Folds completed timings into the counters (only after a stream
 // synchronisation).  A CG launch with cycle index j is charged cg_bytes[j],
 // the algorithmic bytes of the domains that iterated in it; launches in
-// which every domain had finished (no entry, or zero) are dropped.
+// which every domain had finished (no entry, or zero) are dropped.  A span
+// (the CG launches of one cycle between two events) counts its working
+// launches and is charged their bytes and the whole span's time.
 void prof_harvest(osmpm_ctx *c, const std::vector<double> *cg_bytes = nullptr) {
   for (const ProfPending &p : c->pending) {
     double bytes = p.bytes;
-    bool keep = true;
+    int64_t n = 1;
     if (p.cg_iter >= 0) {
       bytes = (cg_bytes && p.cg_iter < (int)cg_bytes->size()) ? (*cg_bytes)[p.cg_iter] : 0.0;
-      keep = bytes > 0.0;
+    } else if (p.cg_iter == kCgSpan) {
+      bytes = 0.0;
+      n = 0;
+      if (cg_bytes)
+        for (double v : *cg_bytes)
+          if (v > 0.0) {
+            bytes += v;
+            ++n;
+          }
     }
-    if (keep) {
+    if (p.cg_iter != -1 && !(bytes > 0.0)) n = 0;
+    if (n > 0) {
       float ms = 0.0f;
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
         ProfSlot &sl = c->slots[p.which];
-        sl.launches += 1;
+        sl.launches += n;
         sl.ms += ms;
         sl.bytes += bytes;
       }
@@ -727,9 +739,20 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     b += b & 1;  // even, so every cycle starts at parity 0
     if (c->graphs && !c->prof) b = (b + 3) & ~3;  // fewer distinct cycle graphs
     auto cycle = [&]() {
+      // With profiling on, the cycle's back-to-back CG launches are timed as
+      // one span between two events: an event pair on every launch would add
+      // a fixed cost of about 2 us to each measured duration.
+      hipEvent_t sa = nullptr, sb = nullptr;
+      if (c->prof && !c->rec) {
+        sa = prof_event(c);
+        sb = prof_event(c);
+        if (sa && sb && hipEventRecord(sa, c->stream) != hipSuccess) sa = nullptr;
+      }
       for (int j = 0; j < b; ++j)
-        launch(c, OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt,
-               o->cg_rtol, (int)o->max_cg);
+        launch(c, sa ? -1 : OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd,
+               j & 1, dt, o->cg_rtol, (int)o->max_cg);
+      if (sa && sb && hipEventRecord(sb, c->stream) == hipSuccess)
+        c->pending.push_back({sa, sb, OSMPM_K_CG_ITER, 0.0, kCgSpan});
       launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
              o->gravity[0], o->gravity[1], o->gravity[2]);
       launch(c, -1, 0, -1, k_ls_check, dim3(1, n), blk, 0, dd, (int)o->max_ls);
