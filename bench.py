@@ -252,6 +252,9 @@ def main():
                     help="scenes of the batched form (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed frames of the batched form")
     ap.add_argument("--adjoint-frames", type=int, default=100, help="frames of the reverse-mode run (0 skips it)")
+    ap.add_argument("--eshelby", default="",
+                    help="only run the inclusion efficiency study (single-domain fine vs OS-MPM to equilibrium) "
+                         "for ratio:inv_dx items, comma separated (e.g. 2:400,2:800), and exit")
     ap.add_argument("--domain-probe", default="",
                     help="only time the kernels on one domain, workload:side[:tile] (e.g. hertz:B:8x8), and exit")
     ap.add_argument("--large", default="hertz:2,fold:1",
@@ -269,6 +272,20 @@ def main():
 
     ctx = binding.Context(0)
     prec = binding.OSMPM_MIXED if args.precision == "mixed" else binding.OSMPM_FP64
+    if args.eshelby:
+        from paper_2605_09097_amd import eshelby
+
+        rows = []
+        for item in args.eshelby.split(","):
+            ratio, inv_dx = item.split(":")
+            pair = {m: eshelby.run(ctx, m, float(ratio), int(inv_dx), prec) for m in ("single", "dual")}
+            pair["speedup"] = pair["single"]["wall_s"] / pair["dual"]["wall_s"]
+            rows.append(pair)
+            print(json.dumps(pair), file=sys.stderr, flush=True)
+        print(json.dumps({"study": "inclusion efficiency, single-domain fine vs OS-MPM",
+                          "path": args.precision, "runs": rows}))
+        ctx.close()
+        return
     if args.domain_probe:
         out = domain_probe(ctx, args.domain_probe, prec)
         if args.calibrate_copy:

@@ -148,14 +148,16 @@ def _domain(dim, h0, origin_q, dx_q, n_nodes, x, mat, E, nu, rho, ppc1d, flags, 
 def inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.05, E_matrix=1e4, E_inc=1e5,
                     nu=0.3, rho=1000.0, seed=0, dT=1e-3, M=2, n_frames=50, top_disp=0.01,
                     ramp_frames=50, tau_rel=1e-3, eps_tol_rel=1e-9, delta=0.0, loaded=True,
-                    name="inclusion"):
+                    clamped=False, name="inclusion"):
     """2D elastic inclusion (Sec. 4.3 geometry).  Coarse grid on [0,1]^2 holding
     the matrix square [0.1,0.9]^2 outside r = 0.1; fine grid on [0.3,0.7]^2
     holding the matrix annulus r_inc < r <= 0.15 and the inclusion r <= r_inc.
 
     loaded=True: bottom layer clamped, top layer driven down in y (roller in x)
-    by top_disp ramped linearly over ramp_frames frames.  delta > 0 gives the
-    inclusion the eigenstrain F0 = (1 - delta) I of Sec. 4.3.
+    by top_disp ramped linearly over ramp_frames frames.  clamped=True (with
+    loaded=False): the outer particle layer of all four edges is fixed.
+    delta > 0 gives the inclusion the eigenstrain F0 = (1 - delta) I of
+    Sec. 4.3.
     """
     lat = math.lcm(inv_dx_B, inv_dx_S, 10)
     h0 = 1.0 / lat
@@ -184,6 +186,9 @@ def inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.05, E_matrix=1e4,
     if loaded:
         flagsB = flagsB | np.where(xB[:, 1] < 0.1 + spB, 2, 0) | np.where(xB[:, 1] > 0.9 - spB, 4, 0)
         bc_kind, bc_mask = [BC_FIX, BC_TRANSLATE], [0b11, 0b10]
+    elif clamped:
+        flagsB = flagsB | np.where(_outer_layer(xB, spB), 2, 0)
+        bc_kind, bc_mask = [BC_FIX], [0b11]
     matS = (rS <= r_inc).astype(np.int32)
     m_ref = rho / (inv_dx_B ** 2 * ppc1d ** 2)
     F0S = None
@@ -208,10 +213,16 @@ def inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.05, E_matrix=1e4,
                        "ramp_frames": ramp_frames})
 
 
+def _outer_layer(x, sp):
+    """Particles within one particle spacing of the edges of [0.1, 0.9]^2."""
+    return (x[:, 0] < 0.1 + sp) | (x[:, 0] > 0.9 - sp) | (x[:, 1] < 0.1 + sp) | (x[:, 1] > 0.9 - sp)
+
+
 def inclusion_single(inv_dx=50, ppc1d=2, r_inc=0.05, E_matrix=1e4, E_inc=1e5, nu=0.3, rho=1000.0,
                      seed=0, dt=1e-3, n_frames=50, top_disp=0.01, ramp_frames=50, delta=0.0,
-                     loaded=True, tau_rel=1e-3):
-    """Single-domain reference of the inclusion: the whole square [0.1,0.9]^2 on one grid."""
+                     loaded=True, clamped=False, tau_rel=1e-3):
+    """Single-domain reference of the inclusion: the whole square [0.1,0.9]^2 on
+    one grid (loaded / clamped outer boundary as in inclusion_scene)."""
     lat = math.lcm(inv_dx, 10)
     h0 = 1.0 / lat
     dxq = lat // inv_dx
@@ -229,6 +240,9 @@ def inclusion_single(inv_dx=50, ppc1d=2, r_inc=0.05, E_matrix=1e4, E_inc=1e5, nu
     if loaded:
         flags = flags | np.where(x[:, 1] < 0.1 + sp, 2, 0) | np.where(x[:, 1] > 0.9 - sp, 4, 0)
         bc_kind, bc_mask = [BC_FIX, BC_TRANSLATE], [0b11, 0b10]
+    elif clamped:
+        flags = flags | np.where(_outer_layer(x, sp), 2, 0)
+        bc_kind, bc_mask = [BC_FIX], [0b11]
     F0 = None
     if delta:
         F0 = np.where((mat == 1)[:, None, None], (1.0 - delta) * np.eye(2), np.eye(2))
