@@ -665,8 +665,12 @@ void p2g_side(osmpm_batch *G, int s, bool want_qall) {
     if (G->act[s][i] == 1 && G->dom[s][i]->bc.n_groups > 0) want_q = 1;
   sort_side<D, TB>(G, s, want_q);
   const Ext &E = G->ext[s];
-  launch(c, OSMPM_K_P2G, active_bytes(G, s, OSMPM_K_P2G), -1, k_p2g<D, TB>, dim3(E.tile_blocks, G->n), dim3(kBlock),
-         E.lds_p2g, (const DomDesc *)G->dd[s], want_q, G->err);
+  if (want_q)
+    launch(c, OSMPM_K_P2G, active_bytes(G, s, OSMPM_K_P2G), -1, k_p2g<D, TB, true>, dim3(E.tile_blocks, G->n),
+           dim3(kBlock), E.lds_p2g, (const DomDesc *)G->dd[s], G->err);
+  else
+    launch(c, OSMPM_K_P2G, active_bytes(G, s, OSMPM_K_P2G), -1, k_p2g<D, TB, false>, dim3(E.tile_blocks, G->n),
+           dim3(kBlock), E.lds_p2g, (const DomDesc *)G->dd[s], G->err);
   launch(c, -1, 0, -1, k_p2g_final<D>, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
   for (int i = 0; i < G->n; ++i)
     if (G->act[s][i] == 1) G->dom[s][i]->have_p2g = true;

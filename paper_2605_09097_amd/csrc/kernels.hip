@@ -441,8 +441,12 @@ __device__ inline int region_slot(const TileGeom &tg, const int *l, const int *k
 // from the TB velocities and affine matrices.  Tile sums are accumulated in
 // FP64 LDS (ds_add_f64, which measures about twice as fast as ds_add_f32 on
 // gfx950) and added to the FP64 grid.
-template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, int *err) {
+// kQ (the launches that also select node sets) is a template parameter so
+// that the common launch carries no per-node branches; particles of scene
+// groups, which are few, add their group masses in a pass of their own.
+template <int D, typename TB, bool kQ>
+__global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
+  constexpr int want_q = kQ ? 1 : 0;
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active || (int)blockIdx.x >= dm.tg.nblocks) return;
   extern __shared__ double lds[];
@@ -509,12 +513,24 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int want_q, i
         for (int b = 0; b < D; ++b) aff += Bp[a * D + b] * dxv[b];
         atomicAdd(&lmv[a * nreg + r], (double)(mN * (vp[a] + Dinv_t * aff)));
       }
-      if (want_q) {
+      if constexpr (kQ) {
         const long long q = fixed_mass(N, mq);
         atomicAdd(reinterpret_cast<unsigned long long *>(&lq[r]), (unsigned long long)q);
-        for (int gi = 0; gi < n_groups; ++gi)
-          if (fl & (2u << gi))
-            atomicAdd(reinterpret_cast<unsigned long long *>(&lq[(1 + gi) * nreg + r]), (unsigned long long)q);
+      }
+    }
+    if constexpr (kQ) {
+      const unsigned gmask = (fl >> 1) & ((1u << n_groups) - 1u);
+      if (gmask) {
+#pragma unroll
+        for (int s = 0; s < stencil_count<D>(); ++s) {
+          int k[3];
+          stencil_offset<D>(s, k);
+          const long long q = fixed_mass(stencil_N<D>(st, k), mq);
+          const int r = region_slot<D>(tg, l, k);
+          for (int gi = 0; gi < n_groups; ++gi)
+            if (gmask & (1u << gi))
+              atomicAdd(reinterpret_cast<unsigned long long *>(&lq[(1 + gi) * nreg + r]), (unsigned long long)q);
+        }
       }
     }
   }
@@ -1852,7 +1868,8 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const DomDesc *dd, doubl
   template __global__ void k_gather_all<D, TB>(const DomDesc *);                                \
   template __global__ void k_bc_init<D, TB>(const DomDesc *, double, int, int);                      \
   template __global__ void k_copy_state<D, TB>(const DomDesc *, int);                           \
-  template __global__ void k_p2g<D, TB>(const DomDesc *, int, int *);                           \
+  template __global__ void k_p2g<D, TB, false>(const DomDesc *, int *);                         \
+  template __global__ void k_p2g<D, TB, true>(const DomDesc *, int *);                          \
   template __global__ void k_g2p<D, TB>(const DomDesc *, double, int *);                        \
   template __global__ void k_grad_hess<D, TB>(const DomDesc *, int, int *);                     \
   template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \

@@ -137,8 +137,8 @@ __global__ void k_copy_state(const DomDesc *dd, int to_store);
 __global__ void k_zero_grid(const DomDesc *dd, int want_q);
 
 // transfers
-template <int D, typename TB>
-__global__ void k_p2g(const DomDesc *dd, int want_q, int *err);
+template <int D, typename TB, bool kQ>
+__global__ void k_p2g(const DomDesc *dd, int *err);
 template <int D>
 __global__ void k_p2g_final(const DomDesc *dd);
 template <int D, typename TB>
