@@ -237,6 +237,83 @@ def adjoint_form(ctx, sc, prec, frames):
                     "reverse sweep (adjoint CG per solve)"}
 
 
+def adjoint_batch_form(n_scenes, frames, workers, prec):
+    """Reverse mode on the batched family: for every scene s, dL/dE (matrix
+    and inclusion Young's moduli) of L = 1/2 sum |x_p(T) - x_p^target|^2 over
+    the driven top-layer coarse particles after `frames` frames, where the
+    target is the same scene run forward with the inclusion modulus drawn
+    from seed 1000 + s.  Targets come from one batched forward run; the
+    gradients from one checkpointed run per scene (one checkpoint every 10
+    frames), `workers` scenes at a time, each on its own stream."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding, diff, scenes
+
+    solve = binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10)
+    tscs = [scenes.batch_scene(s, E_override=scenes.batch_target_E(s)) for s in range(n_scenes)]
+    opts = binding.schwarz_opts(tscs[0].M, eps_tol=tscs[0].eps_tol, coarse=solve, fine=solve)
+    ctx0 = binding.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sb = binding.SchwarzBatch(ctx0, tscs, precision=prec)
+    for _ in range(frames):
+        sb.frame(opts)
+    targets = []
+    for p, sc in zip(sb.pairs, tscs):
+        idx = np.nonzero(sc.B.flags & 4)[0]
+        targets.append((idx, p.B.particles_input_order()[0][idx]))
+    sb.close()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out = [None] * n_scenes
+    errors = []
+
+    def work(w):
+        try:
+            stream = torch.cuda.Stream()
+            ctx = binding.Context(0, stream=stream)
+            with torch.cuda.stream(stream):
+                for s in range(w, n_scenes, workers):
+                    sc = scenes.batch_scene(s)
+                    run = diff.SchwarzRun(ctx, sc, prec, checkpoint_every=10)
+                    xB, _ = run.forward(frames)
+                    idx, tgt = targets[s]
+                    ti = torch.as_tensor(idx, device=xB.device)
+                    diffx = xB[ti] - torch.as_tensor(tgt, device=xB.device)
+                    adj = torch.zeros_like(xB)
+                    adj[ti] = diffx
+                    dE, _, _ = run.backward({"x": adj})
+                    out[s] = {"scene": s, "loss": 0.5 * float((diffx * diffx).sum()), "dL_dE": [float(g) for g in dE],
+                              "E_inclusion": float(sc.S.E[1]), "E_target": scenes.batch_target_E(s)}
+                    run.close()
+                    print("reverse mode: scene %d done" % s, file=sys.stderr, flush=True)
+            stream.synchronize()
+            ctx.close()
+        except Exception as e:  # reported after the join
+            errors.append(repr(e))
+
+    th = [threading.Thread(target=work, args=(w,)) for w in range(workers)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx0.close()
+    if errors:
+        raise RuntimeError("batched reverse mode: " + "; ".join(errors))
+    agree = sum(1 for o in out if (o["dL_dE"][1] > 0) == (o["E_inclusion"] > o["E_target"]))
+    return {"scenes": n_scenes, "frames": frames, "checkpoint_every": 10, "workers": workers,
+            "targets_forward_s": t1 - t0, "gradients_s": t2 - t1,
+            "particle_steps_per_s_forward_and_reverse": n_scenes and
+            sum(_frame_particle_steps(scenes.batch_scene(s)) for s in range(n_scenes)) * frames / (t2 - t1),
+            "sign_agrees_with_E_minus_E_target": agree,
+            "per_scene": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +329,10 @@ def main():
                     help="scenes of the batched form (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5, help="timed frames of the batched form")
     ap.add_argument("--adjoint-frames", type=int, default=100, help="frames of the reverse-mode run (0 skips it)")
+    ap.add_argument("--adjoint-batch-scenes", type=int, default=64,
+                    help="scenes of the batched reverse-mode run (0 skips it)")
+    ap.add_argument("--adjoint-batch-frames", type=int, default=100)
+    ap.add_argument("--adjoint-batch-workers", type=int, default=8, help="scenes in flight, one stream each")
     ap.add_argument("--eshelby", default="",
                     help="only run the inclusion efficiency study (single-domain fine vs OS-MPM to equilibrium) "
                          "for ratio:inv_dx items, comma separated (e.g. 2:400,2:800), and exit")
@@ -368,6 +449,10 @@ def main():
     batched = None
     if args.batch_scenes > 0:
         batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve)
+    adjoint_batch = None
+    if args.adjoint_batch_scenes > 0:
+        adjoint_batch = adjoint_batch_form(args.adjoint_batch_scenes, args.adjoint_batch_frames,
+                                           args.adjoint_batch_workers, prec)
     large = []
     for item in filter(None, args.large.split(",")):
         wl, nf = item.split(":")
@@ -420,6 +505,7 @@ def main():
         "batched": batched,
         "large": large,
         "adjoint": adjoint,
+        "adjoint_batched": adjoint_batch,
     }
     print(json.dumps(out))
     ctx.close()

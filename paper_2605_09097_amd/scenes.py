@@ -487,6 +487,13 @@ def batch_scene(s: int, E_override: Optional[float] = None) -> Scene:
     return sc
 
 
+def batch_target_E(s: int) -> float:
+    """Inclusion Young's modulus of the target run of batched scene s: drawn
+    log-uniform in [2e4, 2e5] like the scene's own, from seed 1000 + s."""
+    u = uniform01(stream_seed(1000 + s, 99), np.arange(4, dtype=np.uint64))
+    return math.exp(math.log(2e4) + (math.log(2e5) - math.log(2e4)) * u[1])
+
+
 def top_edge_target(sc: Scene, n_frames: int, seed: int = 0):
     """Seeded target of the top-edge displacement loss of an inclusion scene:
     the coarse particles of the driven top layer (scene group 1) and target
