@@ -919,6 +919,17 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
 #pragma unroll
       for (int k = 0; k < ns; ++k) Atil[k * cap + p] = At[k];
     }
+    // In 3D, recompute the weight gradients for the diagonal rather than keep
+    // the gradient scatter's 27 x 3 of them live across the tangent work.
+    if constexpr (D == 3) {
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          asm volatile("" : "+v"(st.w[a][c]));
+          asm volatile("" : "+v"(st.dw[a][c]));
+        }
+    }
 #pragma unroll
     for (int s = 0; s < stencil_count<D>(); ++s) {
       int k[3];
@@ -1358,6 +1369,17 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
         qp += G[rr2] * tv;
       }
       dsum += (double)qp;
+      // Recompute the weight gradients below instead of keeping all 3^d of
+      // them live from the gather: an empty register barrier on the weights.
+      if constexpr (D == 3) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            asm volatile("" : "+v"(st.w[a][c]));
+            asm volatile("" : "+v"(st.dw[a][c]));
+          }
+      }
 #pragma unroll
       for (int s = 0; s < stencil_count<D>(); ++s) {
         int k[3];
