@@ -145,6 +145,15 @@ osmpm_status osmpm_ctx_set_stream(osmpm_ctx *ctx, void *stream);
  * a graph does not remove).  Kernel timing (osmpm_profile_enable) always uses
  * individual launches. */
 osmpm_status osmpm_ctx_set_graphs(osmpm_ctx *ctx, int32_t enable);
+/* How the CG scalars (stop test, step length, direction weight; Sec. 2.2.5's
+ * linear solve) are formed.  mode 0: inside every CG launch, each workgroup
+ * summing all workgroups' partial sums of the previous launch; mode 1: by an
+ * extra one-workgroup-per-domain launch after each CG launch; mode -1
+ * (default): mode 1 when the partial sums every workgroup would read exceed
+ * 128 MB per launch (24 B x workgroups^2, summed over the batch side), else
+ * mode 0.  Both sum in the same order, so results are identical.  Any
+ * other value: OSMPM_E_INVALID_ARG. */
+osmpm_status osmpm_ctx_set_cg_split(osmpm_ctx *ctx, int32_t mode);
 /* Waits for all queued work and reports device-side errors. */
 osmpm_status osmpm_sync(osmpm_ctx *ctx);
 const char *osmpm_last_error(const osmpm_ctx *ctx);

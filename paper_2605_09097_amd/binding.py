@@ -23,7 +23,7 @@ OSMPM_K_CG_ITER, OSMPM_K_P2G, OSMPM_K_G2P, OSMPM_K_GRAD_HESS = 0, 1, 2, 3
 
 # Every symbol the header declares (checked by the CPU test suite).
 ABI_SYMBOLS = [
-    "osmpm_ctx_create", "osmpm_ctx_set_stream", "osmpm_ctx_set_graphs", "osmpm_sync", "osmpm_last_error", "osmpm_ctx_destroy",
+    "osmpm_ctx_create", "osmpm_ctx_set_stream", "osmpm_ctx_set_graphs", "osmpm_ctx_set_cg_split", "osmpm_sync", "osmpm_last_error", "osmpm_ctx_destroy",
     "osmpm_profile_enable", "osmpm_profile_query",
     "osmpm_domain_create", "osmpm_domain_destroy", "osmpm_domain_set_materials",
     "osmpm_domain_set_particles", "osmpm_domain_set_selection", "osmpm_domain_set_scene_bc",
@@ -80,6 +80,7 @@ def _declare(L):
         "osmpm_ctx_create": [C.c_int32, _vp, P(_vp)],
         "osmpm_ctx_set_stream": [_vp, _vp],
         "osmpm_ctx_set_graphs": [_vp, C.c_int32],
+        "osmpm_ctx_set_cg_split": [_vp, C.c_int32],
         "osmpm_sync": [_vp],
         "osmpm_profile_enable": [_vp, C.c_int32],
         "osmpm_profile_query": [_vp, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)],
@@ -192,6 +193,11 @@ class Context:
 
     def graphs(self, enable):
         self.check(lib().osmpm_ctx_set_graphs(self.handle, int(enable)), "set_graphs")
+
+    def cg_split(self, mode):
+        """CG scalars inside each CG launch (0), by a launch of their own (1),
+        or chosen by size (-1, the default)."""
+        self.check(lib().osmpm_ctx_set_cg_split(self.handle, int(mode)), "set_cg_split")
 
     def profile(self, enable):
         self.check(lib().osmpm_profile_enable(self.handle, int(enable)), "profile_enable")

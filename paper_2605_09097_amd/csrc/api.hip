@@ -88,6 +88,7 @@ struct osmpm_ctx {
   std::vector<osmpm_batch *> groups;  // every live group (error words)
   uint64_t next_uid = 1;
   bool graphs = false;            // replay solve cycles as HIP graphs
+  int cg_split = -1;              // CG scalars: 0 fused, 1 separate launch, -1 by size
   GraphBuild *rec = nullptr;      // graph being built (launches become nodes)
 };
 
@@ -725,6 +726,14 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd);
   };
   grad_phase();
+  // Split CG scalars (k_cg_reduce after each iteration) when the fused form's
+  // pass of every workgroup over all partial sums would read more than a
+  // dependent launch costs (measured: the 3D fold gains, a 64-scene 2D batch
+  // at ~60 MB does not): sum over domains of 24 B x workgroups^2.
+  double partial_reads = 0.0;
+  for (int i = 0; i < n; ++i)
+    if (G->act[s][i] == 1) partial_reads += 24.0 * (double)G->dom[s][i]->tg.nblocks * G->dom[s][i]->tg.nblocks;
+  const int split = c->cg_split >= 0 ? c->cg_split : (partial_reads > 128e6 ? 1 : 0);
   std::vector<int> hint(n), prev_phase(n, kPhaseCgInit), prev_iter(n, 0), prev_total(n, 0);
   for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
   const long max_cycles = (long)(o->max_newton + 1) * ((o->max_cg + 4) / 4 + o->max_ls + 3) + 8;
@@ -752,9 +761,11 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
         sb = prof_event(c);
         if (sa && sb && hipEventRecord(sa, c->stream) != hipSuccess) sa = nullptr;
       }
-      for (int j = 0; j < b; ++j)
+      for (int j = 0; j < b; ++j) {
         launch(c, sa ? -1 : OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd,
-               j & 1, dt, o->cg_rtol, (int)o->max_cg);
+               j & 1, dt, o->cg_rtol, (int)o->max_cg, split);
+        if (split) launch(c, -1, 0, -1, k_cg_reduce, dim3(1, n), blk, 0, dd, j & 1, o->cg_rtol, (int)o->max_cg);
+      }
       if (sa && sb && hipEventRecord(sb, c->stream) == hipSuccess)
         c->pending.push_back({sa, sb, OSMPM_K_CG_ITER, 0.0, kCgSpan});
       launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
@@ -1274,7 +1285,7 @@ osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const 
   for (int launched = 0;; launched += chunk) {
     for (int j = 0; j < chunk; ++j)
       launch(c, -1, 0, -1, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt, adj_rtol,
-             max_cg);
+             max_cg, 0);
     if ((st = read_status(G))) return st;
     if (h_cg(G, s)[0].done) break;
     if (launched > max_cg + chunk) return fail(c, OSMPM_E_STATE, "adjoint CG did not terminate");
@@ -1584,6 +1595,12 @@ osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out) {
 osmpm_status osmpm_ctx_set_graphs(osmpm_ctx *ctx, int32_t enable) {
   if (!ctx) return OSMPM_E_INVALID_ARG;
   ctx->graphs = enable != 0;
+  return OSMPM_OK;
+}
+
+osmpm_status osmpm_ctx_set_cg_split(osmpm_ctx *ctx, int32_t mode) {
+  if (!ctx || mode < -1 || mode > 1) return OSMPM_E_INVALID_ARG;
+  ctx->cg_split = mode;
   return OSMPM_OK;
 }
 

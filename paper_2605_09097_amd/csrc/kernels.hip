@@ -1117,6 +1117,40 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd) {
   }
 }
 
+// Scalars of CG launch i from the partial sums (sg, sd, sr) of launch i - 1:
+// the stop test on |r_(i-1)| <= rtol |r_0| (or i - 1 = max_cg), beta_(i-1)
+// and alpha_(i-1); with write set, the state the next decision needs.
+struct CgStep {
+  double alpha, beta;
+  bool done;
+};
+__device__ inline CgStep cg_scalars(CgState *S, int i, double sg, double sd, double sr, double rtol, int max_cg,
+                                    bool write) {
+  CgStep r{0.0, 0.0, false};
+  const double rr0 = (i == 1) ? sr : S->rr0;
+  if (i - 1 >= max_cg) {
+    r.done = true;
+  } else if (i == 1) {
+    r.done = !(rr0 > 0.0);
+  } else {
+    r.done = sqrt(sr) <= rtol * sqrt(rr0);
+  }
+  if (!r.done) {
+    r.beta = (i == 1) ? 0.0 : sg / S->gam[i & 1];
+    const double den = (i == 1) ? sd : sd - r.beta * sg / S->alp[i & 1];
+    if (den > 0.0)
+      r.alpha = sg / den;
+    else
+      r.done = true;
+  }
+  if (write) {
+    if (i == 1) S->rr0 = rr0;
+    S->gam[(i + 1) & 1] = sg;
+    S->alp[(i + 1) & 1] = r.alpha;
+  }
+  return r;
+}
+
 // CG iteration i of a domain (i read from the device state at parity q, so
 // launches alternate q = 0, 1 and a chunk of them can be replayed with fixed
 // arguments).  For i >= 1 every workgroup sums the partials of launch i - 1
@@ -1129,8 +1163,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd) {
 // (w_i, u_i), and (r_i, u_i), (r_i, r_i).  i = 0 forms
 // u_0 = D^-1 r_0 and w_0 only.  Loads that do not depend on the scalars are
 // issued before the reduction.
+// split = 1: the scalars are not derived here but read from the state, where
+// k_cg_reduce put them after the previous launch (same sums in the same
+// order, so both forms give identical results); for launches of many
+// workgroups this replaces every workgroup's pass over all partial sums.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg) {
+__global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg,
+                                                    int split) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
@@ -1165,7 +1204,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   const int nreg = tg.nreg;
   // --- independent loads
   double sg = 0.0, sd = 0.0, sr = 0.0;
-  if (i > 0)
+  if (i > 0 && !split)
     for (int j = tid; j < nbt; j += kBlock) {
       sg += pin[j];
       sd += pin[dm.pstride + j];
@@ -1223,40 +1262,30 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   // --- scalars of iteration i - 1
   double alpha = 0.0, beta = 0.0;
   bool done = false;
-  if (i > 0) {
-    block_sum3(sg, sd, sr, red);
-    const double rr0 = (i == 1) ? sr : S->rr0;
-    if (i - 1 >= max_cg) {
-      done = true;
-    } else if (i == 1) {
-      done = !(rr0 > 0.0);
-    } else {
-      done = sqrt(sr) <= rtol * sqrt(rr0);
+  if (split) {
+    if (i > 0) {
+      alpha = S->alpha_n;
+      beta = S->beta_n;
     }
-    if (!done) {
-      beta = (i == 1) ? 0.0 : sg / S->gam[i & 1];
-      const double den = (i == 1) ? sd : sd - beta * sg / S->alp[i & 1];
-      if (den > 0.0)
-        alpha = sg / den;
-      else
-        done = true;
+  } else {
+    if (i > 0) {
+      block_sum3(sg, sd, sr, red);
+      const CgStep st = cg_scalars(S, i, sg, sd, sr, rtol, max_cg, blockIdx.x == 0 && tid == 0);
+      alpha = st.alpha;
+      beta = st.beta;
+      done = st.done;
     }
     if (blockIdx.x == 0 && tid == 0) {
-      if (i == 1) S->rr0 = rr0;
-      S->gam[(i + 1) & 1] = sg;
-      S->alp[(i + 1) & 1] = alpha;
+      if (done) {
+        S->done = 1;
+        S->iter = i - 1;
+      } else {
+        S->iter = i;
+        S->k_at[q ^ 1] = i + 1;
+      }
     }
+    if (done) return;
   }
-  if (blockIdx.x == 0 && tid == 0) {
-    if (done) {
-      S->done = 1;
-      S->iter = i - 1;
-    } else {
-      S->iter = i;
-      S->k_at[q ^ 1] = i + 1;
-    }
-  }
-  if (done) return;
   const double mdt = 1.0 / (dt * dt);
   double gsum = 0.0, dsum = 0.0, rsum = 0.0;
   // --- owned DOFs
@@ -1412,6 +1441,41 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
     pout[blockIdx.x] = gsum;
     pout[dm.pstride + blockIdx.x] = dsum;
     pout[2 * dm.pstride + blockIdx.x] = rsum;
+  }
+}
+
+// Split mode: after CG launch i of parity q, one workgroup per domain adds
+// that launch's partial sums (in the order the fused form uses) and derives
+// the stop test, beta_i and alpha_i for launch i + 1.
+__global__ void __launch_bounds__(kBlock) k_cg_reduce(const DomDesc *dd, int q, double rtol, int max_cg) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  CgState *S = dm.cg;
+  if (S->done) return;
+  __shared__ double red[12];
+  const int tid = threadIdx.x;
+  const int i = S->k_at[q];
+  const int nbt = dm.tg.nblocks;
+  const double *pin = dm.part_cg + (size_t)q * 3 * dm.pstride;
+  double sg = 0.0, sd = 0.0, sr = 0.0;
+  for (int j = tid; j < nbt; j += kBlock) {
+    sg += pin[j];
+    sd += pin[dm.pstride + j];
+    sr += pin[2 * dm.pstride + j];
+  }
+  block_sum3(sg, sd, sr, red);
+  if (tid == 0) {
+    const int n = i + 1;
+    const CgStep st = cg_scalars(S, n, sg, sd, sr, rtol, max_cg, true);
+    S->alpha_n = st.alpha;
+    S->beta_n = st.beta;
+    if (st.done) {
+      S->done = 1;
+      S->iter = n - 1;
+    } else {
+      S->iter = n;
+      S->k_at[q ^ 1] = n;
+    }
   }
 }
 
@@ -1896,7 +1960,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const DomDesc *dd, doubl
   template __global__ void k_grad_hess<D, TB>(const DomDesc *, int, int *);                     \
   template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \
   template __global__ void k_cg_init<D, TB>(const DomDesc *);                                   \
-  template __global__ void k_cg_iter<D, TB>(const DomDesc *, int, double, double, int);         \
+  template __global__ void k_cg_iter<D, TB>(const DomDesc *, int, double, double, int, int);    \
   template __global__ void k_delta_energy<D, TB>(const DomDesc *, double, double, double, double);
 
 OSMPM_INST_D(2)

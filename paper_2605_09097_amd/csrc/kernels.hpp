@@ -21,6 +21,8 @@ struct CgState {
   double gam[2];  // (r, u) of earlier iterations, by parity
   double alp[2];  // step lengths of earlier iterations, by parity
   double rr0;     // |r_0|^2
+  double alpha_n; // split mode: step length and direction weight of the next launch
+  double beta_n;
   double pad;
   int iter;       // directions applied so far
   int done;       // converged, broke down, hit max_cg, or not solving
@@ -156,7 +158,8 @@ __global__ void k_newton_check(const DomDesc *dd, double rtol, double atol, int 
 template <int D, typename TB>
 __global__ void k_cg_init(const DomDesc *dd);
 template <int D, typename TB>
-__global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg);
+__global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg, int split);
+__global__ void k_cg_reduce(const DomDesc *dd, int q, double rtol, int max_cg);
 template <int D, typename TB>
 __global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz);
 __global__ void k_ls_check(const DomDesc *dd, int max_ls);

@@ -217,3 +217,30 @@ def test_autotune_picks_a_measured_candidate(ctx):
     t, tim2 = autotune.tune_batch(ctx, [sc, scenes.inclusion_scene(20, 40, seed=3, delta=0.01)], opts,
                                   candidates=cands)
     assert t in cands and set(tim2) == set(cands)
+
+
+def test_cg_split_scalars_match_fused(ctx):
+    """The CG scalars formed by a launch of their own (split mode, used for
+    launches of many workgroups) give the results of the fused form: same
+    Schwarz, Newton and CG counts, state equal to rounding."""
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("inclusion_tiny")
+    opts = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    runs = {}
+    for mode in (1, 0):
+        ctx.cg_split(mode)
+        pair = b.SchwarzPair(ctx, sc)
+        out = []
+        for _ in range(2):
+            st = pair.frame(opts)
+            out.append(((st.iters, st.newton_B, st.newton_S, st.cg_B, st.cg_S),
+                        pair.B.grid_state()[2].cpu().numpy().copy(), pair.S.grid_state()[2].cpu().numpy().copy()))
+        pair.close()
+        runs[mode] = out
+    ctx.cg_split(-1)
+    for fs, ff in zip(runs[1], runs[0]):
+        assert fs[0] == ff[0]
+        for a, e in zip(fs[1:], ff[1:]):
+            assert rel_err(a, e) < 1e-12
