@@ -130,6 +130,9 @@ def _declare(L):
     L.or_single_frame_adjoint.argtypes = [dom, C.c_double, C.POINTER(SolveOpts), C.c_double] + [_dp] * 10
     L.or_schwarz_frame_adjoint.argtypes = ([dom, dom, C.c_double, C.POINTER(SchwarzOpts), C.c_int, C.c_double]
                                            + [_dp] * 20)
+    L.or_schwarz_frame_adjoint_implicit.argtypes = ([dom, dom, C.c_double, C.POINTER(SchwarzOpts), C.c_int,
+                                                     C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int)]
+                                                    + [_dp] * 20)
 
 
 def _ptr(a, t):
@@ -439,6 +442,27 @@ def schwarz_frame_adjoint(Bd: Domain, Sd: Domain, dT, opts, iters, adjB_end, adj
         *[_ptr(oB[k], _dp) for k in "xvBF"], *[_ptr(oS[k], _dp) for k in "xvBF"],
         _ptr(mubB, _dp), _ptr(labB, _dp), _ptr(mubS, _dp), _ptr(labS, _dp)), "or_schwarz_frame_adjoint")
     return oB, oS, mubB, labB, mubS, labS
+
+
+def schwarz_frame_adjoint_implicit(Bd: Domain, Sd: Domain, dT, opts, iters, adjB_end, adjS_end, fp_tol=1e-10,
+                                   fp_max=200, adj_cg_rtol=1e-13):
+    """Implicit (fixed-point) adjoint of one Schwarz frame: the Neumann series
+    of the adjoint iteration at the last forward iterate, with no term from
+    the first iterate's data (or_schwarz_frame_adjoint_implicit).  Returns the
+    tuple of schwarz_frame_adjoint plus the number of adjoint passes."""
+    aB = _adj_arrays(Bd, adjB_end)
+    aS = _adj_arrays(Sd, adjS_end)
+    oB = {k: np.zeros_like(v) for k, v in aB.items()}
+    oS = {k: np.zeros_like(v) for k, v in aS.items()}
+    mubB, labB = np.zeros_like(Bd.mu), np.zeros_like(Bd.lam)
+    mubS, labS = np.zeros_like(Sd.mu), np.zeros_like(Sd.lam)
+    used = C.c_int(0)
+    _check(lib().or_schwarz_frame_adjoint_implicit(
+        Bd.ref, Sd.ref, dT, C.byref(opts), int(iters), adj_cg_rtol, float(fp_tol), int(fp_max), C.byref(used),
+        *[_ptr(aB[k], _dp) for k in "xvBF"], *[_ptr(aS[k], _dp) for k in "xvBF"],
+        *[_ptr(oB[k], _dp) for k in "xvBF"], *[_ptr(oS[k], _dp) for k in "xvBF"],
+        _ptr(mubB, _dp), _ptr(labB, _dp), _ptr(mubS, _dp), _ptr(labS, _dp)), "or_schwarz_frame_adjoint_implicit")
+    return oB, oS, mubB, labB, mubS, labS, used.value
 
 
 def schwarz_run(scene, E, n_frames, opts):

@@ -30,6 +30,7 @@
 #define OR_E_NOMEM 2
 #define OR_E_OUT_OF_GRID 4
 #define OR_E_INVERTED 5
+#define OR_E_NOT_CONVERGED 6
 
 #define BC_FIX 0
 #define BC_TRANSLATE 1
@@ -1896,17 +1897,22 @@ done:
  * coarse solve k with its projected data; finally the projection of Step 0
  * and the two Step-0 P2Gs.  Inputs xb*, vb*, Bb*, Fb*: adjoint of the
  * end-of-frame particle states; outputs o* (overwritten): adjoint of the
- * start-of-frame states; mubar*, lambar* accumulate per material. */
-int or_schwarz_frame_adjoint(or_domain *B, or_domain *S, double dT, const or_schwarz_opts *o, int iters,
-                             double adj_cg_rtol, const double *xbB, const double *vbB, const double *BbB,
-                             const double *FbB, const double *xbS, const double *vbS, const double *BbS,
-                             const double *FbS, double *oxB, double *ovB, double *oBB, double *oFB,
-                             double *oxS, double *ovS, double *oBS, double *oFS, double *mubarB,
-                             double *lambarB, double *mubarS, double *lambarS) {
+ * start-of-frame states; mubar*, lambar* accumulate per material.  With
+ * `implicit` set the loop over iterations becomes the fixed-point adjoint of
+ * or_schwarz_frame_adjoint_implicit (every pass on the last iteration's
+ * intermediates, no Step-0 projection). */
+static int schwarz_adjoint(or_domain *B, or_domain *S, double dT, const or_schwarz_opts *o, int iters,
+                           double adj_cg_rtol, int implicit, double fp_tol, int fp_max, int *fp_used,
+                           const double *xbB, const double *vbB, const double *BbB, const double *FbB,
+                           const double *xbS, const double *vbS, const double *BbS, const double *FbS,
+                           double *oxB, double *ovB, double *oBB, double *oFB, double *oxS, double *ovS,
+                           double *oBS, double *oFS, double *mubarB, double *lambarB, double *mubarS,
+                           double *lambarS) {
   const int d = B->dim, nnB = nnodes(B), nnS = nnodes(S), npB = B->np, npS = S->np, M = o->M;
   const double dt = dT / (double)M;
   const int K = iters;
   if (K < 1 || M < 1) return OR_E_ARG;
+  if (implicit && fp_max < 1) return OR_E_ARG;
   int rc = OR_OK;
   fwd_point fB = {0};
   fwd_point *fS = (fwd_point *)calloc((size_t)K * (M + 1), sizeof(fwd_point));
@@ -2007,11 +2013,15 @@ int or_schwarz_frame_adjoint(or_domain *B, or_domain *S, double dT, const or_sch
     VB.use_schwarz_bc = 1;
     /* coarse G2P */
     if ((rc = g2p_adjoint(&VB, dT, xbB, vbB, BbB, FbB, ubarB, aB.x, aB.F))) goto done;
-    for (int k = K - 1; k >= 0; --k) {
+    double w_norm = 0.0;
+    for (int j = 0;; ++j) {
+      /* unrolled: iteration k = K-1-j; implicit: always the last iterate */
+      const int k = implicit ? K - 1 : K - 1 - j;
+      if (k < 0) break;
       memset(ubarBk, 0, sizeof(double) * nnB * d);
-      if (k == K - 1) memcpy(ubarBk, ubarB, sizeof(double) * nnB * d);
+      if (j == 0) memcpy(ubarBk, ubarB, sizeof(double) * nnB * d);
       /* adjoint of the fine state after the last sub-step of iteration k */
-      if (k == K - 1) {
+      if (j == 0) {
         memcpy(aS.x, xbS, sizeof(double) * npS * d);
         memcpy(aS.v, vbS, sizeof(double) * npS * d);
         memcpy(aS.B, BbS, sizeof(double) * npS * d * d);
@@ -2074,9 +2084,25 @@ int or_schwarz_frame_adjoint(or_domain *B, or_domain *S, double dT, const or_sch
                               lambarB, pibar)))
         goto done;
       memcpy(pibar_next, pibar, sizeof(double) * nnB * d);
+      if (implicit) {
+        /* pibar is now (Phi_z^T)^j w, w = pibar of j = 0 */
+        double nrm = 0.0;
+        for (int q = 0; q < nnB * d; ++q) nrm += pibar[q] * pibar[q];
+        nrm = sqrt(nrm);
+        if (j == 0) w_norm = nrm;
+        *fp_used = j;
+        if (fp_tol > 0.0 && nrm <= fp_tol * w_norm) break;
+        if (j == fp_max) {
+          if (fp_tol > 0.0) rc = OR_E_NOT_CONVERGED;
+          break;
+        }
+      }
     }
-    /* Step 0: projection of the fine start grid, then both P2Gs */
-    {
+    if (rc) goto done;
+    /* Step 0: projection of the fine start grid (the first iterate's
+     * Dirichlet data; the fixed point does not depend on it), then both
+     * P2Gs */
+    if (!implicit) {
       or_domain V0 = fwd_view(S, &fS[0]);
       memset(mbarS, 0, sizeof(double) * nnS);
       memset(vnbarS, 0, sizeof(double) * nnS * d);
@@ -2126,4 +2152,43 @@ done:
   free(gSn);
   free(gSn1);
   return rc;
+}
+
+int or_schwarz_frame_adjoint(or_domain *B, or_domain *S, double dT, const or_schwarz_opts *o, int iters,
+                             double adj_cg_rtol, const double *xbB, const double *vbB, const double *BbB,
+                             const double *FbB, const double *xbS, const double *vbS, const double *BbS,
+                             const double *FbS, double *oxB, double *ovB, double *oBB, double *oFB,
+                             double *oxS, double *ovS, double *oBS, double *oFS, double *mubarB,
+                             double *lambarB, double *mubarS, double *lambarS) {
+  int unused = 0;
+  return schwarz_adjoint(B, S, dT, o, iters, adj_cg_rtol, 0, 0.0, 0, &unused, xbB, vbB, BbB, FbB, xbS, vbS,
+                         BbS, FbS, oxB, ovB, oBB, oFB, oxS, ovS, oBS, oFS, mubarB, lambarB, mubarS, lambarS);
+}
+
+/* Implicit (fixed-point) adjoint of the Schwarz iteration.  Alg. 1 iterates
+ * z -> Phi(z; theta), z the projected Dirichlet data of the coarse solve and
+ * theta the start-of-frame states and materials; the outputs are psi(z; theta)
+ * (the coarse solve with data z, its G2P, and the fine sub-steps driven by
+ * it).  At the fixed point z* = Phi(z*), dL/dtheta = psi_theta^T obar +
+ * Phi_theta^T mu with (I - Phi_z^T) mu = psi_z^T obar, which the Neumann
+ * series mu = sum_j (Phi_z^T)^j w solves at the contraction rate of the
+ * forward iteration (Sec. 2.3: for a coercive problem the Schwarz iteration
+ * contracts geometrically, Phi_z^T with it).  Every term is linearised at the last forward
+ * iterate, so only that iteration's intermediates are needed, and the first
+ * iterate's data (the Step-0 projection) drops out.  The frame is recomputed
+ * with `iters` Schwarz iterations.  fp_tol > 0: stop once the 2-norm of
+ * (Phi_z^T)^j w falls to fp_tol times that of w, at most fp_max applications
+ * of Phi_z^T (else OR_E_NOT_CONVERGED); fp_tol <= 0: exactly fp_max.  fp_used
+ * receives the number of applications. */
+int or_schwarz_frame_adjoint_implicit(or_domain *B, or_domain *S, double dT, const or_schwarz_opts *o,
+                                      int iters, double adj_cg_rtol, double fp_tol, int fp_max, int *fp_used,
+                                      const double *xbB, const double *vbB, const double *BbB,
+                                      const double *FbB, const double *xbS, const double *vbS,
+                                      const double *BbS, const double *FbS, double *oxB, double *ovB,
+                                      double *oBB, double *oFB, double *oxS, double *ovS, double *oBS,
+                                      double *oFS, double *mubarB, double *lambarB, double *mubarS,
+                                      double *lambarS) {
+  return schwarz_adjoint(B, S, dT, o, iters, adj_cg_rtol, 1, fp_tol, fp_max, fp_used, xbB, vbB, BbB, FbB, xbS,
+                         vbS, BbS, FbS, oxB, ovB, oBB, oFB, oxS, ovS, oBS, oFS, mubarB, lambarB, mubarS,
+                         lambarS);
 }
