@@ -49,6 +49,7 @@ typedef enum {
   OSMPM_E_DEVICE = 3,      /* HIP runtime error */
   OSMPM_E_OUT_OF_GRID = 4, /* a particle's 3^d stencil left its grid */
   OSMPM_E_INVERTED = 5,    /* det F <= 0 at an iterate that had to be evaluated */
+  OSMPM_E_NOT_CONVERGED = 6, /* an iteration with a required tolerance ran out of passes */
   OSMPM_E_STATE = 7        /* call out of order (e.g. solve before P2G) */
 } osmpm_status;
 
@@ -340,6 +341,32 @@ osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, doubl
                                          double *xbar_S_out, double *vbar_S_out, double *Bbar_S_out,
                                          double *Fbar_S_out, double *mubar_B_host, double *lambar_B_host,
                                          double *mubar_S_host, double *lambar_S_host);
+
+/* Implicit (fixed-point) adjoint of the same frame.  Alg. 1 iterates
+ * z -> Phi(z), z the projected Dirichlet data of the coarse solve (Eq.
+ * spatial_projection), and the Schwarz iteration contracts for coercive
+ * problems (Sec. 2.3); at its fixed point z* the derivative of the
+ * end-of-frame states is that of psi(z*) (the coarse solve with data z*, its
+ * G2P and the fine sub-steps it drives) plus Phi's own inputs weighted by
+ * mu = sum_j (Phi_z^T)^j w, w = psi_z^T times the output adjoint.  The series
+ * is summed pass by pass, each pass one reverse Schwarz iteration (Steps 1
+ * and 2 transposed), all linearised at the forward's last iterate: only that
+ * iteration's intermediates are stored (the unrolled call stores all
+ * `iters`), and the first iterate's data (the Step-0 projection) carries no
+ * derivative.  The frame is recomputed with exactly `iters` iterations.
+ * fp_tol > 0: stop once the 2-norm of (Phi_z^T)^j w (all coarse node
+ * components) is at most fp_tol times that of w, or return
+ * OSMPM_E_NOT_CONVERGED after fp_max passes; fp_tol <= 0: exactly fp_max
+ * passes.  fp_max >= 1.  *fp_used_host (may be NULL) receives the number of
+ * passes j.  Arrays, accumulation and end state as osmpm_schwarz_frame_adjoint. */
+osmpm_status osmpm_schwarz_frame_adjoint_implicit(
+    osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *opts, int32_t iters,
+    double adj_cg_rtol, double fp_tol, int32_t fp_max, int32_t *fp_used_host, const double *xbar_B,
+    const double *vbar_B, const double *Bbar_B, const double *Fbar_B, const double *xbar_S,
+    const double *vbar_S, const double *Bbar_S, const double *Fbar_S, double *xbar_B_out, double *vbar_B_out,
+    double *Bbar_B_out, double *Fbar_B_out, double *xbar_S_out, double *vbar_S_out, double *Bbar_S_out,
+    double *Fbar_S_out, double *mubar_B_host, double *lambar_B_host, double *mubar_S_host,
+    double *lambar_S_host);
 
 /* ---------------------------------------------------------------- readback */
 

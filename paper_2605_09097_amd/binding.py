@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libosmpm.so")
 
 OSMPM_OK, OSMPM_E_INVALID_ARG, OSMPM_E_NO_MEMORY, OSMPM_E_DEVICE = 0, 1, 2, 3
-OSMPM_E_OUT_OF_GRID, OSMPM_E_INVERTED, OSMPM_E_STATE = 4, 5, 7
+OSMPM_E_OUT_OF_GRID, OSMPM_E_INVERTED, OSMPM_E_NOT_CONVERGED, OSMPM_E_STATE = 4, 5, 6, 7
 OSMPM_FP64, OSMPM_MIXED = 0, 1
 OSMPM_K_CG_ITER, OSMPM_K_P2G, OSMPM_K_G2P, OSMPM_K_GRAD_HESS = 0, 1, 2, 3
 
@@ -32,7 +32,7 @@ ABI_SYMBOLS = [
     "osmpm_schwarz_frame", "osmpm_single_frame", "osmpm_get_particles", "osmpm_get_grid",
     "osmpm_get_sets", "osmpm_get_sort", "osmpm_domain_info",
     "osmpm_batch_create", "osmpm_batch_schwarz_frame", "osmpm_batch_single_frame", "osmpm_batch_destroy",
-    "osmpm_single_frame_adjoint", "osmpm_schwarz_frame_adjoint",
+    "osmpm_single_frame_adjoint", "osmpm_schwarz_frame_adjoint", "osmpm_schwarz_frame_adjoint_implicit",
 ]
 
 
@@ -111,6 +111,9 @@ def _declare(L):
                                       + [P(C.c_double)] * 2,
         "osmpm_schwarz_frame_adjoint": [_vp, _vp, C.c_double, P(osmpm_schwarz_opts), C.c_int32, C.c_double]
                                        + [_vp] * 16 + [P(C.c_double)] * 4,
+        "osmpm_schwarz_frame_adjoint_implicit": [_vp, _vp, C.c_double, P(osmpm_schwarz_opts), C.c_int32,
+                                                 C.c_double, C.c_double, C.c_int32, P(C.c_int32)]
+                                                + [_vp] * 16 + [P(C.c_double)] * 4,
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -531,3 +534,21 @@ def schwarz_frame_adjoint(B: Domain, S: Domain, dT, opts, iters, adjB_end, adjS_
                 "schwarz_frame_adjoint")
     return (dict(zip("xvBF", oB)), dict(zip("xvBF", oS)), np.array(mB[:]), np.array(lB[:]), np.array(mS[:]),
             np.array(lS[:]))
+
+
+def schwarz_frame_adjoint_implicit(B: Domain, S: Domain, dT, opts, iters, adjB_end, adjS_end, fp_tol=1e-10,
+                                   fp_max=200, adj_cg_rtol=1e-12):
+    """Implicit (fixed-point) adjoint of one Schwarz frame from the pair's
+    current states (see osmpm_schwarz_frame_adjoint_implicit).  Returns the
+    tuple of schwarz_frame_adjoint plus the number of adjoint passes."""
+    aB, aS = _adj_in(B, adjB_end), _adj_in(S, adjS_end)
+    oB, oS = _adj_out(B), _adj_out(S)
+    mB, lB = (C.c_double * B.n_mat)(), (C.c_double * B.n_mat)()
+    mS, lS = (C.c_double * S.n_mat)(), (C.c_double * S.n_mat)()
+    used = C.c_int32(0)
+    B.ctx.check(lib().osmpm_schwarz_frame_adjoint_implicit(
+        B.handle, S.handle, dT, C.byref(opts), int(iters), adj_cg_rtol, float(fp_tol), int(fp_max), C.byref(used),
+        *[_ptr(t) for t in aB], *[_ptr(t) for t in aS], *[_ptr(t) for t in oB], *[_ptr(t) for t in oS],
+        mB, lB, mS, lS), "schwarz_frame_adjoint_implicit")
+    return (dict(zip("xvBF", oB)), dict(zip("xvBF", oS)), np.array(mB[:]), np.array(lB[:]), np.array(mS[:]),
+            np.array(lS[:]), used.value)

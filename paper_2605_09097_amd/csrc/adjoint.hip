@@ -633,4 +633,20 @@ __global__ void __launch_bounds__(kBlock) k_axpy_d(int64_t n, double a, const do
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     y[k] += a * x[k];
 }
+
+// out[0] = sum_k x[k]^2 by one workgroup in a fixed order (strided partial
+// sums per thread, then a tree over the workgroup), so the result does not
+// depend on scheduling.
+__global__ void __launch_bounds__(kBlock) k_sumsq_d(int64_t n, const double *x, double *out) {
+  __shared__ double part[kBlock];
+  double acc = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += kBlock) acc += x[k] * x[k];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = part[0];
+}
 }  // namespace osmpm

@@ -1376,6 +1376,7 @@ osmpm_status single_adjoint_impl(osmpm_domain *d, double dt, const osmpm_solve_o
 // swept in reverse in the order of the oracle's reverse mode; see the ABI.
 template <int D, typename TB>
 osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz_opts *o, int K, double adj_rtol,
+                                  int implicit, double fp_tol, int fp_max, int *fp_used,
                                   const double *const *inB, const double *const *inS, double *const *outB,
                                   double *const *outS, double *mat_h) {
   osmpm_ctx *c = G->c;
@@ -1385,9 +1386,13 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
   const int npB = B->np, npS = S->np, nnB = B->g.nn, nnS = S->g.nn, ndB = nnB * D, ndS = nnS * D;
   osmpm_status s;
   if ((s = group_sync(G))) return s;
+  // Stored iterations: all K (unrolled) or only the last (implicit: every
+  // adjoint pass is linearised there); iteration k lives in slot sl(k).
+  const int n_slots = implicit ? 1 : K;
+  auto sl = [&](int k) -> size_t { return implicit ? 0 : (size_t)k; };
   std::vector<void *> mem;
   TapePoint tB0, tBe;
-  std::vector<TapePoint> tS((size_t)K * (M + 1));
+  std::vector<TapePoint> tS((size_t)n_slots * (M + 1));
   auto cleanup = [&]() {
     tape_free(tB0);
     tape_free(tBe);
@@ -1403,14 +1408,14 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
   double *uB = nullptr, *piB = nullptr, *ubarB = nullptr, *ubarBk = nullptr, *mbarB = nullptr, *vnbarB = nullptr,
          *vBkbar = nullptr, *pibar = nullptr, *pibar_next = nullptr, *hlB = nullptr, *ubarS = nullptr,
          *mbarS = nullptr, *vnbarS = nullptr, *vbcbar = nullptr, *gSn = nullptr, *gSn1 = nullptr, *hlS = nullptr,
-         *mat = nullptr;
+         *mat = nullptr, *nrm = nullptr;
   AdjState aBin, aBo, aSin, aS, aP, aS0;
-  if ((s = tape_alloc(B, tB0)) || (s = tape_alloc(B, tBe)) || (s = dbl((size_t)K * ndB, &uB)) ||
-      (s = dbl((size_t)K * ndB, &piB)) || (s = dbl(ndB, &ubarB)) || (s = dbl(ndB, &ubarBk)) ||
+  if ((s = tape_alloc(B, tB0)) || (s = tape_alloc(B, tBe)) || (s = dbl((size_t)n_slots * ndB, &uB)) ||
+      (s = dbl((size_t)n_slots * ndB, &piB)) || (s = dbl(ndB, &ubarB)) || (s = dbl(ndB, &ubarBk)) ||
       (s = dbl(nnB, &mbarB)) || (s = dbl(ndB, &vnbarB)) || (s = dbl(ndB, &vBkbar)) || (s = dbl(ndB, &pibar)) ||
       (s = dbl(ndB, &pibar_next)) || (s = dbl(ndB, &hlB)) || (s = dbl(ndS, &ubarS)) || (s = dbl(nnS, &mbarS)) ||
       (s = dbl(ndS, &vnbarS)) || (s = dbl(ndS, &vbcbar)) || (s = dbl(ndS, &gSn)) || (s = dbl(ndS, &gSn1)) ||
-      (s = dbl(ndS, &hlS)) || (s = dbl(256, &mat)) || (s = adj_alloc(c, mem, npB, D, aBin)) ||
+      (s = dbl(ndS, &hlS)) || (s = dbl(256, &mat)) || (s = dbl(1, &nrm)) || (s = adj_alloc(c, mem, npB, D, aBin)) ||
       (s = adj_alloc(c, mem, npB, D, aBo)) || (s = adj_alloc(c, mem, npS, D, aSin)) ||
       (s = adj_alloc(c, mem, npS, D, aS)) || (s = adj_alloc(c, mem, npS, D, aP)) ||
       (s = adj_alloc(c, mem, npS, D, aS0))) {
@@ -1432,33 +1437,33 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
   project_group<D>(G, o->eps_tol, nullptr, 0, nullptr);
   HIP_TRY(c, hipMemcpyAsync(piB, B->w0, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
   for (int k = 0; k < K; ++k) {
-    HIP_TRY(c, hipMemcpyAsync(B->w0, piB + (size_t)k * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(B->w0, piB + sl(k) * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
     if ((s = solve_side<D, TB>(G, 0, dT, 1, 0, &o->coarse, nullptr))) return cleanup(), s;
-    HIP_TRY(c, hipMemcpyAsync(uB + (size_t)k * ndB, B->u, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(uB + sl(k) * ndB, B->u, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
     launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(nnB), 1), blk, 0, ddB, dT);
     copy_state_side<D, TB>(G, 1, 0);
     p2g_side<D, TB>(G, 1, false);
-    TapePoint &t0 = tS[(size_t)k * (M + 1)];
+    TapePoint &t0 = tS[sl(k) * (M + 1)];
     if ((s = tape_copy(S, t0, 1, 1 | 2))) return cleanup(), s;
     interp_group<D>(G, kBufVn, nullptr, 0, nullptr);
     interp_group<D>(G, 2, nullptr, 1, nullptr);
     for (int m = 1; m <= M; ++m) {
-      TapePoint &tp = tS[(size_t)k * (M + 1) + (m - 1)];
+      TapePoint &tp = tS[sl(k) * (M + 1) + (m - 1)];
       launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(ndS, 1024), 1), blk, 0, ddS, (double)m / (double)M, 0, 1);
       if ((s = tape_copy(S, tp, 1, 8))) return cleanup(), s;
       if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, nullptr))) return cleanup(), s;
       if ((s = tape_copy(S, tp, 1, 4))) return cleanup(), s;
       g2p_side<D, TB>(G, 1, dt);
       p2g_side<D, TB>(G, 1, false);
-      if ((s = tape_copy(S, tS[(size_t)k * (M + 1) + m], 1, 1 | 2))) return cleanup(), s;
+      if ((s = tape_copy(S, tS[sl(k) * (M + 1) + m], 1, 1 | 2))) return cleanup(), s;
     }
     if (k + 1 < K) {
       project_group<D>(G, o->eps_tol, nullptr, 0, nullptr);
-      HIP_TRY(c, hipMemcpyAsync(piB + (size_t)(k + 1) * ndB, B->w0, (size_t)ndB * 8, hipMemcpyDeviceToDevice,
+      HIP_TRY(c, hipMemcpyAsync(piB + sl(k + 1) * ndB, B->w0, (size_t)ndB * 8, hipMemcpyDeviceToDevice,
                                 c->stream));
     }
   }
-  HIP_TRY(c, hipMemcpyAsync(B->u, uB + (size_t)(K - 1) * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(B->u, uB + sl(K - 1) * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
   g2p_side<D, TB>(G, 0, dT);
   if ((s = tape_copy(B, tBe, 1, 1 | 2 | 4))) return cleanup(), s;
   if ((s = read_status(G))) return cleanup(), s;
@@ -1470,10 +1475,15 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
       (s = zero_bytes(c, mbarB, nnB * 8)) || (s = zero_bytes(c, vnbarB, ndB * 8)) ||
       (s = zero_bytes(c, pibar_next, ndB * 8)) || (s = zero_bytes(c, mat, 256 * 8)))
     return cleanup(), s;
-  adj_g2p<D, TB>(B, tB0, uB + (size_t)(K - 1) * ndB, dT, aBin, ubarB, aBo);
+  adj_g2p<D, TB>(B, tB0, uB + sl(K - 1) * ndB, dT, aBin, ubarB, aBo);
   const int64_t nsS = (int64_t)npS * (2 * D + 2 * D * D);
-  for (int k = K - 1; k >= 0; --k) {
-    if (k == K - 1) {
+  double w_norm = 0.0;
+  for (int j = 0;; ++j) {
+    // unrolled: iteration k = K-1-j; implicit: pass j of the Neumann series
+    // of the fixed-point adjoint, always on the last iteration
+    const int k = implicit ? K - 1 : K - 1 - j;
+    if (k < 0) break;
+    if (j == 0) {
       HIP_TRY(c, hipMemcpyAsync(ubarBk, ubarB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
       for (int f = 0; f < 4; ++f) {
         const size_t bytes = (size_t)std::max(npS, 1) * (f < 2 ? D : D * D) * 8;
@@ -1484,7 +1494,7 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
     } else {
       if ((s = zero_bytes(c, ubarBk, ndB * 8)) || (s = adj_zero(c, aS, npS, D))) return cleanup(), s;
       // the projection of the grid after the last sub-step fed coarse solve k+1
-      TapePoint &tl = tS[(size_t)k * (M + 1) + M];
+      TapePoint &tl = tS[sl(k) * (M + 1) + M];
       if ((s = tape_copy(S, tl, -1, 2))) return cleanup(), s;
       launch(c, -1, 0, -1, k_zero_proj, dim3(blocks_for(ndB, 1024), 1), blk, 0, ddB);
       launch(c, -1, 0, -1, k_project_scatter<D>, dim3(blocks_for(nnS), 1), blk, 0, ddS, ddB, (const double *)nullptr,
@@ -1497,7 +1507,7 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
     }
     if ((s = zero_bytes(c, gSn, ndS * 8)) || (s = zero_bytes(c, gSn1, ndS * 8))) return cleanup(), s;
     for (int m = M; m >= 1; --m) {
-      TapePoint &tp = tS[(size_t)k * (M + 1) + (m - 1)];
+      TapePoint &tp = tS[sl(k) * (M + 1) + (m - 1)];
       if ((s = adj_zero(c, aP, npS, D)) || (s = zero_bytes(c, ubarS, ndS * 8))) return cleanup(), s;
       adj_g2p<D, TB>(S, tp, tp.u, dt, aS, ubarS, aP);
       if ((s = tape_copy(S, tp, -1, 1 | 2 | 8))) return cleanup(), s;
@@ -1531,15 +1541,34 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
            (const double *)vBkbar, dT, ubarBk);
     // coarse solve k
     if ((s = tape_copy(B, tB0, -1, 1 | 2))) return cleanup(), s;
-    HIP_TRY(c, hipMemcpyAsync(B->vbc, piB + (size_t)k * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(B->vbc, piB + sl(k) * ndB, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
     if ((s = zero_bytes(c, pibar, ndB * 8))) return cleanup(), s;
-    if ((s = adj_solve<D, TB>(G, 0, dT, 1, &o->coarse, adj_rtol, uB + (size_t)k * ndB, ubarBk, mbarB, vnbarB, pibar,
+    if ((s = adj_solve<D, TB>(G, 0, dT, 1, &o->coarse, adj_rtol, uB + sl(k) * ndB, ubarBk, mbarB, vnbarB, pibar,
                               hlB, aBo, mat, mat + 64)))
       return cleanup(), s;
     HIP_TRY(c, hipMemcpyAsync(pibar_next, pibar, (size_t)ndB * 8, hipMemcpyDeviceToDevice, c->stream));
+    if (implicit) {
+      // pibar = (Phi_z^T)^j w, w = pibar of pass 0
+      launch(c, -1, 0, -1, k_sumsq_d, dim3(1), blk, 0, (int64_t)ndB, (const double *)pibar, nrm);
+      double h = 0.0;
+      HIP_TRY(c, hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      h = std::sqrt(h);
+      if (j == 0) w_norm = h;
+      *fp_used = j;
+      if (fp_tol > 0.0 && h <= fp_tol * w_norm) break;
+      if (j == fp_max) {
+        if (fp_tol > 0.0) {
+          cleanup();
+          return fail(c, OSMPM_E_NOT_CONVERGED, "adjoint Schwarz iteration did not reach fp_tol within fp_max passes");
+        }
+        break;
+      }
+    }
   }
-  // Step 0: projection of the fine start grid, then both P2Gs
-  {
+  // Step 0: projection of the fine start grid (the first iterate's data, on
+  // which the fixed point does not depend), then both P2Gs
+  if (!implicit) {
     TapePoint &t00 = tS[0];
     if ((s = tape_copy(S, t00, -1, 2))) return cleanup(), s;
     launch(c, -1, 0, -1, k_zero_proj, dim3(blocks_for(ndB, 1024), 1), blk, 0, ddB);
@@ -1554,7 +1583,7 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
   adj_p2g<D, TB>(B, tB0, mbarB, vnbarB, aBo);
   // the pair back at its end-of-frame state
   if ((s = tape_copy(B, tBe, -1, 1 | 2 | 4))) return cleanup(), s;
-  if ((s = tape_copy(S, tS[(size_t)(K - 1) * (M + 1) + M], -1, 1 | 2))) return cleanup(), s;
+  if ((s = tape_copy(S, tS[sl(K - 1) * (M + 1) + M], -1, 1 | 2))) return cleanup(), s;
   adj_to_rows(c, npB, D, aBo, outB[0], outB[1], outB[2], outB[3]);
   adj_to_rows(c, npS, D, aS0, outS[0], outS[1], outS[2], outS[3]);
   HIP_TRY(c, hipMemcpyAsync(mat_h, mat, 256 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -2006,16 +2035,17 @@ osmpm_status osmpm_single_frame_adjoint(osmpm_domain *d, double dt, const osmpm_
   return DISPATCH2(d->D, d->precision, single_adjoint_impl)(d, dt, o, adj_cg_rtol, in, out, mubar, lambar);
 }
 
-osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
-                                         int32_t iters, double adj_cg_rtol, const double *xbB, const double *vbB,
-                                         const double *BbB, const double *FbB, const double *xbS,
-                                         const double *vbS, const double *BbS, const double *FbS, double *oxB,
-                                         double *ovB, double *oBB, double *oFB, double *oxS, double *ovS,
-                                         double *oBS, double *oFS, double *mubarB, double *lambarB, double *mubarS,
-                                         double *lambarS) {
+static osmpm_status schwarz_adjoint_call(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
+                                  int32_t iters, double adj_cg_rtol, int implicit, double fp_tol, int32_t fp_max,
+                                  int32_t *fp_used, const double *xbB, const double *vbB, const double *BbB,
+                                  const double *FbB, const double *xbS, const double *vbS, const double *BbS,
+                                  const double *FbS, double *oxB, double *ovB, double *oBB, double *oFB,
+                                  double *oxS, double *ovS, double *oBS, double *oFS, double *mubarB,
+                                  double *lambarB, double *mubarS, double *lambarS) {
   if (!pair_ok(B, S) || !schwarz_opts_ok(o) || !(dT > 0.0) || iters < 1 || iters > o->k_max ||
       !(adj_cg_rtol > 0.0) || !mubarB || !lambarB || !mubarS || !lambarS)
     return OSMPM_E_INVALID_ARG;
+  if (implicit && (fp_max < 1 || std::isnan(fp_tol))) return OSMPM_E_INVALID_ARG;
   if (B->np > 0 && (!xbB || !vbB || !BbB || !FbB || !oxB || !ovB || !oBB || !oFB)) return OSMPM_E_INVALID_ARG;
   if (S->np > 0 && (!xbS || !vbS || !BbS || !FbS || !oxS || !ovS || !oBS || !oFS)) return OSMPM_E_INVALID_ARG;
   osmpm_batch *G = nullptr;
@@ -2024,8 +2054,10 @@ osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, doubl
   const double *inB[4] = {xbB, vbB, BbB, FbB}, *inS[4] = {xbS, vbS, BbS, FbS};
   double *outB[4] = {oxB, ovB, oBB, oFB}, *outS[4] = {oxS, ovS, oBS, oFS};
   std::vector<double> mat(256, 0.0);
-  s = DISPATCH2(B->D, B->precision, schwarz_adjoint_impl)(G, dT, o, iters, adj_cg_rtol, inB, inS, outB, outS,
-                                                          mat.data());
+  int used = 0;
+  s = DISPATCH2(B->D, B->precision, schwarz_adjoint_impl)(G, dT, o, iters, adj_cg_rtol, implicit, fp_tol, fp_max,
+                                                          &used, inB, inS, outB, outS, mat.data());
+  if (fp_used) *fp_used = used;
   if (s) return s;
   for (int k = 0; k < B->n_mat; ++k) {
     mubarB[k] += mat[k];
@@ -2036,6 +2068,27 @@ osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, doubl
     lambarS[k] += mat[192 + k];
   }
   return OSMPM_OK;
+}
+osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
+                                         int32_t iters, double adj_cg_rtol, const double *xbB, const double *vbB,
+                                         const double *BbB, const double *FbB, const double *xbS,
+                                         const double *vbS, const double *BbS, const double *FbS, double *oxB,
+                                         double *ovB, double *oBB, double *oFB, double *oxS, double *ovS,
+                                         double *oBS, double *oFS, double *mubarB, double *lambarB, double *mubarS,
+                                         double *lambarS) {
+  return schwarz_adjoint_call(B, S, dT, o, iters, adj_cg_rtol, 0, 0.0, 0, nullptr, xbB, vbB, BbB, FbB, xbS, vbS,
+                              BbS, FbS, oxB, ovB, oBB, oFB, oxS, ovS, oBS, oFS, mubarB, lambarB, mubarS, lambarS);
+}
+
+osmpm_status osmpm_schwarz_frame_adjoint_implicit(
+    osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o, int32_t iters, double adj_cg_rtol,
+    double fp_tol, int32_t fp_max, int32_t *fp_used, const double *xbB, const double *vbB, const double *BbB,
+    const double *FbB, const double *xbS, const double *vbS, const double *BbS, const double *FbS, double *oxB,
+    double *ovB, double *oBB, double *oFB, double *oxS, double *ovS, double *oBS, double *oFS, double *mubarB,
+    double *lambarB, double *mubarS, double *lambarS) {
+  return schwarz_adjoint_call(B, S, dT, o, iters, adj_cg_rtol, 1, fp_tol, fp_max, fp_used, xbB, vbB, BbB, FbB,
+                              xbS, vbS, BbS, FbS, oxB, ovB, oBB, oFB, oxS, ovS, oBS, oFS, mubarB, lambarB, mubarS,
+                              lambarS);
 }
 
 osmpm_status osmpm_get_particles(osmpm_domain *d, double *x, double *v, double *B, double *F, int32_t *id) {

@@ -218,6 +218,7 @@ __global__ void k_adj_interp(GridDev gB, GridDev gS, const double *mB, const uin
                              double *vBbar);
 __global__ void k_adj_temporal(int64_t n, double am, const double *vbcbar, double *a, double *b);
 __global__ void k_axpy_d(int64_t n, double a, const double *x, double *y);
+__global__ void k_sumsq_d(int64_t n, const double *x, double *out);
 template <int D>
 __global__ void k_adj_vel(int nn, const double *m, const double *vbar, double dT, double *ubar);
 

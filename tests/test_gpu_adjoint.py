@@ -65,14 +65,14 @@ def test_single_frame_adjoint_parity(ctx, precision):
     D.close()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_schwarz_frame_adjoint_parity(ctx, precision):
+def _schwarz_case(ctx, precision):
+    """The small inclusion on both sides advanced two frames; the pair and
+    the oracle hold the start of frame 3, K = the oracle's iteration count."""
     from paper_2605_09097_amd import binding as b
     from paper_2605_09097_amd import scenes
 
     sc = scenes.workload("inclusion_tiny")
     prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
-    tol = 1e-7 if precision == "fp64" else 1e-3
     so = b.solve_opts(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-12 if precision == "fp64" else 1e-5)
     go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
     sor = oracle.solve_opts(**TIGHT_OR)
@@ -96,14 +96,60 @@ def test_schwarz_frame_adjoint_parity(ctx, precision):
     OS.set_state(sS0)
     WB = _weights({k: v.shape for k, v in sB0.items()}, 5)
     WS = _weights({k: v.shape for k, v in sS0.items()}, 6)
+    return sc, go, oo, pair, OB, OS, K, WB, WS
+
+
+def _cmp_frame(g, o, tol):
+    _cmp(g[0], o[0], tol, "B")
+    _cmp(g[1], o[1], tol, "S")
+    for a, b_ in zip(g[2:6], o[2:6]):
+        assert rel_err(a, b_) < tol, (a, b_)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_schwarz_frame_adjoint_parity(ctx, precision):
+    from paper_2605_09097_amd import binding as b
+
+    sc, go, oo, pair, OB, OS, K, WB, WS = _schwarz_case(ctx, precision)
+    tol = 1e-7 if precision == "fp64" else 1e-3
     print("Schwarz frame adjoint,", precision, "K =", K, flush=True)
-    gB, gS, gmB, glB, gmS, glS = b.schwarz_frame_adjoint(pair.B, pair.S, sc.dT, go, K, WB, WS,
-                                                         adj_cg_rtol=1e-12 if precision == "fp64" else 1e-6)
-    oB, oS_, omB, olB, omS, olS = oracle.schwarz_frame_adjoint(OB, OS, sc.dT, oo, K, WB, WS)
-    _cmp(gB, oB, tol, "B")
-    _cmp(gS, oS_, tol, "S")
-    for g, o in ((gmB, omB), (glB, olB), (gmS, omS), (glS, olS)):
-        assert rel_err(g, o) < tol, (g, o)
+    g = b.schwarz_frame_adjoint(pair.B, pair.S, sc.dT, go, K, WB, WS,
+                                adj_cg_rtol=1e-12 if precision == "fp64" else 1e-6)
+    o = oracle.schwarz_frame_adjoint(OB, OS, sc.dT, oo, K, WB, WS)
+    _cmp_frame(g, o, tol)
+    pair.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_schwarz_frame_adjoint_implicit_parity(ctx, precision):
+    """The fixed-point adjoint with a fixed number of passes (30) against
+    the oracle's, then (FP64) with the pass count left to the tolerance: the
+    same count on both sides."""
+    from paper_2605_09097_amd import binding as b
+
+    sc, go, oo, pair, OB, OS, K, WB, WS = _schwarz_case(ctx, precision)
+    tol = 1e-7 if precision == "fp64" else 1e-3
+    rtol = 1e-12 if precision == "fp64" else 1e-6
+    print("implicit Schwarz frame adjoint, 30 passes,", precision, "K =", K, flush=True)
+    g = b.schwarz_frame_adjoint_implicit(pair.B, pair.S, sc.dT, go, K, WB, WS, fp_tol=0.0, fp_max=30,
+                                         adj_cg_rtol=rtol)
+    o = oracle.schwarz_frame_adjoint_implicit(OB, OS, sc.dT, oo, K, WB, WS, fp_tol=0.0, fp_max=30)
+    assert g[6] == 30 and o[6] == 30
+    _cmp_frame(g, o, tol)
+    if precision == "fp64":
+        # a fresh pair and oracle at the start of the same frame
+        pair.close()
+        sc, go, oo, pair, OB, OS, K2, WB, WS = _schwarz_case(ctx, precision)
+        assert K2 == K
+        print("implicit Schwarz frame adjoint to fp_tol 1e-9, fp64", flush=True)
+        g = b.schwarz_frame_adjoint_implicit(pair.B, pair.S, sc.dT, go, K, WB, WS, fp_tol=1e-9, fp_max=200,
+                                             adj_cg_rtol=rtol)
+        o = oracle.schwarz_frame_adjoint_implicit(OB, OS, sc.dT, oo, K, WB, WS, fp_tol=1e-9, fp_max=200)
+        assert g[6] == o[6] and g[6] > 30, (g[6], o[6])
+        _cmp_frame(g, o, tol)
+        # the pair holds the end-of-frame state afterwards, as after the forward call
+        xg = pair.S.particles_input_order()[0]
+        assert rel_err(xg - sc.S.x, OS.x - sc.S.x) < 1e-9
     pair.close()
 
 
