@@ -207,17 +207,31 @@ def batched_form(ctx, n_scenes, steps, prec, solve):
             "kernels": kern}
 
 
-def adjoint_form(ctx, sc, prec, frames):
+def _tape_bytes(D, prec, points):
+    """Device bytes of `points` stored forward points of domain D (sorted
+    particle arrays, bins and grid of each, as the frame adjoint lays them
+    out)."""
+    from paper_2605_09097_amd import binding
+
+    n, nn, nk = D.info()
+    d, tb = D.dim, (4 if prec == binding.OSMPM_MIXED else 8)
+    per = n * (8 * d + tb * d + 2 * tb * d * d + 8 + 8 + 4 + 4 + 1) + 4 * (nk + 1) + nn * (8 + 3 * 8 * d + d)
+    return points * per
+
+
+def adjoint_form(ctx, sc, prec, frames, mode="unrolled"):
     """Reverse mode on the same workload: dL/dE (matrix and inclusion Young's
     moduli) of the seeded top-edge mismatch after `frames` frames, through
     torch.autograd over the library's frame adjoints with one checkpoint
-    every 10 frames.  Forward and backward timed separately."""
+    every 10 frames.  Forward and backward timed separately.  mode: the
+    unrolled frame adjoint (k* iterations held) or the implicit one
+    (fixed-point adjoint series to the forward's Schwarz tolerance)."""
     import numpy as np
     import torch
 
     from paper_2605_09097_amd import binding, diff, scenes
 
-    run = diff.SchwarzRun(ctx, sc, prec, checkpoint_every=10)
+    run = diff.SchwarzRun(ctx, sc, prec, checkpoint_every=10, adjoint=mode)
     idx, target = scenes.top_edge_target(sc, frames, seed=0)
     E = torch.tensor(np.asarray(sc.S.E, dtype=np.float64), requires_grad=True)
     torch.cuda.synchronize()
@@ -229,12 +243,22 @@ def adjoint_form(ctx, sc, prec, frames):
     L.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    M, K = sc.M, max(run.iters)
+    nnB = run.pair.B.info()[1]
+    slots = 1 if mode == "implicit" else K
+    tape = (_tape_bytes(run.pair.S, prec, slots * (M + 1)) + _tape_bytes(run.pair.B, prec, 2)
+            + 2 * slots * nnB * run.pair.B.dim * 8)
+    out = {"mode": mode, "frames": frames, "checkpoint_every": 10, "loss": float(L),
+           "dL_dE": [float(g) for g in E.grad],
+           "forward_ms_per_frame": 1e3 * (t1 - t0) / frames, "backward_ms_per_frame": 1e3 * (t2 - t1) / frames,
+           "schwarz_iters": run.iters, "frame_tape_MB_max": tape / 1e6,
+           "note": "backward = per segment: restore checkpoint, rerun frames; per frame: recompute with storage, "
+                   "reverse sweep (adjoint CG per solve)"}
+    if mode == "implicit":
+        out["adjoint_passes"] = run.fp_passes
+        out["fp_tol"] = run.fp_tol
     run.close()
-    return {"frames": frames, "checkpoint_every": 10, "loss": float(L), "dL_dE": [float(g) for g in E.grad],
-            "forward_ms_per_frame": 1e3 * (t1 - t0) / frames, "backward_ms_per_frame": 1e3 * (t2 - t1) / frames,
-            "schwarz_iters": run.iters,
-            "note": "backward = per segment: restore checkpoint, rerun frames; per frame: recompute with storage, "
-                    "reverse sweep (adjoint CG per solve)"}
+    return out
 
 
 def adjoint_batch_form(n_scenes, frames, workers, prec):
@@ -445,7 +469,13 @@ def main():
         p64.close()
         fp64 = {"value": args.steps * _frame_particle_steps(sc) / el64, "ms_per_step": 1e3 * el64 / args.steps,
                 "schwarz_iters_mean": float(np.mean([s.iters for s in st64]))}
-    adjoint = adjoint_form(ctx, sc, prec, args.adjoint_frames) if args.adjoint_frames > 0 else None
+    adjoint = None
+    if args.adjoint_frames > 0:
+        adjoint = adjoint_form(ctx, sc, prec, args.adjoint_frames)
+        imp = adjoint_form(ctx, sc, prec, args.adjoint_frames, mode="implicit")
+        g_u, g_i = np.asarray(adjoint["dL_dE"]), np.asarray(imp["dL_dE"])
+        imp["rel_diff_vs_unrolled"] = float(np.abs(g_i - g_u).max() / max(np.abs(g_u).max(), 1e-300))
+        adjoint["implicit"] = imp
     batched = None
     if args.batch_scenes > 0:
         batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve)

@@ -11,6 +11,11 @@ derivative with respect to the Lame parameters, converted to Young's moduli
 with the textbook relations.  Memory is one checkpoint per segment plus one
 segment of frame start states.
 
+adjoint="implicit" applies the fixed-point adjoint of the Schwarz iteration
+instead (osmpm_schwarz_frame_adjoint_implicit): the derivative of the
+converged interface data rather than of the k* iterations actually run, with
+only the last iteration's intermediates stored per frame.
+
 OSMPMStep is the torch.autograd.Function over this: E (the Young's moduli
 of the scene's materials) -> final coarse particle positions.
 """
@@ -30,7 +35,10 @@ class SchwarzRun:
     to the Young's moduli of its materials (indexed as in the fine domain,
     whose material list contains the coarse one's as a prefix)."""
 
-    def __init__(self, ctx, scene, precision=binding.OSMPM_FP64, opts=None, checkpoint_every=10, adj_cg_rtol=None):
+    def __init__(self, ctx, scene, precision=binding.OSMPM_FP64, opts=None, checkpoint_every=10, adj_cg_rtol=None,
+                 adjoint="unrolled", fp_tol=None, fp_max=400):
+        if adjoint not in ("unrolled", "implicit"):
+            raise ValueError("adjoint must be 'unrolled' or 'implicit'")
         self.ctx = ctx
         self.torch = ctx.torch
         self.scene = scene
@@ -45,6 +53,11 @@ class SchwarzRun:
         self.nB = len(scene.B.E)
         self.iters = []
         self.ckpt = {}
+        self.adjoint = adjoint
+        # the adjoint series to the forward's own Schwarz tolerance by default
+        self.fp_tol = float(fp_tol) if fp_tol is not None else float(self.opts.eps_conv)
+        self.fp_max = int(fp_max)
+        self.fp_passes = []
 
     # ---- state handling (input particle order, device tensors)
     def _save(self, D):
@@ -86,6 +99,7 @@ class SchwarzRun:
         (dL/dE per material, adjoint of the initial coarse state, of the
         initial fine state)."""
         n = len(self.iters)
+        self.fp_passes = [0] * n
         dmu, dlam = _lame_de(self.E, self.nu)
         dE = np.zeros_like(self.E)
         aB, aS = adjB_end, adjS_end
@@ -105,8 +119,14 @@ class SchwarzRun:
                 pB, pS = self.scene.bc_params(f)
                 self.pair.B.set_bc_params(pB)
                 self.pair.S.set_bc_params(pS)
-                aB, aS, mB, lB, mS, lS = binding.schwarz_frame_adjoint(
-                    self.pair.B, self.pair.S, self.scene.dT, self.opts, self.iters[f], aB, aS, self.adj_cg_rtol)
+                if self.adjoint == "implicit":
+                    aB, aS, mB, lB, mS, lS, self.fp_passes[f] = binding.schwarz_frame_adjoint_implicit(
+                        self.pair.B, self.pair.S, self.scene.dT, self.opts, self.iters[f], aB, aS,
+                        fp_tol=self.fp_tol, fp_max=self.fp_max, adj_cg_rtol=self.adj_cg_rtol)
+                else:
+                    aB, aS, mB, lB, mS, lS = binding.schwarz_frame_adjoint(
+                        self.pair.B, self.pair.S, self.scene.dT, self.opts, self.iters[f], aB, aS,
+                        self.adj_cg_rtol)
                 dE[: self.nB] += mB * dmu[: self.nB] + lB * dlam[: self.nB]
                 dE += mS * dmu + lS * dlam
         return dE, aB, aS
