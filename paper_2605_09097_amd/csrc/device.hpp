@@ -15,6 +15,29 @@ namespace osmpm {
 constexpr int kBlock = 256;  // threads per workgroup (4 waves)
 constexpr int kMaxGroups = 4;
 
+// Load of p[i] through the global address space.  Pointers copied out of a
+// descriptor are generic, and a generic (flat) load also occupies the LDS
+// wait counter, so a wave could not wait for its particle data without also
+// draining its outstanding LDS atomics.
+template <typename T>
+__device__ inline T gload(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+template <typename T>
+__device__ inline void gstore(T *p, int64_t i, T v) {
+  ((__attribute__((address_space(1))) T *)p)[i] = v;
+}
+// Relaxed device-scope p[i] += v through the global address space (hardware
+// floating-point atomics with -munsafe-fp-atomics).
+template <typename T>
+__device__ inline void gatomic_add(T *p, int64_t i, T v) {
+  __hip_atomic_fetch_add((__attribute__((address_space(1))) T *)p + i, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+}
+// A device word that is the same for the whole launch (a flag, an index),
+// read into a scalar register.
+__device__ inline int uload(const int *p) { return __builtin_amdgcn_readfirstlane(gload(p, 0)); }
+
 // Error bits raised by kernels (OR-ed into a device word).
 constexpr int kErrOutOfGrid = 1;
 constexpr int kErrInverted = 2;

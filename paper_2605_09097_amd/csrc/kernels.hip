@@ -391,8 +391,8 @@ __global__ void __launch_bounds__(kBlock) k_copy_state(const DomDesc *dd, int to
 // padding blocks.
 __device__ inline bool tile_range(const TileGeom &tg, const int *cell_start, int t, int &p0, int &p1, int *org) {
   if (t >= tg.ntiles) return false;
-  p0 = cell_start[t * tg.tvol];
-  p1 = cell_start[(t + 1) * tg.tvol];
+  p0 = gload(cell_start, (int64_t)t * tg.tvol);
+  p1 = gload(cell_start, (int64_t)(t + 1) * tg.tvol);
   tile_origin(tg, t, org);
   return true;
 }
@@ -450,12 +450,21 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active || (int)blockIdx.x >= dm.tg.nblocks) return;
   extern __shared__ double lds[];
-  const TileGeom &tg = dm.tg;
-  const GridDev &g = dm.g;
+  // Descriptor fields are copied to registers: the loops below issue
+  // atomics, after which the compiler would otherwise reload every field
+  // from the descriptor in global memory (a dependent round trip per
+  // particle).
+  const TileGeom tg = dm.tg;
+  const GridDev g = dm.g;
   const int t = tile_of_block(tg, blockIdx.x);
   int p0, p1, org[3];
   if (!tile_range(tg, dm.cell_start, t, p0, p1, org) || p0 == p1) return;
-  const PartPtrs &P = dm.pb[*dm.cur];
+  const PartPtrs P = dm.pb[*dm.cur];
+  const double scale = dm.scale;
+  double *const gm = dm.m;
+  double *const gvn = dm.vn;
+  long long *const gq_all = dm.q_all;
+  long long *const gqg = dm.qg;
   const int64_t cap = dm.cap;
   const TB *v = static_cast<const TB *>(P.v);
   const TB *B = static_cast<const TB *>(P.B);
@@ -470,15 +479,28 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   __syncthreads();
   const TB dx_t = (TB)g.dx, Dinv_t = (TB)dm.Dinv;
   for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
+    // all of the particle's loads are issued together, one round trip
     double xp[D];
     TB vp[D], Bp[D * D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      xp[a] = P.x[a * cap + p];
-      vp[a] = v[a * cap + p];
+      xp[a] = gload(P.x, a * cap + p);
+      vp[a] = gload(v, a * cap + p);
     }
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Bp[k] = B[k * cap + p];
+    for (int k = 0; k < D * D; ++k) Bp[k] = gload(B, k * cap + p);
+    const double mp = gload(P.mass, p);
+    const uint8_t fl = kQ ? gload(P.flags, p) : uint8_t(0);
+    // an empty asm that consumes every loaded value: the compiler would
+    // otherwise issue the velocity, affine and mass loads only after the
+    // tile check, a second round trip per particle
+    if constexpr (D == 2)
+      asm volatile("" ::"v"(xp[0]), "v"(xp[1]), "v"(vp[0]), "v"(vp[1]), "v"(Bp[0]), "v"(Bp[1]), "v"(Bp[2]),
+                   "v"(Bp[3]), "v"(mp));
+    else
+      asm volatile("" ::"v"(xp[0]), "v"(xp[1]), "v"(xp[2]), "v"(vp[0]), "v"(vp[1]), "v"(vp[2]), "v"(Bp[0]),
+                   "v"(Bp[1]), "v"(Bp[2]), "v"(Bp[3]), "v"(Bp[4]), "v"(Bp[5]), "v"(Bp[6]), "v"(Bp[7]),
+                   "v"(Bp[8]), "v"(mp));
     Stencil<D> st;
     stencil_eval<D>(xp, g, st);
     int l[3];
@@ -486,9 +508,7 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
       atomicOr(err, kErrTile);
       continue;
     }
-    const double mp = P.mass[p];
-    const double mq = mp * dm.scale;
-    const uint8_t fl = P.flags[p];
+    const double mq = mp * scale;
     TB f_t[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) f_t[a] = (TB)st.f[a];
@@ -540,16 +560,16 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
     if (i < 0) continue;
     const double m = lm[r];
     if (m != 0.0) {
-      atomicAdd(&dm.m[i], m);
+      atomicAdd(&gm[i], m);
 #pragma unroll
-      for (int a = 0; a < D; ++a) atomicAdd(&dm.vn[i * D + a], lmv[a * nreg + r]);
+      for (int a = 0; a < D; ++a) atomicAdd(&gvn[i * D + a], lmv[a * nreg + r]);
     }
     if (want_q) {
-      if (lq[r] != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&dm.q_all[i]), (unsigned long long)lq[r]);
+      if (lq[r] != 0) atomicAdd(reinterpret_cast<unsigned long long *>(&gq_all[i]), (unsigned long long)lq[r]);
       for (int gi = 0; gi < n_groups; ++gi) {
         const long long q = lq[(1 + gi) * nreg + r];
         if (q != 0)
-          atomicAdd(reinterpret_cast<unsigned long long *>(&dm.qg[(int64_t)gi * g.nn + i]), (unsigned long long)q);
+          atomicAdd(reinterpret_cast<unsigned long long *>(&gqg[(int64_t)gi * g.nn + i]), (unsigned long long)q);
       }
     }
   }
@@ -1124,10 +1144,18 @@ struct CgStep {
   double alpha, beta;
   bool done;
 };
-__device__ inline CgStep cg_scalars(CgState *S, int i, double sg, double sd, double sr, double rtol, int max_cg,
-                                    bool write) {
+// The state launch i reads (written by launches before it): |r_0|^2,
+// gamma_(i-1) and alpha_(i-1) of the previous step.
+struct CgPrev {
+  double rr0, gam, alp;
+};
+__device__ inline CgPrev cg_prev(const CgState *S, int i) {
+  return CgPrev{gload(&S->rr0, 0), gload(&S->gam[i & 1], 0), gload(&S->alp[i & 1], 0)};
+}
+__device__ inline CgStep cg_scalars(CgState *S, const CgPrev &pv, int i, double sg, double sd, double sr,
+                                    double rtol, int max_cg, bool write) {
   CgStep r{0.0, 0.0, false};
-  const double rr0 = (i == 1) ? sr : S->rr0;
+  const double rr0 = (i == 1) ? sr : pv.rr0;
   if (i - 1 >= max_cg) {
     r.done = true;
   } else if (i == 1) {
@@ -1136,8 +1164,8 @@ __device__ inline CgStep cg_scalars(CgState *S, int i, double sg, double sd, dou
     r.done = sqrt(sr) <= rtol * sqrt(rr0);
   }
   if (!r.done) {
-    r.beta = (i == 1) ? 0.0 : sg / S->gam[i & 1];
-    const double den = (i == 1) ? sd : sd - r.beta * sg / S->alp[i & 1];
+    r.beta = (i == 1) ? 0.0 : sg / pv.gam;
+    const double den = (i == 1) ? sd : sd - r.beta * sg / pv.alp;
     if (den > 0.0)
       r.alpha = sg / den;
     else
@@ -1173,31 +1201,59 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
-  const TileGeom &tg = dm.tg;
-  if (!*dm.active || (int)blockIdx.x >= tg.nblocks) return;
-  CgState *S = dm.cg;
-  if (S->done) return;
+  // Every value that is the same for the whole launch is fetched in one
+  // round of scalar loads before anything depends on it, and the vectors of
+  // the rotation are chosen among preloaded pointers instead of indexing the
+  // descriptor with the iteration (which would be one more dependent load).
+  // Data go through global-address-space accesses, so waiting for them never
+  // waits for this wave's LDS atomics as well.
+  const TileGeom tg = dm.tg;
+  CgState *const S = dm.cg;
+  const int act = uload(dm.active);
+  const int sdone = uload(&S->done);
+  const int i = uload(&S->k_at[q]);
+  const int cur = uload(dm.cur);
+  if (!act || sdone || (int)blockIdx.x >= tg.nblocks) return;
   extern __shared__ double lds[];
   __shared__ double red[12];
-  const GridDev &g = dm.g;
+  const GridDev g = dm.g;
   const int tid = threadIdx.x;
-  const int i = S->k_at[q];
   const int ndof = dm.ndof;
   const int nbt = tg.nblocks;
   const int64_t cap = dm.cap;
-  const TB *Atil = static_cast<const TB *>(dm.Atil);
-  const TB *dg = static_cast<const TB *>(dm.gd);
-  const TB *r_old = static_cast<const TB *>(dm.cr[(i + 1) & 1]);
-  TB *r_new = static_cast<TB *>(dm.cr[i & 1]);
-  const TB *w_old = static_cast<const TB *>(dm.cw[(i + 2) % 3]);
-  TB *w_new = static_cast<TB *>(dm.cw[i % 3]);
-  TB *w_clr = static_cast<TB *>(dm.cw[(i + 1) % 3]);
-  const TB *s_old = static_cast<const TB *>(dm.cs[i & 1]);
-  TB *s_new = static_cast<TB *>(dm.cs[(i + 1) & 1]);
-  TB *uu = static_cast<TB *>(dm.cu), *pp = static_cast<TB *>(dm.cp), *del = static_cast<TB *>(dm.del);
-  const double *pin = dm.part_cg + (size_t)(q ^ 1) * 3 * dm.pstride;
-  double *pout = dm.part_cg + (size_t)q * 3 * dm.pstride;
-  const double *x = dm.pb[*dm.cur].x;
+  const int pstride = dm.pstride;
+  const uint8_t *const fr = dm.fr;
+  const double *const gm = dm.m;
+  const TB *const Atil = static_cast<const TB *>(dm.Atil);
+  const TB *const dg = static_cast<const TB *>(dm.gd);
+  void *const cr0 = dm.cr[0], *const cr1 = dm.cr[1];
+  void *const cs0 = dm.cs[0], *const cs1 = dm.cs[1];
+  void *const cw0 = dm.cw[0], *const cw1 = dm.cw[1], *const cw2 = dm.cw[2];
+  const int i2 = i & 1, i3 = i % 3;
+  const TB *const r_old = static_cast<const TB *>(i2 ? cr0 : cr1);  // r_(i-1)
+  TB *const r_new = static_cast<TB *>(i2 ? cr1 : cr0);              // r_i
+  const TB *const w_old = static_cast<const TB *>(i3 == 0 ? cw2 : (i3 == 1 ? cw0 : cw1));
+  TB *const w_new = static_cast<TB *>(i3 == 0 ? cw0 : (i3 == 1 ? cw1 : cw2));
+  TB *const w_clr = static_cast<TB *>(i3 == 0 ? cw1 : (i3 == 1 ? cw2 : cw0));
+  const TB *const s_old = static_cast<const TB *>(i2 ? cs1 : cs0);
+  TB *const s_new = static_cast<TB *>(i2 ? cs0 : cs1);
+  TB *const uu = static_cast<TB *>(dm.cu);
+  TB *const pp = static_cast<TB *>(dm.cp);
+  TB *const del = static_cast<TB *>(dm.del);
+  const double *const pin = dm.part_cg + (size_t)(q ^ 1) * 3 * pstride;
+  double *const pout = dm.part_cg + (size_t)q * 3 * pstride;
+  const double *const x = cur ? dm.pb[1].x : dm.pb[0].x;
+  // scalars of the previous step (launches before this one wrote them)
+  CgPrev prev{0.0, 0.0, 0.0};
+  double alpha = 0.0, beta = 0.0;
+  if (i > 0) {
+    if (split) {
+      alpha = gload(&S->alpha_n, 0);
+      beta = gload(&S->beta_n, 0);
+    } else {
+      prev = cg_prev(S, i);
+    }
+  }
   const int t = tile_of_block(tg, blockIdx.x);
   int p0 = 0, p1 = 0, org[3] = {0, 0, 0};
   const bool tile_ok = tile_range(tg, dm.cell_start, t, p0, p1, org) && p0 < p1;
@@ -1206,9 +1262,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   double sg = 0.0, sd = 0.0, sr = 0.0;
   if (i > 0 && !split)
     for (int j = tid; j < nbt; j += kBlock) {
-      sg += pin[j];
-      sd += pin[dm.pstride + j];
-      sr += pin[2 * dm.pstride + j];
+      sg += gload(pin, j);
+      sd += gload(pin, pstride + j);
+      sr += gload(pin, 2 * pstride + j);
     }
   int ri = -1;
   TB hr[D], hw[D], hs[D], hd[D];
@@ -1218,16 +1274,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const int k = ri * D + a;
-      hf[a] = (ri >= 0) ? dm.fr[k] : 0;
-      hr[a] = (ri >= 0) ? r_old[k] : TB(0);
-      hw[a] = (ri >= 0 && i > 0) ? w_old[k] : TB(0);
-      hs[a] = (ri >= 0 && i > 0) ? s_old[k] : TB(0);
-      hd[a] = (ri >= 0) ? dg[k] : TB(1);
+      hf[a] = (ri >= 0) ? gload(fr, k) : 0;
+      hr[a] = (ri >= 0) ? gload(i == 0 ? (const TB *)r_new : r_old, k) : TB(0);  // r_0 at i = 0
+      hw[a] = (ri >= 0 && i > 0) ? gload(w_old, k) : TB(0);
+      hs[a] = (ri >= 0 && i > 0) ? gload(s_old, k) : TB(0);
+      hd[a] = (ri >= 0) ? gload(dg, k) : TB(1);
     }
-  }
-  if (i == 0 && tile_ok && tid < nreg && ri >= 0) {
-#pragma unroll
-    for (int a = 0; a < D; ++a) hr[a] = r_new[ri * D + a];  // r_0
   }
   const int pp0 = p0 + tid;
   const bool have_p = tile_ok && pp0 < p1;
@@ -1235,9 +1287,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   TB At[ns];
   if (have_p) {
 #pragma unroll
-    for (int a = 0; a < D; ++a) xp[a] = x[a * cap + pp0];
+    for (int a = 0; a < D; ++a) xp[a] = gload(x, a * cap + pp0);
 #pragma unroll
-    for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + pp0];
+    for (int k = 0; k < ns; ++k) At[k] = gload(Atil, k * cap + pp0);
   }
   // first owned DOF of the thread (usually its only one)
   const int k0 = blockIdx.x * kBlock + tid;
@@ -1245,32 +1297,26 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   TB orr = TB(0), ow = TB(0), os = TB(0), od = TB(1), ou = TB(0), op = TB(0), odl = TB(0);
   double om = 0.0;
   if (k0 < ndof) {
-    of = dm.fr[k0];
+    of = gload(fr, k0);
     if (of) {
-      orr = (i == 0) ? r_new[k0] : r_old[k0];
-      od = dg[k0];
-      om = dm.m[k0 / D];
+      orr = gload(i == 0 ? (const TB *)r_new : r_old, k0);
+      od = gload(dg, k0);
+      om = gload(gm, k0 / D);
       if (i > 0) {
-        ow = w_old[k0];
-        os = s_old[k0];
-        ou = uu[k0];
-        op = pp[k0];
-        odl = del[k0];
+        ow = gload(w_old, k0);
+        os = gload(s_old, k0);
+        ou = gload((const TB *)uu, k0);
+        op = gload((const TB *)pp, k0);
+        odl = gload((const TB *)del, k0);
       }
     }
   }
   // --- scalars of iteration i - 1
-  double alpha = 0.0, beta = 0.0;
-  bool done = false;
-  if (split) {
-    if (i > 0) {
-      alpha = S->alpha_n;
-      beta = S->beta_n;
-    }
-  } else {
+  if (!split) {
+    bool done = false;
     if (i > 0) {
       block_sum3(sg, sd, sr, red);
-      const CgStep st = cg_scalars(S, i, sg, sd, sr, rtol, max_cg, blockIdx.x == 0 && tid == 0);
+      const CgStep st = cg_scalars(S, prev, i, sg, sd, sr, rtol, max_cg, blockIdx.x == 0 && tid == 0);
       alpha = st.alpha;
       beta = st.beta;
       done = st.done;
@@ -1291,29 +1337,30 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   // --- owned DOFs
   for (int k = k0; k < ndof; k += nbt * kBlock) {
     const bool first = (k == k0);
-    w_clr[k] = TB(0);
-    if (!(first ? of : dm.fr[k])) continue;
+    gstore(w_clr, k, TB(0));
+    if (!(first ? of : gload(fr, k))) continue;
     TB r, u;
     if (i == 0) {
-      r = first ? orr : r_new[k];
-      u = cg_precond<TB>(r, first ? od : dg[k]);
+      r = first ? orr : gload((const TB *)r_new, k);
+      u = cg_precond<TB>(r, first ? od : gload(dg, k));
     } else {
-      const TB pv = cg_direction<TB>(first ? ou : uu[k], beta, first ? op : pp[k]);
-      pp[k] = pv;
-      del[k] = (TB)((double)(first ? odl : del[k]) + alpha * (double)pv);
-      TB s;
+      const TB pv = cg_direction<TB>(first ? ou : gload((const TB *)uu, k), beta,
+                                     first ? op : gload((const TB *)pp, k));
+      gstore(pp, k, pv);
+      gstore(del, k, (TB)((double)(first ? odl : gload((const TB *)del, k)) + alpha * (double)pv));
+      TB sv;
       if (first)
-        cg_advance<TB>(orr, ow, os, od, alpha, beta, s, r, u);
+        cg_advance<TB>(orr, ow, os, od, alpha, beta, sv, r, u);
       else
-        cg_advance<TB>(r_old[k], w_old[k], s_old[k], dg[k], alpha, beta, s, r, u);
-      s_new[k] = s;
-      r_new[k] = r;
+        cg_advance<TB>(gload(r_old, k), gload(w_old, k), gload(s_old, k), gload(dg, k), alpha, beta, sv, r, u);
+      gstore(s_new, k, sv);
+      gstore(r_new, k, r);
     }
-    uu[k] = u;
+    gstore(uu, k, u);
     // lumped-mass part of w_i = A u_i; the particle part arrives by atomics
     // from the tiles below, so the owner adds its share atomically too
-    const double mu = (first ? om : dm.m[k / D]) * mdt * (double)u;
-    atomicAdd(&w_new[k], (TB)mu);
+    const double mu = (first ? om : gload(gm, k / D)) * mdt * (double)u;
+    gatomic_add(w_new, k, (TB)mu);
     gsum += (double)r * (double)u;
     rsum += (double)r * (double)r;
     dsum += mu * (double)u;
@@ -1338,11 +1385,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
             fs = hs[a];
             fd = hd[a];
           } else {
-            ff = dm.fr[k];
-            fr_r = (i == 0) ? r_new[k] : r_old[k];
-            fw = (i > 0) ? w_old[k] : TB(0);
-            fs = (i > 0) ? s_old[k] : TB(0);
-            fd = dg[k];
+            ff = gload(fr, k);
+            fr_r = gload(i == 0 ? (const TB *)r_new : r_old, k);
+            fw = (i > 0) ? gload(w_old, k) : TB(0);
+            fs = (i > 0) ? gload(s_old, k) : TB(0);
+            fd = gload(dg, k);
           }
           if (ff) {
             if (i == 0) {
@@ -1361,9 +1408,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
     for (int p = pp0; p < p1; p += kBlock) {
       if (p != pp0) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) xp[a] = x[a * cap + p];
+        for (int a = 0; a < D; ++a) xp[a] = gload(x, a * cap + p);
 #pragma unroll
-        for (int k = 0; k < ns; ++k) At[k] = Atil[k * cap + p];
+        for (int k = 0; k < ns; ++k) At[k] = gload(Atil, k * cap + p);
       }
       Stencil<D, TB> st;  // weights in the bulk type
       stencil_eval<D>(xp, g, st);
@@ -1432,15 +1479,15 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         const double hv = lh[a * nreg + r];
-        if (hv != 0.0) atomicAdd(&w_new[nd * D + a], (TB)hv);
+        if (hv != 0.0) gatomic_add(w_new, (int64_t)nd * D + a, (TB)hv);
       }
     }
   }
   block_sum3(gsum, dsum, rsum, red);
   if (tid == 0) {
-    pout[blockIdx.x] = gsum;
-    pout[dm.pstride + blockIdx.x] = dsum;
-    pout[2 * dm.pstride + blockIdx.x] = rsum;
+    gstore(pout, blockIdx.x, gsum);
+    gstore(pout, pstride + blockIdx.x, dsum);
+    gstore(pout, 2 * pstride + blockIdx.x, rsum);
   }
 }
 
@@ -1466,7 +1513,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_reduce(const DomDesc *dd, int q, 
   block_sum3(sg, sd, sr, red);
   if (tid == 0) {
     const int n = i + 1;
-    const CgStep st = cg_scalars(S, n, sg, sd, sr, rtol, max_cg, true);
+    const CgStep st = cg_scalars(S, cg_prev(S, n), n, sg, sd, sr, rtol, max_cg, true);
     S->alpha_n = st.alpha;
     S->beta_n = st.beta;
     if (st.done) {
