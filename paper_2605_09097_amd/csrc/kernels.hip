@@ -613,18 +613,34 @@ __global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
 template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active) return;
+  // launch-uniform flags in one round of scalar loads, then the particle
+  // arrays' pointers; data through global-address-space accesses
+  const int act = uload(dm.active);
+  const int cur = uload(dm.cur);
+  if (!act) return;
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= dm.np) return;
-  const PartPtrs &P = dm.pb[*dm.cur];
+  const PartPtrs &P = dm.pb[cur];
   const int64_t cap = dm.cap;
-  const GridDev &g = dm.g;
-  TB *v = static_cast<TB *>(P.v);
-  TB *B = static_cast<TB *>(P.B);
-  TB *H = static_cast<TB *>(P.F);
-  double xp[D];
+  const GridDev g = dm.g;
+  double *const px = P.x;
+  TB *const v = static_cast<TB *>(P.v);
+  TB *const B = static_cast<TB *>(P.B);
+  TB *const H = static_cast<TB *>(P.F);
+  const double *const gm = dm.m;
+  const double *const gu = dm.u;
+  // In 2D, x and H = F - I are loaded together (H is not needed until after
+  // the gather, but a load issued there is one more round trip).  In 3D, H
+  // is loaded after the gather: holding its nine values through the 27-node
+  // gather costs a wave per SIMD, which measures slower.
+  constexpr bool kEarlyH = (D == 2);
+  double xp[D], Hp[D * D];
 #pragma unroll
-  for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
+  for (int a = 0; a < D; ++a) xp[a] = gload((const double *)px, a * cap + p);
+  if constexpr (kEarlyH) {
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Hp[k] = (double)gload((const TB *)H, k * cap + p);
+  }
   Stencil<D, TB> st;
   if (!stencil_eval<D>(xp, g, st)) atomicOr(err, kErrOutOfGrid);
   TB vp[D], Bp[D * D], G[D * D];
@@ -646,7 +662,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
     const int i = node_flat<D>(g, idx);
     // inactive nodes (m = 0) contribute nothing; both loads are issued
     // unconditionally so that no load waits on the mass test
-    const double mi = dm.m[i];
+    const double mi = gload(gm, i);
     const TB N = stencil_N<D>(st, k);
     TB gN[D], dxv[D];
     double ui[D];
@@ -654,7 +670,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       dxv[a] = ((TB)k[a] - st.f[a]) * dx_t;
-      const double ua = dm.u[i * D + a];
+      const double ua = gload(gu, (int64_t)i * D + a);
       ui[a] = (mi > 0.0) ? ua : 0.0;
     }
 #pragma unroll
@@ -668,9 +684,10 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
       }
     }
   }
-  double Hp[D * D];
+  if constexpr (!kEarlyH) {
 #pragma unroll
-  for (int k = 0; k < D * D; ++k) Hp[k] = (double)H[k * cap + p];
+    for (int k = 0; k < D * D; ++k) Hp[k] = (double)gload((const TB *)H, k * cap + p);
+  }
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -678,13 +695,13 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
       double t = Hp[a * D + b] + (double)G[a * D + b];
 #pragma unroll
       for (int e = 0; e < D; ++e) t += (double)G[a * D + e] * Hp[e * D + b];
-      H[(a * D + b) * cap + p] = (TB)t;
-      B[(a * D + b) * cap + p] = Bp[a * D + b];
+      gstore(H, (a * D + b) * cap + p, (TB)t);
+      gstore(B, (a * D + b) * cap + p, Bp[a * D + b]);
     }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    v[a * cap + p] = vp[a];
-    P.x[a * cap + p] = xp[a] + dt * (double)vp[a];
+    gstore(v, a * cap + p, vp[a]);
+    gstore(px, a * cap + p, xp[a] + dt * (double)vp[a]);
   }
 }
 
@@ -794,18 +811,29 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active || !phase_wants_grad(dm.ss->phase) || (int)blockIdx.x >= dm.tg.nblocks) return;
+  // launch-uniform flags in one round of scalar loads; data through
+  // global-address-space accesses
+  const int act = uload(dm.active);
+  const int phase = uload(&dm.ss->phase);
+  const int cur = uload(dm.cur);
+  const TileGeom tg = dm.tg;
+  if (!act || !phase_wants_grad(phase) || (int)blockIdx.x >= tg.nblocks) return;
   extern __shared__ double lds[];
-  const TileGeom &tg = dm.tg;
-  const GridDev &g = dm.g;
+  const GridDev g = dm.g;
   const int t = tile_of_block(tg, blockIdx.x);
   int p0, p1, org[3];
   if (!tile_range(tg, dm.cell_start, t, p0, p1, org) || p0 == p1) return;
-  const PartPtrs &P = dm.pb[*dm.cur];
+  const PartPtrs &P = dm.pb[cur];
   const int64_t cap = dm.cap;
-  const TB *F = static_cast<const TB *>(P.F);
-  TB *Atil = static_cast<TB *>(dm.Atil);
-  TB *gdiag = static_cast<TB *>(dm.gd);
+  const double *const px = P.x;
+  const TB *const F = static_cast<const TB *>(P.F);
+  const int *const pmat = P.mat;
+  const double *const pvol = P.vol;
+  const double *const gmu = dm.mu, *const glam = dm.lam;
+  const double *const gu = dm.u;
+  double *const ggr = dm.gg;
+  TB *const Atil = static_cast<TB *>(dm.Atil);
+  TB *const gdiag = static_cast<TB *>(dm.gd);
   const int nreg = tg.nreg;
   double *lu = lds;
   double *lg = lds + D * nreg;
@@ -814,16 +842,32 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
     const int i = region_node<D>(tg, g, org, r);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      lu[a * nreg + r] = (i >= 0) ? dm.u[i * D + a] : 0.0;
+      lu[a * nreg + r] = (i >= 0) ? gload(gu, (int64_t)i * D + a) : 0.0;
       lg[a * nreg + r] = 0.0;
       ld[a * nreg + r] = 0.0;
     }
   }
   __syncthreads();
   for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
+    // the particle's loads together: position, F^n (as H), material, volume;
+    // then the material's moduli
     double xp[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) xp[a] = P.x[a * cap + p];
+    for (int a = 0; a < D; ++a) xp[a] = gload(px, a * cap + p);
+    TB Hn[n];
+#pragma unroll
+    for (int k = 0; k < n; ++k) Hn[k] = gload(F, k * cap + p);
+    const int mt = gload(pmat, p);
+    const double V = gload(pvol, p);
+    const double mu = gload(gmu, mt), lam = gload(glam, mt);
+    // an empty asm that consumes the loaded values keeps the compiler from
+    // issuing the loads only after the tile check (one more round trip)
+    if constexpr (D == 2)
+      asm volatile("" ::"v"(xp[0]), "v"(xp[1]), "v"(Hn[0]), "v"(Hn[1]), "v"(Hn[2]), "v"(Hn[3]), "v"(V), "v"(mu),
+                   "v"(lam));
+    else
+      asm volatile("" ::"v"(xp[0]), "v"(xp[1]), "v"(xp[2]), "v"(Hn[0]), "v"(Hn[1]), "v"(Hn[2]), "v"(Hn[3]),
+                   "v"(Hn[4]), "v"(Hn[5]), "v"(Hn[6]), "v"(Hn[7]), "v"(Hn[8]), "v"(V), "v"(mu), "v"(lam));
     Stencil<D> st;
     stencil_eval<D>(xp, g, st);
     int l[3];
@@ -834,7 +878,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
     double Fn[n], Gu[n];
 #pragma unroll
     for (int k = 0; k < n; ++k) {
-      Fn[k] = load_F<D>(F, cap, p, k);
+      Fn[k] = (double)Hn[k] + ((k % (D + 1) == 0) ? 1.0 : 0.0);  // F = I + H
       Gu[k] = 0.0;
     }
 #pragma unroll
@@ -861,8 +905,6 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
         for (int e = 0; e < D; ++e) tv += Gu[a * D + e] * Fn[e * D + b];
         Fc[a * D + b] = tv;
       }
-    const int mt = P.mat[p];
-    const double mu = dm.mu[mt], lam = dm.lam[mt], V = P.vol[p];
     double Pk[n];
     if (!nh_stress<D, double>(Fc, mu, lam, Pk, nullptr)) {
       atomicOr(err, kErrInverted);
@@ -937,7 +979,7 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
             }
         }
 #pragma unroll
-      for (int k = 0; k < ns; ++k) Atil[k * cap + p] = At[k];
+      for (int k = 0; k < ns; ++k) gstore(Atil, k * cap + p, At[k]);
     }
     // In 3D, recompute the weight gradients for the diagonal rather than keep
     // the gradient scatter's 27 x 3 of them live across the tangent work.
@@ -982,9 +1024,9 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const double gv = lg[a * nreg + r];
-      if (gv != 0.0) atomicAdd(&dm.gg[i * D + a], gv);
+      if (gv != 0.0) gatomic_add(ggr, (int64_t)i * D + a, gv);
       const double dv = ld[a * nreg + r];
-      if (dv != 0.0) atomicAdd(&gdiag[i * D + a], (TB)dv);
+      if (dv != 0.0) gatomic_add(gdiag, (int64_t)i * D + a, (TB)dv);
     }
   }
 }
