@@ -1243,27 +1243,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
-  // Every value that is the same for the whole launch is fetched in one
-  // round of scalar loads before anything depends on it, and the vectors of
-  // the rotation are chosen among preloaded pointers instead of indexing the
-  // descriptor with the iteration (which would be one more dependent load).
-  // Data go through global-address-space accesses, so waiting for them never
-  // waits for this wave's LDS atomics as well.
+  // The launch starts in three rounds of scalar loads: the descriptor
+  // fields, then every word at an address they give (flags, iteration, the
+  // tile's particle range), then the data.  Empty asm statements that consume
+  // each round's values keep the compiler from issuing those loads one by one
+  // where they are first used (after the early exit), which would chain
+  // several more round trips.  The vectors of the rotation are chosen among
+  // preloaded pointers instead of indexing the descriptor with the iteration,
+  // and data go through global-address-space accesses, so that waiting for
+  // them never waits for this wave's LDS atomics as well.
   const TileGeom tg = dm.tg;
   CgState *const S = dm.cg;
-  const int act = uload(dm.active);
-  const int sdone = uload(&S->done);
-  const int i = uload(&S->k_at[q]);
-  const int cur = uload(dm.cur);
-  if (!act || sdone || (int)blockIdx.x >= tg.nblocks) return;
-  extern __shared__ double lds[];
-  __shared__ double red[12];
-  const GridDev g = dm.g;
-  const int tid = threadIdx.x;
-  const int ndof = dm.ndof;
-  const int nbt = tg.nblocks;
-  const int64_t cap = dm.cap;
-  const int pstride = dm.pstride;
+  const int *const pactive = dm.active, *const pcur = dm.cur, *const pcs = dm.cell_start;
   const uint8_t *const fr = dm.fr;
   const double *const gm = dm.m;
   const TB *const Atil = static_cast<const TB *>(dm.Atil);
@@ -1271,6 +1262,35 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   void *const cr0 = dm.cr[0], *const cr1 = dm.cr[1];
   void *const cs0 = dm.cs[0], *const cs1 = dm.cs[1];
   void *const cw0 = dm.cw[0], *const cw1 = dm.cw[1], *const cw2 = dm.cw[2];
+  void *const cu = dm.cu, *const cp = dm.cp, *const cdel = dm.del;
+  double *const part_cg = dm.part_cg;
+  const double *const x0 = dm.pb[0].x, *const x1 = dm.pb[1].x;
+  const int ndof = dm.ndof;
+  const int pstride = dm.pstride;
+  const int64_t cap = dm.cap;
+  const GridDev g = dm.g;
+  asm volatile("" ::"s"(S), "s"(pactive), "s"(pcur), "s"(pcs), "s"(fr), "s"(gm), "s"(Atil), "s"(dg), "s"(cr0),
+               "s"(cs1), "s"(cw0), "s"(cw2), "s"(cu), "s"(cdel), "s"(part_cg), "s"(x0), "s"(x1), "s"(ndof),
+               "s"(pstride), "s"(cap), "s"(tg.nblocks), "s"(tg.tvol), "s"(g.n[0]), "s"(g.n[2]), "s"(g.origin[0]),
+               "s"(g.inv_dx));
+  const int t = tile_of_block(tg, blockIdx.x);
+  const bool t_in = (int)blockIdx.x < tg.nblocks && t < tg.ntiles;
+  const int tc = t < tg.ntiles ? t : tg.ntiles - 1;  // a valid tile (ntiles >= 1)
+  const int act = uload(pactive);
+  const int sdone = uload(&S->done);
+  const int i = uload(&S->k_at[q]);
+  const int cur = uload(pcur);
+  const int tp0 = uload(pcs + (int64_t)tc * tg.tvol);
+  const int tp1 = uload(pcs + (int64_t)(tc + 1) * tg.tvol);
+  const double s_rr0 = gload(&S->rr0, 0), s_gam0 = gload(&S->gam[0], 0), s_gam1 = gload(&S->gam[1], 0);
+  const double s_alp0 = gload(&S->alp[0], 0), s_alp1 = gload(&S->alp[1], 0);
+  const double s_alpha_n = gload(&S->alpha_n, 0), s_beta_n = gload(&S->beta_n, 0);
+  asm volatile("" ::"s"(act), "s"(sdone), "s"(i), "s"(cur), "s"(tp0), "s"(tp1));
+  if (!act || sdone || (int)blockIdx.x >= tg.nblocks) return;
+  extern __shared__ double lds[];
+  __shared__ double red[12];
+  const int tid = threadIdx.x;
+  const int nbt = tg.nblocks;
   const int i2 = i & 1, i3 = i % 3;
   const TB *const r_old = static_cast<const TB *>(i2 ? cr0 : cr1);  // r_(i-1)
   TB *const r_new = static_cast<TB *>(i2 ? cr1 : cr0);              // r_i
@@ -1279,26 +1299,22 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   TB *const w_clr = static_cast<TB *>(i3 == 0 ? cw1 : (i3 == 1 ? cw2 : cw0));
   const TB *const s_old = static_cast<const TB *>(i2 ? cs1 : cs0);
   TB *const s_new = static_cast<TB *>(i2 ? cs0 : cs1);
-  TB *const uu = static_cast<TB *>(dm.cu);
-  TB *const pp = static_cast<TB *>(dm.cp);
-  TB *const del = static_cast<TB *>(dm.del);
-  const double *const pin = dm.part_cg + (size_t)(q ^ 1) * 3 * pstride;
-  double *const pout = dm.part_cg + (size_t)q * 3 * pstride;
-  const double *const x = cur ? dm.pb[1].x : dm.pb[0].x;
+  TB *const uu = static_cast<TB *>(cu);
+  TB *const pp = static_cast<TB *>(cp);
+  TB *const del = static_cast<TB *>(cdel);
+  const double *const pin = part_cg + (size_t)(q ^ 1) * 3 * pstride;
+  double *const pout = part_cg + (size_t)q * 3 * pstride;
+  const double *const x = cur ? x1 : x0;
   // scalars of the previous step (launches before this one wrote them)
-  CgPrev prev{0.0, 0.0, 0.0};
+  const CgPrev prev{s_rr0, i2 ? s_gam1 : s_gam0, i2 ? s_alp1 : s_alp0};
   double alpha = 0.0, beta = 0.0;
-  if (i > 0) {
-    if (split) {
-      alpha = gload(&S->alpha_n, 0);
-      beta = gload(&S->beta_n, 0);
-    } else {
-      prev = cg_prev(S, i);
-    }
+  if (i > 0 && split) {
+    alpha = s_alpha_n;
+    beta = s_beta_n;
   }
-  const int t = tile_of_block(tg, blockIdx.x);
-  int p0 = 0, p1 = 0, org[3] = {0, 0, 0};
-  const bool tile_ok = tile_range(tg, dm.cell_start, t, p0, p1, org) && p0 < p1;
+  int p0 = tp0, p1 = tp1, org[3] = {0, 0, 0};
+  if (t_in) tile_origin(tg, t, org);
+  const bool tile_ok = t_in && p0 < p1;
   const int nreg = tg.nreg;
   // --- independent loads
   double sg = 0.0, sd = 0.0, sr = 0.0;
