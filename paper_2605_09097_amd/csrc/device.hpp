@@ -373,6 +373,184 @@ __device__ __host__ constexpr int sym_index(int r, int c) {
   return r * n - (r * (r - 1)) / 2 + (c - r);
 }
 
+// Cyclic Jacobi eigendecomposition of a small symmetric m x m matrix W
+// (m = 2: one rotation, exact): on return the diagonal of W holds the
+// eigenvalues and the columns of Q the eigenvectors, W_in = Q diag(W) Q^T.
+template <int m, typename T>
+__device__ inline void jacobi_eig(T *W, T *Q) {
+  constexpr T tol2 = sizeof(T) == 8 ? T(1e-32) : T(1e-13);
+#pragma unroll
+  for (int i = 0; i < m; ++i)
+#pragma unroll
+    for (int j = 0; j < m; ++j) Q[i * m + j] = (i == j) ? T(1) : T(0);
+  T diag2 = T(0);
+#pragma unroll
+  for (int i = 0; i < m; ++i) diag2 += W[i * m + i] * W[i * m + i];
+  for (int sweep = 0; sweep < (m == 2 ? 1 : 12); ++sweep) {
+    T off = T(0);
+#pragma unroll
+    for (int p = 0; p < m; ++p)
+#pragma unroll
+      for (int q = p + 1; q < m; ++q) off += W[p * m + q] * W[p * m + q];
+    if (off <= tol2 * diag2 || off == T(0)) break;
+#pragma unroll
+    for (int p = 0; p < m; ++p)
+#pragma unroll
+      for (int q = p + 1; q < m; ++q) {
+        const T apq = W[p * m + q];
+        if (apq != T(0)) {
+          const T theta = (W[q * m + q] - W[p * m + p]) / (T(2) * apq);
+          const T t = (theta >= T(0) ? T(1) : T(-1)) / (fabs(theta) + sqrt(theta * theta + T(1)));
+          const T c = T(1) / sqrt(t * t + T(1));
+          const T s = t * c;
+#pragma unroll
+          for (int k = 0; k < m; ++k) {
+            const T wkp = W[k * m + p], wkq = W[k * m + q];
+            W[k * m + p] = c * wkp - s * wkq;
+            W[k * m + q] = s * wkp + c * wkq;
+            const T qkp = Q[k * m + p], qkq = Q[k * m + q];
+            Q[k * m + p] = c * qkp - s * qkq;
+            Q[k * m + q] = s * qkp + c * qkq;
+          }
+#pragma unroll
+          for (int k = 0; k < m; ++k) {
+            const T wpk = W[p * m + k], wqk = W[q * m + k];
+            W[p * m + k] = c * wpk - s * wqk;
+            W[q * m + k] = s * wpk + c * wqk;
+          }
+        }
+      }
+  }
+}
+
+// Folded Neo-Hookean tangent Atil = V C^T A C (A = dP/dF at F, C: G -> G F^n,
+// packed upper triangle, n = D*D) built from the analytic eigensystem of the
+// Hessian of an isotropic energy (Smith, de Goes and Kim, "Analytic
+// Eigensystems for Isotropic Distortion Energies", 2019), with negative
+// eigenvalues clamped to zero when `project` is set: the PSD projection of A
+// without forming A or running a D^2 x D^2 eigensolve.  With F = U S V^T
+// (S = diag(s), from the eigendecomposition of F^T F), psi_i = dPsi/ds_i =
+// mu s_i + (lam ln J - mu) / s_i, and for each pair i < j
+//   twist  Q = (u_i v_j^T - u_j v_i^T) / sqrt2, eigenvalue mu + (lam ln J - mu) / (s_i s_j),
+//   flip   Q = (u_i v_j^T + u_j v_i^T) / sqrt2, eigenvalue mu + (mu - lam ln J) / (s_i s_j);
+// the remaining D modes are U diag(z) V^T over the eigenvectors z of the
+// D x D Hessian in the singular values, H_ii = mu + (mu + lam - lam ln J) /
+// s_i^2, H_ij = lam / (s_i s_j), whose clamped form replaces H (H itself
+// when positive definite).  Each mode Q enters Atil as V vec(Q F^nT)
+// vec(Q F^nT)^T times its (clamped) eigenvalue.
+template <int D, typename T>
+__device__ inline void nh_folded_tangent(const T *F, const T *Fn, T mu, T lam, T Vol, bool project, T *At) {
+  constexpr int n = D * D;
+  constexpr int ns = n * (n + 1) / 2;
+  T W[D * D], Vv[D * D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      T c = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) c += F[k * D + a] * F[k * D + b];
+      W[a * D + b] = c;
+    }
+  jacobi_eig<D, T>(W, Vv);
+  T sg[D], isg[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const T e = W[i * D + i];
+    sg[i] = sqrt(e > T(0) ? e : T(0));
+    isg[i] = sg[i] > T(0) ? T(1) / sg[i] : T(0);
+  }
+  const T lnJ = log(det<D, T>(F));
+  // U = F V S^-1 and g_j = F^n v_j, both column-major by mode: U[a*D+i] = (u_i)_a
+  T U[D * D], g[D * D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      T fu = T(0), fg = T(0);
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        fu += F[a * D + k] * Vv[k * D + i];
+        fg += Fn[a * D + k] * Vv[k * D + i];
+      }
+      U[a * D + i] = fu * isg[i];
+      g[a * D + i] = fg;
+    }
+#pragma unroll
+  for (int k = 0; k < ns; ++k) At[k] = T(0);
+  const T c0 = lam * lnJ - mu;
+  const T rs2 = T(0.70710678118654752440);
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = i + 1; j < D; ++j) {
+      const T iss = isg[i] * isg[j];
+      T lt = mu + c0 * iss, lf = mu - c0 * iss;
+      if (project) {
+        lt = lt > T(0) ? lt : T(0);
+        lf = lf > T(0) ? lf : T(0);
+      }
+      T wt[n], wf[n];
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+          const T x = U[a * D + i] * g[b * D + j], y = U[a * D + j] * g[b * D + i];
+          wt[a * D + b] = rs2 * (x - y);
+          wf[a * D + b] = rs2 * (x + y);
+        }
+#pragma unroll
+      for (int r = 0; r < n; ++r)
+#pragma unroll
+        for (int c = r; c < n; ++c) At[sym_index<n>(r, c)] += lt * wt[r] * wt[c] + lf * wf[r] * wf[c];
+    }
+  // scaling block
+  T H[D * D];
+  const T cd = mu + lam - lam * lnJ;
+#pragma unroll
+  for (int i = 0; i < D; ++i)
+#pragma unroll
+    for (int j = 0; j < D; ++j) H[i * D + j] = (i == j) ? mu + cd * isg[i] * isg[i] : lam * isg[i] * isg[j];
+  if (project && !chol_pd<D, T>(H)) {
+    T Z[D * D];
+    jacobi_eig<D, T>(H, Z);
+    T h[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) h[k] = H[k * D + k] > T(0) ? H[k * D + k] : T(0);
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        T v = T(0);
+#pragma unroll
+        for (int k = 0; k < D; ++k) v += Z[i * D + k] * h[k] * Z[j * D + k];
+        H[i * D + j] = v;
+      }
+  }
+  // Atil += sum_ij H_ij s_i s_j^T with s_i = vec(u_i g_i^T), one i at a time
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    T si[n], ti[n];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        si[a * D + b] = U[a * D + i] * g[b * D + i];
+        T tv = T(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) tv += H[i * D + j] * U[a * D + j] * g[b * D + j];
+        ti[a * D + b] = tv;
+      }
+#pragma unroll
+    for (int r = 0; r < n; ++r)
+#pragma unroll
+      for (int c = r; c < n; ++c) At[sym_index<n>(r, c)] += si[r] * ti[c];
+  }
+#pragma unroll
+  for (int k = 0; k < ns; ++k) At[k] *= Vol;
+}
+
+
 // ---------------------------------------------------------------- reductions
 __device__ inline double wave_sum(double v) {
 #pragma unroll

@@ -803,11 +803,12 @@ __global__ void __launch_bounds__(kBlock) k_solve_begin(const DomDesc *dd, doubl
 // ====================================================================== gradient + Hessian
 // Per particle at the iterate u: F = (I + sum u_i gradN_i^T) F^n and P(F) in
 // FP64; the gradient V P F^nT gradN_i is scattered (FP64).  The particle's
-// tangent A = dP/dF (PSD-projected when asked) is evaluated in the bulk type
-// TB, folded with F^n and V, Atil = V C^T A C with C: G -> G F^n, stored
-// packed, and its contribution to the Jacobi diagonal is scattered.
+// tangent A = dP/dF (PSD-projected when asked), folded with F^n and V,
+// Atil = V C^T A C with C: G -> G F^n, is evaluated in the bulk type TB from
+// the analytic eigensystem of the Neo-Hookean Hessian, stored packed, and
+// its contribution to the Jacobi diagonal is scattered.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int project, int *err) {
+__global__ void __launch_bounds__(kBlock, 2) k_grad_hess(const DomDesc *dd, int project, int *err) {
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
@@ -939,45 +940,15 @@ __global__ void __launch_bounds__(kBlock) k_grad_hess(const DomDesc *dd, int pro
     }
     TB At[ns];
     {
-      TB Fb[n], Fnb[n], A[n * n];
+      TB Fb[n], Fnb[n];
 #pragma unroll
       for (int k = 0; k < n; ++k) {
         Fb[k] = (TB)Fc[k];
         Fnb[k] = (TB)Fn[k];
       }
-      nh_stress<D, TB>(Fb, (TB)mu, (TB)lam, nullptr, A);
-      // positive definite tangents (the common case) skip the eigensolve
-      if (project && !chol_pd<n, TB>(A)) psd_project<n, TB>(A);
-      // Atil[(ab),(ce)] = V sum_z Q[(ab),(cz)] F_ez with Q[(ab),(cz)] =
-      // sum_y F_by A[(ay),(cz)], one (a, c) block of A at a time; blocks with
-      // c < a hold only the lower triangle, which the packed form omits.
-      const TB Vb = (TB)V;
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = a; c < D; ++c) {
-          TB Q[D * D];
-#pragma unroll
-          for (int b = 0; b < D; ++b)
-#pragma unroll
-            for (int z = 0; z < D; ++z) {
-              TB tv = TB(0);
-#pragma unroll
-              for (int y = 0; y < D; ++y) tv += Fnb[b * D + y] * A[(a * D + y) * n + c * D + z];
-              Q[b * D + z] = tv;
-            }
-#pragma unroll
-          for (int b = 0; b < D; ++b)
-#pragma unroll
-            for (int e = 0; e < D; ++e) {
-              const int rr = a * D + b, cc = c * D + e;
-              if (cc < rr) continue;
-              TB tv = TB(0);
-#pragma unroll
-              for (int z = 0; z < D; ++z) tv += Q[b * D + z] * Fnb[e * D + z];
-              At[sym_index<n>(rr, cc)] = Vb * tv;
-            }
-        }
+      // folded (and, when asked, PSD-projected) tangent from the analytic
+      // eigensystem of the Neo-Hookean Hessian
+      nh_folded_tangent<D, TB>(Fb, Fnb, (TB)mu, (TB)lam, (TB)V, project != 0, At);
 #pragma unroll
       for (int k = 0; k < ns; ++k) gstore(Atil, k * cap + p, At[k]);
     }
