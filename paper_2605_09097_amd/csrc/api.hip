@@ -113,6 +113,8 @@ struct osmpm_domain {
   int nk = 0;
   int *key = nullptr, *count = nullptr, *cell_start = nullptr, *cursor = nullptr, *perm = nullptr, *lperm = nullptr;
   int *tcount = nullptr;
+  TileSlot *tl = nullptr;  // work lists (see DomDesc)
+  int *nlist = nullptr, *ncnt = nullptr, *lcnt = nullptr;
   int n_mat = 0;
   double *mu = nullptr, *lam = nullptr;
   double m_ref = 1.0, tau = 0.0;
@@ -480,6 +482,10 @@ DomDesc make_desc(const osmpm_domain *d) {
   x.perm = d->perm;
   x.lperm = d->lperm;
   x.tcount = d->tcount;
+  x.tl = d->tl;
+  x.nlist = d->nlist;
+  x.ncnt = d->ncnt;
+  x.lcnt = d->lcnt;
   x.mu = d->mu;
   x.lam = d->lam;
   x.m = d->m;
@@ -633,6 +639,19 @@ const CgState *h_cg(const osmpm_batch *G, int s) {
 const int *h_int(const osmpm_batch *G, size_t off) { return reinterpret_cast<const int *>(G->h_status + off); }
 const double *h_res(const osmpm_batch *G) { return reinterpret_cast<const double *>(G->h_status + G->off_res); }
 
+// ---------------------------------------------------------------- work lists
+// Live-tile list (from the bin offsets) and active-node list (from the node
+// masses) of every active domain of side s; the CG launches map their
+// workgroups onto them.
+void build_tile_list(osmpm_batch *G, int s) {
+  launch(G->c, -1, 0, -1, k_tile_list, dim3(1, G->n), dim3(1024), 0, (const DomDesc *)G->dd[s]);
+}
+void build_node_list(osmpm_batch *G, int s) {
+  const Ext &E = G->ext[s];
+  launch(G->c, -1, 0, -1, k_node_count, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
+  launch(G->c, -1, 0, -1, k_node_list, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
+}
+
 // ---------------------------------------------------------------- sort + P2G + G2P
 // Stable counting sort of every active domain's particles by tile-major bin
 // key, gathered into the other particle buffer; P2G targets are cleared.
@@ -649,6 +668,7 @@ void sort_side(osmpm_batch *G, int s, int want_q) {
   launch(c, -1, 0, -1, k_tile_sum, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_tile_scan, dim3(1, n), dim3(1024), 0, dd);
   launch(c, -1, 0, -1, k_cell_scan, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
+  build_tile_list(G, s);
   launch(c, -1, 0, -1, k_scatter, dim3(pb, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_cellsort, dim3(blocks_for(E.max_nk), n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_slot_layout, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
@@ -673,6 +693,7 @@ void p2g_side(osmpm_batch *G, int s, bool want_qall) {
     launch(c, OSMPM_K_P2G, active_bytes(G, s, OSMPM_K_P2G), -1, k_p2g<D, TB, false>, dim3(E.tile_blocks, G->n),
            dim3(kBlock), E.lds_p2g, (const DomDesc *)G->dd[s], G->err);
   launch(c, -1, 0, -1, k_p2g_final<D>, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
+  build_node_list(G, s);
   for (int i = 0; i < G->n; ++i)
     if (G->act[s][i] == 1) G->dom[s][i]->have_p2g = true;
   if (c->prof && read_status(G) == OSMPM_OK && !c->pending.empty()) {
@@ -729,10 +750,22 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   // Split CG scalars (k_cg_reduce after each iteration) when the fused form's
   // pass of every workgroup over all partial sums would read more than a
   // dependent launch costs (measured: the 3D fold gains, a 64-scene 2D batch
-  // at ~60 MB does not): sum over domains of 24 B x workgroups^2.
+  // at ~60 MB does not): sum over domains of 24 B x workgroups^2, with the
+  // working workgroups estimated from the live tiles and active nodes of the
+  // last status read (the tile blocks before any).
   double partial_reads = 0.0;
+  const SolveState *hss = h_ss(G, s);
   for (int i = 0; i < n; ++i)
-    if (G->act[s][i] == 1) partial_reads += 24.0 * (double)G->dom[s][i]->tg.nblocks * G->dom[s][i]->tg.nblocks;
+    if (G->act[s][i] == 1) {
+      const osmpm_domain *d = G->dom[s][i];
+      double w = d->tg.nblocks;
+      if (hss[i].n_tiles_live > 0) {
+        const double nt8 = 8.0 * ((hss[i].n_tiles_live + 7) / 8);
+        const double nown = std::ceil((double)hss[i].n_active * d->D / kBlock);
+        w = std::min<double>(d->tg.nblocks, std::max(nt8, nown));
+      }
+      partial_reads += 24.0 * w * w;
+    }
   const int split = c->cg_split >= 0 ? c->cg_split : (partial_reads > 128e6 ? 1 : 0);
   std::vector<int> hint(n), prev_phase(n, kPhaseCgInit), prev_iter(n, 0), prev_total(n, 0);
   for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
@@ -1272,6 +1305,9 @@ osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const 
   const int n = G->n, nd = d->g.nn * d->D;
   const dim3 blk(kBlock);
   set_active(G, s, std::vector<int>(n, 1));
+  // the work lists of the restored binning and grid
+  build_tile_list(G, s);
+  build_node_list(G, s);
   launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, kBufVbc);
   HIP_TRY(c, hipMemcpyAsync(d->u, u_tape, (size_t)nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt);
@@ -1756,6 +1792,10 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->cell_start, (size_t)d->nk + 1);
   if (!s) s = dalloc(d, &d->cursor, (size_t)d->nk + 1);
   if (!s) s = dalloc(d, &d->tcount, (size_t)d->tg.ntiles + 1);
+  if (!s) s = dalloc(d, &d->tl, (size_t)d->tg.nblocks);
+  if (!s) s = dalloc(d, &d->nlist, (size_t)nn);
+  if (!s) s = dalloc(d, &d->ncnt, (size_t)blocks_for(nn));
+  if (!s) s = dalloc(d, &d->lcnt, 2);
   if (!s) s = dalloc(d, &d->m, nn);
   if (!s) s = dalloc(d, &d->vn, nd);
   if (!s) s = dalloc(d, &d->u, nd);
@@ -1794,6 +1834,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
     if (!s && hipMemsetAsync(p, 0, bytes, ctx->stream) != hipSuccess) s = OSMPM_E_DEVICE;
   };
   zero(d->d_cur, sizeof(int));
+  zero(d->lcnt, 2 * sizeof(int));
   zero(d->vbc, nd * sizeof(double));
   zero(d->u, nd * sizeof(double));
   zero(d->m, nn * sizeof(double));

@@ -386,6 +386,111 @@ __global__ void __launch_bounds__(kBlock) k_copy_state(const DomDesc *dd, int to
   b.flags[p] = a.flags[p];
 }
 
+// ====================================================================== work lists
+// Live-tile list of a domain from its bin offsets (after a binning, or after
+// a stored binning is restored): the tiles holding particles, in tile order,
+// with their particle ranges, dealt to the workgroup slots of a tile launch
+// so that each of the 8 XCDs (to which workgroups are dispatched round-robin)
+// takes a contiguous band of tiles: slot b takes list entry
+// (b mod 8) * per + b / 8, per = ceil(live / 8); the other slots get
+// {-1, 0, 0, 0}.  One workgroup of 1024 threads per domain.
+__global__ void __launch_bounds__(1024) k_tile_list(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  __shared__ int wsum[16];
+  const int nt = dm.tg.ntiles, tvol = dm.tg.tvol, nb = dm.tg.nblocks;
+  const int *cs = dm.cell_start;
+  TileSlot *tl = dm.tl;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int c = 0;
+  for (int t = tid; t < nt; t += 1024) c += (cs[(int64_t)(t + 1) * tvol] > cs[(int64_t)t * tvol]) ? 1 : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if (lane == 0) wsum[w] = c;
+  __syncthreads();
+  int live = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) live += wsum[k];
+  __syncthreads();
+  const int per = (live + 7) >> 3;
+  for (int b = tid; b < nb; b += 1024) {
+    const int j = (b & 7) * per + (b >> 3);
+    if (!((b >> 3) < per && j < live)) tl[b] = TileSlot{-1, 0, 0, 0};
+  }
+  int carry = 0;
+  for (int base = 0; base < nt; base += 1024) {
+    const int t = base + tid;
+    int p0 = 0, p1 = 0;
+    if (t < nt) {
+      p0 = cs[(int64_t)t * tvol];
+      p1 = cs[(int64_t)(t + 1) * tvol];
+    }
+    const bool f = p1 > p0;
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) wsum[w] = (int)__popcll(bal);
+    __syncthreads();
+    int woff = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int v = wsum[k];
+      woff += (k < w) ? v : 0;
+      tot += v;
+    }
+    if (f) {
+      const int j = carry + woff + (int)__popcll(bal & ((1ull << lane) - 1ull));
+      tl[(j % per) * 8 + j / per] = TileSlot{t, p0, p1, 0};
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    dm.lcnt[0] = live;
+    dm.ss->n_tiles_live = live;
+  }
+}
+
+// Active nodes (m > 0) per block of 256 nodes.
+__global__ void __launch_bounds__(kBlock) k_node_count(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int nn = dm.g.nn;
+  if ((int)blockIdx.x >= (nn + kBlock - 1) / kBlock) return;
+  __shared__ int wc[kBlock / 64];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool f = i < nn && dm.m[i] > 0.0;
+  const unsigned long long bal = __ballot(f);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) dm.ncnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// Active-node list in node order: each block of 256 nodes writes its active
+// nodes at the sum of the counts of the blocks before it; the last block
+// stores the total.
+__global__ void __launch_bounds__(kBlock) k_node_list(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int nn = dm.g.nn;
+  const int nbn = (nn + kBlock - 1) / kBlock;
+  if ((int)blockIdx.x >= nbn) return;
+  __shared__ int red[kBlock / 64];
+  __shared__ int wc[kBlock / 64];
+  int sp = 0;
+  for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) sp += dm.ncnt[j];
+  const int off = block_sum_int(sp, red);
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool f = i < nn && dm.m[i] > 0.0;
+  const unsigned long long bal = __ballot(f);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wc[w] = (int)__popcll(bal);
+  __syncthreads();
+  int woff = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) woff += (k < w) ? wc[k] : 0;
+  if (f) dm.nlist[off + woff + (int)__popcll(bal & ((1ull << lane) - 1ull))] = i;
+  if ((int)blockIdx.x == nbn - 1 && threadIdx.x == 0) dm.lcnt[1] = off + wc[0] + wc[1] + wc[2] + wc[3];
+}
+
 // ====================================================================== tiles
 // Particle range of tile t and its node-region origin.  Returns false for
 // padding blocks.
@@ -1150,6 +1255,18 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd) {
   }
 }
 
+// Workgroups of a CG launch that do work: one per live-tile slot (whole
+// bands of 8) and enough for the active DOFs, at least one, at most the
+// launch's tile blocks.  The lists do not change during a solve, so every
+// launch of it (and the split-mode reduction) derives the same count.
+__device__ inline int cg_work_blocks(int live_tiles, int active_dofs, int nblocks) {
+  int nw = ((live_tiles + 7) >> 3) * 8;
+  const int nown = (active_dofs + kBlock - 1) / kBlock;
+  nw = nw > nown ? nw : nown;
+  nw = nw > 1 ? nw : 1;
+  return nw < nblocks ? nw : nblocks;
+}
+
 // Scalars of CG launch i from the partial sums (sg, sd, sr) of launch i - 1:
 // the stop test on |r_(i-1)| <= rtol |r_0| (or i - 1 = max_cg), beta_(i-1)
 // and alpha_(i-1); with write set, the state the next decision needs.
@@ -1225,7 +1342,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   // them never waits for this wave's LDS atomics as well.
   const TileGeom tg = dm.tg;
   CgState *const S = dm.cg;
-  const int *const pactive = dm.active, *const pcur = dm.cur, *const pcs = dm.cell_start;
+  const int *const pactive = dm.active, *const pcur = dm.cur, *const plc = dm.lcnt, *const pnl = dm.nlist;
+  const TileSlot *const ptl = dm.tl;
   const uint8_t *const fr = dm.fr;
   const double *const gm = dm.m;
   const TB *const Atil = static_cast<const TB *>(dm.Atil);
@@ -1240,28 +1358,36 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   const int pstride = dm.pstride;
   const int64_t cap = dm.cap;
   const GridDev g = dm.g;
-  asm volatile("" ::"s"(S), "s"(pactive), "s"(pcur), "s"(pcs), "s"(fr), "s"(gm), "s"(Atil), "s"(dg), "s"(cr0),
+  asm volatile("" ::"s"(S), "s"(pactive), "s"(pcur), "s"(plc), "s"(pnl), "s"(ptl), "s"(fr), "s"(gm), "s"(Atil), "s"(dg), "s"(cr0),
                "s"(cs1), "s"(cw0), "s"(cw2), "s"(cu), "s"(cdel), "s"(part_cg), "s"(x0), "s"(x1), "s"(ndof),
                "s"(pstride), "s"(cap), "s"(tg.nblocks), "s"(tg.tvol), "s"(g.n[0]), "s"(g.n[2]), "s"(g.origin[0]),
                "s"(g.inv_dx));
-  const int t = tile_of_block(tg, blockIdx.x);
-  const bool t_in = (int)blockIdx.x < tg.nblocks && t < tg.ntiles;
-  const int tc = t < tg.ntiles ? t : tg.ntiles - 1;  // a valid tile (ntiles >= 1)
+  // the workgroup's slot of the live-tile list and its first active DOF are
+  // read with the flags (indices clamped into the arrays; used only when valid)
+  const int tid = threadIdx.x;
+  const int bq = (int)blockIdx.x < tg.nblocks ? (int)blockIdx.x : tg.nblocks - 1;
+  const int j0 = (int)blockIdx.x * kBlock + tid;
   const int act = uload(pactive);
   const int sdone = uload(&S->done);
   const int i = uload(&S->k_at[q]);
   const int cur = uload(pcur);
-  const int tp0 = uload(pcs + (int64_t)tc * tg.tvol);
-  const int tp1 = uload(pcs + (int64_t)(tc + 1) * tg.tvol);
+  const int ntl = uload(plc);
+  const int nnl = uload(plc + 1);
+  const int *const te4 = reinterpret_cast<const int *>(ptl + bq);  // {tile, p0, p1, pad}, 16-byte aligned
+  const int te_t = uload(te4);
+  const int te_p0 = uload(te4 + 1);
+  const int te_p1 = uload(te4 + 2);
+  const int nd0 = gload(pnl, j0 / D < g.nn ? j0 / D : g.nn - 1);
   const double s_rr0 = gload(&S->rr0, 0), s_gam0 = gload(&S->gam[0], 0), s_gam1 = gload(&S->gam[1], 0);
   const double s_alp0 = gload(&S->alp[0], 0), s_alp1 = gload(&S->alp[1], 0);
   const double s_alpha_n = gload(&S->alpha_n, 0), s_beta_n = gload(&S->beta_n, 0);
-  asm volatile("" ::"s"(act), "s"(sdone), "s"(i), "s"(cur), "s"(tp0), "s"(tp1));
-  if (!act || sdone || (int)blockIdx.x >= tg.nblocks) return;
+  asm volatile("" ::"s"(act), "s"(sdone), "s"(i), "s"(cur), "s"(ntl), "s"(nnl), "s"(te_t), "s"(te_p0), "s"(te_p1),
+               "v"(nd0));
+  const int ndl = nnl * D;  // active DOFs
+  const int nbt = cg_work_blocks(ntl, ndl, tg.nblocks);
+  if (!act || sdone || (int)blockIdx.x >= nbt) return;
   extern __shared__ double lds[];
   __shared__ double red[12];
-  const int tid = threadIdx.x;
-  const int nbt = tg.nblocks;
   const int i2 = i & 1, i3 = i % 3;
   const TB *const r_old = static_cast<const TB *>(i2 ? cr0 : cr1);  // r_(i-1)
   TB *const r_new = static_cast<TB *>(i2 ? cr1 : cr0);              // r_i
@@ -1283,9 +1409,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
     alpha = s_alpha_n;
     beta = s_beta_n;
   }
-  int p0 = tp0, p1 = tp1, org[3] = {0, 0, 0};
-  if (t_in) tile_origin(tg, t, org);
-  const bool tile_ok = t_in && p0 < p1;
+  const int p0 = te_p0, p1 = te_p1;
+  int org[3] = {0, 0, 0};
+  const bool tile_ok = te_t >= 0 && p0 < p1;
+  if (tile_ok) tile_origin(tg, te_t, org);
   const int nreg = tg.nreg;
   // --- independent loads
   double sg = 0.0, sd = 0.0, sr = 0.0;
@@ -1320,12 +1447,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
 #pragma unroll
     for (int k = 0; k < ns; ++k) At[k] = gload(Atil, k * cap + pp0);
   }
-  // first owned DOF of the thread (usually its only one)
-  const int k0 = blockIdx.x * kBlock + tid;
+  // first owned DOF of the thread (usually its only one): active DOF j0
+  const int k0 = (j0 < ndl) ? nd0 * D + j0 % D : -1;
   uint8_t of = 0;
   TB orr = TB(0), ow = TB(0), os = TB(0), od = TB(1), ou = TB(0), op = TB(0), odl = TB(0);
   double om = 0.0;
-  if (k0 < ndof) {
+  if (k0 >= 0) {
     of = gload(fr, k0);
     if (of) {
       orr = gload(i == 0 ? (const TB *)r_new : r_old, k0);
@@ -1363,9 +1490,11 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   }
   const double mdt = 1.0 / (dt * dt);
   double gsum = 0.0, dsum = 0.0, rsum = 0.0;
-  // --- owned DOFs
-  for (int k = k0; k < ndof; k += nbt * kBlock) {
-    const bool first = (k == k0);
+  // --- owned DOFs: the active DOFs, strided over the working workgroups
+  // (only active DOFs ever receive products, so only they need clearing)
+  for (int j = j0; j < ndl; j += nbt * kBlock) {
+    const bool first = (j == j0);
+    const int k = first ? k0 : gload(pnl, j / D) * D + j % D;
     gstore(w_clr, k, TB(0));
     if (!(first ? of : gload(fr, k))) continue;
     TB r, u;
@@ -1531,7 +1660,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_reduce(const DomDesc *dd, int q, 
   __shared__ double red[12];
   const int tid = threadIdx.x;
   const int i = S->k_at[q];
-  const int nbt = dm.tg.nblocks;
+  const int nbt = cg_work_blocks(dm.lcnt[0], dm.lcnt[1] * (dm.ndof / dm.g.nn), dm.tg.nblocks);
   const double *pin = dm.part_cg + (size_t)q * 3 * dm.pstride;
   double sg = 0.0, sd = 0.0, sr = 0.0;
   for (int j = tid; j < nbt; j += kBlock) {

@@ -51,6 +51,7 @@ struct SolveState {
   int converged, ls_failed;
   int newton_iters, cg_iters, ls_halvings;
   int n_active;  // nodes with m > 0 after the last P2G
+  int n_tiles_live;  // tiles holding particles after the last binning
 };
 
 __host__ __device__ inline bool phase_wants_grad(int ph) { return ph == kPhaseGrad || ph == kPhaseStep; }
@@ -73,6 +74,12 @@ struct PartPtrs {
   uint8_t *flags;
 };
 
+// A workgroup slot of a tile launch: the live tile it takes and that tile's
+// particle range (tile -1: none).
+struct alignas(16) TileSlot {
+  int tile, p0, p1, pad;
+};
+
 struct DomDesc {
   GridDev g;
   TileGeom tg;
@@ -88,6 +95,13 @@ struct DomDesc {
   PartPtrs pb[2], st;
   int *key, *count, *cell_start, *cursor, *perm, *lperm;
   int *tcount;  // per-tile bin totals, then tile offsets [ntiles + 1]
+  // Work lists rebuilt after each binning / P2G: tl[b] = {tile, p0, p1, 0} of
+  // the live (particle-holding) tile that workgroup b of a tile launch takes
+  // ({-1, 0, 0, 0}: none), [nblocks]; nlist = active nodes (m > 0) in node
+  // order, [nn]; ncnt = active nodes per block of 256 nodes; lcnt = {live
+  // tiles, active nodes}.
+  TileSlot *tl;
+  int *nlist, *ncnt, *lcnt;
   const double *mu, *lam;
   double *m, *vn, *u, *vbc, *gg;
   int8_t *bcg;
@@ -159,6 +173,9 @@ template <int D, typename TB>
 __global__ void k_cg_init(const DomDesc *dd);
 template <int D, typename TB>
 __global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg, int split);
+__global__ void k_tile_list(const DomDesc *dd);
+__global__ void k_node_count(const DomDesc *dd);
+__global__ void k_node_list(const DomDesc *dd);
 __global__ void k_cg_reduce(const DomDesc *dd, int q, double rtol, int max_cg);
 template <int D, typename TB>
 __global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz);
