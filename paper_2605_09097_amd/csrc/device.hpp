@@ -178,13 +178,7 @@ __device__ inline long long fixed_mass(double N, double mq) {
 }
 
 // ---------------------------------------------------------------- tiles
-__device__ inline int tile_of_block(const TileGeom &tg, int b) {
-  // Consecutive workgroups are dealt round-robin to the 8 XCDs; give each XCD
-  // a contiguous band of tiles so halo nodes stay in one L2.
-  const int per = tg.nblocks >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
+// Origin (lowest base node) of tile t, tiles numbered x fastest.
 __device__ inline void tile_origin(const TileGeom &tg, int t, int *org) {
   org[0] = (t % tg.nt[0]) * tg.T[0];
   org[1] = ((t / tg.nt[0]) % tg.nt[1]) * tg.T[1];

@@ -492,12 +492,16 @@ __global__ void __launch_bounds__(kBlock) k_node_list(const DomDesc *dd) {
 }
 
 // ====================================================================== tiles
-// Particle range of tile t and its node-region origin.  Returns false for
-// padding blocks.
-__device__ inline bool tile_range(const TileGeom &tg, const int *cell_start, int t, int &p0, int &p1, int *org) {
-  if (t >= tg.ntiles) return false;
-  p0 = gload(cell_start, (int64_t)t * tg.tvol);
-  p1 = gload(cell_start, (int64_t)(t + 1) * tg.tvol);
+// The live tile that workgroup b of a tile launch takes (its slot of the
+// live-tile list), its particle range and node-region origin; false for an
+// idle slot, so that workgroups without a tile leave after one load.
+__device__ inline bool tile_slot(const TileSlot *tl, const TileGeom &tg, int b, int &p0, int &p1, int *org) {
+  if (b >= tg.nblocks) return false;
+  const int *e = reinterpret_cast<const int *>(tl + b);
+  const int t = uload(e);
+  p0 = uload(e + 1);
+  p1 = uload(e + 2);
+  if (t < 0 || p0 >= p1) return false;
   tile_origin(tg, t, org);
   return true;
 }
@@ -561,9 +565,8 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   // particle).
   const TileGeom tg = dm.tg;
   const GridDev g = dm.g;
-  const int t = tile_of_block(tg, blockIdx.x);
   int p0, p1, org[3];
-  if (!tile_range(tg, dm.cell_start, t, p0, p1, org) || p0 == p1) return;
+  if (!tile_slot(dm.tl, tg, blockIdx.x, p0, p1, org)) return;
   const PartPtrs P = dm.pb[*dm.cur];
   const double scale = dm.scale;
   double *const gm = dm.m;
@@ -926,9 +929,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_grad_hess(const DomDesc *dd, int 
   if (!act || !phase_wants_grad(phase) || (int)blockIdx.x >= tg.nblocks) return;
   extern __shared__ double lds[];
   const GridDev g = dm.g;
-  const int t = tile_of_block(tg, blockIdx.x);
   int p0, p1, org[3];
-  if (!tile_range(tg, dm.cell_start, t, p0, p1, org) || p0 == p1) return;
+  if (!tile_slot(dm.tl, tg, blockIdx.x, p0, p1, org)) return;
   const PartPtrs &P = dm.pb[cur];
   const int64_t cap = dm.cap;
   const double *const px = P.x;
