@@ -643,12 +643,17 @@ const double *h_res(const osmpm_batch *G) { return reinterpret_cast<const double
 // Live-tile list (from the bin offsets) and active-node list (from the node
 // masses) of every active domain of side s; the CG launches map their
 // workgroups onto them.
+// (After a binning the tile scan builds the tile list, and after a P2G the
+// final P2G pass has the node counts; these rebuild both for a restored
+// binning and grid.)
 void build_tile_list(osmpm_batch *G, int s) {
   launch(G->c, -1, 0, -1, k_tile_list, dim3(1, G->n), dim3(1024), 0, (const DomDesc *)G->dd[s]);
 }
-void build_node_list(osmpm_batch *G, int s) {
+void build_node_list(osmpm_batch *G, int s, bool counted) {
   const Ext &E = G->ext[s];
-  launch(G->c, -1, 0, -1, k_node_count, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
+  if (!counted)
+    launch(G->c, -1, 0, -1, k_node_count, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[s]);
   launch(G->c, -1, 0, -1, k_node_list, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
 }
 
@@ -668,7 +673,6 @@ void sort_side(osmpm_batch *G, int s, int want_q) {
   launch(c, -1, 0, -1, k_tile_sum, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_tile_scan, dim3(1, n), dim3(1024), 0, dd);
   launch(c, -1, 0, -1, k_cell_scan, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
-  build_tile_list(G, s);
   launch(c, -1, 0, -1, k_scatter, dim3(pb, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_cellsort, dim3(blocks_for(E.max_nk), n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_slot_layout, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
@@ -693,7 +697,7 @@ void p2g_side(osmpm_batch *G, int s, bool want_qall) {
     launch(c, OSMPM_K_P2G, active_bytes(G, s, OSMPM_K_P2G), -1, k_p2g<D, TB, false>, dim3(E.tile_blocks, G->n),
            dim3(kBlock), E.lds_p2g, (const DomDesc *)G->dd[s], G->err);
   launch(c, -1, 0, -1, k_p2g_final<D>, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
-  build_node_list(G, s);
+  build_node_list(G, s, true);
   for (int i = 0; i < G->n; ++i)
     if (G->act[s][i] == 1) G->dom[s][i]->have_p2g = true;
   if (c->prof && read_status(G) == OSMPM_OK && !c->pending.empty()) {
@@ -743,8 +747,8 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
            (int)o->project_psd, G->err);
     launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
            o->gravity[2]);
-    launch(c, -1, 0, -1, k_newton_check, dim3(1, n), blk, 0, dd, o->newton_rtol, o->newton_atol, (int)o->max_newton);
-    launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd);
+    launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, 1, o->newton_rtol, o->newton_atol,
+           (int)o->max_newton);
   };
   grad_phase();
   // Split CG scalars (k_cg_reduce after each iteration) when the fused form's
@@ -804,7 +808,6 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
       launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
              o->gravity[0], o->gravity[1], o->gravity[2]);
       launch(c, -1, 0, -1, k_ls_check, dim3(1, n), blk, 0, dd, (int)o->max_ls);
-      launch(c, -1, 0, -1, k_newton_step<TB>, dim3(E.node_blocks, n), blk, 0, dd);
       grad_phase();
     };
     if (c->graphs && !c->prof) {
@@ -1307,7 +1310,7 @@ osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const 
   set_active(G, s, std::vector<int>(n, 1));
   // the work lists of the restored binning and grid
   build_tile_list(G, s);
-  build_node_list(G, s);
+  build_node_list(G, s, false);
   launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, kBufVbc);
   HIP_TRY(c, hipMemcpyAsync(d->u, u_tape, (size_t)nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt);
@@ -1315,7 +1318,7 @@ osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const 
   launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
          o->gravity[2]);
   launch(c, -1, 0, -1, k_adj_set_rhs, dim3(E.node_blocks, n), blk, 0, dd, ubar);
-  launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd);
+  launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, 0, 0.0, 0.0, 0);
   const int max_cg = 20000, chunk = 16;
   osmpm_status st;
   for (int launched = 0;; launched += chunk) {

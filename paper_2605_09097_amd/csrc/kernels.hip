@@ -150,6 +150,123 @@ __device__ inline int block_sum_int(int v, int *lds4) {
   return lds4[0] + lds4[1] + lds4[2] + lds4[3];
 }
 
+// ====================================================================== work lists
+// Live-tile list of a domain from its bin offsets (after a binning, or after
+// a stored binning is restored): the tiles holding particles, in tile order,
+// with their particle ranges, dealt to the workgroup slots of a tile launch
+// so that each of the 8 XCDs (to which workgroups are dispatched round-robin)
+// takes a contiguous band of tiles: slot b takes list entry
+// (b mod 8) * per + b / 8, per = ceil(live / 8); the other slots get
+// {-1, 0, 0, 0}.  The body, for one workgroup of 1024 threads per domain;
+// range(t, p0, p1) gives tile t's particle range.
+template <typename Range>
+__device__ inline void tile_slots(const DomDesc &dm, Range range) {
+  __shared__ int wsum[16];
+  const int nt = dm.tg.ntiles, nb = dm.tg.nblocks;
+  TileSlot *tl = dm.tl;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int c = 0;
+  for (int t = tid; t < nt; t += 1024) {
+    int p0, p1;
+    range(t, p0, p1);
+    c += (p1 > p0) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if (lane == 0) wsum[w] = c;
+  __syncthreads();
+  int live = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) live += wsum[k];
+  __syncthreads();
+  const int per = (live + 7) >> 3;
+  for (int b = tid; b < nb; b += 1024) {
+    const int j = (b & 7) * per + (b >> 3);
+    if (!((b >> 3) < per && j < live)) tl[b] = TileSlot{-1, 0, 0, 0};
+  }
+  int carry = 0;
+  for (int base = 0; base < nt; base += 1024) {
+    const int t = base + tid;
+    int p0 = 0, p1 = 0;
+    if (t < nt) range(t, p0, p1);
+    const bool f = p1 > p0;
+    const unsigned long long bal = __ballot(f);
+    if (lane == 0) wsum[w] = (int)__popcll(bal);
+    __syncthreads();
+    int woff = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int v = wsum[k];
+      woff += (k < w) ? v : 0;
+      tot += v;
+    }
+    if (f) {
+      const int j = carry + woff + (int)__popcll(bal & ((1ull << lane) - 1ull));
+      tl[(j % per) * 8 + j / per] = TileSlot{t, p0, p1, 0};
+    }
+    carry += tot;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    dm.lcnt[0] = live;
+    dm.ss->n_tiles_live = live;
+  }
+}
+
+// The list from the bin offsets of a restored binning.
+__global__ void __launch_bounds__(1024) k_tile_list(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int *cs = dm.cell_start;
+  const int tvol = dm.tg.tvol;
+  tile_slots(dm, [&](int t, int &p0, int &p1) {
+    p0 = cs[(int64_t)t * tvol];
+    p1 = cs[(int64_t)(t + 1) * tvol];
+  });
+}
+
+// Active nodes (m > 0) per block of 256 nodes.
+__global__ void __launch_bounds__(kBlock) k_node_count(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int nn = dm.g.nn;
+  if ((int)blockIdx.x >= (nn + kBlock - 1) / kBlock) return;
+  __shared__ int wc[kBlock / 64];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool f = i < nn && dm.m[i] > 0.0;
+  const unsigned long long bal = __ballot(f);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) dm.ncnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+// Active-node list in node order: each block of 256 nodes writes its active
+// nodes at the sum of the counts of the blocks before it; the last block
+// stores the total.
+__global__ void __launch_bounds__(kBlock) k_node_list(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int nn = dm.g.nn;
+  const int nbn = (nn + kBlock - 1) / kBlock;
+  if ((int)blockIdx.x >= nbn) return;
+  __shared__ int red[kBlock / 64];
+  __shared__ int wc[kBlock / 64];
+  int sp = 0;
+  for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) sp += dm.ncnt[j];
+  const int off = block_sum_int(sp, red);
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool f = i < nn && dm.m[i] > 0.0;
+  const unsigned long long bal = __ballot(f);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wc[w] = (int)__popcll(bal);
+  __syncthreads();
+  int woff = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) woff += (k < w) ? wc[k] : 0;
+  if (f) dm.nlist[off + woff + (int)__popcll(bal & ((1ull << lane) - 1ull))] = i;
+  if ((int)blockIdx.x == nbn - 1 && threadIdx.x == 0) dm.lcnt[1] = off + wc[0] + wc[1] + wc[2] + wc[3];
+}
+
 __global__ void __launch_bounds__(kBlock) k_tile_sum(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active || (int)blockIdx.x >= dm.tg.ntiles) return;
@@ -215,6 +332,12 @@ __global__ void __launch_bounds__(1024) k_tile_scan(const DomDesc *dd) {
     tc[nt] = carry;
     dm.cell_start[dm.nk] = carry;
   }
+  __syncthreads();
+  // the live-tile list from the tile offsets just formed
+  tile_slots(dm, [&](int t, int &p0, int &p1) {
+    p0 = tc[t];
+    p1 = tc[t + 1];
+  });
 }
 
 // Exclusive scan of one tile's bins, offset by the tile's
@@ -384,111 +507,6 @@ __global__ void __launch_bounds__(kBlock) k_copy_state(const DomDesc *dd, int to
   b.mat[p] = a.mat[p];
   b.id[p] = a.id[p];
   b.flags[p] = a.flags[p];
-}
-
-// ====================================================================== work lists
-// Live-tile list of a domain from its bin offsets (after a binning, or after
-// a stored binning is restored): the tiles holding particles, in tile order,
-// with their particle ranges, dealt to the workgroup slots of a tile launch
-// so that each of the 8 XCDs (to which workgroups are dispatched round-robin)
-// takes a contiguous band of tiles: slot b takes list entry
-// (b mod 8) * per + b / 8, per = ceil(live / 8); the other slots get
-// {-1, 0, 0, 0}.  One workgroup of 1024 threads per domain.
-__global__ void __launch_bounds__(1024) k_tile_list(const DomDesc *dd) {
-  const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active) return;
-  __shared__ int wsum[16];
-  const int nt = dm.tg.ntiles, tvol = dm.tg.tvol, nb = dm.tg.nblocks;
-  const int *cs = dm.cell_start;
-  TileSlot *tl = dm.tl;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int c = 0;
-  for (int t = tid; t < nt; t += 1024) c += (cs[(int64_t)(t + 1) * tvol] > cs[(int64_t)t * tvol]) ? 1 : 0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-  if (lane == 0) wsum[w] = c;
-  __syncthreads();
-  int live = 0;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) live += wsum[k];
-  __syncthreads();
-  const int per = (live + 7) >> 3;
-  for (int b = tid; b < nb; b += 1024) {
-    const int j = (b & 7) * per + (b >> 3);
-    if (!((b >> 3) < per && j < live)) tl[b] = TileSlot{-1, 0, 0, 0};
-  }
-  int carry = 0;
-  for (int base = 0; base < nt; base += 1024) {
-    const int t = base + tid;
-    int p0 = 0, p1 = 0;
-    if (t < nt) {
-      p0 = cs[(int64_t)t * tvol];
-      p1 = cs[(int64_t)(t + 1) * tvol];
-    }
-    const bool f = p1 > p0;
-    const unsigned long long bal = __ballot(f);
-    if (lane == 0) wsum[w] = (int)__popcll(bal);
-    __syncthreads();
-    int woff = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int v = wsum[k];
-      woff += (k < w) ? v : 0;
-      tot += v;
-    }
-    if (f) {
-      const int j = carry + woff + (int)__popcll(bal & ((1ull << lane) - 1ull));
-      tl[(j % per) * 8 + j / per] = TileSlot{t, p0, p1, 0};
-    }
-    carry += tot;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    dm.lcnt[0] = live;
-    dm.ss->n_tiles_live = live;
-  }
-}
-
-// Active nodes (m > 0) per block of 256 nodes.
-__global__ void __launch_bounds__(kBlock) k_node_count(const DomDesc *dd) {
-  const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active) return;
-  const int nn = dm.g.nn;
-  if ((int)blockIdx.x >= (nn + kBlock - 1) / kBlock) return;
-  __shared__ int wc[kBlock / 64];
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const bool f = i < nn && dm.m[i] > 0.0;
-  const unsigned long long bal = __ballot(f);
-  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(bal);
-  __syncthreads();
-  if (threadIdx.x == 0) dm.ncnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
-}
-
-// Active-node list in node order: each block of 256 nodes writes its active
-// nodes at the sum of the counts of the blocks before it; the last block
-// stores the total.
-__global__ void __launch_bounds__(kBlock) k_node_list(const DomDesc *dd) {
-  const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active) return;
-  const int nn = dm.g.nn;
-  const int nbn = (nn + kBlock - 1) / kBlock;
-  if ((int)blockIdx.x >= nbn) return;
-  __shared__ int red[kBlock / 64];
-  __shared__ int wc[kBlock / 64];
-  int sp = 0;
-  for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) sp += dm.ncnt[j];
-  const int off = block_sum_int(sp, red);
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  const bool f = i < nn && dm.m[i] > 0.0;
-  const unsigned long long bal = __ballot(f);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) wc[w] = (int)__popcll(bal);
-  __syncthreads();
-  int woff = 0;
-#pragma unroll
-  for (int k = 0; k < kBlock / 64; ++k) woff += (k < w) ? wc[k] : 0;
-  if (f) dm.nlist[off + woff + (int)__popcll(bal & ((1ull << lane) - 1ull))] = i;
-  if ((int)blockIdx.x == nbn - 1 && threadIdx.x == 0) dm.lcnt[1] = off + wc[0] + wc[1] + wc[2] + wc[3];
 }
 
 // ====================================================================== tiles
@@ -694,6 +712,12 @@ __global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
   const double m = (i < dm.g.nn) ? dm.m[i] : 0.0;
   const unsigned long long act = __ballot(m > 0.0);
   if ((threadIdx.x & 63) == 0 && act) atomicAdd(&dm.ss->n_active, (int)__popcll(act));
+  // active nodes of this block of 256 nodes, for the active-node list
+  __shared__ int wc[kBlock / 64];
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(act);
+  __syncthreads();
+  if (threadIdx.x == 0 && (int)blockIdx.x < (dm.g.nn + kBlock - 1) / kBlock)
+    dm.ncnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
   if (i >= dm.g.nn) return;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -925,8 +949,12 @@ __global__ void __launch_bounds__(kBlock, 2) k_grad_hess(const DomDesc *dd, int 
   const int act = uload(dm.active);
   const int phase = uload(&dm.ss->phase);
   const int cur = uload(dm.cur);
+  const double salpha = gload(&dm.ss->alpha, 0);
   const TileGeom tg = dm.tg;
   if (!act || !phase_wants_grad(phase) || (int)blockIdx.x >= tg.nblocks) return;
+  // an accepted line-search step is applied here as u + alpha del (the node
+  // kernel that follows stores it, with the same fused multiply-add)
+  const bool step = phase == kPhaseStep;
   extern __shared__ double lds[];
   const GridDev g = dm.g;
   int p0, p1, org[3];
@@ -939,6 +967,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_grad_hess(const DomDesc *dd, int 
   const double *const pvol = P.vol;
   const double *const gmu = dm.mu, *const glam = dm.lam;
   const double *const gu = dm.u;
+  const TB *const gdel = static_cast<const TB *>(dm.del);
   double *const ggr = dm.gg;
   TB *const Atil = static_cast<TB *>(dm.Atil);
   TB *const gdiag = static_cast<TB *>(dm.gd);
@@ -950,7 +979,12 @@ __global__ void __launch_bounds__(kBlock, 2) k_grad_hess(const DomDesc *dd, int 
     const int i = region_node<D>(tg, g, org, r);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      lu[a * nreg + r] = (i >= 0) ? gload(gu, (int64_t)i * D + a) : 0.0;
+      double uv = 0.0;
+      if (i >= 0) {
+        uv = gload(gu, (int64_t)i * D + a);
+        if (step) uv = __builtin_fma(salpha, (double)gload(gdel, (int64_t)i * D + a), uv);
+      }
+      lu[a * nreg + r] = uv;
       lg[a * nreg + r] = 0.0;
       ld[a * nreg + r] = 0.0;
     }
@@ -1119,6 +1153,10 @@ __global__ void __launch_bounds__(kBlock) k_grad_node(const DomDesc *dd, double 
   if (!*dm.active || !phase_wants_grad(dm.ss->phase) || (int)blockIdx.x >= nb) return;
   __shared__ double red[kBlock / 64];
   TB *gdiag = static_cast<TB *>(dm.gd);
+  // an accepted line-search step: u += alpha del (as the tangent kernel read it)
+  const bool step = dm.ss->phase == kPhaseStep;
+  const double alpha = step ? dm.ss->alpha : 0.0;
+  const TB *del = static_cast<const TB *>(dm.del);
   const double grav[3] = {gx, gy, gz};
   const double idt2 = 1.0 / (dt * dt);
   double s2 = 0.0;
@@ -1127,8 +1165,13 @@ __global__ void __launch_bounds__(kBlock) k_grad_node(const DomDesc *dd, double 
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       const int k = i * D + a;
+      double uk = dm.u[k];
+      if (step) {
+        uk = __builtin_fma(alpha, (double)del[k], uk);
+        dm.u[k] = uk;
+      }
       double gval = dm.gg[k];
-      if (m > 0.0) gval += m * idt2 * (dm.u[k] - dt * dm.vn[k]) - m * grav[a];
+      if (m > 0.0) gval += m * idt2 * (uk - dt * dm.vn[k]) - m * grav[a];
       if (!dm.fr[k]) gval = 0.0;
       dm.gg[k] = gval;
       s2 += gval * gval;
@@ -1137,31 +1180,6 @@ __global__ void __launch_bounds__(kBlock) k_grad_node(const DomDesc *dd, double 
   }
   const double t = block_sum(s2, red);
   if (threadIdx.x == 0) dm.part_a[blockIdx.x] = t;
-}
-
-// Newton stop test of every domain with a fresh gradient: stop when
-// |g_free| <= max(rtol |g_free(u0)|, atol * sum m * dx / dt^2) or after
-// max_newton steps, else go on to CG.  One workgroup per domain.
-__global__ void __launch_bounds__(kBlock) k_newton_check(const DomDesc *dd, double rtol, double atol, int max_newton) {
-  const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active || !phase_wants_grad(dm.ss->phase)) return;
-  __shared__ double red[kBlock / 64];
-  const double g2 = reduce_partials(dm.part_a, node_blocks(dm.ndof), red);
-  if (threadIdx.x == 0) {
-    SolveState &s = *dm.ss;
-    const double gn = sqrt(g2);
-    if (s.it == 0) s.gnorm0 = gn;
-    s.gnorm = gn;
-    const double tol = fmax(rtol * s.gnorm0, atol * s.gscale);
-    if (gn <= tol) {
-      s.converged = 1;
-      s.phase = kPhaseDone;
-    } else if (s.it == max_newton) {
-      s.phase = kPhaseDone;
-    } else {
-      s.phase = kPhaseCgInit;
-    }
-  }
 }
 
 // ====================================================================== CG
@@ -1228,10 +1246,38 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *lds12
 // DOFs); the gradient is cleared for the next Newton iteration and the CG
 // state reset.  Runs for domains whose Newton iteration goes on to CG.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd) {
+__global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd, int check, double rtol, double atol,
+                                                    int max_newton) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
-  if (!*dm.active || dm.ss->phase != kPhaseCgInit || (int)blockIdx.x >= nb) return;
+  if (!*dm.active || (int)blockIdx.x >= nb) return;
+  SolveState &st = *dm.ss;
+  const int ph = st.phase;
+  if (check) {
+    // The Newton stop test on the fresh gradient, by every workgroup from the
+    // same partial sums in the same order: stop when |g_free| <= max(rtol
+    // |g_free(u0)|, atol * sum m * dx / dt^2) or after max_newton steps, else
+    // go on to CG.  Workgroup 0 records the decision; a workgroup that starts
+    // after it did reads the phase it wrote (kPhaseCgInit or kPhaseDone) and
+    // reaches the same decision.
+    if (!(phase_wants_grad(ph) || ph == kPhaseCgInit)) return;
+    __shared__ double red[kBlock / 64];
+    const double gn = sqrt(reduce_partials(dm.part_a, nb, red));
+    const int it = st.it;
+    const double gn0 = (it == 0) ? gn : st.gnorm0;
+    const double tol = fmax(rtol * gn0, atol * st.gscale);
+    const bool conv = gn <= tol;
+    const int next = (conv || it == max_newton) ? kPhaseDone : kPhaseCgInit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (it == 0) st.gnorm0 = gn;
+      st.gnorm = gn;
+      if (conv) st.converged = 1;
+      st.phase = next;
+    }
+    if (next != kPhaseCgInit) return;
+  } else if (ph != kPhaseCgInit) {
+    return;
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     CgState &c = *dm.cg;
     c.iter = 0;
@@ -1855,7 +1901,11 @@ __global__ void __launch_bounds__(kBlock) k_ls_check(const DomDesc *dd, int max_
     const double dE = en + ep;
     s->dE = dE;
     if (dE < 0.0) {
+      // u += alpha del is applied by the next gradient pass (the tangent
+      // kernel reads u + alpha del, the node kernel stores it)
       s->phase = kPhaseStep;
+      s->newton_iters += 1;
+      s->it += 1;
     } else if (s->ls_count == max_ls) {
       s->ls_failed = 1;
       s->phase = kPhaseDone;
@@ -1865,25 +1915,6 @@ __global__ void __launch_bounds__(kBlock) k_ls_check(const DomDesc *dd, int max_
       s->ls_halvings += 1;
       s->phase = kPhaseLs;
     }
-  }
-}
-
-// u += alpha del for every domain that accepted a step.  The phase stays
-// kPhaseStep until the next Newton test.
-template <typename TB>
-__global__ void __launch_bounds__(kBlock) k_newton_step(const DomDesc *dd) {
-  const DomDesc &dm = dd[blockIdx.y];
-  const int nb = node_blocks(dm.ndof);
-  if (!*dm.active || (int)blockIdx.x >= nb) return;
-  SolveState &s = *dm.ss;
-  if (s.phase != kPhaseStep) return;
-  const double alpha = s.alpha;
-  const TB *del = static_cast<const TB *>(dm.del);
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < dm.ndof; k += nb * kBlock)
-    dm.u[k] += alpha * (double)del[k];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    s.newton_iters += 1;
-    s.it += 1;
   }
 }
 
@@ -2166,7 +2197,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const DomDesc *dd, doubl
   template __global__ void k_g2p<D, TB>(const DomDesc *, double, int *);                        \
   template __global__ void k_grad_hess<D, TB>(const DomDesc *, int, int *);                     \
   template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \
-  template __global__ void k_cg_init<D, TB>(const DomDesc *);                                   \
+  template __global__ void k_cg_init<D, TB>(const DomDesc *, int, double, double, int);                                   \
   template __global__ void k_cg_iter<D, TB>(const DomDesc *, int, double, double, int, int);    \
   template __global__ void k_delta_energy<D, TB>(const DomDesc *, double, double, double, double);
 
@@ -2176,7 +2207,5 @@ OSMPM_INST_DT(2, double)
 OSMPM_INST_DT(2, float)
 OSMPM_INST_DT(3, double)
 OSMPM_INST_DT(3, float)
-template __global__ void k_newton_step<double>(const DomDesc *);
-template __global__ void k_newton_step<float>(const DomDesc *);
 
 }  // namespace osmpm

@@ -168,9 +168,8 @@ template <int D, typename TB>
 __global__ void k_grad_hess(const DomDesc *dd, int project, int *err);
 template <int D, typename TB>
 __global__ void k_grad_node(const DomDesc *dd, double dt, double gx, double gy, double gz);
-__global__ void k_newton_check(const DomDesc *dd, double rtol, double atol, int max_newton);
 template <int D, typename TB>
-__global__ void k_cg_init(const DomDesc *dd);
+__global__ void k_cg_init(const DomDesc *dd, int check, double rtol, double atol, int max_newton);
 template <int D, typename TB>
 __global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg, int split);
 __global__ void k_tile_list(const DomDesc *dd);
@@ -180,8 +179,6 @@ __global__ void k_cg_reduce(const DomDesc *dd, int q, double rtol, int max_cg);
 template <int D, typename TB>
 __global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz);
 __global__ void k_ls_check(const DomDesc *dd, int max_ls);
-template <typename TB>
-__global__ void k_newton_step(const DomDesc *dd);
 
 // interface
 template <int D>
