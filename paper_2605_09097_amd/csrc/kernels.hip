@@ -1964,11 +1964,21 @@ __global__ void __launch_bounds__(kBlock) k_gamma(const DomDesc *dd) {
 __global__ void __launch_bounds__(kBlock) k_count_recv(const DomDesc *dd, int *out) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
-  __shared__ double red[kBlock / 64];
-  double c = 0.0;
-  for (int i = threadIdx.x; i < dm.g.nn; i += kBlock) c += dm.recv[i] ? 1.0 : 0.0;
-  c = block_sum(c, red);
-  if (threadIdx.x == 0) out[blockIdx.y] = (int)c;
+  __shared__ int red[kBlock / 64];
+  // the flags are 0/1 bytes: 16 per thread and step, counted four to a word
+  const int nn = dm.g.nn;
+  const uint8_t *rv = dm.recv;
+  int c = 0;
+  for (int i0 = threadIdx.x * 16; i0 < nn; i0 += kBlock * 16) {
+    if (i0 + 16 <= nn) {
+      const uint4 w = *reinterpret_cast<const uint4 *>(rv + i0);
+      c += __popc(w.x) + __popc(w.y) + __popc(w.z) + __popc(w.w);
+    } else {
+      for (int i = i0; i < nn; ++i) c += rv[i] ? 1 : 0;
+    }
+  }
+  c = block_sum_int(c, red);
+  if (threadIdx.x == 0) out[blockIdx.y] = c;
 }
 
 // Overlap arbitration (Eq. overlap_donor): a coarse boundary node whose
@@ -2034,6 +2044,9 @@ __global__ void __launch_bounds__(kBlock) k_project_scatter(const DomDesc *ddS, 
 #pragma unroll
     for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
     const int I = node_flat<D>(B.g, idx);
+    // only the receivers' sums are read (by the division and its transpose);
+    // skipping the others removes most of the contended atomics
+    if (!B.recv[I]) continue;
     const double w = m * stencil_N<D>(st, k);
     atomicAdd(&B.pden[I], w);
 #pragma unroll
