@@ -127,6 +127,8 @@ def _declare(L):
     L.or_single_frame.argtypes = [dom, C.c_double, C.POINTER(SolveOpts), C.POINTER(SolveStats)]
     L.or_schwarz_frame.argtypes = [dom, dom, C.c_double, C.POINTER(SchwarzOpts),
                                    C.POINTER(SchwarzStats)]
+    L.or_schwarz_frame_multi.argtypes = [dom, C.POINTER(dom), C.c_int, C.c_double, C.POINTER(SchwarzOpts),
+                                         C.POINTER(SchwarzStats)]
     L.or_single_frame_adjoint.argtypes = [dom, C.c_double, C.POINTER(SolveOpts), C.c_double] + [_dp] * 10
     L.or_schwarz_frame_adjoint.argtypes = ([dom, dom, C.c_double, C.POINTER(SchwarzOpts), C.c_int, C.c_double]
                                            + [_dp] * 20)
@@ -396,6 +398,16 @@ def schwarz_frame(Bd: Domain, Sd: Domain, dT, opts):
     st = SchwarzStats()
     _check(lib().or_schwarz_frame(Bd.ref, Sd.ref, dT, C.byref(opts), C.byref(st)),
            "or_schwarz_frame")
+    return st
+
+
+def schwarz_frame_multi(Bd: Domain, Sds, dT, opts):
+    """One frame of Alg. 1 with the coarse domain Bd and the disjoint fine
+    domains Sds (or_schwarz_frame_multi)."""
+    st = SchwarzStats()
+    arr = (C.POINTER(_Domain) * len(Sds))(*[C.pointer(S._s) for S in Sds])
+    _check(lib().or_schwarz_frame_multi(Bd.ref, arr, len(Sds), dT, C.byref(opts), C.byref(st)),
+           "or_schwarz_frame_multi")
     return st
 
 

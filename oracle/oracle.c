@@ -1076,12 +1076,19 @@ static int boundary_set(or_domain *D) {
  * both in their boundary sets, are ambiguous; the side with the larger
  * fixed-point node mass is the donor (ties: the coarse side) and is removed
  * from its own receiver set. */
+static int arbitrate(or_domain *B, or_domain *S, int *n_amb);
+
 int or_interface(or_domain *B, or_domain *S, int *n_amb) {
   if (B->dim != S->dim || B->m_ref != S->m_ref || B->h0 != S->h0) return OR_E_ARG;
   int rc = boundary_set(B);
   if (rc) return rc;
   rc = boundary_set(S);
   if (rc) return rc;
+  return arbitrate(B, S, n_amb);
+}
+
+/* The arbitration of or_interface on boundary sets already built. */
+static int arbitrate(or_domain *B, or_domain *S, int *n_amb) {
   const int d = B->dim, nnB = nnodes(B);
   int amb = 0;
   for (int I = 0; I < nnB; ++I) {
@@ -1114,9 +1121,11 @@ int or_interface(or_domain *B, or_domain *S, int *n_amb) {
 /* Pi_{S->B} (Eq. spatial_projection) on the coarse receivers: every active
  * fine node j is a point mass m_S,j at x_S,j; v_B,I = sum m_j v_j N_I(x_j) /
  * (sum m_j N_I(x_j) + eps_tol).  Non-receivers get 0. */
+static int project_sums(const or_domain *S, const or_domain *B, const double *vS, double *num, double *den);
+
 int or_project(const or_domain *S, const or_domain *B, double eps_tol, const double *vS,
                double *out) {
-  const int d = B->dim, nnB = nnodes(B), nnS = nnodes(S), ss = stencil_size(B);
+  const int d = B->dim, nnB = nnodes(B);
   double *num = (double *)calloc((size_t)nnB * d, sizeof(double));
   double *den = (double *)calloc((size_t)nnB, sizeof(double));
   if (!num || !den) {
@@ -1124,6 +1133,20 @@ int or_project(const or_domain *S, const or_domain *B, double eps_tol, const dou
     free(den);
     return OR_E_NOMEM;
   }
+  const int rc = project_sums(S, B, vS, num, den);
+  if (!rc)
+    for (int I = 0; I < nnB; ++I)
+      for (int a = 0; a < d; ++a)
+        out[I * d + a] = B->recv[I] ? num[I * d + a] / (den[I] + eps_tol) : 0.0;
+  free(num);
+  free(den);
+  return rc;
+}
+
+/* The sums of Pi_{S->B}: num_I += sum_j m_j N_I(x_j) v_j, den_I += sum_j
+ * m_j N_I(x_j) over the active fine nodes j. */
+static int project_sums(const or_domain *S, const or_domain *B, const double *vS, double *num, double *den) {
+  const int d = B->dim, nnS = nnodes(S), ss = stencil_size(B);
   for (int j = 0; j < nnS; ++j) {
     if (!(S->m[j] > 0.0)) continue;
     int jS[3];
@@ -1131,11 +1154,7 @@ int or_project(const or_domain *S, const or_domain *B, double eps_tol, const dou
     node_index(S, j, jS);
     node_pos(S, jS, xj);
     stencil st;
-    if (stencil_at(B, xj, &st)) {
-      free(num);
-      free(den);
-      return OR_E_OUT_OF_GRID;
-    }
+    if (stencil_at(B, xj, &st)) return OR_E_OUT_OF_GRID;
     for (int s = 0; s < ss; ++s) {
       int I;
       double N, gN[3], dxv[3];
@@ -1145,11 +1164,6 @@ int or_project(const or_domain *S, const or_domain *B, double eps_tol, const dou
       for (int a = 0; a < d; ++a) num[I * d + a] += w * vS[j * d + a];
     }
   }
-  for (int I = 0; I < nnB; ++I)
-    for (int a = 0; a < d; ++a)
-      out[I * d + a] = B->recv[I] ? num[I * d + a] / (den[I] + eps_tol) : 0.0;
-  free(num);
-  free(den);
   return OR_OK;
 }
 
@@ -1318,6 +1332,179 @@ done:
   free(vGSprev);
   free(vGSn);
   free(vGSn1);
+  return rc;
+}
+
+/* Alg. 1 with one coarse domain B and k fine domains S[0..k-1] whose
+ * particle sets are disjoint and which overlap B only (the several refined
+ * regions the conclusion names as future work; readings, since the paper
+ * gives no algorithm for them):
+ *  - boundary sets as for a pair; each fine domain is arbitrated against B
+ *    by the two-domain rule (Eq. overlap_donor), in index order;
+ *  - Pi (Eq. spatial_projection) over the union of the fine point masses:
+ *    numerator and denominator summed over all fine domains, then divided on
+ *    the coarse receivers;
+ *  - each iteration: coarse solve, then every fine domain in index order
+ *    restored, P2G, interpolated at both endpoints from the same coarse
+ *    solution and sub-cycled (they couple only through B, so their order
+ *    does not matter);
+ *  - r_B over the coarse receivers, r_S over the receivers of all fine
+ *    domains together (Eqs. convergence_residuals, convergence_criterion).
+ * With k = 1 every step is that of or_schwarz_frame.  Statistics sum the
+ * fine domains' counts. */
+int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const or_schwarz_opts *o,
+                           or_schwarz_stats *st) {
+  if (k < 1) return OR_E_ARG;
+  for (int f = 0; f < k; ++f)
+    if (B->dim != S[f]->dim || B->m_ref != S[f]->m_ref || B->h0 != S[f]->h0) return OR_E_ARG;
+  const int d = B->dim, nnB = nnodes(B);
+  const double dt = dT / (double)o->M;
+  int rc = OR_OK;
+  memset(st, 0, sizeof(*st));
+  double **sx = (double **)calloc((size_t)k, sizeof(double *)), **sv = (double **)calloc((size_t)k, sizeof(double *));
+  double **sB = (double **)calloc((size_t)k, sizeof(double *)), **sF = (double **)calloc((size_t)k, sizeof(double *));
+  double **vGSprev = (double **)calloc((size_t)k, sizeof(double *));
+  double **vGSn = (double **)calloc((size_t)k, sizeof(double *));
+  double **vGSn1 = (double **)calloc((size_t)k, sizeof(double *));
+  double *vBn = (double *)malloc(sizeof(double) * nnB * d);
+  double *vBk = (double *)malloc(sizeof(double) * nnB * d);
+  double *vGB = (double *)malloc(sizeof(double) * nnB * d);
+  double *vGBnew = (double *)malloc(sizeof(double) * nnB * d);
+  double *num = (double *)malloc(sizeof(double) * nnB * d);
+  double *den = (double *)malloc(sizeof(double) * nnB);
+  if (!sx || !sv || !sB || !sF || !vGSprev || !vGSn || !vGSn1 || !vBn || !vBk || !vGB || !vGBnew || !num || !den) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
+  for (int f = 0; f < k; ++f) {
+    const int np = S[f]->np > 0 ? S[f]->np : 1, nnS = nnodes(S[f]);
+    sx[f] = (double *)malloc(sizeof(double) * (size_t)np * d);
+    sv[f] = (double *)malloc(sizeof(double) * (size_t)np * d);
+    sB[f] = (double *)malloc(sizeof(double) * (size_t)np * d * d);
+    sF[f] = (double *)malloc(sizeof(double) * (size_t)np * d * d);
+    vGSprev[f] = (double *)malloc(sizeof(double) * nnS * d);
+    vGSn[f] = (double *)malloc(sizeof(double) * nnS * d);
+    vGSn1[f] = (double *)malloc(sizeof(double) * nnS * d);
+    if (!sx[f] || !sv[f] || !sB[f] || !sF[f] || !vGSprev[f] || !vGSn[f] || !vGSn1[f]) {
+      rc = OR_E_NOMEM;
+      goto done;
+    }
+  }
+  /* Step 0: store the fine states, P2G everywhere, boundary sets, arbitration */
+  for (int f = 0; f < k; ++f) {
+    const or_domain *Sf = S[f];
+    memcpy(sx[f], Sf->x, sizeof(double) * Sf->np * d);
+    memcpy(sv[f], Sf->v, sizeof(double) * Sf->np * d);
+    memcpy(sB[f], Sf->B, sizeof(double) * Sf->np * d * d);
+    memcpy(sF[f], Sf->F, sizeof(double) * Sf->np * d * d);
+  }
+  if ((rc = or_p2g(B))) goto done;
+  for (int f = 0; f < k; ++f)
+    if ((rc = or_p2g(S[f]))) goto done;
+  if ((rc = boundary_set(B))) goto done;
+  for (int f = 0; f < k; ++f) {
+    int amb = 0;
+    if ((rc = boundary_set(S[f])) || (rc = arbitrate(B, S[f], &amb))) goto done;
+    st->n_amb += amb;
+  }
+  for (int i = 0; i < nnB; ++i) st->n_recv_B += B->recv[i];
+  for (int f = 0; f < k; ++f)
+    for (int i = 0; i < nnodes(S[f]); ++i) st->n_recv_S += S[f]->recv[i];
+  memcpy(vBn, B->vn, sizeof(double) * nnB * d);
+#define PROJECT_ALL(OUT)                                                          \
+  do {                                                                            \
+    memset(num, 0, sizeof(double) * nnB * d);                                     \
+    memset(den, 0, sizeof(double) * nnB);                                         \
+    for (int f = 0; f < k; ++f)                                                   \
+      if ((rc = project_sums(S[f], B, S[f]->vn, num, den))) goto done;           \
+    for (int I = 0; I < nnB; ++I)                                                 \
+      for (int a = 0; a < d; ++a)                                                 \
+        (OUT)[I * d + a] = B->recv[I] ? num[I * d + a] / (den[I] + o->eps_tol) : 0.0; \
+  } while (0)
+  PROJECT_ALL(vGB);
+  for (int f = 0; f < k; ++f)
+    if ((rc = or_interp(B, vBn, S[f], vGSprev[f]))) goto done;
+  for (int it = 0; it < (o->force_iters > 0 ? o->force_iters : o->k_max); ++it) {
+    or_solve_stats ss;
+    /* 1. coarse solve with the projected data */
+    memcpy(B->vbc, vGB, sizeof(double) * nnB * d);
+    B->use_schwarz_bc = 1;
+    if ((rc = or_solve(B, dT, &o->coarse, &ss))) goto done;
+    st->newton_B += ss.newton_iters;
+    st->cg_B += ss.cg_iters;
+    st->ls_B += ss.ls_halvings;
+    for (int i = 0; i < nnB; ++i)
+      for (int a = 0; a < d; ++a) vBk[i * d + a] = (B->m[i] > 0.0) ? B->u[i * d + a] / dT : 0.0;
+    /* 2. every fine domain sub-cycled from its stored state */
+    for (int f = 0; f < k; ++f) {
+      or_domain *Sf = S[f];
+      const int nnS = nnodes(Sf);
+      memcpy(Sf->x, sx[f], sizeof(double) * Sf->np * d);
+      memcpy(Sf->v, sv[f], sizeof(double) * Sf->np * d);
+      memcpy(Sf->B, sB[f], sizeof(double) * Sf->np * d * d);
+      memcpy(Sf->F, sF[f], sizeof(double) * Sf->np * d * d);
+      if ((rc = or_p2g(Sf))) goto done;
+      if ((rc = or_interp(B, vBn, Sf, vGSn[f]))) goto done;
+      if ((rc = or_interp(B, vBk, Sf, vGSn1[f]))) goto done;
+      for (int m = 1; m <= o->M; ++m) {
+        or_temporal(nnS * d, m, o->M, vGSn[f], vGSn1[f], Sf->vbc);
+        Sf->use_schwarz_bc = 1;
+        if ((rc = or_solve(Sf, dt, &o->fine, &ss))) goto done;
+        st->newton_S += ss.newton_iters;
+        st->cg_S += ss.cg_iters;
+        st->ls_S += ss.ls_halvings;
+        if ((rc = or_g2p(Sf, dt))) goto done;
+        if ((rc = or_p2g(Sf))) goto done;
+      }
+    }
+    /* 3. convergence over all interfaces */
+    PROJECT_ALL(vGBnew);
+    double nB, dB_ = norm_diff_masked(vGBnew, vGB, B->recv, nnB, d, &nB);
+    double dS2 = 0.0, nS2 = 0.0;
+    for (int f = 0; f < k; ++f) {
+      double nSf;
+      const double dSf = norm_diff_masked(vGSn1[f], vGSprev[f], S[f]->recv, nnodes(S[f]), d, &nSf);
+      dS2 += dSf * dSf;
+      nS2 += nSf * nSf;
+    }
+    st->r_B = dB_ / fmax(nB, 1e-30);
+    st->r_S = sqrt(dS2) / fmax(sqrt(nS2), 1e-30);
+    memcpy(vGB, vGBnew, sizeof(double) * nnB * d);
+    for (int f = 0; f < k; ++f) memcpy(vGSprev[f], vGSn1[f], sizeof(double) * nnodes(S[f]) * d);
+    st->iters = it + 1;
+    st->converged = st->r_B <= o->eps_conv && st->r_S <= o->eps_conv;
+    if (o->force_iters > 0) {
+      if (it + 1 == o->force_iters) break;
+      continue;
+    }
+    if (st->converged) break;
+  }
+#undef PROJECT_ALL
+  /* 4. post-convergence coarse G2P and advection (Sec. 3.5) */
+  rc = or_g2p(B, dT);
+done:
+  for (int f = 0; f < k; ++f) {
+    if (sx) free(sx[f]);
+    if (sv) free(sv[f]);
+    if (sB) free(sB[f]);
+    if (sF) free(sF[f]);
+    if (vGSprev) free(vGSprev[f]);
+    if (vGSn) free(vGSn[f]);
+    if (vGSn1) free(vGSn1[f]);
+  }
+  free(sx);
+  free(sv);
+  free(sB);
+  free(sF);
+  free(vGSprev);
+  free(vGSn);
+  free(vGSn1);
+  free(vBn);
+  free(vBk);
+  free(vGB);
+  free(vGBnew);
+  free(num);
+  free(den);
   return rc;
 }
 

@@ -213,6 +213,93 @@ def inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.05, E_matrix=1e4,
                        "ramp_frames": ramp_frames})
 
 
+@dataclass
+class MultiScene:
+    """One coarse domain and several disjoint fine domains.  S_union holds the
+    fine domains' particles together on one fine grid of the same lattice (a
+    single fine domain equivalent to the set).  bc_params(frame) returns
+    (params_B, [params_S...])."""
+
+    name: str
+    B: DomainSpec
+    S: List[DomainSpec]
+    S_union: DomainSpec
+    dT: float
+    M: int
+    n_frames: int
+    bc_params: Callable[[int], tuple]
+    eps_tol: float = 0.0
+    meta: dict = field(default_factory=dict)
+
+
+def two_inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.04, E_matrix=1e4, E_inc=1e5, nu=0.3,
+                        rho=1000.0, seed=0, dT=1e-3, M=2, n_frames=50, top_disp=0.01, ramp_frames=50,
+                        tau_rel=1e-3, eps_tol_rel=1e-9, delta=0.0, name="two_inclusions"):
+    """Two refined regions in one matrix (several refined subdomains, named as
+    future work in the conclusion): the matrix square [0.1,0.9]^2 with
+    inclusions r <= r_inc around c1 = (0.3, 0.5) and c2 = (0.7, 0.5).  Fine
+    domain i holds the material within r = 0.12 of c_i on the box c_i +-
+    0.16; the coarse domain the matrix outside r = 0.08 of both centres.  The
+    fine regions are 0.16 apart, so they meet only the coarse domain.  Loaded
+    like inclusion_scene (bottom clamped, top driven down)."""
+    lat = math.lcm(inv_dx_B, inv_dx_S, 10)
+    h0 = 1.0 / lat
+    dxq_B, dxq_S = lat // inv_dx_B, lat // inv_dx_S
+    cs = [np.array([0.3, 0.5]), np.array([0.7, 0.5])]
+    R_f, R_h = 0.12, 0.08
+    spB, spS = 1.0 / (inv_dx_B * ppc1d), 1.0 / (inv_dx_S * ppc1d)
+
+    def rmin(p):
+        return np.minimum(np.linalg.norm(p - cs[0], axis=1), np.linalg.norm(p - cs[1], axis=1))
+
+    def regB(p):
+        return (p[:, 0] >= 0.1) & (p[:, 0] <= 0.9) & (p[:, 1] >= 0.1) & (p[:, 1] <= 0.9) & (rmin(p) > R_h)
+
+    nB = inv_dx_B + 1
+    xB, _ = _sample(2, inv_dx_B, [0, 0], [inv_dx_B, inv_dx_B], ppc1d, regB, seed, 1)
+    flagsB = np.where(rmin(xB) < R_h + spB, FLAG_BOUNDARY, 0)
+    flagsB = flagsB | np.where(xB[:, 1] < 0.1 + spB, 2, 0) | np.where(xB[:, 1] > 0.9 - spB, 4, 0)
+    bc_kind, bc_mask = [BC_FIX, BC_TRANSLATE], [0b11, 0b10]
+    m_ref = rho / (inv_dx_B ** 2 * ppc1d ** 2)
+    B = _domain(2, h0, [0, 0], dxq_B, [nB, nB], xB, np.zeros(len(xB), np.int32), [E_matrix], [nu], rho,
+                ppc1d, flagsB, bc_kind, bc_mask, m_ref, tau_rel)
+    Ss, parts = [], []
+    for i, c in enumerate(cs):
+        lo = [int(math.floor((c[a] - 0.16) * inv_dx_S + 1e-9)) for a in range(2)]
+        hi = [int(math.ceil((c[a] + 0.16) * inv_dx_S - 1e-9)) for a in range(2)]
+        xS, _ = _sample(2, inv_dx_S, lo, hi, ppc1d, lambda p, c=c: np.linalg.norm(p - c, axis=1) <= R_f, seed, 2 + i)
+        r = np.linalg.norm(xS - c, axis=1)
+        flags = np.where(r > R_f - spS, FLAG_BOUNDARY, 0)
+        mat = (r <= r_inc).astype(np.int32)
+        F0 = np.where((mat == 1)[:, None, None], (1.0 - delta) * np.eye(2), np.eye(2)) if delta else None
+        Ss.append(_domain(2, h0, [lo[0] * dxq_S, lo[1] * dxq_S], dxq_S, [hi[0] - lo[0] + 1, hi[1] - lo[1] + 1], xS,
+                          mat, [E_matrix, E_inc], [nu, nu], rho, ppc1d, flags, [], [], m_ref, tau_rel, F0=F0))
+        parts.append((xS, mat, flags))
+    ulo = [int(math.floor(0.14 * inv_dx_S + 1e-9)), int(math.floor(0.34 * inv_dx_S + 1e-9))]
+    uhi = [int(math.ceil(0.86 * inv_dx_S - 1e-9)), int(math.ceil(0.66 * inv_dx_S - 1e-9))]
+    xU = np.concatenate([q[0] for q in parts])
+    matU = np.concatenate([q[1] for q in parts])
+    F0U = np.where((matU == 1)[:, None, None], (1.0 - delta) * np.eye(2), np.eye(2)) if delta else None
+    U = _domain(2, h0, [ulo[0] * dxq_S, ulo[1] * dxq_S], dxq_S, [uhi[0] - ulo[0] + 1, uhi[1] - ulo[1] + 1], xU,
+                matU, [E_matrix, E_inc], [nu, nu], rho, ppc1d, np.concatenate([q[2] for q in parts]), [], [], m_ref,
+                tau_rel, F0=F0U)
+    # one fixed-point threshold and regulariser for all fine domains (those of the union)
+    for S_ in Ss:
+        S_.tau = U.tau
+
+    def bc_params(frame):
+        pB = np.zeros((2, 8))
+        ds = top_disp / ramp_frames if frame < ramp_frames else 0.0
+        pB[1, 1] = -ds / dT
+        return pB, [np.zeros((1, 8)) for _ in Ss]
+
+    return MultiScene(name=name, B=B, S=Ss, S_union=U, dT=dT, M=M, n_frames=n_frames, bc_params=bc_params,
+                      eps_tol=eps_tol_rel * float(U.mass.mean()),
+                      meta={"inv_dx_B": inv_dx_B, "inv_dx_S": inv_dx_S, "r_inc": r_inc, "E_inc": E_inc,
+                            "E_matrix": E_matrix, "nu": nu, "ppc1d": ppc1d, "top_disp": top_disp,
+                            "ramp_frames": ramp_frames})
+
+
 def _outer_layer(x, sp):
     """Particles within one particle spacing of the edges of [0.1, 0.9]^2."""
     return (x[:, 0] < 0.1 + sp) | (x[:, 0] > 0.9 - sp) | (x[:, 1] < 0.1 + sp) | (x[:, 1] > 0.9 - sp)

@@ -1,0 +1,92 @@
+"""Pins of the oracle's Schwarz frame with several fine domains (one coarse
+domain and k disjoint refined regions; the conclusion names several refined
+subdomains as future work and gives no algorithm, so the frame follows the
+readings in or_schwarz_frame_multi).
+
+* k = 1 is the two-domain frame: every step is the same, so the states agree
+  bit for bit with or_schwarz_frame.
+* Two disjoint fine domains equal one fine domain holding both sets of
+  particles on one grid of the same lattice: the boundary sets, the
+  arbitration, the projection (sums over the same fine point masses) and
+  the interpolation are the same node by node, and the fine solves of the
+  union decouple into the two blocks.  Solved tightly, the runs agree to
+  1e-9 of the displacement, with the same iteration and receiver counts.
+* A rigid translation of stress-free material passes through the frame
+  exactly (every transfer maps a uniform field to itself).
+"""
+import dataclasses
+
+import numpy as np
+
+import oracle
+from paper_2605_09097_amd import scenes
+
+TIGHT = dict(newton_rtol=1e-13, newton_atol=1e-18, cg_rtol=1e-14, max_newton=60, max_cg=20000)
+
+
+def test_one_fine_domain_is_the_pair_frame():
+    sc = scenes.workload("inclusion_tiny")
+    so = oracle.solve_opts(**TIGHT)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
+    B1, S1 = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    B2, S2 = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    for f in range(2):
+        pB, pS = sc.bc_params(f)
+        for O, p in ((B1, pB), (S1, pS), (B2, pB), (S2, pS)):
+            O.set_bc_params(p)
+        a = oracle.schwarz_frame(B1, S1, sc.dT, oo)
+        b = oracle.schwarz_frame_multi(B2, [S2], sc.dT, oo)
+        assert a.iters == b.iters and a.n_recv_B == b.n_recv_B and a.n_recv_S == b.n_recv_S
+        assert a.newton_B == b.newton_B and a.cg_S == b.cg_S
+        for k in ("x", "v", "B", "F"):
+            assert np.array_equal(getattr(B1, k), getattr(B2, k)), k
+            assert np.array_equal(getattr(S1, k), getattr(S2, k)), k
+
+
+def test_two_fine_domains_equal_their_union():
+    sc = scenes.two_inclusion_scene(delta=0.01)
+    so = oracle.solve_opts(**TIGHT)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
+    OB, OS = oracle.Domain(sc.B), [oracle.Domain(s) for s in sc.S]
+    UB, UU = oracle.Domain(sc.B), oracle.Domain(sc.S_union)
+    for f in range(3):
+        pB, _ = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        UB.set_bc_params(pB)
+        st = oracle.schwarz_frame_multi(OB, OS, sc.dT, oo)
+        su = oracle.schwarz_frame(UB, UU, sc.dT, oo)
+        assert st.converged and su.converged
+        assert (st.iters, st.n_recv_B, st.n_recv_S, st.n_amb) == (su.iters, su.n_recv_B, su.n_recv_S, su.n_amb)
+        assert st.n_recv_S > 0 and st.n_amb > 0
+    scale_B = np.abs(UB.x - sc.B.x).max()
+    xs = np.concatenate([O.x for O in OS])
+    scale_S = np.abs(UU.x - sc.S_union.x).max()
+    assert scale_B > 1e-4 and scale_S > 1e-6  # the material has moved well beyond rounding
+    assert np.abs(OB.x - UB.x).max() <= 1e-9 * scale_B
+    assert np.abs(xs - UU.x).max() <= 1e-9 * scale_S
+    Fs = np.concatenate([O.F for O in OS])
+    assert np.abs(Fs - UU.F).max() <= 1e-9 * np.abs(UU.F - np.eye(2)).max()
+
+
+def test_rigid_translation_through_the_multi_frame():
+    sc = scenes.two_inclusion_scene()
+    v0 = np.array([0.2, 0.1])
+
+    def still(spec):
+        n, d = spec.x.shape
+        return dataclasses.replace(spec, bc_kind=[], bc_mask=[],
+                                   flags=(spec.flags & np.uint8(1)).astype(spec.flags.dtype),
+                                   v=np.tile(v0, (n, 1)), B=np.zeros((n, d, d)), F=np.tile(np.eye(d), (n, 1, 1)))
+
+    specs = [still(sc.B)] + [still(s) for s in sc.S]
+    Os = [oracle.Domain(s) for s in specs]
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    step = sc.dT * np.linalg.norm(v0)
+    for f in range(2):
+        st = oracle.schwarz_frame_multi(Os[0], Os[1:], sc.dT, oo)
+        assert st.converged and st.iters == 1 and st.newton_B == 0 and st.newton_S == 0
+        for O, spec in zip(Os, specs):
+            assert np.abs(O.x - spec.x - (f + 1) * sc.dT * v0).max() < 1e-8 * step
+            # the only departure is the projection's regulariser: v_B = v0 den / (den + eps_tol),
+            # eps_tol = 1e-9 of the mean fine particle mass against receiver masses of a few
+            assert np.abs(O.v - v0).max() < 1e-8 * np.linalg.norm(v0)
