@@ -303,6 +303,30 @@ osmpm_status osmpm_batch_single_frame(osmpm_batch *batch, double dt, const osmpm
                                       osmpm_solve_stats *stats_host);
 void osmpm_batch_destroy(osmpm_batch *batch);
 
+/* Several refined regions (named as future work in the conclusion; the
+ * paper gives no algorithm, so these are readings): one coarse domain and k
+ * fine domains whose particle sets are disjoint and which overlap the coarse
+ * domain only.  Boundary sets as for a pair; each fine domain is arbitrated
+ * against the coarse one by the rule of Eq. overlap_donor; Pi (Eq.
+ * spatial_projection) takes the union of the fine point masses (sums over
+ * all fine domains, divided on the coarse receivers); each Schwarz iteration
+ * solves the coarse domain, then sub-cycles every fine domain from the same
+ * coarse solution; r_S (Eq. convergence_residuals) runs over the receivers of
+ * all fine domains together and the frame ends when r_B and r_S pass.  With
+ * k = 1 the frame is that of osmpm_schwarz_frame.  The group holds the coarse
+ * domain k times internally; every fine domain must pair with it as for
+ * osmpm_schwarz_frame (same context, dimension, precision, lattice and
+ * reference mass), each at most once.  k <= 1024. */
+osmpm_status osmpm_multi_create(osmpm_ctx *ctx, osmpm_domain *coarse, int32_t k, osmpm_domain *const *fine_host,
+                                osmpm_batch **out);
+/* One global frame of Alg. 1 on a group from osmpm_multi_create (only that
+ * kind: other groups return OSMPM_E_INVALID_ARG, and osmpm_batch_schwarz_frame
+ * refuses this one); *stats_host (may be NULL) receives the frame's
+ * statistics, fine-domain counts summed.  Synchronises.  Destroy the group
+ * with osmpm_batch_destroy. */
+osmpm_status osmpm_multi_schwarz_frame(osmpm_batch *batch, double dT, const osmpm_schwarz_opts *opts,
+                                       osmpm_schwarz_stats *stats_host);
+
 /* ---------------------------------------------------------------- reverse mode */
 
 /* Adjoints (reverse-mode derivatives) of a frame.  The frame is recomputed

@@ -32,6 +32,7 @@ ABI_SYMBOLS = [
     "osmpm_schwarz_frame", "osmpm_single_frame", "osmpm_get_particles", "osmpm_get_grid",
     "osmpm_get_sets", "osmpm_get_sort", "osmpm_domain_info",
     "osmpm_batch_create", "osmpm_batch_schwarz_frame", "osmpm_batch_single_frame", "osmpm_batch_destroy",
+    "osmpm_multi_create", "osmpm_multi_schwarz_frame",
     "osmpm_single_frame_adjoint", "osmpm_schwarz_frame_adjoint", "osmpm_schwarz_frame_adjoint_implicit",
 ]
 
@@ -107,6 +108,8 @@ def _declare(L):
         "osmpm_batch_create": [_vp, C.c_int32, P(_vp), P(_vp), P(_vp)],
         "osmpm_batch_schwarz_frame": [_vp, C.c_double, P(osmpm_schwarz_opts), P(osmpm_schwarz_stats)],
         "osmpm_batch_single_frame": [_vp, C.c_double, P(osmpm_solve_opts), P(osmpm_solve_stats)],
+        "osmpm_multi_create": [_vp, _vp, C.c_int32, P(_vp), P(_vp)],
+        "osmpm_multi_schwarz_frame": [_vp, C.c_double, P(osmpm_schwarz_opts), P(osmpm_schwarz_stats)],
         "osmpm_single_frame_adjoint": [_vp, C.c_double, P(osmpm_solve_opts), C.c_double] + [_vp] * 8
                                       + [P(C.c_double)] * 2,
         "osmpm_schwarz_frame_adjoint": [_vp, _vp, C.c_double, P(osmpm_schwarz_opts), C.c_int32, C.c_double]
@@ -422,6 +425,42 @@ class SchwarzPair:
     def close(self):
         self.B.close()
         self.S.close()
+
+
+class MultiGroup:
+    """One coarse domain and several disjoint fine domains of a scenes.MultiScene
+    (osmpm_multi_create / osmpm_multi_schwarz_frame)."""
+
+    def __init__(self, ctx: Context, scene, precision=OSMPM_FP64):
+        self.ctx = ctx
+        self.scene = scene
+        self.B = Domain(ctx, scene.B, precision)
+        self.S = [Domain(ctx, s, precision) for s in scene.S]
+        k = len(self.S)
+        fb = (C.c_void_p * k)(*[d.handle.value for d in self.S])
+        h = C.c_void_p()
+        ctx.check(lib().osmpm_multi_create(ctx.handle, self.B.handle, k, fb, C.byref(h)), "multi_create")
+        self.handle = h
+        self.frame_index = 0
+
+    def frame(self, opts):
+        pB, pS = self.scene.bc_params(self.frame_index)
+        self.B.set_bc_params(pB)
+        for D, p in zip(self.S, pS):
+            D.set_bc_params(p)
+        st = osmpm_schwarz_stats()
+        self.ctx.check(lib().osmpm_multi_schwarz_frame(self.handle, self.scene.dT, C.byref(opts), C.byref(st)),
+                       "multi_schwarz_frame")
+        self.frame_index += 1
+        return st
+
+    def close(self):
+        if self.handle:
+            lib().osmpm_batch_destroy(self.handle)
+            self.handle = None
+        self.B.close()
+        for D in self.S:
+            D.close()
 
 
 class Batch:

@@ -148,6 +148,7 @@ struct StatusHdr {
 };
 
 struct osmpm_batch {
+  bool multi = false;  // one coarse domain (repeated on side 0) and k fine domains
   osmpm_ctx *c = nullptr;
   int D = 2, precision = 0;
   size_t tb = sizeof(double);
@@ -1038,6 +1039,110 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
     st[i].n_recv_S = nrecv[n + i];
     if (out) out[i] = st[i];
   }
+  return OSMPM_OK;
+}
+
+// Boundary sets of the coarse domain (once) and of every fine domain, and
+// the arbitration of every fine domain against the coarse one (each copy of
+// the coarse domain on side 0 meets its own fine domain).
+template <int D>
+void interface_multi(osmpm_batch *G, const std::vector<int> &b_one) {
+  osmpm_ctx *c = G->c;
+  const int n = G->n;
+  set_active(G, 0, b_one);
+  for (int s = 0; s < 2; ++s) {
+    launch(c, -1, 0, -1, k_qbnd<D>, dim3(blocks_for(G->ext[s].max_np), n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[s]);
+    launch(c, -1, 0, -1, k_gamma, dim3(blocks_for(G->ext[s].max_nn), n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
+  }
+  launch(c, -1, 0, -1, k_fill<int>, dim3(blocks_for(n)), dim3(kBlock), 0, (int64_t)n, 0, G->n_amb);
+  set_active(G, 0, std::vector<int>(n, 1));
+  launch(c, -1, 0, -1, k_arbitrate<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
+         (const DomDesc *)G->dd[0], (const DomDesc *)G->dd[1], G->n_amb);
+  set_active(G, 0, b_one);
+}
+
+// One frame of Alg. 1 for one coarse domain and the k = G->n disjoint fine
+// domains of a multi group (readings as for the oracle's multi-domain frame):
+// coarse work runs on the first copy of the coarse domain only; the
+// projection scatters every fine domain into the coarse sums; each fine
+// domain is interpolated from the same coarse solution and sub-cycled (all of
+// them in the same launches); r_S is taken over the receivers of all fine
+// domains together, and the frame ends when both residuals pass.
+template <int D, typename TB>
+osmpm_status schwarz_multi(osmpm_batch *G, double dT, const osmpm_schwarz_opts *o, osmpm_schwarz_stats *out) {
+  osmpm_ctx *c = G->c;
+  const int n = G->n;
+  const int M = o->M;
+  const double dt = dT / (double)M;
+  osmpm_status s;
+  if ((s = group_sync(G))) return s;
+  osmpm_schwarz_stats st{};
+  std::vector<int> b_one(n, 0), all(n, 1);
+  b_one[0] = 1;
+  set_active(G, 0, b_one);
+  set_active(G, 1, all);
+  // step 0
+  copy_state_side<D, TB>(G, 1, 1);
+  p2g_side<D, TB>(G, 0, true);
+  p2g_side<D, TB>(G, 1, true);
+  interface_multi<D>(G, b_one);
+  int piB = 0, piB_next = 1, iS_new = 1, iS_prev = 2;
+  project_group<D>(G, o->eps_tol, nullptr, piB, nullptr);
+  interp_group<D>(G, kBufVn, nullptr, iS_prev, nullptr);
+  std::vector<osmpm_solve_stats> ss;
+  for (int k = 0; k < o->k_max; ++k) {
+    // 1. coarse solve with the projected data
+    if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss))) return s;
+    add_stats(st.newton_B, st.cg_B, st.ls_B, ss[0]);
+    launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[0], dT);
+    // 2. every fine domain sub-cycled from its stored state
+    copy_state_side<D, TB>(G, 1, 0);
+    p2g_side<D, TB>(G, 1, false);
+    interp_group<D>(G, kBufVn, nullptr, 0, nullptr);
+    interp_group<D>(G, 2, nullptr, iS_new, nullptr);
+    for (int m = 1; m <= M; ++m) {
+      launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(G->ext[1].max_ndof, 1024), n), dim3(kBlock), 0,
+             (const DomDesc *)G->dd[1], (double)m / (double)M, 0, iS_new);
+      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss))) return s;
+      for (int i = 0; i < n; ++i) add_stats(st.newton_S, st.cg_S, st.ls_S, ss[i]);
+      g2p_side<D, TB>(G, 1, dt);
+      p2g_side<D, TB>(G, 1, false);
+    }
+    // 3. residuals over all interfaces
+    project_group<D>(G, o->eps_tol, nullptr, piB_next, nullptr);
+    resid_side<D>(G, 0, piB_next, piB);
+    resid_side<D>(G, 1, iS_new, iS_prev);
+    if ((s = read_status(G))) return s;
+    const double *res = h_res(G);
+    std::swap(piB, piB_next);
+    std::swap(iS_new, iS_prev);
+    double dS2 = 0.0, nS2 = 0.0;
+    for (int i = 0; i < n; ++i) {
+      dS2 += res[2 * n + 2 * i];
+      nS2 += res[2 * n + 2 * i + 1];
+    }
+    st.r_B = std::sqrt(res[0]) / std::max(std::sqrt(res[1]), 1e-30);
+    st.r_S = std::sqrt(dS2) / std::max(std::sqrt(nS2), 1e-30);
+    st.iters = k + 1;
+    if (st.r_B <= o->eps_conv && st.r_S <= o->eps_conv) {
+      st.converged = 1;
+      break;
+    }
+  }
+  // 4. coarse G2P + advection with the last coarse solution
+  g2p_side<D, TB>(G, 0, dT);
+  count_recv<D>(G);
+  if ((s = read_status(G))) return s;
+  const int *amb = h_int(G, G->off_amb);
+  const int *nrecv = h_int(G, G->off_recv);
+  st.n_recv_B = nrecv[0];
+  for (int i = 0; i < n; ++i) {
+    st.n_amb += amb[i];
+    st.n_recv_S += nrecv[n + i];
+  }
+  if (out) *out = st;
   return OSMPM_OK;
 }
 
@@ -2054,7 +2159,30 @@ osmpm_status osmpm_batch_create(osmpm_ctx *ctx, int32_t n, osmpm_domain *const *
 osmpm_status osmpm_batch_schwarz_frame(osmpm_batch *b, double dT, const osmpm_schwarz_opts *o,
                                        osmpm_schwarz_stats *stats) {
   if (!b || b->sides != 2 || !schwarz_opts_ok(o) || !(dT > 0.0)) return OSMPM_E_INVALID_ARG;
+  if (b->multi) return fail(b->c, OSMPM_E_INVALID_ARG, "a multi-domain group takes osmpm_multi_schwarz_frame");
   return DISPATCH2(b->D, b->precision, schwarz_group)(b, dT, o, stats);
+}
+
+osmpm_status osmpm_multi_create(osmpm_ctx *ctx, osmpm_domain *coarse, int32_t k, osmpm_domain *const *fine,
+                                osmpm_batch **out) {
+  if (!ctx || !out || !coarse || !fine || k < 1 || k > 1024) return OSMPM_E_INVALID_ARG;
+  *out = nullptr;
+  for (int i = 0; i < k; ++i) {
+    if (!pair_ok(coarse, fine[i])) return fail(ctx, OSMPM_E_INVALID_ARG, "mismatched coarse/fine domain");
+    for (int j = 0; j < i; ++j)
+      if (fine[j] == fine[i]) return fail(ctx, OSMPM_E_INVALID_ARG, "a fine domain appears twice");
+  }
+  std::vector<osmpm_domain *> side0((size_t)k, coarse);
+  osmpm_status s = group_create(ctx, k, side0.data(), fine, out);
+  if (!s) (*out)->multi = true;
+  return s;
+}
+
+osmpm_status osmpm_multi_schwarz_frame(osmpm_batch *b, double dT, const osmpm_schwarz_opts *o,
+                                       osmpm_schwarz_stats *stats) {
+  if (!b || b->sides != 2 || !schwarz_opts_ok(o) || !(dT > 0.0)) return OSMPM_E_INVALID_ARG;
+  if (!b->multi) return fail(b->c, OSMPM_E_INVALID_ARG, "not a multi-domain group");
+  return DISPATCH2(b->D, b->precision, schwarz_multi)(b, dT, o, stats);
 }
 
 osmpm_status osmpm_batch_single_frame(osmpm_batch *b, double dt, const osmpm_solve_opts *o,

@@ -1,0 +1,92 @@
+"""GPU parity of the Schwarz frame with several fine domains (one coarse
+domain and disjoint refined regions; osmpm_multi_create /
+osmpm_multi_schwarz_frame) against the oracle's multi-domain frame, which is
+pinned on the CPU (k = 1 is the pair frame, two fine domains equal their
+union on one grid).  Two-inclusion scene at dx = 1/20 | 1/50, M = 2, three
+frames; FP64 to 1e-10 (the tolerance of the pair frames), mixed to 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09097_amd import binding
+
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, precision, n_frames=3):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.two_inclusion_scene(delta=0.01)
+    prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
+    so = b.solve_opts(cg_rtol=1e-10 if precision == "fp64" else 1e-5)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    grp = b.MultiGroup(ctx, sc, precision=prec)
+    OB, OS = oracle.Domain(sc.B), [oracle.Domain(s) for s in sc.S]
+    stats = []
+    for f in range(n_frames):
+        pB, _ = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        print("multi-domain frame", f, precision, flush=True)
+        ost = oracle.schwarz_frame_multi(OB, OS, sc.dT, oo)
+        gst = grp.frame(go)
+        stats.append((gst, ost))
+    return sc, grp, OB, OS, stats
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_multi_frames_match_oracle(ctx, precision):
+    sc, grp, OB, OS, stats = _run(ctx, precision)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    for gst, ost in stats:
+        assert gst.converged == ost.converged == 1
+        if precision == "fp64":
+            assert gst.iters == ost.iters
+            assert (gst.n_recv_B, gst.n_recv_S, gst.n_amb) == (ost.n_recv_B, ost.n_recv_S, ost.n_amb)
+            assert gst.newton_B == ost.newton_B and gst.newton_S == ost.newton_S
+        else:
+            assert abs(gst.iters - ost.iters) <= 1
+    assert stats[-1][1].n_amb > 0 and stats[-1][1].n_recv_S > 0
+    for Dg, Do, spec in [(grp.B, OB, sc.B)] + list(zip(grp.S, OS, sc.S)):
+        m, vn, u = Dg.grid_state()
+        x, v, Bm, F = Dg.particles_input_order()
+        assert rel_err(u.cpu().numpy(), Do.u) < tol
+        assert rel_err(x - spec.x, Do.x - spec.x) < tol
+        assert rel_err(F - np.eye(2), Do.F - np.eye(2)) < tol
+    grp.close()
+
+
+def test_multi_group_kinds_are_not_interchangeable(ctx):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.two_inclusion_scene()
+    grp = b.MultiGroup(ctx, sc)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    st = (b.osmpm_schwarz_stats * len(grp.S))()
+    assert b.lib().osmpm_batch_schwarz_frame(grp.handle, sc.dT, b.C.byref(go), st) == b.OSMPM_E_INVALID_ARG
+    pair = b.SchwarzPair(ctx, scenes.workload("inclusion_tiny"))
+    batch = b.Batch(ctx, [pair.B], [pair.S])
+    one = b.osmpm_schwarz_stats()
+    assert b.lib().osmpm_multi_schwarz_frame(batch.handle, sc.dT, b.C.byref(go), b.C.byref(one)) == \
+        b.OSMPM_E_INVALID_ARG
+    # the same fine domain twice is refused
+    fb = (b.C.c_void_p * 2)(grp.S[0].handle.value, grp.S[0].handle.value)
+    h = b.C.c_void_p()
+    assert b.lib().osmpm_multi_create(ctx.handle, grp.B.handle, 2, fb, b.C.byref(h)) == b.OSMPM_E_INVALID_ARG
+    batch.close()
+    pair.close()
+    grp.close()
