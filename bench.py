@@ -123,6 +123,55 @@ def large_form(ctx, name, prec, solve, frames, warmup):
             "kernels": kern}
 
 
+def multi_form(ctx, prec, solve, frames, warmup=1):
+    """Several refined regions: the two-inclusion scene at dx = 1/160 | 1/400
+    (M = 2, inclusions with eigenstrain, top driven down) run with its two
+    fine domains (osmpm_multi_schwarz_frame), and the same particles as one
+    fine domain on one grid (osmpm_schwarz_frame) for comparison: the same
+    physics, so the positions agree to the solver tolerance."""
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding, scenes
+
+    sc = scenes.two_inclusion_scene(160, 400, delta=0.01, n_frames=200)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
+    out = {"workload": "two refined inclusions, coarse dx 1/160, fine dx 1/400, M=2",
+           "N_B": sc.B.n_particles, "N_S": [s.n_particles for s in sc.S],
+           "frames": "%d-%d" % (warmup, warmup + frames - 1)}
+    runs = {}
+    for kind in ("multi", "union"):
+        if kind == "multi":
+            grp = binding.MultiGroup(ctx, sc, precision=prec)
+            step = lambda: grp.frame(opts)
+        else:
+            usc = scenes.Scene(name="union", B=sc.B, S=sc.S_union, dT=sc.dT, M=sc.M, n_frames=sc.n_frames,
+                               bc_params=lambda f: (sc.bc_params(f)[0], np.zeros((1, 8))), eps_tol=sc.eps_tol)
+            grp = binding.SchwarzPair(ctx, usc, precision=prec)
+            step = lambda: grp.frame(opts)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        stats = [step() for _ in range(frames)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        nS = sum(s.n_particles for s in sc.S)
+        ps = sc.B.n_particles + sc.M * nS
+        xs = [grp.B.particles_input_order()[0]]
+        xs += [D.particles_input_order()[0] for D in grp.S] if kind == "multi" else \
+            [grp.S.particles_input_order()[0]]
+        runs[kind] = (xs[0], np.concatenate(xs[1:]))
+        out[kind] = {"value": frames * ps / el, "unit": "particle-steps/s", "ms_per_step": 1e3 * el / frames,
+                     "schwarz_iters_mean": float(np.mean([st.iters for st in stats]))}
+        grp.close()
+    dB = np.abs(runs["multi"][0] - runs["union"][0]).max() / max(np.abs(runs["union"][0] - sc.B.x).max(), 1e-300)
+    xS0 = np.concatenate([s.x for s in sc.S])
+    dS = np.abs(runs["multi"][1] - runs["union"][1]).max() / max(np.abs(runs["union"][1] - xS0).max(), 1e-300)
+    out["max_rel_diff_multi_vs_union"] = {"B": float(dB), "S": float(dS)}
+    return out
+
+
 def domain_probe(ctx, spec_s, prec):
     """Per-kernel launch durations on one domain of a workload
     (name:side[:tile], side B or S, tile as AxB or AxBxC): five P2Gs, one
@@ -362,6 +411,8 @@ def main():
                          "for ratio:inv_dx items, comma separated (e.g. 2:400,2:800), and exit")
     ap.add_argument("--domain-probe", default="",
                     help="only time the kernels on one domain, workload:side[:tile] (e.g. hertz:B:8x8), and exit")
+    ap.add_argument("--multi-frames", type=int, default=10,
+                    help="timed frames of the several-refined-regions run (0 skips it)")
     ap.add_argument("--large", default="hertz:2,fold:1",
                     help="large single-pair workloads as name:timed_frames, comma separated ('' skips them)")
     args = ap.parse_args()
@@ -483,6 +534,7 @@ def main():
     if args.adjoint_batch_scenes > 0:
         adjoint_batch = adjoint_batch_form(args.adjoint_batch_scenes, args.adjoint_batch_frames,
                                            args.adjoint_batch_workers, prec)
+    multi = multi_form(ctx, prec, solve, args.multi_frames) if args.multi_frames > 0 else None
     large = []
     for item in filter(None, args.large.split(",")):
         wl, nf = item.split(":")
@@ -534,6 +586,7 @@ def main():
         "parity": parity,
         "batched": batched,
         "large": large,
+        "multi_domain": multi,
         "adjoint": adjoint,
         "adjoint_batched": adjoint_batch,
     }
