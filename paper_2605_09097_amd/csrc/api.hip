@@ -779,12 +779,13 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   for (long cyc = 0;; ++cyc) {
     if (cyc > max_cycles) return fail(c, OSMPM_E_STATE, "implicit solve did not terminate");
     // launches wanted this cycle: a fresh CG of n iterations takes n + 2
-    // (the product of u_0, n steps, the stop test), a running one the rest
-    int b = 4;
+    // (the product of u_0, n steps, the stop test), a running one the rest,
+    // at least 4; none when no domain is in CG (a line-search halving only)
+    int b = 0;
     for (int i = 0; i < n; ++i) {
       if (G->act[s][i] != 1) continue;
-      if (prev_phase[i] == kPhaseCgInit) b = std::max(b, hint[i] + 2);
-      if (prev_phase[i] == kPhaseCg) b = std::max(b, hint[i] - prev_iter[i] + 1);
+      if (prev_phase[i] == kPhaseCgInit) b = std::max({b, 4, hint[i] + 2});
+      if (prev_phase[i] == kPhaseCg) b = std::max({b, 4, hint[i] - prev_iter[i] + 1});
     }
     b = std::min(b, o->max_cg + 2);
     b += b & 1;  // even, so every cycle starts at parity 0
