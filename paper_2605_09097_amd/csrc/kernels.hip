@@ -1093,16 +1093,13 @@ __global__ void __launch_bounds__(kBlock, 2) k_grad_hess(const DomDesc *dd, int 
 #pragma unroll
       for (int k = 0; k < ns; ++k) gstore(Atil, k * cap + p, At[k]);
     }
-    // In 3D, recompute the weight gradients for the diagonal rather than keep
-    // the gradient scatter's 27 x 3 of them live across the tangent work.
+    // In 3D, evaluate the stencil again for the diagonal rather than keep its
+    // weights (18 doubles) live across the tangent work: an empty register
+    // barrier on the position stops the compiler from reusing the first one.
     if constexpr (D == 3) {
 #pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          asm volatile("" : "+v"(st.w[a][c]));
-          asm volatile("" : "+v"(st.dw[a][c]));
-        }
+      for (int a = 0; a < D; ++a) asm volatile("" : "+v"(xp[a]));
+      stencil_eval<D>(xp, g, st);
     }
 #pragma unroll
     for (int s = 0; s < stencil_count<D>(); ++s) {
