@@ -29,6 +29,21 @@ def _frame_particle_steps(sc):
     return sc.B.n_particles + sc.M * sc.S.n_particles
 
 
+def _host_cpu():
+    """CPU model and logical CPU count of the host the oracle is timed on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
 def cpu_baseline(sc, frames, budget_s=30.0):
     """The CPU oracle (single-threaded FP64 C) on the first frames of the same
     workload; returns (value, sample description, state)."""
@@ -476,7 +491,8 @@ def main():
                                       max(np.linalg.norm(O.x - spec.x), 1e-300))
         cpu = {"value": value_cpu, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
                "sample": "frames 0-%d of the same workload, FP64 C oracle, one thread, %.1f s"
-                         % (nfr - 1, tcpu)}
+                         % (nfr - 1, tcpu),
+               "host": _host_cpu()}
         parity = {"frames": nfr, "vs": "FP64 CPU oracle", "path": args.precision,
                   "max_rel_err": max(errs.values()), **errs}
         pair.close()
@@ -569,7 +585,11 @@ def main():
                    "schwarz_iters_mean": float(np.mean(iters)),
                    "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
                    "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats])),
+                   "ls_halvings_per_frame_mean": float(np.mean([s.ls_B + s.ls_S for s in stats])),
                    "tile_B": list(tile_B), "tile_S": list(tile_S)},
+        # particle updates done, Schwarz re-iterations included (each pass
+        # repeats the coarse step and the M fine sub-steps)
+        "particle_updates_per_s_incl_schwarz_iters": sum(iters) * ps / elapsed,
         "tile_tuning_ms_per_frame": {k: 1e3 * v for k, v in tune.items()},
         "roofline": ({"bound": "hbm", "kernel": "k_cg_iter (CG iteration with the Hessian-vector product)",
                       "achieved": kern["cg_iter"]["achieved_GBps"], "peak": 8000.0, "unit": "GB/s",
