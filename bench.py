@@ -533,9 +533,21 @@ def main():
     fp64 = None
     if prec == binding.OSMPM_MIXED and not args.no_fp64_compare:
         p64, st64, el64 = timed(binding.OSMPM_FP64, opts64, args.steps, args.warmup)
+        # the FP64 path's kernel durations, instrumented as above
+        ctx.profile(True)
+        for _ in range(args.profile_steps if args.profile_steps > 0 else args.steps):
+            p64.frame(opts64)
+        torch.cuda.synchronize()
+        kern64 = _kernel_stats(ctx)
+        ctx.profile(False)
         p64.close()
+        cg64 = kern64.get("cg_iter")
         fp64 = {"value": args.steps * _frame_particle_steps(sc) / el64, "ms_per_step": 1e3 * el64 / args.steps,
-                "schwarz_iters_mean": float(np.mean([s.iters for s in st64]))}
+                "schwarz_iters_mean": float(np.mean([s.iters for s in st64])),
+                "roofline": ({"bound": "hbm", "kernel": "k_cg_iter", "achieved": cg64["achieved_GBps"],
+                              "peak": 8000.0, "unit": "GB/s", "frac": cg64["frac_hbm"], "avg_us": cg64["avg_us"],
+                              "bytes_per_launch": cg64["bytes_per_launch"]} if cg64 else None),
+                "kernels": kern64}
     adjoint = None
     if args.adjoint_frames > 0:
         adjoint = adjoint_form(ctx, sc, prec, args.adjoint_frames)
