@@ -230,7 +230,10 @@ osmpm_status osmpm_implicit_solve(osmpm_domain *dom, double dt, int32_t use_schw
                                   const osmpm_solve_opts *opts, osmpm_solve_stats *stats_host);
 
 /* Grid-to-particle transfer with v_i = u_i / dt (Eqs. g2p_v, g2p_B), the
- * deformation-gradient update (Eq. F_update) and advection (Eq. advection). */
+ * deformation-gradient update (Eq. F_update) and advection (Eq. advection),
+ * from the displacement u of the implicit solve of the current grid: returns
+ * OSMPM_E_STATE when no osmpm_implicit_solve (or frame) has run on this
+ * domain since its last P2G. */
 osmpm_status osmpm_g2p(osmpm_domain *dom, double dt);
 
 /* Boundary sets Gamma_B, Gamma_S from the boundary-layer particles (Eq.

@@ -128,6 +128,7 @@ struct osmpm_domain {
   double *pnum = nullptr, *pden = nullptr, *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
   int cg_hint = 8;  // iterations of the last CG solve (sizes the next batch of launches)
   bool have_p2g = false;
+  bool have_solve = false;  // an implicit solve since the last P2G (u is then zero on inactive nodes)
   osmpm_batch *solo = nullptr;  // this domain as a group of one
   osmpm_batch *pair = nullptr;  // this coarse domain paired with a fine one
   uint64_t pair_uid = 0;
@@ -700,7 +701,10 @@ void p2g_side(osmpm_batch *G, int s, bool want_qall) {
   launch(c, -1, 0, -1, k_p2g_final<D>, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
   build_node_list(G, s, true);
   for (int i = 0; i < G->n; ++i)
-    if (G->act[s][i] == 1) G->dom[s][i]->have_p2g = true;
+    if (G->act[s][i] == 1) {
+      G->dom[s][i]->have_p2g = true;
+      G->dom[s][i]->have_solve = false;
+    }
   if (c->prof && read_status(G) == OSMPM_OK && !c->pending.empty()) {
     // charge the P2G just timed with the active nodes it produced
     for (auto it = c->pending.rbegin(); it != c->pending.rend(); ++it)
@@ -879,6 +883,7 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   for (int i = 0; i < n; ++i) {
     if (G->act[s][i] != 1) continue;
     G->dom[s][i]->cg_hint = std::max(hint[i], 1);
+    G->dom[s][i]->have_solve = true;
     if (out) {
       osmpm_solve_stats &r = (*out)[i];
       r.newton_iters = hs[i].newton_iters;
@@ -2073,6 +2078,7 @@ osmpm_status osmpm_implicit_solve(osmpm_domain *d, double dt, int32_t use_schwar
 osmpm_status osmpm_g2p(osmpm_domain *d, double dt) {
   if (!d || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
   if (!d->have_p2g) return fail(d->ctx, OSMPM_E_STATE, "g2p before p2g");
+  if (!d->have_solve) return fail(d->ctx, OSMPM_E_STATE, "g2p before an implicit solve of the last p2g's grid");
   return DISPATCH2(d->D, d->precision, g2p_solo)(d, dt);
 }
 

@@ -759,7 +759,6 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
   TB *const v = static_cast<TB *>(P.v);
   TB *const B = static_cast<TB *>(P.B);
   TB *const H = static_cast<TB *>(P.F);
-  const double *const gm = dm.m;
   const double *const gu = dm.u;
   // In 2D, x and H = F - I are loaded together (H is not needed until after
   // the gather, but a load issued there is one more round trip).  In 3D, H
@@ -792,9 +791,9 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
 #pragma unroll
     for (int a = 0; a < D; ++a) idx[a] = st.base[a] + k[a];
     const int i = node_flat<D>(g, idx);
-    // inactive nodes (m = 0) contribute nothing; both loads are issued
-    // unconditionally so that no load waits on the mass test
-    const double mi = gload(gm, i);
+    // inactive nodes (m = 0) contribute nothing: the solve that precedes
+    // every G2P sets u to zero there (its initial iterate) and its steps
+    // change active DOFs only, so no mass test is needed
     const TB N = stencil_N<D>(st, k);
     TB gN[D], dxv[D];
     double ui[D];
@@ -802,8 +801,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       dxv[a] = ((TB)k[a] - st.f[a]) * dx_t;
-      const double ua = gload(gu, (int64_t)i * D + a);
-      ui[a] = (mi > 0.0) ? ua : 0.0;
+      ui[a] = gload(gu, (int64_t)i * D + a);
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {

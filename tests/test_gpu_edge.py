@@ -212,3 +212,24 @@ def test_argument_limits(ctx):
     with pytest.raises(b.OsmpmError) as e:
         b.Domain(ctx, huge)
     assert e.value.status == b.OSMPM_E_INVALID_ARG
+
+
+def test_g2p_requires_a_solve_of_the_current_grid(ctx):
+    """G2P reads the displacement of the implicit solve of the current grid:
+    after a P2G with no solve it is refused (status 7), and accepted again
+    once the grid has been solved."""
+    b = _b()
+    spec = tiny_domain(dim=2, n_cells=8, n_particles=40, seed=48, F_spread=0.05)
+    D = b.Domain(ctx, spec)
+    D.p2g()
+    with pytest.raises(b.OsmpmError) as e:
+        D.g2p(1e-3)
+    assert e.value.status == b.OSMPM_E_STATE
+    D.implicit_solve(1e-3, b.solve_opts())
+    D.g2p(1e-3)
+    D.p2g()
+    with pytest.raises(b.OsmpmError) as e:
+        D.g2p(1e-3)
+    assert e.value.status == b.OSMPM_E_STATE
+    ctx.sync()
+    D.close()
