@@ -332,8 +332,8 @@ double alg_bytes(int which, int D, double np, double nn, double tb) {
       return np * (8.0 * D + tb * ns) + nn * (D * (tb * 15.0 + 1.0) + 8.0);
     case OSMPM_K_P2G:  // x, mass, flags; v, B per particle; mass and momentum (rmw) per node
       return np * (8.0 * (D + 1.0) + tb * (D + D * D) + 1.0) + nn * 16.0 * (1.0 + D);
-    case OSMPM_K_G2P:  // x read and written, F read; v, B, F written; u and mass gathered per node
-      return np * (16.0 * D + tb * (D + 3.0 * D * D)) + nn * 8.0 * (D + 1.0);
+    case OSMPM_K_G2P:  // x read and written, F read; v, B, F written; u gathered per node
+      return np * (16.0 * D + tb * (D + 3.0 * D * D)) + nn * 8.0 * D;
     case OSMPM_K_GRAD_HESS:  // x, vol, mat, F read; Atil written; u read, gradient rmw, diagonal rmw
       return np * (8.0 * (D + 1.0) + 4.0 + tb * (D * D + ns)) + nn * (8.0 * 3.0 * D + tb * 2.0 * D);
     default:
