@@ -435,8 +435,9 @@ def main():
                     help="large single-pair workloads as name:timed_frames, comma separated ('' skips them)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the method's multiplicative Schwarz loop is "
-              "sequential and this build measures one GPU's share (see --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the method's multiplicative Schwarz loop is "
+              "sequential, and splitting a domain over GPUs is a design, not a measured path "
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
