@@ -1,4 +1,4 @@
-"""The paper's printed constants used by the build are read from the golden
+"""The paper's printed constants used by the oracle and the library are read from the golden
 fixture (each line cites its section), and the defaults of the oracle and
 the binding agree with them."""
 import os
