@@ -11,7 +11,8 @@ G2P.  particle-steps per frame = N_B + M N_S; Schwarz re-iterations count as
 cost.  Inputs are resident in HBM before timing starts.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-Prints one JSON line.
+Prints one compact JSON line, last on stdout; the full result (per-kernel
+tables, per-scene records) goes to --detail-out.
 """
 import argparse
 import json
@@ -23,10 +24,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKLOAD = "inclusion_refined"
+METRIC = "particle-steps/s, OS-MPM implicit step, mixed FP32 vs FP64 at <=1e-5 rel err"
+# The paper's own efficiency result, for context (another machine and another
+# comparison: OS-MPM against the single-domain fine solver).
+PAPER_CONTEXT = {"speedup_vs_single_domain_fine": {"E_in/E_out=1": 6.61, "E_in/E_out=2": 9.15,
+                                                   "E_in/E_out=5": 4.34},
+                 "setting": "inclusion study (Sec. 4.3) at the finest tested resolution; Taichi on a "
+                            "workstation with a Ryzen 9950X3D CPU and 64 GB RAM",
+                 "this_gpu": "bench.py --eshelby gives the same comparison on this GPU"}
+# The last stdout line stays well under this size (a reader may keep only the
+# tail of the output); every per-kernel table and per-scene record goes to the
+# detail file instead.
+SUMMARY_MAX_BYTES = 4096
 
 
 def _frame_particle_steps(sc):
     return sc.B.n_particles + sc.M * sc.S.n_particles
+
+
+def _progress(msg):
+    """One progress line on stderr (the result goes to stdout)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def _host_cpu():
@@ -315,7 +333,7 @@ def adjoint_form(ctx, sc, prec, frames, mode="unrolled"):
     slots = 1 if mode == "implicit" else K
     tape = (_tape_bytes(run.pair.S, prec, slots * (M + 1)) + _tape_bytes(run.pair.B, prec, 2)
             + 2 * slots * nnB * run.pair.B.dim * 8)
-    out = {"mode": mode, "frames": frames, "checkpoint_every": 10, "loss": float(L),
+    out = {"mode": mode, "frames": frames, "checkpoint_every": 10, "loss": float(L.detach()),
            "dL_dE": [float(g) for g in E.grad],
            "forward_ms_per_frame": 1e3 * (t1 - t0) / frames, "backward_ms_per_frame": 1e3 * (t2 - t1) / frames,
            "schwarz_iters": run.iters, "frame_tape_MB_max": tape / 1e6,
@@ -405,6 +423,86 @@ def adjoint_batch_form(n_scenes, frames, workers, prec):
             "per_scene": out}
 
 
+def write_detail(detail, path):
+    """Writes the full result (every section, per-kernel tables, per-scene
+    records) as JSON to `path`; returns the path, or None when it could not
+    be written."""
+    if not path:
+        return None
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(detail, f, indent=1)
+        return path
+    except OSError as e:
+        print("bench: could not write %s: %s" % (path, e), file=sys.stderr, flush=True)
+        return None
+
+
+def _r(x, nd=4):
+    """Rounds a float to nd significant digits (None passes)."""
+    if x is None:
+        return None
+    return float("%.*g" % (nd, x))
+
+
+def _kfrac(kern, name):
+    k = (kern or {}).get(name)
+    return None if not k else {"avg_us": _r(k["avg_us"]), "frac": _r(k["frac_hbm"], 3)}
+
+
+def compact_summary(detail, detail_path=None):
+    """The one-line result: the contract's keys, the headline roofline and
+    CPU baseline, and a few numbers of every other section (full tables in
+    the detail file).  Serialised, it stays under SUMMARY_MAX_BYTES."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "roofline", "speedup_vs_fp64_gpu",
+            "particle_updates_per_s_incl_schwarz_iters")
+    out = {k: detail.get(k) for k in keys}
+    cpu = detail.get("cpu_baseline")
+    if cpu:
+        out["cpu_baseline"] = {k: cpu.get(k) for k in ("value", "unit", "cores", "kind", "sample")}
+        out["cpu_baseline"]["host_cpu"] = (cpu.get("host") or {}).get("model")
+    else:
+        out["cpu_baseline"] = None
+    par = detail.get("parity")
+    out["parity"] = None if not par else {k: par.get(k) for k in ("frames", "vs", "path", "max_rel_err")}
+    fp = detail.get("fp64_gpu_path")
+    out["fp64_gpu_path"] = None if not fp else {
+        "value": fp.get("value"), "ms_per_step": fp.get("ms_per_step"),
+        "cg_iter_frac": (fp.get("roofline") or {}).get("frac")}
+    out["kernels"] = {k: _kfrac(detail.get("kernels"), k) for k in ("cg_iter", "p2g", "g2p", "grad_hess")}
+    b = detail.get("batched")
+    if b:
+        out["batched"] = {"scenes": b.get("scenes"), "value": b.get("value"), "ms_per_step": b.get("ms_per_step"),
+                          "schwarz_iters_mean": b.get("schwarz_iters_mean"), "tile": b.get("tile"),
+                          "kernels": {k: _kfrac(b.get("kernels"), k) for k in ("cg_iter", "p2g", "g2p", "grad_hess")}}
+    else:
+        out["batched"] = None
+    out["large"] = [{"workload": L.get("workload"), "frames": L.get("frames"), "value": L.get("value"),
+                     "ms_per_step": L.get("ms_per_step"), "schwarz_iters_mean": L.get("schwarz_iters_mean"),
+                     "cg_per_frame_mean": L.get("cg_per_frame_mean")} for L in (detail.get("large") or [])]
+    m = detail.get("multi_domain")
+    out["multi_domain"] = None if not m else {
+        "multi_ms_per_step": (m.get("multi") or {}).get("ms_per_step"),
+        "union_ms_per_step": (m.get("union") or {}).get("ms_per_step"),
+        "max_rel_diff": m.get("max_rel_diff_multi_vs_union")}
+    a = detail.get("adjoint")
+    out["adjoint"] = None if not a else {
+        "frames": a.get("frames"), "forward_ms_per_frame": a.get("forward_ms_per_frame"),
+        "backward_ms_per_frame": a.get("backward_ms_per_frame"),
+        "implicit_backward_ms_per_frame": (a.get("implicit") or {}).get("backward_ms_per_frame"),
+        "implicit_rel_diff": (a.get("implicit") or {}).get("rel_diff_vs_unrolled")}
+    ab = detail.get("adjoint_batched")
+    out["adjoint_batched"] = None if not ab else {
+        k: ab.get(k) for k in ("scenes", "frames", "checkpoint_every", "forward_s", "backward_s", "targets_forward_s",
+                               "gradients_s", "particle_steps_per_s_forward_and_reverse",
+                               "sign_agrees_with_E_minus_E_target")}
+    out["paper_context"] = {"speedup_vs_single_domain_fine_max": 9.15, "hardware": "Ryzen 9950X3D CPU (Taichi)"}
+    out["detail"] = detail_path
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,7 +511,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--no-fp64-compare", action="store_true", help="skip the FP64 GPU path comparison")
-    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-frames", type=int, default=5)
     ap.add_argument("--profile-steps", type=int, default=0, help="frames of the instrumented pass (0: --steps)")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
     ap.add_argument("--batch-scenes", type=int, default=64,
@@ -431,6 +529,8 @@ def main():
                     help="only time the kernels on one domain, workload:side[:tile] (e.g. hertz:B:8x8), and exit")
     ap.add_argument("--multi-frames", type=int, default=10,
                     help="timed frames of the several-refined-regions run (0 skips it)")
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full result (every section); '' skips it")
     ap.add_argument("--large", default="hertz:2,fold:1",
                     help="large single-pair workloads as name:timed_frames, comma separated ('' skips them)")
     args = ap.parse_args()
@@ -477,6 +577,8 @@ def main():
     opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
     opts64 = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
 
+    _progress("start: %s, %s path, %d + %d particles" % (WORKLOAD, args.precision, sc.B.n_particles,
+                                                         sc.S.n_particles))
     # parity sample: the first frames against the FP64 oracle (also the CPU baseline)
     cpu = None
     parity = None
@@ -501,6 +603,7 @@ def main():
                   "max_rel_err": max(errs.values()), **errs}
         pair.close()
 
+    _progress("cpu baseline and parity sample done")
     # tile shapes picked by measurement (outside the timed region)
     from paper_2605_09097_amd import autotune
 
@@ -518,6 +621,7 @@ def main():
         torch.cuda.synchronize()
         return pr, st, time.perf_counter() - t
 
+    _progress("tiles chosen: B %s, S %s" % (tile_B, tile_S))
     # Timed region (no instrumentation).
     pair, stats, elapsed = timed(prec, opts, args.steps, args.warmup)
     # Kernel durations: the same number of frames again with every launch of
@@ -534,6 +638,7 @@ def main():
     kern = _kernel_stats(ctx)
     ctx.profile(False)
     pair.close()
+    _progress("timed and profiled passes done")
     fp64 = None
     if prec == binding.OSMPM_MIXED and not args.no_fp64_compare:
         p64, st64, el64 = timed(binding.OSMPM_FP64, opts64, args.steps, args.warmup)
@@ -552,6 +657,7 @@ def main():
                               "peak": 8000.0, "unit": "GB/s", "frac": cg64["frac_hbm"], "avg_us": cg64["avg_us"],
                               "bytes_per_launch": cg64["bytes_per_launch"]} if cg64 else None),
                 "kernels": kern64}
+    _progress("fp64 path done")
     adjoint = None
     if args.adjoint_frames > 0:
         adjoint = adjoint_form(ctx, sc, prec, args.adjoint_frames)
@@ -559,18 +665,23 @@ def main():
         g_u, g_i = np.asarray(adjoint["dL_dE"]), np.asarray(imp["dL_dE"])
         imp["rel_diff_vs_unrolled"] = float(np.abs(g_i - g_u).max() / max(np.abs(g_u).max(), 1e-300))
         adjoint["implicit"] = imp
+    _progress("adjoint section done")
     batched = None
     if args.batch_scenes > 0:
         batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve)
+    _progress("batched section done")
     adjoint_batch = None
     if args.adjoint_batch_scenes > 0:
         adjoint_batch = adjoint_batch_form(args.adjoint_batch_scenes, args.adjoint_batch_frames,
                                            args.adjoint_batch_workers, prec)
+    _progress("batched adjoint section done")
     multi = multi_form(ctx, prec, solve, args.multi_frames) if args.multi_frames > 0 else None
+    _progress("multi-domain section done")
     large = []
     for item in filter(None, args.large.split(",")):
         wl, nf = item.split(":")
         large.append(large_form(ctx, wl, prec, solve, int(nf), warmup=1))
+        _progress("large workload %s done" % wl)
     if args.calibrate_copy:
         # a plain device copy of known size, for scaling HBM counters
         a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -582,8 +693,8 @@ def main():
     ps = _frame_particle_steps(sc)
     value = args.steps * ps / elapsed
     iters = [s.iters for s in stats]
-    out = {
-        "metric": "particle-steps/s, OS-MPM implicit step, mixed FP32 vs FP64 at <=1e-5 rel err",
+    detail = {
+        "metric": METRIC,
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -597,21 +708,26 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D inclusion, coarse dx 1/160, fine dx 1/400, 2x2 ppc, M=2, dT=1e-3, "
                                "frames %d-%d" % (args.warmup, args.warmup + args.steps - 1),
-                   "N_B": sc.B.n_particles, "N_S": sc.S.n_particles, "path": args.precision,
+                   "N_B": sc.B.n_particles, "N_S": sc.S.n_particles, "M": sc.M, "path": args.precision,
                    "schwarz_iters_mean": float(np.mean(iters)),
-                   "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
                    "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stats])),
+                   "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stats])),
+                   "cg_per_newton_mean": float(np.sum([s.cg_B + s.cg_S for s in stats]) /
+                                               max(1, np.sum([s.newton_B + s.newton_S for s in stats]))),
                    "ls_halvings_per_frame_mean": float(np.mean([s.ls_B + s.ls_S for s in stats])),
+                   "inner_unconverged_total": int(sum(s.unconv_B + s.unconv_S for s in stats)),
+                   "inner_ls_failed_total": int(sum(s.lsfail_B + s.lsfail_S for s in stats)),
                    "tile_B": list(tile_B), "tile_S": list(tile_S)},
         # particle updates done, Schwarz re-iterations included (each pass
         # repeats the coarse step and the M fine sub-steps)
         "particle_updates_per_s_incl_schwarz_iters": sum(iters) * ps / elapsed,
         "tile_tuning_ms_per_frame": {k: 1e3 * v for k, v in tune.items()},
-        "roofline": ({"bound": "hbm", "kernel": "k_cg_iter (CG iteration with the Hessian-vector product)",
+        "roofline": ({"bound": "hbm", "kernel": "k_cg_iter",
                       "achieved": kern["cg_iter"]["achieved_GBps"], "peak": 8000.0, "unit": "GB/s",
                       "frac": kern["cg_iter"]["frac_hbm"], "traffic": counter_traffic(),
                       "avg_us": kern["cg_iter"]["avg_us"],
-                      "bytes_per_launch": kern["cg_iter"]["bytes_per_launch"]}
+                      "bytes_per_launch": kern["cg_iter"]["bytes_per_launch"],
+                      "launches": kern["cg_iter"]["launches"]}
                      if "cg_iter" in kern else None),
         "kernels": kern,
         "profiled_pass_ms_per_step": 1e3 * elapsed_prof / max(1, args.profile_steps if args.profile_steps > 0
@@ -619,13 +735,7 @@ def main():
         "fp64_gpu_path": fp64,
         "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
         "cpu_baseline": cpu,
-        # the paper's own efficiency result, for context (another machine and
-        # another comparison: OS-MPM against the single-domain fine solver)
-        "paper_context": {"speedup_vs_single_domain_fine": {"E_in/E_out=1": 6.61, "E_in/E_out=2": 9.15,
-                                                            "E_in/E_out=5": 4.34},
-                          "setting": "inclusion study (Sec. 4.3) at the finest tested resolution; Taichi on a "
-                                     "workstation with a Ryzen 9950X3D CPU and 64 GB RAM",
-                          "this_gpu": "bench.py --eshelby gives the same comparison on this GPU"},
+        "paper_context": PAPER_CONTEXT,
         "parity": parity,
         "batched": batched,
         "large": large,
@@ -633,7 +743,10 @@ def main():
         "adjoint": adjoint,
         "adjoint_batched": adjoint_batch,
     }
-    print(json.dumps(out))
+    detail_path = write_detail(detail, args.detail_out)
+    line = compact_summary(detail, detail_path)
+    sys.stderr.flush()
+    print(json.dumps(line, separators=(",", ":")), flush=True)
     ctx.close()
 
 

@@ -122,11 +122,18 @@ typedef struct {
   osmpm_solve_opts coarse, fine;
 } osmpm_schwarz_opts;
 
+/* Statistics of one Schwarz frame: iterations and convergence of the
+ * Schwarz loop, the last residuals, receiver and ambiguous-node counts, and
+ * per side (B coarse, S fine) the Newton, CG and line-search halving counts
+ * summed over the frame's implicit solves, the number of those solves that
+ * ended unconverged (Newton cap reached or line search failed) and the
+ * number whose line search failed. */
 typedef struct {
   int32_t iters, converged;
   double r_B, r_S;
   int32_t n_recv_B, n_recv_S, n_amb;
   int32_t newton_B, newton_S, cg_B, cg_S, ls_B, ls_S;
+  int32_t unconv_B, unconv_S, lsfail_B, lsfail_S;
 } osmpm_schwarz_stats;
 
 /* ---------------------------------------------------------------- context */

@@ -100,6 +100,7 @@ class SchwarzStats(C.Structure):
         ("n_recv_B", C.c_int), ("n_recv_S", C.c_int), ("n_amb", C.c_int),
         ("newton_B", C.c_int), ("newton_S", C.c_int), ("cg_B", C.c_int), ("cg_S", C.c_int),
         ("ls_B", C.c_int), ("ls_S", C.c_int),
+        ("unconv_B", C.c_int), ("unconv_S", C.c_int), ("lsfail_B", C.c_int), ("lsfail_S", C.c_int),
     ]
 
 

@@ -104,6 +104,7 @@ typedef struct {
   double r_B, r_S;
   int n_recv_B, n_recv_S, n_amb;
   int newton_B, newton_S, cg_B, cg_S, ls_B, ls_S;
+  int unconv_B, unconv_S, lsfail_B, lsfail_S; /* inner solves unconverged / with a failed line search */
 } or_schwarz_stats;
 
 /* ------------------------------------------------------------------ */
@@ -1278,6 +1279,8 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
     st->newton_B += ss.newton_iters;
     st->cg_B += ss.cg_iters;
     st->ls_B += ss.ls_halvings;
+    st->unconv_B += !ss.converged;
+    st->lsfail_B += ss.ls_failed;
     for (int i = 0; i < nnB; ++i)
       for (int a = 0; a < d; ++a) vBk[i * d + a] = (B->m[i] > 0.0) ? B->u[i * d + a] / dT : 0.0;
     /* 2. fine sub-cycling from the restored state */
@@ -1295,6 +1298,8 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
       st->newton_S += ss.newton_iters;
       st->cg_S += ss.cg_iters;
       st->ls_S += ss.ls_halvings;
+      st->unconv_S += !ss.converged;
+      st->lsfail_S += ss.ls_failed;
       if ((rc = or_g2p(S, dt))) goto done;
       if ((rc = or_p2g(S))) goto done;
     }
@@ -1433,6 +1438,8 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
     st->newton_B += ss.newton_iters;
     st->cg_B += ss.cg_iters;
     st->ls_B += ss.ls_halvings;
+    st->unconv_B += !ss.converged;
+    st->lsfail_B += ss.ls_failed;
     for (int i = 0; i < nnB; ++i)
       for (int a = 0; a < d; ++a) vBk[i * d + a] = (B->m[i] > 0.0) ? B->u[i * d + a] / dT : 0.0;
     /* 2. every fine domain sub-cycled from its stored state */
@@ -1453,6 +1460,8 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
         st->newton_S += ss.newton_iters;
         st->cg_S += ss.cg_iters;
         st->ls_S += ss.ls_halvings;
+        st->unconv_S += !ss.converged;
+        st->lsfail_S += ss.ls_failed;
         if ((rc = or_g2p(Sf, dt))) goto done;
         if ((rc = or_p2g(Sf))) goto done;
       }

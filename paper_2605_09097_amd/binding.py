@@ -67,7 +67,9 @@ class osmpm_schwarz_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("r_B", C.c_double), ("r_S", C.c_double),
                 ("n_recv_B", C.c_int32), ("n_recv_S", C.c_int32), ("n_amb", C.c_int32),
                 ("newton_B", C.c_int32), ("newton_S", C.c_int32), ("cg_B", C.c_int32),
-                ("cg_S", C.c_int32), ("ls_B", C.c_int32), ("ls_S", C.c_int32)]
+                ("cg_S", C.c_int32), ("ls_B", C.c_int32), ("ls_S", C.c_int32),
+                ("unconv_B", C.c_int32), ("unconv_S", C.c_int32), ("lsfail_B", C.c_int32),
+                ("lsfail_S", C.c_int32)]
 
 
 _vp = C.c_void_p

@@ -952,10 +952,13 @@ void resid_side(osmpm_batch *G, int s, int a_buf, int b_buf) {
          G->res + 2 * s * G->n);
 }
 
-void add_stats(int32_t &nt, int32_t &cg, int32_t &ls, const osmpm_solve_stats &s) {
-  nt += s.newton_iters;
-  cg += s.cg_iters;
-  ls += s.ls_halvings;
+// Adds one implicit solve's counts to a frame's statistics of side B or S.
+void add_stats(osmpm_schwarz_stats &st, bool fine, const osmpm_solve_stats &s) {
+  (fine ? st.newton_S : st.newton_B) += s.newton_iters;
+  (fine ? st.cg_S : st.cg_B) += s.cg_iters;
+  (fine ? st.ls_S : st.ls_B) += s.ls_halvings;
+  (fine ? st.unconv_S : st.unconv_B) += !s.converged;
+  (fine ? st.lsfail_S : st.lsfail_B) += s.ls_failed;
 }
 
 // One global frame of Alg. 1 for every pair of a two-sided group.  Work
@@ -988,7 +991,7 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
     // 1. coarse solve with the projected data
     if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss))) return s;
     for (int i = 0; i < n; ++i)
-      if (live[i]) add_stats(st[i].newton_B, st[i].cg_B, st[i].ls_B, ss[i]);
+      if (live[i]) add_stats(st[i], false, ss[i]);
     launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
            (const DomDesc *)G->dd[0], dT);
     // 2. fine sub-cycling from the stored state
@@ -1001,7 +1004,7 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
              (const DomDesc *)G->dd[1], (double)m / (double)M, 0, iS_new);
       if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss))) return s;
       for (int i = 0; i < n; ++i)
-        if (live[i]) add_stats(st[i].newton_S, st[i].cg_S, st[i].ls_S, ss[i]);
+        if (live[i]) add_stats(st[i], true, ss[i]);
       g2p_side<D, TB>(G, 1, dt);
       p2g_side<D, TB>(G, 1, false);
     }
@@ -1100,7 +1103,7 @@ osmpm_status schwarz_multi(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
   for (int k = 0; k < o->k_max; ++k) {
     // 1. coarse solve with the projected data
     if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss))) return s;
-    add_stats(st.newton_B, st.cg_B, st.ls_B, ss[0]);
+    add_stats(st, false, ss[0]);
     launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
            (const DomDesc *)G->dd[0], dT);
     // 2. every fine domain sub-cycled from its stored state
@@ -1112,7 +1115,7 @@ osmpm_status schwarz_multi(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
       launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(G->ext[1].max_ndof, 1024), n), dim3(kBlock), 0,
              (const DomDesc *)G->dd[1], (double)m / (double)M, 0, iS_new);
       if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss))) return s;
-      for (int i = 0; i < n; ++i) add_stats(st.newton_S, st.cg_S, st.ls_S, ss[i]);
+      for (int i = 0; i < n; ++i) add_stats(st, true, ss[i]);
       g2p_side<D, TB>(G, 1, dt);
       p2g_side<D, TB>(G, 1, false);
     }
