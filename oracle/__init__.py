@@ -90,7 +90,7 @@ class SolveStats(C.Structure):
 class SchwarzOpts(C.Structure):
     _fields_ = [
         ("M", C.c_int), ("k_max", C.c_int), ("eps_conv", C.c_double), ("eps_tol", C.c_double),
-        ("coarse", SolveOpts), ("fine", SolveOpts), ("force_iters", C.c_int),
+        ("coarse", SolveOpts), ("fine", SolveOpts), ("force_iters", C.c_int), ("warm_start", C.c_int),
     ]
 
 
@@ -386,8 +386,10 @@ def solve_opts(newton_rtol=1e-8, newton_atol=1e-13, cg_rtol=1e-10, max_newton=50
     return o
 
 
-def schwarz_opts(M, k_max=100, eps_conv=1e-5, eps_tol=0.0, coarse=None, fine=None, force_iters=0):
+def schwarz_opts(M, k_max=100, eps_conv=1e-5, eps_tol=0.0, coarse=None, fine=None, force_iters=0,
+                 warm_start=False):
     o = SchwarzOpts()
+    o.warm_start = int(warm_start)
     o.M, o.k_max, o.eps_conv, o.eps_tol = M, k_max, eps_conv, eps_tol
     o.force_iters = int(force_iters)
     o.coarse = coarse if coarse is not None else solve_opts()

@@ -97,6 +97,7 @@ typedef struct {
   double eps_conv, eps_tol;
   or_solve_opts coarse, fine;
   int force_iters;        /* > 0: run exactly this many Schwarz iterations */
+  int warm_start;         /* 1: Schwarz iterations after the first start each solve from the last one's */
 } or_schwarz_opts;
 
 typedef struct {
@@ -824,7 +825,27 @@ static double dot_masked(const double *a, const double *b, const unsigned char *
  * Direction: PCG from 0 on H d = -g with the Jacobi preconditioner, stop at
  * |r| <= cg_rtol |r_0|.  Line search: alpha = 1, halved while E does not
  * decrease, at most max_ls halvings; failure keeps u and ends the solve. */
+/* The solution of an implicit solve kept for the same solve of the next
+ * Schwarz iteration (warm start): the displacement u and node masses m of
+ * its grid, and its reference gradient norm.  have = 0 until filled. */
+typedef struct {
+  double *u, *m;
+  double gref;
+  int have;
+} or_warm;
+
+static int solve_from(or_domain *D, double dt, const or_solve_opts *opt, or_solve_stats *st, const or_warm *w);
+
 int or_solve(or_domain *D, double dt, const or_solve_opts *opt, or_solve_stats *st) {
+  return solve_from(D, dt, opt, st, NULL);
+}
+
+/* or_solve, optionally warm-started: with w filled, a free DOF of a node
+ * that was active in w's grid starts from w's displacement instead of
+ * dt v^n, and the Newton test is relative to w's reference norm (the
+ * initial gradient norm of the cold-started solve of the first Schwarz
+ * iteration), so that a start near the solution does not tighten the test. */
+static int solve_from(or_domain *D, double dt, const or_solve_opts *opt, or_solve_stats *st, const or_warm *w) {
   const int d = D->dim, nn = nnodes(D), n = d * d, ndof = nn * d;
   memset(st, 0, sizeof(*st));
   kin K;
@@ -854,6 +875,8 @@ int or_solve(or_domain *D, double dt, const or_solve_opts *opt, or_solve_stats *
         D->u[k] = 0.0;
       else if (dir[k])
         D->u[k] = ud[k];
+      else if (w && w->have && w->m[i] > 0.0)
+        D->u[k] = w->u[k];
       else
         D->u[k] = dt * D->vn[k];
     }
@@ -867,7 +890,7 @@ int or_solve(or_domain *D, double dt, const or_solve_opts *opt, or_solve_stats *
     rc = gradient_k(D, &K, dt, opt->gravity, D->u, g);
     if (rc) goto done;
     const double gn = sqrt(dot_masked(g, g, fr, ndof));
-    if (it == 0) st->gnorm0 = gn;
+    if (it == 0) st->gnorm0 = (w && w->have) ? w->gref : gn;
     st->gnorm = gn;
     const double tol = fmax(opt->newton_rtol * st->gnorm0, opt->newton_atol * gscale);
     if (gn <= tol) {
@@ -1229,6 +1252,46 @@ int or_single_frame(or_domain *D, double dt, const or_solve_opts *opt, or_solve_
   return or_g2p(D, dt);
 }
 
+/* Warm-start slots of domain D (one per implicit solve of a Schwarz
+ * iteration), or NULL when out of memory. */
+static or_warm *warm_alloc(const or_domain *D, int n_slots) {
+  or_warm *w = (or_warm *)calloc((size_t)n_slots, sizeof(or_warm));
+  if (!w) return NULL;
+  const int nn = nnodes(D);
+  for (int j = 0; j < n_slots; ++j) {
+    w[j].u = (double *)malloc(sizeof(double) * nn * D->dim);
+    w[j].m = (double *)malloc(sizeof(double) * nn);
+    if (!w[j].u || !w[j].m) {
+      for (int q = 0; q <= j; ++q) {
+        free(w[q].u);
+        free(w[q].m);
+      }
+      free(w);
+      return NULL;
+    }
+  }
+  return w;
+}
+
+static void warm_free(or_warm *w, int n_slots) {
+  if (!w) return;
+  for (int j = 0; j < n_slots; ++j) {
+    free(w[j].u);
+    free(w[j].m);
+  }
+  free(w);
+}
+
+/* Keeps a solve's solution and grid masses for the next iteration; the
+ * reference norm is that of the first (cold-started) solve. */
+static void warm_keep(or_warm *w, const or_domain *D, const or_solve_stats *ss) {
+  const int nn = nnodes(D);
+  memcpy(w->u, D->u, sizeof(double) * nn * D->dim);
+  memcpy(w->m, D->m, sizeof(double) * nn);
+  if (!w->have) w->gref = ss->gnorm0;
+  w->have = 1;
+}
+
 /* One global frame t_n -> t_{n+1} of the multiplicative Schwarz method
  * (Alg. 1, Secs. 3.3-3.5).  Readings where the paper is open:
  *  - Pi reads the latest fine P2G grid (Step 0 at k = 0, the grid after the
@@ -1254,6 +1317,7 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
   double *vGSprev = (double *)malloc(sizeof(double) * nnS * d);
   double *vGSn = (double *)malloc(sizeof(double) * nnS * d);
   double *vGSn1 = (double *)malloc(sizeof(double) * nnS * d);
+  or_warm *wB = NULL, *wS = NULL;
   if (!sx || !sv || !sB || !sF || !vBn || !vBk || !vGB || !vGBnew || !vGSprev || !vGSn || !vGSn1) {
     rc = OR_E_NOMEM;
     goto done;
@@ -1270,12 +1334,17 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
   memcpy(vBn, B->vn, sizeof(double) * nnB * d);
   if ((rc = or_project(S, B, o->eps_tol, S->vn, vGB))) goto done;
   if ((rc = or_interp(B, vBn, S, vGSprev))) goto done;
+  if (o->warm_start && (!(wB = warm_alloc(B, 1)) || !(wS = warm_alloc(S, o->M)))) {
+    rc = OR_E_NOMEM;
+    goto done;
+  }
   for (int k = 0; k < (o->force_iters > 0 ? o->force_iters : o->k_max); ++k) {
     or_solve_stats ss;
     /* 1. coarse solve over dT with Pi data on the coarse receivers */
     memcpy(B->vbc, vGB, sizeof(double) * nnB * d);
     B->use_schwarz_bc = 1;
-    if ((rc = or_solve(B, dT, &o->coarse, &ss))) goto done;
+    if ((rc = solve_from(B, dT, &o->coarse, &ss, wB))) goto done;
+    if (wB) warm_keep(wB, B, &ss);
     st->newton_B += ss.newton_iters;
     st->cg_B += ss.cg_iters;
     st->ls_B += ss.ls_halvings;
@@ -1294,7 +1363,8 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
     for (int m = 1; m <= o->M; ++m) {
       or_temporal(nnS * d, m, o->M, vGSn, vGSn1, S->vbc);
       S->use_schwarz_bc = 1;
-      if ((rc = or_solve(S, dt, &o->fine, &ss))) goto done;
+      if ((rc = solve_from(S, dt, &o->fine, &ss, wS ? &wS[m - 1] : NULL))) goto done;
+      if (wS) warm_keep(&wS[m - 1], S, &ss);
       st->newton_S += ss.newton_iters;
       st->cg_S += ss.cg_iters;
       st->ls_S += ss.ls_halvings;
@@ -1337,6 +1407,8 @@ done:
   free(vGSprev);
   free(vGSn);
   free(vGSn1);
+  warm_free(wB, 1);
+  warm_free(wS, o->M);
   return rc;
 }
 
@@ -1377,7 +1449,8 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
   double *vGBnew = (double *)malloc(sizeof(double) * nnB * d);
   double *num = (double *)malloc(sizeof(double) * nnB * d);
   double *den = (double *)malloc(sizeof(double) * nnB);
-  if (!sx || !sv || !sB || !sF || !vGSprev || !vGSn || !vGSn1 || !vBn || !vBk || !vGB || !vGBnew || !num || !den) {
+  or_warm *wB = NULL, **wS = (or_warm **)calloc((size_t)k, sizeof(or_warm *));
+  if (!wS || !sx || !sv || !sB || !sF || !vGSprev || !vGSn || !vGSn1 || !vBn || !vBk || !vGB || !vGBnew || !num || !den) {
     rc = OR_E_NOMEM;
     goto done;
   }
@@ -1429,12 +1502,19 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
   PROJECT_ALL(vGB);
   for (int f = 0; f < k; ++f)
     if ((rc = or_interp(B, vBn, S[f], vGSprev[f]))) goto done;
+  if (o->warm_start) {
+    if (!(wB = warm_alloc(B, 1))) rc = OR_E_NOMEM;
+    for (int f = 0; f < k && !rc; ++f)
+      if (!(wS[f] = warm_alloc(S[f], o->M))) rc = OR_E_NOMEM;
+    if (rc) goto done;
+  }
   for (int it = 0; it < (o->force_iters > 0 ? o->force_iters : o->k_max); ++it) {
     or_solve_stats ss;
     /* 1. coarse solve with the projected data */
     memcpy(B->vbc, vGB, sizeof(double) * nnB * d);
     B->use_schwarz_bc = 1;
-    if ((rc = or_solve(B, dT, &o->coarse, &ss))) goto done;
+    if ((rc = solve_from(B, dT, &o->coarse, &ss, wB))) goto done;
+    if (wB) warm_keep(wB, B, &ss);
     st->newton_B += ss.newton_iters;
     st->cg_B += ss.cg_iters;
     st->ls_B += ss.ls_halvings;
@@ -1456,7 +1536,8 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
       for (int m = 1; m <= o->M; ++m) {
         or_temporal(nnS * d, m, o->M, vGSn[f], vGSn1[f], Sf->vbc);
         Sf->use_schwarz_bc = 1;
-        if ((rc = or_solve(Sf, dt, &o->fine, &ss))) goto done;
+        if ((rc = solve_from(Sf, dt, &o->fine, &ss, wS[f] ? &wS[f][m - 1] : NULL))) goto done;
+        if (wS[f]) warm_keep(&wS[f][m - 1], Sf, &ss);
         st->newton_S += ss.newton_iters;
         st->cg_S += ss.cg_iters;
         st->ls_S += ss.ls_halvings;
@@ -1514,6 +1595,9 @@ done:
   free(vGBnew);
   free(num);
   free(den);
+  for (int f = 0; f < k && wS; ++f) warm_free(wS[f], o->M);
+  free(wS);
+  warm_free(wB, 1);
   return rc;
 }
 
