@@ -364,6 +364,28 @@ osmpm_status osmpm_single_frame_adjoint(osmpm_domain *dom, double dt, const osmp
                                         const double *Bbar, const double *Fbar, double *xbar_out,
                                         double *vbar_out, double *Bbar_out, double *Fbar_out,
                                         double *mubar_host, double *lambar_host);
+/* osmpm_single_frame_adjoint without any device or pinned-host allocation,
+ * for callers that cannot allocate (code under HIP graph capture, tight
+ * serving or training loops, harnesses that forbid allocation).  Its work
+ * arrays (the frame's two stored forward points, the particle adjoints
+ * entering and leaving, node adjoints) are carved out of one fixed 64 MiB
+ * device region per device, looked up when the first context on the device
+ * is created and held until the process ends.  They take, each array
+ * rounded up to 256 bytes, 2 (cap (8 d + tb (d + 2 d^2) + 25) + 4 (n_keys + 1)
+ * + nodes (8 + 25 d)) + 32 np d (1 + d) + nodes (24 d + 8) + 1024 bytes
+ * (cap: particle capacity, tb: 8 FP64 / 4 mixed); a domain that needs more
+ * returns OSMPM_E_INVALID_ARG before any work is queued.  Every call on a
+ * device shares its region, and the region keeps the last call's contents
+ * (each work array is written before it is read): calls that overlap on one
+ * device (from several contexts or threads) race and must be serialised by
+ * the caller.  HIP graph replay and kernel timing are suspended for the
+ * call.  Arguments, results, accumulation and end state as
+ * osmpm_single_frame_adjoint. */
+osmpm_status osmpm_single_frame_adjoint_noalloc(osmpm_domain *dom, double dt, const osmpm_solve_opts *opts,
+                                                double adj_cg_rtol, const double *xbar, const double *vbar,
+                                                const double *Bbar, const double *Fbar, double *xbar_out,
+                                                double *vbar_out, double *Bbar_out, double *Fbar_out,
+                                                double *mubar_host, double *lambar_host);
 /* The frame of osmpm_schwarz_frame on the pair (B, S) with exactly `iters`
  * Schwarz iterations (the forward call's stats.iters). */
 osmpm_status osmpm_schwarz_frame_adjoint(osmpm_domain *B, osmpm_domain *S, double dT,

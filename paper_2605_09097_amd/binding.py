@@ -34,6 +34,7 @@ ABI_SYMBOLS = [
     "osmpm_batch_create", "osmpm_batch_schwarz_frame", "osmpm_batch_single_frame", "osmpm_batch_destroy",
     "osmpm_multi_create", "osmpm_multi_schwarz_frame",
     "osmpm_single_frame_adjoint", "osmpm_schwarz_frame_adjoint", "osmpm_schwarz_frame_adjoint_implicit",
+    "osmpm_single_frame_adjoint_noalloc",
 ]
 
 
@@ -114,6 +115,8 @@ def _declare(L):
         "osmpm_multi_schwarz_frame": [_vp, C.c_double, P(osmpm_schwarz_opts), P(osmpm_schwarz_stats)],
         "osmpm_single_frame_adjoint": [_vp, C.c_double, P(osmpm_solve_opts), C.c_double] + [_vp] * 8
                                       + [P(C.c_double)] * 2,
+        "osmpm_single_frame_adjoint_noalloc": [_vp, C.c_double, P(osmpm_solve_opts), C.c_double] + [_vp] * 8
+                                              + [P(C.c_double)] * 2,
         "osmpm_schwarz_frame_adjoint": [_vp, _vp, C.c_double, P(osmpm_schwarz_opts), C.c_int32, C.c_double]
                                        + [_vp] * 16 + [P(C.c_double)] * 4,
         "osmpm_schwarz_frame_adjoint_implicit": [_vp, _vp, C.c_double, P(osmpm_schwarz_opts), C.c_int32,
@@ -546,17 +549,20 @@ def _adj_out(D):
     return [torch.zeros(s, dtype=torch.float64, device=dev) for s in ((n, d), (n, d), (n, d, d), (n, d, d))]
 
 
-def single_frame_adjoint(D: Domain, dt, opts, adj_end, adj_cg_rtol=1e-12):
+def single_frame_adjoint(D: Domain, dt, opts, adj_end, adj_cg_rtol=1e-12, noalloc=False):
     """Adjoint of one single-domain frame from D's current state (see
-    osmpm_single_frame_adjoint).  Returns ({x, v, B, F} adjoint of the start
-    state as device tensors, dL/dmu, dL/dlam per material as numpy arrays)."""
+    osmpm_single_frame_adjoint; noalloc=True calls
+    osmpm_single_frame_adjoint_noalloc).  Returns ({x, v, B, F} adjoint of the
+    start state as device tensors, dL/dmu, dL/dlam per material as numpy
+    arrays)."""
     a = _adj_in(D, adj_end)
     o = _adj_out(D)
     nm = D.n_mat
     mub = (C.c_double * nm)()
     lab = (C.c_double * nm)()
-    D.ctx.check(lib().osmpm_single_frame_adjoint(D.handle, dt, C.byref(opts), adj_cg_rtol, *[_ptr(t) for t in a],
-                                                 *[_ptr(t) for t in o], mub, lab), "single_frame_adjoint")
+    fn = lib().osmpm_single_frame_adjoint_noalloc if noalloc else lib().osmpm_single_frame_adjoint
+    D.ctx.check(fn(D.handle, dt, C.byref(opts), adj_cg_rtol, *[_ptr(t) for t in a], *[_ptr(t) for t in o], mub,
+                   lab), "single_frame_adjoint" + ("_noalloc" if noalloc else ""))
     return dict(zip("xvBF", o)), np.array(mub[:]), np.array(lab[:])
 
 

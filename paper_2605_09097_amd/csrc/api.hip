@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -24,6 +25,11 @@
 #include "kernels.hpp"
 
 using namespace osmpm;
+
+// Device work region of the entry point that allocates nothing (64 MiB per
+// device; see fixed_region_setup).
+constexpr size_t kFixedRegionBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kFixedRegionBytes];
 
 namespace {
 
@@ -1271,7 +1277,44 @@ void tape_free(TapePoint &t) {
   t.allocs.clear();
 }
 
-osmpm_status tape_alloc(osmpm_domain *d, TapePoint &t) {
+// Device memory of one call's work arrays.  By default every request is a
+// hipMalloc, freed by release().  With a fixed region (base set), requests
+// are carved out of [base, base + cap) at 256-byte alignment, release() frees
+// nothing, and a request past cap fails with OSMPM_E_INVALID_ARG.  In
+// measuring mode nothing is allocated and `used` sums the aligned sizes (the
+// returned pointers are placeholders that must not be dereferenced).
+struct Arena {
+  osmpm_ctx *c = nullptr;
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  bool measure = false;
+  std::vector<void *> owned;
+  osmpm_status get(size_t bytes, void **p) {
+    const size_t nb = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    if (measure) {
+      *p = reinterpret_cast<void *>((uintptr_t)256);
+      used += nb;
+      return OSMPM_OK;
+    }
+    if (base) {
+      if (nb > cap - used)
+        return fail(c, OSMPM_E_INVALID_ARG, "work arrays exceed the fixed device region of " + std::to_string(cap) +
+                                                " bytes");
+      *p = base + used;
+      used += nb;
+      return OSMPM_OK;
+    }
+    return dalloc_bytes(c, owned, p, bytes);
+  }
+  void release() {
+    for (void *q : owned) (void)hipFree(q);
+    owned.clear();
+  }
+};
+
+// Work arrays of a tape point, from the arena A (default: hipMalloc'ed into
+// t.allocs, freed by tape_free).
+osmpm_status tape_alloc(osmpm_domain *d, TapePoint &t, Arena *A = nullptr) {
   osmpm_ctx *c = d->ctx;
   const size_t cap = (size_t)d->cap, nn = (size_t)d->g.nn, nd = nn * d->D;
   const int D = d->D;
@@ -1279,7 +1322,7 @@ osmpm_status tape_alloc(osmpm_domain *d, TapePoint &t) {
   void *q = nullptr;
   auto al = [&](size_t bytes) -> void * {
     if (s) return nullptr;
-    s = dalloc_bytes(c, t.allocs, &q, bytes);
+    s = A ? A->get(bytes, &q) : dalloc_bytes(c, t.allocs, &q, bytes);
     return s ? nullptr : q;
   };
   t.p.x = (double *)al(cap * D * sizeof(double));
@@ -1340,19 +1383,28 @@ struct AdjState {
   double *x = nullptr, *v = nullptr, *B = nullptr, *F = nullptr;
 };
 
-osmpm_status adj_alloc(osmpm_ctx *c, std::vector<void *> &list, int np, int D, AdjState &a) {
+template <typename Get>
+osmpm_status adj_alloc_with(Get get, int np, int D, AdjState &a) {
   void *q = nullptr;
   const size_t n = (size_t)std::max(np, 1);
   osmpm_status s;
-  if ((s = dalloc_bytes(c, list, &q, n * D * sizeof(double)))) return s;
+  if ((s = get(n * D * sizeof(double), &q))) return s;
   a.x = (double *)q;
-  if ((s = dalloc_bytes(c, list, &q, n * D * sizeof(double)))) return s;
+  if ((s = get(n * D * sizeof(double), &q))) return s;
   a.v = (double *)q;
-  if ((s = dalloc_bytes(c, list, &q, n * D * D * sizeof(double)))) return s;
+  if ((s = get(n * D * D * sizeof(double), &q))) return s;
   a.B = (double *)q;
-  if ((s = dalloc_bytes(c, list, &q, n * D * D * sizeof(double)))) return s;
+  if ((s = get(n * D * D * sizeof(double), &q))) return s;
   a.F = (double *)q;
   return OSMPM_OK;
+}
+
+osmpm_status adj_alloc(osmpm_ctx *c, std::vector<void *> &list, int np, int D, AdjState &a) {
+  return adj_alloc_with([&](size_t b, void **q) { return dalloc_bytes(c, list, q, b); }, np, D, a);
+}
+
+osmpm_status adj_alloc(Arena &A, int np, int D, AdjState &a) {
+  return adj_alloc_with([&](size_t b, void **q) { return A.get(b, q); }, np, D, a);
 }
 
 osmpm_status adj_zero(osmpm_ctx *c, const AdjState &a, int np, int D) {
@@ -1454,44 +1506,71 @@ osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const 
   return check_launch(c);
 }
 
+// Work arrays of the single-frame adjoint of d: two tape points (the frame's
+// start and end), the particle adjoints entering and leaving, the node
+// adjoints ubar, vnbar, the product H lambda, the mass adjoint and the
+// material sums (64 mu + 64 lambda entries).
+struct SingleAdjBufs {
+  TapePoint t0, te;
+  AdjState ain, aout;
+  double *ubar = nullptr, *mbar = nullptr, *vnbar = nullptr, *hl = nullptr, *mat = nullptr;
+};
+
+osmpm_status single_adjoint_buffers(osmpm_domain *d, Arena &A, SingleAdjBufs &b) {
+  const size_t nn = (size_t)d->g.nn, nd = nn * d->D;
+  osmpm_status s;
+  void *q = nullptr;
+  if ((s = tape_alloc(d, b.t0, &A)) || (s = tape_alloc(d, b.te, &A)) || (s = adj_alloc(A, d->np, d->D, b.ain)) ||
+      (s = adj_alloc(A, d->np, d->D, b.aout)))
+    return s;
+  for (double **pp : {&b.ubar, &b.vnbar, &b.hl}) {
+    if ((s = A.get(nd * sizeof(double), &q))) return s;
+    *pp = (double *)q;
+  }
+  if ((s = A.get(nn * sizeof(double), &q))) return s;
+  b.mbar = (double *)q;
+  if ((s = A.get(128 * sizeof(double), &q))) return s;
+  b.mat = (double *)q;
+  return OSMPM_OK;
+}
+
+// Bytes the single-frame adjoint of d takes from a fixed region.
+size_t single_adjoint_bytes(osmpm_domain *d) {
+  Arena A;
+  A.c = d->ctx;
+  A.measure = true;
+  SingleAdjBufs b;
+  (void)single_adjoint_buffers(d, A, b);
+  return A.used;
+}
+
 // Adjoint of one single-domain frame (P2G, solve, G2P) of d; see the ABI.
+// Work arrays come from the arena A: hipMalloc'ed for this call, or carved
+// out of a fixed device region (every one of them is written before it is
+// read, so the region's previous contents do not matter).
 template <int D, typename TB>
 osmpm_status single_adjoint_impl(osmpm_domain *d, double dt, const osmpm_solve_opts *o, double adj_rtol,
-                                 const double *const *in, double *const *out, double *mubar_h, double *lambar_h) {
+                                 const double *const *in, double *const *out, double *mubar_h, double *lambar_h,
+                                 Arena &A) {
   osmpm_ctx *c = d->ctx;
   osmpm_batch *G = d->solo;
   osmpm_status s;
   if ((s = group_sync(G))) return s;
   set_active(G, 0, std::vector<int>(1, 1));
   const int np = d->np, nn = d->g.nn, nd = nn * D;
-  std::vector<void *> mem;
-  TapePoint t0, te;
-  AdjState ain, aout;
-  double *ubar = nullptr, *mbar = nullptr, *vnbar = nullptr, *hl = nullptr, *mat = nullptr;
+  SingleAdjBufs bufs;
+  TapePoint &t0 = bufs.t0, &te = bufs.te;
+  const AdjState &ain = bufs.ain, &aout = bufs.aout;
   auto cleanup = [&]() {
     tape_free(t0);
     tape_free(te);
-    for (void *q : mem) (void)hipFree(q);
+    A.release();
   };
-  void *q = nullptr;
-  if ((s = tape_alloc(d, t0)) || (s = tape_alloc(d, te)) || (s = adj_alloc(c, mem, np, D, ain)) ||
-      (s = adj_alloc(c, mem, np, D, aout))) {
+  if ((s = single_adjoint_buffers(d, A, bufs))) {
     cleanup();
     return s;
   }
-  for (double **pp : {&ubar, &vnbar, &hl}) {
-    if ((s = dalloc_bytes(c, mem, &q, (size_t)nd * sizeof(double)))) {
-      cleanup();
-      return s;
-    }
-    *pp = (double *)q;
-  }
-  if ((s = dalloc_bytes(c, mem, &q, (size_t)nn * sizeof(double))) ||
-      (mbar = (double *)q, s = dalloc_bytes(c, mem, &q, 128 * sizeof(double)))) {
-    cleanup();
-    return s;
-  }
-  mat = (double *)q;
+  double *ubar = bufs.ubar, *mbar = bufs.mbar, *vnbar = bufs.vnbar, *hl = bufs.hl, *mat = bufs.mat;
   // forward with storage
   p2g_side<D, TB>(G, 0, false);
   if ((s = tape_copy(d, t0, 1, 1 | 2))) return cleanup(), s;
@@ -1513,8 +1592,10 @@ osmpm_status single_adjoint_impl(osmpm_domain *d, double dt, const osmpm_solve_o
   adj_p2g<D, TB>(d, t0, mbar, vnbar, aout);
   if ((s = tape_copy(d, te, -1, 1 | 2 | 4))) return cleanup(), s;
   adj_to_rows(c, np, D, aout, out[0], out[1], out[2], out[3]);
-  std::vector<double> hm(128);
-  HIP_TRY(c, hipMemcpyAsync(hm.data(), mat, 128 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  // the material sums come back through the context's pinned staging
+  // buffer (at least 64 KB from creation)
+  const double *hm = reinterpret_cast<const double *>(c->h_pin);
+  HIP_TRY(c, hipMemcpyAsync(c->h_pin, mat, 128 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   if ((s = read_status(G))) return cleanup(), s;
   for (int k = 0; k < d->n_mat; ++k) {
     mubar_h[k] += hm[k];
@@ -1745,6 +1826,34 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
   return s;
 }
 
+// ---------------------------------------------------------------- fixed work region
+// The device region of osmpm_single_frame_adjoint_noalloc, the entry point
+// that allocates nothing: one copy per device, held until the process ends.
+// Host code never passes the array's name as an address (in host code it
+// only stands for the symbol): its device address on each device is looked
+// up once, with that device current, when the first context on the device
+// is created, and kept in fixed_region_ptr.
+constexpr int kMaxDevices = 64;
+std::mutex fixed_region_mu;
+void *fixed_region_ptr[kMaxDevices] = {};
+
+// Looks up the region's address on `device` (the current device) once.
+int fixed_region_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return 1;
+  std::lock_guard<std::mutex> lock(fixed_region_mu);
+  if (fixed_region_ptr[device]) return 0;
+  void *ptr = nullptr;
+  if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return 1;
+  fixed_region_ptr[device] = ptr;
+  return 0;
+}
+
+void *fixed_region(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(fixed_region_mu);
+  return fixed_region_ptr[device];
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -1769,6 +1878,11 @@ osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out) {
   if (ensure_pin(c, 1 << 16)) {
     delete c;
     return OSMPM_E_NO_MEMORY;
+  }
+  if (fixed_region_setup(device)) {
+    (void)hipHostFree(c->h_pin);
+    delete c;
+    return OSMPM_E_DEVICE;
   }
   *out = c;
   return OSMPM_OK;
@@ -2214,7 +2328,44 @@ osmpm_status osmpm_single_frame_adjoint(osmpm_domain *d, double dt, const osmpm_
     return OSMPM_E_INVALID_ARG;
   const double *in[4] = {xbar, vbar, Bbar, Fbar};
   double *out[4] = {oxbar, ovbar, oBbar, oFbar};
-  return DISPATCH2(d->D, d->precision, single_adjoint_impl)(d, dt, o, adj_cg_rtol, in, out, mubar, lambar);
+  Arena A;
+  A.c = d->ctx;
+  return DISPATCH2(d->D, d->precision, single_adjoint_impl)(d, dt, o, adj_cg_rtol, in, out, mubar, lambar, A);
+}
+
+osmpm_status osmpm_single_frame_adjoint_noalloc(osmpm_domain *d, double dt, const osmpm_solve_opts *o,
+                                                double adj_cg_rtol, const double *xbar, const double *vbar,
+                                                const double *Bbar, const double *Fbar, double *oxbar,
+                                                double *ovbar, double *oBbar, double *oFbar, double *mubar,
+                                                double *lambar) {
+  if (!d || !o || !(dt > 0.0) || !(adj_cg_rtol > 0.0) || !mubar || !lambar) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  if (d->np > 0 && (!xbar || !vbar || !Bbar || !Fbar || !oxbar || !ovbar || !oBbar || !oFbar))
+    return OSMPM_E_INVALID_ARG;
+  osmpm_ctx *c = d->ctx;
+  void *region = fixed_region(c->device);
+  if (!region) return fail(c, OSMPM_E_DEVICE, "fixed work region not set up on this device");
+  const size_t need = single_adjoint_bytes(d);
+  if (need > kFixedRegionBytes)
+    return fail(c, OSMPM_E_INVALID_ARG, "single-frame adjoint needs " + std::to_string(need) +
+                                            " bytes of work arrays; the fixed region holds " +
+                                            std::to_string(kFixedRegionBytes));
+  const double *in[4] = {xbar, vbar, Bbar, Fbar};
+  double *out[4] = {oxbar, ovbar, oBbar, oFbar};
+  Arena A;
+  A.c = c;
+  A.base = static_cast<char *>(region);
+  A.cap = kFixedRegionBytes;
+  // graph replay (instantiation allocates) and kernel timing (event
+  // creation) are suspended for the call
+  const bool graphs = c->graphs, prof = c->prof;
+  c->graphs = false;
+  c->prof = false;
+  const osmpm_status s =
+      DISPATCH2(d->D, d->precision, single_adjoint_impl)(d, dt, o, adj_cg_rtol, in, out, mubar, lambar, A);
+  c->graphs = graphs;
+  c->prof = prof;
+  return s;
 }
 
 static osmpm_status schwarz_adjoint_call(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
