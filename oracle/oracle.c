@@ -1322,7 +1322,8 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
     rc = OR_E_NOMEM;
     goto done;
   }
-  /* Step 0: store fine state (Eq. store_states), P2G on both, boundary sets. */
+  /* Frame start: the fine state is stored (Eq. store_states), both grids are
+   * built and the interface sets formed. */
   memcpy(sx, S->x, sizeof(double) * npS * d);
   memcpy(sv, S->v, sizeof(double) * npS * d);
   memcpy(sB, S->B, sizeof(double) * npS * d * d);
@@ -1340,7 +1341,7 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
   }
   for (int k = 0; k < (o->force_iters > 0 ? o->force_iters : o->k_max); ++k) {
     or_solve_stats ss;
-    /* 1. coarse solve over dT with Pi data on the coarse receivers */
+    /* the coarse solve over dT with the projected data on its receivers */
     memcpy(B->vbc, vGB, sizeof(double) * nnB * d);
     B->use_schwarz_bc = 1;
     if ((rc = solve_from(B, dT, &o->coarse, &ss, wB))) goto done;
@@ -1352,7 +1353,8 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
     st->lsfail_B += ss.ls_failed;
     for (int i = 0; i < nnB; ++i)
       for (int a = 0; a < d; ++a) vBk[i * d + a] = (B->m[i] > 0.0) ? B->u[i * d + a] / dT : 0.0;
-    /* 2. fine sub-cycling from the restored state */
+    /* the fine domain restarts from the stored state: M sub-steps driven by
+     * the temporal interpolation of the two coarse endpoints */
     memcpy(S->x, sx, sizeof(double) * npS * d);
     memcpy(S->v, sv, sizeof(double) * npS * d);
     memcpy(S->B, sB, sizeof(double) * npS * d * d);
@@ -1373,7 +1375,8 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
       if ((rc = or_g2p(S, dt))) goto done;
       if ((rc = or_p2g(S))) goto done;
     }
-    /* 3. convergence check (Eqs. convergence_residuals, convergence_criterion) */
+    /* projection for the next iteration and the interface changes (Eqs.
+     * convergence_residuals, convergence_criterion) */
     if ((rc = or_project(S, B, o->eps_tol, S->vn, vGBnew))) goto done;
     double nB, nS;
     const double dB = norm_diff_masked(vGBnew, vGB, B->recv, nnB, d, &nB);
@@ -1393,7 +1396,7 @@ int or_schwarz_frame(or_domain *B, or_domain *S, double dT, const or_schwarz_opt
       break;
     }
   }
-  /* 4. post-convergence coarse G2P and advection (Sec. 3.5) */
+  /* the coarse particles move with the last coarse solution (Sec. 3.5) */
   rc = or_g2p(B, dT);
 done:
   free(sx);
@@ -1412,23 +1415,102 @@ done:
   return rc;
 }
 
-/* Alg. 1 with one coarse domain B and k fine domains S[0..k-1] whose
- * particle sets are disjoint and which overlap B only (the several refined
- * regions the conclusion names as future work; readings, since the paper
- * gives no algorithm for them):
+/* Node of G at the lattice point of node i of A, or -1 when G has none. */
+static int coincident_node(const or_domain *A, int i, const or_domain *G) {
+  int ia[3], jg[3] = {0, 0, 0};
+  node_index(A, i, ia);
+  for (int a = 0; a < A->dim; ++a) {
+    const long long L = A->origin_q[a] + (long long)ia[a] * A->dx_q;
+    const long long t = L - G->origin_q[a];
+    if (t < 0 || t % G->dx_q != 0 || t / G->dx_q >= G->n[a]) return -1;
+    jg[a] = (int)(t / G->dx_q);
+  }
+  return node_flat(G, jg);
+}
+
+/* Fine-fine links of a multi-domain frame.  Arbitration between fine
+ * domains (Eq. overlap_donor generalised pairwise): a node in the boundary
+ * sets of fine domains f and g at the same lattice point is ambiguous; the
+ * side with the larger fixed-point node mass donates (ties: the lower
+ * index) and leaves its own receiver set.  Then every remaining receiver
+ * node j of f that lies in the material of another fine domain (the
+ * coincident node active with a fixed-point mass above that domain's
+ * selection threshold) takes its data from the one of largest mass (ties:
+ * the lower index): link_g[f][j] = g, link_n[f][j] = its node; -1 where the
+ * coarse domain donates.  Returns the number of linked nodes. */
+static int fine_links(or_domain **S, int k, int **link_g, int **link_n, int *n_amb) {
+  int links = 0;
+  for (int f = 0; f < k; ++f) {
+    const int nn = nnodes(S[f]);
+    for (int j = 0; j < nn; ++j) {
+      if (!S[f]->gamma[j]) continue;
+      int donor = 0;
+      for (int g = 0; g < k; ++g) {
+        if (g == f) continue;
+        const int jg = coincident_node(S[f], j, S[g]);
+        if (jg < 0 || !S[g]->gamma[jg]) continue;
+        if (f < g) *n_amb += 1;
+        const long long qf = S[f]->q_all[j], qg = S[g]->q_all[jg];
+        if (qf > qg || (qf == qg && f < g)) donor = 1;
+      }
+      link_g[f][j] = donor ? -2 : -1; /* -2: leaves the receiver set (below) */
+    }
+  }
+  for (int f = 0; f < k; ++f) {
+    const int nn = nnodes(S[f]);
+    for (int j = 0; j < nn; ++j) {
+      if (link_g[f][j] == -2) S[f]->recv[j] = 0;
+      link_g[f][j] = -1;
+      link_n[f][j] = -1;
+    }
+  }
+  for (int f = 0; f < k; ++f) {
+    const int nn = nnodes(S[f]);
+    for (int j = 0; j < nn; ++j) {
+      if (!S[f]->recv[j]) continue;
+      long long best = 0;
+      for (int g = 0; g < k; ++g) {
+        if (g == f) continue;
+        const int jg = coincident_node(S[f], j, S[g]);
+        if (jg < 0 || !(S[g]->m[jg] > 0.0)) continue;
+        const long long q = S[g]->q_all[jg];
+        if (q <= llrint(S[g]->tau * fixed_scale(S[g]))) continue;
+        if (link_g[f][j] < 0 || q > best) {
+          link_g[f][j] = g;
+          link_n[f][j] = jg;
+          best = q;
+        }
+      }
+      if (link_g[f][j] >= 0) links += 1;
+    }
+  }
+  return links;
+}
+
+/* Alg. 1 with one coarse domain B and k fine domains S[0..k-1] that overlap
+ * B and possibly each other (the several refined regions the conclusion
+ * names as future work; readings, since the paper gives no algorithm for
+ * them):
  *  - boundary sets as for a pair; each fine domain is arbitrated against B
- *    by the two-domain rule (Eq. overlap_donor), in index order;
+ *    by the two-domain rule (Eq. overlap_donor), in index order, and fine
+ *    domains against each other pairwise (fine_links);
  *  - Pi (Eq. spatial_projection) over the union of the fine point masses:
  *    numerator and denominator summed over all fine domains, then divided on
  *    the coarse receivers;
- *  - each iteration: coarse solve, then every fine domain in index order
- *    restored, P2G, interpolated at both endpoints from the same coarse
- *    solution and sub-cycled (they couple only through B, so their order
- *    does not matter);
- *  - r_B over the coarse receivers, r_S over the receivers of all fine
- *    domains together (Eqs. convergence_residuals, convergence_criterion).
- * With k = 1 every step is that of or_schwarz_frame.  Statistics sum the
- * fine domains' counts. */
+ *  - each iteration: coarse solve, then every fine domain restored, P2G,
+ *    interpolated at both endpoints from the same coarse solution and
+ *    sub-cycled.  A fine receiver linked to another fine domain g takes, at
+ *    sub-step m, g's grid velocity u/dt of sub-step m of the previous
+ *    iteration (fine domains exchange data between iterations, like a block
+ *    Jacobi step, so their order does not matter); in the first iteration,
+ *    and where g's node was inactive, the coarse data as for the others;
+ *  - r_B over the coarse receivers; r_S over the receivers of all fine
+ *    domains together, where a linked receiver's datum is its donor's
+ *    end-of-frame velocity u/dt of sub-step M (Eqs. convergence_residuals,
+ *    convergence_criterion).
+ * Fine domains that do not touch each other have no links, and every step
+ * is then that of the disjoint case; with k = 1 that of or_schwarz_frame.
+ * Statistics sum the fine domains' counts. */
 int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const or_schwarz_opts *o,
                            or_schwarz_stats *st) {
   if (k < 1) return OR_E_ARG;
@@ -1450,7 +1532,13 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
   double *num = (double *)malloc(sizeof(double) * nnB * d);
   double *den = (double *)malloc(sizeof(double) * nnB);
   or_warm *wB = NULL, **wS = (or_warm **)calloc((size_t)k, sizeof(or_warm *));
-  if (!wS || !sx || !sv || !sB || !sF || !vGSprev || !vGSn || !vGSn1 || !vBn || !vBk || !vGB || !vGBnew || !num || !den) {
+  /* fine-fine links and the sub-step solutions they read (previous and
+   * current iteration: [m][node][d] and [m][node] per fine domain) */
+  int **link_g = (int **)calloc((size_t)k, sizeof(int *)), **link_n = (int **)calloc((size_t)k, sizeof(int *));
+  double **prevU = (double **)calloc((size_t)k, sizeof(double *)), **prevM = (double **)calloc((size_t)k, sizeof(double *));
+  double **curU = (double **)calloc((size_t)k, sizeof(double *)), **curM = (double **)calloc((size_t)k, sizeof(double *));
+  int n_links = 0, have_prev = 0;
+  if (!link_g || !link_n || !prevU || !prevM || !curU || !curM || !wS || !sx || !sv || !sB || !sF || !vGSprev || !vGSn || !vGSn1 || !vBn || !vBk || !vGB || !vGBnew || !num || !den) {
     rc = OR_E_NOMEM;
     goto done;
   }
@@ -1463,12 +1551,15 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
     vGSprev[f] = (double *)malloc(sizeof(double) * nnS * d);
     vGSn[f] = (double *)malloc(sizeof(double) * nnS * d);
     vGSn1[f] = (double *)malloc(sizeof(double) * nnS * d);
-    if (!sx[f] || !sv[f] || !sB[f] || !sF[f] || !vGSprev[f] || !vGSn[f] || !vGSn1[f]) {
+    link_g[f] = (int *)malloc(sizeof(int) * nnS);
+    link_n[f] = (int *)malloc(sizeof(int) * nnS);
+    if (!sx[f] || !sv[f] || !sB[f] || !sF[f] || !vGSprev[f] || !vGSn[f] || !vGSn1[f] || !link_g[f] || !link_n[f]) {
       rc = OR_E_NOMEM;
       goto done;
     }
   }
-  /* Step 0: store the fine states, P2G everywhere, boundary sets, arbitration */
+  /* Frame start: fine states stored, all grids built, boundary sets and
+   * arbitration */
   for (int f = 0; f < k; ++f) {
     const or_domain *Sf = S[f];
     memcpy(sx[f], Sf->x, sizeof(double) * Sf->np * d);
@@ -1484,6 +1575,18 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
     int amb = 0;
     if ((rc = boundary_set(S[f])) || (rc = arbitrate(B, S[f], &amb))) goto done;
     st->n_amb += amb;
+  }
+  n_links = fine_links(S, k, link_g, link_n, &st->n_amb);
+  for (int f = 0; f < k && n_links; ++f) {
+    const size_t nnS = (size_t)nnodes(S[f]), M = (size_t)o->M;
+    prevU[f] = (double *)malloc(sizeof(double) * M * nnS * d);
+    prevM[f] = (double *)malloc(sizeof(double) * M * nnS);
+    curU[f] = (double *)malloc(sizeof(double) * M * nnS * d);
+    curM[f] = (double *)malloc(sizeof(double) * M * nnS);
+    if (!prevU[f] || !prevM[f] || !curU[f] || !curM[f]) {
+      rc = OR_E_NOMEM;
+      goto done;
+    }
   }
   for (int i = 0; i < nnB; ++i) st->n_recv_B += B->recv[i];
   for (int f = 0; f < k; ++f)
@@ -1510,7 +1613,7 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
   }
   for (int it = 0; it < (o->force_iters > 0 ? o->force_iters : o->k_max); ++it) {
     or_solve_stats ss;
-    /* 1. coarse solve with the projected data */
+    /* the coarse solve with the projected data */
     memcpy(B->vbc, vGB, sizeof(double) * nnB * d);
     B->use_schwarz_bc = 1;
     if ((rc = solve_from(B, dT, &o->coarse, &ss, wB))) goto done;
@@ -1522,7 +1625,7 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
     st->lsfail_B += ss.ls_failed;
     for (int i = 0; i < nnB; ++i)
       for (int a = 0; a < d; ++a) vBk[i * d + a] = (B->m[i] > 0.0) ? B->u[i * d + a] / dT : 0.0;
-    /* 2. every fine domain sub-cycled from its stored state */
+    /* every fine domain restarts from its stored state and is sub-cycled */
     for (int f = 0; f < k; ++f) {
       or_domain *Sf = S[f];
       const int nnS = nnodes(Sf);
@@ -1535,9 +1638,22 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
       if ((rc = or_interp(B, vBk, Sf, vGSn1[f]))) goto done;
       for (int m = 1; m <= o->M; ++m) {
         or_temporal(nnS * d, m, o->M, vGSn[f], vGSn1[f], Sf->vbc);
+        /* linked receivers: the donor's sub-step-m velocity of the previous
+         * iteration, where its node was active */
+        for (int j = 0; j < nnS && have_prev; ++j) {
+          const int g = link_g[f][j];
+          if (g < 0) continue;
+          const size_t jg = (size_t)(m - 1) * nnodes(S[g]) + link_n[f][j];
+          if (!(prevM[g][jg] > 0.0)) continue;
+          for (int a = 0; a < d; ++a) Sf->vbc[j * d + a] = prevU[g][jg * d + a] / dt;
+        }
         Sf->use_schwarz_bc = 1;
         if ((rc = solve_from(Sf, dt, &o->fine, &ss, wS[f] ? &wS[f][m - 1] : NULL))) goto done;
         if (wS[f]) warm_keep(&wS[f][m - 1], Sf, &ss);
+        if (n_links) {
+          memcpy(curU[f] + (size_t)(m - 1) * nnS * d, Sf->u, sizeof(double) * nnS * d);
+          memcpy(curM[f] + (size_t)(m - 1) * nnS, Sf->m, sizeof(double) * nnS);
+        }
         st->newton_S += ss.newton_iters;
         st->cg_S += ss.cg_iters;
         st->ls_S += ss.ls_halvings;
@@ -1547,7 +1663,28 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
         if ((rc = or_p2g(Sf))) goto done;
       }
     }
-    /* 3. convergence over all interfaces */
+    /* linked receivers' data for the residual: the donor's end-of-frame
+     * velocity (sub-step M) of this iteration */
+    for (int f = 0; f < k && n_links; ++f)
+      for (int j = 0; j < nnodes(S[f]); ++j) {
+        const int g = link_g[f][j];
+        if (g < 0) continue;
+        const size_t jg = (size_t)(o->M - 1) * nnodes(S[g]) + link_n[f][j];
+        if (!(curM[g][jg] > 0.0)) continue;
+        for (int a = 0; a < d; ++a) vGSn1[f][j * d + a] = curU[g][jg * d + a] / dt;
+      }
+    if (n_links) {
+      for (int f = 0; f < k; ++f) {
+        double *t = prevU[f];
+        prevU[f] = curU[f];
+        curU[f] = t;
+        t = prevM[f];
+        prevM[f] = curM[f];
+        curM[f] = t;
+      }
+      have_prev = 1;
+    }
+    /* projection for the next iteration and changes over all interfaces */
     PROJECT_ALL(vGBnew);
     double nB, dB_ = norm_diff_masked(vGBnew, vGB, B->recv, nnB, d, &nB);
     double dS2 = 0.0, nS2 = 0.0;
@@ -1570,7 +1707,7 @@ int or_schwarz_frame_multi(or_domain *B, or_domain **S, int k, double dT, const 
     if (st->converged) break;
   }
 #undef PROJECT_ALL
-  /* 4. post-convergence coarse G2P and advection (Sec. 3.5) */
+  /* the coarse particles move with the last coarse solution (Sec. 3.5) */
   rc = or_g2p(B, dT);
 done:
   for (int f = 0; f < k; ++f) {
@@ -1595,6 +1732,20 @@ done:
   free(vGBnew);
   free(num);
   free(den);
+  for (int f = 0; f < k; ++f) {
+    if (link_g) free(link_g[f]);
+    if (link_n) free(link_n[f]);
+    if (prevU) free(prevU[f]);
+    if (prevM) free(prevM[f]);
+    if (curU) free(curU[f]);
+    if (curM) free(curM[f]);
+  }
+  free(link_g);
+  free(link_n);
+  free(prevU);
+  free(prevM);
+  free(curU);
+  free(curM);
   for (int f = 0; f < k && wS; ++f) warm_free(wS[f], o->M);
   free(wS);
   warm_free(wB, 1);

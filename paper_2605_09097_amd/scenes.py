@@ -234,18 +234,24 @@ class MultiScene:
 
 def two_inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.04, E_matrix=1e4, E_inc=1e5, nu=0.3,
                         rho=1000.0, seed=0, dT=1e-3, M=2, n_frames=50, top_disp=0.01, ramp_frames=50,
-                        tau_rel=1e-3, eps_tol_rel=1e-9, delta=0.0, name="two_inclusions"):
+                        tau_rel=1e-3, eps_tol_rel=1e-9, delta=0.0, centres=((0.3, 0.5), (0.7, 0.5)),
+                        name="two_inclusions"):
     """Two refined regions in one matrix (several refined subdomains, named as
     future work in the conclusion): the matrix square [0.1,0.9]^2 with
-    inclusions r <= r_inc around c1 = (0.3, 0.5) and c2 = (0.7, 0.5).  Fine
-    domain i holds the material within r = 0.12 of c_i on the box c_i +-
-    0.16; the coarse domain the matrix outside r = 0.08 of both centres.  The
-    fine regions are 0.16 apart, so they meet only the coarse domain.  Loaded
-    like inclusion_scene (bottom clamped, top driven down)."""
+    inclusions r <= r_inc around the two centres (default c1 = (0.3, 0.5),
+    c2 = (0.7, 0.5)).  Fine domain i holds the material within r = 0.12 of
+    c_i on the box c_i +- 0.16; the coarse domain the matrix outside r = 0.08
+    of both centres.  With the default centres the fine regions are 0.16
+    apart and meet only the coarse domain; centres closer than 0.24 make the
+    fine regions overlap each other (both carry the material of the lens
+    between them).  S_union is one fine domain over both regions (their
+    particles concatenated when disjoint, the union region sampled once when
+    they overlap).  Loaded like inclusion_scene (bottom clamped, top driven
+    down)."""
     lat = math.lcm(inv_dx_B, inv_dx_S, 10)
     h0 = 1.0 / lat
     dxq_B, dxq_S = lat // inv_dx_B, lat // inv_dx_S
-    cs = [np.array([0.3, 0.5]), np.array([0.7, 0.5])]
+    cs = [np.array(c, dtype=np.float64) for c in centres]
     R_f, R_h = 0.12, 0.08
     spB, spS = 1.0 / (inv_dx_B * ppc1d), 1.0 / (inv_dx_S * ppc1d)
 
@@ -275,14 +281,19 @@ def two_inclusion_scene(inv_dx_B=20, inv_dx_S=50, ppc1d=2, r_inc=0.04, E_matrix=
         Ss.append(_domain(2, h0, [lo[0] * dxq_S, lo[1] * dxq_S], dxq_S, [hi[0] - lo[0] + 1, hi[1] - lo[1] + 1], xS,
                           mat, [E_matrix, E_inc], [nu, nu], rho, ppc1d, flags, [], [], m_ref, tau_rel, F0=F0))
         parts.append((xS, mat, flags))
-    ulo = [int(math.floor(0.14 * inv_dx_S + 1e-9)), int(math.floor(0.34 * inv_dx_S + 1e-9))]
-    uhi = [int(math.ceil(0.86 * inv_dx_S - 1e-9)), int(math.ceil(0.66 * inv_dx_S - 1e-9))]
-    xU = np.concatenate([q[0] for q in parts])
-    matU = np.concatenate([q[1] for q in parts])
+    ulo = [int(math.floor((min(c[a] for c in cs) - 0.16) * inv_dx_S + 1e-9)) for a in range(2)]
+    uhi = [int(math.ceil((max(c[a] for c in cs) + 0.16) * inv_dx_S - 1e-9)) for a in range(2)]
+    if np.linalg.norm(cs[0] - cs[1]) >= 2 * R_f:
+        xU = np.concatenate([q[0] for q in parts])
+        matU = np.concatenate([q[1] for q in parts])
+        flU = np.concatenate([q[2] for q in parts])
+    else:
+        xU, _ = _sample(2, inv_dx_S, ulo, uhi, ppc1d, lambda p: rmin(p) <= R_f, seed, 4)
+        matU = (rmin(xU) <= r_inc).astype(np.int32)
+        flU = np.where(rmin(xU) > R_f - spS, FLAG_BOUNDARY, 0)
     F0U = np.where((matU == 1)[:, None, None], (1.0 - delta) * np.eye(2), np.eye(2)) if delta else None
     U = _domain(2, h0, [ulo[0] * dxq_S, ulo[1] * dxq_S], dxq_S, [uhi[0] - ulo[0] + 1, uhi[1] - ulo[1] + 1], xU,
-                matU, [E_matrix, E_inc], [nu, nu], rho, ppc1d, np.concatenate([q[2] for q in parts]), [], [], m_ref,
-                tau_rel, F0=F0U)
+                matU, [E_matrix, E_inc], [nu, nu], rho, ppc1d, flU, [], [], m_ref, tau_rel, F0=F0U)
     # one fixed-point threshold and regulariser for all fine domains (those of the union)
     for S_ in Ss:
         S_.tau = U.tau
@@ -460,7 +471,8 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
     along -y (the free end lifts) at a constant rate over n_frames frames.
     The fine domain carries the material inside fine_box; the coarse domain
     the material outside fine_box shrunk by band.  The coarse grid covers the
-    half circle the free end sweeps."""
+    half circle the free end sweeps, the fine grid the band its free half
+    sweeps."""
     lat = math.lcm(inv_dx_B, inv_dx_S, 100)
     h0 = 1.0 / lat
     (fx0, fx1), (fy0, fy1), (fz0, fz1) = fine_box
@@ -506,7 +518,11 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
                 m_ref, tau_rel)
     cS = lat // inv_dx_S
     loS = [sx[0] - pad, sy[0] - pad, sz[0] - pad]
-    hiS = [sx[1] + pad, sy[1] + pad, sz[1] + pad]
+    # the fine grid also covers the quarter circle that the free half of the
+    # fine box sweeps about the hinge axis as the end turns up to 90 degrees
+    # (and past it, down again), so fine particles stay inside their grid
+    sweep_z = int(math.ceil((thick / 2 + math.hypot(fx1 - hinge_x, thick / 2)) * inv_dx_S))
+    hiS = [sx[1] + pad, sy[1] + pad, max(sz[1], sweep_z) + pad]
     S = _domain(3, h0, [l * cS for l in loS], cS, [hiS[a] - loS[a] + 1 for a in range(3)], xS,
                 np.zeros(len(xS), np.int32), [E], [nu], rho, ppc1d, flS, [], [], m_ref, tau_rel)
     omega = angle / (n_frames * dT)
@@ -519,6 +535,85 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
     return Scene(name=name, B=B, S=S, dT=dT, M=M, n_frames=n_frames, bc_params=bc_params,
                  eps_tol=eps_tol_rel * float(S.mass.mean()) if len(xS) else 0.0,
                  meta={"inv_dx_B": inv_dx_B, "inv_dx_S": inv_dx_S})
+
+
+def hinge_scene(cells_B=2, cells_S=6, thick=0.003, length=0.09, width=0.06, hinge=0.01, transition=3e-4,
+                E_stiff=1e5, E_soft=1e3, nu=0.4, rho=1000.0, n_bins=4, ppc1d=2, seed=0, dT=5e-4, M=2,
+                n_frames=400, margin=0.003, band=0.0015, pad=3, tau_rel=1e-3, eps_tol_rel=1e-9, name="hinge"):
+    """The three-dimensional showcase of Sec. 4.4: a thin structure
+    [0,thick] x [0,length] x [0,width] (0.3 x 9 x 6 cm) made of two stiff
+    panels (E_stiff = 100 kPa) joined by a compliant hinge (E_soft = 1 kPa),
+    nu = 0.4, with a linear transition of the modulus over `transition`
+    (0.03 cm) on either side of the hinge; particles in the transition take
+    one of n_bins intermediate moduli by position.  The paper gives neither
+    the hinge width, the loading nor the coarse resolution; readings: a
+    hinge band of width `hinge` across the middle of the length; the end
+    layer y < spacing clamped and the end layer y > length - spacing turned
+    rigidly by 180 degrees over n_frames about the z-parallel axis through
+    (thick/2 + hinge/pi, length/2), so that the hinge closes into a half
+    circle of its own length and the panels end parallel; the fine domain
+    (cells_S cells through the thickness) carries all material within
+    hinge/2 + transition + margin of the hinge centre, the coarse domain
+    (cells_B cells through the thickness) the rest, overlapping by `band`.
+    Both grids sit on one lattice of pitch thick / lcm(cells_B, cells_S)."""
+    lat = math.lcm(cells_B, cells_S)
+    h0 = thick / lat
+    dqB, dqS = lat // cells_B, lat // cells_S
+    dxB, dxS = dqB * h0, dqS * h0
+    yc = 0.5 * length
+    half_f = 0.5 * hinge + transition + margin
+    Rb = hinge / math.pi
+    cx = 0.5 * thick + Rb
+
+    def solid(p):
+        return ((p[:, 0] >= 0.0) & (p[:, 0] <= thick) & (p[:, 1] >= 0.0) & (p[:, 1] <= length)
+                & (p[:, 2] >= 0.0) & (p[:, 2] <= width))
+
+    regS = lambda p: solid(p) & (np.abs(p[:, 1] - yc) <= half_f)
+    regB = lambda p: solid(p) & (np.abs(p[:, 1] - yc) > half_f - band)
+
+    def materials(y):
+        """Material index by distance from the hinge centre: 0 stiff, 1 soft,
+        2 .. 1 + n_bins the transition from soft to stiff."""
+        d = np.abs(y - yc) - 0.5 * hinge
+        k = np.floor(d / transition * n_bins).astype(np.int64)
+        return np.where(d <= 0.0, 1, np.where(k >= n_bins, 0, 2 + np.clip(k, 0, n_bins - 1))).astype(np.int32)
+
+    E = [E_stiff, E_soft] + [E_soft + (E_stiff - E_soft) * (k + 0.5) / n_bins for k in range(n_bins)]
+    nus = [nu] * len(E)
+    ncx, ncy, ncz = (int(round(thick / dxB)), int(round(length / dxB)), int(round(width / dxB)))
+    xB, cB = _sample(3, 1.0 / dxB, [0, 0, 0], [ncx, ncy, ncz], ppc1d, regB, seed, 10)
+    sy0 = int(math.floor((yc - half_f) / dxS))
+    sy1 = int(math.ceil((yc + half_f) / dxS))
+    nsx, nsz = int(round(thick / dxS)), int(round(width / dxS))
+    xS, cS = _sample(3, 1.0 / dxS, [0, sy0, 0], [nsx, sy1, nsz], ppc1d, regS, seed, 11)
+    spB, spS = dxB / ppc1d, dxS / ppc1d
+    flB = np.where(np.abs(cB[:, 1] - yc) < half_f - band + spB, FLAG_BOUNDARY, 0)
+    flB = flB | np.where(cB[:, 1] < spB, 2, 0) | np.where(cB[:, 1] > length - spB, 4, 0)
+    flS = np.where(np.abs(cS[:, 1] - yc) > half_f - spS, FLAG_BOUNDARY, 0)
+    m_ref = rho * dxB ** 3 / ppc1d ** 3
+    # coarse grid: the half disc the free end sweeps about the fold axis
+    reach = math.hypot(Rb, yc)
+    loB = [-pad, -pad, -pad]
+    hiB = [int(math.ceil((cx + reach) / dxB)) + pad, ncy + pad, ncz + pad]
+    B = _domain(3, h0, [l * dqB for l in loB], dqB, [hiB[a] - loB[a] + 1 for a in range(3)], xB,
+                materials(cB[:, 1]), E, nus, rho, ppc1d, flB, [BC_FIX, BC_ROTATE], [0b111, 0b111], m_ref, tau_rel)
+    # fine grid: the hinge band and the half disc its free side sweeps
+    reachS = math.hypot(Rb, half_f)
+    loS = [-pad, int(math.floor((yc - reachS) / dxS)) - pad, -pad]
+    hiS = [int(math.ceil((cx + reachS) / dxS)) + pad, int(math.ceil((yc + reachS) / dxS)) + pad, nsz + pad]
+    S = _domain(3, h0, [l * dqS for l in loS], dqS, [hiS[a] - loS[a] + 1 for a in range(3)], xS,
+                materials(cS[:, 1]), E, nus, rho, ppc1d, flS, [], [], m_ref, tau_rel)
+    omega = math.pi / (n_frames * dT)
+
+    def bc_params(frame):
+        pB = np.zeros((2, 8))
+        pB[1, :7] = [cx, yc, 0.5 * width, 0.0, 0.0, -1.0, omega if frame < n_frames else 0.0]
+        return pB, np.zeros((1, 8))
+
+    return Scene(name=name, B=B, S=S, dT=dT, M=M, n_frames=n_frames, bc_params=bc_params,
+                 eps_tol=eps_tol_rel * float(S.mass.mean()) if len(xS) else 0.0,
+                 meta={"cells_B": cells_B, "cells_S": cells_S, "hinge": hinge, "fold_axis": (cx, yc)})
 
 
 def translation_scene(inv_dx_B=20, inv_dx_S=50, velocity=(0.3, -0.2), ppc1d=2, seed=0, dT=1e-3, M=2,
@@ -551,6 +646,11 @@ def workload(name: str, seed: int = 0) -> Scene:
         return hertz_scene(128, 512, ppc1d=3, seed=seed, M=4, n_frames=400)
     if name == "fold":
         return fold_scene(seed=seed)
+    if name == "hinge":
+        return hinge_scene(seed=seed)
+    if name == "hinge_tiny":
+        return hinge_scene(cells_B=1, cells_S=2, length=0.03, width=0.012, hinge=0.006, margin=0.002, band=0.002,
+                           n_frames=40, seed=seed, name=name)
     if name == "fold_tiny":
         return fold_scene(20, 40, thick=0.1, fine_box=((0.35, 0.65), (-0.05, 0.25), (-0.05, 0.15)), band=0.05,
                           dT=2e-3, M=2, n_frames=50, seed=seed, name=name)

@@ -90,3 +90,61 @@ def test_rigid_translation_through_the_multi_frame():
             # the only departure is the projection's regulariser: v_B = v0 den / (den + eps_tol),
             # eps_tol = 1e-9 of the mean fine particle mass against receiver masses of a few
             assert np.abs(O.v - v0).max() < 1e-8 * np.linalg.norm(v0)
+
+
+def test_overlapping_fine_domains():
+    """Two refined regions that overlap each other (centres 0.16 apart, fine
+    radius 0.12): fine receivers lying in the other fine domain's material
+    take that domain's sub-step velocities of the previous iteration
+    (readings of the oracle's multi-domain frame).  Checked: the frames
+    converge; the result does not depend on the order of the fine domains
+    (they exchange data between iterations); a rigid translation passes
+    through exactly; and the coarse particles agree with the run that holds
+    both regions in one fine domain (the lens material is carried twice in
+    the overlapping run, so the two discretisations differ at the level of
+    the discretisation: measured 2.9 % of the displacement after three
+    frames)."""
+    sc = scenes.two_inclusion_scene(20, 50, delta=0.01, n_frames=10, centres=((0.42, 0.5), (0.58, 0.5)))
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    runs = {}
+    for order in ((0, 1), (1, 0)):
+        OB, OS = oracle.Domain(sc.B), [oracle.Domain(sc.S[i]) for i in order]
+        for f in range(3):
+            pB, _ = sc.bc_params(f)
+            OB.set_bc_params(pB)
+            st = oracle.schwarz_frame_multi(OB, OS, sc.dT, oo)
+            assert st.converged and st.n_recv_S > 0
+        runs[order] = (OB, dict(zip(order, OS)))
+    (B1, S1), (B2, S2) = runs[(0, 1)], runs[(1, 0)]
+    disp = np.abs(B1.x - sc.B.x).max()
+    assert disp > 1e-4
+    assert np.abs(B1.x - B2.x).max() <= 1e-12 * disp
+    for i in (0, 1):
+        assert np.abs(S1[i].x - S2[i].x).max() <= 1e-12 * disp
+    UB, UU = oracle.Domain(sc.B), oracle.Domain(sc.S_union)
+    for f in range(3):
+        pB, _ = sc.bc_params(f)
+        UB.set_bc_params(pB)
+        oracle.schwarz_frame(UB, UU, sc.dT, oo)
+    assert np.abs(UB.x - B1.x).max() <= 0.05 * disp
+
+
+def test_overlapping_fine_domains_translate_rigidly():
+    sc = scenes.two_inclusion_scene(20, 50, centres=((0.42, 0.5), (0.58, 0.5)))
+    v0 = np.array([0.3, -0.2])
+
+    def free(spec):
+        n, d = spec.x.shape
+        return dataclasses.replace(spec, bc_kind=[], bc_mask=[], flags=(spec.flags & np.uint8(1)).astype(np.uint8),
+                                   v=np.tile(v0, (n, 1)), B=np.zeros((n, d, d)), F=np.tile(np.eye(d), (n, 1, 1)))
+
+    OB, OS = oracle.Domain(free(sc.B)), [oracle.Domain(free(s)) for s in sc.S]
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    for f in range(2):
+        st = oracle.schwarz_frame_multi(OB, OS, sc.dT, oo)
+        assert st.converged and st.iters == 1 and st.newton_B == 0 and st.newton_S == 0
+    step = sc.dT * np.linalg.norm(v0)
+    for O, spec in [(OB, sc.B)] + list(zip(OS, sc.S)):
+        # the departure is the projection's regulariser eps_tol (1e-9 of the
+        # mean fine particle mass) against receiver masses of a few particles
+        assert np.abs(O.x - spec.x - 2 * sc.dT * v0).max() < 5e-8 * step
