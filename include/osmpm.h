@@ -115,11 +115,20 @@ typedef struct {
 /* Multiplicative Schwarz controls (Alg. 1): sub-cycling ratio M = dT/dt,
  * iteration cap k_max, convergence tolerance eps_conv on the relative
  * interface-velocity changes r_B and r_S (Eq. convergence_criterion) and the
- * vacuum regulariser eps_tol of the projection (Eq. spatial_projection). */
+ * vacuum regulariser eps_tol of the projection (Eq. spatial_projection).
+ * warm_start = 1: from the second Schwarz iteration of a frame on, every
+ * implicit solve (the coarse solve, fine sub-step m) starts its free DOFs
+ * from the same solve's solution in the previous iteration (on nodes that
+ * were active then; dt v^n elsewhere) instead of dt v^n, and tests Newton
+ * convergence against the initial gradient norm of that solve in the
+ * frame's first iteration; the converged states agree with cold starts to
+ * the solver tolerances (the paper does not state the initial iterate).
+ * The reverse-mode entry points recompute frames with cold starts. */
 typedef struct {
   int32_t M, k_max;
   double eps_conv, eps_tol;
   osmpm_solve_opts coarse, fine;
+  int32_t warm_start;
 } osmpm_schwarz_opts;
 
 /* Statistics of one Schwarz frame: iterations and convergence of the
@@ -311,19 +320,64 @@ osmpm_status osmpm_batch_schwarz_frame(osmpm_batch *batch, double dT, const osmp
  * batch created with fine = NULL; stats_host[n] may be NULL.  Synchronises. */
 osmpm_status osmpm_batch_single_frame(osmpm_batch *batch, double dt, const osmpm_solve_opts *opts,
                                       osmpm_solve_stats *stats_host);
+/* A multi-frame run of a Schwarz batch and its reverse mode (Alg. 1 frame
+ * after frame; the gradient of a loss of the end-of-run particle positions
+ * with respect to every material's Young's modulus).
+ *
+ * osmpm_batch_run: n_frames >= 1 frames of osmpm_batch_schwarz_frame from the
+ * domains' current states.  bc_host is NULL (scene-BC parameters left as set
+ * on the domains) or [n_frames][n][2][4][8] doubles: at frame f, pair i's
+ * coarse (0) and fine (1) domain take parameters [f][i][side][g][0..7] for
+ * its scene groups g (as osmpm_domain_set_scene_bc; rows past a domain's
+ * group count are ignored).  The batch keeps, for osmpm_batch_backward,
+ * every pair's Schwarz iteration count per frame, a device copy of every
+ * domain's particle state at the start of frames 0, c, 2c, ...
+ * (c = checkpoint_every >= 1) and at the end, replacing the previous run's.
+ * stats_host (may be NULL) receives [n_frames][n] frame statistics.
+ * Synchronises. */
+osmpm_status osmpm_batch_run(osmpm_batch *batch, int32_t n_frames, double dT, const osmpm_schwarz_opts *opts,
+                             int32_t checkpoint_every, const double *bc_host, osmpm_schwarz_stats *stats_host);
+/* Reverse mode over the last osmpm_batch_run: xbar_B_host / xbar_S_host are
+ * host arrays of n device pointers (either array, or any entry, may be NULL
+ * for zero), entry i the adjoint dL/dx of pair i's end-of-run coarse / fine
+ * particle positions, FP64 [np][d] in the order of the last
+ * osmpm_domain_set_particles.  Each checkpointed segment is restored and
+ * rerun to recover its frame start states; the frames are then swept from
+ * last to first through each pair's frame adjoint (mode 0: that of
+ * osmpm_schwarz_frame_adjoint with the run's iteration count; mode 1: the
+ * implicit one of osmpm_schwarz_frame_adjoint_implicit with fp_tol, fp_max),
+ * with adjoint CG tolerance adj_cg_rtol, carrying the particle adjoints.
+ * The Lame-parameter derivatives are mapped to Young's moduli by the chain
+ * rule of mu = E / (2 (1 + nu)), lam = E nu / ((1 + nu) (1 - 2 nu)).
+ * dL_dE_host receives, pair after pair, dL/dE of each material of the coarse
+ * domain followed by each material of the fine domain (sum over pairs of
+ * n_mat_B + n_mat_S values; a material present in both domains appears
+ * twice and the two entries add).  The domains hold the end-of-run state
+ * afterwards.  OSMPM_E_STATE without a run.  Synchronises. */
+osmpm_status osmpm_batch_backward(osmpm_batch *batch, const double *const *xbar_B_host,
+                                  const double *const *xbar_S_host, double adj_cg_rtol, int32_t mode, double fp_tol,
+                                  int32_t fp_max, double *dL_dE_host);
 void osmpm_batch_destroy(osmpm_batch *batch);
 
 /* Several refined regions (named as future work in the conclusion; the
  * paper gives no algorithm, so these are readings): one coarse domain and k
- * fine domains whose particle sets are disjoint and which overlap the coarse
- * domain only.  Boundary sets as for a pair; each fine domain is arbitrated
- * against the coarse one by the rule of Eq. overlap_donor; Pi (Eq.
+ * fine domains that overlap the coarse domain and possibly each other.
+ * Boundary sets as for a pair; each fine domain is arbitrated against the
+ * coarse one by the rule of Eq. overlap_donor, and fine domains against each
+ * other pairwise by the same rule (ties: the lower index donates); Pi (Eq.
  * spatial_projection) takes the union of the fine point masses (sums over
  * all fine domains, divided on the coarse receivers); each Schwarz iteration
  * solves the coarse domain, then sub-cycles every fine domain from the same
- * coarse solution; r_S (Eq. convergence_residuals) runs over the receivers of
- * all fine domains together and the frame ends when r_B and r_S pass.  With
- * k = 1 the frame is that of osmpm_schwarz_frame.  The group holds the coarse
+ * coarse solution.  A fine receiver that lies in another fine domain's
+ * material (the coincident lattice node active with a fixed-point mass above
+ * that domain's threshold; the largest such mass wins, ties to the lower
+ * index) takes, at sub-step m, that domain's grid velocity u/dt of sub-step
+ * m of the previous Schwarz iteration (the first iteration uses the coarse
+ * data); r_S (Eq. convergence_residuals) runs over the receivers of all fine
+ * domains together, a linked receiver's datum being its donor's sub-step-M
+ * velocity, and the frame ends when r_B and r_S pass.  Disjoint fine
+ * domains have no links; with k = 1 the frame is that of
+ * osmpm_schwarz_frame.  The group holds the coarse
  * domain k times internally; every fine domain must pair with it as for
  * osmpm_schwarz_frame (same context, dimension, precision, lattice and
  * reference mass), each at most once.  k <= 1024. */

@@ -34,7 +34,7 @@ ABI_SYMBOLS = [
     "osmpm_batch_create", "osmpm_batch_schwarz_frame", "osmpm_batch_single_frame", "osmpm_batch_destroy",
     "osmpm_multi_create", "osmpm_multi_schwarz_frame",
     "osmpm_single_frame_adjoint", "osmpm_schwarz_frame_adjoint", "osmpm_schwarz_frame_adjoint_implicit",
-    "osmpm_single_frame_adjoint_noalloc",
+    "osmpm_single_frame_adjoint_noalloc", "osmpm_batch_run", "osmpm_batch_backward",
 ]
 
 
@@ -61,7 +61,7 @@ class osmpm_solve_stats(C.Structure):
 
 class osmpm_schwarz_opts(C.Structure):
     _fields_ = [("M", C.c_int32), ("k_max", C.c_int32), ("eps_conv", C.c_double), ("eps_tol", C.c_double),
-                ("coarse", osmpm_solve_opts), ("fine", osmpm_solve_opts)]
+                ("coarse", osmpm_solve_opts), ("fine", osmpm_solve_opts), ("warm_start", C.c_int32)]
 
 
 class osmpm_schwarz_stats(C.Structure):
@@ -115,6 +115,9 @@ def _declare(L):
         "osmpm_multi_schwarz_frame": [_vp, C.c_double, P(osmpm_schwarz_opts), P(osmpm_schwarz_stats)],
         "osmpm_single_frame_adjoint": [_vp, C.c_double, P(osmpm_solve_opts), C.c_double] + [_vp] * 8
                                       + [P(C.c_double)] * 2,
+        "osmpm_batch_run": [_vp, C.c_int32, C.c_double, P(osmpm_schwarz_opts), C.c_int32, P(C.c_double),
+                            P(osmpm_schwarz_stats)],
+        "osmpm_batch_backward": [_vp, P(_vp), P(_vp), C.c_double, C.c_int32, C.c_double, C.c_int32, P(C.c_double)],
         "osmpm_single_frame_adjoint_noalloc": [_vp, C.c_double, P(osmpm_solve_opts), C.c_double] + [_vp] * 8
                                               + [P(C.c_double)] * 2,
         "osmpm_schwarz_frame_adjoint": [_vp, _vp, C.c_double, P(osmpm_schwarz_opts), C.c_int32, C.c_double]
@@ -170,9 +173,10 @@ def solve_opts(newton_rtol=1e-8, newton_atol=1e-13, cg_rtol=1e-10, max_newton=50
     return o
 
 
-def schwarz_opts(M, k_max=100, eps_conv=1e-5, eps_tol=0.0, coarse=None, fine=None):
+def schwarz_opts(M, k_max=100, eps_conv=1e-5, eps_tol=0.0, coarse=None, fine=None, warm_start=False):
     o = osmpm_schwarz_opts()
     o.M, o.k_max, o.eps_conv, o.eps_tol = M, k_max, eps_conv, eps_tol
+    o.warm_start = int(warm_start)
     o.coarse = coarse if coarse is not None else solve_opts()
     o.fine = fine if fine is not None else solve_opts()
     return o
@@ -493,6 +497,51 @@ class Batch:
         self.ctx.check(lib().osmpm_batch_single_frame(self.handle, dt, C.byref(opts), st), "batch_single_frame")
         return list(st)
 
+    def run(self, n_frames, dT, opts, checkpoint_every, bc=None):
+        """osmpm_batch_run: n_frames frames; bc is None or a float64 array
+        [n_frames][n][2][4][8] of scene-BC parameters.  Returns the frame
+        statistics as a list (frames) of lists (pairs)."""
+        st = (osmpm_schwarz_stats * (n_frames * self.n))()
+        bcp = None
+        if bc is not None:
+            bc = np.ascontiguousarray(bc, dtype=np.float64)
+            if bc.shape != (n_frames, self.n, 2, 4, 8):
+                raise ValueError("bc must have shape (n_frames, n, 2, 4, 8)")
+            self._bc = bc
+            bcp = bc.ctypes.data_as(C.POINTER(C.c_double))
+        self.ctx.check(lib().osmpm_batch_run(self.handle, int(n_frames), float(dT), C.byref(opts),
+                                             int(checkpoint_every), bcp, st), "batch_run")
+        return [list(st[f * self.n:(f + 1) * self.n]) for f in range(n_frames)]
+
+    def backward(self, xbar_B=None, xbar_S=None, adj_cg_rtol=1e-12, implicit=False, fp_tol=1e-10, fp_max=400):
+        """osmpm_batch_backward: xbar_B / xbar_S are lists (one entry per pair,
+        None for zero) of device float64 tensors [np][d] in input order.
+        Returns per pair (dL/dE of the coarse materials, of the fine
+        materials) as numpy arrays."""
+        keep = []
+
+        def ptrs(lst):
+            if lst is None:
+                return None
+            arr = (C.c_void_p * self.n)()
+            for i, t in enumerate(lst):
+                if t is not None:
+                    t = t.to(dtype=self.ctx.torch.float64).contiguous()
+                    keep.append(t)
+                    arr[i] = t.data_ptr()
+            return arr
+
+        counts = [(b.n_mat, f.n_mat) for b, f in zip(self.coarse, self.fine)]
+        out = (C.c_double * sum(a + b for a, b in counts))()
+        self.ctx.check(lib().osmpm_batch_backward(self.handle, ptrs(xbar_B), ptrs(xbar_S), float(adj_cg_rtol),
+                                                  1 if implicit else 0, float(fp_tol), int(fp_max), out),
+                       "batch_backward")
+        res, off = [], 0
+        for a, b in counts:
+            res.append((np.array(out[off:off + a]), np.array(out[off + a:off + a + b])))
+            off += a + b
+        return res
+
     def close(self):
         if self.handle:
             lib().osmpm_batch_destroy(self.handle)
@@ -520,6 +569,29 @@ class SchwarzBatch:
         st = self.batch.schwarz_frame(self.dT, opts)
         self.frame_index += 1
         return st
+
+    def bc_table(self, n_frames, first=0):
+        """Scene-BC parameters of frames first .. first + n_frames - 1 of every
+        scene, in the layout of osmpm_batch_run."""
+        bc = np.zeros((n_frames, len(self.pairs), 2, 4, 8))
+        for f in range(n_frames):
+            for i, p in enumerate(self.pairs):
+                for side, prm in enumerate(p.scene.bc_params(first + f)):
+                    prm = np.atleast_2d(np.asarray(prm, dtype=np.float64))
+                    bc[f, i, side, :prm.shape[0], :prm.shape[1]] = prm
+        return bc
+
+    def run(self, n_frames, opts, checkpoint_every=10):
+        """n_frames frames from the current frame index in one osmpm_batch_run
+        (kept for backward)."""
+        st = self.batch.run(n_frames, self.dT, opts, checkpoint_every, self.bc_table(n_frames, self.frame_index))
+        self.frame_index += n_frames
+        for p in self.pairs:
+            p.frame_index = self.frame_index
+        return st
+
+    def backward(self, xbar_B=None, xbar_S=None, **kw):
+        return self.batch.backward(xbar_B, xbar_S, **kw)
 
     def close(self):
         self.batch.close()

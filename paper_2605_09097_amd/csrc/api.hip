@@ -11,6 +11,7 @@
 // CG states, the Schwarz residual sums and the device error word.  All
 // arithmetic on particles and nodes runs in the kernels of kernels.hip.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -123,6 +124,7 @@ struct osmpm_domain {
   int *nlist = nullptr, *ncnt = nullptr, *lcnt = nullptr;
   int n_mat = 0;
   double *mu = nullptr, *lam = nullptr;
+  std::vector<double> E_h, nu_h;  // host copy of the material table
   double m_ref = 1.0, tau = 0.0;
   SceneBC bc{};
   double *m = nullptr, *vn = nullptr, *u = nullptr, *vbc = nullptr, *gg = nullptr;
@@ -132,6 +134,9 @@ struct osmpm_domain {
   void *gd = nullptr, *cr[2] = {}, *cs[2] = {}, *cw[3] = {}, *cu = nullptr, *cp = nullptr, *del = nullptr,
        *Atil = nullptr;
   double *pnum = nullptr, *pden = nullptr, *w0 = nullptr, *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
+  int *flink = nullptr;    // fine-fine links [node][2] (multi groups)
+  double *warm = nullptr;  // warm-start slots (see DomDesc), allocated on first use
+  int warm_slots = 0;
   int cg_hint = 8;  // iterations of the last CG solve (sizes the next batch of launches)
   bool have_p2g = false;
   bool have_solve = false;  // an implicit solve since the last P2G (u is then zero on inactive nodes)
@@ -147,6 +152,11 @@ struct Ext {
   int tile_blocks = 8, node_blocks = 1, part_blocks = 1, nn_blocks = 1;
   size_t lds_p2g = 0, lds_grad = 0, lds_hvp = 0;
 };
+
+namespace {
+struct RunRecord;  // multi-frame run record of a Schwarz batch (defined with the reverse mode)
+void run_free(RunRecord *r);
+}  // namespace
 
 // Status block read back once per cycle (one copy).
 struct StatusHdr {
@@ -181,6 +191,7 @@ struct osmpm_batch {
   Ext ext[2];
   std::vector<double> bytes[2][OSMPM_K_COUNT];  // algorithmic bytes per domain and kernel
   std::vector<CycleGraph> cycles[2];            // cached solve-cycle graphs per side
+  RunRecord *run = nullptr;                     // last multi-frame run (osmpm_batch_run)
   std::vector<void *> allocs;
 };
 
@@ -336,8 +347,9 @@ double alg_bytes(int which, int D, double np, double nn, double tb) {
     case OSMPM_K_CG_ITER:  // x, Atil per particle; per DOF r, w, s, u, p, del, diag and the mask read,
                            // p, s, r, u, del written, one w cleared, w accumulated (rmw); mass per node
       return np * (8.0 * D + tb * ns) + nn * (D * (tb * 15.0 + 1.0) + 8.0);
-    case OSMPM_K_P2G:  // x, mass, flags; v, B per particle; mass and momentum (rmw) per node
-      return np * (8.0 * (D + 1.0) + tb * (D + D * D) + 1.0) + nn * 16.0 * (1.0 + D);
+    case OSMPM_K_P2G:  // every particle array read once (pre-sort order) and written once (storage
+                       // order): x, mass, vol, mat, id, flags; v, B, F; mass and momentum (rmw) per node
+      return np * 2.0 * (8.0 * (D + 2.0) + 9.0 + tb * (D + 2.0 * D * D)) + nn * 16.0 * (1.0 + D);
     case OSMPM_K_G2P:  // x read and written, F read; v, B, F written; u gathered per node
       return np * (16.0 * D + tb * (D + 3.0 * D * D)) + nn * 8.0 * D;
     case OSMPM_K_GRAD_HESS:  // x, vol, mat, F read; Atil written; u read, gradient rmw, diagonal rmw
@@ -380,6 +392,7 @@ void group_free(osmpm_batch *G) {
     for (CycleGraph &cgph : G->cycles[s])
       if (cgph.exec) (void)hipGraphExecDestroy(cgph.exec);
   if (G->h_status) (void)hipHostFree(G->h_status);
+  run_free(G->run);
   for (void *p : G->allocs) (void)hipFree(p);
   delete G;
 }
@@ -524,6 +537,9 @@ DomDesc make_desc(const osmpm_domain *d) {
   x.w1 = d->w1;
   x.w2 = d->w2;
   x.w3 = d->w3;
+  x.flink = d->flink;
+  x.warm = d->warm;
+  x.warm_stride = d->g.nn * (d->D + 1) + 1;
   return x;
 }
 
@@ -667,7 +683,8 @@ void build_node_list(osmpm_batch *G, int s, bool counted) {
 
 // ---------------------------------------------------------------- sort + P2G + G2P
 // Stable counting sort of every active domain's particles by tile-major bin
-// key, gathered into the other particle buffer; P2G targets are cleared.
+// key (the storage permutation lperm; P2G gathers the particle arrays into
+// the other buffer in that order); P2G targets are cleared.
 template <int D, typename TB>
 void sort_side(osmpm_batch *G, int s, int want_q) {
   osmpm_ctx *c = G->c;
@@ -684,10 +701,6 @@ void sort_side(osmpm_batch *G, int s, int want_q) {
   launch(c, -1, 0, -1, k_scatter, dim3(pb, n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_cellsort, dim3(blocks_for(E.max_nk), n), dim3(kBlock), 0, dd);
   launch(c, -1, 0, -1, k_slot_layout, dim3(E.tile_blocks, n), dim3(kBlock), 0, dd);
-  launch(c, -1, 0, -1, k_gather_all<D, TB>, dim3(pb, n), dim3(kBlock), 0, dd);
-  launch(c, -1, 0, -1, k_flip, dim3(blocks_for(n)), dim3(kBlock), 0, dd, n);
-  for (int i = 0; i < n; ++i)
-    if (G->act[s][i] == 1) G->dom[s][i]->cur ^= 1;
 }
 
 template <int D, typename TB>
@@ -704,6 +717,10 @@ void p2g_side(osmpm_batch *G, int s, bool want_qall) {
   else
     launch(c, OSMPM_K_P2G, active_bytes(G, s, OSMPM_K_P2G), -1, k_p2g<D, TB, false>, dim3(E.tile_blocks, G->n),
            dim3(kBlock), E.lds_p2g, (const DomDesc *)G->dd[s], G->err);
+  // P2G wrote the particles in storage order into the other buffer
+  launch(c, -1, 0, -1, k_flip, dim3(blocks_for(G->n)), dim3(kBlock), 0, (const DomDesc *)G->dd[s], G->n);
+  for (int i = 0; i < G->n; ++i)
+    if (G->act[s][i] == 1) G->dom[s][i]->cur ^= 1;
   launch(c, -1, 0, -1, k_p2g_final<D>, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
   build_node_list(G, s, true);
   for (int i = 0; i < G->n; ++i)
@@ -744,14 +761,15 @@ void copy_state_side(osmpm_batch *G, int s, int to_store) {
 // is sized from each domain's previous CG count.
 template <int D, typename TB>
 osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int vbc_buf, const osmpm_solve_opts *o,
-                        std::vector<osmpm_solve_stats> *out) {
+                        std::vector<osmpm_solve_stats> *out, int warm_slot = -1, int warm_use = 0) {
   osmpm_ctx *c = G->c;
   const Ext &E = G->ext[s];
   const DomDesc *dd = G->dd[s];
   const int n = G->n;
   const dim3 blk(kBlock);
-  launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, vbc_buf);
-  launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt);
+  const int wstart = (warm_slot >= 0 && warm_use) ? warm_slot : -1;
+  launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, vbc_buf, wstart);
+  launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt, wstart);
   const double bg = active_bytes(G, s, OSMPM_K_GRAD_HESS);
   auto grad_phase = [&]() {
     launch(c, OSMPM_K_GRAD_HESS, bg, -1, k_grad_hess<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_grad, dd,
@@ -786,7 +804,18 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
   const long max_cycles = (long)(o->max_newton + 1) * ((o->max_cg + 4) / 4 + o->max_ls + 3) + 8;
   osmpm_status st;
-  for (long cyc = 0;; ++cyc) {
+  // A warm-started solve often passes its first Newton test: one status
+  // read then costs less than a cycle of launches that would find every
+  // domain done.
+  bool skip_cycles = false;
+  if (wstart >= 0 && !c->graphs) {
+    if ((st = read_status(G))) return st;
+    const SolveState *h0 = h_ss(G, s);
+    skip_cycles = true;
+    for (int i = 0; i < n; ++i)
+      if (G->act[s][i] == 1 && h0[i].phase != kPhaseDone) skip_cycles = false;
+  }
+  for (long cyc = 0; !skip_cycles; ++cyc) {
     if (cyc > max_cycles) return fail(c, OSMPM_E_STATE, "implicit solve did not terminate");
     // launches wanted this cycle: a fresh CG of n iterations takes n + 2
     // (the product of u_0, n steps, the stop test), a running one the rest,
@@ -884,6 +913,8 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     prof_harvest(c, &cg_bytes);
     if (all_done) break;
   }
+  if (warm_slot >= 0)
+    launch(c, -1, 0, -1, k_warm_keep, dim3(E.node_blocks, n), blk, 0, dd, warm_slot, warm_use ? 0 : 1);
   const SolveState *hs = h_ss(G, s);
   if (out) out->assign(n, osmpm_solve_stats{});
   for (int i = 0; i < n; ++i) {
@@ -967,6 +998,32 @@ void add_stats(osmpm_schwarz_stats &st, bool fine, const osmpm_solve_stats &s) {
   (fine ? st.lsfail_S : st.lsfail_B) += s.ls_failed;
 }
 
+// Warm-start slots of every domain of side s of a group (n_slots each),
+// allocated or grown on first use; descriptors are re-uploaded when a
+// buffer changes.
+osmpm_status ensure_warm(osmpm_batch *G, int s, int n_slots) {
+  bool changed = false;
+  for (int i = 0; i < G->n; ++i) {
+    osmpm_domain *d = G->dom[s][i];
+    if (d->warm_slots >= n_slots) continue;
+    if (d->warm) {
+      (void)hipStreamSynchronize(d->ctx->stream);
+      auto it = std::find(d->allocs.begin(), d->allocs.end(), (void *)d->warm);
+      if (it != d->allocs.end()) d->allocs.erase(it);
+      (void)hipFree(d->warm);
+      d->warm = nullptr;
+      d->warm_slots = 0;
+    }
+    const size_t stride = (size_t)d->g.nn * (d->D + 1) + 1;
+    osmpm_status st = dalloc(d, &d->warm, stride * n_slots);
+    if (st) return st;
+    d->warm_slots = n_slots;
+    d->version += 1;
+    changed = true;
+  }
+  return changed ? group_sync(G) : OSMPM_OK;
+}
+
 // One global frame of Alg. 1 for every pair of a two-sided group.  Work
 // buffer roles: on B, Pi data of the current and the next iteration alternate
 // between w0 and w1, and w2 holds v_B^(k+1); on S, w0 holds I(v_B^n), and the
@@ -981,9 +1038,12 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
   const double dt = dT / (double)M;
   osmpm_status s;
   if ((s = group_sync(G))) return s;
+  const bool warm = o->warm_start != 0;
+  if (warm && ((s = ensure_warm(G, 0, 1)) || (s = ensure_warm(G, 1, M)))) return s;
   std::vector<osmpm_schwarz_stats> st(n);
   set_all_active(G);
-  // step 0
+  // frame start: the fine state is stored, both grids built, the
+  // interface sets formed, and the first iterate's coarse data projected
   copy_state_side<D, TB>(G, 1, 1);
   p2g_side<D, TB>(G, 0, true);
   p2g_side<D, TB>(G, 1, true);
@@ -994,13 +1054,14 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
   std::vector<int> live(n, 1);
   std::vector<osmpm_solve_stats> ss;
   for (int k = 0; k < o->k_max; ++k) {
-    // 1. coarse solve with the projected data
-    if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss))) return s;
+    // the coarse solve over dT takes buffer piB on its receivers
+    if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss, warm ? 0 : -1, k > 0))) return s;
     for (int i = 0; i < n; ++i)
       if (live[i]) add_stats(st[i], false, ss[i]);
     launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
            (const DomDesc *)G->dd[0], dT);
-    // 2. fine sub-cycling from the stored state
+    // the fine domains restart from the stored state and take M sub-steps
+    // driven by the temporal interpolation of the two coarse endpoints
     copy_state_side<D, TB>(G, 1, 0);
     p2g_side<D, TB>(G, 1, false);
     interp_group<D>(G, kBufVn, nullptr, 0, nullptr);
@@ -1008,13 +1069,13 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
     for (int m = 1; m <= M; ++m) {
       launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(G->ext[1].max_ndof, 1024), n), dim3(kBlock), 0,
              (const DomDesc *)G->dd[1], (double)m / (double)M, 0, iS_new);
-      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss))) return s;
+      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss, warm ? m - 1 : -1, k > 0))) return s;
       for (int i = 0; i < n; ++i)
         if (live[i]) add_stats(st[i], true, ss[i]);
       g2p_side<D, TB>(G, 1, dt);
       p2g_side<D, TB>(G, 1, false);
     }
-    // 3. residuals
+    // the projection for iteration k + 1 and the interface changes
     project_group<D>(G, o->eps_tol, nullptr, piB_next, nullptr);
     resid_side<D>(G, 0, piB_next, piB);
     resid_side<D>(G, 1, iS_new, iS_prev);
@@ -1041,7 +1102,7 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
     set_active(G, 0, live);
     set_active(G, 1, live);
   }
-  // 4. coarse G2P + advection with the last coarse solution of every pair
+  // every pair's coarse particles move with its last coarse solution
   set_all_active(G);
   g2p_side<D, TB>(G, 0, dT);
   count_recv<D>(G);
@@ -1092,27 +1153,37 @@ osmpm_status schwarz_multi(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
   const double dt = dT / (double)M;
   osmpm_status s;
   if ((s = group_sync(G))) return s;
+  const bool warm = o->warm_start != 0;
+  // the fine domains keep every sub-step's solution (the warm-start slots):
+  // linked receivers of overlapping regions read them
+  if ((warm && (s = ensure_warm(G, 0, 1))) || (s = ensure_warm(G, 1, M))) return s;
   osmpm_schwarz_stats st{};
   std::vector<int> b_one(n, 0), all(n, 1);
   b_one[0] = 1;
   set_active(G, 0, b_one);
   set_active(G, 1, all);
-  // step 0
+  // frame start: fine states stored, all grids built, interface sets
   copy_state_side<D, TB>(G, 1, 1);
   p2g_side<D, TB>(G, 0, true);
   p2g_side<D, TB>(G, 1, true);
   interface_multi<D>(G, b_one);
+  if (n > 1) {
+    launch(c, -1, 0, -1, k_fine_arbitrate<D>, dim3(blocks_for(G->ext[1].max_nn), n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[1], n, G->n_amb);
+    launch(c, -1, 0, -1, k_fine_links<D>, dim3(blocks_for(G->ext[1].max_nn), n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[1], n);
+  }
   int piB = 0, piB_next = 1, iS_new = 1, iS_prev = 2;
   project_group<D>(G, o->eps_tol, nullptr, piB, nullptr);
   interp_group<D>(G, kBufVn, nullptr, iS_prev, nullptr);
   std::vector<osmpm_solve_stats> ss;
   for (int k = 0; k < o->k_max; ++k) {
-    // 1. coarse solve with the projected data
-    if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss))) return s;
+    // the coarse solve over dT takes buffer piB on its receivers
+    if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss, warm ? 0 : -1, k > 0))) return s;
     add_stats(st, false, ss[0]);
     launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
            (const DomDesc *)G->dd[0], dT);
-    // 2. every fine domain sub-cycled from its stored state
+    // every fine domain restarts from its stored state and is sub-cycled
     copy_state_side<D, TB>(G, 1, 0);
     p2g_side<D, TB>(G, 1, false);
     interp_group<D>(G, kBufVn, nullptr, 0, nullptr);
@@ -1120,12 +1191,20 @@ osmpm_status schwarz_multi(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
     for (int m = 1; m <= M; ++m) {
       launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(G->ext[1].max_ndof, 1024), n), dim3(kBlock), 0,
              (const DomDesc *)G->dd[1], (double)m / (double)M, 0, iS_new);
-      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss))) return s;
+      if (n > 1 && k > 0)  // linked receivers: the donors' sub-step m of the previous iteration
+        launch(c, -1, 0, -1, k_fine_link_apply<D>, dim3(blocks_for(G->ext[1].max_nn), n), dim3(kBlock), 0,
+               (const DomDesc *)G->dd[1], m - 1, dt, -1);
+      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss, m - 1, warm && k > 0))) return s;
       for (int i = 0; i < n; ++i) add_stats(st, true, ss[i]);
       g2p_side<D, TB>(G, 1, dt);
       p2g_side<D, TB>(G, 1, false);
     }
-    // 3. residuals over all interfaces
+    // linked receivers' data for the residual: the donors' end-of-frame
+    // velocity (sub-step M) of this iteration
+    if (n > 1)
+      launch(c, -1, 0, -1, k_fine_link_apply<D>, dim3(blocks_for(G->ext[1].max_nn), n), dim3(kBlock), 0,
+             (const DomDesc *)G->dd[1], M - 1, dt, iS_new);
+    // the projection for iteration k + 1 and the changes over all interfaces
     project_group<D>(G, o->eps_tol, nullptr, piB_next, nullptr);
     resid_side<D>(G, 0, piB_next, piB);
     resid_side<D>(G, 1, iS_new, iS_prev);
@@ -1146,7 +1225,7 @@ osmpm_status schwarz_multi(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
       break;
     }
   }
-  // 4. coarse G2P + advection with the last coarse solution
+  // the coarse particles move with the last coarse solution
   g2p_side<D, TB>(G, 0, dT);
   count_recv<D>(G);
   if ((s = read_status(G))) return s;
@@ -1314,7 +1393,7 @@ struct Arena {
 
 // Work arrays of a tape point, from the arena A (default: hipMalloc'ed into
 // t.allocs, freed by tape_free).
-osmpm_status tape_alloc(osmpm_domain *d, TapePoint &t, Arena *A = nullptr) {
+osmpm_status tape_alloc(osmpm_domain *d, TapePoint &t, Arena *A = nullptr, bool particles_only = false) {
   osmpm_ctx *c = d->ctx;
   const size_t cap = (size_t)d->cap, nn = (size_t)d->g.nn, nd = nn * d->D;
   const int D = d->D;
@@ -1335,6 +1414,10 @@ osmpm_status tape_alloc(osmpm_domain *d, TapePoint &t, Arena *A = nullptr) {
   t.p.id = (int *)al(cap * sizeof(int));
   t.p.flags = (uint8_t *)al(cap);
   t.cell_start = (int *)al(((size_t)d->nk + 1) * sizeof(int));
+  if (particles_only) {
+    if (s) tape_free(t);
+    return s;
+  }
   t.m = (double *)al(nn * sizeof(double));
   t.vn = (double *)al(nd * sizeof(double));
   t.u = (double *)al(nd * sizeof(double));
@@ -1477,9 +1560,9 @@ osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const 
   // the work lists of the restored binning and grid
   build_tile_list(G, s);
   build_node_list(G, s, false);
-  launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, kBufVbc);
+  launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, kBufVbc, -1);
   HIP_TRY(c, hipMemcpyAsync(d->u, u_tape, (size_t)nd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-  launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt);
+  launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt, -1);
   launch(c, -1, 0, -1, k_grad_hess<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_grad, dd, 0, G->err);
   launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
          o->gravity[2]);
@@ -1826,6 +1909,196 @@ osmpm_status schwarz_adjoint_impl(osmpm_batch *G, double dT, const osmpm_schwarz
   return s;
 }
 
+// ---------------------------------------------------------------- multi-frame runs and their reverse mode
+// What a multi-frame run of a Schwarz batch keeps for its reverse mode: the
+// run's settings, the scene-BC parameters of every frame (when given), every
+// pair's Schwarz iteration count per frame, and the particle state of every
+// domain (index side * n + pair) at the start of frames 0, c, 2c, ... (c the
+// checkpoint interval) and at the end of the run.  `starts` holds one
+// segment's frame start states during the reverse pass.
+struct RunRecord {
+  int n_frames = 0, every = 1;
+  double dT = 0.0;
+  osmpm_schwarz_opts o{};
+  std::vector<double> bc;  // [n_frames][n][2][kMaxGroups][8]; empty: parameters left as they are
+  std::vector<int> iters;  // [n_frames][n]
+  std::vector<std::vector<TapePoint>> ckpt;
+  std::vector<TapePoint> end;
+  std::vector<std::vector<TapePoint>> starts;
+};
+
+void run_free(RunRecord *r) {
+  if (!r) return;
+  for (auto &v : r->ckpt)
+    for (TapePoint &t : v) tape_free(t);
+  for (auto &v : r->starts)
+    for (TapePoint &t : v) tape_free(t);
+  for (TapePoint &t : r->end) tape_free(t);
+  delete r;
+}
+
+// Saves (dir > 0) or restores (dir < 0) the particle state of every domain
+// of a Schwarz batch; the points are allocated on the first save.
+osmpm_status batch_states(osmpm_batch *G, std::vector<TapePoint> &pts, int dir) {
+  const int n = G->n;
+  osmpm_status s;
+  if (pts.empty()) {
+    if (dir < 0) return fail(G->c, OSMPM_E_STATE, "no stored state to restore");
+    pts.resize((size_t)2 * n);
+    for (int sd = 0; sd < 2; ++sd)
+      for (int i = 0; i < n; ++i)
+        if ((s = tape_alloc(G->dom[sd][i], pts[(size_t)sd * n + i], nullptr, true))) return s;
+  }
+  for (int sd = 0; sd < 2; ++sd)
+    for (int i = 0; i < n; ++i)
+      if ((s = tape_copy(G->dom[sd][i], pts[(size_t)sd * n + i], dir, 1))) return s;
+  return OSMPM_OK;
+}
+
+// Scene-BC parameters of frame f on every domain of the batch (a domain
+// whose parameters change gets its descriptor uploaded by the next frame).
+void apply_frame_bc(osmpm_batch *G, const RunRecord &R, int f) {
+  if (R.bc.empty()) return;
+  const int n = G->n;
+  for (int i = 0; i < n; ++i)
+    for (int sd = 0; sd < 2; ++sd) {
+      osmpm_domain *d = G->dom[sd][i];
+      const double *p = &R.bc[((((size_t)f * n + i) * 2 + sd) * kMaxGroups) * 8];
+      SceneBC bc = d->bc;
+      for (int g = 0; g < bc.n_groups; ++g)
+        for (int k = 0; k < 8; ++k) bc.param[g][k] = p[g * 8 + k];
+      if (std::memcmp(&bc, &d->bc, sizeof(SceneBC)) != 0) {
+        d->bc = bc;
+        d->version += 1;
+      }
+    }
+}
+
+// n_frames frames of Alg. 1 on every pair of the batch, recording what the
+// reverse pass needs (RunRecord); see the ABI.
+template <int D, typename TB>
+osmpm_status batch_run_impl(osmpm_batch *G, int n_frames, double dT, const osmpm_schwarz_opts *o, int every,
+                            const double *bc_host, osmpm_schwarz_stats *stats) {
+  const int n = G->n;
+  run_free(G->run);
+  G->run = nullptr;
+  auto *R = new RunRecord();
+  R->n_frames = n_frames;
+  R->every = every;
+  R->dT = dT;
+  R->o = *o;
+  if (bc_host) R->bc.assign(bc_host, bc_host + (size_t)n_frames * n * 2 * kMaxGroups * 8);
+  R->iters.assign((size_t)n_frames * n, 0);
+  R->ckpt.resize((size_t)(n_frames + every - 1) / every);
+  std::vector<osmpm_schwarz_stats> st(n);
+  osmpm_status s = OSMPM_OK;
+  for (int f = 0; f < n_frames && !s; ++f) {
+    if (f % every == 0 && (s = batch_states(G, R->ckpt[f / every], 1))) break;
+    apply_frame_bc(G, *R, f);
+    if ((s = schwarz_group<D, TB>(G, dT, o, st.data()))) break;
+    for (int i = 0; i < n; ++i) {
+      R->iters[(size_t)f * n + i] = st[i].iters;
+      if (stats) stats[(size_t)f * n + i] = st[i];
+    }
+  }
+  if (!s) s = batch_states(G, R->end, 1);
+  if (!s) s = check_launch(G->c);
+  if (s) {
+    run_free(R);
+    return s;
+  }
+  G->run = R;
+  return OSMPM_OK;
+}
+
+// Reverse mode over the last run of the batch; see the ABI.  Each segment of
+// `every` frames is restored from its checkpoint and rerun (batched) to
+// recover its frame start states; the frames are then swept last to first,
+// every pair through its frame adjoint (the unrolled or the implicit one)
+// with its recorded iteration count, carrying the particle adjoints and
+// summing the Lame-parameter derivatives, which are finally mapped to
+// Young's moduli with dmu/dE = 1 / (2 (1 + nu)), dlam/dE = nu / ((1 + nu)
+// (1 - 2 nu)).  The domains are left at the end-of-run state.
+template <int D, typename TB>
+osmpm_status batch_backward_impl(osmpm_batch *G, const double *const *xbB, const double *const *xbS,
+                                 double adj_rtol, int implicit, double fp_tol, int fp_max, double *dE_host) {
+  osmpm_ctx *c = G->c;
+  RunRecord &R = *G->run;
+  const int n = G->n;
+  std::vector<void *> mem;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(c->stream);
+    for (void *q : mem) (void)hipFree(q);
+  };
+  // adjoint rows [np][d], [np][d][d] of every domain: current and next
+  std::vector<std::array<double *, 4>> cur((size_t)2 * n), nxt((size_t)2 * n);
+  osmpm_status s;
+  for (int sd = 0; sd < 2; ++sd)
+    for (int i = 0; i < n; ++i) {
+      const osmpm_domain *d = G->dom[sd][i];
+      const size_t np = (size_t)std::max(d->np, 1);
+      for (auto *v : {&cur, &nxt})
+        for (int f = 0; f < 4; ++f) {
+          void *q = nullptr;
+          const size_t bytes = np * (f < 2 ? D : D * D) * sizeof(double);
+          if ((s = dalloc_bytes(c, mem, &q, bytes)) || (s = zero_bytes(c, q, bytes))) return cleanup(), s;
+          (*v)[(size_t)sd * n + i][f] = (double *)q;
+        }
+      const double *xb = sd == 0 ? (xbB ? xbB[i] : nullptr) : (xbS ? xbS[i] : nullptr);
+      if (xb && d->np > 0)
+        HIP_TRY(c, hipMemcpyAsync(cur[(size_t)sd * n + i][0], xb, (size_t)d->np * D * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c->stream));
+    }
+  std::vector<double> lame((size_t)n * 256, 0.0);  // per pair: mu_B, lam_B, mu_S, lam_S (64 each)
+  if (R.starts.size() < (size_t)R.every) R.starts.resize((size_t)R.every);
+  for (int sg = (int)R.ckpt.size() - 1; sg >= 0; --sg) {
+    const int f0 = sg * R.every, f1 = std::min(f0 + R.every, R.n_frames);
+    if ((s = batch_states(G, R.ckpt[(size_t)sg], -1))) return cleanup(), s;
+    for (int f = f0; f < f1; ++f) {
+      if ((s = batch_states(G, R.starts[(size_t)(f - f0)], 1))) return cleanup(), s;
+      if (f + 1 < f1) {
+        apply_frame_bc(G, R, f);
+        if ((s = schwarz_group<D, TB>(G, R.dT, &R.o, nullptr))) return cleanup(), s;
+      }
+    }
+    for (int f = f1 - 1; f >= f0; --f) {
+      if ((s = batch_states(G, R.starts[(size_t)(f - f0)], -1))) return cleanup(), s;
+      apply_frame_bc(G, R, f);
+      for (int i = 0; i < n; ++i) {
+        osmpm_batch *P = nullptr;
+        if ((s = pair_group(G->dom[0][i], G->dom[1][i], &P))) return cleanup(), s;
+        const size_t kB = (size_t)i, kS = (size_t)n + i;
+        const double *inB[4] = {cur[kB][0], cur[kB][1], cur[kB][2], cur[kB][3]};
+        const double *inS[4] = {cur[kS][0], cur[kS][1], cur[kS][2], cur[kS][3]};
+        double *outB[4] = {nxt[kB][0], nxt[kB][1], nxt[kB][2], nxt[kB][3]};
+        double *outS[4] = {nxt[kS][0], nxt[kS][1], nxt[kS][2], nxt[kS][3]};
+        double mh[256];
+        int used = 0;
+        if ((s = schwarz_adjoint_impl<D, TB>(P, R.dT, &R.o, R.iters[(size_t)f * n + i], adj_rtol, implicit, fp_tol,
+                                             fp_max, &used, inB, inS, outB, outS, mh)))
+          return cleanup(), s;
+        for (int k = 0; k < 256; ++k) lame[(size_t)i * 256 + k] += mh[k];
+        std::swap(cur[kB], nxt[kB]);
+        std::swap(cur[kS], nxt[kS]);
+      }
+    }
+  }
+  if ((s = batch_states(G, R.end, -1))) return cleanup(), s;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i)
+    for (int sd = 0; sd < 2; ++sd) {
+      const osmpm_domain *d = G->dom[sd][i];
+      for (int k = 0; k < d->n_mat; ++k) {
+        const double nu = d->nu_h[k];
+        const double dmu = 1.0 / (2.0 * (1.0 + nu)), dlam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+        dE_host[off++] = lame[(size_t)i * 256 + sd * 128 + k] * dmu + lame[(size_t)i * 256 + sd * 128 + 64 + k] * dlam;
+      }
+    }
+  s = check_launch(c);
+  cleanup();
+  return s;
+}
+
 // ---------------------------------------------------------------- fixed work region
 // The device region of osmpm_single_frame_adjoint_noalloc, the entry point
 // that allocates nothing: one copy per device, held until the process ends.
@@ -2034,6 +2307,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->bcg, nd);
   if (!s) s = dalloc(d, &d->gamma, nn);
   if (!s) s = dalloc(d, &d->recv, nn);
+  if (!s) s = dalloc(d, &d->flink, (size_t)2 * nn);
   if (!s) s = dalloc(d, &d->fr, nd);
   if (!s) s = dalloc(d, &d->q_all, nn);
   if (!s) s = dalloc(d, &d->q_bnd, nn);
@@ -2117,6 +2391,12 @@ osmpm_status osmpm_domain_set_materials(osmpm_domain *d, const osmpm_material *m
   HIP_TRY(c, hipMemcpyAsync(d->lam, lam.data(), n_mat * sizeof(double), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   d->n_mat = n_mat;
+  d->E_h.resize(n_mat);
+  d->nu_h.resize(n_mat);
+  for (int i = 0; i < n_mat; ++i) {
+    d->E_h[i] = mats[i].E;
+    d->nu_h[i] = mats[i].nu;
+  }
   return OSMPM_OK;
 }
 
@@ -2314,6 +2594,33 @@ osmpm_status osmpm_batch_single_frame(osmpm_batch *b, double dt, const osmpm_sol
   if (!b || b->sides != 1 || !o || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
   if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
   return DISPATCH2(b->D, b->precision, single_group)(b, dt, o, stats);
+}
+
+osmpm_status osmpm_batch_run(osmpm_batch *b, int32_t n_frames, double dT, const osmpm_schwarz_opts *o,
+                             int32_t checkpoint_every, const double *bc_host, osmpm_schwarz_stats *stats) {
+  if (!b || b->sides != 2 || !schwarz_opts_ok(o) || !(dT > 0.0) || n_frames < 1 || checkpoint_every < 1)
+    return OSMPM_E_INVALID_ARG;
+  if (b->multi) return fail(b->c, OSMPM_E_INVALID_ARG, "a multi-domain group has no multi-frame run");
+  osmpm_status s = group_sync(b);
+  if (s) return s;
+  return DISPATCH2(b->D, b->precision, batch_run_impl)(b, n_frames, dT, o, checkpoint_every, bc_host, stats);
+}
+
+osmpm_status osmpm_batch_backward(osmpm_batch *b, const double *const *xbar_B_host,
+                                  const double *const *xbar_S_host, double adj_cg_rtol, int32_t mode, double fp_tol,
+                                  int32_t fp_max, double *dL_dE_host) {
+  if (!b || b->sides != 2 || !dL_dE_host || !(adj_cg_rtol > 0.0) || (mode != 0 && mode != 1))
+    return OSMPM_E_INVALID_ARG;
+  if (mode == 1 && (fp_max < 1 || std::isnan(fp_tol))) return OSMPM_E_INVALID_ARG;
+  if (!b->run) return fail(b->c, OSMPM_E_STATE, "no osmpm_batch_run to differentiate");
+  for (int i = 0; i < b->n; ++i)
+    for (int sd = 0; sd < 2; ++sd)
+      if (b->dom[sd][i]->n_mat < 1 || (int)b->dom[sd][i]->nu_h.size() != b->dom[sd][i]->n_mat)
+        return fail(b->c, OSMPM_E_STATE, "a domain has no material table");
+  osmpm_status s = group_sync(b);
+  if (s) return s;
+  return DISPATCH2(b->D, b->precision, batch_backward_impl)(b, xbar_B_host, xbar_S_host, adj_cg_rtol, mode, fp_tol,
+                                                            fp_max, dL_dE_host);
 }
 
 void osmpm_batch_destroy(osmpm_batch *b) { group_free(b); }

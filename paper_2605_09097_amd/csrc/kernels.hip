@@ -447,34 +447,6 @@ __global__ void __launch_bounds__(kBlock) k_slot_layout(const DomDesc *dd) {
   }
 }
 
-// Gathers every particle array into the other buffer in storage order.
-template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_gather_all(const DomDesc *dd) {
-  const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active) return;
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= dm.np) return;
-  const int c = *dm.cur;
-  const PartPtrs &a = dm.pb[c], &b = dm.pb[c ^ 1];
-  const int64_t cap = dm.cap;
-  const int q = dm.lperm[p];
-#pragma unroll
-  for (int r = 0; r < D; ++r) {
-    b.x[r * cap + p] = a.x[r * cap + q];
-    static_cast<TB *>(b.v)[r * cap + p] = static_cast<const TB *>(a.v)[r * cap + q];
-  }
-#pragma unroll
-  for (int r = 0; r < D * D; ++r) {
-    static_cast<TB *>(b.B)[r * cap + p] = static_cast<const TB *>(a.B)[r * cap + q];
-    static_cast<TB *>(b.F)[r * cap + p] = static_cast<const TB *>(a.F)[r * cap + q];
-  }
-  b.mass[p] = a.mass[q];
-  b.vol[p] = a.vol[q];
-  b.mat[p] = a.mat[q];
-  b.id[p] = a.id[q];
-  b.flags[p] = a.flags[q];
-}
-
 __global__ void __launch_bounds__(kBlock) k_flip(const DomDesc *dd, int ndom) {
   const int i = threadIdx.x + blockIdx.x * blockDim.x;
   if (i < ndom && *dd[i].active) *dd[i].cur ^= 1;
@@ -571,6 +543,11 @@ __device__ inline int region_slot(const TileGeom &tg, const int *l, const int *k
 // kQ (the launches that also select node sets) is a template parameter so
 // that the common launch carries no per-node branches; particles of scene
 // groups, which are few, add their group masses in a pass of their own.
+// The kernel also completes the binning: it reads each particle's arrays
+// from the buffer in pre-sort order at lperm[p] and writes them to the other
+// buffer at their storage position p, so every array is read once for both
+// the permuted copy and the scatter (the host flips the current buffer
+// after the launch).
 template <int D, typename TB, bool kQ>
 __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   constexpr int want_q = kQ ? 1 : 0;
@@ -585,7 +562,10 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   const GridDev g = dm.g;
   int p0, p1, org[3];
   if (!tile_slot(dm.tl, tg, blockIdx.x, p0, p1, org)) return;
-  const PartPtrs P = dm.pb[*dm.cur];
+  const int cur = *dm.cur;
+  const PartPtrs P = dm.pb[cur];      // pre-sort order (read at lperm)
+  const PartPtrs Q = dm.pb[cur ^ 1];  // storage order (written)
+  const int *const lperm = dm.lperm;
   const double scale = dm.scale;
   double *const gm = dm.m;
   double *const gvn = dm.vn;
@@ -594,6 +574,10 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   const int64_t cap = dm.cap;
   const TB *v = static_cast<const TB *>(P.v);
   const TB *B = static_cast<const TB *>(P.B);
+  const TB *Fs = static_cast<const TB *>(P.F);
+  TB *const vd = static_cast<TB *>(Q.v);
+  TB *const Bd = static_cast<TB *>(Q.B);
+  TB *const Fd = static_cast<TB *>(Q.F);
   const int nreg = tg.nreg;
   const int n_groups = dm.bc.n_groups;
   long long *lq = reinterpret_cast<long long *>(lds);
@@ -604,29 +588,45 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   for (int r = threadIdx.x; r < nreg * nq; r += kBlock) lq[r] = 0;
   __syncthreads();
   const TB dx_t = (TB)g.dx, Dinv_t = (TB)dm.Dinv;
+  int q_next = (p0 + (int)threadIdx.x < p1) ? gload(lperm, p0 + (int)threadIdx.x) : 0;
   for (int p = p0 + threadIdx.x; p < p1; p += kBlock) {
-    // all of the particle's loads are issued together, one round trip
+    // the source index of the next particle is fetched one iteration ahead;
+    // all of this particle's loads are issued together, one round trip
+    const int q = q_next;
+    if (p + kBlock < p1) q_next = gload(lperm, p + kBlock);
     double xp[D];
-    TB vp[D], Bp[D * D];
+    TB vp[D], Bp[D * D], Fp[D * D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      xp[a] = gload(P.x, a * cap + p);
-      vp[a] = gload(v, a * cap + p);
+      xp[a] = gload(P.x, a * cap + q);
+      vp[a] = gload(v, a * cap + q);
     }
 #pragma unroll
-    for (int k = 0; k < D * D; ++k) Bp[k] = gload(B, k * cap + p);
-    const double mp = gload(P.mass, p);
-    const uint8_t fl = kQ ? gload(P.flags, p) : uint8_t(0);
-    // an empty asm that consumes every loaded value: the compiler would
-    // otherwise issue the velocity, affine and mass loads only after the
-    // tile check, a second round trip per particle
-    if constexpr (D == 2)
-      asm volatile("" ::"v"(xp[0]), "v"(xp[1]), "v"(vp[0]), "v"(vp[1]), "v"(Bp[0]), "v"(Bp[1]), "v"(Bp[2]),
-                   "v"(Bp[3]), "v"(mp));
-    else
-      asm volatile("" ::"v"(xp[0]), "v"(xp[1]), "v"(xp[2]), "v"(vp[0]), "v"(vp[1]), "v"(vp[2]), "v"(Bp[0]),
-                   "v"(Bp[1]), "v"(Bp[2]), "v"(Bp[3]), "v"(Bp[4]), "v"(Bp[5]), "v"(Bp[6]), "v"(Bp[7]),
-                   "v"(Bp[8]), "v"(mp));
+    for (int k = 0; k < D * D; ++k) {
+      Bp[k] = gload(B, k * cap + q);
+      Fp[k] = gload(Fs, k * cap + q);
+    }
+    const double mp = gload(P.mass, q);
+    const double vol = gload(P.vol, q);
+    const int mat = gload(P.mat, q);
+    const int id = gload(P.id, q);
+    const uint8_t fl = gload(P.flags, q);
+    // the permuted copy at the storage position
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      gstore(Q.x, a * cap + p, xp[a]);
+      gstore(vd, a * cap + p, vp[a]);
+    }
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) {
+      gstore(Bd, k * cap + p, Bp[k]);
+      gstore(Fd, k * cap + p, Fp[k]);
+    }
+    gstore(Q.mass, p, mp);
+    gstore(Q.vol, p, vol);
+    gstore(Q.mat, p, mat);
+    gstore(Q.id, p, id);
+    gstore(Q.flags, p, fl);
     Stencil<D> st;
     stencil_eval<D>(xp, g, st);
     int l[3];
@@ -864,7 +864,8 @@ __device__ inline double scene_value(const SceneBC &bc, int gi, const GridDev &g
 // the Jacobi-diagonal scatter targets of the first Newton iteration; partial
 // sums of the node mass (part_a) for the Newton tolerance floor.
 template <int D, typename TB>
-__global__ void __launch_bounds__(kBlock) k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf) {
+__global__ void __launch_bounds__(kBlock) k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf,
+                                                    int warm_slot) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || (int)blockIdx.x >= nb) return;
@@ -872,6 +873,10 @@ __global__ void __launch_bounds__(kBlock) k_bc_init(const DomDesc *dd, double dt
   const GridDev &g = dm.g;
   TB *gdiag = static_cast<TB *>(dm.gd);
   const double *vbc = wbuf(dm, vbc_buf);
+  // warm start: the same solve's displacement in the previous Schwarz
+  // iteration, on nodes that were active in that iteration's grid
+  const double *wu = (warm_slot >= 0 && dm.warm) ? dm.warm + (size_t)warm_slot * dm.warm_stride : nullptr;
+  const double *wm = wu ? wu + dm.ndof : nullptr;
   double msum = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += nb * kBlock) {
     const double m = dm.m[i];
@@ -890,7 +895,7 @@ __global__ void __launch_bounds__(kBlock) k_bc_init(const DomDesc *dd, double dt
           val = dt * vbc[k];
         } else {
           f = 1;
-          val = dt * dm.vn[k];
+          val = (wu && wm[i] > 0.0) ? wu[k] : dt * dm.vn[k];
         }
       }
       dm.fr[k] = f;
@@ -905,13 +910,16 @@ __global__ void __launch_bounds__(kBlock) k_bc_init(const DomDesc *dd, double dt
 
 // Solve state at the start of an implicit solve: the gradient scale of the
 // absolute Newton floor, sum_i m_i * dx / dt^2.  One workgroup per domain.
-__global__ void __launch_bounds__(kBlock) k_solve_begin(const DomDesc *dd, double dt) {
+__global__ void __launch_bounds__(kBlock) k_solve_begin(const DomDesc *dd, double dt, int warm_slot) {
   const DomDesc &dm = dd[blockIdx.y];
   __shared__ double red[kBlock / 64];
   const bool act = *dm.active != 0;
   const double mtot = act ? reduce_partials(dm.part_a, node_blocks(dm.ndof), red) : 0.0;
   if (threadIdx.x == 0) {
     SolveState &s = *dm.ss;
+    s.gref = (act && warm_slot >= 0 && dm.warm)
+                 ? dm.warm[(size_t)warm_slot * dm.warm_stride + dm.ndof + dm.g.nn]
+                 : -1.0;
     s.gnorm0 = 0.0;
     s.gnorm = 0.0;
     s.gscale = mtot * dm.g.dx / (dt * dt);
@@ -928,6 +936,21 @@ __global__ void __launch_bounds__(kBlock) k_solve_begin(const DomDesc *dd, doubl
     dm.cg->done = 1;
     dm.cg->iter = 0;
   }
+}
+
+// After a solve: its displacement and node masses into warm-start slot
+// `slot`; at the frame's first Schwarz iteration (first = 1) also the
+// solve's initial gradient norm, the reference of the later iterations'
+// Newton tests.
+__global__ void __launch_bounds__(kBlock) k_warm_keep(const DomDesc *dd, int slot, int first) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active || !dm.warm) return;
+  double *w = dm.warm + (size_t)slot * dm.warm_stride;
+  const int stride = gridDim.x * blockDim.x;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int k = i0; k < dm.ndof; k += stride) w[k] = dm.u[k];
+  for (int i = i0; i < dm.g.nn; i += stride) w[dm.ndof + i] = dm.m[i];
+  if (first && i0 == 0) w[dm.ndof + dm.g.nn] = dm.ss->gnorm0;
 }
 
 // ====================================================================== gradient + Hessian
@@ -1259,12 +1282,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd, int check
     __shared__ double red[kBlock / 64];
     const double gn = sqrt(reduce_partials(dm.part_a, nb, red));
     const int it = st.it;
-    const double gn0 = (it == 0) ? gn : st.gnorm0;
+    // a warm-started solve tests against the reference norm of its slot
+    const double gn0 = (it == 0) ? (st.gref >= 0.0 ? st.gref : gn) : st.gnorm0;
     const double tol = fmax(rtol * gn0, atol * st.gscale);
     const bool conv = gn <= tol;
     const int next = (conv || it == max_newton) ? kPhaseDone : kPhaseCgInit;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      if (it == 0) st.gnorm0 = gn;
+      if (it == 0) st.gnorm0 = gn0;
       st.gnorm = gn;
       if (conv) st.converged = 1;
       st.phase = next;
@@ -2115,6 +2139,101 @@ __global__ void __launch_bounds__(kBlock) k_temporal(const DomDesc *dd, double a
     dm.vbc[k] = (1.0 - am) * a[k] + am * b[k];
 }
 
+// ---------------------------------------------------------------- refined regions that overlap
+// Node of grid G at the lattice point of node i of grid A, or -1.
+template <int D>
+__device__ inline int coincident_node(const GridDev &A, int i, const GridDev &G) {
+  int ia[3], jg[3] = {0, 0, 0};
+  node_unflat<D>(A, i, ia);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const long long L = A.origin_q[a] + (long long)ia[a] * A.dx_q;
+    const long long t = L - G.origin_q[a];
+    if (t < 0 || t % G.dx_q != 0 || t / G.dx_q >= G.n[a]) return -1;
+    jg[a] = (int)(t / G.dx_q);
+  }
+  return node_flat<D>(G, jg);
+}
+
+// Arbitration between the n fine domains of a multi group (Eq. overlap_donor
+// applied pairwise): a node in the boundary sets of fine domains f and g at
+// one lattice point is ambiguous; the side with the larger fixed-point node
+// mass donates (ties: the lower index) and leaves its own receiver set.
+// Reads boundary sets and masses only, so the order of the pairs does not
+// matter; ambiguous pairs are counted once, at the lower index.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fine_arbitrate(const DomDesc *dd, int n, int *n_amb) {
+  const int f = blockIdx.y;
+  const DomDesc &F = dd[f];
+  if (!*F.active) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= F.g.nn || !F.gamma[j]) return;
+  bool donor = false;
+  for (int g = 0; g < n; ++g) {
+    if (g == f) continue;
+    const DomDesc &G = dd[g];
+    const int jg = coincident_node<D>(F.g, j, G.g);
+    if (jg < 0 || !G.gamma[jg]) continue;
+    if (f < g) atomicAdd(&n_amb[f], 1);
+    const long long qf = F.q_all[j], qg = G.q_all[jg];
+    if (qf > qg || (qf == qg && f < g)) donor = true;
+  }
+  if (donor) F.recv[j] = 0;
+}
+
+// Links of the fine receivers after all arbitration: a receiver node of f
+// lying in another fine domain's material (the coincident node active with
+// a fixed-point mass above that domain's threshold) takes its data from the
+// one of largest mass (ties: the lower index); flink[j] = {g, node}, or
+// {-1, -1} where the coarse domain donates.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fine_links(const DomDesc *dd, int n) {
+  const int f = blockIdx.y;
+  const DomDesc &F = dd[f];
+  if (!*F.active) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= F.g.nn) return;
+  int bg = -1, bn = -1;
+  long long best = 0;
+  if (F.recv[j]) {
+    for (int g = 0; g < n; ++g) {
+      if (g == f) continue;
+      const DomDesc &G = dd[g];
+      const int jg = coincident_node<D>(F.g, j, G.g);
+      if (jg < 0 || !(G.m[jg] > 0.0)) continue;
+      const long long q = G.q_all[jg];
+      if (q <= G.tau_q) continue;
+      if (bg < 0 || q > best) {
+        bg = g;
+        bn = jg;
+        best = q;
+      }
+    }
+  }
+  F.flink[2 * j] = bg;
+  F.flink[2 * j + 1] = bn;
+}
+
+// Linked receivers' data: the donor's grid velocity u / dt of the solve kept
+// in its slot `slot` (its node active then), into v_bc (dst_buf < 0) or a
+// work buffer.
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fine_link_apply(const DomDesc *dd, int slot, double dt, int dst_buf) {
+  const DomDesc &F = dd[blockIdx.y];
+  if (!*F.active) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= F.g.nn) return;
+  const int g = F.flink[2 * j];
+  if (g < 0) return;
+  const int jg = F.flink[2 * j + 1];
+  const DomDesc &G = dd[g];
+  const double *w = G.warm + (size_t)slot * G.warm_stride;
+  if (!(w[G.ndof + jg] > 0.0)) return;
+  double *dst = dst_buf < 0 ? F.vbc : wbuf(F, dst_buf);
+#pragma unroll
+  for (int a = 0; a < D; ++a) dst[j * D + a] = w[(size_t)jg * D + a] / dt;
+}
+
 // w2 = u / dt on active nodes, 0 elsewhere (v_B^(k+1) of Eq. implicit_solve_coarse).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_vel_from_u(const DomDesc *dd, double dt) {
@@ -2194,11 +2313,13 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const DomDesc *dd, doubl
   template __global__ void k_temporal<D>(const DomDesc *, double, int, int);                                       \
   template __global__ void k_vel_from_u<D>(const DomDesc *, double);                                     \
   template __global__ void k_resid<D>(const DomDesc *, int, int);                                        \
+  template __global__ void k_fine_arbitrate<D>(const DomDesc *, int, int *);                             \
+  template __global__ void k_fine_links<D>(const DomDesc *, int);                                        \
+  template __global__ void k_fine_link_apply<D>(const DomDesc *, int, double, int);                      \
   template __global__ void k_copy_vbc<D>(const DomDesc *, int);
 
 #define OSMPM_INST_DT(D, TB)                                                                    \
-  template __global__ void k_gather_all<D, TB>(const DomDesc *);                                \
-  template __global__ void k_bc_init<D, TB>(const DomDesc *, double, int, int);                      \
+  template __global__ void k_bc_init<D, TB>(const DomDesc *, double, int, int, int);                      \
   template __global__ void k_copy_state<D, TB>(const DomDesc *, int);                           \
   template __global__ void k_p2g<D, TB, false>(const DomDesc *, int *);                         \
   template __global__ void k_p2g<D, TB, true>(const DomDesc *, int *);                          \

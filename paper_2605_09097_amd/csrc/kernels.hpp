@@ -45,6 +45,7 @@ enum : int {
 // Newton / line-search state of one domain's implicit solve.
 struct SolveState {
   double gnorm0, gnorm, gscale, alpha, dE;
+  double gref;  // reference norm of the Newton test from a warm-start slot, or -1
   int it;  // Newton iteration index
   int phase;
   int ls_count;
@@ -117,6 +118,14 @@ struct DomDesc {
   double *part_cg;          // CG partials [parity][(r,u), (Au,u), (r,r)][pstride]
   int pstride;
   double *pnum, *pden, *w0, *w1, *w2, *w3;                // interface work buffers
+  // Warm-start slots (one per implicit solve of a Schwarz iteration), each
+  // [u: ndof][m: nn][reference norm: 1], warm_stride doubles apart; null
+  // when the domain has none.
+  double *warm;
+  int warm_stride;
+  // Fine-fine links of a multi group with overlapping refined regions:
+  // [node][2] = {donor fine domain, its node}, or {-1, -1}.
+  int *flink;
 };
 
 // Blocks a grid-stride node kernel uses for a domain (also the number of
@@ -145,8 +154,6 @@ __global__ void k_cell_scan(const DomDesc *dd);
 __global__ void k_scatter(const DomDesc *dd);
 __global__ void k_cellsort(const DomDesc *dd);
 __global__ void k_slot_layout(const DomDesc *dd);
-template <int D, typename TB>
-__global__ void k_gather_all(const DomDesc *dd);
 __global__ void k_flip(const DomDesc *dd, int ndom);
 template <int D, typename TB>
 __global__ void k_copy_state(const DomDesc *dd, int to_store);
@@ -162,8 +169,9 @@ __global__ void k_g2p(const DomDesc *dd, double dt, int *err);
 
 // implicit solve
 template <int D, typename TB>
-__global__ void k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf);
-__global__ void k_solve_begin(const DomDesc *dd, double dt);
+__global__ void k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf, int warm_slot);
+__global__ void k_solve_begin(const DomDesc *dd, double dt, int warm_slot);
+__global__ void k_warm_keep(const DomDesc *dd, int slot, int first);
 template <int D, typename TB>
 __global__ void k_grad_hess(const DomDesc *dd, int project, int *err);
 template <int D, typename TB>
@@ -199,6 +207,12 @@ template <int D>
 __global__ void k_temporal(const DomDesc *dd, double am, int a_buf, int b_buf);
 template <int D>
 __global__ void k_vel_from_u(const DomDesc *dd, double dt);
+template <int D>
+__global__ void k_fine_arbitrate(const DomDesc *dd, int n, int *n_amb);
+template <int D>
+__global__ void k_fine_links(const DomDesc *dd, int n);
+template <int D>
+__global__ void k_fine_link_apply(const DomDesc *dd, int slot, double dt, int dst_buf);
 template <int D>
 __global__ void k_resid(const DomDesc *dd, int a_buf, int b_buf);
 template <int D>

@@ -1,33 +1,26 @@
 """Gradients through many Schwarz frames (reverse mode over time).
 
-The forward pass runs the frames of a coarse/fine pair and keeps a
-checkpoint of both particle states every `checkpoint_every` frames.  The
-reverse pass walks the segments backwards: it restores a segment's
-checkpoint, reruns its frames to recover every frame's start state, and
-applies the frame adjoint of the C ABI (osmpm_schwarz_frame_adjoint, which
-recomputes one frame with its intermediates stored) from the last frame to
-the first, carrying the adjoint of the particle states and accumulating the
-derivative with respect to the Lame parameters, converted to Young's moduli
-with the textbook relations.  Memory is one checkpoint per segment plus one
-segment of frame start states.
+A thin layer over the library's multi-frame run and its reverse mode
+(osmpm_batch_run / osmpm_batch_backward): the library runs the frames, keeps
+a checkpoint of every particle state every `checkpoint_every` frames,
+reruns each segment in the reverse pass to recover its frame start states,
+applies the frame adjoints from the last frame to the first and maps the
+Lame-parameter derivatives to Young's moduli.  This module only marshals:
+scene boundary-condition tables in, device tensors of the loss adjoint in,
+and the per-domain material derivatives out, added onto the scene's
+material list (the fine domain's list, whose first entries are the coarse
+domain's materials).
 
 adjoint="implicit" applies the fixed-point adjoint of the Schwarz iteration
-instead (osmpm_schwarz_frame_adjoint_implicit): the derivative of the
-converged interface data rather than of the k* iterations actually run, with
-only the last iteration's intermediates stored per frame.
+to every frame instead of the unrolled one (the derivative of the converged
+interface data rather than of the k* iterations actually run).
 
 OSMPMStep is the torch.autograd.Function over this: E (the Young's moduli
-of the scene's materials) -> final coarse particle positions.
+of the scene's materials) -> final coarse and fine particle positions.
 """
 import numpy as np
 
 from . import binding
-
-
-def _lame_de(E, nu):
-    """d mu / dE and d lam / dE per material."""
-    nu = np.asarray(nu, dtype=np.float64)
-    return 1.0 / (2.0 * (1.0 + nu)), nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
 
 
 class SchwarzRun:
@@ -42,97 +35,66 @@ class SchwarzRun:
         self.ctx = ctx
         self.torch = ctx.torch
         self.scene = scene
-        self.pair = binding.SchwarzPair(ctx, scene, precision)
+        self.sb = binding.SchwarzBatch(ctx, [scene], precision)
+        self.pair = self.sb.pairs[0]
         so = binding.solve_opts(cg_rtol=1e-5 if precision == binding.OSMPM_MIXED else 1e-10)
         self.opts = opts if opts is not None else binding.schwarz_opts(scene.M, eps_tol=scene.eps_tol, coarse=so,
                                                                         fine=so)
         self.every = int(checkpoint_every)
         self.adj_cg_rtol = adj_cg_rtol or (1e-6 if precision == binding.OSMPM_MIXED else 1e-12)
-        self.nu = np.asarray(scene.S.nu if scene.S is not None else scene.B.nu, dtype=np.float64)
-        self.E = np.asarray(scene.S.E if scene.S is not None else scene.B.E, dtype=np.float64).copy()
+        self.nu = np.asarray(scene.S.nu, dtype=np.float64)
+        self.E = np.asarray(scene.S.E, dtype=np.float64).copy()
         self.nB = len(scene.B.E)
         self.iters = []
-        self.ckpt = {}
         self.adjoint = adjoint
         # the adjoint series to the forward's own Schwarz tolerance by default
         self.fp_tol = float(fp_tol) if fp_tol is not None else float(self.opts.eps_conv)
         self.fp_max = int(fp_max)
-        self.fp_passes = []
 
-    # ---- state handling (input particle order, device tensors)
-    def _save(self, D):
-        torch = self.torch
-        x, v, B, F, i = D.particles()
-        order = torch.argsort(i.long())
-        return tuple(t[order].clone() for t in (x, v, B, F))
-
-    def _restore(self, D, st):
-        D.set_state(*st)
+    def _positions(self, D):
+        x, _, _, _, i = D.particles()
+        return x[self.torch.argsort(i.long())]
 
     def set_E(self, E):
         self.E = np.asarray(E, dtype=np.float64).copy()
         self.pair.B.set_materials(self.E[: self.nB], self.nu[: self.nB])
         self.pair.S.set_materials(self.E, self.nu)
 
-    def _frame(self, f):
-        pB, pS = self.scene.bc_params(f)
-        self.pair.B.set_bc_params(pB)
-        self.pair.S.set_bc_params(pS)
-        return binding.schwarz_frame(self.pair.B, self.pair.S, self.scene.dT, self.opts)
-
-    # ---- passes
     def forward(self, n_frames):
         """Runs frames 0 .. n_frames-1 from the scene's initial state; returns
         the final coarse and fine particle positions ([N_B][d], [N_S][d],
-        input order)."""
+        input order, device tensors)."""
         self.pair.B.set_particles(self.scene.B)
         self.pair.S.set_particles(self.scene.S)
-        self.iters, self.ckpt = [], {}
-        for f in range(n_frames):
-            if f % self.every == 0:
-                self.ckpt[f] = (self._save(self.pair.B), self._save(self.pair.S))
-            self.iters.append(self._frame(f).iters)
-        return self._save(self.pair.B)[0], self._save(self.pair.S)[0]
+        self.sb.frame_index = 0
+        st = self.sb.run(int(n_frames), self.opts, self.every)
+        self.iters = [fr[0].iters for fr in st]
+        return self._positions(self.pair.B), self._positions(self.pair.S)
 
     def backward(self, adjB_end, adjS_end=None):
-        """Reverse sweep from the adjoint of the final particle states; returns
-        (dL/dE per material, adjoint of the initial coarse state, of the
-        initial fine state)."""
-        n = len(self.iters)
-        self.fp_passes = [0] * n
-        dmu, dlam = _lame_de(self.E, self.nu)
+        """dL/dE per material from the adjoint of the final particle positions
+        ({"x": tensor [N][d]} per domain, or None)."""
+        for a in (adjB_end, adjS_end):
+            if a is not None and any(a.get(k) is not None for k in ("v", "B", "F")):
+                raise ValueError("the multi-frame reverse mode takes position adjoints only")
+
+        def dev(a):
+            if a is None or a.get("x") is None:
+                return None
+            t = a["x"]
+            if not hasattr(t, "device"):
+                t = self.torch.as_tensor(np.asarray(t, dtype=np.float64))
+            return t.to(device=self.ctx.device, dtype=self.torch.float64).contiguous()
+
+        (dB, dS), = self.sb.backward([dev(adjB_end)], [dev(adjS_end)], adj_cg_rtol=self.adj_cg_rtol,
+                                     implicit=self.adjoint == "implicit", fp_tol=self.fp_tol, fp_max=self.fp_max)
         dE = np.zeros_like(self.E)
-        aB, aS = adjB_end, adjS_end
-        for s0 in sorted(self.ckpt, reverse=True):
-            s1 = min(s0 + self.every, n)
-            self._restore(self.pair.B, self.ckpt[s0][0])
-            self._restore(self.pair.S, self.ckpt[s0][1])
-            starts = []
-            for f in range(s0, s1):
-                starts.append((self._save(self.pair.B), self._save(self.pair.S)))
-                if f + 1 < s1:
-                    self._frame(f)
-            for f in range(s1 - 1, s0 - 1, -1):
-                stB, stS = starts[f - s0]
-                self._restore(self.pair.B, stB)
-                self._restore(self.pair.S, stS)
-                pB, pS = self.scene.bc_params(f)
-                self.pair.B.set_bc_params(pB)
-                self.pair.S.set_bc_params(pS)
-                if self.adjoint == "implicit":
-                    aB, aS, mB, lB, mS, lS, self.fp_passes[f] = binding.schwarz_frame_adjoint_implicit(
-                        self.pair.B, self.pair.S, self.scene.dT, self.opts, self.iters[f], aB, aS,
-                        fp_tol=self.fp_tol, fp_max=self.fp_max, adj_cg_rtol=self.adj_cg_rtol)
-                else:
-                    aB, aS, mB, lB, mS, lS = binding.schwarz_frame_adjoint(
-                        self.pair.B, self.pair.S, self.scene.dT, self.opts, self.iters[f], aB, aS,
-                        self.adj_cg_rtol)
-                dE[: self.nB] += mB * dmu[: self.nB] + lB * dlam[: self.nB]
-                dE += mS * dmu + lS * dlam
-        return dE, aB, aS
+        dE[: self.nB] += dB
+        dE += dS
+        return dE
 
     def close(self):
-        self.pair.close()
+        self.sb.close()
 
 
 def _autograd_function():
@@ -152,7 +114,7 @@ def _autograd_function():
         def backward(fctx, grad_xB, grad_xS):
             aB = {"x": grad_xB.detach().to(torch.float64)} if grad_xB is not None else None
             aS = {"x": grad_xS.detach().to(torch.float64)} if grad_xS is not None else None
-            dE, _, _ = fctx.run.backward(aB, aS)
+            dE = fctx.run.backward(aB, aS)
             return torch.as_tensor(dE, dtype=torch.float64), None, None
 
     return OSMPMStep

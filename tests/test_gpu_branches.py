@@ -1,0 +1,271 @@
+"""GPU parity on branches and configurations the default frames do not reach.
+
+* Sub-cycling ratio M = 4 (the Hertz and 3D fold configurations): Schwarz
+  frames of a reduced Hertz-type contact (FP64 and mixed) and of the small
+  3D fold at M = 4, so the temporal interpolation at m/M = 1/4, 2/4, 3/4
+  and the fine sub-step loop past two sub-steps are compared with the
+  oracle.
+* The line search's halving branch (Sec. 2.2.5: the step is halved until
+  the energy decreases): a quasi-static gravity cantilever taken in one
+  long step, where full Newton steps overshoot, single-domain and as a
+  two-domain Schwarz frame; halving counts must be equal.
+* The projected tangent itself: one Newton step with exactly k CG
+  iterations (no stopping test) from a deformed state with compressed
+  particles, whose projected tangents differ from the exact ones.  After a
+  fixed number of CG iterations the step depends on every entry of the
+  Hessian, so a wrong tangent fails here even though a converged solve
+  would not show it (at convergence u does not depend on the Hessian).
+
+Bars as elsewhere: FP64 1e-10 relative (2-norm and max-norm, with equal
+discrete counts), mixed 1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err, tiny_domain
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09097_amd import binding
+
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _b():
+    from paper_2605_09097_amd import binding
+
+    return binding
+
+
+def _s():
+    from paper_2605_09097_amd import scenes
+
+    return scenes
+
+
+def _frames(ctx, sc, n_frames, prec, go, oo):
+    b = _b()
+    pair = b.SchwarzPair(ctx, sc, precision=prec)
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    stats = []
+    for f in range(n_frames):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        print("frame", f, flush=True)
+        ost = oracle.schwarz_frame(OB, OS, sc.dT, oo)
+        gst = pair.frame(go)
+        stats.append((gst, ost))
+    return pair, OB, OS, stats
+
+
+def _check_pair(pair, OB, OS, sc, tol):
+    d = sc.B.dim
+    for Dg, Do, spec in ((pair.B, OB, sc.B), (pair.S, OS, sc.S)):
+        _, _, u = Dg.grid_state()
+        x, _, _, F = Dg.particles_input_order()
+        assert rel_err(u.cpu().numpy(), Do.u) < tol
+        assert rel_err(x - spec.x, Do.x - spec.x) < tol
+        assert rel_err(F - np.eye(d), Do.F - np.eye(d)) < tol
+
+
+def _hertz_small():
+    """Reduced Hertz-type contact (1/16 | 1/64, M = 4) with the cylinder
+    moving onto the block at 0.1 m/s from the start: the plate drive alone
+    takes tens of frames to reach the contact, and a fine domain at rest has
+    displacements at the rounding level of its positions, where relative
+    errors say nothing."""
+    sc = _s().hertz_scene(16, 64, ppc1d=2, M=4, n_frames=20)
+    for D in (sc.B, sc.S):
+        D.v[D.mat == 1] = (0.0, -0.1)
+    return sc
+
+
+# Tight solves for FP64 frames whose solves stop after one or two Newton
+# steps: the displacement is then converged to rounding on both sides and
+# the comparison measures the implementations, not where each solver's
+# stopping test happened to fall (at the default tolerances the two differ
+# by ~1e-8 of the displacement on this stiffer contact scene).
+TIGHT = dict(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-12)
+TIGHT_OR = dict(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-13, max_newton=60, max_cg=20000)
+
+
+def test_hertz_m4_frames_fp64(ctx):
+    b = _b()
+    sc = _hertz_small()
+    so, oso = b.solve_opts(**TIGHT), oracle.solve_opts(**TIGHT_OR)
+    print("Hertz-type contact 1/16 | 1/64, M = 4, FP64:", sc.B.n_particles, "+", sc.S.n_particles, flush=True)
+    pair, OB, OS, stats = _frames(ctx, sc, 3, b.OSMPM_FP64,
+                                  b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so),
+                                  oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=oso, fine=oso))
+    for gst, ost in stats:
+        assert gst.iters == ost.iters and gst.converged == ost.converged
+        assert (gst.n_recv_B, gst.n_recv_S, gst.n_amb) == (ost.n_recv_B, ost.n_recv_S, ost.n_amb)
+        assert (gst.newton_B, gst.newton_S) == (ost.newton_B, ost.newton_S)
+        assert (gst.ls_B, gst.ls_S) == (ost.ls_B, ost.ls_S)
+    _check_pair(pair, OB, OS, sc, FP64_TOL)
+    pair.close()
+
+
+def test_hertz_m4_frames_mixed(ctx):
+    b = _b()
+    sc = _hertz_small()
+    so = b.solve_opts(cg_rtol=1e-5)
+    print("Hertz-type contact 1/16 | 1/64, M = 4, mixed", flush=True)
+    pair, OB, OS, stats = _frames(ctx, sc, 3, b.OSMPM_MIXED, b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so,
+                                                                              fine=so),
+                                  oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol))
+    for gst, ost in stats:
+        assert gst.iters == ost.iters
+    _check_pair(pair, OB, OS, sc, MIXED_TOL)
+    pair.close()
+
+
+def test_fold_m4_frames_fp64(ctx):
+    b = _b()
+    sc = _s().fold_scene(20, 40, thick=0.1, fine_box=((0.35, 0.65), (-0.05, 0.25), (-0.05, 0.15)), band=0.05,
+                         dT=2e-3, M=4, n_frames=50, name="fold_tiny_m4")
+    print("3D fold 1/20 | 1/40, M = 4, FP64", flush=True)
+    pair, OB, OS, stats = _frames(ctx, sc, 2, b.OSMPM_FP64, b.schwarz_opts(sc.M, eps_tol=sc.eps_tol),
+                                  oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol))
+    for gst, ost in stats:
+        assert gst.iters == ost.iters
+        assert (gst.n_recv_B, gst.n_recv_S, gst.n_amb) == (ost.n_recv_B, ost.n_recv_S, ost.n_amb)
+        assert (gst.newton_B, gst.newton_S) == (ost.newton_B, ost.newton_S)
+    _check_pair(pair, OB, OS, sc, FP64_TOL)
+    pair.close()
+
+
+# ---------------------------------------------------------------- line search
+G_CANT = 9.81
+
+
+def test_line_search_halvings_single_domain(ctx):
+    """One 0.2 s step of the clamped beam under gravity: the full Newton
+    steps of the early iterations overshoot and are halved."""
+    b = _b()
+    sc = _s().cantilever_scene(inv_dx=20, ppc1d=2, split=False, gravity=-G_CANT, dt=0.2)
+    D = b.Domain(ctx, sc.B)
+    O = oracle.Domain(sc.B)
+    D.set_bc_params(np.zeros((1, 8)))
+    O.set_bc_params(np.zeros((1, 8)))
+    print("cantilever, one 0.2 s step", flush=True)
+    st = D.single_frame(0.2, b.solve_opts(gravity=(0.0, -G_CANT)))
+    ost = O.single_frame(0.2, oracle.solve_opts(gravity=(0.0, -G_CANT)))
+    assert ost.ls_halvings > 0
+    assert (st.newton_iters, st.ls_halvings, st.converged, st.ls_failed) == \
+        (ost.newton_iters, ost.ls_halvings, ost.converged, ost.ls_failed)
+    _, _, u = D.grid_state()
+    x = D.particles_input_order()[0]
+    assert rel_err(u.cpu().numpy(), O.u) < FP64_TOL
+    assert rel_err(x - sc.B.x, O.x - sc.B.x) < FP64_TOL
+    D.close()
+
+
+def test_line_search_halvings_schwarz_frame(ctx):
+    """The two-domain beam (Sec. 4.1 split) in one 0.05 s frame under a
+    strong body force: halvings on both sides, equal counts throughout the
+    Schwarz iterations."""
+    b = _b()
+    g = 40.0
+    sc = _s().cantilever_scene(inv_dx=20, ppc1d=2, split=True, gravity=-g, dt=0.05)
+    so = b.solve_opts(gravity=(0.0, -g))
+    oso = oracle.solve_opts(gravity=(0.0, -g))
+    print("two-domain cantilever, one 0.05 s frame", flush=True)
+    pair, OB, OS, stats = _frames(ctx, sc, 1, b.OSMPM_FP64,
+                                  b.schwarz_opts(1, eps_tol=sc.eps_tol, coarse=so, fine=so),
+                                  oracle.schwarz_opts(1, eps_tol=sc.eps_tol, coarse=oso, fine=oso))
+    gst, ost = stats[0]
+    assert ost.ls_B + ost.ls_S > 0
+    assert gst.iters == ost.iters and gst.converged == ost.converged
+    assert (gst.newton_B, gst.newton_S, gst.ls_B, gst.ls_S) == (ost.newton_B, ost.newton_S, ost.ls_B, ost.ls_S)
+    assert (gst.unconv_B, gst.unconv_S, gst.lsfail_B, gst.lsfail_S) == \
+        (ost.unconv_B, ost.unconv_S, ost.lsfail_B, ost.lsfail_S)
+    _check_pair(pair, OB, OS, sc, FP64_TOL)
+    pair.close()
+
+
+# ---------------------------------------------------------------- projected tangent
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("k", [1, 4, 12])
+def test_one_newton_step_with_fixed_cg_count(ctx, dim, k):
+    """u after one Newton step whose CG runs exactly k iterations."""
+    b = _b()
+    spec = tiny_domain(dim=dim, n_cells=12 if dim == 2 else 8, n_particles=900 if dim == 2 else 500, seed=70 + k,
+                       F_spread=0.25, v_scale=0.5, bc_kind=[0], bc_mask=[3 if dim == 2 else 7])
+    # compressed particles: J < 1 makes the twist eigenvalue negative, where
+    # the projection changes the tangent
+    spec.F[:] = spec.F * 0.85
+    spec.flags[:] = np.where(spec.x[:, 1] < spec.x[:, 1].min() + 1.5 * spec.dx, 2, 0)
+    dt = 2e-3
+    D = b.Domain(ctx, spec)
+    O = oracle.Domain(spec)
+    D.p2g()
+    O.p2g()
+    opts = dict(newton_rtol=0.0, newton_atol=0.0, cg_rtol=0.0, max_newton=1, max_cg=k)
+    print("one Newton step, dim", dim, "CG iterations", k, flush=True)
+    st = D.implicit_solve(dt, b.solve_opts(**opts))
+    ost = O.solve(dt, oracle.solve_opts(**opts))
+    assert (st.newton_iters, st.cg_iters, st.ls_halvings) == (ost.newton_iters, ost.cg_iters, ost.ls_halvings)
+    assert ost.cg_iters == k
+    _, _, u = D.grid_state()
+    u = u.cpu().numpy()
+    assert rel_err(u, O.u) < 1e-9
+    D.close()
+
+
+# ---------------------------------------------------------------- warm-started Schwarz iterations
+@pytest.mark.parametrize("name,frames", [("inclusion_tiny", 3), ("fold_tiny", 1)])
+def test_warm_started_frames_fp64(ctx, name, frames):
+    """Schwarz frames with warm-started solves against the oracle's
+    warm-started frames: equal Schwarz and Newton counts, FP64 bar."""
+    b = _b()
+    sc = _s().workload(name)
+    print("warm-started frames,", name, flush=True)
+    pair, OB, OS, stats = _frames(ctx, sc, frames, b.OSMPM_FP64,
+                                  b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=True),
+                                  oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=True))
+    for gst, ost in stats:
+        assert gst.iters == ost.iters
+        assert (gst.newton_B, gst.newton_S) == (ost.newton_B, ost.newton_S)
+    _check_pair(pair, OB, OS, sc, FP64_TOL)
+    pair.close()
+
+
+def test_warm_started_batch_mixed(ctx):
+    """Three inclusion scenes of different grids as one batch, mixed path,
+    warm-started, each against the oracle's warm-started run of the scene."""
+    b = _b()
+    s = _s()
+    d = s.INCLUSION_DELTA
+    scs = [s.inclusion_scene(20, 50, r_inc=0.04, E_inc=3e4, seed=11, delta=d, name="w0"),
+           s.inclusion_scene(30, 60, r_inc=0.07, E_inc=1.5e5, seed=12, delta=d, name="w1"),
+           s.inclusion_scene(20, 40, r_inc=0.05, E_inc=8e4, seed=13, delta=d, name="w2")]
+    so = b.solve_opts(cg_rtol=1e-5)
+    sb = b.SchwarzBatch(ctx, scs, precision=b.OSMPM_MIXED)
+    go = b.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol, coarse=so, fine=so, warm_start=True)
+    print("warm-started batch, mixed", flush=True)
+    for f in range(2):
+        sb.frame(go)
+    for sc, p in zip(scs, sb.pairs):
+        OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+        oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=True)
+        for f in range(2):
+            pB, pS = sc.bc_params(f)
+            OB.set_bc_params(pB)
+            OS.set_bc_params(pS)
+            oracle.schwarz_frame(OB, OS, sc.dT, oo)
+        _check_pair(p, OB, OS, sc, MIXED_TOL)
+    sb.close()

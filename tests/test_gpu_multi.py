@@ -1,5 +1,5 @@
 """GPU parity of the Schwarz frame with several fine domains (one coarse
-domain and disjoint refined regions; osmpm_multi_create /
+domain and refined regions, disjoint or overlapping each other; osmpm_multi_create /
 osmpm_multi_schwarz_frame) against the oracle's multi-domain frame, which is
 pinned on the CPU (k = 1 is the pair frame, two fine domains equal their
 union on one grid).  Two-inclusion scene at dx = 1/20 | 1/50, M = 2, three
@@ -25,11 +25,14 @@ def ctx():
     c.close()
 
 
-def _run(ctx, precision, n_frames=3):
+OVERLAP = ((0.42, 0.5), (0.58, 0.5))  # fine regions that overlap each other
+
+
+def _run(ctx, precision, n_frames=3, centres=((0.3, 0.5), (0.7, 0.5))):
     from paper_2605_09097_amd import binding as b
     from paper_2605_09097_amd import scenes
 
-    sc = scenes.two_inclusion_scene(delta=0.01)
+    sc = scenes.two_inclusion_scene(delta=0.01, centres=centres)
     prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
     so = b.solve_opts(cg_rtol=1e-10 if precision == "fp64" else 1e-5)
     go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
@@ -47,9 +50,14 @@ def _run(ctx, precision, n_frames=3):
     return sc, grp, OB, OS, stats
 
 
+@pytest.mark.parametrize("centres", ["disjoint", "overlapping"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_multi_frames_match_oracle(ctx, precision):
-    sc, grp, OB, OS, stats = _run(ctx, precision)
+def test_multi_frames_match_oracle(ctx, precision, centres):
+    """Disjoint refined regions, and refined regions overlapping each other
+    (fine-fine arbitration and linked receivers, readings of the oracle's
+    multi-domain frame)."""
+    sc, grp, OB, OS, stats = _run(ctx, precision, centres=OVERLAP if centres == "overlapping" else
+                                  ((0.3, 0.5), (0.7, 0.5)))
     tol = 1e-10 if precision == "fp64" else 1e-5
     for gst, ost in stats:
         assert gst.converged == ost.converged == 1
