@@ -463,7 +463,7 @@ def hertz_scene(inv_dx_B=32, inv_dx_S=128, ppc1d=2, R=0.5, E_cyl=1e5, E_block=1e
 
 def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick=0.02, E=5e5, nu=0.35,
                rho=1000.0, seed=0, dT=2e-3, M=4, n_frames=500, angle=math.pi, hinge_x=0.5,
-               fine_box=((0.4, 0.6), (-0.02, 0.22), (-0.02, 0.04)), band=0.02, tau_rel=1e-3,
+               fine_box=((0.4, 0.6), (-0.02, 0.22), (-0.02, 0.04)), band=0.02, margin=0.05, tau_rel=1e-3,
                eps_tol_rel=1e-9, name="fold"):
     """3D folding slab: [0,length] x [0,width] x [0,thick], the layer of
     particles within one spacing of x = 0 clamped, the layer at x = length
@@ -472,7 +472,10 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
     The fine domain carries the material inside fine_box; the coarse domain
     the material outside fine_box shrunk by band.  The coarse grid covers the
     half circle the free end sweeps, the fine grid the band its free half
-    sweeps."""
+    sweeps; both grids extend a further `margin` along x and below the slab,
+    where the soft slab's own motion (the stretch towards the lifted end, the
+    sag between the clamp and the hinge) carries material past the box and
+    the sweep."""
     lat = math.lcm(inv_dx_B, inv_dx_S, 100)
     h0 = 1.0 / lat
     (fx0, fx1), (fy0, fy1), (fz0, fz1) = fine_box
@@ -511,18 +514,19 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
     pad = 3
     reach = length - hinge_x
     cB = lat // inv_dx_B
-    lo = [-pad, -pad, -pad]
-    hi = [ncx + pad, ncy + pad, int(math.ceil((thick / 2 + reach) * inv_dx_B)) + pad]
+    mB, mS = int(math.ceil(margin * inv_dx_B)), int(math.ceil(margin * inv_dx_S))
+    lo = [-pad - mB, -pad, -pad - mB]
+    hi = [ncx + pad + mB, ncy + pad, int(math.ceil((thick / 2 + reach) * inv_dx_B)) + pad]
     B = _domain(3, h0, [l * cB for l in lo], cB, [hi[a] - lo[a] + 1 for a in range(3)], xB,
                 np.zeros(len(xB), np.int32), [E], [nu], rho, ppc1d, flB, [BC_FIX, BC_ROTATE], [0b111, 0b111],
                 m_ref, tau_rel)
     cS = lat // inv_dx_S
-    loS = [sx[0] - pad, sy[0] - pad, sz[0] - pad]
+    loS = [sx[0] - pad - mS, sy[0] - pad, sz[0] - pad - mS]
     # the fine grid also covers the quarter circle that the free half of the
     # fine box sweeps about the hinge axis as the end turns up to 90 degrees
     # (and past it, down again), so fine particles stay inside their grid
     sweep_z = int(math.ceil((thick / 2 + math.hypot(fx1 - hinge_x, thick / 2)) * inv_dx_S))
-    hiS = [sx[1] + pad, sy[1] + pad, max(sz[1], sweep_z) + pad]
+    hiS = [sx[1] + pad + mS, sy[1] + pad, max(sz[1], sweep_z) + pad]
     S = _domain(3, h0, [l * cS for l in loS], cS, [hiS[a] - loS[a] + 1 for a in range(3)], xS,
                 np.zeros(len(xS), np.int32), [E], [nu], rho, ppc1d, flS, [], [], m_ref, tau_rel)
     omega = angle / (n_frames * dT)
