@@ -152,15 +152,24 @@ typedef struct {
  * NULL for the default stream; the context never destroys it. */
 osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out);
 osmpm_status osmpm_ctx_set_stream(osmpm_ctx *ctx, void *stream);
-/* Solve cycles (a fixed sequence of CG, line-search, Newton-step, gradient
- * and Newton-test launches plus the copy of the small status block) are
- * replayed as HIP graphs, built once per batch side and cycle shape and
- * cached; enable = 0 enqueues the launches one by one instead.  Results are
- * identical either way.  Default: disabled (on the MI355X with ROCm 7 the
- * replay measured about 2 % slower per frame than direct launches for the
+/* HIP graph replay.  enable = 1: solve cycles (a fixed sequence of CG,
+ * line-search, Newton-step, gradient and Newton-test launches plus the copy
+ * of the small status block) are replayed as HIP graphs, built once per
+ * batch side and cycle shape and cached.  enable = 2: in addition, a whole
+ * Schwarz iteration of a pair or batch frame (Alg. 1's loop body: the coarse
+ * solve, the fine restart, interpolations and M sub-steps, the projection
+ * and the residuals, then the status copy) is one graph, built once per
+ * iteration class (the first iteration, later odd and even ones), frame
+ * step and option set, when both solves have a fixed schedule: max_newton =
+ * 1, max_ls = 0, cg_rtol = 0 (one Newton step of exactly max_cg CG
+ * iterations, the step taken only if it lowers the energy).  Adaptive solves
+ * decide Newton steps and halvings on the host between cycles and keep
+ * cycle graphs (or direct launches).  enable = 0 enqueues every launch
+ * individually.  Results are the same either way.  Default: 0 (cycle
+ * replay measured about 2 % slower per frame than direct launches on the
  * refined inclusion: the cost is the GPU's dependent-dispatch latency, which
  * a graph does not remove).  Kernel timing (osmpm_profile_enable) always uses
- * individual launches. */
+ * individual launches.  OSMPM_E_INVALID_ARG for other values. */
 osmpm_status osmpm_ctx_set_graphs(osmpm_ctx *ctx, int32_t enable);
 /* How the CG scalars (stop test, step length, direction weight; Sec. 2.2.5's
  * linear solve) are formed.  mode 0: inside every CG launch, each workgroup

@@ -74,6 +74,18 @@ struct CycleGraph {
   hipGraphExec_t exec = nullptr;
 };
 
+// A cached whole Schwarz iteration of a two-sided group (fixed-schedule
+// solves only): key (iteration class, frame step, Schwarz options) and the
+// instantiated graph.  Iteration classes: 0 the first iteration (cold
+// solves), 1 and 2 later iterations of odd and even index (the work-buffer
+// roles alternate).
+struct IterGraph {
+  int cls = 0;
+  double dT = 0.0;
+  osmpm_schwarz_opts o{};
+  hipGraphExec_t exec = nullptr;
+};
+
 // Work buffer indices understood by the kernels (see wbuf).
 constexpr int kBufVn = 4, kBufVbc = 5;
 // Partial-sum arrays per domain: two scalar reductions and the CG's three
@@ -94,7 +106,7 @@ struct osmpm_ctx {
   std::vector<ProfPending> pending;
   std::vector<osmpm_batch *> groups;  // every live group (error words)
   uint64_t next_uid = 1;
-  bool graphs = false;            // replay solve cycles as HIP graphs
+  int graphs = 0;                 // 1: replay solve cycles as HIP graphs; 2: also whole Schwarz iterations
   int cg_split = -1;              // CG scalars: 0 fused, 1 separate launch, -1 by size
   GraphBuild *rec = nullptr;      // graph being built (launches become nodes)
 };
@@ -191,6 +203,7 @@ struct osmpm_batch {
   Ext ext[2];
   std::vector<double> bytes[2][OSMPM_K_COUNT];  // algorithmic bytes per domain and kernel
   std::vector<CycleGraph> cycles[2];            // cached solve-cycle graphs per side
+  std::vector<IterGraph> iters;                 // cached whole-iteration graphs
   RunRecord *run = nullptr;                     // last multi-frame run (osmpm_batch_run)
   std::vector<void *> allocs;
 };
@@ -391,6 +404,8 @@ void group_free(osmpm_batch *G) {
   for (int s = 0; s < 2; ++s)
     for (CycleGraph &cgph : G->cycles[s])
       if (cgph.exec) (void)hipGraphExecDestroy(cgph.exec);
+  for (IterGraph &ig : G->iters)
+    if (ig.exec) (void)hipGraphExecDestroy(ig.exec);
   if (G->h_status) (void)hipHostFree(G->h_status);
   run_free(G->run);
   for (void *p : G->allocs) (void)hipFree(p);
@@ -573,6 +588,9 @@ osmpm_status group_sync(osmpm_batch *G) {
     for (CycleGraph &cgph : G->cycles[s])  // launch extents may change
       if (cgph.exec) (void)hipGraphExecDestroy(cgph.exec);
     G->cycles[s].clear();
+    for (IterGraph &ig : G->iters)
+      if (ig.exec) (void)hipGraphExecDestroy(ig.exec);
+    G->iters.clear();
     HIP_TRY(c, hipMemcpyAsync(G->dd[s], G->hdd[s].data(), sizeof(DomDesc) * G->n, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     Ext E;
@@ -804,6 +822,27 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
   const long max_cycles = (long)(o->max_newton + 1) * ((o->max_cg + 4) / 4 + o->max_ls + 3) + 8;
   osmpm_status st;
+  if (c->rec) {
+    // Recorded into a whole-iteration graph (fixed-schedule solves: one
+    // Newton step of exactly max_cg CG iterations, no halving): one cycle
+    // of max_cg + 2 CG launches ends every domain's solve, so no state is
+    // read back; the counts go to the device totals.
+    int b = o->max_cg + 2;
+    b += b & 1;
+    for (int j = 0; j < b; ++j) {
+      launch(c, -1, 0, -1, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt, o->cg_rtol,
+             (int)o->max_cg, split);
+      if (split) launch(c, -1, 0, -1, k_cg_reduce, dim3(1, n), blk, 0, dd, j & 1, o->cg_rtol, (int)o->max_cg);
+    }
+    launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
+           o->gravity[0], o->gravity[1], o->gravity[2]);
+    launch(c, -1, 0, -1, k_ls_check, dim3(1, n), blk, 0, dd, (int)o->max_ls);
+    grad_phase();
+    if (warm_slot >= 0)
+      launch(c, -1, 0, -1, k_warm_keep, dim3(E.node_blocks, n), blk, 0, dd, warm_slot, warm_use ? 0 : 1);
+    launch(c, -1, 0, -1, k_solve_tally, dim3(1, n), blk, 0, dd, 0);
+    return OSMPM_OK;
+  }
   // A warm-started solve often passes its first Newton test: one status
   // read then costs less than a cycle of launches that would find every
   // domain done.
@@ -1053,11 +1092,16 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
   interp_group<D>(G, kBufVn, nullptr, iS_prev, nullptr);
   std::vector<int> live(n, 1);
   std::vector<osmpm_solve_stats> ss;
-  for (int k = 0; k < o->k_max; ++k) {
+  // One Schwarz iteration's launches; while a graph is being recorded
+  // (c->rec) the solves take their fixed schedule and report no counts.
+  auto iteration = [&](int k) -> osmpm_status {
+    osmpm_status r;
+    const bool rec = c->rec != nullptr;
     // the coarse solve over dT takes buffer piB on its receivers
-    if ((s = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss, warm ? 0 : -1, k > 0))) return s;
-    for (int i = 0; i < n; ++i)
-      if (live[i]) add_stats(st[i], false, ss[i]);
+    if ((r = solve_side<D, TB>(G, 0, dT, 1, piB, &o->coarse, &ss, warm ? 0 : -1, k > 0))) return r;
+    if (!rec)
+      for (int i = 0; i < n; ++i)
+        if (live[i]) add_stats(st[i], false, ss[i]);
     launch(c, -1, 0, -1, k_vel_from_u<D>, dim3(blocks_for(G->ext[0].max_nn), n), dim3(kBlock), 0,
            (const DomDesc *)G->dd[0], dT);
     // the fine domains restart from the stored state and take M sub-steps
@@ -1069,9 +1113,10 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
     for (int m = 1; m <= M; ++m) {
       launch(c, -1, 0, -1, k_temporal<D>, dim3(blocks_for(G->ext[1].max_ndof, 1024), n), dim3(kBlock), 0,
              (const DomDesc *)G->dd[1], (double)m / (double)M, 0, iS_new);
-      if ((s = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss, warm ? m - 1 : -1, k > 0))) return s;
-      for (int i = 0; i < n; ++i)
-        if (live[i]) add_stats(st[i], true, ss[i]);
+      if ((r = solve_side<D, TB>(G, 1, dt, 1, kBufVbc, &o->fine, &ss, warm ? m - 1 : -1, k > 0))) return r;
+      if (!rec)
+        for (int i = 0; i < n; ++i)
+          if (live[i]) add_stats(st[i], true, ss[i]);
       g2p_side<D, TB>(G, 1, dt);
       p2g_side<D, TB>(G, 1, false);
     }
@@ -1079,7 +1124,88 @@ osmpm_status schwarz_group(osmpm_batch *G, double dT, const osmpm_schwarz_opts *
     project_group<D>(G, o->eps_tol, nullptr, piB_next, nullptr);
     resid_side<D>(G, 0, piB_next, piB);
     resid_side<D>(G, 1, iS_new, iS_prev);
-    if ((s = read_status(G))) return s;
+    return OSMPM_OK;
+  };
+  // Whole iterations as graphs: both solves must have a fixed schedule, so
+  // that an iteration is a fixed launch sequence (the Newton and line-search
+  // decisions of adaptive solves are taken on the host between cycles, and
+  // HIP graphs here have no conditional nodes).
+  auto fixed = [](const osmpm_solve_opts &so) {
+    return so.max_newton == 1 && so.max_ls == 0 && so.cg_rtol == 0.0 && so.max_cg >= 1;
+  };
+  const bool whole = c->graphs >= 2 && !c->prof && fixed(o->coarse) && fixed(o->fine);
+  std::vector<int> prev_tally(whole ? 10 * n : 0, 0);
+  if (whole)
+    for (int sd = 0; sd < 2; ++sd)
+      launch(c, -1, 0, -1, k_solve_tally, dim3(1, n), dim3(kBlock), 0, (const DomDesc *)G->dd[sd], 1);
+  for (int k = 0; k < o->k_max; ++k) {
+    if (whole) {
+      const int cls = k == 0 ? 0 : 1 + (k & 1);
+      IterGraph *ig = nullptr;
+      for (IterGraph &x : G->iters)
+        if (x.cls == cls && x.dT == dT && std::memcmp(&x.o, o, sizeof(osmpm_schwarz_opts)) == 0) ig = &x;
+      if (!ig) {
+        // recorded now and launched below; the host mirrors of the buffer
+        // parity were advanced while recording
+        GraphBuild gb;
+        HIP_TRY(c, hipGraphCreate(&gb.graph, 0));
+        c->rec = &gb;
+        s = iteration(k);
+        c->rec = nullptr;
+        hipGraphNode_t cp = nullptr;
+        if (!s && gb.err == hipSuccess)
+          gb.err = hipGraphAddMemcpyNode1D(&cp, gb.graph, gb.last ? &gb.last : nullptr, gb.last ? 1 : 0,
+                                           G->h_status, G->status, G->status_bytes, hipMemcpyDeviceToHost);
+        hipGraphExec_t ex = nullptr;
+        if (!s && gb.err == hipSuccess) gb.err = hipGraphInstantiate(&ex, gb.graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gb.graph);
+        if (s) return s;
+        if (gb.err != hipSuccess)
+          return fail(c, OSMPM_E_DEVICE, std::string("Schwarz iteration graph: ") + hipGetErrorString(gb.err));
+        IterGraph x;
+        x.cls = cls;
+        x.dT = dT;
+        x.o = *o;
+        x.exec = ex;
+        G->iters.push_back(x);
+        ig = &G->iters.back();
+      } else {
+        // a replay flips the particle buffers of every active fine domain
+        // once per fine P2G (1 + M of them)
+        if ((M + 1) & 1)
+          for (int i = 0; i < n; ++i)
+            if (G->act[1][i] == 1) G->dom[1][i]->cur ^= 1;
+        for (int i = 0; i < n; ++i)
+          if (G->act[1][i] == 1) {
+            G->dom[1][i]->have_p2g = true;
+            G->dom[1][i]->have_solve = false;
+          }
+      }
+      if ((s = check_launch(c))) return s;
+      HIP_TRY(c, hipGraphLaunch(ig->exec, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      if ((s = status_error(G))) return s;
+      // the solves' counts of this iteration from the device totals
+      for (int sd = 0; sd < 2; ++sd) {
+        const SolveState *hs = h_ss(G, sd);
+        for (int i = 0; i < n; ++i) {
+          int *pv = &prev_tally[(sd * n + i) * 5];
+          if (live[i]) {
+            osmpm_schwarz_stats &q = st[i];
+            const int *t = hs[i].tally;
+            (sd ? q.newton_S : q.newton_B) += t[0] - pv[0];
+            (sd ? q.cg_S : q.cg_B) += t[1] - pv[1];
+            (sd ? q.ls_S : q.ls_B) += t[2] - pv[2];
+            (sd ? q.unconv_S : q.unconv_B) += t[3] - pv[3];
+            (sd ? q.lsfail_S : q.lsfail_B) += t[4] - pv[4];
+          }
+          for (int j = 0; j < 5; ++j) pv[j] = hs[i].tally[j];
+        }
+      }
+    } else {
+      if ((s = iteration(k))) return s;
+      if ((s = read_status(G))) return s;
+    }
     const double *res = h_res(G);
     std::swap(piB, piB_next);
     std::swap(iS_new, iS_prev);
@@ -2162,8 +2288,8 @@ osmpm_status osmpm_ctx_create(int32_t device, void *stream, osmpm_ctx **out) {
 }
 
 osmpm_status osmpm_ctx_set_graphs(osmpm_ctx *ctx, int32_t enable) {
-  if (!ctx) return OSMPM_E_INVALID_ARG;
-  ctx->graphs = enable != 0;
+  if (!ctx || enable < 0 || enable > 2) return OSMPM_E_INVALID_ARG;
+  ctx->graphs = enable;
   return OSMPM_OK;
 }
 
@@ -2665,8 +2791,9 @@ osmpm_status osmpm_single_frame_adjoint_noalloc(osmpm_domain *d, double dt, cons
   A.cap = kFixedRegionBytes;
   // graph replay (instantiation allocates) and kernel timing (event
   // creation) are suspended for the call
-  const bool graphs = c->graphs, prof = c->prof;
-  c->graphs = false;
+  const int graphs = c->graphs;
+  const bool prof = c->prof;
+  c->graphs = 0;
   c->prof = false;
   const osmpm_status s =
       DISPATCH2(d->D, d->precision, single_adjoint_impl)(d, dt, o, adj_cg_rtol, in, out, mubar, lambar, A);

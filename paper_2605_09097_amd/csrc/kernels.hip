@@ -953,6 +953,24 @@ __global__ void __launch_bounds__(kBlock) k_warm_keep(const DomDesc *dd, int slo
   if (first && i0 == 0) w[dm.ndof + dm.g.nn] = dm.ss->gnorm0;
 }
 
+// After a solve: its counts added to the domain's running totals (reset = 1
+// clears them instead).  One thread per domain.
+__global__ void __launch_bounds__(kBlock) k_solve_tally(const DomDesc *dd, int reset) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (threadIdx.x != 0) return;
+  SolveState &s = *dm.ss;
+  if (reset) {
+    for (int k = 0; k < 5; ++k) s.tally[k] = 0;
+    return;
+  }
+  if (!*dm.active) return;
+  s.tally[0] += s.newton_iters;
+  s.tally[1] += s.cg_iters;
+  s.tally[2] += s.ls_halvings;
+  s.tally[3] += s.converged ? 0 : 1;
+  s.tally[4] += s.ls_failed;
+}
+
 // ====================================================================== gradient + Hessian
 // Per particle at the iterate u: F = (I + sum u_i gradN_i^T) F^n and P(F) in
 // FP64; the gradient V P F^nT gradN_i is scattered (FP64).  The particle's

@@ -53,6 +53,10 @@ struct SolveState {
   int newton_iters, cg_iters, ls_halvings;
   int n_active;  // nodes with m > 0 after the last P2G
   int n_tiles_live;  // tiles holding particles after the last binning
+  // running totals over the solves of a frame (Newton steps, CG iterations,
+  // line-search halvings, unconverged solves, failed line searches), kept
+  // on the device when a whole Schwarz iteration replays as one graph
+  int tally[5];
 };
 
 __host__ __device__ inline bool phase_wants_grad(int ph) { return ph == kPhaseGrad || ph == kPhaseStep; }
@@ -172,6 +176,7 @@ template <int D, typename TB>
 __global__ void k_bc_init(const DomDesc *dd, double dt, int use_schwarz, int vbc_buf, int warm_slot);
 __global__ void k_solve_begin(const DomDesc *dd, double dt, int warm_slot);
 __global__ void k_warm_keep(const DomDesc *dd, int slot, int first);
+__global__ void k_solve_tally(const DomDesc *dd, int reset);
 template <int D, typename TB>
 __global__ void k_grad_hess(const DomDesc *dd, int project, int *err);
 template <int D, typename TB>

@@ -203,6 +203,61 @@ def test_graph_replay_matches_eager(ctx):
         assert rel_err(fg[3] - x0, fe[3] - x0) < 1e-12
 
 
+@pytest.mark.parametrize("warm", [False, True])
+def test_whole_iteration_graphs_match_eager(ctx, warm):
+    """Whole Schwarz iterations replayed as HIP graphs (osmpm_ctx_set_graphs
+    mode 2, fixed-schedule solves: one Newton step of exactly 12 CG
+    iterations, no halving) against the same frames enqueued launch by
+    launch, on a batch of three scenes whose pairs leave the launches at
+    different iterations: every frame replays the three cached iteration
+    graphs (first, odd, even) several times, with eager work and host reads
+    between the replays; Schwarz, Newton, CG, halving and failure counts are
+    equal per scene and frame, and the state equal to rounding."""
+    from paper_2605_09097_amd import binding as b
+
+    scs = _batch_scenes()
+    fixed = b.solve_opts(cg_rtol=0.0, max_newton=1, max_ls=0, max_cg=12)
+    opts = b.schwarz_opts(scs[0].M, k_max=9, eps_tol=scs[0].eps_tol, coarse=fixed, fine=fixed, warm_start=warm)
+    runs = {}
+    for mode in (2, 0):
+        ctx.graphs(mode)
+        batch = b.SchwarzBatch(ctx, scs)
+        frames = []
+        for _ in range(3):
+            st = batch.frame(opts)
+            frames.append([(q.iters, q.converged, q.newton_B, q.newton_S, q.cg_B, q.cg_S, q.ls_B, q.ls_S,
+                            q.unconv_B, q.unconv_S, q.lsfail_B, q.lsfail_S) for q in st])
+            frames.append([(pr.B.grid_state()[2].cpu().numpy().copy(), pr.S.grid_state()[2].cpu().numpy().copy(),
+                            pr.S.particles_input_order()[0].copy(), pr.B.particles_input_order()[0].copy())
+                           for pr in batch.pairs])
+        batch.close()
+        runs[mode] = frames
+    ctx.graphs(0)
+    g, e = runs[2], runs[0]
+    for f in range(0, len(g), 2):
+        assert g[f] == e[f], (f // 2, g[f], e[f])
+        for i, sc in enumerate(scs):
+            for a, r in zip(g[f + 1][i][:2], e[f + 1][i][:2]):
+                assert rel_err(a, r) < 1e-12
+            assert rel_err(g[f + 1][i][2] - sc.S.x, e[f + 1][i][2] - sc.S.x) < 1e-12
+            assert rel_err(g[f + 1][i][3] - sc.B.x, e[f + 1][i][3] - sc.B.x) < 1e-12
+    # the schedule is what was asked for: at most one Newton attempt per
+    # coarse solve (none where the start passes the Newton test), each of
+    # exactly 12 CG iterations, taken or refused by the energy test
+    for row in e[0]:
+        iters, newton_B, cg_B, lsfail_B = row[0], row[2], row[4], row[10]
+        assert newton_B + lsfail_B <= iters and cg_B == 12 * (newton_B + lsfail_B)
+
+
+def test_graph_mode_rejects_unknown_values(ctx):
+    from paper_2605_09097_amd import binding as b
+
+    for bad in (-1, 3):
+        with pytest.raises(b.OsmpmError):
+            ctx.graphs(bad)
+    ctx.graphs(0)
+
+
 def test_autotune_picks_a_measured_candidate(ctx):
     from paper_2605_09097_amd import autotune
     from paper_2605_09097_amd import binding as b
