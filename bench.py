@@ -62,13 +62,13 @@ def _host_cpu():
             "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
-def cpu_baseline(sc, frames, budget_s=30.0):
+def cpu_baseline(sc, frames, budget_s=30.0, warm_start=False):
     """The CPU oracle (single-threaded FP64 C) on the first frames of the same
     workload; returns (value, sample description, state)."""
     import oracle
 
     OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
-    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=warm_start)
     t0 = time.perf_counter()
     done = 0
     for f in range(frames):
@@ -98,7 +98,7 @@ def counter_traffic():
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     csrc = os.path.join(ROOT, "paper_2605_09097_amd", "csrc")
-    src = open(os.path.join(csrc, "kernels.hip"), "rb").read() + open(os.path.join(csrc, "device.hpp"), "rb").read()
+    src = b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("kernels.hip", "kernels.hpp", "device.hpp"))
     if hashlib.sha256(src).hexdigest()[:16] != vals.get("kernel_source_sha256_16"):
         return None
     try:
@@ -122,20 +122,24 @@ def _kernel_stats(ctx):
     return out
 
 
-def large_form(ctx, name, prec, solve, frames, warmup):
-    """A large single-pair workload (the Hertz contact or the 3D fold): warm-up
-    frames, timed frames, then one instrumented frame for the per-kernel
-    launch durations.  Default tile shapes (no tuning)."""
+def large_form(ctx, name, prec, solve, frames, warmup, warm_start=False):
+    """A large single-pair workload (the Hertz contact or the 3D fold): `warmup`
+    frames from the initial state (untimed: they bring the run to a
+    representative point, e.g. the contact loaded or the fold under way),
+    timed frames, then one instrumented frame for the per-kernel launch
+    durations.  Default tile shapes (no tuning)."""
     import numpy as np
     import torch
 
     from paper_2605_09097_amd import binding, scenes
 
     sc = scenes.workload(name)
-    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve, warm_start=warm_start)
     pair = binding.SchwarzPair(ctx, sc, precision=prec)
-    for _ in range(warmup):
+    for f in range(warmup):
         pair.frame(opts)
+        if f % 20 == 19:
+            _progress("%s: frame %d of %d reached" % (name, f + 1, warmup))
     torch.cuda.synchronize()
     t = time.perf_counter()
     stats = [pair.frame(opts) for _ in range(frames)]
@@ -152,11 +156,13 @@ def large_form(ctx, name, prec, solve, frames, warmup):
             "frames": "%d-%d" % (warmup, warmup + frames - 1), "value": frames * ps / el,
             "unit": "particle-steps/s", "ms_per_step": 1e3 * el / frames,
             "schwarz_iters_mean": float(np.mean([st.iters for st in stats])),
+            "newton_per_frame_mean": float(np.mean([st.newton_B + st.newton_S for st in stats])),
             "cg_per_frame_mean": float(np.mean([st.cg_B + st.cg_S for st in stats])),
+            "ls_halvings_per_frame_mean": float(np.mean([st.ls_B + st.ls_S for st in stats])),
             "kernels": kern}
 
 
-def multi_form(ctx, prec, solve, frames, warmup=1):
+def multi_form(ctx, prec, solve, frames, warmup=1, warm_start=False):
     """Several refined regions: the two-inclusion scene at dx = 1/160 | 1/400
     (M = 2, inclusions with eigenstrain, top driven down) run with its two
     fine domains (osmpm_multi_schwarz_frame), and the same particles as one
@@ -168,7 +174,7 @@ def multi_form(ctx, prec, solve, frames, warmup=1):
     from paper_2605_09097_amd import binding, scenes
 
     sc = scenes.two_inclusion_scene(160, 400, delta=0.01, n_frames=200)
-    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve, warm_start=warm_start)
     out = {"workload": "two refined inclusions, coarse dx 1/160, fine dx 1/400, M=2",
            "N_B": sc.B.n_particles, "N_S": [s.n_particles for s in sc.S],
            "frames": "%d-%d" % (warmup, warmup + frames - 1)}
@@ -202,6 +208,49 @@ def multi_form(ctx, prec, solve, frames, warmup=1):
     xS0 = np.concatenate([s.x for s in sc.S])
     dS = np.abs(runs["multi"][1] - runs["union"][1]).max() / max(np.abs(runs["union"][1] - xS0).max(), 1e-300)
     out["max_rel_diff_multi_vs_union"] = {"B": float(dB), "S": float(dS)}
+    return out
+
+
+def graph_form(ctx, sc, prec, tiles, frames, max_cg, warmup=1):
+    """Whole Schwarz iterations as HIP graphs against direct launches: the
+    same frames of the headline workload with fixed-schedule solves (one
+    Newton step of exactly max_cg CG iterations, no halving, warm-started
+    iterations), run with every launch enqueued (graphs 0), with solve
+    cycles replayed (graphs 1) and with each whole iteration replayed
+    (graphs 2), each from a fresh pair.  The iteration counts must agree;
+    the final positions are compared."""
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding
+
+    fixed = binding.solve_opts(cg_rtol=0.0, max_newton=1, max_ls=0, max_cg=max_cg)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=fixed, fine=fixed, warm_start=True)
+    out = {"solves": "1 Newton step, %d CG iterations, no halving, warm-started iterations" % max_cg,
+           "frames": "%d-%d" % (warmup, warmup + frames - 1)}
+    xs = {}
+    try:
+        for mode, name in ((0, "direct"), (1, "cycle_graphs"), (2, "iteration_graphs")):
+            ctx.graphs(mode)
+            pair = binding.SchwarzPair(ctx, sc, precision=prec, tile_B=tiles[0], tile_S=tiles[1])
+            for _ in range(warmup):
+                pair.frame(opts)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            stats = [pair.frame(opts) for _ in range(frames)]
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            xs[name] = pair.S.particles_input_order()[0]
+            out[name] = {"ms_per_step": 1e3 * el / frames,
+                         "schwarz_iters": [st.iters for st in stats],
+                         "cg_per_frame_mean": float(np.mean([st.cg_B + st.cg_S for st in stats]))}
+            pair.close()
+    finally:
+        ctx.graphs(0)
+    ref = xs["direct"]
+    span = max(np.abs(ref - sc.S.x).max(), 1e-300)
+    out["max_rel_diff_vs_direct"] = {k: float(np.abs(v - ref).max() / span) for k, v in xs.items() if k != "direct"}
+    out["iteration_graph_speedup"] = out["direct"]["ms_per_step"] / out["iteration_graphs"]["ms_per_step"]
     return out
 
 
@@ -246,7 +295,7 @@ def domain_probe(ctx, spec_s, prec):
             else "fp64", "newton": st.newton_iters, "cg": st.cg_iters, "kernels": kern}
 
 
-def batched_form(ctx, n_scenes, steps, prec, solve):
+def batched_form(ctx, n_scenes, steps, prec, solve, warm_start=False, tile_cache=None):
     """The batched form: n_scenes independent inclusion scenes of uneven sizes
     (scenes.batch_scene) as one Schwarz batch, every stage one launch over all
     scenes.  One warm-up frame, `steps` timed frames, then one instrumented
@@ -259,8 +308,8 @@ def batched_form(ctx, n_scenes, steps, prec, solve):
     from paper_2605_09097_amd import autotune
 
     scs = [scenes.batch_scene(s) for s in range(n_scenes)]
-    opts = binding.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol, coarse=solve, fine=solve)
-    tile, tune = autotune.tune_batch(ctx, scs, opts, prec)
+    opts = binding.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol, coarse=solve, fine=solve, warm_start=warm_start)
+    tile, tune = autotune.tune_batch(ctx, scs, opts, prec, advance=1, cache=tile_cache)
     sb = binding.SchwarzBatch(ctx, scs, precision=prec, tile=tile)
     sb.frame(opts)
     torch.cuda.synchronize()
@@ -340,34 +389,31 @@ def adjoint_form(ctx, sc, prec, frames, mode="unrolled"):
            "note": "backward = per segment: restore checkpoint, rerun frames; per frame: recompute with storage, "
                    "reverse sweep (adjoint CG per solve)"}
     if mode == "implicit":
-        out["adjoint_passes"] = run.fp_passes
         out["fp_tol"] = run.fp_tol
     run.close()
     return out
 
 
-def adjoint_batch_form(n_scenes, frames, workers, prec):
+def adjoint_batch_form(ctx, n_scenes, frames, prec, warm_start=False):
     """Reverse mode on the batched family: for every scene s, dL/dE (matrix
     and inclusion Young's moduli) of L = 1/2 sum |x_p(T) - x_p^target|^2 over
     the driven top-layer coarse particles after `frames` frames, where the
     target is the same scene run forward with the inclusion modulus drawn
     from seed 1000 + s.  Targets come from one batched forward run; the
-    gradients from one checkpointed run per scene (one checkpoint every 10
-    frames), `workers` scenes at a time, each on its own stream."""
-    import threading
-
+    gradients from one osmpm_batch_run over all scenes (a checkpoint every 10
+    frames) and its osmpm_batch_backward."""
     import numpy as np
     import torch
 
-    from paper_2605_09097_amd import binding, diff, scenes
+    from paper_2605_09097_amd import binding, scenes
 
     solve = binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10)
     tscs = [scenes.batch_scene(s, E_override=scenes.batch_target_E(s)) for s in range(n_scenes)]
-    opts = binding.schwarz_opts(tscs[0].M, eps_tol=tscs[0].eps_tol, coarse=solve, fine=solve)
-    ctx0 = binding.Context(0)
+    opts = binding.schwarz_opts(tscs[0].M, eps_tol=tscs[0].eps_tol, coarse=solve, fine=solve,
+                                warm_start=warm_start)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sb = binding.SchwarzBatch(ctx0, tscs, precision=prec)
+    sb = binding.SchwarzBatch(ctx, tscs, precision=prec)
     for _ in range(frames):
         sb.frame(opts)
     targets = []
@@ -377,48 +423,34 @@ def adjoint_batch_form(n_scenes, frames, workers, prec):
     sb.close()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    out = [None] * n_scenes
-    errors = []
-
-    def work(w):
-        try:
-            stream = torch.cuda.Stream()
-            ctx = binding.Context(0, stream=stream)
-            with torch.cuda.stream(stream):
-                for s in range(w, n_scenes, workers):
-                    sc = scenes.batch_scene(s)
-                    run = diff.SchwarzRun(ctx, sc, prec, checkpoint_every=10)
-                    xB, _ = run.forward(frames)
-                    idx, tgt = targets[s]
-                    ti = torch.as_tensor(idx, device=xB.device)
-                    diffx = xB[ti] - torch.as_tensor(tgt, device=xB.device)
-                    adj = torch.zeros_like(xB)
-                    adj[ti] = diffx
-                    dE, _, _ = run.backward({"x": adj})
-                    out[s] = {"scene": s, "loss": 0.5 * float((diffx * diffx).sum()), "dL_dE": [float(g) for g in dE],
-                              "E_inclusion": float(sc.S.E[1]), "E_target": scenes.batch_target_E(s)}
-                    run.close()
-                    print("reverse mode: scene %d done" % s, file=sys.stderr, flush=True)
-            stream.synchronize()
-            ctx.close()
-        except Exception as e:  # reported after the join
-            errors.append(repr(e))
-
-    th = [threading.Thread(target=work, args=(w,)) for w in range(workers)]
-    for t in th:
-        t.start()
-    for t in th:
-        t.join()
+    scs = [scenes.batch_scene(s) for s in range(n_scenes)]
+    sb = binding.SchwarzBatch(ctx, scs, precision=prec)
+    sb.run(frames, opts, checkpoint_every=10)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    ctx0.close()
-    if errors:
-        raise RuntimeError("batched reverse mode: " + "; ".join(errors))
+    adjs, out = [], []
+    for s, p in enumerate(sb.pairs):
+        x, _, _, _ = p.B.particles_input_order()
+        idx, tgt = targets[s]
+        r = x[idx] - tgt
+        a = np.zeros_like(x)
+        a[idx] = r
+        adjs.append(torch.as_tensor(a, device="cuda"))
+        out.append({"scene": s, "loss": 0.5 * float((r * r).sum()), "E_inclusion": float(scs[s].S.E[1]),
+                    "E_target": scenes.batch_target_E(s)})
+    grads = sb.backward(adjs, None, adj_cg_rtol=1e-6 if prec == binding.OSMPM_MIXED else 1e-12)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for o, (dB, dS) in zip(out, grads):
+        dE = np.array(dS, dtype=np.float64)
+        dE[: len(dB)] += dB
+        o["dL_dE"] = [float(g) for g in dE]
+    sb.close()
     agree = sum(1 for o in out if (o["dL_dE"][1] > 0) == (o["E_inclusion"] > o["E_target"]))
-    return {"scenes": n_scenes, "frames": frames, "checkpoint_every": 10, "workers": workers,
-            "targets_forward_s": t1 - t0, "gradients_s": t2 - t1,
-            "particle_steps_per_s_forward_and_reverse": n_scenes and
-            sum(_frame_particle_steps(scenes.batch_scene(s)) for s in range(n_scenes)) * frames / (t2 - t1),
+    ps = sum(_frame_particle_steps(sc) for sc in scs) * frames
+    return {"scenes": n_scenes, "frames": frames, "checkpoint_every": 10,
+            "targets_forward_s": t1 - t0, "forward_s": t2 - t1, "backward_s": t3 - t2,
+            "particle_steps_per_s_forward_and_reverse": ps / (t3 - t1),
             "sign_agrees_with_E_minus_E_target": agree,
             "per_scene": out}
 
@@ -471,6 +503,8 @@ def compact_summary(detail, detail_path=None):
     out["fp64_gpu_path"] = None if not fp else {
         "value": fp.get("value"), "ms_per_step": fp.get("ms_per_step"),
         "cg_iter_frac": (fp.get("roofline") or {}).get("frac")}
+    cs = detail.get("cold_start")
+    out["cold_start"] = None if not cs else {k: cs.get(k) for k in ("value", "ms_per_step", "cg_per_frame_mean")}
     out["kernels"] = {k: _kfrac(detail.get("kernels"), k) for k in ("cg_iter", "p2g", "g2p", "grad_hess")}
     b = detail.get("batched")
     if b:
@@ -479,9 +513,19 @@ def compact_summary(detail, detail_path=None):
                           "kernels": {k: _kfrac(b.get("kernels"), k) for k in ("cg_iter", "p2g", "g2p", "grad_hess")}}
     else:
         out["batched"] = None
-    out["large"] = [{"workload": L.get("workload"), "frames": L.get("frames"), "value": L.get("value"),
+    out["large"] = [{"workload": L.get("workload"), "error": L.get("error"), "frames": L.get("frames"),
+                     "value": L.get("value"),
                      "ms_per_step": L.get("ms_per_step"), "schwarz_iters_mean": L.get("schwarz_iters_mean"),
-                     "cg_per_frame_mean": L.get("cg_per_frame_mean")} for L in (detail.get("large") or [])]
+                     "newton_per_frame_mean": L.get("newton_per_frame_mean"),
+                     "cg_per_frame_mean": L.get("cg_per_frame_mean"),
+                     "ls_halvings_per_frame_mean": L.get("ls_halvings_per_frame_mean")}
+                    for L in (detail.get("large") or [])]
+    g = detail.get("graphs")
+    out["graphs"] = None if not g else {
+        "direct_ms": (g.get("direct") or {}).get("ms_per_step"),
+        "cycle_graphs_ms": (g.get("cycle_graphs") or {}).get("ms_per_step"),
+        "iteration_graphs_ms": (g.get("iteration_graphs") or {}).get("ms_per_step"),
+        "max_rel_diff": g.get("max_rel_diff_vs_direct")}
     m = detail.get("multi_domain")
     out["multi_domain"] = None if not m else {
         "multi_ms_per_step": (m.get("multi") or {}).get("ms_per_step"),
@@ -495,9 +539,8 @@ def compact_summary(detail, detail_path=None):
         "implicit_rel_diff": (a.get("implicit") or {}).get("rel_diff_vs_unrolled")}
     ab = detail.get("adjoint_batched")
     out["adjoint_batched"] = None if not ab else {
-        k: ab.get(k) for k in ("scenes", "frames", "checkpoint_every", "forward_s", "backward_s", "targets_forward_s",
-                               "gradients_s", "particle_steps_per_s_forward_and_reverse",
-                               "sign_agrees_with_E_minus_E_target")}
+        k: ab.get(k) for k in ("scenes", "frames", "checkpoint_every", "targets_forward_s", "forward_s", "backward_s",
+                               "particle_steps_per_s_forward_and_reverse", "sign_agrees_with_E_minus_E_target")}
     out["paper_context"] = {"speedup_vs_single_domain_fine_max": 9.15, "hardware": "Ryzen 9950X3D CPU (Taichi)"}
     out["detail"] = detail_path
     return out
@@ -521,7 +564,6 @@ def main():
     ap.add_argument("--adjoint-batch-scenes", type=int, default=64,
                     help="scenes of the batched reverse-mode run (0 skips it)")
     ap.add_argument("--adjoint-batch-frames", type=int, default=100)
-    ap.add_argument("--adjoint-batch-workers", type=int, default=8, help="scenes in flight, one stream each")
     ap.add_argument("--eshelby", default="",
                     help="only run the inclusion efficiency study (single-domain fine vs OS-MPM to equilibrium) "
                          "for ratio:inv_dx items, comma separated (e.g. 2:400,2:800), and exit")
@@ -529,10 +571,19 @@ def main():
                     help="only time the kernels on one domain, workload:side[:tile] (e.g. hertz:B:8x8), and exit")
     ap.add_argument("--multi-frames", type=int, default=10,
                     help="timed frames of the several-refined-regions run (0 skips it)")
+    ap.add_argument("--warm-start", type=int, default=1,
+                    help="1: warm-started Schwarz iterations (each solve starts from its previous iteration's "
+                         "solution); 0: cold starts")
+    ap.add_argument("--graph-frames", type=int, default=10,
+                    help="frames of the graph-replay comparison (0 skips it)")
+    ap.add_argument("--graph-cg", type=int, default=16, help="CG iterations of its fixed-schedule solves")
+    ap.add_argument("--tile-cache", default=None,
+                    help="JSON file of tile choices kept between runs (default: $OSMPM_TILE_CACHE, else none)")
     ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file for the full result (every section); '' skips it")
-    ap.add_argument("--large", default="hertz:2,fold:1",
-                    help="large single-pair workloads as name:timed_frames, comma separated ('' skips them)")
+    ap.add_argument("--large", default="hertz:200+3,fold:60+1,hinge:20+2",
+                    help="large single-pair workloads as name:advance+timed (frames run untimed to reach a "
+                         "representative state, then frames timed), comma separated ('' skips them)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the method's multiplicative Schwarz loop is "
@@ -574,8 +625,9 @@ def main():
         return
     sc = scenes.workload(WORKLOAD)
     solve = binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10)
-    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve)
-    opts64 = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    warm = bool(args.warm_start)
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve, warm_start=warm)
+    opts64 = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=warm)
 
     _progress("start: %s, %s path, %d + %d particles" % (WORKLOAD, args.precision, sc.B.n_particles,
                                                          sc.S.n_particles))
@@ -583,7 +635,7 @@ def main():
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
-        value_cpu, nfr, tcpu, (OB, OS) = cpu_baseline(sc, args.cpu_frames)
+        value_cpu, nfr, tcpu, (OB, OS) = cpu_baseline(sc, args.cpu_frames, warm_start=warm)
         pair = binding.SchwarzPair(ctx, sc, precision=prec)
         for _ in range(nfr):
             pair.frame(opts)
@@ -607,7 +659,8 @@ def main():
     # tile shapes picked by measurement (outside the timed region)
     from paper_2605_09097_amd import autotune
 
-    tile_B, tile_S, tune = autotune.tune_pair(ctx, sc, opts, prec)
+    # candidates are timed after the same untimed frames as the timed region
+    tile_B, tile_S, tune = autotune.tune_pair(ctx, sc, opts, prec, advance=args.warmup, cache=args.tile_cache)
 
     def timed(precision, o, steps, warmup):
         pr = binding.SchwarzPair(ctx, sc, precision=precision, tile_B=tile_B, tile_S=tile_S)
@@ -658,6 +711,17 @@ def main():
                               "bytes_per_launch": cg64["bytes_per_launch"]} if cg64 else None),
                 "kernels": kern64}
     _progress("fp64 path done")
+    cold = None
+    if warm:
+        # the same frames with cold-started solves, for the effect of the warm start
+        o_cold = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve, warm_start=False)
+        pc, stc, elc = timed(prec, o_cold, args.steps, args.warmup)
+        pc.close()
+        cold = {"value": args.steps * _frame_particle_steps(sc) / elc, "ms_per_step": 1e3 * elc / args.steps,
+                "schwarz_iters_mean": float(np.mean([s.iters for s in stc])),
+                "newton_per_frame_mean": float(np.mean([s.newton_B + s.newton_S for s in stc])),
+                "cg_per_frame_mean": float(np.mean([s.cg_B + s.cg_S for s in stc]))}
+        _progress("cold-start comparison done")
     adjoint = None
     if args.adjoint_frames > 0:
         adjoint = adjoint_form(ctx, sc, prec, args.adjoint_frames)
@@ -668,19 +732,27 @@ def main():
     _progress("adjoint section done")
     batched = None
     if args.batch_scenes > 0:
-        batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve)
+        batched = batched_form(ctx, args.batch_scenes, args.batch_steps, prec, solve, warm_start=warm,
+                               tile_cache=args.tile_cache)
     _progress("batched section done")
     adjoint_batch = None
     if args.adjoint_batch_scenes > 0:
-        adjoint_batch = adjoint_batch_form(args.adjoint_batch_scenes, args.adjoint_batch_frames,
-                                           args.adjoint_batch_workers, prec)
+        adjoint_batch = adjoint_batch_form(ctx, args.adjoint_batch_scenes, args.adjoint_batch_frames, prec,
+                                           warm_start=warm)
     _progress("batched adjoint section done")
-    multi = multi_form(ctx, prec, solve, args.multi_frames) if args.multi_frames > 0 else None
+    graphs = graph_form(ctx, sc, prec, (tile_B, tile_S), args.graph_frames, args.graph_cg) \
+        if args.graph_frames > 0 else None
+    _progress("graph replay section done")
+    multi = multi_form(ctx, prec, solve, args.multi_frames, warm_start=warm) if args.multi_frames > 0 else None
     _progress("multi-domain section done")
     large = []
     for item in filter(None, args.large.split(",")):
-        wl, nf = item.split(":")
-        large.append(large_form(ctx, wl, prec, solve, int(nf), warmup=1))
+        wl, spec = item.split(":")
+        adv, nf = spec.split("+") if "+" in spec else ("1", spec)
+        try:
+            large.append(large_form(ctx, wl, prec, solve, int(nf), warmup=int(adv), warm_start=warm))
+        except binding.OsmpmError as e:  # reported in the result; the other sections still run
+            large.append({"workload": wl, "error": str(e)})
         _progress("large workload %s done" % wl)
     if args.calibrate_copy:
         # a plain device copy of known size, for scaling HBM counters
@@ -717,7 +789,7 @@ def main():
                    "ls_halvings_per_frame_mean": float(np.mean([s.ls_B + s.ls_S for s in stats])),
                    "inner_unconverged_total": int(sum(s.unconv_B + s.unconv_S for s in stats)),
                    "inner_ls_failed_total": int(sum(s.lsfail_B + s.lsfail_S for s in stats)),
-                   "tile_B": list(tile_B), "tile_S": list(tile_S)},
+                   "warm_start": warm, "tile_B": list(tile_B), "tile_S": list(tile_S)},
         # particle updates done, Schwarz re-iterations included (each pass
         # repeats the coarse step and the M fine sub-steps)
         "particle_updates_per_s_incl_schwarz_iters": sum(iters) * ps / elapsed,
@@ -734,11 +806,14 @@ def main():
                                                                else args.steps),
         "fp64_gpu_path": fp64,
         "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
+        "cold_start": cold,
+        "speedup_vs_cold_start": (value / cold["value"]) if cold else None,
         "cpu_baseline": cpu,
         "paper_context": PAPER_CONTEXT,
         "parity": parity,
         "batched": batched,
         "large": large,
+        "graphs": graphs,
         "multi_domain": multi,
         "adjoint": adjoint,
         "adjoint_batched": adjoint_batch,

@@ -48,12 +48,19 @@ def _stub_detail():
                    "cg_per_frame_mean": 54, "kernels": kern},
                   {"workload": "fold", "frames": "1-1", "value": 1e6, "ms_per_step": 1000.0,
                    "schwarz_iters_mean": 28, "cg_per_frame_mean": 22338, "kernels": kern}],
+        "graphs": {"solves": "s" * 80, "frames": "1-10",
+                   "direct": {"ms_per_step": 5.0, "schwarz_iters": [30] * 10, "cg_per_frame_mean": 2000.0},
+                   "cycle_graphs": {"ms_per_step": 5.1, "schwarz_iters": [30] * 10, "cg_per_frame_mean": 2000.0},
+                   "iteration_graphs": {"ms_per_step": 4.9, "schwarz_iters": [30] * 10,
+                                        "cg_per_frame_mean": 2000.0},
+                   "max_rel_diff_vs_direct": {"cycle_graphs": 1e-9, "iteration_graphs": 1e-9},
+                   "iteration_graph_speedup": 1.02},
         "multi_domain": {"multi": {"ms_per_step": 6.14}, "union": {"ms_per_step": 5.85},
                          "max_rel_diff_multi_vs_union": {"B": 3e-8, "S": 3e-8}},
         "adjoint": {"frames": 100, "forward_ms_per_frame": 5.5, "backward_ms_per_frame": 16.1,
                     "dL_dE": [1.0, 2.0], "implicit": {"backward_ms_per_frame": 14.7, "rel_diff_vs_unrolled": 1.8e-8}},
         "adjoint_batched": {"scenes": 64, "frames": 100, "checkpoint_every": 10, "targets_forward_s": 7.5,
-                            "gradients_s": 67.0, "particle_steps_per_s_forward_and_reverse": 8.8e6,
+                            "forward_s": 7.0, "backward_s": 60.0, "particle_steps_per_s_forward_and_reverse": 8.8e6,
                             "sign_agrees_with_E_minus_E_target": 64,
                             "per_scene": [{"scene": s, "loss": 1e-9, "dL_dE": [1e-10, 1e-13], "E_inclusion": 3e4,
                                            "E_target": 1e5} for s in range(64)]},
