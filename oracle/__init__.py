@@ -67,7 +67,7 @@ class _Domain(C.Structure):
         ("m_ref", C.c_double), ("tau", C.c_double),
         ("m", _dp), ("vn", _dp), ("u", _dp), ("bcg", _i8p), ("q_all", _i64p),
         ("q_bnd", _i64p), ("gamma", _u8p), ("recv", _u8p), ("vbc", _dp),
-        ("use_schwarz_bc", C.c_int),
+        ("use_schwarz_bc", C.c_int), ("tau_y", _dp),
     ]
 
 
@@ -113,6 +113,7 @@ def _declare(L):
     L.or_p2g.argtypes = [dom]
     L.or_nh_eval.argtypes = [C.c_int, _dp, C.c_double, C.c_double, _dp, _dp, _dp, C.c_int]
     L.or_psd_project.argtypes = [_dp, C.c_int]
+    L.or_vm_return.argtypes = [C.c_int, _dp, C.c_double, C.c_double]
     L.or_energy.argtypes = [dom, C.c_double, _dp, _dp, _dp]
     L.or_delta_energy.argtypes = [dom, C.c_double, _dp, _dp, _dp, C.c_double, _dp]
     L.or_gradient.argtypes = [dom, C.c_double, _dp, _dp, _dp]
@@ -221,6 +222,10 @@ class Domain:
         s.vbc = _ptr(self.vbc, _dp)
         s.use_schwarz_bc = 0
         self._s = s
+        self.tau_y = None
+        ty = getattr(spec, "tau_y", None)
+        if ty is not None:
+            self.set_yield(ty)
 
     # -- state helpers -------------------------------------------------
     @property
@@ -239,6 +244,16 @@ class Domain:
         """Overwrite the particle state in place (arrays keep their addresses)."""
         for k in ("x", "v", "B", "F"):
             getattr(self, k)[...] = st[k]
+
+    def set_yield(self, tau_y):
+        """von Mises yield stress per material (<= 0 or inf: elastic); None
+        makes every material elastic."""
+        if tau_y is None:
+            self.tau_y = None
+            self._s.tau_y = _dp()
+            return
+        self.tau_y = np.ascontiguousarray(np.broadcast_to(np.asarray(tau_y, dtype=np.float64), self.mu.shape)).copy()
+        self._s.tau_y = _ptr(self.tau_y, _dp)
 
     def set_lame(self, mu, lam):
         self.mu[...] = mu
@@ -337,6 +352,16 @@ def nh_eval(F, mu, lam, project=False):
     rc = lib().or_nh_eval(d, _ptr(F, _dp), mu, lam, _ptr(psi, _dp), _ptr(P, _dp), _ptr(A, _dp),
                           int(project))
     return float(psi[0]), P, A, rc
+
+
+def vm_return(F, mu, tau_y):
+    """The von Mises return in Hencky strain applied to one deformation
+    gradient (returns the projected F and whether it changed)."""
+    F = np.ascontiguousarray(F, dtype=np.float64).copy()
+    rc = lib().or_vm_return(F.shape[0], _ptr(F, _dp), mu, tau_y)
+    if rc < 0:
+        raise ValueError("dimension")
+    return F, bool(rc)
 
 
 def psd_project(A):

@@ -78,6 +78,8 @@ typedef struct {
   unsigned char *recv;    /* [nn]     receiver set after arbitration */
   double *vbc;            /* [nn][d]  Schwarz Dirichlet velocity on receivers */
   int use_schwarz_bc;
+  double *tau_y;          /* [n_mat] von Mises yield stress, or NULL: every material elastic
+                           * (an entry <= 0 or infinite: that material elastic) */
 } or_domain;
 
 typedef struct {
@@ -1025,6 +1027,128 @@ int or_hvp(const or_domain *D, double dt, const double *u, const double *w, int 
 /* With v_i = u_i / dt on the active nodes:
  *   v_p = sum N_ip v_i,  B_p = sum N_ip v_i (x_i - x_p)^T,
  *   F_p <- (I + sum u_i grad N_ip^T) F_p,  x_p <- x_p + dt v_p. */
+/* ------------------------------------------------------------------ */
+/* Elastoplastic extension (von Mises, Hencky strain)                   */
+/* ------------------------------------------------------------------ */
+/* The paper keeps to elasticity and names elastoplastic hinges as future
+ * work (Sec. 4.4, Sec. 5).  Reading used here: multiplicative split
+ * F = F^E F^P, with the particle storing F^E; the implicit solve sees only
+ * the elastic energy Psi(F^E); after G2P's deformation-gradient update the
+ * trial F^E is projected onto the von Mises set in logarithmic strain,
+ * |dev eps| <= tau_y / (2 mu) with eps = log of the principal stretches
+ * (the closest point in eps, which keeps the principal directions and
+ * tr eps, hence det F^E).  A material with tau_y <= 0 or infinite is
+ * elastic. */
+
+/* Eigen-decomposition of the symmetric d x d matrix C (d = 2, 3) by cyclic
+ * Jacobi rotations: C = V diag(w) V^T, V column-major in V[a * d + k]
+ * (component a of eigenvector k). */
+static void sym_eig_small(const double *C, int d, double *w, double *V) {
+  double A[9];
+  memcpy(A, C, sizeof(double) * (size_t)(d * d));
+  for (int a = 0; a < d; ++a)
+    for (int k = 0; k < d; ++k) V[a * d + k] = (a == k) ? 1.0 : 0.0;
+  double scale = 0.0;
+  for (int k = 0; k < d * d; ++k) scale += A[k] * A[k];
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j) off += A[i * d + j] * A[i * d + j];
+    if (off == 0.0 || off <= 1e-34 * scale) break;
+    for (int i = 0; i < d; ++i)
+      for (int j = i + 1; j < d; ++j) {
+        const double aij = A[i * d + j];
+        if (aij == 0.0) continue;
+        /* rotation in the (i, j) plane that zeroes A_ij */
+        const double th = (A[j * d + j] - A[i * d + i]) / (2.0 * aij);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < d; ++k) {
+          const double aki = A[k * d + i], akj = A[k * d + j];
+          A[k * d + i] = c * aki - sn * akj;
+          A[k * d + j] = sn * aki + c * akj;
+        }
+        for (int k = 0; k < d; ++k) {
+          const double aik = A[i * d + k], ajk = A[j * d + k];
+          A[i * d + k] = c * aik - sn * ajk;
+          A[j * d + k] = sn * aik + c * ajk;
+        }
+        for (int k = 0; k < d; ++k) {
+          const double vki = V[k * d + i], vkj = V[k * d + j];
+          V[k * d + i] = c * vki - sn * vkj;
+          V[k * d + j] = sn * vki + c * vkj;
+        }
+      }
+  }
+  for (int k = 0; k < d; ++k) w[k] = A[k * d + k];
+}
+
+/* Projection of F (row-major d x d) onto the von Mises set in Hencky strain
+ * (see above).  With C = F^T F = V diag(s^2) V^T and eps_k = ln s_k, the
+ * projected stretches are s_k exp(-delta n_k), n = dev eps / |dev eps| and
+ * delta = |dev eps| - tau_y / (2 mu), so F <- F V diag(exp(-delta n)) V^T.
+ * Returns 1 when F was changed. */
+static int vm_return(double *F, int d, double mu, double tau_y) {
+  if (!(tau_y > 0.0) || isinf(tau_y) || !(mu > 0.0)) return 0;
+  double Cm[9], w[3], V[9];
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double t = 0.0;
+      for (int k = 0; k < d; ++k) t += F[k * d + a] * F[k * d + b];
+      Cm[a * d + b] = t;
+    }
+  sym_eig_small(Cm, d, w, V);
+  double eps[3], mean = 0.0;
+  for (int k = 0; k < d; ++k) {
+    if (!(w[k] > 0.0)) return 0; /* singular F: left to the solver's det check */
+    eps[k] = 0.5 * log(w[k]);
+    mean += eps[k];
+  }
+  mean /= d;
+  double nd = 0.0, dev[3];
+  for (int k = 0; k < d; ++k) {
+    dev[k] = eps[k] - mean;
+    nd += dev[k] * dev[k];
+  }
+  nd = sqrt(nd);
+  const double ky = tau_y / (2.0 * mu);
+  if (nd <= ky) return 0;
+  const double delta = nd - ky;
+  double f[3];
+  for (int k = 0; k < d; ++k) f[k] = exp(-delta * dev[k] / nd);
+  /* S = V diag(f) V^T, F <- F S */
+  double S[9], Fo[9];
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double t = 0.0;
+      for (int k = 0; k < d; ++k) t += V[a * d + k] * f[k] * V[b * d + k];
+      S[a * d + b] = t;
+    }
+  memcpy(Fo, F, sizeof(double) * (size_t)(d * d));
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
+      double t = 0.0;
+      for (int k = 0; k < d; ++k) t += Fo[a * d + k] * S[k * d + b];
+      F[a * d + b] = t;
+    }
+  return 1;
+}
+
+/* 1 when some material of D yields (the reverse mode has no derivative of
+ * the projection and refuses such domains). */
+static int is_plastic(const or_domain *D) {
+  if (!D->tau_y) return 0;
+  for (int k = 0; k < D->n_mat; ++k)
+    if (D->tau_y[k] > 0.0 && !isinf(D->tau_y[k])) return 1;
+  return 0;
+}
+
+/* Exported for the plasticity pins. */
+int or_vm_return(int d, double *F, double mu, double tau_y) {
+  if (d < 2 || d > 3) return -1;
+  return vm_return(F, d, mu, tau_y);
+}
+
 int or_g2p(or_domain *D, double dt) {
   const int d = D->dim, ss = stencil_size(D);
   for (int p = 0; p < D->np; ++p) {
@@ -1053,6 +1177,10 @@ int or_g2p(or_domain *D, double dt) {
         for (int e = 0; e < d; ++e) t += G[a * d + e] * Fp[e * d + b];
         Fnew[a * d + b] = t;
       }
+    if (D->tau_y) {
+      const int mt = D->mat[p];
+      vm_return(Fnew, d, D->mu[mt], D->tau_y[mt]);
+    }
     for (int k = 0; k < d * d; ++k) {
       Fp[k] = Fnew[k];
       D->B[p * d * d + k] = Bp[k];
@@ -2276,6 +2404,7 @@ int or_single_frame_adjoint(or_domain *D, double dt, const or_solve_opts *opt, d
                             const double *xb, const double *vb, const double *Bb, const double *Fb,
                             double *oxb, double *ovb, double *oBb, double *oFb, double *mubar,
                             double *lambar) {
+  if (is_plastic(D)) return OR_E_ARG;
   const int d = D->dim, nn = nnodes(D), np = D->np;
   fwd_point f0;
   int rc = fwd_alloc(&f0, D);
@@ -2591,6 +2720,7 @@ int or_schwarz_frame_adjoint(or_domain *B, or_domain *S, double dT, const or_sch
                              const double *FbS, double *oxB, double *ovB, double *oBB, double *oFB,
                              double *oxS, double *ovS, double *oBS, double *oFS, double *mubarB,
                              double *lambarB, double *mubarS, double *lambarS) {
+  if (is_plastic(B) || is_plastic(S)) return OR_E_ARG;
   int unused = 0;
   return schwarz_adjoint(B, S, dT, o, iters, adj_cg_rtol, 0, 0.0, 0, &unused, xbB, vbB, BbB, FbB, xbS, vbS,
                          BbS, FbS, oxB, ovB, oBB, oFB, oxS, ovS, oBS, oFS, mubarB, lambarB, mubarS, lambarS);
@@ -2619,6 +2749,7 @@ int or_schwarz_frame_adjoint_implicit(or_domain *B, or_domain *S, double dT, con
                                       double *oBB, double *oFB, double *oxS, double *ovS, double *oBS,
                                       double *oFS, double *mubarB, double *lambarB, double *mubarS,
                                       double *lambarS) {
+  if (is_plastic(B) || is_plastic(S)) return OR_E_ARG;
   return schwarz_adjoint(B, S, dT, o, iters, adj_cg_rtol, 1, fp_tol, fp_max, fp_used, xbB, vbB, BbB, FbB, xbS,
                          vbS, BbS, FbS, oxB, ovB, oBB, oFB, oxS, ovS, oBS, oFS, mubarB, lambarB, mubarS,
                          lambarS);
