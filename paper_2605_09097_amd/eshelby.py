@@ -86,10 +86,10 @@ def stress_error(parts, R, Pc, r_eval=R_EVAL):
     return float(np.sqrt(num / den))
 
 
-def run(ctx, mode, ratio, inv_dx, precision, max_frames=20000, check_every=10):
+def run(ctx, mode, ratio, inv_dx, precision, max_frames=20000, check_every=10, warm_start=False):
     """One run to static equilibrium ("single" or "dual"); returns frames, wall
     time of the frame loop (inputs already resident), particle count and the
-    stress error."""
+    stress error.  warm_start applies to the dual run's Schwarz iterations."""
     import torch
 
     from . import binding, scenes
@@ -110,7 +110,7 @@ def run(ctx, mode, ratio, inv_dx, precision, max_frames=20000, check_every=10):
         pair = binding.SchwarzPair(ctx, sc, precision=precision)
         doms = [pair.B, pair.S]
         specs = [sc.B, sc.S]
-        opts = binding.schwarz_opts(2, eps_tol=sc.eps_tol, coarse=so, fine=so)
+        opts = binding.schwarz_opts(2, eps_tol=sc.eps_tol, coarse=so, fine=so, warm_start=warm_start)
 
         def step():
             pair.frame(opts)

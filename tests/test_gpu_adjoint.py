@@ -4,7 +4,10 @@ a Schwarz frame for a random linear functional of the end-of-frame states,
 both with respect to the start-of-frame particle states and the Lame
 parameters of every material.  FP64 path: 1e-7 relative (the forward states
 of the two implementations agree to ~1e-13 and both adjoint solves run to
-1e-12); mixed path (FP32 stored states and adjoint CG vectors): 1e-3."""
+1e-12); mixed path (FP32 stored states and adjoint CG vectors, adjoint CG
+to 1e-6): 1e-4, which the FP32 storage (relative 6e-8) and the adjoint
+solves' tolerance times the small systems' condition numbers (tens) bound
+with a wide margin (measured: at most 3.5e-6, on the Lame gradients)."""
 import numpy as np
 import pytest
 
@@ -46,7 +49,7 @@ def test_single_frame_adjoint_parity(ctx, precision):
 
     sc = scenes.inclusion_single(inv_dx=16, n_frames=3, delta=0.01)
     prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
-    tol = 1e-7 if precision == "fp64" else 1e-3
+    tol = 1e-7 if precision == "fp64" else 1e-4
     so = b.solve_opts(newton_rtol=1e-12, newton_atol=1e-16, cg_rtol=1e-12 if precision == "fp64" else 1e-5)
     D = b.Domain(ctx, sc.B, precision=prec)
     O = oracle.Domain(sc.B)
@@ -111,7 +114,7 @@ def test_schwarz_frame_adjoint_parity(ctx, precision):
     from paper_2605_09097_amd import binding as b
 
     sc, go, oo, pair, OB, OS, K, WB, WS = _schwarz_case(ctx, precision)
-    tol = 1e-7 if precision == "fp64" else 1e-3
+    tol = 1e-7 if precision == "fp64" else 1e-4
     print("Schwarz frame adjoint,", precision, "K =", K, flush=True)
     g = b.schwarz_frame_adjoint(pair.B, pair.S, sc.dT, go, K, WB, WS,
                                 adj_cg_rtol=1e-12 if precision == "fp64" else 1e-6)
@@ -128,7 +131,7 @@ def test_schwarz_frame_adjoint_implicit_parity(ctx, precision):
     from paper_2605_09097_amd import binding as b
 
     sc, go, oo, pair, OB, OS, K, WB, WS = _schwarz_case(ctx, precision)
-    tol = 1e-7 if precision == "fp64" else 1e-3
+    tol = 1e-7 if precision == "fp64" else 1e-4
     rtol = 1e-12 if precision == "fp64" else 1e-6
     print("implicit Schwarz frame adjoint, 30 passes,", precision, "K =", K, flush=True)
     g = b.schwarz_frame_adjoint_implicit(pair.B, pair.S, sc.dT, go, K, WB, WS, fp_tol=0.0, fp_max=30,
@@ -191,5 +194,5 @@ def test_autograd_gradient_matches_oracle(ctx):
     xbar[idx] = r
     # (the reverse sweep leaves the oracle domains at an earlier state)
     dE, _, _ = oracle.schwarz_run_gradient(sc, E0, Bd, Sd, starts, iters, oo, {"x": xbar}, {"x": q})
-    assert abs(float(L) - Lo) <= 1e-9 * abs(Lo)
+    assert abs(float(L.detach()) - Lo) <= 1e-9 * abs(Lo)
     assert rel_err(E.grad.numpy(), dE) < 1e-6, (E.grad.numpy(), dE)
