@@ -210,6 +210,19 @@ void osmpm_domain_destroy(osmpm_domain *dom);
 /* Material table (host array of n_mat entries). */
 osmpm_status osmpm_domain_set_materials(osmpm_domain *dom, const osmpm_material *mats_host,
                                         int32_t n_mat);
+/* Elastoplastic extension (the paper keeps to elasticity and names
+ * elastoplastic hinges as future work, Sec. 4.4 and Sec. 5): von Mises yield
+ * stress per material (host array of n_mat entries, n_mat equal to the
+ * material table's; n_mat = 0 makes every material elastic; an entry <= 0
+ * or infinite: that material is elastic).  Reading: F = F^E F^P with the
+ * particle holding F^E; the implicit solve sees the elastic energy only;
+ * after G2P's deformation-gradient update F^E is projected onto
+ * |dev eps| <= tau_y / (2 mu), eps the logarithms of its singular values
+ * (the closest point in eps: det F^E, the polar rotation and the principal
+ * directions are kept).  The reverse-mode entry points return
+ * OSMPM_E_INVALID_ARG for domains with a finite yield stress.  NaN entries
+ * or a length mismatch: OSMPM_E_INVALID_ARG.  Synchronises. */
+osmpm_status osmpm_domain_set_yield(osmpm_domain *dom, int32_t n_mat, const double *tau_y_host);
 
 /* Copies n particles in: positions x [n][d], velocities v [n][d], affine
  * matrices B [n][d][d], deformation gradients F [n][d][d], masses m_p and

@@ -25,7 +25,7 @@ OSMPM_K_CG_ITER, OSMPM_K_P2G, OSMPM_K_G2P, OSMPM_K_GRAD_HESS = 0, 1, 2, 3
 ABI_SYMBOLS = [
     "osmpm_ctx_create", "osmpm_ctx_set_stream", "osmpm_ctx_set_graphs", "osmpm_ctx_set_cg_split", "osmpm_sync", "osmpm_last_error", "osmpm_ctx_destroy",
     "osmpm_profile_enable", "osmpm_profile_query",
-    "osmpm_domain_create", "osmpm_domain_destroy", "osmpm_domain_set_materials",
+    "osmpm_domain_create", "osmpm_domain_destroy", "osmpm_domain_set_materials", "osmpm_domain_set_yield",
     "osmpm_domain_set_particles", "osmpm_domain_set_selection", "osmpm_domain_set_scene_bc",
     "osmpm_p2g", "osmpm_implicit_solve", "osmpm_g2p", "osmpm_interface_build",
     "osmpm_project_S_to_B", "osmpm_interp_B_to_S", "osmpm_temporal_interp", "osmpm_set_schwarz_bc",
@@ -90,6 +90,7 @@ def _declare(L):
         "osmpm_profile_query": [_vp, C.c_int32, P(C.c_int64), P(C.c_double), P(C.c_double)],
         "osmpm_domain_create": [_vp, P(osmpm_grid), C.c_int32, C.c_int64, P(C.c_int32), P(_vp)],
         "osmpm_domain_set_materials": [_vp, P(osmpm_material), C.c_int32],
+        "osmpm_domain_set_yield": [_vp, C.c_int32, P(C.c_double)],
         "osmpm_domain_set_particles": [_vp, C.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
         "osmpm_domain_set_selection": [_vp, C.c_double, C.c_double],
         "osmpm_domain_set_scene_bc": [_vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_double)],
@@ -261,6 +262,8 @@ class Domain:
                                                   for E, nu in zip(spec.E, spec.nu)])
         ctx.check(lib().osmpm_domain_set_materials(h, mats, len(spec.E)), "set_materials")
         ctx.check(lib().osmpm_domain_set_selection(h, float(spec.m_ref), float(spec.tau)), "set_selection")
+        if getattr(spec, "tau_y", None) is not None:
+            self.set_yield(spec.tau_y)
         self.n_groups = len(spec.bc_kind)
         self._kind = (C.c_int32 * max(self.n_groups, 1))(*spec.bc_kind)
         self._mask = (C.c_int32 * max(self.n_groups, 1))(*spec.bc_mask)
@@ -287,6 +290,16 @@ class Domain:
         mats = (osmpm_material * len(E))(*[osmpm_material(float(a), float(b)) for a, b in zip(E, nu)])
         self.ctx.check(lib().osmpm_domain_set_materials(self.handle, mats, len(E)), "set_materials")
         self.n_mat = len(E)
+
+    def set_yield(self, tau_y):
+        """von Mises yield stress per material (<= 0 or inf: elastic); None
+        makes every material elastic."""
+        if tau_y is None:
+            self.ctx.check(lib().osmpm_domain_set_yield(self.handle, 0, None), "set_yield")
+            return
+        t = np.broadcast_to(np.asarray(tau_y, dtype=np.float64), (self.n_mat,))
+        arr = (C.c_double * self.n_mat)(*[float(v) for v in t])
+        self.ctx.check(lib().osmpm_domain_set_yield(self.handle, self.n_mat, arr), "set_yield")
 
     def set_state(self, x, v, B, F):
         """Overwrite the particle state (device tensors in input order) keeping

@@ -137,6 +137,8 @@ struct osmpm_domain {
   int n_mat = 0;
   double *mu = nullptr, *lam = nullptr;
   std::vector<double> E_h, nu_h;  // host copy of the material table
+  double *tau_y = nullptr;        // von Mises yield stress per material (device)
+  bool plastic = false;           // some material yields
   double m_ref = 1.0, tau = 0.0;
   SceneBC bc{};
   double *m = nullptr, *vn = nullptr, *u = nullptr, *vbc = nullptr, *gg = nullptr;
@@ -209,6 +211,9 @@ struct osmpm_batch {
 };
 
 namespace {
+
+constexpr const char *kNoPlasticAdjoint =
+    "the reverse mode has no derivative of the plastic projection (a material has a finite yield stress)";
 
 osmpm_status fail(osmpm_ctx *c, osmpm_status s, const std::string &msg) {
   if (c) c->last_error = msg;
@@ -524,6 +529,8 @@ DomDesc make_desc(const osmpm_domain *d) {
   x.lcnt = d->lcnt;
   x.mu = d->mu;
   x.lam = d->lam;
+  x.tau_y = d->tau_y;
+  x.plastic = d->plastic ? 1 : 0;
   x.m = d->m;
   x.vn = d->vn;
   x.u = d->u;
@@ -2452,6 +2459,7 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   if (!s) s = dalloc(d, &d->w3, nd);
   if (!s) s = dalloc(d, &d->mu, 64);
   if (!s) s = dalloc(d, &d->lam, 64);
+  if (!s) s = dalloc(d, &d->tau_y, 64);
   if (!s) {
     osmpm_domain *self = d;
     s = group_create(ctx, 1, &self, nullptr, &d->solo);
@@ -2522,6 +2530,27 @@ osmpm_status osmpm_domain_set_materials(osmpm_domain *d, const osmpm_material *m
   for (int i = 0; i < n_mat; ++i) {
     d->E_h[i] = mats[i].E;
     d->nu_h[i] = mats[i].nu;
+  }
+  return OSMPM_OK;
+}
+
+osmpm_status osmpm_domain_set_yield(osmpm_domain *d, int32_t n_mat, const double *tau_y) {
+  if (!d || n_mat < 0 || n_mat > 64 || (n_mat > 0 && !tau_y)) return OSMPM_E_INVALID_ARG;
+  if (n_mat > 0 && n_mat != d->n_mat)
+    return fail(d->ctx, OSMPM_E_INVALID_ARG, "yield table length differs from the material table's");
+  std::vector<double> t(64, 0.0);
+  bool plastic = false;
+  for (int i = 0; i < n_mat; ++i) {
+    if (std::isnan(tau_y[i])) return fail(d->ctx, OSMPM_E_INVALID_ARG, "NaN yield stress");
+    t[i] = tau_y[i];
+    if (tau_y[i] > 0.0 && !std::isinf(tau_y[i])) plastic = true;
+  }
+  osmpm_ctx *c = d->ctx;
+  HIP_TRY(c, hipMemcpyAsync(d->tau_y, t.data(), 64 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (plastic != d->plastic) {
+    d->plastic = plastic;
+    d->version += 1;  // the descriptor carries the flag
   }
   return OSMPM_OK;
 }
@@ -2741,6 +2770,9 @@ osmpm_status osmpm_batch_backward(osmpm_batch *b, const double *const *xbar_B_ho
   if (!b->run) return fail(b->c, OSMPM_E_STATE, "no osmpm_batch_run to differentiate");
   for (int i = 0; i < b->n; ++i)
     for (int sd = 0; sd < 2; ++sd)
+      if (b->dom[sd][i]->plastic) return fail(b->c, OSMPM_E_INVALID_ARG, kNoPlasticAdjoint);
+  for (int i = 0; i < b->n; ++i)
+    for (int sd = 0; sd < 2; ++sd)
       if (b->dom[sd][i]->n_mat < 1 || (int)b->dom[sd][i]->nu_h.size() != b->dom[sd][i]->n_mat)
         return fail(b->c, OSMPM_E_STATE, "a domain has no material table");
   osmpm_status s = group_sync(b);
@@ -2759,6 +2791,7 @@ osmpm_status osmpm_single_frame_adjoint(osmpm_domain *d, double dt, const osmpm_
   if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
   if (d->np > 0 && (!xbar || !vbar || !Bbar || !Fbar || !oxbar || !ovbar || !oBbar || !oFbar))
     return OSMPM_E_INVALID_ARG;
+  if (d->plastic) return fail(d->ctx, OSMPM_E_INVALID_ARG, kNoPlasticAdjoint);
   const double *in[4] = {xbar, vbar, Bbar, Fbar};
   double *out[4] = {oxbar, ovbar, oBbar, oFbar};
   Arena A;
@@ -2776,6 +2809,7 @@ osmpm_status osmpm_single_frame_adjoint_noalloc(osmpm_domain *d, double dt, cons
   if (d->np > 0 && (!xbar || !vbar || !Bbar || !Fbar || !oxbar || !ovbar || !oBbar || !oFbar))
     return OSMPM_E_INVALID_ARG;
   osmpm_ctx *c = d->ctx;
+  if (d->plastic) return fail(c, OSMPM_E_INVALID_ARG, kNoPlasticAdjoint);
   void *region = fixed_region(c->device);
   if (!region) return fail(c, OSMPM_E_DEVICE, "fixed work region not set up on this device");
   const size_t need = single_adjoint_bytes(d);
@@ -2815,6 +2849,7 @@ static osmpm_status schwarz_adjoint_call(osmpm_domain *B, osmpm_domain *S, doubl
   if (implicit && (fp_max < 1 || std::isnan(fp_tol))) return OSMPM_E_INVALID_ARG;
   if (B->np > 0 && (!xbB || !vbB || !BbB || !FbB || !oxB || !ovB || !oBB || !oFB)) return OSMPM_E_INVALID_ARG;
   if (S->np > 0 && (!xbS || !vbS || !BbS || !FbS || !oxS || !ovS || !oBS || !oFS)) return OSMPM_E_INVALID_ARG;
+  if (B->plastic || S->plastic) return fail(B->ctx, OSMPM_E_INVALID_ARG, kNoPlasticAdjoint);
   osmpm_batch *G = nullptr;
   osmpm_status s = pair_group(B, S, &G);
   if (s) return s;

@@ -417,6 +417,72 @@ __device__ inline void jacobi_eig(T *W, T *Q) {
   }
 }
 
+// Elastoplastic extension (the paper names elastoplastic hinges as future
+// work): the particle holds the elastic part F^E of F = F^E F^P; after the
+// deformation-gradient update F^E is projected onto the von Mises set in
+// logarithmic strain, |dev eps| <= tau_y / (2 mu), eps_k = ln s_k over the
+// singular values s_k.  The closest point keeps tr eps and the principal
+// directions: with F^T F = Q diag(s^2) Q^T, F <- F Q diag(exp(-delta n)) Q^T,
+// n = dev eps / |dev eps|, delta = |dev eps| - tau_y / (2 mu).  Returns
+// whether F changed; a material with tau_y <= 0 or infinite is elastic.
+template <int D>
+__device__ inline bool von_mises_project(double *F, double mu, double tau_y) {
+  if (!(tau_y > 0.0) || isinf(tau_y) || !(mu > 0.0)) return false;
+  double W[D * D], Q[D * D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) t += F[k * D + a] * F[k * D + b];
+      W[a * D + b] = t;
+    }
+  jacobi_eig<D, double>(W, Q);
+  double e[D], mean = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const double s2 = W[k * D + k];
+    if (!(s2 > 0.0)) return false;  // singular: the solver's det check reports it
+    e[k] = 0.5 * log(s2);
+    mean += e[k];
+  }
+  mean *= 1.0 / D;
+  double nrm2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    e[k] -= mean;
+    nrm2 += e[k] * e[k];
+  }
+  const double nrm = sqrt(nrm2), ky = tau_y / (2.0 * mu);
+  if (!(nrm > ky)) return false;
+  const double c = (nrm - ky) / nrm;
+  double f[D], S[D * D], Fo[D * D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) f[k] = exp(-c * e[k]);
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) t += Q[a * D + k] * f[k] * Q[b * D + k];
+      S[a * D + b] = t;
+    }
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) Fo[k] = F[k];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < D; ++k) t += Fo[a * D + k] * S[k * D + b];
+      F[a * D + b] = t;
+    }
+  return true;
+}
+
 // Folded Neo-Hookean tangent Atil = V C^T A C (A = dP/dF at F, C: G -> G F^n,
 // packed upper triangle, n = D*D) built from the analytic eigensystem of the
 // Hessian of an isotropic energy (Smith, de Goes and Kim, "Analytic

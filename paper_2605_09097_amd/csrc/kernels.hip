@@ -818,6 +818,7 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
 #pragma unroll
     for (int k = 0; k < D * D; ++k) Hp[k] = (double)gload((const TB *)H, k * cap + p);
   }
+  double Hn[D * D];
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -825,9 +826,24 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
       double t = Hp[a * D + b] + (double)G[a * D + b];
 #pragma unroll
       for (int e = 0; e < D; ++e) t += (double)G[a * D + e] * Hp[e * D + b];
-      gstore(H, (a * D + b) * cap + p, (TB)t);
-      gstore(B, (a * D + b) * cap + p, Bp[a * D + b]);
+      Hn[a * D + b] = t;
     }
+  if (uload(&dm.plastic)) {
+    // elastoplastic materials: F^E projected onto the yield set (FP64)
+    const int mt = gload((const int *)P.mat, p);
+    double Fe[D * D];
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) Fe[k] = Hn[k] + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+    if (von_mises_project<D>(Fe, dm.mu[mt], dm.tau_y[mt])) {
+#pragma unroll
+      for (int k = 0; k < D * D; ++k) Hn[k] = Fe[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) {
+    gstore(H, k * cap + p, (TB)Hn[k]);
+    gstore(B, k * cap + p, Bp[k]);
+  }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     gstore(v, a * cap + p, vp[a]);

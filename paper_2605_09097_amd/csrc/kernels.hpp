@@ -130,6 +130,10 @@ struct DomDesc {
   // Fine-fine links of a multi group with overlapping refined regions:
   // [node][2] = {donor fine domain, its node}, or {-1, -1}.
   int *flink;
+  // von Mises yield stress per material (elastoplastic extension), and
+  // whether any material yields (0: G2P skips the projection)
+  const double *tau_y;
+  int plastic;
 };
 
 // Blocks a grid-stride node kernel uses for a domain (also the number of

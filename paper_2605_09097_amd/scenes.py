@@ -76,6 +76,7 @@ class DomainSpec:
     m_ref: float = 1.0
     tau: float = 0.0
     ppc1d: int = 2
+    tau_y: Optional[np.ndarray] = None  # von Mises yield stress per material (None: elastic)
 
     @property
     def dx(self) -> float:
@@ -91,6 +92,8 @@ class DomainSpec:
         c.n_nodes = list(self.n_nodes)
         c.bc_kind = list(self.bc_kind)
         c.bc_mask = list(self.bc_mask)
+        if self.tau_y is not None:
+            c.tau_y = np.array(self.tau_y, dtype=np.float64)
         return c
 
 

@@ -1,0 +1,177 @@
+"""GPU parity of the elastoplastic extension (von Mises in Hencky strain,
+projected after G2P's deformation-gradient update; the oracle's projection
+is pinned in test_oracle_plastic.py) against the FP64 oracle: a
+single-domain run and Schwarz frames in 2D and 3D, FP64 to 1e-10 with
+equal iteration counts and mixed to 1e-5; the reverse mode refuses plastic
+domains.  Yield stresses are set per material at the median deviatoric
+log-strain that the elastic oracle reaches, so that about half of the
+particles yield."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_09097_amd import binding
+
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _dev_norms(F):
+    s = np.linalg.svd(F, compute_uv=False)
+    e = np.log(s)
+    return np.linalg.norm(e - e.mean(axis=1, keepdims=True), axis=1)
+
+
+def _with_yield(spec, O_elastic):
+    """spec with tau_y = 2 mu k per material, k the median deviatoric
+    log-strain of that material's particles in the elastic oracle run."""
+    dn = _dev_norms(O_elastic.F)
+    ty = np.zeros(len(O_elastic.mu))
+    for m in range(len(ty)):
+        sel = O_elastic.mat == m
+        if sel.any() and np.median(dn[sel]) > 0:
+            ty[m] = 2.0 * O_elastic.mu[m] * np.median(dn[sel])
+    out = spec.copy()
+    out.tau_y = ty
+    return out
+
+
+def _plastic_pair_scene(sc, n_frames):
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    for f in range(n_frames):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        oracle.schwarz_frame(OB, OS, sc.dT, oo)
+    return dataclasses.replace(sc, B=_with_yield(sc.B, OB), S=_with_yield(sc.S, OS))
+
+
+def _run_pair(ctx, sc, n_frames, precision):
+    from paper_2605_09097_amd import binding as b
+
+    pair = b.SchwarzPair(ctx, sc, precision=precision)
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    assert OB.tau_y is not None and OS.tau_y is not None
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    so = b.solve_opts() if precision == b.OSMPM_FP64 else b.solve_opts(cg_rtol=1e-5)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
+    stats = []
+    for f in range(n_frames):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        ost = oracle.schwarz_frame(OB, OS, sc.dT, oo)
+        stats.append((pair.frame(go), ost))
+    return pair, OB, OS, stats
+
+
+def _yielded(spec, O):
+    """Particles whose deviatoric log-strain sits on the yield surface."""
+    dn = _dev_norms(O.F)
+    ky = np.array([O.tau_y[m] / (2 * O.mu[m]) if O.tau_y[m] > 0 else np.inf for m in O.mat])
+    return int(np.sum(np.abs(dn - ky) <= 1e-9 * ky))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_single_domain_plastic_frames(ctx, precision):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.inclusion_single(inv_dx=20, n_frames=3, delta=0.05, loaded=False)
+    Oe = oracle.Domain(sc.B)
+    p, _ = sc.bc_params(0)
+    Oe.set_bc_params(p)
+    Oe.single_frame(sc.dT, oracle.solve_opts())
+    spec = _with_yield(sc.B, Oe)
+    prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
+    tol = FP64_TOL if precision == "fp64" else MIXED_TOL
+    D = b.Domain(ctx, spec, precision=prec)
+    O = oracle.Domain(spec)
+    so = b.solve_opts() if precision == "fp64" else b.solve_opts(cg_rtol=1e-5)
+    print("plastic single domain,", precision, flush=True)
+    for f in range(3):
+        p, _ = sc.bc_params(f)
+        D.set_bc_params(p)
+        O.set_bc_params(p)
+        st = D.single_frame(sc.dT, so)
+        ost = O.single_frame(sc.dT, oracle.solve_opts())
+        if precision == "fp64":
+            assert st.newton_iters == ost.newton_iters
+    assert _yielded(spec, O) > 0
+    x, _, _, F = D.particles_input_order()
+    assert rel_err(D.grid_state()[2].cpu().numpy(), O.u) < tol
+    assert rel_err(x - spec.x, O.x - spec.x) < tol
+    assert rel_err(F - np.eye(2), O.F - np.eye(2)) < tol
+    D.close()
+
+
+@pytest.mark.parametrize("name,dim", [("inclusion_tiny", 2), ("fold_tiny", 3)])
+def test_schwarz_plastic_frames_fp64(ctx, name, dim):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = _plastic_pair_scene(scenes.workload(name), 1)
+    print("plastic Schwarz frames,", name, flush=True)
+    pair, OB, OS, stats = _run_pair(ctx, sc, 2, b.OSMPM_FP64)
+    for gst, ost in stats:
+        assert gst.iters == ost.iters
+        assert (gst.n_recv_B, gst.n_recv_S, gst.n_amb) == (ost.n_recv_B, ost.n_recv_S, ost.n_amb)
+        assert gst.newton_B == ost.newton_B and gst.newton_S == ost.newton_S
+    assert _yielded(sc.B, OB) + _yielded(sc.S, OS) > 0
+    for Dg, Do, spec in ((pair.B, OB, sc.B), (pair.S, OS, sc.S)):
+        x, _, _, F = Dg.particles_input_order()
+        assert rel_err(Dg.grid_state()[2].cpu().numpy(), Do.u) < FP64_TOL
+        assert rel_err(x - spec.x, Do.x - spec.x) < FP64_TOL
+        assert rel_err(F - np.eye(dim), Do.F - np.eye(dim)) < FP64_TOL
+    pair.close()
+
+
+def test_schwarz_plastic_frames_mixed(ctx):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = _plastic_pair_scene(scenes.workload("inclusion_tiny"), 1)
+    print("plastic Schwarz frames, mixed", flush=True)
+    pair, OB, OS, stats = _run_pair(ctx, sc, 2, b.OSMPM_MIXED)
+    for Dg, Do, spec in ((pair.B, OB, sc.B), (pair.S, OS, sc.S)):
+        x, _, _, F = Dg.particles_input_order()
+        assert rel_err(Dg.grid_state()[2].cpu().numpy(), Do.u) < MIXED_TOL
+        assert rel_err(x - spec.x, Do.x - spec.x) < MIXED_TOL
+        assert rel_err(F - np.eye(2), Do.F - np.eye(2)) < MIXED_TOL
+    pair.close()
+
+
+def test_reverse_mode_refuses_plastic_domains(ctx):
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.inclusion_single(inv_dx=16, n_frames=3, delta=0.01)
+    spec = sc.B.copy()
+    spec.tau_y = np.full(len(spec.E), 1.0)
+    D = b.Domain(ctx, spec)
+    O = oracle.Domain(sc.B)
+    W = {k: np.zeros_like(v) for k, v in O.state().items()}
+    with pytest.raises(b.OsmpmError):
+        b.single_frame_adjoint(D, sc.dT, b.solve_opts(), W)
+    with pytest.raises(b.OsmpmError):
+        b.single_frame_adjoint(D, sc.dT, b.solve_opts(), W, noalloc=True)
+    D.set_yield(None)
+    b.single_frame_adjoint(D, sc.dT, b.solve_opts(), W)
+    D.close()
