@@ -16,6 +16,7 @@ tables, per-scene records) goes to --detail-out.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -251,6 +252,43 @@ def graph_form(ctx, sc, prec, tiles, frames, max_cg, warmup=1):
     span = max(np.abs(ref - sc.S.x).max(), 1e-300)
     out["max_rel_diff_vs_direct"] = {k: float(np.abs(v - ref).max() / span) for k, v in xs.items() if k != "direct"}
     out["iteration_graph_speedup"] = out["direct"]["ms_per_step"] / out["iteration_graphs"]["ms_per_step"]
+    return out
+
+
+def plastic_form(ctx, sc, prec, solve, tiles, frames, ky=1e-4, warmup=1, warm_start=False):
+    """The elastoplastic extension on the headline workload: every material
+    given the yield stress 2 mu ky (deviatoric log-strain ky), the same
+    frames timed elastic and plastic from fresh pairs, and G2P's launch
+    duration (it carries the projection) from one instrumented frame each."""
+    import numpy as np
+    import torch
+
+    from paper_2605_09097_amd import binding
+
+    opts = binding.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve, warm_start=warm_start)
+    out = {"yield_dev_log_strain": ky, "frames": "%d-%d" % (warmup, warmup + frames - 1)}
+    for kind in ("elastic", "plastic"):
+        pair = binding.SchwarzPair(ctx, sc, precision=prec, tile_B=tiles[0], tile_S=tiles[1])
+        if kind == "plastic":
+            for D, spec in ((pair.B, sc.B), (pair.S, sc.S)):
+                mu = np.asarray(spec.E) / (2.0 * (1.0 + np.asarray(spec.nu)))
+                D.set_yield(2.0 * mu * ky)
+        for _ in range(warmup):
+            pair.frame(opts)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        stats = [pair.frame(opts) for _ in range(frames)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ctx.profile(True)
+        pair.frame(opts)
+        torch.cuda.synchronize()
+        kern = _kernel_stats(ctx)
+        ctx.profile(False)
+        g2p = kern.get("g2p") or {}
+        out[kind] = {"ms_per_step": 1e3 * el / frames, "schwarz_iters_mean": float(np.mean([st.iters for st in stats])),
+                     "g2p_avg_us": g2p.get("avg_us"), "g2p_frac": g2p.get("frac_hbm")}
+        pair.close()
     return out
 
 
@@ -526,6 +564,10 @@ def compact_summary(detail, detail_path=None):
         "cycle_graphs_ms": (g.get("cycle_graphs") or {}).get("ms_per_step"),
         "iteration_graphs_ms": (g.get("iteration_graphs") or {}).get("ms_per_step"),
         "max_rel_diff": g.get("max_rel_diff_vs_direct")}
+    pl = detail.get("plastic")
+    out["plastic"] = None if not pl else {
+        k: {"ms": (pl.get(k) or {}).get("ms_per_step"), "g2p_us": (pl.get(k) or {}).get("g2p_avg_us")}
+        for k in ("elastic", "plastic")}
     m = detail.get("multi_domain")
     out["multi_domain"] = None if not m else {
         "multi_ms_per_step": (m.get("multi") or {}).get("ms_per_step"),
@@ -543,7 +585,27 @@ def compact_summary(detail, detail_path=None):
                                "particle_steps_per_s_forward_and_reverse", "sign_agrees_with_E_minus_E_target")}
     out["paper_context"] = {"speedup_vs_single_domain_fine_max": 9.15, "hardware": "Ryzen 9950X3D CPU (Taichi)"}
     out["detail"] = detail_path
+    out = _round_floats(out)
+    # over the limit (unexpectedly long error messages, say): the secondary
+    # sections go first, the contract's keys always stay
+    for k in ("large", "plastic", "graphs", "multi_domain", "adjoint", "adjoint_batched", "cold_start", "kernels", "batched",
+              "parity", "fp64_gpu_path"):
+        if len(json.dumps(out, separators=(",", ":"))) < SUMMARY_MAX_BYTES:
+            break
+        out[k] = "in the detail file"
     return out
+
+
+def _round_floats(obj, sig=5):
+    """Floats to `sig` significant digits (the line carries measurements,
+    not bit patterns)."""
+    if isinstance(obj, float):
+        return float("%.*g" % (sig, obj)) if math.isfinite(obj) else obj
+    if isinstance(obj, dict):
+        return {k: _round_floats(v, sig) for k, v in obj.items()}
+    if isinstance(obj, (list, tuple)):
+        return [_round_floats(v, sig) for v in obj]
+    return obj
 
 
 def main():
@@ -577,6 +639,8 @@ def main():
     ap.add_argument("--graph-frames", type=int, default=10,
                     help="frames of the graph-replay comparison (0 skips it)")
     ap.add_argument("--graph-cg", type=int, default=16, help="CG iterations of its fixed-schedule solves")
+    ap.add_argument("--plastic-frames", type=int, default=10,
+                    help="frames of the elastoplastic comparison (0 skips it)")
     ap.add_argument("--tile-cache", default=None,
                     help="JSON file of tile choices kept between runs (default: $OSMPM_TILE_CACHE, else none)")
     ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
@@ -604,12 +668,13 @@ def main():
         rows = []
         for item in args.eshelby.split(","):
             ratio, inv_dx = item.split(":")
-            pair = {m: eshelby.run(ctx, m, float(ratio), int(inv_dx), prec) for m in ("single", "dual")}
+            pair = {m: eshelby.run(ctx, m, float(ratio), int(inv_dx), prec, warm_start=bool(args.warm_start))
+                    for m in ("single", "dual")}
             pair["speedup"] = pair["single"]["wall_s"] / pair["dual"]["wall_s"]
             rows.append(pair)
             print(json.dumps(pair), file=sys.stderr, flush=True)
         print(json.dumps({"study": "inclusion efficiency, single-domain fine vs OS-MPM",
-                          "path": args.precision, "runs": rows}))
+                          "path": args.precision, "warm_start": bool(args.warm_start), "runs": rows}))
         ctx.close()
         return
     if args.domain_probe:
@@ -675,8 +740,16 @@ def main():
         return pr, st, time.perf_counter() - t
 
     _progress("tiles chosen: B %s, S %s" % (tile_B, tile_S))
-    # Timed region (no instrumentation).
-    pair, stats, elapsed = timed(prec, opts, args.steps, args.warmup)
+    # Timed region (no instrumentation): the same W + K frames three times,
+    # each from a fresh pair; the median span is reported and the last pair
+    # continues into the instrumented pass.
+    spans = []
+    for rep in range(3):
+        if rep:
+            pair.close()
+        pair, st_rep, el_rep = timed(prec, opts, args.steps, args.warmup)
+        spans.append((el_rep, st_rep))
+    elapsed, stats = sorted(spans, key=lambda t: t[0])[1]
     # Kernel durations: the same number of frames again with every launch of
     # the instrumented kernels timestamped by its dispatch (HIP events on the
     # library's stream).  Timestamped dispatches serialise the queue, so this
@@ -743,6 +816,9 @@ def main():
     graphs = graph_form(ctx, sc, prec, (tile_B, tile_S), args.graph_frames, args.graph_cg) \
         if args.graph_frames > 0 else None
     _progress("graph replay section done")
+    plastic = plastic_form(ctx, sc, prec, solve, (tile_B, tile_S), args.plastic_frames, warm_start=warm) \
+        if args.plastic_frames > 0 else None
+    _progress("elastoplastic section done")
     multi = multi_form(ctx, prec, solve, args.multi_frames, warm_start=warm) if args.multi_frames > 0 else None
     _progress("multi-domain section done")
     large = []
@@ -789,7 +865,9 @@ def main():
                    "ls_halvings_per_frame_mean": float(np.mean([s.ls_B + s.ls_S for s in stats])),
                    "inner_unconverged_total": int(sum(s.unconv_B + s.unconv_S for s in stats)),
                    "inner_ls_failed_total": int(sum(s.lsfail_B + s.lsfail_S for s in stats)),
-                   "warm_start": warm, "tile_B": list(tile_B), "tile_S": list(tile_S)},
+                   "warm_start": warm, "tile_B": list(tile_B), "tile_S": list(tile_S),
+                   "timing": "median of 3 spans of the same frames, each from a fresh pair",
+                   "span_ms_per_step": [round(1e3 * e / args.steps, 4) for e, _ in spans]},
         # particle updates done, Schwarz re-iterations included (each pass
         # repeats the coarse step and the M fine sub-steps)
         "particle_updates_per_s_incl_schwarz_iters": sum(iters) * ps / elapsed,
@@ -814,6 +892,7 @@ def main():
         "batched": batched,
         "large": large,
         "graphs": graphs,
+        "plastic": plastic,
         "multi_domain": multi,
         "adjoint": adjoint,
         "adjoint_batched": adjoint_batch,
