@@ -87,3 +87,18 @@ def test_summary_line_is_compact_and_keeps_the_contract():
     for k in ("value", "unit", "cores", "kind", "sample"):
         assert k in line["cpu_baseline"], k
     assert json.loads(text)["value"] == detail["value"]
+
+
+def test_summary_line_stays_under_the_limit_with_a_long_error():
+    sys.path.insert(0, ROOT)
+    import json
+
+    import bench
+
+    detail = _stub_detail()
+    detail["large"][1] = {"workload": "fold", "error": "e" * 6000}
+    line = bench.compact_summary(detail, "gpurun_out/bench_detail.json")
+    text = json.dumps(line, separators=(",", ":"))
+    assert len(text) < bench.SUMMARY_MAX_BYTES, len(text)
+    assert line["value"] == detail["value"] and line["roofline"]["frac"] is not None
+    assert line["large"] == "in the detail file"
