@@ -645,7 +645,7 @@ def main():
                     help="JSON file of tile choices kept between runs (default: $OSMPM_TILE_CACHE, else none)")
     ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file for the full result (every section); '' skips it")
-    ap.add_argument("--large", default="hertz:200+3,fold:60+1,hinge:20+2",
+    ap.add_argument("--large", default="hertz:200+3,fold:40+2,hinge:20+2",
                     help="large single-pair workloads as name:advance+timed (frames run untimed to reach a "
                          "representative state, then frames timed), comma separated ('' skips them)")
     args = ap.parse_args()

@@ -466,14 +466,14 @@ def hertz_scene(inv_dx_B=32, inv_dx_S=128, ppc1d=2, R=0.5, E_cyl=1e5, E_block=1e
 
 def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick=0.02, E=5e5, nu=0.35,
                rho=1000.0, seed=0, dT=2e-3, M=4, n_frames=500, angle=math.pi, hinge_x=0.5,
-               fine_box=((0.4, 0.6), (-0.02, 0.22), (-0.02, 0.04)), band=0.02, margin=0.05, tau_rel=1e-3,
+               fine_box=((0.4, 0.6), (-0.02, 0.22), (-0.02, 0.04)), band=0.06, margin=0.05, tau_rel=1e-3,
                eps_tol_rel=1e-9, name="fold"):
     """3D folding slab: [0,length] x [0,width] x [0,thick], the layer of
     particles within one spacing of x = 0 clamped, the layer at x = length
     turned rigidly by `angle` about the axis through (hinge_x, ., thick/2)
     along -y (the free end lifts) at a constant rate over n_frames frames.
     The fine domain carries the material inside fine_box; the coarse domain
-    the material outside fine_box shrunk by band.  The coarse grid covers the
+    the material outside fine_box shrunk by band along x.  The coarse grid covers the
     half circle the free end sweeps, the fine grid the band its free half
     sweeps; both grids extend a further `margin` along x and below the slab,
     where the soft slab's own motion (the stretch towards the lifted end, the
@@ -487,9 +487,16 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
         return ((p[:, 0] >= 0.0) & (p[:, 0] <= length) & (p[:, 1] >= 0.0) & (p[:, 1] <= width)
                 & (p[:, 2] >= 0.0) & (p[:, 2] <= thick))
 
+    # The coarse domain's hole is the fine box shrunk by `band` along x only:
+    # the box spans the slab's whole width and thickness, so its y and z
+    # faces carry no interface and the overlap width is the band along x.
+    # Default 0.06 (six coarse cells, like the inclusion's overlap of eight):
+    # the Schwarz contraction improves with the overlap width (Sec. 2.3);
+    # measured on the first frames, 26 iterations per frame at 0.02, 9 at
+    # 0.04 and 6 at 0.06.
     def in_box(p, sh):
-        return ((p[:, 0] >= fx0 + sh) & (p[:, 0] <= fx1 - sh) & (p[:, 1] >= fy0 + sh) & (p[:, 1] <= fy1 - sh)
-                & (p[:, 2] >= fz0 + sh) & (p[:, 2] <= fz1 - sh))
+        return ((p[:, 0] >= fx0 + sh) & (p[:, 0] <= fx1 - sh) & (p[:, 1] >= fy0) & (p[:, 1] <= fy1)
+                & (p[:, 2] >= fz0) & (p[:, 2] <= fz1))
 
     regB = lambda p: slab(p) & ~in_box(p, band)
     regS = lambda p: slab(p) & in_box(p, 0.0)
@@ -503,7 +510,8 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
     spB, spS = 1.0 / (inv_dx_B * ppc1d), 1.0 / (inv_dx_S * ppc1d)
 
     def dist_out(p, sh):
-        e = [np.maximum.reduce([(lo + sh) - p[:, a], p[:, a] - (hi - sh), np.zeros(len(p))])
+        e = [np.maximum.reduce([(lo + (sh if a == 0 else 0.0)) - p[:, a], p[:, a] - (hi - (sh if a == 0 else 0.0)),
+                                np.zeros(len(p))])
              for a, (lo, hi) in enumerate(fine_box)]
         return np.sqrt(e[0] ** 2 + e[1] ** 2 + e[2] ** 2)
 
@@ -546,7 +554,7 @@ def fold_scene(inv_dx_B=100, inv_dx_S=400, ppc1d=2, length=1.0, width=0.2, thick
 
 def hinge_scene(cells_B=2, cells_S=6, thick=0.003, length=0.09, width=0.06, hinge=0.01, transition=3e-4,
                 E_stiff=1e5, E_soft=1e3, nu=0.4, rho=1000.0, n_bins=4, ppc1d=2, seed=0, dT=5e-4, M=2,
-                n_frames=400, margin=0.003, band=0.0015, pad=3, tau_rel=1e-3, eps_tol_rel=1e-9, name="hinge"):
+                n_frames=400, margin=0.006, band=0.0045, pad=3, tau_rel=1e-3, eps_tol_rel=1e-9, name="hinge"):
     """The three-dimensional showcase of Sec. 4.4: a thin structure
     [0,thick] x [0,length] x [0,width] (0.3 x 9 x 6 cm) made of two stiff
     panels (E_stiff = 100 kPa) joined by a compliant hinge (E_soft = 1 kPa),
@@ -561,8 +569,12 @@ def hinge_scene(cells_B=2, cells_S=6, thick=0.003, length=0.09, width=0.06, hing
     circle of its own length and the panels end parallel; the fine domain
     (cells_S cells through the thickness) carries all material within
     hinge/2 + transition + margin of the hinge centre, the coarse domain
-    (cells_B cells through the thickness) the rest, overlapping by `band`.
-    Both grids sit on one lattice of pitch thick / lcm(cells_B, cells_S)."""
+    (cells_B cells through the thickness) the rest, overlapping by `band`
+    (three coarse cells by default: the Schwarz contraction improves with
+    the overlap width, Sec. 2.3; measured on the first frames, 70 iterations
+    per frame at one coarse cell and a 3 mm margin, 20 at three cells and
+    6 mm).  Both grids sit on one lattice of pitch thick / lcm(cells_B,
+    cells_S)."""
     lat = math.lcm(cells_B, cells_S)
     h0 = thick / lat
     dqB, dqS = lat // cells_B, lat // cells_S
