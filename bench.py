@@ -63,6 +63,47 @@ def _host_cpu():
             "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
+def _oracle_batch_frame(s, warm_start):
+    """Frame 0 of batched scene s on the CPU oracle (a worker process's task)."""
+    import oracle
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.batch_scene(s)
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=warm_start)
+    pB, pS = sc.bc_params(0)
+    OB.set_bc_params(pB)
+    OS.set_bc_params(pS)
+    oracle.schwarz_frame(OB, OS, sc.dT, oo)
+    return _frame_particle_steps(sc)
+
+
+def _worker_ready(_=None):
+    import oracle  # noqa: F401  (loads the library once per worker)
+
+    return os.getpid()
+
+
+def cpu_baseline_batched(n_scenes, warm_start=False, max_workers=16):
+    """The CPU oracle on the batched family, every host core in use: frame 0
+    of each of the n_scenes scenes, one scene per task over a pool of
+    processes (spawned, so that no worker inherits the GPU context);
+    particle-steps of all scenes over the wall time of the pool's work."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    workers = max(1, min(max_workers, usable))
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(_worker_ready, range(workers)))  # start-up outside the timed span
+        t = time.perf_counter()
+        steps = sum(ex.map(_oracle_batch_frame, range(n_scenes), [warm_start] * n_scenes))
+        el = time.perf_counter() - t
+    return {"value": steps / el, "unit": "particle-steps/s", "cores": workers, "kind": "oracle",
+            "sample": "frame 0 of each of the %d batched scenes, one scene per process, %d processes, %.1f s"
+                      % (n_scenes, workers, el)}
+
+
 def cpu_baseline(sc, frames, budget_s=30.0, warm_start=False):
     """The CPU oracle (single-threaded FP64 C) on the first frames of the same
     workload; returns (value, sample description, state)."""
@@ -535,6 +576,8 @@ def compact_summary(detail, detail_path=None):
         out["cpu_baseline"]["host_cpu"] = (cpu.get("host") or {}).get("model")
     else:
         out["cpu_baseline"] = None
+    cb = detail.get("cpu_baseline_batched")
+    out["cpu_baseline_batched"] = None if not cb else {k: cb.get(k) for k in ("value", "cores", "sample")}
     par = detail.get("parity")
     out["parity"] = None if not par else {k: par.get(k) for k in ("frames", "vs", "path", "max_rel_err")}
     fp = detail.get("fp64_gpu_path")
@@ -659,6 +702,13 @@ def main():
     import torch
 
     from paper_2605_09097_amd import binding, scenes
+
+    # the oracle over every host core for the batched family, before this
+    # process touches the GPU (its workers are fresh interpreters)
+    cpu_batched = None
+    if (not args.no_cpu_baseline and args.batch_scenes > 0 and not args.eshelby and not args.domain_probe):
+        cpu_batched = cpu_baseline_batched(args.batch_scenes, warm_start=bool(args.warm_start))
+        _progress("batched cpu baseline done")
 
     ctx = binding.Context(0)
     prec = binding.OSMPM_MIXED if args.precision == "mixed" else binding.OSMPM_FP64
@@ -893,6 +943,7 @@ def main():
         "large": large,
         "graphs": graphs,
         "plastic": plastic,
+        "cpu_baseline_batched": cpu_batched,
         "multi_domain": multi,
         "adjoint": adjoint,
         "adjoint_batched": adjoint_batch,
