@@ -51,7 +51,13 @@ def signature(kind, scenes, opts, precision, candidates, advance):
     """Key of a tuning problem (see the module docstring)."""
     import torch
 
-    parts = [kind, torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu", _lib_digest(),
+    # the device by compute-unit count and memory size (its name string is
+    # not reported the same way under every tool)
+    dev = "cpu"
+    if torch.cuda.is_available():
+        pr = torch.cuda.get_device_properties(0)
+        dev = "%d-%d" % (pr.multi_processor_count, pr.total_memory)
+    parts = [kind, dev, _lib_digest(),
              "prec%d" % precision, "M%d" % opts.M, "warm%d" % getattr(opts, "warm_start", 0),
              "adv%d" % advance, repr([tuple(c) for c in candidates])]
     for sc in scenes:
