@@ -10,6 +10,11 @@
   outputs it computes quickly are compared: the binning sort (bit-exact),
   the fixed-point node masses (bit-exact) and the P2G grid state.
 
+* The throughput run's configuration (mixed, warm-started iterations) on the
+  refined inclusion, and the 64-scene batch as launched by the throughput
+  run with three sampled scenes checked against the oracle run of that
+  scene alone.
+
 Bars: bit-exact for integers; 1e-10 relative (2-norm) for the FP64 path with
 equal Schwarz and Newton counts; 1e-5 for the mixed path (FP32 bulk, CG
 tolerance 1e-5, which bounds the error each solve leaves).
@@ -126,3 +131,65 @@ def test_large_domain_sort_and_p2g(ctx, name, side, tile):
     assert rel_err(m.cpu().numpy(), O.m) < MIXED_TOL
     assert rel_err(vn.cpu().numpy(), O.vn) < MIXED_TOL
     D.close()
+
+
+@pytest.fixture(scope="module")
+def headline_warm():
+    """The refined inclusion's first frames on the oracle with warm-started
+    Schwarz iterations (the throughput run's setting)."""
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("inclusion_refined")
+    OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=True)
+    stats = []
+    for f in range(FRAMES):
+        pB, pS = sc.bc_params(f)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        stats.append(oracle.schwarz_frame(OB, OS, sc.dT, oo))
+    return sc, OB, OS, stats
+
+
+def test_headline_frames_mixed_warm(ctx, headline_warm):
+    """The throughput run's configuration (mixed path, warm-started Schwarz
+    iterations, tuned tiles) against the warm-started FP64 oracle."""
+    from paper_2605_09097_amd import binding as b
+
+    sc, OB, OS, ostats = headline_warm
+    pair = b.SchwarzPair(ctx, sc, precision=b.OSMPM_MIXED, tile_B=(8, 4), tile_S=(8, 8))
+    solve = b.solve_opts(cg_rtol=1e-5)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=solve, fine=solve, warm_start=True)
+    print("refined inclusion, warm-started, mixed", flush=True)
+    for f in range(FRAMES):
+        st = pair.frame(go)
+        assert st.converged
+        assert abs(st.iters - ostats[f].iters) <= 1
+    _compare(pair, sc, OB, OS, MIXED_TOL)
+    pair.close()
+
+
+def test_batch64_sampled_scenes_mixed(ctx):
+    """The batched configuration as the throughput run launches it (64 scenes
+    of uneven sizes in shared launches, mixed path, warm-started iterations,
+    16 x 16 tiles), one frame; three sampled scenes (the first, a middle and
+    the last) against the FP64 oracle run of that scene alone."""
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    scs = [scenes.batch_scene(s) for s in range(64)]
+    solve = b.solve_opts(cg_rtol=1e-5)
+    go = b.schwarz_opts(scs[0].M, eps_tol=scs[0].eps_tol, coarse=solve, fine=solve, warm_start=True)
+    batch = b.SchwarzBatch(ctx, scs, precision=b.OSMPM_MIXED, tile=(16, 16))
+    print("64-scene batch, one frame", flush=True)
+    gst = batch.frame(go)
+    for s in (0, 31, 63):
+        sc = scs[s]
+        OB, OS = oracle.Domain(sc.B), oracle.Domain(sc.S)
+        pB, pS = sc.bc_params(0)
+        OB.set_bc_params(pB)
+        OS.set_bc_params(pS)
+        ost = oracle.schwarz_frame(OB, OS, sc.dT, oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=True))
+        assert gst[s].converged and abs(gst[s].iters - ost.iters) <= 1, (s, gst[s].iters, ost.iters)
+        _compare(batch.pairs[s], sc, OB, OS, MIXED_TOL)
+    batch.close()
