@@ -249,6 +249,35 @@ def test_whole_iteration_graphs_match_eager(ctx, warm):
         assert newton_B + lsfail_B <= iters and cg_B == 12 * (newton_B + lsfail_B)
 
 
+def test_whole_iteration_graphs_3d_pair(ctx):
+    """The same comparison on the small 3D fold (27-node stencils, the
+    rotation drive), one pair, warm-started iterations, three frames."""
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    sc = scenes.workload("fold_tiny")
+    fixed = b.solve_opts(cg_rtol=0.0, max_newton=1, max_ls=0, max_cg=10)
+    opts = b.schwarz_opts(sc.M, k_max=7, eps_tol=sc.eps_tol, coarse=fixed, fine=fixed, warm_start=True)
+    runs = {}
+    for mode in (2, 0):
+        ctx.graphs(mode)
+        pair = b.SchwarzPair(ctx, sc)
+        out = []
+        for _ in range(3):
+            q = pair.frame(opts)
+            out.append(((q.iters, q.newton_B, q.newton_S, q.cg_B, q.cg_S, q.lsfail_B, q.lsfail_S),
+                        pair.B.grid_state()[2].cpu().numpy().copy(), pair.S.particles_input_order()[0].copy()))
+        pair.close()
+        runs[mode] = out
+    ctx.graphs(0)
+    # 27-node scatters sum with FP64 atomics in either order: rounding-level
+    # differences grow over the frames' iterations, so the FP64 parity bar
+    for g, e in zip(runs[2], runs[0]):
+        assert g[0] == e[0]
+        assert rel_err(g[1], e[1]) < 1e-10
+        assert rel_err(g[2] - sc.S.x, e[2] - sc.S.x) < 1e-10
+
+
 def test_graph_mode_rejects_unknown_values(ctx):
     from paper_2605_09097_amd import binding as b
 
