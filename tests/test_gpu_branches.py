@@ -148,6 +148,22 @@ def test_fold_m4_frames_fp64(ctx):
     pair.close()
 
 
+def test_inclusion_m4_frames_fp64(ctx):
+    """The small inclusion at sub-cycling ratio M = 4 (fine sub-steps at
+    m/M = 1/4 .. 1), FP64, three frames: equal Schwarz and Newton counts."""
+    b = _b()
+    sc = _s().inclusion_scene(20, 50, M=4, n_frames=50, delta=_s().INCLUSION_DELTA, name="inclusion_tiny_m4")
+    print("inclusion 1/20 | 1/50, M = 4, FP64", flush=True)
+    pair, OB, OS, stats = _frames(ctx, sc, 3, b.OSMPM_FP64, b.schwarz_opts(sc.M, eps_tol=sc.eps_tol),
+                                  oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol))
+    for gst, ost in stats:
+        assert (gst.iters, gst.converged) == (ost.iters, ost.converged)
+        assert (gst.n_recv_B, gst.n_recv_S, gst.n_amb) == (ost.n_recv_B, ost.n_recv_S, ost.n_amb)
+        assert (gst.newton_B, gst.newton_S) == (ost.newton_B, ost.newton_S)
+    _check_pair(pair, OB, OS, sc, FP64_TOL)
+    pair.close()
+
+
 # ---------------------------------------------------------------- line search
 G_CANT = 9.81
 

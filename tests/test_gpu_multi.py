@@ -28,15 +28,15 @@ def ctx():
 OVERLAP = ((0.42, 0.5), (0.58, 0.5))  # fine regions that overlap each other
 
 
-def _run(ctx, precision, n_frames=3, centres=((0.3, 0.5), (0.7, 0.5))):
+def _run(ctx, precision, n_frames=3, centres=((0.3, 0.5), (0.7, 0.5)), warm=False):
     from paper_2605_09097_amd import binding as b
     from paper_2605_09097_amd import scenes
 
     sc = scenes.two_inclusion_scene(delta=0.01, centres=centres)
     prec = b.OSMPM_FP64 if precision == "fp64" else b.OSMPM_MIXED
     so = b.solve_opts(cg_rtol=1e-10 if precision == "fp64" else 1e-5)
-    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so)
-    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol)
+    go = b.schwarz_opts(sc.M, eps_tol=sc.eps_tol, coarse=so, fine=so, warm_start=warm)
+    oo = oracle.schwarz_opts(sc.M, eps_tol=sc.eps_tol, warm_start=warm)
     grp = b.MultiGroup(ctx, sc, precision=prec)
     OB, OS = oracle.Domain(sc.B), [oracle.Domain(s) for s in sc.S]
     stats = []
@@ -74,6 +74,21 @@ def test_multi_frames_match_oracle(ctx, precision, centres):
         assert rel_err(u.cpu().numpy(), Do.u) < tol
         assert rel_err(x - spec.x, Do.x - spec.x) < tol
         assert rel_err(F - np.eye(2), Do.F - np.eye(2)) < tol
+    grp.close()
+
+
+def test_overlapping_regions_warm_started_fp64(ctx):
+    """Overlapping refined regions with warm-started Schwarz iterations
+    (the linked receivers read the same kept sub-step solutions the warm
+    starts use), FP64 against the oracle with equal counts."""
+    sc, grp, OB, OS, stats = _run(ctx, "fp64", centres=OVERLAP, warm=True)
+    for gst, ost in stats:
+        assert (gst.iters, gst.converged) == (ost.iters, ost.converged)
+        assert gst.newton_B == ost.newton_B and gst.newton_S == ost.newton_S
+    for Dg, Do, spec in [(grp.B, OB, sc.B)] + list(zip(grp.S, OS, sc.S)):
+        x = Dg.particles_input_order()[0]
+        assert rel_err(Dg.grid_state()[2].cpu().numpy(), Do.u) < 1e-10
+        assert rel_err(x - spec.x, Do.x - spec.x) < 1e-10
     grp.close()
 
 

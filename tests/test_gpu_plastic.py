@@ -158,6 +158,33 @@ def test_schwarz_plastic_frames_mixed(ctx):
     pair.close()
 
 
+def test_plastic_batch_matches_single_pairs(ctx):
+    """Plastic scenes in a batch (shared launches, per-domain plastic flags;
+    one scene left elastic) reproduce their single-pair runs."""
+    from paper_2605_09097_amd import binding as b
+    from paper_2605_09097_amd import scenes
+
+    base = _plastic_pair_scene(scenes.workload("inclusion_tiny"), 1)
+    elastic = dataclasses.replace(base, B=base.B.copy(), S=base.S.copy())
+    elastic.B.tau_y = None
+    elastic.S.tau_y = None
+    scs = [base, elastic]
+    opts = b.schwarz_opts(base.M, eps_tol=base.eps_tol)
+    batch = b.SchwarzBatch(ctx, scs)
+    print("plastic batch", flush=True)
+    bst = [batch.frame(opts) for _ in range(2)]
+    for i, sc in enumerate(scs):
+        pair = b.SchwarzPair(ctx, sc)
+        for f in range(2):
+            st = pair.frame(opts)
+            assert (st.iters, st.newton_B, st.newton_S) == (bst[f][i].iters, bst[f][i].newton_B, bst[f][i].newton_S)
+        for Dp, Db in ((pair.B, batch.pairs[i].B), (pair.S, batch.pairs[i].S)):
+            assert rel_err(Db.grid_state()[2].cpu().numpy(), Dp.grid_state()[2].cpu().numpy()) < 1e-12
+            assert rel_err(Db.particles_input_order()[3] - np.eye(2), Dp.particles_input_order()[3] - np.eye(2)) < 1e-12
+        pair.close()
+    batch.close()
+
+
 def test_reverse_mode_refuses_plastic_domains(ctx):
     from paper_2605_09097_amd import binding as b
     from paper_2605_09097_amd import scenes
