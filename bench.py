@@ -333,13 +333,19 @@ def plastic_form(ctx, sc, prec, solve, tiles, frames, ky=1e-4, warmup=1, warm_st
     return out
 
 
-def domain_probe(ctx, spec_s, prec):
+def domain_probe(ctx, spec_s, prec, adaptive=False):
     """Per-kernel launch durations on one domain of a workload
     (name:side[:tile], side B or S, tile as AxB or AxBxC): five P2Gs, one
     implicit solve of two Newton steps with exactly 100 CG iterations each
     (random particle velocities from seed 7 so that the solve has work),
     and three G2P + P2G pairs, each new grid solved with no Newton step (u
-    stays at its initial iterate dt v^n, which is what G2P then reads)."""
+    stays at its initial iterate dt v^n, which is what G2P then reads).
+
+    adaptive: then, untimed by the kernel statistics, one implicit solve to
+    the bench's tolerances (CG relative residual 1e-5 on the mixed path,
+    1e-10 on FP64) from a smooth bending velocity (a half sine along the
+    domain's longest extent, directed along its shortest, 0.05 m/s peak),
+    for the Newton and CG counts and the wall time of a solve."""
     import numpy as np
     import torch
 
@@ -348,14 +354,18 @@ def domain_probe(ctx, spec_s, prec):
     parts = spec_s.split(":")
     sc = scenes.workload(parts[0])
     spec = sc.B if parts[1] == "B" else sc.S
+    _progress("probe %s: %d particles, %d nodes generated" % (spec_s, spec.n_particles, int(np.prod(spec.n_nodes))))
     tile = tuple(int(t) for t in parts[2].split("x")) if len(parts) > 2 else None
     dom = binding.Domain(ctx, spec, precision=prec, tile=tile)
     rng = np.random.default_rng(7)
     v = 0.05 * rng.standard_normal(spec.x.shape)
     dom.set_state(*[torch.as_tensor(a) for a in (spec.x, v, spec.B, spec.F)])
+    del v
     dt = sc.dT / (sc.M if parts[1] == "S" else 1)
     dom.p2g()
     torch.cuda.synchronize()
+    free, total = torch.cuda.mem_get_info()
+    _progress("probe %s: domain on the device, %.1f of %.1f GB in use" % (spec_s, (total - free) / 1e9, total / 1e9))
     ctx.profile(True)
     for _ in range(5):
         dom.p2g()
@@ -369,9 +379,32 @@ def domain_probe(ctx, spec_s, prec):
     torch.cuda.synchronize()
     kern = _kernel_stats(ctx)
     ctx.profile(False)
+    _progress("probe %s: fixed-count pass done" % spec_s)
+    out = {"probe": spec_s, "particles": spec.n_particles, "nodes": int(np.prod(spec.n_nodes)),
+           "path": "mixed" if prec == binding.OSMPM_MIXED else "fp64", "newton": st.newton_iters,
+           "cg": st.cg_iters, "kernels": kern}
+    if adaptive:
+        ext = spec.x.max(axis=0) - spec.x.min(axis=0)
+        long_ax, short_ax = int(np.argmax(ext)), int(np.argmin(ext))
+        vs = np.zeros_like(spec.x)
+        phase = (spec.x[:, long_ax] - spec.x[:, long_ax].min()) / max(ext[long_ax], 1e-30)
+        vs[:, short_ax] = 0.05 * np.sin(np.pi * phase)
+        dom.set_state(*[torch.as_tensor(a) for a in (spec.x, vs, spec.B, spec.F)])
+        del vs
+        dom.p2g()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sta = dom.implicit_solve(dt, binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out["adaptive"] = {"newton": sta.newton_iters, "cg": sta.cg_iters, "converged": bool(sta.converged),
+                           "ls_halvings": sta.ls_halvings,
+                           "cg_per_newton": sta.cg_iters / max(sta.newton_iters, 1), "wall_ms": 1e3 * wall,
+                           "dt": dt}
+        _progress("probe %s: adaptive solve %d Newton, %d CG, %.0f ms" % (spec_s, sta.newton_iters, sta.cg_iters,
+                                                                         1e3 * wall))
     dom.close()
-    return {"probe": spec_s, "particles": spec.n_particles, "path": "mixed" if prec == binding.OSMPM_MIXED
-            else "fp64", "newton": st.newton_iters, "cg": st.cg_iters, "kernels": kern}
+    return out
 
 
 def batched_form(ctx, n_scenes, steps, prec, solve, warm_start=False, tile_cache=None):
@@ -674,6 +707,8 @@ def main():
                          "for ratio:inv_dx items, comma separated (e.g. 2:400,2:800), and exit")
     ap.add_argument("--domain-probe", default="",
                     help="only time the kernels on one domain, workload:side[:tile] (e.g. hertz:B:8x8), and exit")
+    ap.add_argument("--probe-adaptive", action="store_true",
+                    help="with --domain-probe: also one solve to the bench's tolerances from a smooth velocity")
     ap.add_argument("--multi-frames", type=int, default=10,
                     help="timed frames of the several-refined-regions run (0 skips it)")
     ap.add_argument("--warm-start", type=int, default=1,
@@ -728,7 +763,7 @@ def main():
         ctx.close()
         return
     if args.domain_probe:
-        out = domain_probe(ctx, args.domain_probe, prec)
+        out = domain_probe(ctx, args.domain_probe, prec, adaptive=args.probe_adaptive)
         if args.calibrate_copy:
             a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
             b = torch.empty_like(a)

@@ -202,7 +202,10 @@ void osmpm_ctx_destroy(osmpm_ctx *ctx);
 
 /* Creates a subdomain (Sec. 3.1) with room for `capacity` particles.  tile
  * gives the cells per axis of one workgroup tile of the particle/grid
- * kernels (0 = library default); the particle sort orders bins tile-major. */
+ * kernels (0 = library default); the particle sort orders bins tile-major.
+ * The capacity, the node count and the bin count (the cells of whole tiles)
+ * are each limited to 2^28; beyond that, or with a tile too large for LDS:
+ * OSMPM_E_INVALID_ARG. */
 osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t precision,
                                  int64_t capacity, const int32_t *tile_host, osmpm_domain **out);
 void osmpm_domain_destroy(osmpm_domain *dom);

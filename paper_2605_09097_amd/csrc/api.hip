@@ -34,7 +34,13 @@ static __device__ __align__(256) char scratch[kFixedRegionBytes];
 
 namespace {
 
-int blocks_for(int64_t n, int cap_blocks = 1 << 20) {
+// Workgroups of a one-item-per-thread launch (at most kMaxBlocks; a domain's
+// particle, node and bin counts are limited to kMaxItems so that such a
+// launch covers all of them).
+constexpr int kMaxBlocks = 1 << 20;
+constexpr int64_t kMaxItems = (int64_t)kMaxBlocks * kBlock;
+
+int blocks_for(int64_t n, int cap_blocks = kMaxBlocks) {
   int64_t b = (n + kBlock - 1) / kBlock;
   if (b < 1) b = 1;
   if (b > cap_blocks) b = cap_blocks;
@@ -703,6 +709,8 @@ void build_node_list(osmpm_batch *G, int s, bool counted) {
   if (!counted)
     launch(G->c, -1, 0, -1, k_node_count, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0,
            (const DomDesc *)G->dd[s]);
+  if (blocks_for(E.max_nn) > kNodeListDirect)
+    launch(G->c, -1, 0, -1, k_node_scan, dim3(1, G->n), dim3(1024), 0, (const DomDesc *)G->dd[s]);
   launch(G->c, -1, 0, -1, k_node_list, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0, (const DomDesc *)G->dd[s]);
 }
 
@@ -2370,14 +2378,23 @@ osmpm_status osmpm_domain_create(osmpm_ctx *ctx, const osmpm_grid *grid, int32_t
   for (int a = 0; a < grid->dim; ++a)
     if (grid->n_nodes[a] < 3) return fail(ctx, OSMPM_E_INVALID_ARG, "grid needs >= 3 nodes per axis");
   if (grid->dim == 2 && grid->n_nodes[2] != 1) return fail(ctx, OSMPM_E_INVALID_ARG, "n_nodes[2] must be 1 in 2D");
-  if (!(grid->h0 > 0.0) || grid->dx_q <= 0 || capacity < 0 || capacity > (1LL << 30))
+  if (!(grid->h0 > 0.0) || grid->dx_q <= 0 || capacity < 0 || capacity > kMaxItems)
     return fail(ctx, OSMPM_E_INVALID_ARG, "bad grid spacing or capacity");
-  if ((int64_t)grid->n_nodes[0] * grid->n_nodes[1] * grid->n_nodes[2] * grid->dim >= (1LL << 31))
+  if ((int64_t)grid->n_nodes[0] * grid->n_nodes[1] * grid->n_nodes[2] > kMaxItems)
     return fail(ctx, OSMPM_E_INVALID_ARG, "grid too large");
   int T[3] = {grid->dim == 2 ? 8 : 4, grid->dim == 2 ? 8 : 4, grid->dim == 2 ? 1 : 4};
   if (tile_host)
     for (int a = 0; a < grid->dim; ++a)
       if (tile_host[a] > 0) T[a] = tile_host[a];
+  {
+    // bins: whole tiles over the cells, tile-major
+    int64_t nk = 1;
+    for (int a = 0; a < grid->dim; ++a) {
+      if (T[a] > 1024) return fail(ctx, OSMPM_E_INVALID_ARG, "tile too large for LDS");
+      nk *= (((int64_t)grid->n_nodes[a] - 2 + T[a] - 1) / T[a]) * T[a];
+    }
+    if (nk > kMaxItems) return fail(ctx, OSMPM_E_INVALID_ARG, "grid too large for its tiles");
+  }
   auto *d = new osmpm_domain();
   d->ctx = ctx;
   d->uid = ctx->next_uid++;

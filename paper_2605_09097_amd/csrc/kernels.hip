@@ -150,6 +150,53 @@ __device__ inline int block_sum_int(int v, int *lds4) {
   return lds4[0] + lds4[1] + lds4[2] + lds4[3];
 }
 
+// In-place exclusive scan of a[0, n) by one workgroup of 1024 threads, 4096
+// entries per pass (four consecutive ones per thread, so loads and stores
+// are coalesced); returns the total to every thread.
+__device__ inline int wg_exclusive_scan(int *a, int n) {
+  __shared__ int wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int carry = 0;
+  for (int base = 0; base < n; base += 4096) {
+    int v[4];
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = base + 4 * tid + j;
+      v[j] = (idx < n) ? a[idx] : 0;
+      s += v[j];
+    }
+    int xs = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(xs, off, 64);
+      if (lane >= off) xs += y;
+    }
+    if (lane == 63) wsum[w] = xs;
+    __syncthreads();
+    if (w == 0) {
+      int ws = (lane < 16) ? wsum[lane] : 0;
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const int y = __shfl_up(ws, off, 64);
+        if (lane >= off) ws += y;
+      }
+      if (lane < 16) wsum[lane] = ws;
+    }
+    __syncthreads();
+    int excl = carry + (w > 0 ? wsum[w - 1] : 0) + (xs - s);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int idx = base + 4 * tid + j;
+      if (idx < n) a[idx] = excl;
+      excl += v[j];
+    }
+    carry += wsum[15];
+    __syncthreads();
+  }
+  return carry;
+}
+
 // ====================================================================== work lists
 // Live-tile list of a domain from its bin offsets (after a binning, or after
 // a stored binning is restored): the tiles holding particles, in tile order,
@@ -240,9 +287,23 @@ __global__ void __launch_bounds__(kBlock) k_node_count(const DomDesc *dd) {
   if (threadIdx.x == 0) dm.ncnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
 }
 
+// Exclusive scan of the per-block active-node counts of a grid of more than
+// kNodeListDirect node blocks, in place; one workgroup of 1024 threads per
+// domain.  Smaller grids keep their counts (k_node_list sums them itself).
+__global__ void __launch_bounds__(1024) k_node_scan(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if (!*dm.active) return;
+  const int nbn = (dm.g.nn + kBlock - 1) / kBlock;
+  if (nbn <= kNodeListDirect) return;
+  (void)wg_exclusive_scan(dm.ncnt, nbn);
+}
+
 // Active-node list in node order: each block of 256 nodes writes its active
-// nodes at the sum of the counts of the blocks before it; the last block
-// stores the total.
+// nodes at the number of active nodes in the blocks before it; the last
+// block stores the total.  Up to kNodeListDirect blocks that offset is the
+// sum of the earlier blocks' counts, formed here (at most 16 loads a thread);
+// larger grids read it from k_node_scan, which keeps the work linear in the
+// grid size.
 __global__ void __launch_bounds__(kBlock) k_node_list(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
@@ -251,9 +312,14 @@ __global__ void __launch_bounds__(kBlock) k_node_list(const DomDesc *dd) {
   if ((int)blockIdx.x >= nbn) return;
   __shared__ int red[kBlock / 64];
   __shared__ int wc[kBlock / 64];
-  int sp = 0;
-  for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) sp += dm.ncnt[j];
-  const int off = block_sum_int(sp, red);
+  int off;
+  if (nbn > kNodeListDirect) {
+    off = dm.ncnt[blockIdx.x];
+  } else {
+    int sp = 0;
+    for (int j = threadIdx.x; j < (int)blockIdx.x; j += kBlock) sp += dm.ncnt[j];
+    off = block_sum_int(sp, red);
+  }
   const int i = blockIdx.x * kBlock + threadIdx.x;
   const bool f = i < nn && dm.m[i] > 0.0;
   const unsigned long long bal = __ballot(f);
@@ -280,55 +346,14 @@ __global__ void __launch_bounds__(kBlock) k_tile_sum(const DomDesc *dd) {
 }
 
 // In-place exclusive scan of the tile totals by one workgroup of 1024
-// threads, 4096 totals per pass (four consecutive ones per thread, so loads
-// and stores are coalesced); the grand total goes to tcount[ntiles] and to
-// cell_start[nk].
+// threads; the grand total goes to tcount[ntiles] and to cell_start[nk].
 __global__ void __launch_bounds__(1024) k_tile_scan(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
-  __shared__ int wsum[16];
   const int nt = dm.tg.ntiles;
   int *tc = dm.tcount;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  int carry = 0;
-  for (int base = 0; base < nt; base += 4096) {
-    int v[4];
-    int s = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int idx = base + 4 * tid + j;
-      v[j] = (idx < nt) ? tc[idx] : 0;
-      s += v[j];
-    }
-    int xs = s;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int y = __shfl_up(xs, off, 64);
-      if (lane >= off) xs += y;
-    }
-    if (lane == 63) wsum[w] = xs;
-    __syncthreads();
-    if (w == 0) {
-      int ws = (lane < 16) ? wsum[lane] : 0;
-#pragma unroll
-      for (int off = 1; off < 16; off <<= 1) {
-        const int y = __shfl_up(ws, off, 64);
-        if (lane >= off) ws += y;
-      }
-      if (lane < 16) wsum[lane] = ws;
-    }
-    __syncthreads();
-    int excl = carry + (w > 0 ? wsum[w - 1] : 0) + (xs - s);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int idx = base + 4 * tid + j;
-      if (idx < nt) tc[idx] = excl;
-      excl += v[j];
-    }
-    carry += wsum[15];
-    __syncthreads();
-  }
-  if (tid == 0) {
+  const int carry = wg_exclusive_scan(tc, nt);
+  if (threadIdx.x == 0) {
     tc[nt] = carry;
     dm.cell_start[dm.nk] = carry;
   }

@@ -191,6 +191,11 @@ template <int D, typename TB>
 __global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg, int split);
 __global__ void k_tile_list(const DomDesc *dd);
 __global__ void k_node_count(const DomDesc *dd);
+// Node blocks (of kBlock nodes) up to which k_node_list forms each block's
+// offset from the per-block counts itself; larger grids scan the counts
+// first with k_node_scan.
+constexpr int kNodeListDirect = 1024;
+__global__ void k_node_scan(const DomDesc *dd);
 __global__ void k_node_list(const DomDesc *dd);
 __global__ void k_cg_reduce(const DomDesc *dd, int q, double rtol, int max_cg);
 template <int D, typename TB>

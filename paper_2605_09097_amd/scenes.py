@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import Callable, List, Optional
+from typing import Callable, List, Optional, Tuple, Union
 
 import numpy as np
 
@@ -75,7 +75,7 @@ class DomainSpec:
     bc_mask: List[int] = field(default_factory=list)
     m_ref: float = 1.0
     tau: float = 0.0
-    ppc1d: int = 2
+    ppc1d: Union[int, Tuple[int, ...]] = 2  # particles per cell, per axis or the same on every axis
     tau_y: Optional[np.ndarray] = None  # von Mises yield stress per material (None: elastic)
 
     @property
@@ -114,13 +114,26 @@ class Scene:
     meta: dict = field(default_factory=dict)
 
 
+def _per_axis(ppc1d, dim):
+    """Particles per cell along each axis: an int means the same count on
+    every axis, a sequence gives one count per axis."""
+    if isinstance(ppc1d, (int, np.integer)):
+        return (int(ppc1d),) * dim
+    out = tuple(int(k) for k in ppc1d)
+    if len(out) != dim or min(out) < 1:
+        raise ValueError("ppc1d needs %d positive counts" % dim)
+    return out
+
+
 def _sample(dim, inv_dx, lo_cell, hi_cell, ppc1d, region, seed, key, jitter=0.1):
     """Sub-cell centres of cells lo_cell..hi_cell-1 (per axis) kept by region(),
-    then jittered.  Returns positions (n, dim) and the unjittered centres."""
+    then jittered.  ppc1d is the count per axis (int or one per axis).
+    Returns positions (n, dim) and the unjittered centres."""
     dx = 1.0 / inv_dx
+    ppc = _per_axis(ppc1d, dim)
     axes = [np.arange(lo_cell[a], hi_cell[a]) for a in range(dim)]
-    sub = (np.arange(ppc1d) + 0.5) / ppc1d
-    grids = np.meshgrid(*[(ax[:, None] + sub[None, :]).ravel() for ax in axes], indexing="ij")
+    subs = [(np.arange(ppc[a]) + 0.5) / ppc[a] for a in range(dim)]
+    grids = np.meshgrid(*[(axes[a][:, None] + subs[a][None, :]).ravel() for a in range(dim)], indexing="ij")
     centres = np.stack([g.ravel() for g in grids], axis=1) * dx
     keep = region(centres)
     centres = centres[keep]
@@ -135,7 +148,7 @@ def _domain(dim, h0, origin_q, dx_q, n_nodes, x, mat, E, nu, rho, ppc1d, flags, 
             m_ref, tau_rel, F0=None):
     n = x.shape[0]
     dx = dx_q * h0
-    vol = np.full(n, dx ** dim / ppc1d ** dim)
+    vol = np.full(n, dx ** dim / math.prod(_per_axis(ppc1d, dim)))
     mass = rho * vol
     F = np.broadcast_to(np.eye(dim), (n, dim, dim)).copy()
     if F0 is not None:
@@ -574,7 +587,8 @@ def hinge_scene(cells_B=2, cells_S=6, thick=0.003, length=0.09, width=0.06, hing
     the overlap width, Sec. 2.3; measured on the first frames, 70 iterations
     per frame at one coarse cell and a 3 mm margin, 20 at three cells and
     6 mm).  Both grids sit on one lattice of pitch thick / lcm(cells_B,
-    cells_S)."""
+    cells_S).  ppc1d: particles per cell, per axis or the same on every
+    axis."""
     lat = math.lcm(cells_B, cells_S)
     h0 = thick / lat
     dqB, dqS = lat // cells_B, lat // cells_S
@@ -606,11 +620,12 @@ def hinge_scene(cells_B=2, cells_S=6, thick=0.003, length=0.09, width=0.06, hing
     sy1 = int(math.ceil((yc + half_f) / dxS))
     nsx, nsz = int(round(thick / dxS)), int(round(width / dxS))
     xS, cS = _sample(3, 1.0 / dxS, [0, sy0, 0], [nsx, sy1, nsz], ppc1d, regS, seed, 11)
-    spB, spS = dxB / ppc1d, dxS / ppc1d
+    ppc = _per_axis(ppc1d, 3)
+    spB, spS = dxB / ppc[1], dxS / ppc[1]
     flB = np.where(np.abs(cB[:, 1] - yc) < half_f - band + spB, FLAG_BOUNDARY, 0)
     flB = flB | np.where(cB[:, 1] < spB, 2, 0) | np.where(cB[:, 1] > length - spB, 4, 0)
     flS = np.where(np.abs(cS[:, 1] - yc) > half_f - spS, FLAG_BOUNDARY, 0)
-    m_ref = rho * dxB ** 3 / ppc1d ** 3
+    m_ref = rho * dxB ** 3 / math.prod(ppc)
     # coarse grid: the half disc the free end sweeps about the fold axis
     reach = math.hypot(Rb, yc)
     loB = [-pad, -pad, -pad]
@@ -667,6 +682,12 @@ def workload(name: str, seed: int = 0) -> Scene:
         return fold_scene(seed=seed)
     if name == "hinge":
         return hinge_scene(seed=seed)
+    if name == "hinge_paper":
+        # Sec. 4.4 at its own resolution: h = 0.3 cm / 54 = 5.6e-3 cm in the
+        # fine domain and 4 particles per cell (2 x 2 across the thickness and
+        # along the length, one layer along the fold axis); the coarse domain
+        # is 3x coarser, the ratio of the reduced hinge.
+        return hinge_scene(cells_B=18, cells_S=54, ppc1d=(2, 2, 1), seed=seed, name=name)
     if name == "hinge_tiny":
         return hinge_scene(cells_B=1, cells_S=2, length=0.03, width=0.012, hinge=0.006, margin=0.002, band=0.002,
                            n_frames=40, seed=seed, name=name)

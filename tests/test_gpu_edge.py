@@ -10,8 +10,12 @@
   stops after its first pass and each domain runs on its own.
 * A fine grid not covered by the coarse grid's stencils: out-of-grid on
   both sides.
-* Argument limits: capacity above 2^30 particles, more particles than the
-  capacity, a grid with 2^31 or more DOFs.
+* A grid of more than 1024 blocks of 256 nodes with scattered particle
+  clusters: the active-node list is then built from a scan of the per-block
+  counts instead of per-block sums (the solve runs over that list).
+* Argument limits: capacity above 2^28 particles, more particles than the
+  capacity, a grid of more than 2^28 nodes, a grid whose whole tiles hold
+  more than 2^28 bins (each refused before anything is allocated).
 
 Bars as in the other parity tests: bit-exact for integers, 1e-10 (FP64) and
 1e-5 (mixed) relative for real outputs.
@@ -134,6 +138,23 @@ def test_all_particles_on_one_base_node(ctx, name):
     D.close()
 
 
+@pytest.mark.parametrize("name", ["fp64", "mixed"])
+@pytest.mark.parametrize("dim,cells", [(2, 600), (3, 70)])
+def test_large_sparse_grid(ctx, dim, cells, name):
+    """361,201 (2D) or 357,911 (3D) nodes, more than 1024 node blocks, with
+    twelve clusters of 40 particles spread over the grid, so that the active
+    nodes lie in a few scattered blocks."""
+    b = _b()
+    spec = tiny_domain(dim=dim, n_cells=cells, n_particles=480, seed=49, F_spread=0.08, v_scale=0.1)
+    assert ((cells + 1) ** dim + 255) // 256 > 1024
+    rng = np.random.default_rng(49)
+    centres = (3.0 + (cells - 6) * rng.random((12, dim))) * spec.dx
+    spec.x[:] = np.repeat(centres, 40, axis=0) + rng.uniform(-1.5, 1.5, (480, dim)) * spec.dx
+    D = b.Domain(ctx, spec, _prec(b, name))
+    _step_parity(ctx, D, spec, name)
+    D.close()
+
+
 def _uncoupled_pair(cover):
     """Coarse dx = 0.025 and fine dx = 0.0125 domains with no Schwarz-boundary
     particles.  cover=True: the coarse grid [0, 0.3]^2 holds the 3^2 stencil
@@ -202,15 +223,20 @@ def test_argument_limits(ctx):
     b = _b()
     spec = tiny_domain(dim=2, n_cells=8, n_particles=10, seed=46)
     with pytest.raises(b.OsmpmError) as e:
-        b.Domain(ctx, spec, capacity=(1 << 30) + 1)
+        b.Domain(ctx, spec, capacity=(1 << 28) + 1)
     assert e.value.status == b.OSMPM_E_INVALID_ARG
     with pytest.raises(b.OsmpmError) as e:
         b.Domain(ctx, spec, capacity=5)  # 10 particles
     assert e.value.status == b.OSMPM_E_INVALID_ARG
     huge = tiny_domain(dim=3, n_cells=8, n_particles=10, seed=47)
-    huge.n_nodes = [1 << 10, 1 << 10, 1 << 10]  # 2^30 nodes x 3 DOFs >= 2^31
+    huge.n_nodes = [1 << 10, 1 << 10, 1 << 9]  # 2^29 nodes
     with pytest.raises(b.OsmpmError) as e:
         b.Domain(ctx, huge)
+    assert e.value.status == b.OSMPM_E_INVALID_ARG
+    padded = tiny_domain(dim=2, n_cells=8, n_particles=10, seed=47)
+    padded.n_nodes = [3, 1 << 26, 1]  # 3 * 2^26 nodes, 64 * (2^26 - 2) bins in 64 x 1 tiles
+    with pytest.raises(b.OsmpmError) as e:
+        b.Domain(ctx, padded, tile=(64, 1))
     assert e.value.status == b.OSMPM_E_INVALID_ARG
 
 
