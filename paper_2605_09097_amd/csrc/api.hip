@@ -38,6 +38,9 @@ namespace {
 // particle, node and bin counts are limited to kMaxItems so that such a
 // launch covers all of them).
 constexpr int kMaxBlocks = 1 << 20;
+// Tile workgroups above which a solve sizes its tangent and CG launches to
+// the working workgroups (one status read per solve).
+constexpr int kSizedLaunch = 4096;
 constexpr int64_t kMaxItems = (int64_t)kMaxBlocks * kBlock;
 
 int blocks_for(int64_t n, int cap_blocks = kMaxBlocks) {
@@ -75,6 +78,7 @@ struct GraphBuild {
 // instantiated graph.
 struct CycleGraph {
   int b = 0;
+  int grid_t = 0, grid_cg = 0;  // launch sizes of the tangent pass and the CG iteration
   double dt = 0.0;
   osmpm_solve_opts o{};
   hipGraphExec_t exec = nullptr;
@@ -801,11 +805,34 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   const int n = G->n;
   const dim3 blk(kBlock);
   const int wstart = (warm_slot >= 0 && warm_use) ? warm_slot : -1;
+  osmpm_status st;
+  // Launch sizes of the tangent pass and the CG iteration.  Their workgroups
+  // past the live-tile slots and the active-DOF blocks leave at once, but on
+  // a grid that is mostly empty tiles those are most of the launch (on the
+  // fine domain of the hinge at the paper's resolution, 1.9M of 2.2M
+  // workgroups, 2 ms of each 12 ms CG iteration).  Above kSizedLaunch tile
+  // workgroups the solve first reads the status (the live-tile and
+  // active-node counts of the last binning and P2G, which no solve kernel
+  // changes) and sizes both launches to the largest working count of its
+  // domains, by the formula the kernels use.  A recorded solve keeps the full
+  // launches, whose sizes do not depend on the state.
+  int grid_t = E.tile_blocks, grid_cg = E.tile_blocks;
+  if (!c->rec && E.tile_blocks > kSizedLaunch) {
+    if ((st = read_status(G))) return st;
+    const SolveState *h = h_ss(G, s);
+    grid_t = grid_cg = 1;
+    for (int i = 0; i < n; ++i)
+      if (G->act[s][i] == 1) {
+        const osmpm_domain *d = G->dom[s][i];
+        grid_t = std::max(grid_t, std::min(((h[i].n_tiles_live + 7) / 8) * 8, d->tg.nblocks));
+        grid_cg = std::max(grid_cg, cg_work_blocks(h[i].n_tiles_live, h[i].n_active * d->D, d->tg.nblocks));
+      }
+  }
   launch(c, -1, 0, -1, k_bc_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, use_schwarz, vbc_buf, wstart);
   launch(c, -1, 0, -1, k_solve_begin, dim3(1, n), blk, 0, dd, dt, wstart);
   const double bg = active_bytes(G, s, OSMPM_K_GRAD_HESS);
   auto grad_phase = [&]() {
-    launch(c, OSMPM_K_GRAD_HESS, bg, -1, k_grad_hess<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_grad, dd,
+    launch(c, OSMPM_K_GRAD_HESS, bg, -1, k_grad_hess<D, TB>, dim3(grid_t, n), blk, E.lds_grad, dd,
            (int)o->project_psd, G->err);
     launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
            o->gravity[2]);
@@ -836,7 +863,6 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   std::vector<int> hint(n), prev_phase(n, kPhaseCgInit), prev_iter(n, 0), prev_total(n, 0);
   for (int i = 0; i < n; ++i) hint[i] = G->dom[s][i]->cg_hint;
   const long max_cycles = (long)(o->max_newton + 1) * ((o->max_cg + 4) / 4 + o->max_ls + 3) + 8;
-  osmpm_status st;
   if (c->rec) {
     // Recorded into a whole-iteration graph (fixed-schedule solves: one
     // Newton step of exactly max_cg CG iterations, no halving): one cycle
@@ -847,7 +873,9 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     for (int j = 0; j < b; ++j) {
       launch(c, -1, 0, -1, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd, j & 1, dt, o->cg_rtol,
              (int)o->max_cg, split);
-      if (split) launch(c, -1, 0, -1, k_cg_reduce, dim3(1, n), blk, 0, dd, j & 1, o->cg_rtol, (int)o->max_cg);
+      if (split)
+        launch(c, -1, 0, -1, k_cg_reduce, dim3(cg_reduce_blocks(E.tile_blocks), n), blk, 0, dd, j & 1, o->cg_rtol,
+               (int)o->max_cg);
     }
     launch(c, -1, 0, -1, k_delta_energy<D, TB>, dim3(E.part_blocks + E.node_blocks, n), blk, 0, dd, dt,
            o->gravity[0], o->gravity[1], o->gravity[2]);
@@ -894,9 +922,11 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
         if (sa && sb && hipEventRecord(sa, c->stream) != hipSuccess) sa = nullptr;
       }
       for (int j = 0; j < b; ++j) {
-        launch(c, sa ? -1 : OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(E.tile_blocks, n), blk, E.lds_hvp, dd,
+        launch(c, sa ? -1 : OSMPM_K_CG_ITER, 0.0, j, k_cg_iter<D, TB>, dim3(grid_cg, n), blk, E.lds_hvp, dd,
                j & 1, dt, o->cg_rtol, (int)o->max_cg, split);
-        if (split) launch(c, -1, 0, -1, k_cg_reduce, dim3(1, n), blk, 0, dd, j & 1, o->cg_rtol, (int)o->max_cg);
+        if (split)
+          launch(c, -1, 0, -1, k_cg_reduce, dim3(cg_reduce_blocks(grid_cg), n), blk, 0, dd, j & 1,
+                 o->cg_rtol, (int)o->max_cg);
       }
       if (sa && sb && hipEventRecord(sb, c->stream) == hipSuccess)
         c->pending.push_back({sa, sb, OSMPM_K_CG_ITER, 0.0, kCgSpan});
@@ -909,7 +939,9 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
       // replay the cycle (its launches and the status copy) as one graph
       CycleGraph *cg = nullptr;
       for (CycleGraph &x : G->cycles[s])
-        if (x.b == b && x.dt == dt && std::memcmp(&x.o, o, sizeof(osmpm_solve_opts)) == 0) cg = &x;
+        if (x.b == b && x.grid_t == grid_t && x.grid_cg == grid_cg && x.dt == dt &&
+            std::memcmp(&x.o, o, sizeof(osmpm_solve_opts)) == 0)
+          cg = &x;
       if (!cg) {
         GraphBuild gb;
         HIP_TRY(c, hipGraphCreate(&gb.graph, 0));
@@ -927,6 +959,8 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
           return fail(c, OSMPM_E_DEVICE, std::string("solve cycle graph: ") + hipGetErrorString(gb.err));
         CycleGraph x;
         x.b = b;
+        x.grid_t = grid_t;
+        x.grid_cg = grid_cg;
         x.dt = dt;
         x.o = *o;
         x.exec = ex;

@@ -97,7 +97,6 @@ __global__ void __launch_bounds__(kBlock) k_zero_grid(const DomDesc *dd, int wan
   const int nn = dm.g.nn;
   const int stride = gridDim.x * blockDim.x;
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 == 0) dm.ss->n_active = 0;
   for (int i = i0; i < dm.nk; i += stride) dm.count[i] = 0;
   for (int i = i0; i < nn; i += stride) {
     dm.m[i] = 0.0;
@@ -330,7 +329,11 @@ __global__ void __launch_bounds__(kBlock) k_node_list(const DomDesc *dd) {
 #pragma unroll
   for (int k = 0; k < kBlock / 64; ++k) woff += (k < w) ? wc[k] : 0;
   if (f) dm.nlist[off + woff + (int)__popcll(bal & ((1ull << lane) - 1ull))] = i;
-  if ((int)blockIdx.x == nbn - 1 && threadIdx.x == 0) dm.lcnt[1] = off + wc[0] + wc[1] + wc[2] + wc[3];
+  if ((int)blockIdx.x == nbn - 1 && threadIdx.x == 0) {
+    const int total = off + wc[0] + wc[1] + wc[2] + wc[3];
+    dm.lcnt[1] = total;
+    dm.ss->n_active = total;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_tile_sum(const DomDesc *dd) {
@@ -728,7 +731,8 @@ __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
 
 // v_i = (mv)_i / m_i on active nodes; scene-BC group of each DOF (lowest
 // group selecting the node whose mask holds the component); the count of
-// active nodes.
+// active nodes of each block of 256 nodes (k_node_list, which follows, forms
+// the total).
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
   const DomDesc &dm = dd[blockIdx.y];
@@ -736,8 +740,6 @@ __global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const double m = (i < dm.g.nn) ? dm.m[i] : 0.0;
   const unsigned long long act = __ballot(m > 0.0);
-  if ((threadIdx.x & 63) == 0 && act) atomicAdd(&dm.ss->n_active, (int)__popcll(act));
-  // active nodes of this block of 256 nodes, for the active-node list
   __shared__ int wc[kBlock / 64];
   if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (int)__popcll(act);
   __syncthreads();
@@ -1360,6 +1362,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd, int check
     CgState &c = *dm.cg;
     c.iter = 0;
     c.done = 0;
+    c.red_cnt = 0;
     c.k_at[0] = 0;
     c.k_at[1] = 0;
   }
@@ -1379,18 +1382,6 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd, int check
     p[k] = TB(0);
     del[k] = TB(0);
   }
-}
-
-// Workgroups of a CG launch that do work: one per live-tile slot (whole
-// bands of 8) and enough for the active DOFs, at least one, at most the
-// launch's tile blocks.  The lists do not change during a solve, so every
-// launch of it (and the split-mode reduction) derives the same count.
-__device__ inline int cg_work_blocks(int live_tiles, int active_dofs, int nblocks) {
-  int nw = ((live_tiles + 7) >> 3) * 8;
-  const int nown = (active_dofs + kBlock - 1) / kBlock;
-  nw = nw > nown ? nw : nown;
-  nw = nw > 1 ? nw : 1;
-  return nw < nblocks ? nw : nblocks;
 }
 
 // Scalars of CG launch i from the partial sums (sg, sd, sr) of launch i - 1:
@@ -1775,28 +1766,58 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   }
 }
 
-// Split mode: after CG launch i of parity q, one workgroup per domain adds
-// that launch's partial sums (in the order the fused form uses) and derives
-// the stop test, beta_i and alpha_i for launch i + 1.
+// Split mode: after CG launch i of parity q, the launch's partial sums are
+// added and the stop test, beta_i and alpha_i derived for launch i + 1.
+// Each of the gridDim.x workgroups of a domain adds a contiguous share of the
+// partials (lane l taking every 256th, as the fused form does over all of
+// them) and stores its three sums in the other parity's partial area, which
+// split mode leaves unused until the next CG launch writes it.  The last
+// workgroup to arrive (a counter in the CG state, which it resets) adds those
+// sums in workgroup order and derives the scalars.  With one workgroup the
+// sums are the fused form's.  No workgroup waits for another.
 __global__ void __launch_bounds__(kBlock) k_cg_reduce(const DomDesc *dd, int q, double rtol, int max_cg) {
   const DomDesc &dm = dd[blockIdx.y];
   if (!*dm.active) return;
   CgState *S = dm.cg;
   if (S->done) return;
   __shared__ double red[12];
+  __shared__ int last;
   const int tid = threadIdx.x;
-  const int i = S->k_at[q];
   const int nbt = cg_work_blocks(dm.lcnt[0], dm.lcnt[1] * (dm.ndof / dm.g.nn), dm.tg.nblocks);
-  const double *pin = dm.part_cg + (size_t)q * 3 * dm.pstride;
+  const int nr = gridDim.x;
+  const int share = (nbt + nr - 1) / nr;
+  const int j0 = blockIdx.x * share;
+  const int j1 = min(nbt, j0 + share);
+  const int ps = dm.pstride;
+  const double *pin = dm.part_cg + (size_t)q * 3 * ps;
   double sg = 0.0, sd = 0.0, sr = 0.0;
-  for (int j = tid; j < nbt; j += kBlock) {
+  for (int j = j0 + tid; j < j1; j += kBlock) {
     sg += pin[j];
-    sd += pin[dm.pstride + j];
-    sr += pin[2 * dm.pstride + j];
+    sd += pin[ps + j];
+    sr += pin[2 * ps + j];
   }
   block_sum3(sg, sd, sr, red);
+  if (nr > 1) {
+    double *tri = dm.part_cg + (size_t)(q ^ 1) * 3 * ps;
+    if (tid == 0) {
+      __hip_atomic_store(tri + blockIdx.x, sg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(tri + ps + blockIdx.x, sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(tri + 2 * ps + blockIdx.x, sr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = __hip_atomic_fetch_add(&S->red_cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == nr - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    sg = sd = sr = 0.0;
+    for (int j = tid; j < nr; j += kBlock) {
+      sg += __hip_atomic_load(tri + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sd += __hip_atomic_load(tri + ps + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sr += __hip_atomic_load(tri + 2 * ps + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    block_sum3(sg, sd, sr, red);
+    if (tid == 0) __hip_atomic_store(&S->red_cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (tid == 0) {
-    const int n = i + 1;
+    const int n = S->k_at[q] + 1;
     const CgStep st = cg_scalars(S, cg_prev(S, n), n, sg, sd, sr, rtol, max_cg, true);
     S->alpha_n = st.alpha;
     S->beta_n = st.beta;

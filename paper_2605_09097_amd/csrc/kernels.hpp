@@ -23,7 +23,8 @@ struct CgState {
   double rr0;     // |r_0|^2
   double alpha_n; // split mode: step length and direction weight of the next launch
   double beta_n;
-  double pad;
+  int red_cnt;    // split mode: workgroups of the current k_cg_reduce that have added their share
+  int pad;
   int iter;       // directions applied so far
   int done;       // converged, broke down, hit max_cg, or not solving
   int k_at[2];    // iteration index read by a launch of parity q (written for q ^ 1)
@@ -197,6 +198,25 @@ __global__ void k_node_count(const DomDesc *dd);
 constexpr int kNodeListDirect = 1024;
 __global__ void k_node_scan(const DomDesc *dd);
 __global__ void k_node_list(const DomDesc *dd);
+// Workgroups of a CG launch that do work: one per live-tile slot (whole
+// bands of 8) and enough for the active DOFs, at least one, at most the
+// domain's tile blocks.  The lists do not change during a solve, so every
+// launch of it (and the split-mode reduction) derives the same count; the
+// host sizes large launches with the same formula.
+__host__ __device__ inline int cg_work_blocks(int live_tiles, int active_dofs, int nblocks) {
+  int nw = ((live_tiles + 7) >> 3) * 8;
+  const int nown = (active_dofs + kBlock - 1) / kBlock;
+  nw = nw > nown ? nw : nown;
+  nw = nw > 1 ? nw : 1;
+  return nw < nblocks ? nw : nblocks;
+}
+
+// Workgroups per domain of k_cg_reduce for launches of up to `tile_blocks`
+// workgroups (one up to 8192, at most 256).
+inline int cg_reduce_blocks(int tile_blocks) {
+  const int r = tile_blocks / 4096;
+  return r < 1 ? 1 : (r > 256 ? 256 : r);
+}
 __global__ void k_cg_reduce(const DomDesc *dd, int q, double rtol, int max_cg);
 template <int D, typename TB>
 __global__ void k_delta_energy(const DomDesc *dd, double dt, double gx, double gy, double gz);

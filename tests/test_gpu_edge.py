@@ -12,7 +12,9 @@
   both sides.
 * A grid of more than 1024 blocks of 256 nodes with scattered particle
   clusters: the active-node list is then built from a scan of the per-block
-  counts instead of per-block sums (the solve runs over that list).
+  counts instead of per-block sums (the solve runs over that list).  On
+  small tiles the same grid makes the split-mode CG reduction run on
+  several workgroups.
 * Argument limits: capacity above 2^28 particles, more particles than the
   capacity, a grid of more than 2^28 nodes, a grid whose whole tiles hold
   more than 2^28 bins (each refused before anything is allocated).
@@ -138,21 +140,84 @@ def test_all_particles_on_one_base_node(ctx, name):
     D.close()
 
 
+def _sparse_clusters(dim, cells, seed=49):
+    """twelve clusters of 40 particles spread over a grid of `cells` cells
+    per axis, so that the active nodes lie in a few scattered blocks"""
+    spec = tiny_domain(dim=dim, n_cells=cells, n_particles=480, seed=seed, F_spread=0.08, v_scale=0.1)
+    rng = np.random.default_rng(seed)
+    centres = (3.0 + (cells - 6) * rng.random((12, dim))) * spec.dx
+    spec.x[:] = np.repeat(centres, 40, axis=0) + rng.uniform(-1.5, 1.5, (480, dim)) * spec.dx
+    return spec
+
+
 @pytest.mark.parametrize("name", ["fp64", "mixed"])
 @pytest.mark.parametrize("dim,cells", [(2, 600), (3, 70)])
 def test_large_sparse_grid(ctx, dim, cells, name):
     """361,201 (2D) or 357,911 (3D) nodes, more than 1024 node blocks, with
-    twelve clusters of 40 particles spread over the grid, so that the active
-    nodes lie in a few scattered blocks."""
+    scattered particle clusters."""
     b = _b()
-    spec = tiny_domain(dim=dim, n_cells=cells, n_particles=480, seed=49, F_spread=0.08, v_scale=0.1)
+    spec = _sparse_clusters(dim, cells)
     assert ((cells + 1) ** dim + 255) // 256 > 1024
-    rng = np.random.default_rng(49)
-    centres = (3.0 + (cells - 6) * rng.random((12, dim))) * spec.dx
-    spec.x[:] = np.repeat(centres, 40, axis=0) + rng.uniform(-1.5, 1.5, (480, dim)) * spec.dx
     D = b.Domain(ctx, spec, _prec(b, name))
     _step_parity(ctx, D, spec, name)
     D.close()
+
+
+@pytest.mark.parametrize("name", ["fp64", "mixed"])
+def test_cg_scalars_from_several_workgroups(ctx, name):
+    """CG scalars formed in their own launch (split mode) by several
+    workgroups per domain: on 4 x 4 tiles the 600 x 600-cell grid has 22,500
+    tile slots, so the reduction launch takes five workgroups, each adding a
+    share of the partial sums, the last to finish adding theirs.  Against the
+    oracle, and against the fused form (same Newton and CG counts, solution
+    equal to rounding)."""
+    b = _b()
+    spec = _sparse_clusters(2, 600, seed=50)
+    out = {}
+    try:
+        for mode in (1, 0):
+            ctx.cg_split(mode)
+            D = b.Domain(ctx, spec, _prec(b, name), tile=(4, 4))
+            if mode == 1:
+                _step_parity(ctx, D, spec, name)
+                D.close()
+                D = b.Domain(ctx, spec, _prec(b, name), tile=(4, 4))
+            D.p2g()
+            st = D.implicit_solve(2e-3, _solve_opts(b, name, (0.0, -9.8)))
+            out[mode] = ((st.newton_iters, st.cg_iters), D.grid_state()[2].cpu().numpy().copy())
+            D.close()
+    finally:
+        ctx.cg_split(-1)
+    assert out[1][0] == out[0][0]
+    assert rel_err(out[1][1], out[0][1]) < 1e-12
+
+
+def test_large_sparse_grid_cycle_graphs(ctx):
+    """Solves on a grid above the size at which a solve sizes its tangent and
+    CG launches to the working workgroups (4913 tiles of 4^3 cells), as cycle
+    graphs keyed by those sizes: two steps with graphs (the second replays
+    the cached cycles) give the eager steps' counts and solutions (FP64; the
+    grid's atomic sums vary in order either way)."""
+    b = _b()
+    spec = _sparse_clusters(3, 70, seed=51)
+    res = {}
+    try:
+        for graphs in (1, 0):
+            ctx.graphs(graphs)
+            D = b.Domain(ctx, spec, b.OSMPM_FP64)
+            out = []
+            for _ in range(2):
+                D.p2g()
+                st = D.implicit_solve(2e-3, _solve_opts(b, "fp64", (0.0, -9.8, 0.0)))
+                D.g2p(2e-3)
+                out.append(((st.newton_iters, st.cg_iters), D.grid_state()[2].cpu().numpy().copy()))
+            D.close()
+            res[graphs] = out
+    finally:
+        ctx.graphs(0)
+    for g, e in zip(res[1], res[0]):
+        assert g[0] == e[0]
+        assert rel_err(g[1], e[1]) < 1e-12
 
 
 def _uncoupled_pair(cover):
