@@ -580,7 +580,7 @@ template <int D, typename TB, bool kQ>
 __global__ void __launch_bounds__(kBlock) k_p2g(const DomDesc *dd, int *err) {
   constexpr int want_q = kQ ? 1 : 0;
   const DomDesc &dm = dd[blockIdx.y];
-  if (!*dm.active || (int)blockIdx.x >= dm.tg.nblocks) return;
+  if ((int)blockIdx.x >= dm.tg.nblocks || !*dm.active) return;
   extern __shared__ double lds[];
   // Descriptor fields are copied to registers: the loops below issue
   // atomics, after which the compiler would otherwise reload every field
@@ -772,8 +772,10 @@ __global__ void __launch_bounds__(kBlock) k_p2g_final(const DomDesc *dd) {
 template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, int *err) {
   const DomDesc &dm = dd[blockIdx.y];
-  // launch-uniform flags in one round of scalar loads, then the particle
-  // arrays' pointers; data through global-address-space accesses
+  // workgroups past the domain's particles leave on the descriptor alone;
+  // then the launch-uniform flags in one round of scalar loads, then the
+  // particle arrays' pointers; data through global-address-space accesses
+  if ((int)(blockIdx.x * blockDim.x) >= dm.np) return;
   const int act = uload(dm.active);
   const int cur = uload(dm.cur);
   if (!act) return;
@@ -1026,8 +1028,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_grad_hess(const DomDesc *dd, int 
   constexpr int n = D * D;
   constexpr int ns = n * (n + 1) / 2;
   const DomDesc &dm = dd[blockIdx.y];
-  // launch-uniform flags in one round of scalar loads; data through
+  // workgroups past the domain's tile slots leave on the descriptor alone;
+  // then the launch-uniform flags in one round of scalar loads; data through
   // global-address-space accesses
+  if ((int)blockIdx.x >= dm.tg.nblocks) return;
   const int act = uload(dm.active);
   const int phase = uload(&dm.ss->phase);
   const int cur = uload(dm.cur);
@@ -1479,10 +1483,13 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
                "s"(cs1), "s"(cw0), "s"(cw2), "s"(cu), "s"(cdel), "s"(part_cg), "s"(x0), "s"(x1), "s"(ndof),
                "s"(pstride), "s"(cap), "s"(tg.nblocks), "s"(tg.tvol), "s"(g.n[0]), "s"(g.n[2]), "s"(g.origin[0]),
                "s"(g.inv_dx));
+  // workgroups past the domain's tile slots leave on the descriptor alone;
   // the workgroup's slot of the live-tile list and its first active DOF are
-  // read with the flags (indices clamped into the arrays; used only when valid)
+  // read with the flags (the node index clamped into the list; used only
+  // when valid)
+  if ((int)blockIdx.x >= tg.nblocks) return;
   const int tid = threadIdx.x;
-  const int bq = (int)blockIdx.x < tg.nblocks ? (int)blockIdx.x : tg.nblocks - 1;
+  const int bq = (int)blockIdx.x;
   const int j0 = (int)blockIdx.x * kBlock + tid;
   const int act = uload(pactive);
   const int sdone = uload(&S->done);
