@@ -780,6 +780,14 @@ void g2p_side(osmpm_batch *G, int s, double dt) {
   const Ext &E = G->ext[s];
   launch(G->c, OSMPM_K_G2P, active_bytes(G, s, OSMPM_K_G2P), -1, k_g2p<D, TB>, dim3(blocks_for(E.max_np), G->n),
          dim3(kBlock), 0, (const DomDesc *)G->dd[s], dt, G->err);
+  // any member with a yielding material (the kernel skips inactive and
+  // elastic domains itself, so a recorded launch serves every active set)
+  bool plastic = false;
+  for (int i = 0; i < G->n; ++i)
+    if (G->dom[s][i]->plastic) plastic = true;
+  if (plastic)
+    launch(G->c, -1, 0, -1, k_plastic_return<D, TB>, dim3(blocks_for(E.max_np), G->n), dim3(kBlock), 0,
+           (const DomDesc *)G->dd[s]);
 }
 
 template <int D, typename TB>

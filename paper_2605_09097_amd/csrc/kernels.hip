@@ -857,17 +857,6 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
       for (int e = 0; e < D; ++e) t += (double)G[a * D + e] * Hp[e * D + b];
       Hn[a * D + b] = t;
     }
-  if (uload(&dm.plastic)) {
-    // elastoplastic materials: F^E projected onto the yield set (FP64)
-    const int mt = gload((const int *)P.mat, p);
-    double Fe[D * D];
-#pragma unroll
-    for (int k = 0; k < D * D; ++k) Fe[k] = Hn[k] + ((k % (D + 1) == 0) ? 1.0 : 0.0);
-    if (von_mises_project<D>(Fe, dm.mu[mt], dm.tau_y[mt])) {
-#pragma unroll
-      for (int k = 0; k < D * D; ++k) Hn[k] = Fe[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0);
-    }
-  }
 #pragma unroll
   for (int k = 0; k < D * D; ++k) {
     gstore(H, k * cap + p, (TB)Hn[k]);
@@ -877,6 +866,34 @@ __global__ void __launch_bounds__(kBlock) k_g2p(const DomDesc *dd, double dt, in
   for (int a = 0; a < D; ++a) {
     gstore(v, a * cap + p, vp[a]);
     gstore(px, a * cap + p, xp[a] + dt * (double)vp[a]);
+  }
+}
+
+// Elastoplastic materials, after G2P on a domain with a yielding material:
+// each particle's elastic F = I + H projected onto the yield set in FP64
+// (von_mises_project).  A kernel of its own, so that G2P keeps the registers
+// of the elastic update alone (the projection's eigensolve in G2P held 3D
+// G2P to two waves per SIMD: fold fine 37.5 -> 25-27 us without it).
+template <int D, typename TB>
+__global__ void __launch_bounds__(kBlock) k_plastic_return(const DomDesc *dd) {
+  const DomDesc &dm = dd[blockIdx.y];
+  if ((int)(blockIdx.x * blockDim.x) >= dm.np) return;
+  const int act = uload(dm.active);
+  const int plastic = uload(&dm.plastic);
+  const int cur = uload(dm.cur);
+  if (!act || !plastic) return;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= dm.np) return;
+  const PartPtrs &P = dm.pb[cur];
+  const int64_t cap = dm.cap;
+  TB *const H = static_cast<TB *>(P.F);
+  const int mt = gload((const int *)P.mat, p);
+  double Fe[D * D];
+#pragma unroll
+  for (int k = 0; k < D * D; ++k) Fe[k] = (double)gload((const TB *)H, k * cap + p) + ((k % (D + 1) == 0) ? 1.0 : 0.0);
+  if (von_mises_project<D>(Fe, dm.mu[mt], dm.tau_y[mt])) {
+#pragma unroll
+    for (int k = 0; k < D * D; ++k) gstore(H, k * cap + p, (TB)(Fe[k] - ((k % (D + 1) == 0) ? 1.0 : 0.0)));
   }
 }
 
@@ -2411,6 +2428,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const DomDesc *dd, doubl
   template __global__ void k_p2g<D, TB, false>(const DomDesc *, int *);                         \
   template __global__ void k_p2g<D, TB, true>(const DomDesc *, int *);                          \
   template __global__ void k_g2p<D, TB>(const DomDesc *, double, int *);                        \
+  template __global__ void k_plastic_return<D, TB>(const DomDesc *);                            \
   template __global__ void k_grad_hess<D, TB>(const DomDesc *, int, int *);                     \
   template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \
   template __global__ void k_cg_init<D, TB>(const DomDesc *, int, double, double, int);                                   \

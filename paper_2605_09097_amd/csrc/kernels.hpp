@@ -175,6 +175,8 @@ template <int D>
 __global__ void k_p2g_final(const DomDesc *dd);
 template <int D, typename TB>
 __global__ void k_g2p(const DomDesc *dd, double dt, int *err);
+template <int D, typename TB>
+__global__ void k_plastic_return(const DomDesc *dd);
 
 // implicit solve
 template <int D, typename TB>
