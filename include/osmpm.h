@@ -99,12 +99,21 @@ typedef struct {
  * newton_atol * sum_i m_i * dx / dt^2) or after max_newton steps; CG stops at
  * |r| <= cg_rtol |r0| or after max_cg iterations; the line search halves at
  * most max_ls times.  project_psd = 1 projects each particle's dP/dF onto the
- * PSD cone.  gravity is the body-force acceleration (f_ext = m_i g). */
+ * PSD cone.  gravity is the body-force acceleration (f_ext = m_i g).
+ * forcing > 0 (an extension; the paper fixes no CG tolerance) loosens CG per
+ * Newton step by the Eisenstat-Walker rule (choice 2: eta_k = 0.9
+ * (|g_k| / |g_k-1|)^2, safeguarded by 0.9 eta_k-1^2 when that exceeds 0.1,
+ * at least 0.5 times the Newton tolerance over |g_k|, at most forcing; the
+ * first step takes forcing), CG then stopping at |r| <= max(cg_rtol,
+ * eta_k) |r0|; 0 keeps cg_rtol alone.  Newton's own test is unchanged, so a
+ * converged solve meets the same tolerance.  Negative or NaN:
+ * OSMPM_E_INVALID_ARG. */
 typedef struct {
   double newton_rtol, newton_atol, cg_rtol;
   int32_t max_newton, max_cg, max_ls;
   int32_t project_psd;
   double gravity[3];
+  double forcing;
 } osmpm_solve_opts;
 
 typedef struct {

@@ -50,7 +50,7 @@ class osmpm_material(C.Structure):
 class osmpm_solve_opts(C.Structure):
     _fields_ = [("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("cg_rtol", C.c_double),
                 ("max_newton", C.c_int32), ("max_cg", C.c_int32), ("max_ls", C.c_int32),
-                ("project_psd", C.c_int32), ("gravity", C.c_double * 3)]
+                ("project_psd", C.c_int32), ("gravity", C.c_double * 3), ("forcing", C.c_double)]
 
 
 class osmpm_solve_stats(C.Structure):
@@ -164,10 +164,13 @@ def _ptr(t):
 
 
 def solve_opts(newton_rtol=1e-8, newton_atol=1e-13, cg_rtol=1e-10, max_newton=50, max_cg=2000, max_ls=30,
-               project_psd=True, gravity=(0.0, 0.0, 0.0)):
+               project_psd=True, gravity=(0.0, 0.0, 0.0), forcing=0.0):
+    """forcing > 0: Eisenstat-Walker CG tolerances per Newton step, at most
+    forcing (see osmpm_solve_opts); 0: cg_rtol alone."""
     o = osmpm_solve_opts()
     o.newton_rtol, o.newton_atol, o.cg_rtol = newton_rtol, newton_atol, cg_rtol
     o.max_newton, o.max_cg, o.max_ls, o.project_psd = max_newton, max_cg, max_ls, int(project_psd)
+    o.forcing = forcing
     g = list(gravity) + [0.0] * (3 - len(gravity))
     for a in range(3):
         o.gravity[a] = g[a]

@@ -845,7 +845,7 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
     launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
            o->gravity[2]);
     launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, 1, o->newton_rtol, o->newton_atol,
-           (int)o->max_newton);
+           (int)o->max_newton, o->forcing);
   };
   grad_phase();
   // Split CG scalars (k_cg_reduce after each iteration) when the fused form's
@@ -1750,7 +1750,7 @@ osmpm_status adj_solve(osmpm_batch *G, int s, double dt, int use_schwarz, const 
   launch(c, -1, 0, -1, k_grad_node<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, dt, o->gravity[0], o->gravity[1],
          o->gravity[2]);
   launch(c, -1, 0, -1, k_adj_set_rhs, dim3(E.node_blocks, n), blk, 0, dd, ubar);
-  launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, 0, 0.0, 0.0, 0);
+  launch(c, -1, 0, -1, k_cg_init<D, TB>, dim3(E.node_blocks, n), blk, 0, dd, 0, 0.0, 0.0, 0, 0.0);
   const int max_cg = 20000, chunk = 16;
   osmpm_status st;
   for (int launched = 0;; launched += chunk) {
@@ -2680,7 +2680,7 @@ osmpm_status osmpm_p2g(osmpm_domain *d) {
 osmpm_status osmpm_implicit_solve(osmpm_domain *d, double dt, int32_t use_schwarz_bc, const osmpm_solve_opts *o,
                                   osmpm_solve_stats *st) {
   if (!d || !o) return OSMPM_E_INVALID_ARG;
-  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0 || !(o->forcing >= 0.0)) return OSMPM_E_INVALID_ARG;
   if (!(dt > 0.0)) return fail(d->ctx, OSMPM_E_INVALID_ARG, "dt must be positive");
   if (!d->have_p2g) return fail(d->ctx, OSMPM_E_STATE, "solve before p2g");
   return DISPATCH2(d->D, d->precision, solve_solo)(d, dt, use_schwarz_bc, o, st);
@@ -2742,7 +2742,8 @@ osmpm_status osmpm_set_schwarz_bc(osmpm_domain *d, const double *vbc) {
 
 static bool schwarz_opts_ok(const osmpm_schwarz_opts *o) {
   return o && o->M >= 1 && o->k_max >= 1 && o->eps_tol >= 0.0 && o->coarse.max_newton >= 0 && o->coarse.max_cg >= 0 &&
-         o->coarse.max_ls >= 0 && o->fine.max_newton >= 0 && o->fine.max_cg >= 0 && o->fine.max_ls >= 0;
+         o->coarse.max_ls >= 0 && o->fine.max_newton >= 0 && o->fine.max_cg >= 0 && o->fine.max_ls >= 0 &&
+         o->coarse.forcing >= 0.0 && o->fine.forcing >= 0.0;
 }
 
 osmpm_status osmpm_schwarz_frame(osmpm_domain *B, osmpm_domain *S, double dT, const osmpm_schwarz_opts *o,
@@ -2756,7 +2757,7 @@ osmpm_status osmpm_schwarz_frame(osmpm_domain *B, osmpm_domain *S, double dT, co
 
 osmpm_status osmpm_single_frame(osmpm_domain *d, double dt, const osmpm_solve_opts *o, osmpm_solve_stats *st) {
   if (!d || !o || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
-  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0 || !(o->forcing >= 0.0)) return OSMPM_E_INVALID_ARG;
   return DISPATCH2(d->D, d->precision, single_group)(d->solo, dt, o, st);
 }
 
@@ -2806,7 +2807,7 @@ osmpm_status osmpm_multi_schwarz_frame(osmpm_batch *b, double dT, const osmpm_sc
 osmpm_status osmpm_batch_single_frame(osmpm_batch *b, double dt, const osmpm_solve_opts *o,
                                       osmpm_solve_stats *stats) {
   if (!b || b->sides != 1 || !o || !(dt > 0.0)) return OSMPM_E_INVALID_ARG;
-  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0 || !(o->forcing >= 0.0)) return OSMPM_E_INVALID_ARG;
   return DISPATCH2(b->D, b->precision, single_group)(b, dt, o, stats);
 }
 
@@ -2847,7 +2848,7 @@ osmpm_status osmpm_single_frame_adjoint(osmpm_domain *d, double dt, const osmpm_
                                         const double *Fbar, double *oxbar, double *ovbar, double *oBbar,
                                         double *oFbar, double *mubar, double *lambar) {
   if (!d || !o || !(dt > 0.0) || !(adj_cg_rtol > 0.0) || !mubar || !lambar) return OSMPM_E_INVALID_ARG;
-  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0 || !(o->forcing >= 0.0)) return OSMPM_E_INVALID_ARG;
   if (d->np > 0 && (!xbar || !vbar || !Bbar || !Fbar || !oxbar || !ovbar || !oBbar || !oFbar))
     return OSMPM_E_INVALID_ARG;
   if (d->plastic) return fail(d->ctx, OSMPM_E_INVALID_ARG, kNoPlasticAdjoint);
@@ -2864,7 +2865,7 @@ osmpm_status osmpm_single_frame_adjoint_noalloc(osmpm_domain *d, double dt, cons
                                                 double *ovbar, double *oBbar, double *oFbar, double *mubar,
                                                 double *lambar) {
   if (!d || !o || !(dt > 0.0) || !(adj_cg_rtol > 0.0) || !mubar || !lambar) return OSMPM_E_INVALID_ARG;
-  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0) return OSMPM_E_INVALID_ARG;
+  if (o->max_newton < 0 || o->max_cg < 0 || o->max_ls < 0 || !(o->forcing >= 0.0)) return OSMPM_E_INVALID_ARG;
   if (d->np > 0 && (!xbar || !vbar || !Bbar || !Fbar || !oxbar || !ovbar || !oBbar || !oFbar))
     return OSMPM_E_INVALID_ARG;
   osmpm_ctx *c = d->ctx;

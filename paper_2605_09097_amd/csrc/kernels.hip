@@ -1347,12 +1347,13 @@ __device__ inline void block_sum3(double &a, double &b, double &c, double *lds12
 // state reset.  Runs for domains whose Newton iteration goes on to CG.
 template <int D, typename TB>
 __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd, int check, double rtol, double atol,
-                                                    int max_newton) {
+                                                    int max_newton, double forcing) {
   const DomDesc &dm = dd[blockIdx.y];
   const int nb = node_blocks(dm.ndof);
   if (!*dm.active || (int)blockIdx.x >= nb) return;
   SolveState &st = *dm.ss;
   const int ph = st.phase;
+  double eta = 0.0;
   if (check) {
     // The Newton stop test on the fresh gradient, by every workgroup from the
     // same partial sums in the same order: stop when |g_free| <= max(rtol
@@ -1370,6 +1371,17 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd, int check
     const bool conv = gn <= tol;
     const int next = (conv || it == max_newton) ? kPhaseDone : kPhaseCgInit;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (forcing > 0.0 && next == kPhaseCgInit) {
+        // Eisenstat-Walker choice 2 with its safeguards
+        if (it == 0) {
+          eta = forcing;
+        } else {
+          const double q = gn / st.gnorm, ep = dm.cg->eta;
+          eta = 0.9 * q * q;
+          if (0.9 * ep * ep > 0.1) eta = fmax(eta, 0.9 * ep * ep);
+        }
+        eta = fmin(forcing, fmax(eta, 0.5 * tol / gn));
+      }
       if (it == 0) st.gnorm0 = gn0;
       st.gnorm = gn;
       if (conv) st.converged = 1;
@@ -1383,6 +1395,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_init(const DomDesc *dd, int check
     CgState &c = *dm.cg;
     c.iter = 0;
     c.done = 0;
+    c.eta = eta;
     c.red_cnt = 0;
     c.k_at[0] = 0;
     c.k_at[1] = 0;
@@ -1522,6 +1535,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
   const double s_rr0 = gload(&S->rr0, 0), s_gam0 = gload(&S->gam[0], 0), s_gam1 = gload(&S->gam[1], 0);
   const double s_alp0 = gload(&S->alp[0], 0), s_alp1 = gload(&S->alp[1], 0);
   const double s_alpha_n = gload(&S->alpha_n, 0), s_beta_n = gload(&S->beta_n, 0);
+  const double s_eta = gload(&S->eta, 0);
   asm volatile("" ::"s"(act), "s"(sdone), "s"(i), "s"(cur), "s"(ntl), "s"(nnl), "s"(te_t), "s"(te_p0), "s"(te_p1),
                "v"(nd0));
   const int ndl = nnl * D;  // active DOFs
@@ -1613,7 +1627,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_iter(const DomDesc *dd, int q, do
     bool done = false;
     if (i > 0) {
       block_sum3(sg, sd, sr, red);
-      const CgStep st = cg_scalars(S, prev, i, sg, sd, sr, rtol, max_cg, blockIdx.x == 0 && tid == 0);
+      const CgStep st = cg_scalars(S, prev, i, sg, sd, sr, fmax(rtol, s_eta), max_cg, blockIdx.x == 0 && tid == 0);
       alpha = st.alpha;
       beta = st.beta;
       done = st.done;
@@ -1842,7 +1856,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_reduce(const DomDesc *dd, int q, 
   }
   if (tid == 0) {
     const int n = S->k_at[q] + 1;
-    const CgStep st = cg_scalars(S, cg_prev(S, n), n, sg, sd, sr, rtol, max_cg, true);
+    const CgStep st = cg_scalars(S, cg_prev(S, n), n, sg, sd, sr, fmax(rtol, S->eta), max_cg, true);
     S->alpha_n = st.alpha;
     S->beta_n = st.beta;
     if (st.done) {
@@ -2431,7 +2445,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_final(const DomDesc *dd, doubl
   template __global__ void k_plastic_return<D, TB>(const DomDesc *);                            \
   template __global__ void k_grad_hess<D, TB>(const DomDesc *, int, int *);                     \
   template __global__ void k_grad_node<D, TB>(const DomDesc *, double, double, double, double); \
-  template __global__ void k_cg_init<D, TB>(const DomDesc *, int, double, double, int);                                   \
+  template __global__ void k_cg_init<D, TB>(const DomDesc *, int, double, double, int, double);                                   \
   template __global__ void k_cg_iter<D, TB>(const DomDesc *, int, double, double, int, int);    \
   template __global__ void k_delta_energy<D, TB>(const DomDesc *, double, double, double, double);
 

@@ -23,6 +23,7 @@ struct CgState {
   double rr0;     // |r_0|^2
   double alpha_n; // split mode: step length and direction weight of the next launch
   double beta_n;
+  double eta;     // relative CG tolerance of this Newton step beyond the fixed one (0: none)
   int red_cnt;    // split mode: workgroups of the current k_cg_reduce that have added their share
   int pad;
   int iter;       // directions applied so far
@@ -189,7 +190,7 @@ __global__ void k_grad_hess(const DomDesc *dd, int project, int *err);
 template <int D, typename TB>
 __global__ void k_grad_node(const DomDesc *dd, double dt, double gx, double gy, double gz);
 template <int D, typename TB>
-__global__ void k_cg_init(const DomDesc *dd, int check, double rtol, double atol, int max_newton);
+__global__ void k_cg_init(const DomDesc *dd, int check, double rtol, double atol, int max_newton, double forcing);
 template <int D, typename TB>
 __global__ void k_cg_iter(const DomDesc *dd, int q, double dt, double rtol, int max_cg, int split);
 __global__ void k_tile_list(const DomDesc *dd);
