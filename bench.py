@@ -334,7 +334,7 @@ def plastic_form(ctx, sc, prec, solve, tiles, frames, ky=1e-4, warmup=1, warm_st
     return out
 
 
-def domain_probe(ctx, spec_s, prec, adaptive=False):
+def domain_probe(ctx, spec_s, prec, adaptive=False, forcing=0.0):
     """Per-kernel launch durations on one domain of a workload
     (name:side[:tile], side B or S, tile as AxB or AxBxC): five P2Gs, one
     implicit solve of two Newton steps with exactly 100 CG iterations each
@@ -346,7 +346,8 @@ def domain_probe(ctx, spec_s, prec, adaptive=False):
     the bench's tolerances (CG relative residual 1e-5 on the mixed path,
     1e-10 on FP64) from a smooth bending velocity (a half sine along the
     domain's longest extent, directed along its shortest, 0.05 m/s peak),
-    for the Newton and CG counts and the wall time of a solve."""
+    for the Newton and CG counts and the wall time of a solve; with forcing
+    > 0 the same solve again with Eisenstat-Walker CG tolerances."""
     import numpy as np
     import torch
 
@@ -390,20 +391,24 @@ def domain_probe(ctx, spec_s, prec, adaptive=False):
         vs = np.zeros_like(spec.x)
         phase = (spec.x[:, long_ax] - spec.x[:, long_ax].min()) / max(ext[long_ax], 1e-30)
         vs[:, short_ax] = 0.05 * np.sin(np.pi * phase)
-        dom.set_state(*[torch.as_tensor(a) for a in (spec.x, vs, spec.B, spec.F)])
+        vs = torch.as_tensor(vs)
+        for key, fc in (("adaptive", 0.0), ("adaptive_forcing", forcing)):
+            if key == "adaptive_forcing" and not forcing > 0.0:
+                continue
+            dom.set_state(torch.as_tensor(spec.x), vs, torch.as_tensor(spec.B), torch.as_tensor(spec.F))
+            dom.p2g()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sta = dom.implicit_solve(dt, binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10,
+                                                            forcing=fc))
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            out[key] = {"forcing": fc, "newton": sta.newton_iters, "cg": sta.cg_iters,
+                        "converged": bool(sta.converged), "ls_halvings": sta.ls_halvings,
+                        "cg_per_newton": sta.cg_iters / max(sta.newton_iters, 1), "wall_ms": 1e3 * wall, "dt": dt}
+            _progress("probe %s: solve (forcing %g) %d Newton, %d CG, %.0f ms" % (spec_s, fc, sta.newton_iters,
+                                                                                sta.cg_iters, 1e3 * wall))
         del vs
-        dom.p2g()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sta = dom.implicit_solve(dt, binding.solve_opts(cg_rtol=1e-5 if prec == binding.OSMPM_MIXED else 1e-10))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        out["adaptive"] = {"newton": sta.newton_iters, "cg": sta.cg_iters, "converged": bool(sta.converged),
-                           "ls_halvings": sta.ls_halvings,
-                           "cg_per_newton": sta.cg_iters / max(sta.newton_iters, 1), "wall_ms": 1e3 * wall,
-                           "dt": dt}
-        _progress("probe %s: adaptive solve %d Newton, %d CG, %.0f ms" % (spec_s, sta.newton_iters, sta.cg_iters,
-                                                                         1e3 * wall))
     dom.close()
     return out
 
@@ -767,7 +772,7 @@ def main():
         ctx.close()
         return
     if args.domain_probe:
-        out = domain_probe(ctx, args.domain_probe, prec, adaptive=args.probe_adaptive)
+        out = domain_probe(ctx, args.domain_probe, prec, adaptive=args.probe_adaptive, forcing=args.forcing)
         if args.calibrate_copy:
             a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
             b = torch.empty_like(a)
