@@ -164,6 +164,10 @@ struct osmpm_domain {
   int cg_hint = 8;  // iterations of the last CG solve (sizes the next batch of launches)
   bool have_p2g = false;
   bool have_solve = false;  // an implicit solve since the last P2G (u is then zero on inactive nodes)
+  // uid of the group whose status holds the live-tile and active-node counts
+  // of the current work lists (the last group to bin this domain or rebuild
+  // them; 0: none)
+  uint64_t lists_by = 0;
   osmpm_batch *solo = nullptr;  // this domain as a group of one
   osmpm_batch *pair = nullptr;  // this coarse domain paired with a fine one
   uint64_t pair_uid = 0;
@@ -191,6 +195,7 @@ struct StatusHdr {
 struct osmpm_batch {
   bool multi = false;  // one coarse domain (repeated on side 0) and k fine domains
   osmpm_ctx *c = nullptr;
+  uint64_t uid = 0;  // unique in the context (a freed group's address may be reused)
   int D = 2, precision = 0;
   size_t tb = sizeof(double);
   int n = 0, sides = 1;
@@ -440,6 +445,7 @@ osmpm_status group_create(osmpm_ctx *c, int n, osmpm_domain *const *side0, osmpm
   if (n < 1 || n > 1024 || !side0) return fail(c, OSMPM_E_INVALID_ARG, "group size must be 1..1024");
   auto *G = new osmpm_batch();
   G->c = c;
+  G->uid = c->next_uid++;
   G->n = n;
   G->sides = side1 ? 2 : 1;
   G->D = side0[0] ? side0[0]->D : 2;
@@ -710,6 +716,10 @@ void build_tile_list(osmpm_batch *G, int s) {
 }
 void build_node_list(osmpm_batch *G, int s, bool counted) {
   const Ext &E = G->ext[s];
+  // the tile list of side s is rebuilt (binning or restore) before its node
+  // list, so from here this group's status holds both counts
+  for (int i = 0; i < G->n; ++i)
+    if (G->act[s][i] == 1) G->dom[s][i]->lists_by = G->uid;
   if (!counted)
     launch(G->c, -1, 0, -1, k_node_count, dim3(blocks_for(E.max_nn), G->n), dim3(kBlock), 0,
            (const DomDesc *)G->dd[s]);
@@ -822,10 +832,17 @@ osmpm_status solve_side(osmpm_batch *G, int s, double dt, int use_schwarz, int v
   // workgroups the solve first reads the status (the live-tile and
   // active-node counts of the last binning and P2G, which no solve kernel
   // changes) and sizes both launches to the largest working count of its
-  // domains, by the formula the kernels use.  A recorded solve keeps the full
-  // launches, whose sizes do not depend on the state.
+  // domains, by the formula the kernels use.  The counts live in the status
+  // of the group that built the lists, so a solve through another group
+  // keeps the full launches (the entry points bin a domain in the group that
+  // then solves it, and a solve after G2P without a new binning is refused,
+  // so this only guards the sequencing), as does a recorded solve, whose
+  // sizes must not depend on the state.
   int grid_t = E.tile_blocks, grid_cg = E.tile_blocks;
-  if (!c->rec && E.tile_blocks > kSizedLaunch) {
+  bool own_counts = true;  // this group built every solving domain's work lists
+  for (int i = 0; i < n; ++i)
+    if (G->act[s][i] == 1 && G->dom[s][i]->lists_by != G->uid) own_counts = false;
+  if (!c->rec && own_counts && E.tile_blocks > kSizedLaunch) {
     if ((st = read_status(G))) return st;
     const SolveState *h = h_ss(G, s);
     grid_t = grid_cg = 1;
